@@ -1,0 +1,158 @@
+"""Element-by-element discretisation of a workload (paper Sec. 2.2.1 with the
+Helmholtz data of Sec. 2.3.4 and Sec. 3).  Test infrastructure only.
+
+Time convention e^{-i omega t}: the outgoing impedance condition is
+d_n u - i k u = g, i.e. the Robin form n.grad(phi) + gamma phi = q with
+gamma = -i k and q = g.  Helmholtz: alpha = I, beta = -k^2 eps_r.
+"""
+import numpy as np
+from scipy.special import hankel2
+
+from . import element as el
+from . import legendre as lg
+from .mesh import Mesh
+
+NORMALS = {1: (-1.0, 0.0), 2: (1.0, 0.0), 3: (0.0, -1.0), 4: (0.0, 1.0)}
+
+
+def make_mesh(w):
+    x0, x1, y0, y1 = w["domain"]
+    bnx, bny = w["base"]
+    return Mesh(x0, x1, y0, y1, bnx, bny, w["leaves"])
+
+
+def coarse_order(w, mesh=None):
+    """l: explicit, or from the dispersion rule with h = the longest element edge
+    and the free-space k (Sec. 2.3.4)."""
+    if w.get("l", -1) >= 1:
+        return int(w["l"])
+    mesh = mesh or make_mesh(w)
+    h = max(max(mesh.size(e)) for e in range(mesh.E))
+    return lg.dispersion_l(w["k"], h)
+
+
+def edge_param(mesh, e, side):
+    """Map s in [-1,1] along a side to (x, y)."""
+    (ox, oy), (hx, hy) = mesh.origin(e), mesh.size(e)
+    if side in (1, 2):
+        xc = ox if side == 1 else ox + hx
+        return lambda s: (np.full_like(s, xc), oy + (s + 1) * hy / 2), hy
+    yc = oy if side == 3 else oy + hy
+    return lambda s: (ox + (s + 1) * hx / 2, np.full_like(s, yc)), hx
+
+
+class Discretisation:
+    """A_e (paper basis N), the Laplace-only part, loads b_e, Dirichlet data."""
+
+    def __init__(self, w, mesh=None, bc=None, alpha=None, poisson=False):
+        self.w = w
+        self.mesh = mesh or make_mesh(w)
+        m = self.mesh
+        self.k = float(w.get("k", 0.0))
+        self.degrees = np.asarray(w["degree"])
+        eps = np.asarray(w.get("eps_r", np.ones(m.E)))
+        alpha = np.ones(m.E) if alpha is None else np.asarray(alpha)
+        if bc is None:
+            bc = {s: ("dirichlet" if w.get("bc") == "dirichlet" else "robin") for s in (1, 2, 3, 4)}
+        self.bc = bc
+        gamma = -1j * self.k
+        self.A, self.A_lap, self.b = [], [], []
+        rhs = w.get("rhs", {"kind": "none"})
+        for e in range(m.E):
+            n = int(self.degrees[e]) + 1
+            hx, hy = m.size(e)
+            beta = 0.0 if poisson else -self.k ** 2 * eps[e]
+            robin = {}
+            for side in (1, 2, 3, 4):
+                bnd = m.boundary_side(e, side)
+                if bnd and bc[bnd] == "robin":
+                    robin[side] = gamma
+            self.A.append(el.element_matrix(n, hx, hy, alpha=alpha[e], beta=beta, robin=robin))
+            self.A_lap.append(el.element_matrix(n, hx, hy, alpha=alpha[e]))
+            self.b.append(self._load(e, n, hx, hy, eps[e], rhs, robin))
+
+    def _load(self, e, n, hx, hy, eps_e, rhs, robin):
+        m = self.mesh
+        kind = rhs["kind"]
+        k = self.k
+        b = np.zeros(n * n, complex)
+        (ox, oy) = m.origin(e)
+        if kind == "plane_wave_total":
+            th = rhs["angles"][0]
+            d = np.array([np.cos(th), np.sin(th)])
+            for side in robin:
+                xy, h_edge = edge_param(m, e, side)
+                nrm = np.array(NORMALS[side])
+
+                def q(s, xy=xy, nrm=nrm):
+                    x, y = xy(s)
+                    return 1j * k * (d @ nrm - 1.0) * np.exp(1j * k * (d[0] * x + d[1] * y))
+                b += el.edge_load(n, h_edge, side, el.legendre_coeffs_1d(q, n))
+        elif kind == "plane_wave_scattered":
+            th = rhs["angles"][0]
+            d = np.array([np.cos(th), np.sin(th)])
+            if eps_e != 1.0:
+                def f(u, v):
+                    x = ox + (u + 1) * hx / 2
+                    y = oy + (v + 1) * hy / 2
+                    return k ** 2 * (eps_e - 1.0) * np.exp(1j * k * (d[0] * x + d[1] * y))
+                b += el.volume_load(n, hx, hy, el.legendre_coeffs_2d(f, n))
+        elif kind == "point":
+            for (px, py) in rhs["points"]:
+                owners = [f for f in range(m.E) if _contains(m, f, px, py)]
+                if e in owners:
+                    u = 2 * (px - ox) / hx - 1
+                    v = 2 * (py - oy) / hy - 1
+                    b += el.point_load(n, u, v) / len(owners)
+        elif kind == "random":
+            rng = np.random.default_rng(rhs.get("seed", 0) + e)
+            b += rng.uniform(0.0, 1.0, n * n)
+        return b
+
+    def dirichlet_fun(self):
+        """Legendre coefficients of the Dirichlet data along a side, or None."""
+        rhs = self.w.get("rhs", {"kind": "none"})
+        if rhs["kind"] != "dirichlet_hankel":
+            return None
+        xc, yc = rhs["center"]
+        k = self.k
+        m = self.mesh
+
+        def fun(e, side, n):
+            xy, _ = edge_param(m, e, side)
+
+            def pfun(s):
+                x, y = xy(s)
+                return -0.25j * hankel2(0, k * np.hypot(x - xc, y - yc))
+            return el.legendre_coeffs_1d(pfun, n)
+        return fun
+
+
+def _contains(m, e, px, py):
+    (ox, oy), (hx, hy) = m.origin(e), m.size(e)
+    tol = 1e-12
+    return (ox - tol <= px <= ox + hx + tol) and (oy - tol <= py <= oy + hy + tol)
+
+
+def exact_plane_wave(w):
+    th = w["rhs"]["angles"][0]
+    k = w["k"]
+    return lambda x, y: np.exp(1j * k * (np.cos(th) * x + np.sin(th) * y))
+
+
+def sample_field(mesh, degrees, phis, pts_fun):
+    """Evaluate each element expansion phi = N(u)^T Phi N(v) on a local tensor grid
+    given by pts_fun(n) -> 1-D points; returns list of (n_pts^2,) arrays, x fastest."""
+    out = []
+    for e in range(mesh.E):
+        n = int(degrees[e]) + 1
+        t = pts_fun(n)
+        Nt = lg.basis_N(t, n)          # (n, npts)
+        Phi = phis[e].reshape(n, n, order="F")
+        out.append((Nt.T @ Phi @ Nt).reshape(-1, order="F"))
+    return out
+
+
+def gll_field(mesh, degrees, phis):
+    """Field at the tensor GLL nodes of each element, x fastest."""
+    return sample_field(mesh, degrees, phis, lg.gll_nodes)

@@ -1,0 +1,228 @@
+"""Pins of the oracle's dual-primal method (paper Sec. 2.3, 3.1, 3.2, 3.3.1)
+against printed tables, the direct conforming solution, a manufactured plane
+wave, structural identities and a far-field closed form."""
+import os
+
+import numpy as np
+import pytest
+from scipy.special import hankel1
+
+import workloads as W
+from oracle import constraints as cs
+from oracle import direct, dp, dp_elementwise as dpe, farfield as ff
+from oracle import legendre as lg
+from oracle import problem as pb
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _table(name):
+    rows = []
+    for line in open(os.path.join(GOLD, name)):
+        if line.startswith("#") or not line.strip():
+            continue
+        rows.append(line.split())
+    return rows
+
+
+def _square(n, p, k, bc, rhs, alpha=None, poisson=False):
+    w = dict(domain=(-1.0, 1.0, -1.0, 1.0), base=(n, n), leaves=W.morton_leaves(n, n),
+             degree=np.full(n * n, p), k=k, bc=bc, rhs=rhs)
+    mesh = pb.make_mesh(w)
+    return pb.Discretisation(w, mesh=mesh, alpha=alpha, poisson=poisson)
+
+
+def poisson_table1(p, N, l):
+    n = int(round(np.sqrt(N)))
+    leaves = W.morton_leaves(n, n)
+    rho = np.array([10.0 ** (((ix + 1) - (iy + 1)) / 4) for (_, ix, iy) in leaves])
+    disc = _square(n, p, 0.0, "dirichlet", dict(kind="random"), alpha=rho, poisson=True)
+    return dp.LiteralDP(disc, l, scaling=True)
+
+
+@pytest.mark.parametrize("row", _table("table1_lambda_max.txt"), ids=lambda r: f"p{r[0]}N{r[1]}")
+def test_table1_lambda_max(row):
+    p, N = int(row[0]), int(row[1])
+    for l, ref in zip((1, 2, 3, 4), row[2:]):
+        D = poisson_table1(p, N, l)
+        if ref == "-":
+            # l >= p: every constraint is primal, nothing is left to iterate on
+            assert D.F.shape[0] == 0
+            continue
+        ev = np.linalg.eigvals(D.Pinv @ D.F)
+        assert abs(ev.real.max() - float(ref)) <= 0.0051, (p, N, l)
+        assert abs(ev.real.min() - 1.0) < 5e-3
+        assert np.abs(ev.imag).max() < 1e-8
+
+
+@pytest.mark.parametrize("row", _table("table2_iterations.txt"), ids=lambda r: f"p{r[0]}N{r[1]}k{r[2]}")
+def test_table2_iterations(row):
+    p, N, k = int(row[0]), int(row[1]), float(row[2])
+    n = int(round(np.sqrt(N)))
+    for l, ref in zip((1, 2, 3, 4), row[3:]):
+        disc = _square(n, p, k, "dirichlet", dict(kind="dirichlet_hankel", center=(-2.0, 1.0)))
+        D = dp.LiteralDP(disc, l)
+        D.solve(tol=1e-10, max_iter=100)
+        if ref == "-":
+            assert D.iters >= 95
+        else:
+            assert abs(D.iters - int(ref)) <= 2, (p, N, k, l, D.iters)
+
+
+def _max_err(mesh, deg, phis, fun):
+    vals = pb.gll_field(mesh, deg, phis)
+    err = 0.0
+    for e in range(mesh.E):
+        n = int(deg[e]) + 1
+        (ox, oy), (hx, hy) = mesh.origin(e), mesh.size(e)
+        t = lg.gll_nodes(n)
+        X, Y = np.meshgrid(ox + (t + 1) * hx / 2, oy + (t + 1) * hy / 2, indexing="xy")
+        err = max(err, np.abs(vals[e] - fun(X.ravel(), Y.ravel())).max())
+    return err
+
+
+def test_plane_wave_solution_equals_direct_and_converges_spectrally():
+    errs = []
+    for p in (5, 8, 11):
+        w = W.plane_wave_4x4()
+        w["degree"] = np.full(16, p)
+        disc = pb.Discretisation(w)
+        D = dp.LiteralDP(disc, 1)
+        phis = D.solve(tol=1e-13, max_iter=400)
+        ref = direct.conforming_solution(disc)
+        assert max(np.abs(a - b).max() for a, b in zip(phis, ref)) < 1e-10
+        errs.append(_max_err(disc.mesh, disc.degrees, phis, pb.exact_plane_wave(w)))
+    assert errs[0] > 1e3 * errs[2] and errs[2] < 1e-10, errs
+
+
+def test_structure_of_the_split():
+    w = W.small_uniform(3, 5, 9.0, l=2)
+    disc = pb.Discretisation(w)
+    D = dp.LiteralDP(disc, 2)
+    assert np.abs(D.Cp @ D.Z).max() < 1e-13
+    assert np.linalg.matrix_rank(D.Z) == D.Z.shape[1]
+    assert D.Z.shape[1] == D.Z.shape[0] - np.linalg.matrix_rank(D.Cp)
+    # A_11 is block diagonal, one block per element
+    el_of, _ = D._element_of_type1()
+    off_block = el_of[:, None] != el_of[None, :]
+    assert np.abs(D.A11[off_block]).max() < 1e-13
+    # complex symmetry of the element blocks and of F
+    assert np.allclose(D.Ah, D.Ah.T) and np.allclose(D.F, D.F.T)
+    # F and the interface right-hand side do not depend on the basis of the nullspace
+    T = np.eye(D.Z.shape[1]) + 0.1 * np.random.default_rng(1).standard_normal((D.Z.shape[1],) * 2)
+    Z2 = D.Z @ T
+    Ah = Z2.T @ D.A @ Z2
+    Ch = D.Cd @ Z2
+    F2 = Ch @ np.linalg.solve(Ah, Ch.T)
+    assert np.allclose(F2, D.F, atol=1e-10 * np.abs(D.F).max())
+    # the preconditioned projection C* C^ is a projection (Sec. 2.3.1)
+    Cst = D.Ch.T @ np.linalg.inv(D.Ch @ D.Ch.T)
+    Pr = Cst @ D.Ch
+    assert np.allclose(Pr @ Pr, Pr, atol=1e-12)
+
+
+@pytest.mark.parametrize("n,p,k,l", [(4, 8, 10.0, 1), (4, 6, 7.0, 2), (3, 5, 12.0, 3)])
+def test_elementwise_equals_literal(n, p, k, l):
+    w = W.small_uniform(n, p, k, l=l)
+    disc = pb.Discretisation(w)
+    D = dp.LiteralDP(disc, l)
+    E = dpe.ElementwiseDP(disc, l)
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal(E.nlam) + 1j * rng.standard_normal(E.nlam)
+    assert np.allclose(E.apply_F(v), D.F @ v, rtol=1e-12, atol=1e-12 * np.abs(D.F @ v).max())
+    assert np.allclose(E.apply_P(v), D.Pinv @ v, rtol=1e-12, atol=1e-12 * np.abs(D.Pinv @ v).max())
+    assert np.allclose(E.interface_rhs(), D.g, atol=1e-12 * np.abs(D.g).max())
+    p1, p2 = D.solve(1e-12), E.solve(1e-12)
+    assert D.iters == E.iters
+    assert max(np.abs(a - b).max() for a, b in zip(p1, p2)) < 1e-11
+
+
+def test_point_source_split_matches_direct():
+    w = W.small_uniform(4, 6, 9.0, rhs=dict(kind="point", points=[(0.5, 0.5)]), l=2)
+    disc = pb.Discretisation(w)
+    E = dpe.ElementwiseDP(disc, 2)
+    phis = E.solve(1e-13)
+    ref = direct.conforming_solution(disc)
+    assert max(np.abs(a - b).max() for a, b in zip(phis, ref)) < 1e-10
+
+
+def _refined_small(pvals=None, seed=0):
+    lv = W.refine_where(W.morton_leaves(3, 3), 0, 1, 0, 1, 3, 3,
+                        lambda x, y: (x - 0.5) ** 2 + (y - 0.5) ** 2 < 0.02, 2)
+    rng = np.random.default_rng(seed)
+    deg = np.full(len(lv), 4) if pvals is None else rng.integers(pvals[0], pvals[1] + 1, len(lv))
+    return dict(domain=(0.0, 1.0, 0.0, 1.0), base=(3, 3), leaves=lv, degree=deg, k=6.0,
+                bc="impedance", rhs=dict(kind="plane_wave_total", angles=[0.4]))
+
+
+@pytest.mark.parametrize("pvals", [None, (3, 6)])
+def test_nonconforming_dp_equals_direct_and_is_continuous(pvals):
+    w = _refined_small(pvals)
+    disc = pb.Discretisation(w)
+    mesh = disc.mesh
+    assert mesh.Lmax == 2
+    D = dp.LiteralDP(disc, 1)
+    assert np.abs(D.C2).max() > 0          # hanging edges give a non-zero C_2
+    phis = D.solve(tol=1e-13, max_iter=500)
+    ref = direct.conforming_solution(disc)
+    assert max(np.abs(a - b).max() for a, b in zip(phis, ref)) < 1e-9
+    # strong continuity across every edge, hanging ones included
+    for e in range(mesh.E):
+        for side in (1, 2, 3, 4):
+            if mesh.boundary_side(e, side):
+                continue
+            for (f, sf) in mesh.neighbours(e, side):
+                _check_trace_match(mesh, disc.degrees, phis, e, side, f, sf)
+
+
+def _eval_at(mesh, deg, phis, e, x, y):
+    n = int(deg[e]) + 1
+    (ox, oy), (hx, hy) = mesh.origin(e), mesh.size(e)
+    u, v = 2 * (x - ox) / hx - 1, 2 * (y - oy) / hy - 1
+    Phi = phis[e].reshape(n, n, order="F")
+    return np.einsum("iq,ij,jq->q", lg.basis_N(u, n), Phi, lg.basis_N(v, n))
+
+
+def _check_trace_match(mesh, deg, phis, e, side, f, sf):
+    key, lo, hi = mesh.side_segment(e, side)
+    _, lo2, hi2 = mesh.side_segment(f, sf)
+    a, b = max(lo, lo2), min(hi, hi2)
+    t = np.linspace(a, b, 7)
+    if key[0] == "v":
+        x = np.full(7, mesh.x0 + key[1] * mesh.fine_hx)
+        y = mesh.y0 + t * mesh.fine_hy
+    else:
+        y = np.full(7, mesh.y0 + key[1] * mesh.fine_hy)
+        x = mesh.x0 + t * mesh.fine_hx
+    ve = _eval_at(mesh, deg, phis, e, x, y)
+    vf = _eval_at(mesh, deg, phis, f, x, y)
+    assert np.abs(ve - vf).max() < 1e-9
+
+
+def test_algorithm1_counts_conforming():
+    # 4 vertices + 4(l-1) low bubbles leave every element of a conforming mesh
+    w = W.small_uniform(4, 7, 5.0, l=3)
+    mesh = pb.make_mesh(w)
+    st = cs.algorithm1(mesh, w["degree"], 3, {s: "robin" for s in (1, 2, 3, 4)})
+    for e in range(mesh.E):
+        assert (st[e] != 1).sum() == 4 * 3
+    # one kept copy per mesh vertex and per low bubble of every edge
+    n_vert = 5 * 5
+    n_edge = 2 * 4 * 5
+    assert sum((s == 2).sum() for s in st) == n_vert + n_edge * 2
+
+
+def test_far_field_of_an_outgoing_cylindrical_wave():
+    # u_s = H_0^(1)(k |x - x0|) with x0 inside Gamma has E_far = (4/k) e^{-i k xhat.x0}
+    w = W.small_uniform(8, 20, 12.0, domain=(-1.0, 1.0, -1.0, 1.0))
+    mesh = pb.make_mesh(w)
+    c = W.leaf_centres(w)
+    inside = (np.abs(c[:, 0]) < 0.5) & (np.abs(c[:, 1]) < 0.5)
+    k, x0 = 12.0, np.array([0.1, -0.2])
+    phis = ff.interpolate_function(mesh, w["degree"],
+                                   lambda X, Y: hankel1(0, k * np.hypot(X - x0[0], Y - x0[1])))
+    ang = np.linspace(0, 2 * np.pi, 9)
+    E = ff.far_field(mesh, w["degree"], phis, k, inside, ang)
+    ref = 4 / k * np.exp(-1j * k * (np.cos(ang) * x0[0] + np.sin(ang) * x0[1]))
+    assert np.abs(E - ref).max() < 1e-11
+    assert np.allclose(ff.rcs(ref, k), 4.0 / k)
