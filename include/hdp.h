@@ -1,0 +1,197 @@
+/*
+ * hdp -- dual-primal spectral-element Helmholtz solver for MI355X (gfx950).
+ *
+ * C ABI of the interface-problem solver of Galagusz & McFee, "An iterative
+ * domain decomposition, spectral finite element method on non-conforming
+ * meshes suitable for high frequency Helmholtz problems" (arXiv:1808.04713).
+ *
+ * The boundary value problem is the paper's prototype PDE (Sec. 2, eqs.
+ * prototype_pde and prototype_robin) with alpha = I, beta = -k^2 eps_r
+ * (piecewise constant per element) and, on the whole outer boundary, the
+ * first-order impedance condition d_n u - i k u = g (time factor e^{-i w t};
+ * Robin coefficient gamma = -i k).  The discretisation is the paper's
+ * integrated-Legendre spectral element method on axis-aligned quadtree
+ * leaves (Sec. 2.1-2.2); continuity is imposed by hierarchical edge moments
+ * whose first l+1 orders per edge form the primal (coarse) space and whose
+ * remaining orders are dual (Sec. 2.3.2-2.3.4).  The interface system
+ * C^ A^-1 C^T nu = C^ A^-1 b^ (eq. schur_complement_system) is solved by
+ * left-preconditioned GMRES with the Laplace-only Dirichlet preconditioner
+ * (eqs. general_preconditioner, weight_matrix).
+ *
+ * Conventions
+ *  - Complex numbers are interleaved (re, im) doubles (hdp_c64).
+ *  - Elements are the mesh leaves in the caller's order.  Element e has
+ *    degree p_e and n_e = p_e + 1 modes per direction.
+ *  - Fields are returned at the (n_e x n_e) tensor Gauss-Lobatto-Legendre
+ *    nodes of each element, x index fastest, elements concatenated in leaf
+ *    order; with several right-hand sides the field of RHS r starts at
+ *    r * sum_e n_e^2 (RHS-major).
+ *  - Dual vectors passed to the operator entry points use the solver's
+ *    internal layout: row-major [n_lambda][n_rhs] (RHS index fastest).
+ *    Dual rows are numbered edge by edge in the visiting order of the
+ *    paper's Algorithm 1 (finest level first, leaves in caller order, sides
+ *    left, right, bottom, top), orders k = l+1 .. max(p_a, p_b) ascending;
+ *    a row reads +sqrt(2) times the neighbour's trace coefficient minus
+ *    sqrt(2) times the visiting element's (eq. final_constraint in the
+ *    vertex basis of eq. interpolatory_relation).
+ *  - Pointers documented as "device" must be device memory of the handle's
+ *    device; all work is enqueued on the handle's stream.  Unless stated
+ *    otherwise the call returns after the stream has finished that work.
+ *  - The caller owns every array it passes.  A handle owns its device
+ *    memory.  Handles are not thread-safe; distinct handles are independent.
+ *  - On an error (negative status) output arrays are left untouched and
+ *    hdp_last_error_detail() describes the cause.
+ */
+#ifndef HDP_H
+#define HDP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } hdp_c64;
+
+typedef enum {
+  HDP_OK = 0,
+  HDP_W_NOT_CONVERGED = 1,  /* outputs hold the last iterate */
+  HDP_E_ARG = -1,           /* invalid argument (null pointer, size, NaN) */
+  HDP_E_MESH = -2,          /* leaves do not tile the domain, or unsupported topology */
+  HDP_E_RESONANCE = -3,     /* an element block A_11 is (near) singular at this k */
+  HDP_E_COARSE = -4,        /* coarse matrix K singular */
+  HDP_E_DEVICE = -5,        /* HIP runtime error */
+  HDP_E_NOMEM = -6,         /* device allocation failed */
+  HDP_E_UNSUPPORTED = -7    /* valid input outside what this build implements */
+} hdp_status;
+
+enum { HDP_FP64 = 0, HDP_MIXED = 1 };
+
+enum {
+  HDP_RHS_PLANE_WAVE_TOTAL = 0,     /* total field e^{ik d.x} through impedance data g = ik(d.n-1)u */
+  HDP_RHS_POINT = 1,                /* unit point source delta(x - x0) */
+  HDP_RHS_PLANE_WAVE_SCATTERED = 2  /* scattered field: f = k^2 (eps_r - 1) e^{ik d.x}, g = 0 */
+};
+
+typedef struct {
+  double x0, x1, y0, y1;      /* domain */
+  int32_t base_nx, base_ny;   /* base grid; each cell roots a quadtree */
+  int32_t n_leaves;
+  const int32_t* leaf;        /* host, 3 per leaf: level, ix, iy (ix,iy on that level's grid) */
+  const int32_t* degree;      /* host, p per leaf, 1 <= p <= 40 */
+} hdp_mesh;
+
+typedef struct {
+  double k;                   /* free-space wavenumber, > 0 */
+  const double* eps_r;        /* host, per leaf relative permittivity; NULL means 1 */
+  int32_t l;                  /* coarse order; <= 0 selects the dispersion rule (Sec. 2.3.4) */
+  int32_t l_safety;           /* added to the rule's value (the paper adds 1 in Sec. 3.3) */
+} hdp_problem;
+
+typedef struct {
+  int32_t precision;          /* HDP_FP64, or HDP_MIXED (FP32 local operators, FP64 outer GMRES) */
+  double tol;                 /* preconditioned relative residual target, e.g. 1e-8 */
+  int32_t max_iter;           /* GMRES iteration cap (no restart) */
+  int32_t max_rhs;            /* largest n_rhs that hdp_solve will receive */
+  void* stream;               /* hipStream_t or NULL for the null stream */
+} hdp_options;
+
+typedef struct {
+  int32_t kind;               /* HDP_RHS_* */
+  int32_t n_rhs;              /* 1 .. max_rhs */
+  const double* angles;       /* host, n_rhs propagation angles (plane-wave kinds) */
+  const double* points;       /* host, 2*n_rhs source points (HDP_RHS_POINT) */
+} hdp_rhs;
+
+typedef struct {
+  int64_t dof;                /* sum_e n_e^2 */
+  int32_t n_elements, n_lambda, n_coarse, l, n_classes;
+  int32_t iterations;         /* GMRES iterations (max over RHS; mixed: inner iterations in total) */
+  int32_t refinements;        /* outer refinement steps (mixed precision), else 0 */
+  double rel_residual;        /* final preconditioned relative residual, max over RHS */
+  double min_element_margin;  /* min over element classes of min|lambda_x+lambda_y| / max|.| */
+  double setup_ms, solve_ms;
+} hdp_stats;
+
+typedef struct hdp_handle hdp_handle;
+
+/* Build the solver (paper Sec. 2.3.2-2.3.3): classify leaves into element
+ * classes, compute each class's separable eigenbasis and boundary operators,
+ * number dual rows and coarse unknowns (Algorithm 1), assemble the coarse
+ * matrix K = A_22 - A_12^T A_11^-1 A_12 and invert it on the device.
+ * Supported meshes: conforming quadtree leaves (every interior side shared
+ * by exactly two leaves of equal size); others return HDP_E_UNSUPPORTED.
+ * Requires l < p_e for every element. */
+hdp_status hdp_setup(const hdp_mesh* mesh, const hdp_problem* prob,
+                     const hdp_options* opt, hdp_handle** out);
+
+/* Solve for n_rhs right-hand sides at once (paper Sec. 2.3.1: interface
+ * right-hand side, GMRES on the interface problem, recovery of phi).
+ * field: device, n_rhs * dof complex values at GLL nodes (RHS-major), or NULL.
+ * far:   device, n_rhs * n_far complex values E_far(phi_q) (Sec. 3.3.1, for the
+ *        e^{-i w t} convention) over the boundary of the leaves with
+ *        far_inside[e] != 0, or NULL.  far_angles: host, n_far observation
+ *        angles.  far_inside: host, one byte per leaf.
+ * Returns HDP_W_NOT_CONVERGED if some RHS did not reach tol in max_iter. */
+hdp_status hdp_solve(hdp_handle* h, const hdp_rhs* rhs, hdp_c64* field,
+                     int32_t n_far, const double* far_angles, const uint8_t* far_inside,
+                     hdp_c64* far, hdp_stats* stats);
+
+/* u = F v with F = C^ A^-1 C^T (eq. schur_complement_system, conforming form
+ * C_1 [A_11^-1 + A_11^-1 A_12 K^-1 A_12^T A_11^-1] C_1^T).  v, u: device,
+ * [n_lambda][n_rhs] complex.  precision selects FP64 or FP32 local operators. */
+hdp_status hdp_apply_interface(hdp_handle* h, const hdp_c64* v, hdp_c64* u,
+                               int32_t n_rhs, int32_t precision);
+
+/* u = P^-1 v with the Dirichlet preconditioner built from the Laplace-only
+ * part (eq. general_preconditioner with W_1 of eq. weight_matrix, W_2 = 0).
+ * Layout as hdp_apply_interface. */
+hdp_status hdp_apply_precond(hdp_handle* h, const hdp_c64* v, hdp_c64* u,
+                             int32_t n_rhs, int32_t precision);
+
+/* g = C^ A^-1 b^ (the interface right-hand side) for the given RHS.
+ * g: device, [n_lambda][n_rhs]. */
+hdp_status hdp_interface_rhs(hdp_handle* h, const hdp_rhs* rhs, hdp_c64* g);
+
+/* x_e = A_e^-1 y_e for every element by the separable fast solver
+ * X = E_x [(E_x^T Y E_y) ./ (lambda_x,i + lambda_y,j)] E_y^T (Sec. 2.2.1 remark
+ * on the fast solver), on the full element matrix in the vertex basis of
+ * eq. interpolatory_relation.  y, x: device, [sum_e n_e^2][n_rhs] complex,
+ * element blocks in leaf order, x-mode fastest inside a block. */
+hdp_status hdp_local_solve(hdp_handle* h, const hdp_c64* y, hdp_c64* x, int32_t n_rhs);
+
+/* Host-only analysis of a problem without touching the device: sizes, l,
+ * number of element classes and the smallest separable-solver margin
+ * min|lambda_x + lambda_y| / max|lambda_x + lambda_y| over classes (an
+ * element resonance, Sec. 2.3.4, drives it to zero). */
+hdp_status hdp_inspect(const hdp_mesh* mesh, const hdp_problem* prob, hdp_stats* stats);
+
+/* Sizes of the handle's problem (host call, no device work). */
+hdp_status hdp_get_stats(const hdp_handle* h, hdp_stats* stats);
+
+/* Kernel timing.  While enabled, every kernel launch family of the handle is
+ * bracketed by HIP events on the handle's stream; hdp_profile_read returns,
+ * per family, the launches, the summed event durations and the algorithmic
+ * HBM bytes and floating-point operations of those launches (sizes of the
+ * operands each launch must read and write once, and the useful arithmetic).
+ * enable = 1 clears and starts, 0 stops.  Profiling adds per-launch event
+ * overhead and is meant for measurement runs. */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+  double bytes;
+  double flops;
+} hdp_kernel_time;
+hdp_status hdp_profile(hdp_handle* h, int32_t enable);
+hdp_status hdp_profile_read(const hdp_handle* h, hdp_kernel_time* out, int32_t max, int32_t* count);
+
+void hdp_destroy(hdp_handle* h);
+const char* hdp_status_string(hdp_status s);
+const char* hdp_last_error_detail(void);   /* thread-local, valid until the next call */
+
+#ifdef __cplusplus
+}
+#endif
+#endif

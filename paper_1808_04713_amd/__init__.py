@@ -1,0 +1,249 @@
+"""Python binding of libhdp, the MI355X dual-primal spectral-element Helmholtz
+solver (Galagusz & McFee, arXiv:1808.04713).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch provides device memory and the current stream.  Importing this module
+does not need a GPU; creating a Solver does, and it fails loudly when the
+library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhdp.so")
+
+HDP_FP64, HDP_MIXED = 0, 1
+RHS_KINDS = {"plane_wave_total": 0, "point": 1, "plane_wave_scattered": 2}
+STATUS_OK, STATUS_NOT_CONVERGED = 0, 1
+
+
+class HdpError(RuntimeError):
+    def __init__(self, status, detail):
+        super().__init__(f"hdp status {status}: {detail}")
+        self.status = status
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double),
+                ("y1", ctypes.c_double), ("base_nx", ctypes.c_int32), ("base_ny", ctypes.c_int32),
+                ("n_leaves", ctypes.c_int32), ("leaf", ctypes.POINTER(ctypes.c_int32)),
+                ("degree", ctypes.POINTER(ctypes.c_int32))]
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_double), ("eps_r", ctypes.POINTER(ctypes.c_double)),
+                ("l", ctypes.c_int32), ("l_safety", ctypes.c_int32)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("max_rhs", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class _Rhs(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_rhs", ctypes.c_int32),
+                ("angles", ctypes.POINTER(ctypes.c_double)), ("points", ctypes.POINTER(ctypes.c_double))]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("dof", ctypes.c_int64), ("n_elements", ctypes.c_int32), ("n_lambda", ctypes.c_int32),
+                ("n_coarse", ctypes.c_int32), ("l", ctypes.c_int32), ("n_classes", ctypes.c_int32),
+                ("iterations", ctypes.c_int32), ("refinements", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("min_element_margin", ctypes.c_double),
+                ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
+
+
+EXPORTS = ["hdp_inspect", "hdp_setup", "hdp_solve", "hdp_apply_interface", "hdp_apply_precond",
+           "hdp_interface_rhs", "hdp_local_solve", "hdp_get_stats", "hdp_profile", "hdp_profile_read",
+           "hdp_destroy", "hdp_status_string", "hdp_last_error_detail"]
+
+_lib = None
+
+
+def load_library():
+    """Load libhdp.so (no GPU needed) and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)
+    L.hdp_setup.argtypes = [ctypes.POINTER(_Mesh), ctypes.POINTER(_Problem), ctypes.POINTER(_Options),
+                            ctypes.POINTER(vp)]
+    L.hdp_solve.argtypes = [vp, ctypes.POINTER(_Rhs), vp, i32, dp, ctypes.POINTER(ctypes.c_uint8), vp,
+                            ctypes.POINTER(Stats)]
+    L.hdp_apply_interface.argtypes = [vp, vp, vp, i32, i32]
+    L.hdp_apply_precond.argtypes = [vp, vp, vp, i32, i32]
+    L.hdp_interface_rhs.argtypes = [vp, ctypes.POINTER(_Rhs), vp]
+    L.hdp_local_solve.argtypes = [vp, vp, vp, i32]
+    L.hdp_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    L.hdp_inspect.argtypes = [ctypes.POINTER(_Mesh), ctypes.POINTER(_Problem), ctypes.POINTER(Stats)]
+    L.hdp_profile.argtypes = [vp, i32]
+    L.hdp_profile_read.argtypes = [vp, ctypes.POINTER(KernelTime), i32, ctypes.POINTER(i32)]
+    L.hdp_destroy.argtypes = [vp]
+    L.hdp_destroy.restype = None
+    L.hdp_status_string.restype = ctypes.c_char_p
+    L.hdp_last_error_detail.restype = ctypes.c_char_p
+    for name in ("hdp_inspect", "hdp_setup", "hdp_solve", "hdp_apply_interface", "hdp_apply_precond",
+                 "hdp_interface_rhs", "hdp_local_solve", "hdp_get_stats", "hdp_profile", "hdp_profile_read"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status, allow_not_converged=False):
+    if status == STATUS_OK or (allow_not_converged and status == STATUS_NOT_CONVERGED):
+        return status
+    L = load_library()
+    raise HdpError(status, L.hdp_last_error_detail().decode())
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _structs(w, l_safety=0):
+    leaves = np.ascontiguousarray(np.asarray(w["leaves"], dtype=np.int32).reshape(-1, 3))
+    deg = np.ascontiguousarray(np.asarray(w["degree"], dtype=np.int32))
+    eps = np.ascontiguousarray(np.asarray(w.get("eps_r", np.ones(len(deg))), dtype=np.float64))
+    x0, x1, y0, y1 = w["domain"]
+    mesh = _Mesh(x0, x1, y0, y1, int(w["base"][0]), int(w["base"][1]), len(deg),
+                 leaves.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                 deg.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    prob = _Problem(float(w["k"]), eps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                    int(w.get("l", -1)), int(l_safety))
+    return mesh, prob, (leaves, deg, eps)
+
+
+def inspect(w, l_safety=0):
+    """Host-only analysis (no GPU): sizes, l, classes, smallest solver margin."""
+    L = load_library()
+    mesh, prob, keep = _structs(w, l_safety)
+    st = Stats()
+    _check(L.hdp_inspect(ctypes.byref(mesh), ctypes.byref(prob), ctypes.byref(st)))
+    return st.as_dict()
+
+
+class Solver:
+    """setup(mesh, degrees, k, coefficients, constraint set) -> solve(rhs) -> field.
+
+    mesh: dict with domain (x0,x1,y0,y1), base (nx,ny), leaves [(level,ix,iy)],
+    degree (per leaf), k, eps_r (per leaf) and l (<= 0: dispersion rule).
+    """
+
+    def __init__(self, w, precision="fp64", tol=1e-8, max_iter=300, max_rhs=1, l_safety=0, device=0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("hdp needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        L = load_library()
+        mesh, prob, self._keep = _structs(w, l_safety)
+        self.precision = HDP_MIXED if precision == "mixed" else HDP_FP64
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            opt = _Options(self.precision, float(tol), int(max_iter), int(max_rhs), ctypes.c_void_p(stream))
+            h = ctypes.c_void_p()
+            _check(L.hdp_setup(ctypes.byref(mesh), ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(h)))
+        self.h = h
+        self.max_rhs = max_rhs
+        st = Stats()
+        _check(L.hdp_get_stats(self.h, ctypes.byref(st)))
+        self.info = st.as_dict()
+        self.dof, self.n_lambda, self.n_coarse = st.dof, st.n_lambda, st.n_coarse
+
+    def close(self):
+        if getattr(self, "h", None):
+            load_library().hdp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _rhs(self, kind, values):
+        vals = np.ascontiguousarray(np.asarray(values, dtype=np.float64))
+        n = len(vals) if RHS_KINDS[kind] != 1 else len(vals.reshape(-1, 2))
+        r = _Rhs(RHS_KINDS[kind], n, None, None)
+        ptr = vals.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if kind == "point":
+            r.points = ptr
+        else:
+            r.angles = ptr
+        return r, vals, n
+
+    def solve(self, kind, values, want_field=True):
+        """Returns (field, stats): field is a (n_rhs, dof) complex128 tensor of
+        GLL-node values (element blocks in leaf order, x fastest) or None."""
+        torch = self.torch
+        r, keep, n = self._rhs(kind, values)
+        field = torch.empty((n, self.dof), dtype=torch.complex128, device=self.device) if want_field else None
+        st = Stats()
+        status = load_library().hdp_solve(self.h, ctypes.byref(r), _dptr(field) if want_field else None,
+                                          0, None, None, None, ctypes.byref(st))
+        _check(status, allow_not_converged=True)
+        d = st.as_dict()
+        d["converged"] = status == STATUS_OK
+        return field, d
+
+    def apply_interface(self, v, precision=None):
+        """u = F v; v is a (n_lambda, n_rhs) complex128 device tensor."""
+        v = v.contiguous()
+        u = self.torch.empty_like(v)
+        p = self.precision if precision is None else (HDP_MIXED if precision == "mixed" else HDP_FP64)
+        _check(load_library().hdp_apply_interface(self.h, _dptr(v), _dptr(u), v.shape[1], p))
+        return u
+
+    def apply_precond(self, v, precision=None):
+        v = v.contiguous()
+        u = self.torch.empty_like(v)
+        p = self.precision if precision is None else (HDP_MIXED if precision == "mixed" else HDP_FP64)
+        _check(load_library().hdp_apply_precond(self.h, _dptr(v), _dptr(u), v.shape[1], p))
+        return u
+
+    def interface_rhs(self, kind, values):
+        r, keep, n = self._rhs(kind, values)
+        g = self.torch.empty((self.n_lambda, n), dtype=self.torch.complex128, device=self.device)
+        _check(load_library().hdp_interface_rhs(self.h, ctypes.byref(r), _dptr(g)))
+        return g
+
+    def profile(self, enable=True):
+        """Bracket every kernel launch family with HIP events (enable clears totals)."""
+        _check(load_library().hdp_profile(self.h, 1 if enable else 0))
+
+    def kernel_times(self):
+        """Per launch family: launches, summed event ms, algorithmic bytes and flops."""
+        L = load_library()
+        buf = (KernelTime * 64)()
+        n = ctypes.c_int32()
+        _check(L.hdp_profile_read(self.h, buf, 64, ctypes.byref(n)))
+        return [dict(name=buf[i].name.decode(), launches=buf[i].launches, total_ms=buf[i].total_ms,
+                     bytes=buf[i].bytes, flops=buf[i].flops) for i in range(n.value)]
+
+    def local_solve(self, y):
+        """x_e = A_e^-1 y_e by the separable fast solver; y is (dof, n_rhs)."""
+        y = y.contiguous()
+        x = self.torch.empty_like(y)
+        _check(load_library().hdp_local_solve(self.h, _dptr(y), _dptr(x), y.shape[1]))
+        return x
+
+
+def rhs_values(w):
+    """(kind, values) of a workload's right-hand side."""
+    rhs = w["rhs"]
+    if rhs["kind"] == "point":
+        return "point", np.asarray(rhs["points"], float).reshape(-1)
+    return rhs["kind"], np.asarray(rhs["angles"], float)

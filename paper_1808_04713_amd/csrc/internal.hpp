@@ -1,0 +1,161 @@
+// Internal state of a solver handle and the kernel launch interface.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hdp.h"
+#include "dense.hpp"
+
+namespace hdp {
+
+struct Error {
+  hdp_status status;
+  std::string msg;
+};
+[[noreturn]] void fail(hdp_status s, const std::string& msg);
+void check_hip(hipError_t e, const char* what);
+#define HIPCHECK(x) ::hdp::check_hip((x), #x)
+
+// One element class: every element with the same degree, size, material and
+// boundary pattern shares all operators below (vertex basis of
+// eq. interpolatory_relation, flat mode index ix + n*iy).
+struct ElemClass {
+  int p = 0, n = 0;
+  double hx = 0, hy = 0, eps = 1;
+  int bmask = 0;               // bit (s-1): side s on the outer impedance boundary
+  int m = 0, nr = 0;           // dual slots, coarse modes (4l)
+  std::vector<int> R;          // coarse (removed, type-2) modes, canonical order
+  std::vector<int> Gam;        // dual-touched type-1 edge modes, slot order
+  MatC Ex, Ey;                 // generalised eigenvectors, E^T M~ E = I
+  std::vector<cd> Dg;          // (hy/2) lx_i + (hx/2) ly_j, index i + n j
+  MatC G;                      // A~^-1 E_R           (n^2 x nr)
+  MatC Kc;                     // (E_R^T A~^-1 E_R)^-1 (nr x nr)
+  MatC Op1;                    // [D_c ; Phi_c^T]      ((m+nr) x m)
+  MatC Phi;                    // Phi_c = -G_Gam Kc    (m x nr)
+  MatD Se;                     // Laplace-only Schur complement on Gam (m x m)
+  double margin = 0;           // min|Dg| / max|Dg|
+  std::vector<int> elems;      // members, leaf indices
+};
+
+// Device copies of one precision of the class operators.
+template <class T>
+struct DevOps {
+  T* op1 = nullptr;   // per class, column-major (m+nr) x m
+  T* phi = nullptr;   // per class, column-major m x nr
+  T* se = nullptr;    // per class, column-major m x m (real part only used)
+};
+
+enum KernelFamily {
+  KF_SLOT_F = 0, KF_SLOT_P, KF_ASSEMBLE, KF_COARSE, KF_SLOT_COARSE, KF_ROWGATHER, KF_DOTS, KF_UPDATE,
+  KF_NORM_SCALE, KF_FDM, KF_ELEMENT_MISC, KF_GLL, KF_CAST, KF_COUNT
+};
+extern const char* const KF_NAMES[KF_COUNT];
+
+struct Prof {
+  bool on = false;
+  struct Pending { int fam; hipEvent_t a, b; double bytes, flops; };
+  std::vector<Pending> pend;
+  std::vector<hipEvent_t> pool;
+  double ms[KF_COUNT] = {0}, bytes[KF_COUNT] = {0}, flops[KF_COUNT] = {0};
+  int64_t n[KF_COUNT] = {0};
+};
+
+struct Handle {
+  // problem
+  int E = 0, l = 0, nlam = 0, nK = 0;
+  int64_t dof = 0;
+  double k = 0;
+  int max_rhs = 1, max_iter = 100, precision = HDP_FP64;
+  double tol = 1e-8;
+  hipStream_t stream = nullptr;
+  std::vector<int> deg;
+  std::vector<double> eps;
+  std::vector<double> ox, oy, hx, hy;   // element origin and size
+  std::vector<int> cls;                 // class of each element
+  std::vector<ElemClass> classes;
+  std::vector<int> bmask;
+  // offsets
+  std::vector<int64_t> dof_off;   // per element, n_e^2 blocks
+  std::vector<int> slot_off;      // per element, dual slots
+  std::vector<int> cm_off;        // per element, coarse modes
+  int nslots = 0, ncm = 0;
+  // dual rows: up to two (slot, coef) entries each
+  std::vector<int> row_slot;      // 2 * nlam, -1 if absent
+  std::vector<double> row_coef;   // 2 * nlam
+  std::vector<double> row_xinv;   // 1 / (C_1 C_1^T)_rr
+  std::vector<int> slot_row;      // per slot
+  std::vector<double> slot_coef;
+  std::vector<int> slot_mode;     // per slot, local mode index (for full arrays)
+  // coarse map
+  std::vector<int> cm_dof;        // per coarse mode, global coarse unknown
+  std::vector<int> cdof_ptr, cdof_list;  // CSR: coarse unknown -> coarse modes
+  std::vector<int> cm_mode;       // per coarse mode, local mode index
+  // class-sorted element order and launch tables
+  std::vector<int> order;         // elements grouped by class
+  double min_margin = 1;
+  double setup_ms = 0;
+  // algorithmic work per right-hand side (bytes of class operators are
+  // counted once per launch, like any operand read from memory once)
+  double op1_bytes = 0, se_bytes = 0, phi_bytes = 0;
+  double flops_F = 0, flops_P = 0, flops_coarse = 0, flops_fdm = 0, flops_gll = 0;
+
+  // device buffers --------------------------------------------------------
+  struct Dev {
+    // maps
+    int *elem_cls = nullptr, *order = nullptr, *slot_off = nullptr, *cm_off = nullptr;
+    int64_t* dof_off = nullptr;
+    int *row_slot = nullptr, *slot_row = nullptr, *slot_mode = nullptr;
+    int64_t *slot_pos = nullptr, *cm_pos = nullptr;   // positions in full-element arrays
+    double *row_coef = nullptr, *row_xinv = nullptr, *slot_coef = nullptr;
+    int *cm_dof = nullptr, *cdof_ptr = nullptr, *cdof_list = nullptr, *cm_mode = nullptr;
+    // per-class tables
+    int *cls_n = nullptr, *cls_m = nullptr, *cls_nr = nullptr;
+    int64_t *cls_op1 = nullptr, *cls_phi = nullptr, *cls_se = nullptr;   // offsets
+    int64_t *cls_E = nullptr, *cls_D = nullptr, *cls_G = nullptr, *cls_Kc = nullptr, *cls_V = nullptr;
+    int* cls_gam = nullptr;   // per class offset into gam_modes
+    int* gam_modes = nullptr;
+    int* cls_R = nullptr;     // per class offset into r_modes
+    int* r_modes = nullptr;
+    // operators
+    double2 *op1 = nullptr, *phi = nullptr;   // FP64
+    double* se = nullptr;
+    float2 *op1_f = nullptr, *phi_f = nullptr; // FP32 copies
+    float* se_f = nullptr;
+    double2 *Ex = nullptr, *Ey = nullptr, *Dinv = nullptr, *G = nullptr, *Kc = nullptr;
+    double* V = nullptr;      // GLL sampling matrices per class
+    double2* Kinv = nullptr;  // nK x nK, row-major
+    // work
+    double2 *slotA = nullptr, *slotB = nullptr, *cmA = nullptr, *gK = nullptr, *wK = nullptr;
+    float2 *slotA_f = nullptr, *slotB_f = nullptr, *cmA_f = nullptr;
+    double2 *full0 = nullptr, *full1 = nullptr;   // [dof][R]
+    double2 *V_kry = nullptr;                      // (max_iter+1) x nlam x R
+    double2 *w = nullptr, *t0 = nullptr, *t1 = nullptr, *t2 = nullptr;
+    double2 *hbuf = nullptr, *hsum = nullptr, *part = nullptr;
+    double *nrm = nullptr, *npart = nullptr;
+    float2* vf = nullptr;
+    double2* ycoef = nullptr;
+  } d;
+  std::vector<void*> allocations;
+  Prof prof;
+};
+
+// Brackets the launches issued during its lifetime with profiling events.
+struct Timed {
+  Handle& h;
+  int fam;
+  double bytes, flops;
+  hipEvent_t a = nullptr;
+  Timed(Handle& h_, int fam_, double bytes_, double flops_);
+  ~Timed();
+};
+void prof_flush(Handle& h);   // after a stream synchronisation
+
+// setup.cpp
+void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob);
+void build_device(Handle& h);
+void compute_loads(const Handle& h, const hdp_rhs* rhs, std::vector<cd>& B);  // [dof][R]
+
+}  // namespace hdp

@@ -1,0 +1,58 @@
+// Launchers of the device kernels (kernels.hip).  All arrays are device
+// pointers; "R" is the right-hand-side stride (RHS index fastest).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hdp {
+
+struct Handle;
+
+// Class-batched boundary operators on dual slots (one block per element).
+// mode 0: X = D_c y, GL = Phi_c^T y, with y_s = coef_s v[row_s]            (F, first half)
+// mode 1: X = Se y with y_s = coef_s v[row_s] / (C1 C1^T)_row              (P^-1, first half)
+template <class T2>
+void launch_slot_apply(const Handle& h, int mode, const T2* v, T2* X, T2* GL, int R, hipStream_t s);
+// Z = X + Phi_c (T_e w)
+template <class T2>
+void launch_slot_coarse(const Handle& h, const T2* X, const double2* w, T2* Z, int R, hipStream_t s);
+// u[row] = scale_row * sum coef * src[pos(slot)]  (pos = slot if full == false)
+template <class T2>
+void launch_rowgather(const Handle& h, const T2* src, bool full, bool precond, double2* u, int R,
+                      hipStream_t s);
+// g[d] = sum_{coarse modes of d} (GL[i] + (Bfull ? Bfull[pos(i)] : 0))
+template <class T2>
+void launch_assemble(const Handle& h, const T2* GL, const double2* Bfull, double2* g, int R,
+                     hipStream_t s);
+// w = K^-1 g (dense, FP64)
+void launch_coarse_solve(const Handle& h, const double2* g, double2* w, int R, hipStream_t s);
+
+// Full-element operations (arrays [dof][R])
+void launch_fdm(const Handle& h, const double2* in, double2* out, int R, hipStream_t s);
+void launch_zero_R(const Handle& h, double2* X, int R, hipStream_t s);
+void launch_extract_kc(const Handle& h, const double2* X, double2* GL, int R, hipStream_t s);
+void launch_correct(const Handle& h, double2* X, const double2* w, int R, hipStream_t s);
+void launch_sub_dual(const Handle& h, double2* Y, const double2* nu, int R, hipStream_t s);
+void launch_gll(const Handle& h, const double2* X, double2* field, int R, int64_t rhs_stride,
+                int nrhs_out, hipStream_t s);
+
+// Krylov vector kernels (R must divide 256)
+void launch_dots(const double2* V, int64_t vstride, int nvec, const double2* w, int n, int R,
+                 double2* part, int nblk, hipStream_t s);
+void launch_dots_final(const double2* part, int nblk, int nvec, int R, double2* h, double2* hsum,
+                       hipStream_t s);
+void launch_update(const double2* V, int64_t vstride, int nvec, const double2* hcoef, double2* w,
+                   int n, int R, double sign, hipStream_t s);
+void launch_norm(const double2* w, int n, int R, double* part, int nblk, double* nrm, hipStream_t s);
+void launch_scale(const double2* w, const double* nrm, double2* out, int n, int R, hipStream_t s);
+void launch_axpby(const double2* x, const double2* y, double2* z, int64_t count, double a, double b,
+                  hipStream_t s);
+void launch_cast_f(const double2* x, float2* y, int64_t count, hipStream_t s);
+void launch_cast_d(const float2* x, double2* y, int64_t count, hipStream_t s);
+void launch_dense_scatter(const int64_t* idx, const double2* val, int64_t nnz, double2* M,
+                          hipStream_t s);
+
+int dots_blocks(int n, int R);
+
+}  // namespace hdp

@@ -1,0 +1,218 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Tolerances: FP64 path 1e-10 relative L2 on the field (solves driven to 1e-12),
+1e-12 on single operator applications; mixed path 1e-8 on the field."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import dp, dp_elementwise as dpe, element as el, problem as pb
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def hdp():
+    import paper_1808_04713_amd as m
+    return m
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
+
+
+def small_cases():
+    sq = W.small_uniform(6, 6, 12.0, domain=(-1.0, 1.0, -1.0, 1.0), l=2,
+                         rhs=dict(kind="plane_wave_scattered", angles=[0.7]))
+    c = W.leaf_centres(sq)
+    sq["eps_r"] = np.where((np.abs(c[:, 0]) < 0.4) & (np.abs(c[:, 1]) < 0.4), 4.0, 1.0)
+    return {
+        "plane_wave_4x4": W.plane_wave_4x4(),
+        "uniform_4x4_p6_l2": W.small_uniform(4, 6, 7.0, l=2),
+        "uniform_5x5_p7_l3": W.small_uniform(5, 7, 11.0, l=3),
+        "point_4x4_p6": W.small_uniform(4, 6, 9.0, rhs=dict(kind="point", points=[(0.5, 0.5)]), l=2),
+        "scatterer_6x6_p6": sq,
+    }
+
+
+CASES = small_cases()
+
+
+@pytest.fixture(scope="module")
+def oracles():
+    out = {}
+    for name, w in CASES.items():
+        disc = pb.Discretisation(w)
+        l = pb.coarse_order(w, disc.mesh)
+        out[name] = (disc, l, dpe.ElementwiseDP(disc, l))
+    return out
+
+
+def vertex_element_matrices(disc):
+    mats = []
+    for e in range(disc.mesh.E):
+        n = int(disc.degrees[e]) + 1
+        B = el.to_vertex_basis(n)
+        mats.append(B @ disc.A[e] @ B)
+    return mats
+
+
+@pytest.mark.parametrize("name", ["plane_wave_4x4", "scatterer_6x6_p6"])
+def test_local_solve_separable(name, oracles):
+    disc, l, _ = oracles[name]
+    w = CASES[name]
+    s = hdp().Solver(w)
+    R = 3
+    rng = np.random.default_rng(7)
+    y = rng.standard_normal((s.dof, R)) + 1j * rng.standard_normal((s.dof, R))
+    x = s.local_solve(torch.from_numpy(y).cuda()).cpu().numpy()
+    off = 0
+    for A in vertex_element_matrices(disc):
+        n2 = A.shape[0]
+        ref = np.linalg.solve(A, y[off:off + n2])
+        assert rel(x[off:off + n2], ref) < 1e-11
+        off += n2
+    s.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_interface_operator_and_preconditioner(name, oracles):
+    disc, l, E = oracles[name]
+    s = hdp().Solver(CASES[name], max_rhs=2)
+    assert s.n_lambda == E.nlam and s.n_coarse == E.nK
+    rng = np.random.default_rng(11)
+    v = rng.standard_normal((E.nlam, 2)) + 1j * rng.standard_normal((E.nlam, 2))
+    vd = torch.from_numpy(v).cuda()
+    Fv = s.apply_interface(vd, "fp64").cpu().numpy()
+    Pv = s.apply_precond(vd, "fp64").cpu().numpy()
+    for r in range(2):
+        assert rel(Fv[:, r], E.apply_F(v[:, r])) < 1e-12
+        assert rel(Pv[:, r], E.apply_P(v[:, r])) < 1e-12
+    Fv32 = s.apply_interface(vd, "mixed").cpu().numpy()
+    Pv32 = s.apply_precond(vd, "mixed").cpu().numpy()
+    assert rel(Fv32[:, 0], E.apply_F(v[:, 0])) < 1e-4
+    assert rel(Pv32[:, 0], E.apply_P(v[:, 0])) < 1e-5
+    s.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_interface_rhs(name, oracles):
+    disc, l, E = oracles[name]
+    w = CASES[name]
+    s = hdp().Solver(w)
+    kind, vals = hdp().rhs_values(w)
+    g = s.interface_rhs(kind, vals).cpu().numpy()[:, 0]
+    assert rel(g, E.interface_rhs()) < 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve_fp64_matches_oracle(name, oracles):
+    disc, l, E = oracles[name]
+    w = CASES[name]
+    s = hdp().Solver(w, tol=1e-12, max_iter=400)
+    kind, vals = hdp().rhs_values(w)
+    field, st = s.solve(kind, vals)
+    gpu = field.cpu().numpy()[0]
+    phis = E.solve(tol=1e-12, max_iter=400)
+    ref = np.concatenate(pb.gll_field(disc.mesh, disc.degrees, phis))
+    assert st["converged"]
+    assert rel(gpu, ref) < 1e-10
+    assert abs(st["iterations"] - E.iters) <= 1
+    s.close()
+
+
+def test_plane_wave_against_literal_method_and_exact_solution():
+    w = W.plane_wave_4x4()
+    disc = pb.Discretisation(w)
+    D = dp.LiteralDP(disc, 1)
+    phis = D.solve(tol=1e-10, max_iter=300)
+    ref = np.concatenate(pb.gll_field(disc.mesh, disc.degrees, phis))
+    s = hdp().Solver(w, tol=1e-10)
+    field, st = s.solve("plane_wave_total", w["rhs"]["angles"])
+    gpu = field.cpu().numpy()[0]
+    assert rel(gpu, ref) < 1e-9
+    assert abs(st["iterations"] - D.iters) <= 1
+    # the discrete solution approximates the exact plane wave (p = 8)
+    ex = pb.exact_plane_wave(w)
+    from oracle import legendre as lg
+    vals = []
+    for e in range(disc.mesh.E):
+        (ox, oy), (hx, hy) = disc.mesh.origin(e), disc.mesh.size(e)
+        t = lg.gll_nodes(9)
+        X, Y = np.meshgrid(ox + (t + 1) * hx / 2, oy + (t + 1) * hy / 2, indexing="xy")
+        vals.append(ex(X.ravel(), Y.ravel()))
+    assert np.abs(gpu - np.concatenate(vals)).max() < 1e-7
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["plane_wave_4x4", "uniform_5x5_p7_l3", "scatterer_6x6_p6"])
+def test_mixed_precision_solve(name, oracles):
+    disc, l, E = oracles[name]
+    w = CASES[name]
+    s = hdp().Solver(w, precision="mixed", tol=1e-12, max_iter=400)
+    kind, vals = hdp().rhs_values(w)
+    field, st = s.solve(kind, vals)
+    phis = E.solve(tol=1e-12, max_iter=400)
+    ref = np.concatenate(pb.gll_field(disc.mesh, disc.degrees, phis))
+    assert st["converged"] and st["refinements"] >= 1
+    assert rel(field.cpu().numpy()[0], ref) < 1e-8
+    s.close()
+
+
+def test_batched_rhs_equal_single_solves():
+    w = small_cases()["scatterer_6x6_p6"]
+    angles = np.array([0.0, 0.9, 2.1, 4.0, 5.5])
+    s = hdp().Solver(w, tol=1e-12, max_rhs=len(angles))
+    fb, stb = s.solve("plane_wave_scattered", angles)
+    fb = fb.cpu().numpy()
+    for i, a in enumerate(angles):
+        f1, st1 = s.solve("plane_wave_scattered", [a])
+        assert rel(fb[i], f1.cpu().numpy()[0]) < 1e-11
+    s.close()
+
+
+def test_point_source_32x32_against_stored_oracle_samples():
+    """Full-size workload: sampled field values, F v and P^-1 v rows written by
+    tests/golden/make_point_source_32x32.py from the oracle."""
+    path = os.path.join(GOLD, "point_source_32x32_samples.txt")
+    meta, field, Fv, Pv = {}, [], [], []
+    for line in open(path):
+        if line.startswith("#"):
+            continue
+        t = line.split()
+        if t[0] == "field":
+            field.append((int(t[1]), float(t[2]) + 1j * float(t[3])))
+        elif t[0] == "Fv":
+            Fv.append((int(t[1]), float(t[2]) + 1j * float(t[3])))
+        elif t[0] == "Pv":
+            Pv.append((int(t[1]), float(t[2]) + 1j * float(t[3])))
+        else:
+            meta[t[0]] = int(t[1])
+    w = W.point_source_32x32()
+    s = hdp().Solver(w, tol=1e-12, max_iter=400)
+    assert (s.n_lambda, s.n_coarse, s.info["l"]) == (meta["n_lambda"], meta["n_coarse"], meta["l"])
+    rng = np.random.default_rng(meta["vector_seed"])
+    v = rng.standard_normal(s.n_lambda) + 1j * rng.standard_normal(s.n_lambda)
+    vd = torch.from_numpy(v.reshape(-1, 1)).cuda()
+    Fg = s.apply_interface(vd).cpu().numpy()[:, 0]
+    Pg = s.apply_precond(vd).cpu().numpy()[:, 0]
+    iF, vF = zip(*Fv)
+    iP, vP = zip(*Pv)
+    assert rel(Fg[list(iF)], vF) < 1e-11
+    assert rel(Pg[list(iP)], vP) < 1e-12
+    f, st = s.solve("point", [0.5, 0.5])
+    g = f.cpu().numpy()[0]
+    idx, vals = zip(*field)
+    assert rel(g[list(idx)], vals) < 1e-9
+    assert st["converged"]
+    assert abs(st["iterations"] - meta["iterations_1e-12"]) <= 2
+    s.close()
+    s8 = hdp().Solver(w, tol=1e-8, max_iter=400)
+    _, st8 = s8.solve("point", [0.5, 0.5], want_field=False)
+    assert abs(st8["iterations"] - meta["iterations_1e-8"]) <= 1
+    s8.close()
