@@ -35,8 +35,9 @@
  *    sqrt(2) times the visiting element's (eq. final_constraint in the
  *    vertex basis of eq. interpolatory_relation).
  *  - Pointers documented as "device" must be device memory of the handle's
- *    device; all work is enqueued on the handle's stream.  Unless stated
- *    otherwise the call returns after the stream has finished that work.
+ *    device.  A handle issues its work on a stream of its own, ordered after
+ *    the work already enqueued on the caller's stream (hdp_options.stream);
+ *    unless stated otherwise a call returns after that work has finished.
  *  - The caller owns every array it passes.  A handle owns its device
  *    memory.  Handles are not thread-safe; distinct handles are independent.
  *  - On an error (negative status) output arrays are left untouched and
@@ -92,10 +93,15 @@ typedef struct {
 typedef struct {
   int32_t precision;          /* HDP_FP64, or HDP_MIXED (FP32 local operators, FP64 outer GMRES) */
   double tol;                 /* preconditioned relative residual target, e.g. 1e-8 */
-  int32_t max_iter;           /* GMRES iteration cap (no restart) */
-  int32_t max_rhs;            /* largest n_rhs that hdp_solve will receive */
-  void* stream;               /* hipStream_t or NULL for the null stream */
+  int32_t max_iter;           /* GMRES iteration cap (no restart), 1..1000 */
+  int32_t max_rhs;            /* largest n_rhs that hdp_solve will receive, 1..64 */
+  void* stream;               /* caller's hipStream_t (NULL: null stream) the solver orders after */
+  int32_t flags;              /* HDP_FLAG_* bits, 0 for defaults */
 } hdp_options;
+
+/* hdp_options.flags: launch every kernel of a GMRES iteration individually
+ * instead of replaying the iteration as a captured HIP graph. */
+#define HDP_FLAG_EAGER 1
 
 typedef struct {
   int32_t kind;               /* HDP_RHS_* */
@@ -112,6 +118,9 @@ typedef struct {
   double rel_residual;        /* final preconditioned relative residual, max over RHS */
   double min_element_margin;  /* min over element classes of min|lambda_x+lambda_y| / max|.| */
   double setup_ms, solve_ms;
+  /* host-side breakdown of solve_ms: loads and interface right-hand side,
+   * GMRES (launch calls, waits for the device), recovery and sampling */
+  double rhs_ms, gmres_ms, gmres_launch_ms, gmres_wait_ms, recover_ms;
 } hdp_stats;
 
 typedef struct hdp_handle hdp_handle;
@@ -169,6 +178,13 @@ hdp_status hdp_inspect(const hdp_mesh* mesh, const hdp_problem* prob, hdp_stats*
 
 /* Sizes of the handle's problem (host call, no device work). */
 hdp_status hdp_get_stats(const hdp_handle* h, hdp_stats* stats);
+
+/* Preconditioned relative residual ||P^-1 r_k|| / ||P^-1 r_0|| after each
+ * iteration k = 0, 1, .. of the last GMRES run of the handle, for right-hand
+ * side `rhs` (the quantity plotted in the paper's residual figures, Sec. 3.2).
+ * Mixed precision: the last inner run.  count receives the number of entries;
+ * at most max are written to out (host). */
+hdp_status hdp_residual_history(const hdp_handle* h, int32_t rhs, double* out, int32_t max, int32_t* count);
 
 /* Kernel timing.  While enabled, every kernel launch family of the handle is
  * bracketed by HIP events on the handle's stream; hdp_profile_read returns,

@@ -39,7 +39,7 @@ class _Problem(ctypes.Structure):
 
 class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
-                ("max_rhs", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("max_rhs", ctypes.c_int32), ("stream", ctypes.c_void_p), ("flags", ctypes.c_int32)]
 
 
 class _Rhs(ctypes.Structure):
@@ -52,7 +52,9 @@ class Stats(ctypes.Structure):
                 ("n_coarse", ctypes.c_int32), ("l", ctypes.c_int32), ("n_classes", ctypes.c_int32),
                 ("iterations", ctypes.c_int32), ("refinements", ctypes.c_int32),
                 ("rel_residual", ctypes.c_double), ("min_element_margin", ctypes.c_double),
-                ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double)]
+                ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double), ("rhs_ms", ctypes.c_double),
+                ("gmres_ms", ctypes.c_double), ("gmres_launch_ms", ctypes.c_double),
+                ("gmres_wait_ms", ctypes.c_double), ("recover_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -65,6 +67,7 @@ class KernelTime(ctypes.Structure):
 
 EXPORTS = ["hdp_inspect", "hdp_setup", "hdp_solve", "hdp_apply_interface", "hdp_apply_precond",
            "hdp_interface_rhs", "hdp_local_solve", "hdp_get_stats", "hdp_profile", "hdp_profile_read",
+           "hdp_residual_history",
            "hdp_destroy", "hdp_status_string", "hdp_last_error_detail"]
 
 _lib = None
@@ -90,13 +93,15 @@ def load_library():
     L.hdp_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.hdp_inspect.argtypes = [ctypes.POINTER(_Mesh), ctypes.POINTER(_Problem), ctypes.POINTER(Stats)]
     L.hdp_profile.argtypes = [vp, i32]
+    L.hdp_residual_history.argtypes = [vp, i32, dp, i32, ctypes.POINTER(i32)]
     L.hdp_profile_read.argtypes = [vp, ctypes.POINTER(KernelTime), i32, ctypes.POINTER(i32)]
     L.hdp_destroy.argtypes = [vp]
     L.hdp_destroy.restype = None
     L.hdp_status_string.restype = ctypes.c_char_p
     L.hdp_last_error_detail.restype = ctypes.c_char_p
     for name in ("hdp_inspect", "hdp_setup", "hdp_solve", "hdp_apply_interface", "hdp_apply_precond",
-                 "hdp_interface_rhs", "hdp_local_solve", "hdp_get_stats", "hdp_profile", "hdp_profile_read"):
+                 "hdp_interface_rhs", "hdp_local_solve", "hdp_get_stats", "hdp_profile", "hdp_profile_read",
+                 "hdp_residual_history"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -142,7 +147,8 @@ class Solver:
     degree (per leaf), k, eps_r (per leaf) and l (<= 0: dispersion rule).
     """
 
-    def __init__(self, w, precision="fp64", tol=1e-8, max_iter=300, max_rhs=1, l_safety=0, device=0):
+    def __init__(self, w, precision="fp64", tol=1e-8, max_iter=300, max_rhs=1, l_safety=0, device=0,
+                 graphs=True):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("hdp needs a ROCm GPU (torch.cuda.is_available() is False)")
@@ -153,7 +159,8 @@ class Solver:
         self.precision = HDP_MIXED if precision == "mixed" else HDP_FP64
         with torch.cuda.device(self.device):
             stream = torch.cuda.current_stream(self.device).cuda_stream
-            opt = _Options(self.precision, float(tol), int(max_iter), int(max_rhs), ctypes.c_void_p(stream))
+            opt = _Options(self.precision, float(tol), int(max_iter), int(max_rhs), ctypes.c_void_p(stream),
+                           0 if graphs else 1)
             h = ctypes.c_void_p()
             _check(L.hdp_setup(ctypes.byref(mesh), ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(h)))
         self.h = h
@@ -219,6 +226,16 @@ class Solver:
         g = self.torch.empty((self.n_lambda, n), dtype=self.torch.complex128, device=self.device)
         _check(load_library().hdp_interface_rhs(self.h, ctypes.byref(r), _dptr(g)))
         return g
+
+    def residual_history(self, rhs=0):
+        """Preconditioned relative residual after each iteration of the last GMRES run."""
+        L = load_library()
+        n = ctypes.c_int32()
+        _check(L.hdp_residual_history(self.h, rhs, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value)
+        _check(L.hdp_residual_history(self.h, rhs, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      n.value, ctypes.byref(n)))
+        return out
 
     def profile(self, enable=True):
         """Bracket every kernel launch family with HIP events (enable clears totals)."""

@@ -59,7 +59,7 @@ std::vector<double2> pack_c(const std::vector<cd>& v) {
 const char* const KF_NAMES[KF_COUNT] = {"slot_apply_F", "slot_apply_P", "coarse_assemble", "coarse_gemv",
                                         "slot_coarse", "row_gather", "gmres_dots", "gmres_update",
                                         "gmres_norm_scale", "fdm_local_solve", "element_coarse_fix",
-                                        "gll_sample", "precision_cast"};
+                                        "gll_sample", "precision_cast", "gmres_givens"};
 
 static hipEvent_t prof_event(Handle& h) {
   if (!h.prof.pool.empty()) {
@@ -244,6 +244,23 @@ void build_device(Handle& h) {
   d.hsum = dalloc<double2>(h, (size_t(h.max_iter) + 1) * Rp);
   d.part = dalloc<double2>(h, size_t(512) * (h.max_iter + 1) * Rp);
   d.npart = dalloc<double>(h, size_t(512) * Rp);
+  size_t mv = size_t(h.max_iter) + 1;
+  d.vcur = dalloc<double2>(h, nl * Rp);
+  d.Hdev = dalloc<double2>(h, size_t(h.max_iter) * mv * Rp);
+  d.cs = dalloc<double2>(h, mv * Rp);
+  d.sn = dalloc<double2>(h, mv * Rp);
+  d.gvec = dalloc<double2>(h, (mv + 1) * Rp);
+  d.beta = dalloc<double>(h, Rp);
+  d.resid = dalloc<double>(h, Rp);
+  d.hist = dalloc<double>(h, (mv + 1) * Rp);
+  d.jdev = dalloc<int>(h, 1);
+  d.counter = dalloc<int>(h, 1);
+  d.status = dalloc<int>(h, 2);
+  d.done = dalloc<int>(h, Rp);
+  d.iters = dalloc<int>(h, Rp);
+  void* ph = nullptr;
+  HIPCHECK(hipHostMalloc(&ph, 4 * sizeof(int), hipHostMallocDefault));
+  d.status_host = static_cast<int*>(ph);
   d.nrm = dalloc<double>(h, Rp);
   d.ycoef = dalloc<double2>(h, (size_t(h.max_iter) + 1) * Rp);
   HIPCHECK(hipStreamSynchronize(h.stream));
@@ -251,7 +268,9 @@ void build_device(Handle& h) {
 
 // ---------------------------------------------------------------------------
 // Operators on dual vectors ([nlam][R]).
-void apply_F(Handle& h, const double2* v, double2* u, int R, int prec) {
+// F up to the element slots: z = A_11^-1 y + Phi K^-1 Phi^T y with y = C_1^T v,
+// left in slotB (FP64) or slotB_f (FP32).
+static void apply_F_slots(Handle& h, const double2* v, int R, int prec) {
   auto& d = h.d;
   hipStream_t s = h.stream;
   const double c = 16.0 * R, nsl = h.nslots, ncm = h.ncm, nl = h.nlam, nK = h.nK;
@@ -280,10 +299,35 @@ void apply_F(Handle& h, const double2* v, double2* u, int R, int prec) {
     if (prec == HDP_FP64) launch_slot_coarse<double2>(h, d.slotA, d.wK, d.slotB, R, s);
     else launch_slot_coarse<float2>(h, d.slotA_f, d.wK, d.slotB_f, R, s);
   }
+}
+
+void apply_F(Handle& h, const double2* v, double2* u, int R, int prec) {
+  auto& d = h.d;
+  const double c = 16.0 * R, nsl = h.nslots, nl = h.nlam;
+  const double cw = prec == HDP_FP64 ? 16.0 * R : 8.0 * R;
+  apply_F_slots(h, v, R, prec);
+  Timed t(h, KF_ROWGATHER, nsl * cw + nl * c, 0);
+  if (prec == HDP_FP64) launch_rowgather<double2>(h, d.slotB, false, false, u, R, h.stream);
+  else launch_rowgather<float2>(h, d.slotB_f, false, false, u, R, h.stream);
+}
+
+// w = P^-1 F v with the preconditioner's gather reading F's slot values directly.
+void apply_PF(Handle& h, const double2* v, double2* w, int R, int prec) {
+  auto& d = h.d;
+  hipStream_t s = h.stream;
+  const double c = 16.0 * R, nsl = h.nslots, nl = h.nlam;
+  const double cw = prec == HDP_FP64 ? 16.0 * R : 8.0 * R;
+  const double ob = prec == HDP_FP64 ? 1.0 : 0.5;
+  apply_F_slots(h, v, R, prec);
+  {
+    Timed t(h, KF_SLOT_P, nsl * cw * 2 + ob * h.se_bytes, h.flops_P * R);
+    if (prec == HDP_FP64) launch_slot_apply<double2>(h, 2, d.slotB, d.slotA, nullptr, R, s);
+    else launch_slot_apply<float2>(h, 2, d.slotB_f, d.slotA_f, nullptr, R, s);
+  }
   {
     Timed t(h, KF_ROWGATHER, nsl * cw + nl * c, 0);
-    if (prec == HDP_FP64) launch_rowgather<double2>(h, d.slotB, false, false, u, R, s);
-    else launch_rowgather<float2>(h, d.slotB_f, false, false, u, R, s);
+    if (prec == HDP_FP64) launch_rowgather<double2>(h, d.slotA, false, true, w, R, s);
+    else launch_rowgather<float2>(h, d.slotA_f, false, true, w, R, s);
   }
 }
 
@@ -359,107 +403,142 @@ struct GmresResult {
 
 // Left-preconditioned GMRES with CGS2 on R systems at once (x0 = 0); stops
 // each system when ||P^-1 r_k|| / ||P^-1 r_0|| <= tol.  x receives the iterate.
+// The Arnoldi step, the Hessenberg column and the Givens rotations stay on the
+// device; the host reads a two-word status one iteration behind the GPU.
 GmresResult gmres(Handle& h, const double2* rhs, double2* x, int R, int prec, double tol, int max_iter) {
   auto& d = h.d;
   hipStream_t s = h.stream;
-  int n = h.nlam;
-  int64_t vs = int64_t(n) * R;
-  int nblk = dots_blocks(n, R);
+  const int n = h.nlam;
+  const int64_t vs = int64_t(n) * R;
+  const int maxvec = h.max_iter + 1;
+  max_iter = std::min(max_iter, h.max_iter);
+  GmresDims gd = gmres_dims(n, R, maxvec);
+  const double vb = 16.0 * double(vs);
   GmresResult res;
   res.iters.assign(R, 0);
   res.rel.assign(R, 1.0);
   HIPCHECK(hipMemsetAsync(x, 0, size_t(vs) * sizeof(double2), s));
-  // V_0 = P^-1 rhs / beta
   apply_P(h, rhs, d.w, R, prec);
-  launch_norm(d.w, n, R, d.npart, nblk, d.nrm, s);
-  std::vector<double> beta(R);
-  HIPCHECK(hipMemcpyAsync(beta.data(), d.nrm, R * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipStreamSynchronize(s));
-  launch_scale(d.w, d.nrm, d.V_kry, n, R, s);
-  std::vector<std::vector<cd>> H(R), cs(R), sn(R), gv(R);
-  std::vector<int> done(R, 0);
-  for (int r = 0; r < R; ++r) {
-    gv[r].assign(max_iter + 1, 0.0);
-    gv[r][0] = beta[r];
-    if (!(beta[r] > 0)) { done[r] = 1; res.rel[r] = 0; }
-    H[r].assign(size_t(max_iter + 1) * max_iter, 0.0);
-    cs[r].assign(max_iter, 0.0);
-    sn[r].assign(max_iter, 0.0);
+  {
+    Timed t(h, KF_NORM_SCALE, 3 * vb, 6.0 * double(vs));
+    launch_normalize(d.w, n, R, gd, d.npart, d.nrm, d.V_kry, nullptr, vs, d.vcur, s);
   }
-  std::vector<double2> hh(size_t(max_iter + 1) * R);
-  std::vector<double> nr(R);
-  int j = 0;
-  for (; j < max_iter; ++j) {
-    if (std::all_of(done.begin(), done.end(), [](int v) { return v; })) break;
-    double2* Vj = d.V_kry + vs * j;
-    apply_F(h, Vj, d.t1, R, prec);
-    apply_P(h, d.t1, d.w, R, prec);
-    int nvec = j + 1;
-    HIPCHECK(hipMemsetAsync(d.hsum, 0, size_t(nvec) * R * sizeof(double2), s));
-    const double vb = 16.0 * double(vs);
-    for (int pass = 0; pass < 2; ++pass) {
-      {
-        Timed t(h, KF_DOTS, (nvec + 1) * vb, 8.0 * nvec * double(vs));
-        launch_dots(d.V_kry, vs, nvec, d.w, n, R, d.part, nblk, s);
-        launch_dots_final(d.part, nblk, nvec, R, d.hbuf, d.hsum, s);
+  launch_gmres_init(d.nrm, d.beta, d.gvec, d.done, d.iters, d.resid, d.jdev, d.counter, d.status, R, d.hist, s);
+  hipEvent_t ev[2];
+  HIPCHECK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  HIPCHECK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  int launched = 0;
+  try {
+    auto issue = [&](int nv) {
+      apply_PF(h, d.vcur, d.w, R, prec);
+      for (int pass = 0; pass < 2; ++pass) {
+        {
+          Timed t(h, KF_DOTS, (nv + 1) * vb, 8.0 * nv * double(vs));
+          launch_mdot(d.V_kry, vs, d.jdev, 0, d.w, n, R, gd, maxvec, d.part, s);
+          launch_mdot_reduce(d.part, gd, d.jdev, 0, maxvec, R, d.hbuf, d.hsum, pass == 0, s);
+        }
+        {
+          Timed t(h, KF_UPDATE, (nv + 2) * vb, 8.0 * nv * double(vs));
+          launch_mupdate(d.V_kry, vs, d.jdev, 0, d.hbuf, d.w, n, R, -1.0, s);
+        }
       }
       {
-        Timed t(h, KF_UPDATE, (nvec + 2) * vb, 8.0 * nvec * double(vs));
-        launch_update(d.V_kry, vs, nvec, d.hbuf, d.w, n, R, -1.0, s);
+        Timed t(h, KF_NORM_SCALE, 4 * vb, 6.0 * double(vs));
+        launch_normalize(d.w, n, R, gd, d.npart, d.nrm, d.V_kry, d.jdev, vs, d.vcur, s);
+      }
+      {
+        Timed t(h, KF_GIVENS, 0, 0);
+        launch_givens(d.jdev, d.hsum, d.nrm, d.Hdev, d.cs, d.sn, d.gvec, d.beta, d.done, d.iters, d.resid, tol,
+                      maxvec, R, d.counter, d.status, d.hist, s);
+      }
+    };
+    // one GMRES iteration as a captured graph (every launch reads j on the device)
+    hipGraphExec_t exec = nullptr;
+    const bool graph = h.use_graphs && !h.prof.on;
+    if (graph) {
+      auto key = std::make_tuple(R, prec, tol);
+      auto itg = h.graphs.find(key);
+      if (itg == h.graphs.end()) {
+        hipGraph_t gr;
+        HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        issue(1);
+        HIPCHECK(hipStreamEndCapture(s, &gr));
+        hipGraphExec_t ex;
+        hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        HIPCHECK(ie);
+        itg = h.graphs.emplace(key, ex).first;
+      }
+      exec = itg->second;
+    }
+    using clk = std::chrono::steady_clock;
+    for (int it = 0; it < max_iter; ++it) {
+      auto t0 = clk::now();
+      if (graph) HIPCHECK(hipGraphLaunch(exec, s));
+      else issue(it + 1);
+      HIPCHECK(hipMemcpyAsync(d.status_host + 2 * (it & 1), d.status, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipEventRecord(ev[it & 1], s));
+      auto t1 = clk::now();
+      h.t_launch += std::chrono::duration<double, std::milli>(t1 - t0).count();
+      launched = it + 1;
+      if (it >= 1) {
+        HIPCHECK(hipEventSynchronize(ev[(it - 1) & 1]));
+        h.t_wait += std::chrono::duration<double, std::milli>(clk::now() - t1).count();
+        if (d.status_host[2 * ((it - 1) & 1)]) break;
       }
     }
-    {
-      Timed t(h, KF_NORM_SCALE, 3 * vb, 6.0 * double(vs));
-      launch_norm(d.w, n, R, d.npart, nblk, d.nrm, s);
-      launch_scale(d.w, d.nrm, d.V_kry + vs * (j + 1), n, R, s);
-    }
-    HIPCHECK(hipMemcpyAsync(hh.data(), d.hsum, size_t(nvec) * R * sizeof(double2), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipMemcpyAsync(nr.data(), d.nrm, R * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
-    for (int r = 0; r < R; ++r) {
-      if (done[r]) continue;
-      auto Hc = [&](int i) -> cd& { return H[r][size_t(j) * (max_iter + 1) + i]; };
-      for (int i = 0; i < nvec; ++i) Hc(i) = cd(hh[size_t(i) * R + r].x, hh[size_t(i) * R + r].y);
-      Hc(j + 1) = nr[r];
-      for (int i = 0; i < j; ++i) {
-        cd t = cs[r][i] * Hc(i) + sn[r][i] * Hc(i + 1);
-        Hc(i + 1) = -std::conj(sn[r][i]) * Hc(i) + cs[r][i] * Hc(i + 1);
-        Hc(i) = t;
-      }
-      cd a = Hc(j), b = Hc(j + 1);
-      double den = std::sqrt(std::norm(a) + std::norm(b));
-      if (den == 0) { cs[r][j] = 1; sn[r][j] = 0; }
-      else if (std::abs(a) == 0) { cs[r][j] = 0; sn[r][j] = std::conj(b) / den; }
-      else { cs[r][j] = std::abs(a) / den; sn[r][j] = (a / std::abs(a)) * std::conj(b) / den; }
-      Hc(j) = cs[r][j] * a + sn[r][j] * b;
-      Hc(j + 1) = 0;
-      gv[r][j + 1] = -std::conj(sn[r][j]) * gv[r][j];
-      gv[r][j] = cs[r][j] * gv[r][j];
-      res.iters[r] = j + 1;
-      res.rel[r] = std::abs(gv[r][j + 1]) / beta[r];
-      if (res.rel[r] <= tol || nr[r] == 0.0) done[r] = 1;
-    }
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    throw;
   }
-  // x = sum_i V_i y_i with H y = g (upper triangular, per system)
-  std::vector<double2> ycoef(size_t(max_iter + 1) * R, make_double2(0, 0));
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  prof_flush(h);
+  std::vector<int> iters(R);
+  std::vector<double> resid(R);
+  HIPCHECK(hipMemcpy(iters.data(), d.iters, R * sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(resid.data(), d.resid, R * sizeof(double), hipMemcpyDeviceToHost));
   int kmax = 0;
   for (int r = 0; r < R; ++r) {
-    int k = res.iters[r];
-    kmax = std::max(kmax, k);
+    res.iters[r] = iters[r];
+    res.rel[r] = resid[r];
+    kmax = std::max(kmax, iters[r]);
+  }
+  (void)launched;
+  h.last_hist.assign(size_t(kmax + 1) * R, 0.0);
+  HIPCHECK(hipMemcpy(h.last_hist.data(), d.hist, h.last_hist.size() * sizeof(double), hipMemcpyDeviceToHost));
+  h.last_hist_R = R;
+  h.last_hist_len = kmax + 1;
+  if (kmax == 0) return res;
+  // x = sum_i V_i y_i with H y = g (upper triangular, per system), on the host
+  std::vector<double2> Hh(size_t(kmax) * maxvec * R), gh(size_t(kmax + 1) * R);
+  HIPCHECK(hipMemcpy(Hh.data(), d.Hdev, Hh.size() * sizeof(double2), hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(gh.data(), d.gvec, gh.size() * sizeof(double2), hipMemcpyDeviceToHost));
+  auto Hc = [&](int i, int jj, int r) { double2 v = Hh[(size_t(jj) * maxvec + i) * R + r]; return cd(v.x, v.y); };
+  std::vector<double2> ycoef(size_t(kmax) * R, make_double2(0, 0));
+  for (int r = 0; r < R; ++r) {
+    int k = iters[r];
     std::vector<cd> y(k);
     for (int i = k - 1; i >= 0; --i) {
-      cd sum = gv[r][i];
-      for (int jj = i + 1; jj < k; ++jj) sum -= H[r][size_t(jj) * (max_iter + 1) + i] * y[jj];
-      y[i] = sum / H[r][size_t(i) * (max_iter + 1) + i];
+      cd sum(gh[size_t(i) * R + r].x, gh[size_t(i) * R + r].y);
+      for (int jj = i + 1; jj < k; ++jj) sum -= Hc(i, jj, r) * y[jj];
+      y[i] = sum / Hc(i, i, r);
     }
     for (int i = 0; i < k; ++i) ycoef[size_t(i) * R + r] = make_double2(y[i].real(), y[i].imag());
   }
-  if (kmax > 0) {
-    HIPCHECK(hipMemcpyAsync(d.ycoef, ycoef.data(), size_t(kmax) * R * sizeof(double2), hipMemcpyHostToDevice, s));
-    launch_update(d.V_kry, vs, kmax, d.ycoef, x, n, R, 1.0, s);
-  }
+  HIPCHECK(hipMemcpyAsync(d.ycoef, ycoef.data(), ycoef.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+  launch_mupdate(d.V_kry, vs, nullptr, kmax - 1, d.ycoef, x, n, R, 1.0, s);
   HIPCHECK(hipStreamSynchronize(s));
   return res;
+}
+
+// Order the handle's stream after everything already issued on the caller's stream.
+void after_user(Handle& h) {
+  HIPCHECK(hipEventRecord(h.order_ev, h.user_stream));
+  HIPCHECK(hipStreamWaitEvent(h.stream, h.order_ev, 0));
 }
 
 }  // namespace hdp
@@ -484,8 +563,8 @@ hdp_status hdp_setup(const hdp_mesh* mesh, const hdp_problem* prob, const hdp_op
   API_BEGIN
   if (!out || !opt) fail(HDP_E_ARG, "null output or options");
   *out = nullptr;
-  if (opt->max_rhs < 1 || opt->max_rhs > 256) fail(HDP_E_ARG, "max_rhs must lie in 1..256");
-  if (opt->max_iter < 1 || opt->max_iter > 2000) fail(HDP_E_ARG, "max_iter must lie in 1..2000");
+  if (opt->max_rhs < 1 || opt->max_rhs > 64) fail(HDP_E_ARG, "max_rhs must lie in 1..64");
+  if (opt->max_iter < 1 || opt->max_iter > 1000) fail(HDP_E_ARG, "max_iter must lie in 1..1000");
   if (!(opt->tol > 0) || !(opt->tol < 1)) fail(HDP_E_ARG, "tol must lie in (0,1)");
   if (opt->precision != HDP_FP64 && opt->precision != HDP_MIXED) fail(HDP_E_ARG, "unknown precision");
   auto t0 = std::chrono::steady_clock::now();
@@ -495,12 +574,22 @@ hdp_status hdp_setup(const hdp_mesh* mesh, const hdp_problem* prob, const hdp_op
   h.max_iter = opt->max_iter;
   h.tol = opt->tol;
   h.precision = opt->precision;
-  h.stream = static_cast<hipStream_t>(opt->stream);
+  h.user_stream = static_cast<hipStream_t>(opt->stream);
+  h.use_graphs = !(opt->flags & HDP_FLAG_EAGER);
   try {
+    // a stream of the handle's own (default priority): capturable, unlike the null stream
+    HIPCHECK(hipStreamCreateWithFlags(&h.stream, hipStreamNonBlocking));
+    HIPCHECK(hipEventCreateWithFlags(&h.order_ev, hipEventDisableTiming));
+    HIPCHECK(hipEventRecord(h.order_ev, h.user_stream));
+    HIPCHECK(hipStreamWaitEvent(h.stream, h.order_ev, 0));
     build_host(h, mesh, prob);
     build_device(h);
   } catch (...) {
+    if (h.stream) (void)hipStreamSynchronize(h.stream);
     for (void* p : h.allocations) (void)hipFree(p);
+    if (h.d.status_host) (void)hipHostFree(h.d.status_host);
+    if (h.order_ev) (void)hipEventDestroy(h.order_ev);
+    if (h.stream) (void)hipStreamDestroy(h.stream);
     delete H;
     throw;
   }
@@ -541,6 +630,7 @@ hdp_status hdp_apply_interface(hdp_handle* H, const hdp_c64* v, hdp_c64* u, int3
   if (!H || !v || !u) fail(HDP_E_ARG, "null argument");
   Handle& h = H->h;
   if (n_rhs < 1 || n_rhs > pow2ceil(h.max_rhs)) fail(HDP_E_ARG, "n_rhs out of range");
+  after_user(h);
   apply_F(h, reinterpret_cast<const double2*>(v), reinterpret_cast<double2*>(u), n_rhs, precision);
   HIPCHECK(hipStreamSynchronize(h.stream));
   prof_flush(h);
@@ -553,6 +643,7 @@ hdp_status hdp_apply_precond(hdp_handle* H, const hdp_c64* v, hdp_c64* u, int32_
   if (!H || !v || !u) fail(HDP_E_ARG, "null argument");
   Handle& h = H->h;
   if (n_rhs < 1 || n_rhs > pow2ceil(h.max_rhs)) fail(HDP_E_ARG, "n_rhs out of range");
+  after_user(h);
   apply_P(h, reinterpret_cast<const double2*>(v), reinterpret_cast<double2*>(u), n_rhs, precision);
   HIPCHECK(hipStreamSynchronize(h.stream));
   prof_flush(h);
@@ -565,6 +656,7 @@ hdp_status hdp_local_solve(hdp_handle* H, const hdp_c64* y, hdp_c64* x, int32_t 
   if (!H || !y || !x) fail(HDP_E_ARG, "null argument");
   Handle& h = H->h;
   if (n_rhs < 1) fail(HDP_E_ARG, "n_rhs out of range");
+  after_user(h);
   launch_fdm(h, reinterpret_cast<const double2*>(y), reinterpret_cast<double2*>(x), n_rhs, h.stream);
   HIPCHECK(hipStreamSynchronize(h.stream));
   return HDP_OK;
@@ -587,16 +679,39 @@ static void check_rhs(const Handle& h, const hdp_rhs* rhs) {
   }
 }
 
-// Loads of all RHS into full0 with stride Rp (zero-padded columns).
+// Loads of all RHS into full0 with stride Rp (zero-padded columns): packed
+// non-zero element blocks are uploaded and scattered into a zeroed array.
 static void load_rhs(Handle& h, const hdp_rhs* rhs, int Rp) {
-  std::vector<cd> B;
-  compute_loads(h, rhs, B);
-  int R = rhs->n_rhs;
-  std::vector<double2> P(size_t(h.dof) * Rp, make_double2(0, 0));
-  for (int64_t i = 0; i < h.dof; ++i)
-    for (int r = 0; r < R; ++r) P[size_t(i) * Rp + r] = make_double2(B[size_t(i) * R + r].real(), B[size_t(i) * R + r].imag());
-  HIPCHECK(hipMemcpyAsync(h.d.full0, P.data(), P.size() * sizeof(double2), hipMemcpyHostToDevice, h.stream));
-  HIPCHECK(hipStreamSynchronize(h.stream));
+  std::vector<int> elems;
+  std::vector<cd> vals;
+  compute_loads(h, rhs, Rp, elems, vals);
+  auto& d = h.d;
+  hipStream_t s = h.stream;
+  int nb = int(elems.size());
+  std::vector<int64_t> off(nb + 1, 0);
+  for (int b = 0; b < nb; ++b) {
+    int n = h.deg[elems[b]] + 1;
+    off[b + 1] = off[b] + int64_t(n) * n * Rp;
+  }
+  size_t need_blocks = size_t(nb), need_vals = vals.size();
+  if (need_blocks > h.load_cap_blocks || need_vals > h.load_cap_vals) {
+    // staging grows on demand; freed with the handle
+    h.load_cap_blocks = std::max(need_blocks, h.load_cap_blocks);
+    h.load_cap_vals = std::max(need_vals, h.load_cap_vals);
+    d.load_elems = dalloc<int>(h, h.load_cap_blocks);
+    d.load_off = dalloc<int64_t>(h, h.load_cap_blocks + 1);
+    d.load_vals = dalloc<double2>(h, h.load_cap_vals);
+  }
+  launch_fill_zero(d.full0, h.dof * Rp, s);
+  if (nb) {
+    std::vector<double2> pv(vals.size());
+    for (size_t i = 0; i < vals.size(); ++i) pv[i] = make_double2(vals[i].real(), vals[i].imag());
+    HIPCHECK(hipMemcpyAsync(d.load_elems, elems.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(d.load_off, off.data(), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(d.load_vals, pv.data(), pv.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+    launch_block_scatter(d.load_elems, d.load_off, nb, d.dof_off, d.load_vals, d.full0, Rp, s);
+  }
+  HIPCHECK(hipStreamSynchronize(s));
 }
 
 hdp_status hdp_interface_rhs(hdp_handle* H, const hdp_rhs* rhs, hdp_c64* g) {
@@ -605,6 +720,7 @@ hdp_status hdp_interface_rhs(hdp_handle* H, const hdp_rhs* rhs, hdp_c64* g) {
   Handle& h = H->h;
   check_rhs(h, rhs);
   int R = rhs->n_rhs;
+  after_user(h);
   load_rhs(h, rhs, R);
   interface_rhs(h, reinterpret_cast<double2*>(g), R);
   HIPCHECK(hipStreamSynchronize(h.stream));
@@ -624,9 +740,17 @@ hdp_status hdp_solve(hdp_handle* H, const hdp_rhs* rhs, hdp_c64* field, int32_t 
   auto& d = h.d;
   hipStream_t s = h.stream;
   int R = rhs->n_rhs, Rp = pow2ceil(R);
+  h.t_launch = h.t_wait = 0;
+  auto ms_since = [](std::chrono::steady_clock::time_point a) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count();
+  };
   int64_t vs = int64_t(h.nlam) * Rp;
+  after_user(h);
   load_rhs(h, rhs, Rp);
   interface_rhs(h, d.t0, Rp);                       // g
+  HIPCHECK(hipStreamSynchronize(s));
+  double t_rhs = ms_since(t0);
+  auto tg = std::chrono::steady_clock::now();
   int iters = 0, refinements = 0;
   double rel = 0;
   bool conv = true;
@@ -639,10 +763,10 @@ hdp_status hdp_solve(hdp_handle* H, const hdp_rhs* rhs, hdp_c64* field, int32_t 
     }
   } else {
     // GMRES-IR: inner GMRES on FP32 local operators, FP64 residual and update
-    int nblk = dots_blocks(h.nlam, Rp);
+    GmresDims gd = gmres_dims(h.nlam, Rp, h.max_iter + 1);
     HIPCHECK(hipMemsetAsync(d.t2, 0, size_t(vs) * sizeof(double2), s));
     apply_P(h, d.t0, d.w, Rp, HDP_FP64);
-    launch_norm(d.w, h.nlam, Rp, d.npart, nblk, d.nrm, s);
+    launch_normalize(d.w, h.nlam, Rp, gd, d.npart, d.nrm, d.t1, nullptr, vs, nullptr, s);
     std::vector<double> s0(Rp), sk(Rp);
     HIPCHECK(hipMemcpyAsync(s0.data(), d.nrm, Rp * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
@@ -651,8 +775,13 @@ hdp_status hdp_solve(hdp_handle* H, const hdp_rhs* rhs, hdp_c64* field, int32_t 
     delta = d.full1;   // scratch of at least nlam * Rp (dof >= nlam)
     int budget = h.max_iter;
     conv = false;
+    rel = 1.0;
+    // inner tolerance: as far as the FP32 operator usefully goes on the first
+    // pass, then only the reduction the outer residual still needs
+    const double floor32 = 5e-8;
     for (int outer = 0; outer < 30 && budget > 0; ++outer) {
-      GmresResult gr = gmres(h, d.t1, delta, Rp, HDP_MIXED, 1e-5, budget);
+      double inner = std::min(0.1, std::max(floor32, 0.5 * h.tol / std::max(rel, 1e-300)));
+      GmresResult gr = gmres(h, d.t1, delta, Rp, HDP_MIXED, inner, budget);
       int used = 0;
       for (int r = 0; r < R; ++r) used = std::max(used, gr.iters[r]);
       iters += used;
@@ -662,7 +791,7 @@ hdp_status hdp_solve(hdp_handle* H, const hdp_rhs* rhs, hdp_c64* field, int32_t 
       apply_F(h, d.t2, d.t1, Rp, HDP_FP64);                // F nu
       launch_axpby(d.t0, d.t1, d.t1, vs, 1.0, -1.0, s);   // r = g - F nu
       apply_P(h, d.t1, d.w, Rp, HDP_FP64);
-      launch_norm(d.w, h.nlam, Rp, d.npart, nblk, d.nrm, s);
+      launch_normalize(d.w, h.nlam, Rp, gd, d.npart, d.nrm, d.vcur, nullptr, vs, nullptr, s);
       HIPCHECK(hipMemcpyAsync(sk.data(), d.nrm, Rp * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHECK(hipStreamSynchronize(s));
       rel = 0;
@@ -670,6 +799,9 @@ hdp_status hdp_solve(hdp_handle* H, const hdp_rhs* rhs, hdp_c64* field, int32_t 
       if (rel <= h.tol) { conv = true; break; }
     }
   }
+  HIPCHECK(hipStreamSynchronize(s));
+  double t_gmres = ms_since(tg);
+  auto tr = std::chrono::steady_clock::now();
   // recovery phi = A^-1 (b^ - C^T nu) (Sec. 2.3.1) and the field at GLL nodes
   HIPCHECK(hipMemcpyAsync(d.full1, d.full0, size_t(h.dof) * Rp * sizeof(double2), hipMemcpyDeviceToDevice, s));
   launch_sub_dual(h, d.full1, d.t2, Rp, s);
@@ -687,8 +819,24 @@ hdp_status hdp_solve(hdp_handle* H, const hdp_rhs* rhs, hdp_c64* field, int32_t 
     stats->refinements = refinements;
     stats->rel_residual = rel;
     stats->solve_ms = ms;
+    stats->rhs_ms = t_rhs;
+    stats->gmres_ms = t_gmres;
+    stats->gmres_launch_ms = h.t_launch;
+    stats->gmres_wait_ms = h.t_wait;
+    stats->recover_ms = ms_since(tr);
   }
   return conv ? HDP_OK : HDP_W_NOT_CONVERGED;
+  API_END
+}
+
+hdp_status hdp_residual_history(const hdp_handle* H, int32_t rhs, double* out, int32_t max, int32_t* count) {
+  API_BEGIN
+  if (!H || !count) fail(HDP_E_ARG, "null argument");
+  const Handle& h = H->h;
+  if (rhs < 0 || (h.last_hist_R && rhs >= h.last_hist_R)) fail(HDP_E_ARG, "rhs index out of range");
+  *count = h.last_hist_len;
+  for (int i = 0; i < h.last_hist_len && i < max && out; ++i) out[i] = h.last_hist[size_t(i) * h.last_hist_R + rhs];
+  return HDP_OK;
   API_END
 }
 
@@ -725,13 +873,16 @@ hdp_status hdp_profile_read(const hdp_handle* H, hdp_kernel_time* out, int32_t m
 
 void hdp_destroy(hdp_handle* H) {
   if (!H) return;
-  if (H->h.stream) (void)hipStreamSynchronize(H->h.stream);
-  else (void)hipDeviceSynchronize();
+  (void)hipStreamSynchronize(H->h.stream);
   for (auto& p : H->h.prof.pend) {
     (void)hipEventDestroy(p.a);
     (void)hipEventDestroy(p.b);
   }
   for (auto e : H->h.prof.pool) (void)hipEventDestroy(e);
+  if (H->h.d.status_host) (void)hipHostFree(H->h.d.status_host);
+  for (auto& kv : H->h.graphs) (void)hipGraphExecDestroy(kv.second);
+  if (H->h.order_ev) (void)hipEventDestroy(H->h.order_ev);
+  if (H->h.stream) (void)hipStreamDestroy(H->h.stream);
   for (void* p : H->h.allocations) (void)hipFree(p);
   delete H;
 }

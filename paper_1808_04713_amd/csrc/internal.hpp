@@ -3,7 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/hdp.h"
@@ -50,7 +52,7 @@ struct DevOps {
 
 enum KernelFamily {
   KF_SLOT_F = 0, KF_SLOT_P, KF_ASSEMBLE, KF_COARSE, KF_SLOT_COARSE, KF_ROWGATHER, KF_DOTS, KF_UPDATE,
-  KF_NORM_SCALE, KF_FDM, KF_ELEMENT_MISC, KF_GLL, KF_CAST, KF_COUNT
+  KF_NORM_SCALE, KF_FDM, KF_ELEMENT_MISC, KF_GLL, KF_CAST, KF_GIVENS, KF_COUNT
 };
 extern const char* const KF_NAMES[KF_COUNT];
 
@@ -70,7 +72,9 @@ struct Handle {
   double k = 0;
   int max_rhs = 1, max_iter = 100, precision = HDP_FP64;
   double tol = 1e-8;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;        // internal stream all work is issued on
+  hipStream_t user_stream = nullptr;   // caller's stream; work is ordered after it
+  hipEvent_t order_ev = nullptr;
   std::vector<int> deg;
   std::vector<double> eps;
   std::vector<double> ox, oy, hx, hy;   // element origin and size
@@ -95,6 +99,8 @@ struct Handle {
   std::vector<int> cm_mode;       // per coarse mode, local mode index
   // class-sorted element order and launch tables
   std::vector<int> order;         // elements grouped by class
+  // per degree n: Gauss-Legendre rule with n+40 nodes and the vertex basis there
+  std::map<int, std::vector<double>> quad_x, quad_w, quad_N;
   double min_margin = 1;
   double setup_ms = 0;
   // algorithmic work per right-hand side (bytes of class operators are
@@ -136,10 +142,23 @@ struct Handle {
     double2 *hbuf = nullptr, *hsum = nullptr, *part = nullptr;
     double *nrm = nullptr, *npart = nullptr;
     float2* vf = nullptr;
+    double2 *vcur = nullptr, *Hdev = nullptr, *cs = nullptr, *sn = nullptr, *gvec = nullptr;
+    double *beta = nullptr, *resid = nullptr, *hist = nullptr;   // hist: (max_iter+1) x R
+    int *jdev = nullptr, *counter = nullptr, *status = nullptr, *done = nullptr, *iters = nullptr;
+    int* status_host = nullptr;   // pinned, 4 ints (two in-flight status slots)
+    int* load_elems = nullptr;
+    int64_t* load_off = nullptr;
+    double2* load_vals = nullptr;
     double2* ycoef = nullptr;
   } d;
   std::vector<void*> allocations;
   Prof prof;
+  bool use_graphs = true;
+  std::vector<double> last_hist;   // residual history of the last GMRES run, [iteration][R]
+  int last_hist_R = 0, last_hist_len = 0;
+  double t_launch = 0, t_wait = 0;
+  size_t load_cap_blocks = 0, load_cap_vals = 0;   // host time in GMRES launch calls / waits (ms)
+  std::map<std::tuple<int, int, double>, hipGraphExec_t> graphs;   // (R, precision, tol)
 };
 
 // Brackets the launches issued during its lifetime with profiling events.
@@ -156,6 +175,8 @@ void prof_flush(Handle& h);   // after a stream synchronisation
 // setup.cpp
 void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob);
 void build_device(Handle& h);
-void compute_loads(const Handle& h, const hdp_rhs* rhs, std::vector<cd>& B);  // [dof][R]
+// Element loads of the elements with a non-zero load: elems lists them and
+// vals holds their blocks back to back, each [n_e^2][R].
+void compute_loads(const Handle& h, const hdp_rhs* rhs, int R, std::vector<int>& elems, std::vector<cd>& vals);
 
 }  // namespace hdp

@@ -17,6 +17,7 @@ constexpr int NT = 256;      // threads per block
 constexpr int RC = 8;        // RHS columns per block in the slot kernels
 constexpr int MMAX = 160;    // max dual slots per element (4 sides x 40 modes)
 constexpr int NRMAX = 160;   // max coarse modes per element
+constexpr int GVEC = 4;      // Arnoldi vectors per block in the multi-dot
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -47,8 +48,8 @@ __global__ void __launch_bounds__(NT) k_slot_apply(
     const int* __restrict__ cm_off, const int* __restrict__ cls_m, const int* __restrict__ cls_nr,
     const int64_t* __restrict__ cls_op, const T2* __restrict__ op1, const typename Scal<T2>::T* __restrict__ se,
     const int64_t* __restrict__ cls_se, const int* __restrict__ slot_row, const double* __restrict__ slot_coef,
-    const double* __restrict__ row_xinv, const T2* __restrict__ v, T2* __restrict__ X, T2* __restrict__ GL,
-    int R) {
+    const double* __restrict__ row_xinv, const int* __restrict__ row_slot, const double* __restrict__ row_coef,
+    const T2* __restrict__ v, T2* __restrict__ X, T2* __restrict__ GL, int R) {
   using S = typename Scal<T2>::T;
   __shared__ T2 y[MMAX * RC];
   const int e = order[blockIdx.x];
@@ -63,8 +64,23 @@ __global__ void __launch_bounds__(NT) k_slot_apply(
     int slot = so + s;
     int row = slot_row[slot];
     S f = S(slot_coef[slot]);
-    if (MODE == 1) f *= S(row_xinv[row]);
-    T2 a = v[(int64_t)row * R + r0 + r];
+    if (MODE >= 1) f *= S(row_xinv[row]);
+    T2 a;
+    if (MODE == 2) {
+      // v holds dual slots: the row value is the jump C_1 z of its two slots
+      S ax = 0, ay = 0;
+      for (int t = 0; t < 2; ++t) {
+        int sl = row_slot[2 * row + t];
+        if (sl < 0) continue;
+        S cf = S(row_coef[2 * row + t]);
+        T2 z = v[(int64_t)sl * R + r0 + r];
+        ax += cf * z.x;
+        ay += cf * z.y;
+      }
+      a = mk<T2>(ax, ay);
+    } else {
+      a = v[(int64_t)row * R + r0 + r];
+    }
     y[s * RC + r] = mk<T2>(f * a.x, f * a.y);
   }
   __syncthreads();
@@ -498,10 +514,270 @@ __global__ void k_cast_d(const float2* __restrict__ x, double2* __restrict__ y, 
   if (idx < count) y[idx] = make_double2(double(x[idx].x), double(x[idx].y));
 }
 
+__global__ void k_fill_zero(double2* __restrict__ x, int64_t count) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < count) x[idx] = make_double2(0.0, 0.0);
+}
+
+// Scatter packed element blocks into a zeroed full-element array.
+__global__ void k_block_scatter(const int* __restrict__ elems, const int64_t* __restrict__ src_off,
+                                const int64_t* __restrict__ dof_off, const double2* __restrict__ src,
+                                double2* __restrict__ full, int R) {
+  const int b = blockIdx.x;
+  const int e = elems[b];
+  const int64_t len = src_off[b + 1] - src_off[b];
+  const double2* sp = src + src_off[b];
+  double2* dp = full + dof_off[e] * R;
+  for (int64_t t = threadIdx.x; t < len; t += blockDim.x) dp[t] = sp[t];
+}
+
 __global__ void k_dense_scatter(const int64_t* __restrict__ idx, const double2* __restrict__ val, int64_t nnz,
                                 double2* __restrict__ M) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < nnz) M[idx[t]] = val[t];
+}
+
+// ---------------------------------------------------------------------------
+// Device-resident GMRES.  The iteration index j lives in device memory so every
+// launch has a fixed shape; R (RHS count) divides 64 and thread t owns RHS
+// column t % R.  nvec = j + 1 Arnoldi vectors take part in an iteration.
+
+// Reduce a per-thread value over the threads of a block that share an RHS
+// column (lanes with equal lane % R inside a wave, then the four waves).
+__device__ __forceinline__ double2 block_sum_by_rhs(double2 v, int R, double2* red) {
+  for (int off = 32; off >= R && off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane < R) red[wv * 64 + lane] = v;
+  __syncthreads();
+  double2 s = make_double2(0, 0);
+  if (threadIdx.x < R)
+    for (int q = 0; q < NT / 64; ++q) {
+      s.x += red[q * 64 + threadIdx.x].x;
+      s.y += red[q * 64 + threadIdx.x].y;
+    }
+  __syncthreads();
+  return s;   // valid in threads 0..R-1
+}
+
+// part[c][i][r] = sum over the rows of chunk c of conj(V_i) w, i in group blockIdx.y.
+template <int GV>
+__global__ void __launch_bounds__(NT) k_mdot(const double2* __restrict__ V, int64_t vs, const int* __restrict__ jptr,
+                                             int jfix, const double2* __restrict__ w, int n, int R, int chunk,
+                                             int maxvec, double2* __restrict__ part) {
+  __shared__ double2 red[NT];
+  const int nvec = (jptr ? *jptr : jfix) + 1;
+  const int i0 = blockIdx.y * GV;
+  if (i0 >= nvec) return;
+  const int r = threadIdx.x % R, rl = threadIdx.x / R, step = NT / R;
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min((int64_t)n, lo + chunk);
+  double ax[GV], ay[GV];
+#pragma unroll
+  for (int t = 0; t < GV; ++t) ax[t] = ay[t] = 0;
+  for (int64_t row = lo + rl; row < hi; row += step) {
+    const int64_t o = row * R + r;
+    double2 b = w[o];
+#pragma unroll
+    for (int t = 0; t < GV; ++t) {
+      if (i0 + t < nvec) {
+        double2 a = V[(int64_t)(i0 + t) * vs + o];
+        ax[t] += a.x * b.x + a.y * b.y;
+        ay[t] += a.x * b.y - a.y * b.x;
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < GV; ++t) {
+    double2 s = block_sum_by_rhs(make_double2(ax[t], ay[t]), R, red);
+    if (threadIdx.x < R && i0 + t < nvec)
+      part[((int64_t)blockIdx.x * maxvec + i0 + t) * R + threadIdx.x] = s;
+  }
+}
+
+// h[i][r] = sum_c part[c][i][r]; hsum = h (first pass) or hsum += h.
+__global__ void k_mdot_reduce(const double2* __restrict__ part, int nchunks, const int* __restrict__ jptr, int jfix,
+                              int maxvec, int R, double2* __restrict__ hh, double2* __restrict__ hsum, int first) {
+  const int nvec = (jptr ? *jptr : jfix) + 1;
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nvec * R) return;
+  double ax = 0, ay = 0;
+  for (int c = 0; c < nchunks; ++c) {
+    double2 a = part[(int64_t)c * maxvec * R + idx];
+    ax += a.x;
+    ay += a.y;
+  }
+  hh[idx] = make_double2(ax, ay);
+  if (hsum) {
+    if (first) hsum[idx] = make_double2(ax, ay);
+    else {
+      hsum[idx].x += ax;
+      hsum[idx].y += ay;
+    }
+  }
+}
+
+// w[row][r] += sign * sum_{i < nvec} V_i[row][r] h[i][r]
+__global__ void __launch_bounds__(NT) k_mupdate(const double2* __restrict__ V, int64_t vs, const int* __restrict__ jptr,
+                                                int jfix, const double2* __restrict__ hc, double2* __restrict__ w,
+                                                int n, int R, double sign) {
+  const int nvec = (jptr ? *jptr : jfix) + 1;
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * R) return;
+  const int r = int(idx % R);
+  double ax = 0, ay = 0;
+#pragma unroll 4
+  for (int i = 0; i < nvec; ++i) {
+    double2 a = V[(int64_t)i * vs + idx], b = hc[i * R + r];
+    ax += a.x * b.x - a.y * b.y;
+    ay += a.x * b.y + a.y * b.x;
+  }
+  double2 c = w[idx];
+  w[idx] = make_double2(c.x + sign * ax, c.y + sign * ay);
+}
+
+// Partial squared norms of w per block and RHS column.
+__global__ void __launch_bounds__(NT) k_norm2_part(const double2* __restrict__ w, int n, int R, double* __restrict__ part) {
+  __shared__ double2 red[NT];
+  const int r = threadIdx.x % R, rl = threadIdx.x / R, step = NT / R;
+  double acc = 0;
+  for (int64_t row = (int64_t)blockIdx.x * step + rl; row < n; row += (int64_t)gridDim.x * step) {
+    double2 a = w[row * R + r];
+    acc += a.x * a.x + a.y * a.y;
+  }
+  double2 s = block_sum_by_rhs(make_double2(acc, 0), R, red);
+  if (threadIdx.x < R) part[blockIdx.x * R + threadIdx.x] = s.x;
+}
+
+// nrm[r] = sqrt(sum of partials); out = w / nrm (zero where nrm = 0).  Every
+// block reduces the partials itself; block 0 publishes nrm.  out2 (optional)
+// receives the same vector.  The destination is V_kry + (j + 1 + dst_shift) * vs
+// when jptr is given, else out directly.
+__global__ void __launch_bounds__(NT) k_normalize(const double2* __restrict__ w, const double* __restrict__ part,
+                                                  int nblk, int n, int R, double* __restrict__ nrm,
+                                                  double2* __restrict__ out, const int* __restrict__ jptr, int64_t vs,
+                                                  double2* __restrict__ out2) {
+  __shared__ double inv[64];
+  if (threadIdx.x < R) {
+    double s = 0;
+    for (int b = 0; b < nblk; ++b) s += part[b * R + threadIdx.x];
+    double nv = sqrt(s);
+    inv[threadIdx.x] = nv > 0 ? 1.0 / nv : 0.0;
+    if (blockIdx.x == 0) nrm[threadIdx.x] = nv;
+  }
+  __syncthreads();
+  double2* dst = out + (jptr ? (int64_t)(*jptr + 1) * vs : 0);
+  for (int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x; idx < (int64_t)n * R; idx += (int64_t)gridDim.x * NT) {
+    double f = inv[idx % R];
+    double2 a = w[idx];
+    double2 o = make_double2(a.x * f, a.y * f);
+    dst[idx] = o;
+    if (out2) out2[idx] = o;
+  }
+}
+
+// One block per RHS column: append column j of the Hessenberg matrix, apply the
+// previous Givens rotations, form the new one, update the residual estimate.
+// The last block to finish publishes status = {all converged, j + 1} and
+// advances j.
+__global__ void __launch_bounds__(NT) k_givens(int* __restrict__ jptr, const double2* __restrict__ hsum,
+                                               const double* __restrict__ nrm, double2* __restrict__ H,
+                                               double2* __restrict__ cs, double2* __restrict__ sn,
+                                               double2* __restrict__ g, const double* __restrict__ beta,
+                                               int* __restrict__ done, int* __restrict__ iters,
+                                               double* __restrict__ resid, double tol, int maxvec, int R,
+                                               int* __restrict__ counter, int* __restrict__ status,
+                                               double* __restrict__ hist) {
+  extern __shared__ double2 col[];   // column (maxvec + 1) then the rotations (2 * maxvec)
+  double2* csl = col + maxvec + 1;
+  double2* snl = csl + maxvec;
+  const int r = blockIdx.x;
+  const int j = *jptr;
+  if (!done[r]) {
+    for (int i = threadIdx.x; i <= j; i += NT) col[i] = hsum[i * R + r];
+    for (int i = threadIdx.x; i < j; i += NT) {
+      csl[i] = cs[i * R + r];
+      snl[i] = sn[i * R + r];
+    }
+    if (threadIdx.x == 0) col[j + 1] = make_double2(nrm[r], 0.0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int i = 0; i < j; ++i) {
+        double2 c = csl[i], s = snl[i], a = col[i], b = col[i + 1];
+        // t = c a + s b ; b' = -conj(s) a + c b
+        double2 t = make_double2(c.x * a.x - c.y * a.y + s.x * b.x - s.y * b.y,
+                                 c.x * a.y + c.y * a.x + s.x * b.y + s.y * b.x);
+        double2 bn = make_double2(-(s.x * a.x + s.y * a.y) + c.x * b.x - c.y * b.y,
+                                  -(s.x * a.y - s.y * a.x) + c.x * b.y + c.y * b.x);
+        col[i] = t;
+        col[i + 1] = bn;
+      }
+      double2 a = col[j], b = col[j + 1];
+      double aa = sqrt(a.x * a.x + a.y * a.y), bb = sqrt(b.x * b.x + b.y * b.y);
+      double den = sqrt(aa * aa + bb * bb);
+      double2 c, s;
+      if (den == 0) { c = make_double2(1, 0); s = make_double2(0, 0); }
+      else if (aa == 0) { c = make_double2(0, 0); s = make_double2(b.x / den, -b.y / den); }
+      else {
+        c = make_double2(aa / den, 0);
+        double2 ph = make_double2(a.x / aa, a.y / aa);          // a / |a|
+        s = make_double2((ph.x * b.x + ph.y * b.y) / den, (ph.y * b.x - ph.x * b.y) / den);  // ph conj(b) / den
+      }
+      cs[j * R + r] = c;
+      sn[j * R + r] = s;
+      col[j] = make_double2(c.x * a.x + s.x * b.x - s.y * b.y, c.x * a.y + s.x * b.y + s.y * b.x);
+      col[j + 1] = make_double2(0, 0);
+      double2 gj = g[j * R + r];
+      g[(j + 1) * R + r] = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
+      g[j * R + r] = make_double2(c.x * gj.x, c.x * gj.y);
+      double2 gn = g[(j + 1) * R + r];
+      double res = sqrt(gn.x * gn.x + gn.y * gn.y) / beta[r];
+      resid[r] = res;
+      if (hist) hist[(int64_t)(j + 1) * R + r] = res;
+      iters[r] = j + 1;
+      if (res <= tol || nrm[r] == 0.0) done[r] = 1;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= j; i += NT) H[((int64_t)j * maxvec + i) * R + r] = col[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    int prev = atomicAdd(counter, 1);
+    if (prev == gridDim.x - 1) {
+      __threadfence();
+      int all = 1;
+      for (int q = 0; q < R; ++q) all &= __hip_atomic_load(done + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      status[0] = all;
+      status[1] = j + 1;
+      *jptr = j + 1;
+      *counter = 0;
+    }
+  }
+}
+
+// Start of a GMRES run: g_0 = beta = ||P^-1 rhs||, flags cleared, j = 0.
+__global__ void k_gmres_init(const double* __restrict__ nrm, double* __restrict__ beta, double2* __restrict__ g,
+                             int* __restrict__ done, int* __restrict__ iters, double* __restrict__ resid,
+                             int* __restrict__ jptr, int* __restrict__ counter, int* __restrict__ status, int R,
+                             double* __restrict__ hist) {
+  int r = threadIdx.x;
+  if (r < R) {
+    double b = nrm[r];
+    beta[r] = b;
+    g[r] = make_double2(b, 0);
+    done[r] = b > 0 ? 0 : 1;
+    iters[r] = 0;
+    resid[r] = b > 0 ? 1.0 : 0.0;
+    if (hist) hist[r] = resid[r];
+  }
+  if (r == 0) {
+    *jptr = 0;
+    *counter = 0;
+    status[0] = 0;
+    status[1] = 0;
+  }
 }
 
 inline unsigned nblocks(int64_t n, int t = NT) { return unsigned((n + t - 1) / t); }
@@ -517,14 +793,15 @@ void launch_slot_apply(const Handle& h, int mode, const T2* v, T2* X, T2* GL, in
   const typename Scal<T2>::T* se;
   if constexpr (std::is_same<T2, double2>::value) { op1 = d.op1; se = d.se; }
   else { op1 = d.op1_f; se = d.se_f; }
+#define HDP_SLOT_ARGS d.order, d.elem_cls, d.slot_off, d.cm_off, d.cls_m, d.cls_nr, d.cls_op1, op1, se, d.cls_se, \
+                      d.slot_row, d.slot_coef, d.row_xinv, d.row_slot, d.row_coef, v, X, GL, R
   if (mode == 0)
-    hipLaunchKernelGGL((k_slot_apply<T2, 0>), grid, dim3(NT), 0, s, d.order, d.elem_cls, d.slot_off, d.cm_off,
-                       d.cls_m, d.cls_nr, d.cls_op1, op1, se, d.cls_se, d.slot_row, d.slot_coef, d.row_xinv, v, X,
-                       GL, R);
+    hipLaunchKernelGGL((k_slot_apply<T2, 0>), grid, dim3(NT), 0, s, HDP_SLOT_ARGS);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_slot_apply<T2, 1>), grid, dim3(NT), 0, s, HDP_SLOT_ARGS);
   else
-    hipLaunchKernelGGL((k_slot_apply<T2, 1>), grid, dim3(NT), 0, s, d.order, d.elem_cls, d.slot_off, d.cm_off,
-                       d.cls_m, d.cls_nr, d.cls_op1, op1, se, d.cls_se, d.slot_row, d.slot_coef, d.row_xinv, v, X,
-                       GL, R);
+    hipLaunchKernelGGL((k_slot_apply<T2, 2>), grid, dim3(NT), 0, s, HDP_SLOT_ARGS);
+#undef HDP_SLOT_ARGS
   HIPCHECK(hipGetLastError());
 }
 
@@ -618,6 +895,60 @@ void launch_gll(const Handle& h, const double2* X, double2* field, int R, int64_
   HIPCHECK(hipGetLastError());
 }
 
+GmresDims gmres_dims(int n, int R, int maxvec) {
+  GmresDims g;
+  g.step = NT / R;
+  int64_t want = (int64_t(n) * R + 4 * NT - 1) / (4 * NT);
+  g.nchunks = int(std::max<int64_t>(1, std::min<int64_t>(64, want)));
+  g.chunk = int((int64_t(n) + g.nchunks - 1) / g.nchunks);
+  g.nchunks = int((int64_t(n) + g.chunk - 1) / g.chunk);
+  g.ngroups = (maxvec + GVEC - 1) / GVEC;
+  g.nnorm = int(std::max<int64_t>(1, std::min<int64_t>(256, (int64_t(n) * R + NT - 1) / NT)));
+  return g;
+}
+
+void launch_mdot(const double2* V, int64_t vs, const int* jptr, int jfix, const double2* w, int n, int R,
+                 const GmresDims& g, int maxvec, double2* part, hipStream_t s) {
+  hipLaunchKernelGGL((k_mdot<GVEC>), dim3(g.nchunks, g.ngroups), dim3(NT), 0, s, V, vs, jptr, jfix, w, n, R, g.chunk,
+                     maxvec, part);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_mdot_reduce(const double2* part, const GmresDims& g, const int* jptr, int jfix, int maxvec, int R,
+                        double2* hh, double2* hsum, int first, hipStream_t s) {
+  hipLaunchKernelGGL(k_mdot_reduce, dim3(nblocks(int64_t(maxvec) * R)), dim3(NT), 0, s, part, g.nchunks, jptr, jfix,
+                     maxvec, R, hh, hsum, first);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_mupdate(const double2* V, int64_t vs, const int* jptr, int jfix, const double2* hc, double2* w, int n,
+                    int R, double sign, hipStream_t s) {
+  hipLaunchKernelGGL(k_mupdate, dim3(nblocks(int64_t(n) * R)), dim3(NT), 0, s, V, vs, jptr, jfix, hc, w, n, R, sign);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_normalize(const double2* w, int n, int R, const GmresDims& g, double* part, double* nrm, double2* out,
+                      const int* jptr, int64_t vs, double2* out2, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm2_part, dim3(g.nnorm), dim3(NT), 0, s, w, n, R, part);
+  hipLaunchKernelGGL(k_normalize, dim3(g.nnorm), dim3(NT), 0, s, w, part, g.nnorm, n, R, nrm, out, jptr, vs, out2);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_givens(int* jptr, const double2* hsum, const double* nrm, double2* H, double2* cs, double2* sn, double2* g,
+                   const double* beta, int* done, int* iters, double* resid, double tol, int maxvec, int R,
+                   int* counter, int* status, double* hist, hipStream_t s) {
+  hipLaunchKernelGGL(k_givens, dim3(R), dim3(NT), size_t(3 * maxvec + 1) * sizeof(double2), s, jptr, hsum, nrm, H, cs, sn,
+                     g, beta, done, iters, resid, tol, maxvec, R, counter, status, hist);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_gmres_init(const double* nrm, double* beta, double2* g, int* done, int* iters, double* resid, int* jptr,
+                       int* counter, int* status, int R, double* hist, hipStream_t s) {
+  hipLaunchKernelGGL(k_gmres_init, dim3(1), dim3(64), 0, s, nrm, beta, g, done, iters, resid, jptr, counter, status,
+                     R, hist);
+  HIPCHECK(hipGetLastError());
+}
+
 int dots_blocks(int n, int R) {
   int64_t want = (int64_t(n) * R + NT - 1) / NT;
   return int(std::max<int64_t>(1, std::min<int64_t>(512, want)));
@@ -663,6 +994,19 @@ void launch_cast_f(const double2* x, float2* y, int64_t count, hipStream_t s) {
 
 void launch_cast_d(const float2* x, double2* y, int64_t count, hipStream_t s) {
   hipLaunchKernelGGL(k_cast_d, dim3(nblocks(count)), dim3(NT), 0, s, x, y, count);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_block_scatter(const int* elems, const int64_t* src_off, int nblk, const int64_t* dof_off,
+                          const double2* src, double2* full, int R, hipStream_t s) {
+  if (nblk == 0) return;
+  hipLaunchKernelGGL(k_block_scatter, dim3(nblk), dim3(NT), 0, s, elems, src_off, dof_off, src, full, R);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_fill_zero(double2* x, int64_t count, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_fill_zero, dim3(nblocks(count)), dim3(NT), 0, s, x, count);
   HIPCHECK(hipGetLastError());
 }
 

@@ -12,6 +12,7 @@ struct Handle;
 // Class-batched boundary operators on dual slots (one block per element).
 // mode 0: X = D_c y, GL = Phi_c^T y, with y_s = coef_s v[row_s]            (F, first half)
 // mode 1: X = Se y with y_s = coef_s v[row_s] / (C1 C1^T)_row              (P^-1, first half)
+// mode 2: as mode 1 with v a dual-slot array z and v[row] = (C_1 z)[row]     (P^-1 F, fused)
 template <class T2>
 void launch_slot_apply(const Handle& h, int mode, const T2* v, T2* X, T2* GL, int R, hipStream_t s);
 // Z = X + Phi_c (T_e w)
@@ -53,6 +54,28 @@ void launch_cast_d(const float2* x, double2* y, int64_t count, hipStream_t s);
 void launch_dense_scatter(const int64_t* idx, const double2* val, int64_t nnz, double2* M,
                           hipStream_t s);
 
+void launch_block_scatter(const int* elems, const int64_t* src_off, int nblk, const int64_t* dof_off,
+                          const double2* src, double2* full, int R, hipStream_t s);
+void launch_fill_zero(double2* x, int64_t count, hipStream_t s);
 int dots_blocks(int n, int R);
+
+// Device-resident GMRES (R divides 64; j read from device memory when jptr != nullptr)
+struct GmresDims {
+  int nchunks = 1, chunk = 1, ngroups = 1, nnorm = 1, step = 1;
+};
+GmresDims gmres_dims(int n, int R, int maxvec);
+void launch_mdot(const double2* V, int64_t vs, const int* jptr, int jfix, const double2* w, int n, int R,
+                 const GmresDims& g, int maxvec, double2* part, hipStream_t s);
+void launch_mdot_reduce(const double2* part, const GmresDims& g, const int* jptr, int jfix, int maxvec, int R,
+                        double2* hh, double2* hsum, int first, hipStream_t s);
+void launch_mupdate(const double2* V, int64_t vs, const int* jptr, int jfix, const double2* hc, double2* w, int n,
+                    int R, double sign, hipStream_t s);
+void launch_normalize(const double2* w, int n, int R, const GmresDims& g, double* part, double* nrm, double2* out,
+                      const int* jptr, int64_t vs, double2* out2, hipStream_t s);
+void launch_givens(int* jptr, const double2* hsum, const double* nrm, double2* H, double2* cs, double2* sn, double2* g,
+                   const double* beta, int* done, int* iters, double* resid, double tol, int maxvec, int R,
+                   int* counter, int* status, double* hist, hipStream_t s);
+void launch_gmres_init(const double* nrm, double* beta, double2* g, int* done, int* iters, double* resid, int* jptr,
+                       int* counter, int* status, int R, double* hist, hipStream_t s);
 
 }  // namespace hdp

@@ -426,30 +426,67 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
     h.flops_fdm += 4.0 * 8.0 * double(C.n) * C.n * C.n;
     h.flops_gll += 2.0 * 4.0 * double(C.n) * C.n * C.n;
   }
+  // quadrature tables for the loads, one per degree present
+  for (auto& C : h.classes) {
+    if (h.quad_x.count(C.n)) continue;
+    std::vector<double> xq, wq;
+    gauss_legendre(C.n + 40, xq, wq);
+    std::vector<double> Nq(xq.size() * C.n);
+    for (size_t t = 0; t < xq.size(); ++t) vertex_basis(C.n, xq[t], &Nq[t * C.n]);
+    h.quad_x[C.n] = xq;
+    h.quad_w[C.n] = wq;
+    h.quad_N[C.n] = Nq;
+  }
   // class-grouped element order
   h.order.clear();
   for (auto& C : h.classes)
     for (int e : C.elems) h.order.push_back(e);
 }
 
-// Element loads b~_e in the vertex basis (Sec. 2.2.1: f~ and r_i), [dof][R].
-void compute_loads(const Handle& h, const hdp_rhs* rhs, std::vector<cd>& B) {
-  int R = rhs->n_rhs;
-  B.assign(size_t(h.dof) * R, 0.0);
+// Element loads b~_e in the vertex basis (Sec. 2.2.1: f~ and r_i), only for
+// elements whose load is non-zero.
+void compute_loads(const Handle& h, const hdp_rhs* rhs, int R, std::vector<int>& elems, std::vector<cd>& vals) {
+  elems.clear();
+  vals.clear();
+  const int nr = rhs->n_rhs;
   double k = h.k;
   cd I(0, 1);
+  // owners of each point source (equal split among the elements whose closure holds it)
+  std::vector<std::vector<int>> owners(nr);
+  if (rhs->kind == HDP_RHS_POINT) {
+    for (int r = 0; r < nr; ++r) {
+      double px = rhs->points[2 * r], py = rhs->points[2 * r + 1];
+      double tol = 1e-12 * std::max(1.0, std::max(std::abs(px), std::abs(py)));
+      for (int f = 0; f < h.E; ++f)
+        if (px >= h.ox[f] - tol && px <= h.ox[f] + h.hx[f] + tol && py >= h.oy[f] - tol &&
+            py <= h.oy[f] + h.hy[f] + tol)
+          owners[r].push_back(f);
+    }
+  }
+  std::vector<char> touched(h.E, 0);
+  if (rhs->kind == HDP_RHS_POINT) {
+    for (auto& o : owners)
+      for (int f : o) touched[f] = 1;
+  } else if (rhs->kind == HDP_RHS_PLANE_WAVE_TOTAL) {
+    for (int e = 0; e < h.E; ++e) touched[e] = h.bmask[e] != 0;
+  } else if (rhs->kind == HDP_RHS_PLANE_WAVE_SCATTERED) {
+    for (int e = 0; e < h.E; ++e) touched[e] = h.eps[e] != 1.0;
+  } else {
+    fail(HDP_E_ARG, "unknown right-hand-side kind");
+  }
   for (int e = 0; e < h.E; ++e) {
+    if (!touched[e]) continue;
     int n = h.deg[e] + 1;
+    const std::vector<double>& xq = h.quad_x.at(n);
+    const std::vector<double>& wq = h.quad_w.at(n);
+    const std::vector<double>& Nq = h.quad_N.at(n);
+    int q = int(xq.size());
     double hx = h.hx[e], hy = h.hy[e], ox = h.ox[e], oy = h.oy[e];
-    int q = n + 40;
-    std::vector<double> xq, wq;
-    gauss_legendre(q, xq, wq);
-    std::vector<double> Nq(size_t(q) * n);
-    for (int t = 0; t < q; ++t) vertex_basis(n, xq[t], &Nq[size_t(t) * n]);
-    auto at = [&](int ix, int iy, int r) -> cd& {
-      return B[(size_t(h.dof_off[e]) + ix + size_t(n) * iy) * R + r];
-    };
-    for (int r = 0; r < R; ++r) {
+    size_t base = vals.size();
+    elems.push_back(e);
+    vals.resize(base + size_t(n) * n * R, 0.0);
+    auto at = [&](int ix, int iy, int r) -> cd& { return vals[base + (ix + size_t(n) * iy) * R + r]; };
+    for (int r = 0; r < nr; ++r) {
       if (rhs->kind == HDP_RHS_PLANE_WAVE_TOTAL) {
         double th = rhs->angles[r], dx = std::cos(th), dy = std::sin(th);
         for (int s = 1; s <= 4; ++s) {
@@ -472,7 +509,6 @@ void compute_loads(const Handle& h, const hdp_rhs* rhs, std::vector<cd>& B) {
           }
         }
       } else if (rhs->kind == HDP_RHS_PLANE_WAVE_SCATTERED) {
-        if (h.eps[e] == 1.0) continue;
         double th = rhs->angles[r], dx = std::cos(th), dy = std::sin(th);
         std::vector<cd> a(n, 0.0), b(n, 0.0);
         for (int t = 0; t < q; ++t) {
@@ -486,26 +522,17 @@ void compute_loads(const Handle& h, const hdp_rhs* rhs, std::vector<cd>& B) {
         double f0 = k * k * (h.eps[e] - 1.0) * (hx / 2) * (hy / 2);
         for (int iy = 0; iy < n; ++iy)
           for (int ix = 0; ix < n; ++ix) at(ix, iy, r) += f0 * a[ix] * b[iy];
-      } else if (rhs->kind == HDP_RHS_POINT) {
+      } else {
+        const auto& o = owners[r];
+        if (std::find(o.begin(), o.end(), e) == o.end()) continue;
         double px = rhs->points[2 * r], py = rhs->points[2 * r + 1];
-        // owners: every element whose closure holds the point (equal split)
-        double tol = 1e-12 * std::max(1.0, std::max(std::abs(px), std::abs(py)));
-        auto inside = [&](int f) {
-          return px >= h.ox[f] - tol && px <= h.ox[f] + h.hx[f] + tol && py >= h.oy[f] - tol &&
-                 py <= h.oy[f] + h.hy[f] + tol;
-        };
-        if (!inside(e)) continue;
-        int cnt = 0;
-        for (int f = 0; f < h.E; ++f) cnt += inside(f);
         double u = std::clamp(2 * (px - ox) / hx - 1, -1.0, 1.0);
         double v = std::clamp(2 * (py - oy) / hy - 1, -1.0, 1.0);
         std::vector<double> Nu(n), Nv(n);
         vertex_basis(n, u, Nu.data());
         vertex_basis(n, v, Nv.data());
         for (int iy = 0; iy < n; ++iy)
-          for (int ix = 0; ix < n; ++ix) at(ix, iy, r) += Nu[ix] * Nv[iy] / double(cnt);
-      } else {
-        fail(HDP_E_ARG, "unknown right-hand-side kind");
+          for (int ix = 0; ix < n; ++ix) at(ix, iy, r) += Nu[ix] * Nv[iy] / double(o.size());
       }
     }
   }
