@@ -13,7 +13,7 @@ FP64 GMRES-IR) are timed; `value` is the faster path that reaches 1e-8.  A
 second, profiled pass over the same K solves brackets each kernel launch with
 HIP events on the solver's stream to give the dominant kernel's average launch
 duration and its roofline fraction.  The CPU oracle is timed on a bounded
-sample (an 8x8 sub-square with the same h, p and k) on this host.
+sample (a 16x16 sub-square with the same h, p and k) on this host.
 """
 import argparse
 import json
@@ -100,6 +100,63 @@ def roofline(kernels, precision):
     return r
 
 
+def batched_scatterer(hdp, torch, steps, warmup):
+    """The 64-angle dielectric-square workload (64x64 elements on [-1,1]^2, p=12,
+    k=150, eps_r=4 on [-1/4,1/4]^2, scattered-field formulation, 360 far-field
+    angles): the plain FP64 path with one right-hand side per call (timed on a
+    sample of angles and scaled to 64) against the FP64 and mixed paths with all
+    64 angles in one batched solve."""
+    import numpy as np
+    import workloads as W
+    w = W.square_scatterer_64x64()
+    ang = np.asarray(w["rhs"]["angles"])
+    fa = np.asarray(w["far_angles"])
+    inside = np.asarray(w["eps_r"]) != 1.0
+    out = {}
+    fars = {}
+    for prec in ("fp64", "mixed"):
+        s = hdp.Solver(w, precision=prec, tol=1e-8, max_iter=300, max_rhs=len(ang))
+        if prec == "fp64":
+            n1 = 4
+            for _ in range(max(1, warmup)):
+                s.solve("plane_wave_scattered", ang[:1], want_field=False, far_angles=fa, far_inside=inside)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for a in ang[:n1]:
+                _, _, st1 = s.solve("plane_wave_scattered", [a], want_field=False, far_angles=fa, far_inside=inside)
+            torch.cuda.synchronize()
+            ms1 = (time.perf_counter() - t0) * 1e3 / n1
+            out["fp64_one_rhs_per_call"] = dict(ms_per_rhs=ms1, ms_for_64=ms1 * len(ang), iterations=st1["iterations"],
+                                                sample=f"{n1} of the 64 angles, one per call, scaled to 64")
+        for _ in range(warmup):
+            s.solve("plane_wave_scattered", ang, want_field=False, far_angles=fa, far_inside=inside)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, far, st = s.solve("plane_wave_scattered", ang, want_field=False, far_angles=fa, far_inside=inside)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        fars[prec] = far.cpu().numpy()
+        out[prec + "_batched_64"] = dict(ms_per_solve=ms, dof_per_s=s.dof * len(ang) / (ms * 1e-3),
+                                         iterations=st["iterations"], refinements=st["refinements"],
+                                         converged=st["converged"], rhs_ms=st["rhs_ms"], gmres_ms=st["gmres_ms"],
+                                         recover_ms=st["recover_ms"], setup_ms=s.info["setup_ms"])
+        out["dof"] = s.dof
+        out["l"] = s.info["l"]
+        out["n_lambda"] = s.info["n_lambda"]
+        out["n_coarse"] = s.info["n_coarse"]
+        s.close()
+        print(f"bench: batched scatterer {prec} done ({ms:.1f} ms per 64-angle solve)", file=sys.stderr, flush=True)
+    a, b = fars["mixed"], fars["fp64"]
+    out["far_field_rel_diff_mixed_vs_fp64"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    out["speedup_mixed_batched_vs_fp64_one_rhs_per_call"] = (
+        out["fp64_one_rhs_per_call"]["ms_for_64"] / out["mixed_batched_64"]["ms_per_solve"])
+    out["speedup_fp64_batched_vs_fp64_one_rhs_per_call"] = (
+        out["fp64_one_rhs_per_call"]["ms_for_64"] / out["fp64_batched_64"]["ms_per_solve"])
+    out["workload"] = "square_scatterer_64x64_p12_k150_eps4_64angles_360far"
+    return out
+
+
 def cpu_baseline():
     """The oracle as it stands on a bounded sample of the same workload."""
     import numpy as np
@@ -110,7 +167,7 @@ def cpu_baseline():
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count()
-    n = 8
+    n = 16
     h = 1.0 / 32
     w = W.small_uniform(n, 16, 100.0, domain=(0.0, n * h, 0.0, n * h),
                         rhs=dict(kind="point", points=[(n * h / 2, n * h / 2)]))
@@ -121,7 +178,7 @@ def cpu_baseline():
     t = time.perf_counter() - t0
     dof = n * n * 17 * 17
     return dict(value=dof / t, unit="DOF/s", cores=int(threads), kind="oracle",
-                sample=f"8x8 sub-square of the 32x32 mesh (h=1/32, p=16, k=100, point source at its "
+                sample=f"16x16 sub-square of the 32x32 mesh (h=1/32, p=16, k=100, point source at its "
                        f"centre vertex, l=2): {dof} DOF, oracle setup+solve to 1e-8 in {t:.1f} s, "
                        f"{E.iters} iterations, host cpu_count={os.cpu_count()}")
 
@@ -132,6 +189,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-angle batched scatterer measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the multi-GPU path is not part of this build "
@@ -143,7 +201,9 @@ def main():
     w = W.point_source_32x32()
     samples = load_samples()
     fp64, info = time_path(hdp, torch, w, "fp64", args.steps, args.warmup, samples)
+    print(f"bench: point source fp64 done ({fp64['ms_per_solve']:.2f} ms per solve)", file=sys.stderr, flush=True)
     mixed, _ = time_path(hdp, torch, w, "mixed", args.steps, args.warmup, samples)
+    print(f"bench: point source mixed done ({mixed['ms_per_solve']:.2f} ms per solve)", file=sys.stderr, flush=True)
     best_name, best = ("mixed", mixed) if (mixed["converged"] and mixed["ms_per_solve"] < fp64["ms_per_solve"]) \
         else ("fp64", fp64)
     line = {
@@ -170,6 +230,8 @@ def main():
     }
     line["roofline"]["launches_per_step"] = next(
         k["launches"] for k in best["kernels"] if k["name"] == line["roofline"]["kernel"]) / args.steps
+    if not args.no_batched:
+        line["batched_rhs"] = batched_scatterer(hdp, torch, max(1, min(args.steps, 3)), min(args.warmup, 1))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

@@ -86,7 +86,9 @@ typedef struct {
 typedef struct {
   double k;                   /* free-space wavenumber, > 0 */
   const double* eps_r;        /* host, per leaf relative permittivity; NULL means 1 */
-  int32_t l;                  /* coarse order; <= 0 selects the dispersion rule (Sec. 2.3.4) */
+  int32_t l;                  /* coarse order; <= 0 selects the dispersion rule (Sec. 2.3.4),
+                                 evaluated with each element's longest edge and local
+                                 wavenumber k sqrt(eps_r), the largest value taken */
   int32_t l_safety;           /* added to the rule's value (the paper adds 1 in Sec. 3.3) */
 } hdp_problem;
 
@@ -99,9 +101,9 @@ typedef struct {
   int32_t flags;              /* HDP_FLAG_* bits, 0 for defaults */
 } hdp_options;
 
-/* hdp_options.flags: launch every kernel of a GMRES iteration individually
- * instead of replaying the iteration as a captured HIP graph. */
-#define HDP_FLAG_EAGER 1
+/* hdp_options.flags: replay each GMRES iteration as a captured HIP graph
+ * instead of launching its kernels one by one. */
+#define HDP_FLAG_GRAPH 1
 
 typedef struct {
   int32_t kind;               /* HDP_RHS_* */

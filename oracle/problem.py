@@ -22,13 +22,15 @@ def make_mesh(w):
 
 
 def coarse_order(w, mesh=None):
-    """l: explicit, or from the dispersion rule with h = the longest element edge
-    and the free-space k (Sec. 2.3.4)."""
+    """l: explicit, or from the dispersion rule of Sec. 2.3.4 evaluated per element
+    with its longest edge and its local wavenumber k sqrt(eps_r), taking the largest
+    (with eps_r = 1: the free-space k and the longest edge, as in Sec. 3.3.1)."""
     if w.get("l", -1) >= 1:
         return int(w["l"])
     mesh = mesh or make_mesh(w)
-    h = max(max(mesh.size(e)) for e in range(mesh.E))
-    return lg.dispersion_l(w["k"], h)
+    eps = np.asarray(w.get("eps_r", np.ones(mesh.E)))
+    kh = max(w["k"] * np.sqrt(eps[e]) * max(mesh.size(e)) for e in range(mesh.E))
+    return lg.dispersion_l(kh, 1.0)
 
 
 def edge_param(mesh, e, side):

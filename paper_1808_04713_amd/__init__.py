@@ -148,7 +148,7 @@ class Solver:
     """
 
     def __init__(self, w, precision="fp64", tol=1e-8, max_iter=300, max_rhs=1, l_safety=0, device=0,
-                 graphs=True):
+                 graphs=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("hdp needs a ROCm GPU (torch.cuda.is_available() is False)")
@@ -160,7 +160,7 @@ class Solver:
         with torch.cuda.device(self.device):
             stream = torch.cuda.current_stream(self.device).cuda_stream
             opt = _Options(self.precision, float(tol), int(max_iter), int(max_rhs), ctypes.c_void_p(stream),
-                           0 if graphs else 1)
+                           1 if graphs else 0)
             h = ctypes.c_void_p()
             _check(L.hdp_setup(ctypes.byref(mesh), ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(h)))
         self.h = h
@@ -192,18 +192,34 @@ class Solver:
             r.angles = ptr
         return r, vals, n
 
-    def solve(self, kind, values, want_field=True):
-        """Returns (field, stats): field is a (n_rhs, dof) complex128 tensor of
-        GLL-node values (element blocks in leaf order, x fastest) or None."""
+    def solve(self, kind, values, want_field=True, far_angles=None, far_inside=None):
+        """Returns (field, stats) or, with far_angles, (field, far, stats).
+
+        field: (n_rhs, dof) complex128 GLL-node values (element blocks in leaf
+        order, x fastest) or None; far: (n_rhs, n_far) far-field amplitudes
+        E_far over the boundary of the leaves with far_inside != 0."""
         torch = self.torch
         r, keep, n = self._rhs(kind, values)
         field = torch.empty((n, self.dof), dtype=torch.complex128, device=self.device) if want_field else None
+        far = None
+        fa = fi = None
+        nfar = 0
+        if far_angles is not None:
+            fa = np.ascontiguousarray(np.asarray(far_angles, dtype=np.float64))
+            fi = np.ascontiguousarray(np.asarray(far_inside, dtype=np.uint8))
+            nfar = len(fa)
+            far = torch.empty((n, nfar), dtype=torch.complex128, device=self.device)
         st = Stats()
-        status = load_library().hdp_solve(self.h, ctypes.byref(r), _dptr(field) if want_field else None,
-                                          0, None, None, None, ctypes.byref(st))
+        status = load_library().hdp_solve(
+            self.h, ctypes.byref(r), _dptr(field) if want_field else None, nfar,
+            fa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if fa is not None else None,
+            fi.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if fi is not None else None,
+            _dptr(far) if far is not None else None, ctypes.byref(st))
         _check(status, allow_not_converged=True)
         d = st.as_dict()
         d["converged"] = status == STATUS_OK
+        if far_angles is not None:
+            return field, far, d
         return field, d
 
     def apply_interface(self, v, precision=None):

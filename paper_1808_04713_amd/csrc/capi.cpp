@@ -59,7 +59,7 @@ std::vector<double2> pack_c(const std::vector<cd>& v) {
 const char* const KF_NAMES[KF_COUNT] = {"slot_apply_F", "slot_apply_P", "coarse_assemble", "coarse_gemv",
                                         "slot_coarse", "row_gather", "gmres_dots", "gmres_update",
                                         "gmres_norm_scale", "fdm_local_solve", "element_coarse_fix",
-                                        "gll_sample", "precision_cast", "gmres_givens"};
+                                        "gll_sample", "precision_cast", "gmres_givens", "far_field"};
 
 static hipEvent_t prof_event(Handle& h) {
   if (!h.prof.pool.empty()) {
@@ -166,6 +166,38 @@ void build_device(Handle& h) {
   d.cls_Kc = upload(h, o_Kc); d.cls_V = upload(h, o_V);
   d.cls_gam = upload(h, cgam); d.gam_modes = upload(h, gam);
   d.cls_R = upload(h, cR); d.r_modes = upload(h, rmod);
+  // plane-wave load tables
+  {
+    std::vector<int> cq(NC);
+    std::vector<int64_t> cqo(NC);
+    std::vector<double> qx, qw, qN;
+    int64_t acc = 0;
+    for (int c = 0; c < NC; ++c) {
+      const ElemClass& C = h.classes[c];
+      const auto& xs = h.quad_x.at(C.n);
+      const auto& ws = h.quad_w.at(C.n);
+      const auto& Ns = h.quad_N.at(C.n);
+      cq[c] = int(xs.size());
+      cqo[c] = acc;
+      acc += int64_t(xs.size());
+      qx.insert(qx.end(), xs.begin(), xs.end());
+      qw.insert(qw.end(), ws.begin(), ws.end());
+      for (size_t t = 0; t < xs.size(); ++t)
+        for (int m = 0; m < 64; ++m) qN.push_back(m < C.n ? Ns[t * C.n + m] : 0.0);
+    }
+    d.cls_q = upload(h, cq);
+    d.cls_qoff = upload(h, cqo);
+    d.qx = upload(h, qx);
+    d.qw = upload(h, qw);
+    d.qN = upload(h, qN);
+    d.ox = upload(h, h.ox);
+    d.oy = upload(h, h.oy);
+    d.hx = upload(h, h.hx);
+    d.hy = upload(h, h.hy);
+    d.eps = upload(h, h.eps);
+    d.bmask = upload(h, h.bmask);
+    d.angles = dalloc<double>(h, size_t(h.max_rhs));
+  }
   d.op1 = upload(h, op1); d.phi = upload(h, phi); d.se = upload(h, se);
   std::vector<float2> op1f(op1.size()), phif(phi.size());
   std::vector<float> sef(se.size());
@@ -196,6 +228,11 @@ void build_device(Handle& h) {
     kval.push_back(make_double2(s.real(), s.imag()));
   }
   size_t nK = size_t(h.nK);
+  // the dense coarse inverse is addressed with 32-bit sizes by the factorisation
+  // routines: refuse coarse spaces whose square does not fit that range
+  if (int64_t(h.nK) * int64_t(h.nK) >= (int64_t(1) << 31))
+    fail(HDP_E_UNSUPPORTED, "coarse space too large for the dense coarse inverse (n_K = " +
+                                std::to_string(h.nK) + ", n_K^2 >= 2^31)");
   d.Kinv = dalloc<double2>(h, nK * nK);
   HIPCHECK(hipMemsetAsync(d.Kinv, 0, nK * nK * sizeof(double2), h.stream));
   int64_t* didx = upload(h, kidx);
@@ -218,7 +255,7 @@ void build_device(Handle& h) {
     HIPCHECK(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, h.stream));
     HIPCHECK(hipStreamSynchronize(h.stream));
   }
-  rocblas_destroy_handle(rb);
+  h.rocblas = rb;   // kept for the batched coarse solve
   if (st != rocblas_status_success) fail(HDP_E_DEVICE, "rocsolver failed on the coarse matrix");
   if (hinfo != 0) fail(HDP_E_COARSE, "coarse matrix K is singular");
   // work buffers sized for the largest RHS batch (padded to a power of two)
@@ -243,7 +280,7 @@ void build_device(Handle& h) {
   d.hbuf = dalloc<double2>(h, (size_t(h.max_iter) + 1) * Rp);
   d.hsum = dalloc<double2>(h, (size_t(h.max_iter) + 1) * Rp);
   d.part = dalloc<double2>(h, size_t(512) * (h.max_iter + 1) * Rp);
-  d.npart = dalloc<double>(h, size_t(512) * Rp);
+  d.npart = dalloc<double>(h, size_t(update_blocks(h.nlam, int(Rp)) + 512) * Rp);
   size_t mv = size_t(h.max_iter) + 1;
   d.vcur = dalloc<double2>(h, nl * Rp);
   d.Hdev = dalloc<double2>(h, size_t(h.max_iter) * mv * Rp);
@@ -268,6 +305,23 @@ void build_device(Handle& h) {
 
 // ---------------------------------------------------------------------------
 // Operators on dual vectors ([nlam][R]).
+// w = K^-1 g for R right-hand sides ([n_K][R]): a streaming GEMV kernel for a
+// few columns, a plain library GEMM (rocBLAS zgemm) once R makes it compute-bound.
+void coarse_solve(Handle& h, const double2* g, double2* w, int R) {
+  if (R < 4) {
+    launch_coarse_solve(h, g, w, R, h.stream);
+    return;
+  }
+  // [n_K][R] row-major is the column-major R x n_K matrix; W^T = G^T K^-1
+  rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+  rocblas_status st = rocblas_zgemm(static_cast<rocblas_handle>(h.rocblas), rocblas_operation_none,
+                                    rocblas_operation_none, R, h.nK, h.nK, &one,
+                                    reinterpret_cast<const rocblas_double_complex*>(g), R,
+                                    reinterpret_cast<const rocblas_double_complex*>(h.d.Kinv), h.nK, &zero,
+                                    reinterpret_cast<rocblas_double_complex*>(w), R);
+  if (st != rocblas_status_success) fail(HDP_E_DEVICE, "rocblas_zgemm failed in the coarse solve");
+}
+
 // F up to the element slots: z = A_11^-1 y + Phi K^-1 Phi^T y with y = C_1^T v,
 // left in slotB (FP64) or slotB_f (FP32).
 static void apply_F_slots(Handle& h, const double2* v, int R, int prec) {
@@ -292,7 +346,7 @@ static void apply_F_slots(Handle& h, const double2* v, int R, int prec) {
   }
   {
     Timed t(h, KF_COARSE, nK * nK * 16.0 + 2 * nK * c, 8.0 * nK * nK * R);
-    launch_coarse_solve(h, d.gK, d.wK, R, s);
+    coarse_solve(h, d.gK, d.wK, R);
   }
   {
     Timed t(h, KF_SLOT_COARSE, nsl * cw * 2 + ncm * c + ob * h.phi_bytes, h.flops_coarse * R);
@@ -378,7 +432,7 @@ void element_solve(Handle& h, double2* X, const double2* Bfull, int R) {
   }
   {
     Timed t(h, KF_COARSE, nK * nK * 16.0 + 2 * nK * c, 8.0 * nK * nK * R);
-    launch_coarse_solve(h, d.gK, d.wK, R, s);
+    coarse_solve(h, d.gK, d.wK, R);
   }
   {
     Timed t(h, KF_ELEMENT_MISC, 2 * dof * c + ncm * c, 0);
@@ -413,6 +467,7 @@ GmresResult gmres(Handle& h, const double2* rhs, double2* x, int R, int prec, do
   const int maxvec = h.max_iter + 1;
   max_iter = std::min(max_iter, h.max_iter);
   GmresDims gd = gmres_dims(n, R, maxvec);
+  const int nupd = update_blocks(n, R);
   const double vb = 16.0 * double(vs);
   GmresResult res;
   res.iters.assign(R, 0);
@@ -438,13 +493,14 @@ GmresResult gmres(Handle& h, const double2* rhs, double2* x, int R, int prec, do
           launch_mdot_reduce(d.part, gd, d.jdev, 0, maxvec, R, d.hbuf, d.hsum, pass == 0, s);
         }
         {
+          // the second pass also leaves the partial squared norms of w
           Timed t(h, KF_UPDATE, (nv + 2) * vb, 8.0 * nv * double(vs));
-          launch_mupdate(d.V_kry, vs, d.jdev, 0, d.hbuf, d.w, n, R, -1.0, s);
+          launch_mupdate(d.V_kry, vs, d.jdev, 0, d.hbuf, d.w, n, R, -1.0, pass == 1 ? d.npart : nullptr, s);
         }
       }
       {
-        Timed t(h, KF_NORM_SCALE, 4 * vb, 6.0 * double(vs));
-        launch_normalize(d.w, n, R, gd, d.npart, d.nrm, d.V_kry, d.jdev, vs, d.vcur, s);
+        Timed t(h, KF_NORM_SCALE, 3 * vb, 2.0 * double(vs));
+        launch_normalize_parts(d.w, n, R, d.npart, nupd, d.nrm, d.V_kry, d.jdev, vs, d.vcur, gd.nnorm, s);
       }
       {
         Timed t(h, KF_GIVENS, 0, 0);
@@ -530,9 +586,74 @@ GmresResult gmres(Handle& h, const double2* rhs, double2* x, int R, int prec, do
     for (int i = 0; i < k; ++i) ycoef[size_t(i) * R + r] = make_double2(y[i].real(), y[i].imag());
   }
   HIPCHECK(hipMemcpyAsync(d.ycoef, ycoef.data(), ycoef.size() * sizeof(double2), hipMemcpyHostToDevice, s));
-  launch_mupdate(d.V_kry, vs, nullptr, kmax - 1, d.ycoef, x, n, R, 1.0, s);
+  launch_mupdate(d.V_kry, vs, nullptr, kmax - 1, d.ycoef, x, n, R, 1.0, nullptr, s);
   HIPCHECK(hipStreamSynchronize(s));
   return res;
+}
+
+// Geometry of the far-field integral over the boundary of the leaves marked
+// inside (Sec. 3.3.1): every side of an outside leaf whose neighbour is inside,
+// Gauss-Legendre with n+12 nodes per side.
+void far_prepare(Handle& h, int n_far, const double* angles, const uint8_t* inside, int R) {
+  auto& f = h.far;
+  std::vector<uint8_t> in(inside, inside + h.E);
+  std::vector<double> an(angles, angles + n_far);
+  if (f.elem && in == f.inside && an == f.angles && f.capR >= R) return;
+  std::vector<int> el, sd, noff{0};
+  std::vector<int64_t> toff{0};
+  std::vector<double> tab, dsc, px, py, pw, pnx, pny;
+  for (int e = 0; e < h.E; ++e) {
+    if (in[e]) continue;
+    for (int s = 1; s <= 4; ++s) {
+      int nb = h.nb_e[4 * e + s - 1];
+      if (nb < 0 || !in[nb]) continue;
+      int n = h.deg[e] + 1, q = n + 12;
+      std::vector<double> xq, wq;
+      gauss_legendre(q, xq, wq);
+      double ox = h.ox[e], oy = h.oy[e], hx = h.hx[e], hy = h.hy[e];
+      double nx = s == 1 ? 1 : s == 2 ? -1 : 0, ny = s == 3 ? 1 : s == 4 ? -1 : 0;   // into e
+      std::vector<double> row(n);
+      for (int t = 0; t < q; ++t) {
+        vertex_basis(n, xq[t], row.data());
+        tab.insert(tab.end(), row.begin(), row.end());
+        double x, y;
+        if (s <= 2) { x = s == 1 ? ox : ox + hx; y = oy + (xq[t] + 1) * hy / 2; }
+        else { y = s == 3 ? oy : oy + hy; x = ox + (xq[t] + 1) * hx / 2; }
+        px.push_back(x);
+        py.push_back(y);
+        pw.push_back(wq[t] * (s <= 2 ? hy : hx) / 2);
+        pnx.push_back(nx);
+        pny.push_back(ny);
+      }
+      vertex_basis_dx(n, (s == 2 || s == 4) ? 1.0 : -1.0, row.data());
+      tab.insert(tab.end(), row.begin(), row.end());
+      dsc.push_back(s <= 2 ? nx * 2.0 / hx : ny * 2.0 / hy);
+      el.push_back(e);
+      sd.push_back(s);
+      noff.push_back(noff.back() + q);
+      toff.push_back(int64_t(tab.size()));
+    }
+  }
+  f.nsides = int(el.size());
+  f.nq = noff.back();
+  f.nfar = n_far;
+  f.inside = in;
+  f.angles = an;
+  f.capR = std::max(f.capR, R);
+  f.elem = upload(h, el);
+  f.side = upload(h, sd);
+  f.node_off = upload(h, noff);
+  f.tab_off = upload(h, toff);
+  f.tab = upload(h, tab);
+  f.dscale = upload(h, dsc);
+  f.px = upload(h, px);
+  f.py = upload(h, py);
+  f.pw = upload(h, pw);
+  f.pnx = upload(h, pnx);
+  f.pny = upload(h, pny);
+  f.ang = upload(h, an);
+  f.U = dalloc<double2>(h, size_t(std::max(1, f.nq)) * f.capR);
+  f.DU = dalloc<double2>(h, size_t(std::max(1, f.nq)) * f.capR);
 }
 
 // Order the handle's stream after everything already issued on the caller's stream.
@@ -575,7 +696,7 @@ hdp_status hdp_setup(const hdp_mesh* mesh, const hdp_problem* prob, const hdp_op
   h.tol = opt->tol;
   h.precision = opt->precision;
   h.user_stream = static_cast<hipStream_t>(opt->stream);
-  h.use_graphs = !(opt->flags & HDP_FLAG_EAGER);
+  h.use_graphs = (opt->flags & HDP_FLAG_GRAPH) != 0;
   try {
     // a stream of the handle's own (default priority): capturable, unlike the null stream
     HIPCHECK(hipStreamCreateWithFlags(&h.stream, hipStreamNonBlocking));
@@ -589,6 +710,7 @@ hdp_status hdp_setup(const hdp_mesh* mesh, const hdp_problem* prob, const hdp_op
     for (void* p : h.allocations) (void)hipFree(p);
     if (h.d.status_host) (void)hipHostFree(h.d.status_host);
     if (h.order_ev) (void)hipEventDestroy(h.order_ev);
+    if (h.rocblas) rocblas_destroy_handle(static_cast<rocblas_handle>(h.rocblas));
     if (h.stream) (void)hipStreamDestroy(h.stream);
     delete H;
     throw;
@@ -682,11 +804,30 @@ static void check_rhs(const Handle& h, const hdp_rhs* rhs) {
 // Loads of all RHS into full0 with stride Rp (zero-padded columns): packed
 // non-zero element blocks are uploaded and scattered into a zeroed array.
 static void load_rhs(Handle& h, const hdp_rhs* rhs, int Rp) {
+  auto& d = h.d;
+  hipStream_t s = h.stream;
+  if (rhs->kind == HDP_RHS_PLANE_WAVE_TOTAL || rhs->kind == HDP_RHS_PLANE_WAVE_SCATTERED) {
+    // computed on the device for the elements that carry a load
+    const int kind = rhs->kind;
+    if (d.pw_kind != kind) {
+      std::vector<int> el;
+      for (int e = 0; e < h.E; ++e)
+        if (kind == HDP_RHS_PLANE_WAVE_TOTAL ? h.bmask[e] != 0 : h.eps[e] != 1.0) el.push_back(e);
+      d.pw_elems = upload(h, el);
+      d.n_pw_elems = int(el.size());
+      d.pw_kind = kind;
+    }
+    std::vector<double> ang(Rp, 0.0);
+    for (int r = 0; r < rhs->n_rhs; ++r) ang[r] = rhs->angles[r];
+    HIPCHECK(hipMemcpyAsync(d.angles, ang.data(), rhs->n_rhs * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_fill_zero(d.full0, h.dof * Rp, s);
+    launch_plane_wave_loads(h, kind, d.pw_elems, d.n_pw_elems, d.angles, d.full0, rhs->n_rhs, Rp, s);
+    HIPCHECK(hipStreamSynchronize(s));
+    return;
+  }
   std::vector<int> elems;
   std::vector<cd> vals;
   compute_loads(h, rhs, Rp, elems, vals);
-  auto& d = h.d;
-  hipStream_t s = h.stream;
   int nb = int(elems.size());
   std::vector<int64_t> off(nb + 1, 0);
   for (int b = 0; b < nb; ++b) {
@@ -735,7 +876,6 @@ hdp_status hdp_solve(hdp_handle* H, const hdp_rhs* rhs, hdp_c64* field, int32_t 
   Handle& h = H->h;
   check_rhs(h, rhs);
   if (far && (n_far < 1 || !far_angles || !far_inside)) fail(HDP_E_ARG, "far-field arguments incomplete");
-  if (far) fail(HDP_E_UNSUPPORTED, "far field not implemented in this build");
   auto t0 = std::chrono::steady_clock::now();
   auto& d = h.d;
   hipStream_t s = h.stream;
@@ -809,6 +949,11 @@ hdp_status hdp_solve(hdp_handle* H, const hdp_rhs* rhs, hdp_c64* field, int32_t 
   if (field) {
     Timed t(h, KF_GLL, 2.0 * h.dof * 16.0 * R, h.flops_gll * R);
     launch_gll(h, d.full1, reinterpret_cast<double2*>(field), Rp, h.dof, R, s);
+  }
+  if (far) {
+    far_prepare(h, n_far, far_angles, far_inside, Rp);
+    Timed t(h, KF_FAR, 0, 0);
+    launch_far_field(h, d.full1, Rp, R, reinterpret_cast<double2*>(far), s);
   }
   HIPCHECK(hipStreamSynchronize(s));
   prof_flush(h);

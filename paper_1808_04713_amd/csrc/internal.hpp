@@ -52,7 +52,7 @@ struct DevOps {
 
 enum KernelFamily {
   KF_SLOT_F = 0, KF_SLOT_P, KF_ASSEMBLE, KF_COARSE, KF_SLOT_COARSE, KF_ROWGATHER, KF_DOTS, KF_UPDATE,
-  KF_NORM_SCALE, KF_FDM, KF_ELEMENT_MISC, KF_GLL, KF_CAST, KF_GIVENS, KF_COUNT
+  KF_NORM_SCALE, KF_FDM, KF_ELEMENT_MISC, KF_GLL, KF_CAST, KF_GIVENS, KF_FAR, KF_COUNT
 };
 extern const char* const KF_NAMES[KF_COUNT];
 
@@ -81,6 +81,7 @@ struct Handle {
   std::vector<int> cls;                 // class of each element
   std::vector<ElemClass> classes;
   std::vector<int> bmask;
+  std::vector<int> nb_e;                // neighbour across each side (4 per element), -1 on the boundary
   // offsets
   std::vector<int64_t> dof_off;   // per element, n_e^2 blocks
   std::vector<int> slot_off;      // per element, dual slots
@@ -149,11 +150,30 @@ struct Handle {
     int* load_elems = nullptr;
     int64_t* load_off = nullptr;
     double2* load_vals = nullptr;
+    // plane-wave load tables: per class the Gauss rule (q nodes) and the vertex basis there
+    int *cls_q = nullptr, *bmask = nullptr, *pw_elems = nullptr;
+    int64_t* cls_qoff = nullptr;
+    double *qx = nullptr, *qw = nullptr, *qN = nullptr, *ox = nullptr, *oy = nullptr, *hx = nullptr, *hy = nullptr,
+           *eps = nullptr, *angles = nullptr;
+    int n_pw_elems = 0, pw_kind = -1;
     double2* ycoef = nullptr;
   } d;
   std::vector<void*> allocations;
   Prof prof;
-  bool use_graphs = true;
+  // far-field geometry of the last request (device arrays, grown on demand)
+  struct Far {
+    int nsides = 0, nq = 0, nfar = 0;
+    std::vector<uint8_t> inside;
+    std::vector<double> angles;
+    int *elem = nullptr, *side = nullptr, *node_off = nullptr;
+    int64_t* tab_off = nullptr;
+    double *tab = nullptr, *dscale = nullptr, *px = nullptr, *py = nullptr, *pw = nullptr, *pnx = nullptr,
+           *pny = nullptr, *ang = nullptr;
+    double2 *U = nullptr, *DU = nullptr;
+    int capR = 0;
+  } far;
+  void* rocblas = nullptr;   // rocblas_handle for the batched coarse solve
+  bool use_graphs = false;
   std::vector<double> last_hist;   // residual history of the last GMRES run, [iteration][R]
   int last_hist_R = 0, last_hist_len = 0;
   double t_launch = 0, t_wait = 0;

@@ -40,6 +40,26 @@ template <class T2> __device__ __forceinline__ T2 mk(double x, double y);
 template <> __device__ __forceinline__ double2 mk<double2>(double x, double y) { return make_double2(x, y); }
 template <> __device__ __forceinline__ float2 mk<float2>(double x, double y) { return make_float2(float(x), float(y)); }
 
+// Reduce a per-thread value over the threads of a block that share an RHS
+// column (lanes with equal lane % R inside a wave, then the four waves).
+__device__ __forceinline__ double2 block_sum_by_rhs(double2 v, int R, double2* red) {
+  for (int off = 32; off >= R && off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane < R) red[wv * 64 + lane] = v;
+  __syncthreads();
+  double2 s = make_double2(0, 0);
+  if (threadIdx.x < R)
+    for (int q = 0; q < NT / 64; ++q) {
+      s.x += red[q * 64 + threadIdx.x].x;
+      s.y += red[q * 64 + threadIdx.x].y;
+    }
+  __syncthreads();
+  return s;   // valid in threads 0..R-1
+}
+
 // ---------------------------------------------------------------------------
 // Slot kernels: one block per element (class-grouped order), RC RHS per block.
 template <class T2, int MODE>
@@ -514,6 +534,159 @@ __global__ void k_cast_d(const float2* __restrict__ x, double2* __restrict__ y, 
   if (idx < count) y[idx] = make_double2(double(x[idx].x), double(x[idx].y));
 }
 
+// Far field, step 1: trace u and normal derivative d_n' u at the Gauss nodes of
+// every boundary side of the enclosed region (Sec. 3.3.1), one block per
+// (side, RHS).  For a side normal to x the trace row of the vertex-basis
+// coefficients is X[a0, b] (a0 = 0 at x = +1, 1 at x = -1) and the normal
+// derivative uses dN~_a(+-1); sides normal to y swap the roles.
+__global__ void __launch_bounds__(NT) k_far_trace(const int* __restrict__ elem, const int* __restrict__ side,
+                                                  const int* __restrict__ node_off, const int64_t* __restrict__ tab_off,
+                                                  const double* __restrict__ tab, const double* __restrict__ dscale,
+                                                  const int* __restrict__ elem_cls, const int* __restrict__ cls_n,
+                                                  const int64_t* __restrict__ dof_off, const double2* __restrict__ X,
+                                                  int R, double2* __restrict__ U, double2* __restrict__ DU) {
+  __shared__ double2 tv[64], dv[64];
+  const int g = blockIdx.x, r = blockIdx.y;
+  const int e = elem[g], sd = side[g];
+  const int n = cls_n[elem_cls[e]];
+  const int64_t base = dof_off[e];
+  // tab for this side: [q][n] basis values at the nodes, then dN~(end) (n values)
+  const int q0 = node_off[g], nq = node_off[g + 1] - q0;
+  const double* Nq = tab + tab_off[g];
+  const double* dend = Nq + (int64_t)nq * n;
+  const bool xside = sd <= 2;
+  const int a0 = (sd == 2 || sd == 4) ? 0 : 1;
+  for (int b = threadIdx.x; b < n; b += NT) {
+    double2 t = xside ? X[(base + a0 + (int64_t)n * b) * R + r] : X[(base + b + (int64_t)n * a0) * R + r];
+    double dx = 0, dy = 0;
+    for (int a = 0; a < n; ++a) {
+      double2 c = xside ? X[(base + a + (int64_t)n * b) * R + r] : X[(base + b + (int64_t)n * a) * R + r];
+      dx += dend[a] * c.x;
+      dy += dend[a] * c.y;
+    }
+    tv[b] = t;
+    dv[b] = make_double2(dx * dscale[g], dy * dscale[g]);
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < nq; q += NT) {
+    double ux = 0, uy = 0, vx = 0, vy = 0;
+    for (int b = 0; b < n; ++b) {
+      double w = Nq[(int64_t)q * n + b];
+      ux += w * tv[b].x;
+      uy += w * tv[b].y;
+      vx += w * dv[b].x;
+      vy += w * dv[b].y;
+    }
+    U[(int64_t)(q0 + q) * R + r] = make_double2(ux, uy);
+    DU[(int64_t)(q0 + q) * R + r] = make_double2(vx, vy);
+  }
+}
+
+// Far field, step 2: E[r][phi] = sum_q w_q e^{-i k xhat.x_q} [(xhat.n'_q) U_q + (i k)^-1 DU_q].
+__global__ void __launch_bounds__(NT) k_far_sum(int nq, const double* __restrict__ px, const double* __restrict__ py,
+                                                const double* __restrict__ pw, const double* __restrict__ pnx,
+                                                const double* __restrict__ pny, const double* __restrict__ ang,
+                                                double k, const double2* __restrict__ U, const double2* __restrict__ DU,
+                                                int R, int nrhs_out, int nfar, double2* __restrict__ E) {
+  __shared__ double2 red[NT];
+  const int f = blockIdx.x;
+  const double cx = cos(ang[f]), cy = sin(ang[f]);
+  const int r = threadIdx.x % R, rl = threadIdx.x / R, step = NT / R;
+  double ax = 0, ay = 0;
+  for (int q = rl; q < nq; q += step) {
+    double ph = -k * (cx * px[q] + cy * py[q]);
+    double c = cos(ph), s = sin(ph);
+    double xn = cx * pnx[q] + cy * pny[q];
+    double2 u = U[(int64_t)q * R + r], du = DU[(int64_t)q * R + r];
+    // (i k)^-1 du = -i du / k
+    double tx = xn * u.x + du.y / k, ty = xn * u.y - du.x / k;
+    ax += pw[q] * (c * tx - s * ty);
+    ay += pw[q] * (c * ty + s * tx);
+  }
+  double2 t = block_sum_by_rhs(make_double2(ax, ay), R, red);
+  if (threadIdx.x < R && threadIdx.x < nrhs_out) E[(int64_t)threadIdx.x * nfar + f] = t;
+}
+
+// Plane-wave loads in the vertex basis, one block per (listed element, RHS):
+// scattered field, f = k^2 (eps - 1) e^{ik d.x} (separable: b = f0 a (x) b);
+// total field, impedance data g = ik(d.n - 1) e^{ik d.x} on the boundary sides.
+// Nq holds the vertex basis at the element degree's Gauss nodes ([q][n]).
+__global__ void __launch_bounds__(NT) k_plane_wave_loads(
+    int kind, const int* __restrict__ elems, const int* __restrict__ elem_cls, const int* __restrict__ cls_n,
+    const int64_t* __restrict__ dof_off, const int* __restrict__ cls_q, const int64_t* __restrict__ cls_qoff,
+    const double* __restrict__ qx, const double* __restrict__ qw, const double* __restrict__ qN,
+    const double* __restrict__ ox, const double* __restrict__ oy, const double* __restrict__ hx,
+    const double* __restrict__ hy, const double* __restrict__ eps, const int* __restrict__ bmask,
+    const double* __restrict__ angles, double k, double2* __restrict__ B, int R) {
+  __shared__ double2 a[64], b[64], sv[4][64];
+  const int e = elems[blockIdx.x], r = blockIdx.y;
+  const int c = elem_cls[e], n = cls_n[c], q = cls_q[c];
+  const double* xq = qx + cls_qoff[c];
+  const double* wq = qw + cls_qoff[c];
+  const double* N = qN + cls_qoff[c] * 64;   // [q][64], basis padded to 64 columns
+  const double dx = cos(angles[r]), dy = sin(angles[r]);
+  const double X0 = ox[e], Y0 = oy[e], HX = hx[e], HY = hy[e];
+  const int64_t base = dof_off[e];
+  if (kind == 2) {
+    for (int m = threadIdx.x; m < 2 * n; m += NT) {
+      const bool yd = m >= n;
+      const int mm = yd ? m - n : m;
+      double sx = 0, sy = 0;
+      for (int t = 0; t < q; ++t) {
+        double pos = yd ? Y0 + (xq[t] + 1) * HY / 2 : X0 + (xq[t] + 1) * HX / 2;
+        double ph = k * (yd ? dy : dx) * pos;
+        double wn = wq[t] * N[(int64_t)t * 64 + mm];
+        sx += wn * cos(ph);
+        sy += wn * sin(ph);
+      }
+      if (yd) b[mm] = make_double2(sx, sy); else a[mm] = make_double2(sx, sy);
+    }
+    __syncthreads();
+    const double f0 = k * k * (eps[e] - 1.0) * (HX / 2) * (HY / 2);
+    for (int t = threadIdx.x; t < n * n; t += NT) {
+      int ix = t % n, iy = t / n;
+      double2 p = cmul(a[ix], b[iy]);
+      B[(base + t) * R + r] = make_double2(f0 * p.x, f0 * p.y);
+    }
+  } else {
+    for (int t = threadIdx.x; t < n * n; t += NT) B[(base + t) * R + r] = make_double2(0, 0);
+    for (int m = threadIdx.x; m < 4 * n; m += NT) {
+      const int sd = m / n + 1, mm = m % n;
+      double sx = 0, sy = 0;
+      if (bmask[e] & (1 << (sd - 1))) {
+        const double nx = sd == 1 ? -1 : sd == 2 ? 1 : 0, ny = sd == 3 ? -1 : sd == 4 ? 1 : 0;
+        const double hl = sd <= 2 ? HY : HX;
+        const double gx = 0, gy = k * (dx * nx + dy * ny - 1.0);   // ik(d.n - 1)
+        for (int t = 0; t < q; ++t) {
+          double x, y;
+          if (sd <= 2) { x = sd == 1 ? X0 : X0 + HX; y = Y0 + (xq[t] + 1) * HY / 2; }
+          else { y = sd == 3 ? Y0 : Y0 + HY; x = X0 + (xq[t] + 1) * HX / 2; }
+          double ph = k * (dx * x + dy * y);
+          double cr = cos(ph), ci = sin(ph);
+          double wn = wq[t] * (hl / 2) * N[(int64_t)t * 64 + mm];
+          sx += wn * (gx * cr - gy * ci);
+          sy += wn * (gx * ci + gy * cr);
+        }
+      }
+      sv[sd - 1][mm] = make_double2(sx, sy);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      // scatter the four side vectors onto the trace modes (left: ix=1, right: ix=0,
+      // bottom: iy=1, top: iy=0); corners receive two contributions
+      for (int sd = 1; sd <= 4; ++sd) {
+        if (!(bmask[e] & (1 << (sd - 1)))) continue;
+        for (int mm = 0; mm < n; ++mm) {
+          int64_t pos = sd == 1 ? 1 + (int64_t)n * mm : sd == 2 ? (int64_t)n * mm : sd == 3 ? mm + n : mm;
+          double2& dst = B[(base + pos) * R + r];
+          dst.x += sv[sd - 1][mm].x;
+          dst.y += sv[sd - 1][mm].y;
+        }
+      }
+    }
+  }
+}
+
 __global__ void k_fill_zero(double2* __restrict__ x, int64_t count) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < count) x[idx] = make_double2(0.0, 0.0);
@@ -541,26 +714,6 @@ __global__ void k_dense_scatter(const int64_t* __restrict__ idx, const double2* 
 // Device-resident GMRES.  The iteration index j lives in device memory so every
 // launch has a fixed shape; R (RHS count) divides 64 and thread t owns RHS
 // column t % R.  nvec = j + 1 Arnoldi vectors take part in an iteration.
-
-// Reduce a per-thread value over the threads of a block that share an RHS
-// column (lanes with equal lane % R inside a wave, then the four waves).
-__device__ __forceinline__ double2 block_sum_by_rhs(double2 v, int R, double2* red) {
-  for (int off = 32; off >= R && off > 0; off >>= 1) {
-    v.x += __shfl_xor(v.x, off, 64);
-    v.y += __shfl_xor(v.y, off, 64);
-  }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane < R) red[wv * 64 + lane] = v;
-  __syncthreads();
-  double2 s = make_double2(0, 0);
-  if (threadIdx.x < R)
-    for (int q = 0; q < NT / 64; ++q) {
-      s.x += red[q * 64 + threadIdx.x].x;
-      s.y += red[q * 64 + threadIdx.x].y;
-    }
-  __syncthreads();
-  return s;   // valid in threads 0..R-1
-}
 
 // part[c][i][r] = sum over the rows of chunk c of conj(V_i) w, i in group blockIdx.y.
 template <int GV>
@@ -597,44 +750,64 @@ __global__ void __launch_bounds__(NT) k_mdot(const double2* __restrict__ V, int6
 }
 
 // h[i][r] = sum_c part[c][i][r]; hsum = h (first pass) or hsum += h.
-__global__ void k_mdot_reduce(const double2* __restrict__ part, int nchunks, const int* __restrict__ jptr, int jfix,
-                              int maxvec, int R, double2* __restrict__ hh, double2* __restrict__ hsum, int first) {
+// One wavefront per (i, r): lanes stride over the chunks, then a shuffle tree.
+__global__ void __launch_bounds__(NT) k_mdot_reduce(const double2* __restrict__ part, int nchunks,
+                                                    const int* __restrict__ jptr, int jfix, int maxvec, int R,
+                                                    double2* __restrict__ hh, double2* __restrict__ hsum,
+                                                    int first) {
   const int nvec = (jptr ? *jptr : jfix) + 1;
-  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int idx = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);   // i * R + r
   if (idx >= nvec * R) return;
   double ax = 0, ay = 0;
-  for (int c = 0; c < nchunks; ++c) {
+  for (int c = lane; c < nchunks; c += 64) {
     double2 a = part[(int64_t)c * maxvec * R + idx];
     ax += a.x;
     ay += a.y;
   }
-  hh[idx] = make_double2(ax, ay);
-  if (hsum) {
-    if (first) hsum[idx] = make_double2(ax, ay);
-    else {
-      hsum[idx].x += ax;
-      hsum[idx].y += ay;
+  for (int off = 32; off > 0; off >>= 1) {
+    ax += __shfl_xor(ax, off, 64);
+    ay += __shfl_xor(ay, off, 64);
+  }
+  if (lane == 0) {
+    hh[idx] = make_double2(ax, ay);
+    if (hsum) {
+      if (first) hsum[idx] = make_double2(ax, ay);
+      else {
+        hsum[idx].x += ax;
+        hsum[idx].y += ay;
+      }
     }
   }
 }
 
-// w[row][r] += sign * sum_{i < nvec} V_i[row][r] h[i][r]
+// w[row][r] += sign * sum_{i < nvec} V_i[row][r] h[i][r]; when npart is given the
+// block also writes the partial squared norms of the updated w (per RHS column).
 __global__ void __launch_bounds__(NT) k_mupdate(const double2* __restrict__ V, int64_t vs, const int* __restrict__ jptr,
                                                 int jfix, const double2* __restrict__ hc, double2* __restrict__ w,
-                                                int n, int R, double sign) {
+                                                int n, int R, double sign, double* __restrict__ npart) {
+  __shared__ double2 red[NT];
   const int nvec = (jptr ? *jptr : jfix) + 1;
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)n * R) return;
-  const int r = int(idx % R);
-  double ax = 0, ay = 0;
+  const int r = threadIdx.x % R;   // NT is a multiple of R, so idx % R == threadIdx.x % R
+  double nx = 0;
+  if (idx < (int64_t)n * R) {
+    double ax = 0, ay = 0;
 #pragma unroll 4
-  for (int i = 0; i < nvec; ++i) {
-    double2 a = V[(int64_t)i * vs + idx], b = hc[i * R + r];
-    ax += a.x * b.x - a.y * b.y;
-    ay += a.x * b.y + a.y * b.x;
+    for (int i = 0; i < nvec; ++i) {
+      double2 a = V[(int64_t)i * vs + idx], b = hc[i * R + r];
+      ax += a.x * b.x - a.y * b.y;
+      ay += a.x * b.y + a.y * b.x;
+    }
+    double2 c = w[idx];
+    double2 o = make_double2(c.x + sign * ax, c.y + sign * ay);
+    w[idx] = o;
+    nx = o.x * o.x + o.y * o.y;
   }
-  double2 c = w[idx];
-  w[idx] = make_double2(c.x + sign * ax, c.y + sign * ay);
+  if (npart) {
+    double2 t = block_sum_by_rhs(make_double2(nx, 0), R, red);
+    if (threadIdx.x < R) npart[blockIdx.x * R + threadIdx.x] = t.x;
+  }
 }
 
 // Partial squared norms of w per block and RHS column.
@@ -654,17 +827,27 @@ __global__ void __launch_bounds__(NT) k_norm2_part(const double2* __restrict__ w
 // block reduces the partials itself; block 0 publishes nrm.  out2 (optional)
 // receives the same vector.  The destination is V_kry + (j + 1 + dst_shift) * vs
 // when jptr is given, else out directly.
-__global__ void __launch_bounds__(NT) k_normalize(const double2* __restrict__ w, const double* __restrict__ part,
-                                                  int nblk, int n, int R, double* __restrict__ nrm,
-                                                  double2* __restrict__ out, const int* __restrict__ jptr, int64_t vs,
+// nrm[r] = sqrt(sum_b part[b][r]): one block per RHS column.
+__global__ void __launch_bounds__(NT) k_norm_reduce(const double* __restrict__ part, int nblk, int R,
+                                                    double* __restrict__ nrm) {
+  __shared__ double2 red[NT];
+  const int r = blockIdx.x;
+  double acc = 0;
+  for (int b = threadIdx.x; b < nblk; b += NT) acc += part[(int64_t)b * R + r];
+  double2 t = block_sum_by_rhs(make_double2(acc, 0), 1, red);
+  if (threadIdx.x == 0) nrm[r] = sqrt(t.x);
+}
+
+// out = w / nrm (zero where nrm = 0); out2 (optional) receives the same vector.
+// The destination is V_kry + (j + 1) * vs when jptr is given, else out directly.
+__global__ void __launch_bounds__(NT) k_normalize(const double2* __restrict__ w, const double* __restrict__ nrm,
+                                                  int n, int R, double2* __restrict__ out,
+                                                  const int* __restrict__ jptr, int64_t vs,
                                                   double2* __restrict__ out2) {
   __shared__ double inv[64];
   if (threadIdx.x < R) {
-    double s = 0;
-    for (int b = 0; b < nblk; ++b) s += part[b * R + threadIdx.x];
-    double nv = sqrt(s);
+    double nv = nrm[threadIdx.x];
     inv[threadIdx.x] = nv > 0 ? 1.0 / nv : 0.0;
-    if (blockIdx.x == 0) nrm[threadIdx.x] = nv;
   }
   __syncthreads();
   double2* dst = out + (jptr ? (int64_t)(*jptr + 1) * vs : 0);
@@ -916,21 +1099,32 @@ void launch_mdot(const double2* V, int64_t vs, const int* jptr, int jfix, const 
 
 void launch_mdot_reduce(const double2* part, const GmresDims& g, const int* jptr, int jfix, int maxvec, int R,
                         double2* hh, double2* hsum, int first, hipStream_t s) {
-  hipLaunchKernelGGL(k_mdot_reduce, dim3(nblocks(int64_t(maxvec) * R)), dim3(NT), 0, s, part, g.nchunks, jptr, jfix,
-                     maxvec, R, hh, hsum, first);
+  hipLaunchKernelGGL(k_mdot_reduce, dim3(nblocks(int64_t(maxvec) * R, NT / 64)), dim3(NT), 0, s, part, g.nchunks,
+                     jptr, jfix, maxvec, R, hh, hsum, first);
   HIPCHECK(hipGetLastError());
 }
 
 void launch_mupdate(const double2* V, int64_t vs, const int* jptr, int jfix, const double2* hc, double2* w, int n,
-                    int R, double sign, hipStream_t s) {
-  hipLaunchKernelGGL(k_mupdate, dim3(nblocks(int64_t(n) * R)), dim3(NT), 0, s, V, vs, jptr, jfix, hc, w, n, R, sign);
+                    int R, double sign, double* npart, hipStream_t s) {
+  hipLaunchKernelGGL(k_mupdate, dim3(nblocks(int64_t(n) * R)), dim3(NT), 0, s, V, vs, jptr, jfix, hc, w, n, R, sign,
+                     npart);
+  HIPCHECK(hipGetLastError());
+}
+
+int update_blocks(int n, int R) { return int(nblocks(int64_t(n) * R)); }
+
+void launch_normalize_parts(const double2* w, int n, int R, const double* part, int nblk, double* nrm, double2* out,
+                            const int* jptr, int64_t vs, double2* out2, int nout_blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm_reduce, dim3(R), dim3(NT), 0, s, part, nblk, R, nrm);
+  hipLaunchKernelGGL(k_normalize, dim3(nout_blocks), dim3(NT), 0, s, w, nrm, n, R, out, jptr, vs, out2);
   HIPCHECK(hipGetLastError());
 }
 
 void launch_normalize(const double2* w, int n, int R, const GmresDims& g, double* part, double* nrm, double2* out,
                       const int* jptr, int64_t vs, double2* out2, hipStream_t s) {
   hipLaunchKernelGGL(k_norm2_part, dim3(g.nnorm), dim3(NT), 0, s, w, n, R, part);
-  hipLaunchKernelGGL(k_normalize, dim3(g.nnorm), dim3(NT), 0, s, w, part, g.nnorm, n, R, nrm, out, jptr, vs, out2);
+  hipLaunchKernelGGL(k_norm_reduce, dim3(R), dim3(NT), 0, s, part, g.nnorm, R, nrm);
+  hipLaunchKernelGGL(k_normalize, dim3(g.nnorm), dim3(NT), 0, s, w, nrm, n, R, out, jptr, vs, out2);
   HIPCHECK(hipGetLastError());
 }
 
@@ -1001,6 +1195,30 @@ void launch_block_scatter(const int* elems, const int64_t* src_off, int nblk, co
                           const double2* src, double2* full, int R, hipStream_t s) {
   if (nblk == 0) return;
   hipLaunchKernelGGL(k_block_scatter, dim3(nblk), dim3(NT), 0, s, elems, src_off, dof_off, src, full, R);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_far_field(const Handle& h, const double2* X, int R, int nrhs_out, double2* E, hipStream_t s) {
+  const auto& d = h.d;
+  const auto& f = h.far;
+  if (f.nsides == 0) {
+    launch_fill_zero(E, int64_t(nrhs_out) * f.nfar, s);
+    return;
+  }
+  hipLaunchKernelGGL(k_far_trace, dim3(f.nsides, R), dim3(NT), 0, s, f.elem, f.side, f.node_off, f.tab_off, f.tab,
+                     f.dscale, d.elem_cls, d.cls_n, d.dof_off, X, R, f.U, f.DU);
+  hipLaunchKernelGGL(k_far_sum, dim3(f.nfar), dim3(NT), 0, s, f.nq, f.px, f.py, f.pw, f.pnx, f.pny, f.ang, h.k, f.U,
+                     f.DU, R, nrhs_out, f.nfar, E);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_plane_wave_loads(const Handle& h, int kind, const int* elems, int nel, const double* angles, double2* B,
+                             int nrhs, int R, hipStream_t s) {
+  if (nel == 0 || nrhs == 0) return;
+  if (nrhs > R) fail(HDP_E_ARG, "plane-wave loads: more right-hand sides than the stride");
+  const auto& d = h.d;
+  hipLaunchKernelGGL(k_plane_wave_loads, dim3(nel, nrhs), dim3(NT), 0, s, kind, elems, d.elem_cls, d.cls_n, d.dof_off,
+                     d.cls_q, d.cls_qoff, d.qx, d.qw, d.qN, d.ox, d.oy, d.hx, d.hy, d.eps, d.bmask, angles, h.k, B, R);
   HIPCHECK(hipGetLastError());
 }
 

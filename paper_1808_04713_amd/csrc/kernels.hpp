@@ -57,6 +57,12 @@ void launch_dense_scatter(const int64_t* idx, const double2* val, int64_t nnz, d
 void launch_block_scatter(const int* elems, const int64_t* src_off, int nblk, const int64_t* dof_off,
                           const double2* src, double2* full, int R, hipStream_t s);
 void launch_fill_zero(double2* x, int64_t count, hipStream_t s);
+// plane-wave loads (kind 0 total field, 2 scattered field) of the listed elements into columns
+// 0..nrhs-1 of B ([dof][R]); the other columns and the other elements are left untouched
+void launch_plane_wave_loads(const Handle& h, int kind, const int* elems, int nel, const double* angles, double2* B,
+                             int nrhs, int R, hipStream_t s);
+// far field of the recovered fields X ([dof][R]) into E ([nrhs_out][nfar]) using h.far
+void launch_far_field(const Handle& h, const double2* X, int R, int nrhs_out, double2* E, hipStream_t s);
 int dots_blocks(int n, int R);
 
 // Device-resident GMRES (R divides 64; j read from device memory when jptr != nullptr)
@@ -69,7 +75,11 @@ void launch_mdot(const double2* V, int64_t vs, const int* jptr, int jfix, const 
 void launch_mdot_reduce(const double2* part, const GmresDims& g, const int* jptr, int jfix, int maxvec, int R,
                         double2* hh, double2* hsum, int first, hipStream_t s);
 void launch_mupdate(const double2* V, int64_t vs, const int* jptr, int jfix, const double2* hc, double2* w, int n,
-                    int R, double sign, hipStream_t s);
+                    int R, double sign, double* npart, hipStream_t s);
+int update_blocks(int n, int R);
+// normalisation from partial squared norms already in part ([nblk][R])
+void launch_normalize_parts(const double2* w, int n, int R, const double* part, int nblk, double* nrm, double2* out,
+                            const int* jptr, int64_t vs, double2* out2, int nout_blocks, hipStream_t s);
 void launch_normalize(const double2* w, int n, int R, const GmresDims& g, double* part, double* nrm, double2* out,
                       const int* jptr, int64_t vs, double2* out2, hipStream_t s);
 void launch_givens(int* jptr, const double2* hsum, const double* nrm, double2* H, double2* cs, double2* sn, double2* g,

@@ -287,10 +287,14 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
       nb_e[4 * e + s - 1] = o.first;
       nb_s[4 * e + s - 1] = o.second;
     }
-  // coarse order l (Sec. 2.3.4): h is the longest element edge, k the free-space k
-  double hmax = 0;
-  for (int e = 0; e < E; ++e) hmax = std::max(hmax, std::max(h.hx[e], h.hy[e]));
-  h.l = prob->l > 0 ? prob->l : dispersion_l(prob->k, hmax) + std::max(0, prob->l_safety);
+  h.nb_e = nb_e;
+  // coarse order l (Sec. 2.3.4): the criterion is evaluated for every element with
+  // its longest edge and its local wavenumber k sqrt(eps_r), and the largest value
+  // is used (with eps_r = 1 this is the free-space k and the longest edge)
+  double khmax = 0;
+  for (int e = 0; e < E; ++e)
+    khmax = std::max(khmax, prob->k * std::sqrt(std::max(h.eps[e], 0.0)) * std::max(h.hx[e], h.hy[e]));
+  h.l = prob->l > 0 ? prob->l : dispersion_l(khmax, 1.0) + std::max(0, prob->l_safety);
   for (int e = 0; e < E; ++e)
     if (h.l >= h.deg[e])
       fail(HDP_E_UNSUPPORTED, "coarse order l must be below every element degree in this build");

@@ -110,6 +110,25 @@ def test_interface_rhs(name, oracles):
     s.close()
 
 
+@pytest.mark.parametrize("name,kind", [("plane_wave_4x4", "plane_wave_total"),
+                                       ("scatterer_6x6_p6", "plane_wave_scattered"),
+                                       ("scatterer_6x6_p6", "plane_wave_total")])
+def test_interface_rhs_several_angles(name, kind):
+    """Device-computed plane-wave loads, three angles in a stride of four columns:
+    each column equals the oracle's interface data for that angle alone."""
+    w = CASES[name]
+    angles = [0.3, 2.0, 4.4]
+    s = hdp().Solver(w, max_rhs=4)
+    g = s.interface_rhs(kind, angles).cpu().numpy()
+    assert g.shape[1] >= len(angles)
+    for i, a in enumerate(angles):
+        w1 = dict(w, rhs=dict(kind=kind, angles=[a]))
+        d1 = pb.Discretisation(w1)
+        ref = dpe.ElementwiseDP(d1, pb.coarse_order(w1, d1.mesh)).interface_rhs()
+        assert rel(g[:, i], ref) < 1e-12
+    s.close()
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_solve_fp64_matches_oracle(name, oracles):
     disc, l, E = oracles[name]
@@ -227,7 +246,7 @@ def test_graph_replays_match_eager_launches():
     launching every kernel, over several solves with eager work in between."""
     w = CASES["uniform_5x5_p7_l3"]
     kind, vals = hdp().rhs_values(w)
-    sg = hdp().Solver(w, tol=1e-11)
+    sg = hdp().Solver(w, tol=1e-11, graphs=True)
     se = hdp().Solver(w, tol=1e-11, graphs=False)
     ref, st_ref = se.solve(kind, vals)
     ref = ref.cpu().numpy()
@@ -240,7 +259,7 @@ def test_graph_replays_match_eager_launches():
         assert st["iterations"] == st_ref["iterations"]
         assert rel(f.cpu().numpy(), ref) < 1e-13
     for prec in ("mixed",):
-        sm = hdp().Solver(w, tol=1e-11, precision=prec)
+        sm = hdp().Solver(w, tol=1e-11, precision=prec, graphs=True)
         sme = hdp().Solver(w, tol=1e-11, precision=prec, graphs=False)
         a, _ = sm.solve(kind, vals)
         b, _ = sme.solve(kind, vals)
@@ -251,3 +270,26 @@ def test_graph_replays_match_eager_launches():
         sme.close()
     sg.close()
     se.close()
+
+
+def test_far_field_matches_oracle(oracles):
+    """E_far over the boundary of the dielectric block (Sec. 3.3.1, e^{-iwt} form)."""
+    from oracle import farfield as ff
+    name = "scatterer_6x6_p6"
+    disc, l, E = oracles[name]
+    w = CASES[name]
+    inside = (np.asarray(w["eps_r"]) != 1.0)
+    angles = np.linspace(0, 2 * np.pi, 37)
+    s = hdp().Solver(w, tol=1e-12, max_iter=400, max_rhs=2)
+    kind, vals = hdp().rhs_values(w)
+    vals2 = np.array([vals[0], vals[0] + 1.3])
+    field, far, st = s.solve(kind, vals2, far_angles=angles, far_inside=inside)
+    far = far.cpu().numpy()
+    for r, a in enumerate(vals2):
+        w1 = dict(w, rhs=dict(kind=kind, angles=[a]))
+        d1 = pb.Discretisation(w1)
+        E1 = dpe.ElementwiseDP(d1, l)
+        phis = E1.solve(tol=1e-12, max_iter=400)
+        ref = ff.far_field(d1.mesh, d1.degrees, phis, d1.k, inside, angles)
+        assert rel(far[r], ref) < 1e-9
+    s.close()

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 
 @pytest.mark.parametrize("make,l,nlam,nK", [(W.plane_wave_4x4, 1, 168, 25),
                                              (W.point_source_32x32, 2, 27776, 3201),
-                                             (W.square_scatterer_64x64, 3, 72576, 20865)])
+                                             (W.square_scatterer_64x64, 6, 48384, 45825)])
 def test_inspect_sizes(make, l, nlam, nK):
     st = hdp.inspect(make())
     assert (st["l"], st["n_lambda"], st["n_coarse"]) == (l, nlam, nK)
