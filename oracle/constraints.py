@@ -55,6 +55,15 @@ def side_vertices(n, side):
     return [a + n * b for (a, b) in pairs], pairs
 
 
+def edge_l(l, na, nb):
+    """Number of primal rows minus one on an edge between elements with na and nb
+    modes per direction: min(l, p_a, p_b).  A primal row above the smaller degree
+    would only involve the other side's mode and zero a kept unknown; it stays
+    dual instead (Sec. 2.3.2 reading: with l at or above every degree every
+    shared mode is primal and the method is the nullspace method)."""
+    return min(l, na - 1, nb - 1)
+
+
 class Constraints:
     """Global C (rows per edge, k ascending), data d, primal flags and edge list.
 
@@ -63,7 +72,8 @@ class Constraints:
     visiting (finer or same-level) element f toward its neighbour c as
     (L_c^f)^T C_j^c phi_c - C_i^f phi_f = 0 (eq. final_constraint), with both
     sides zero-padded to L = max(p_c, p_f) (eq. fine_constraints); a Dirichlet
-    side gives C_i phi = d_i.  Rows k <= l are primal (C_p), the rest dual (C_d).
+    side gives C_i phi = d_i.  Rows k <= min(l, p_c, p_f) are primal (C_p), the rest
+    dual (C_d).
     Rows that only zero coarse modes already zeroed by a sibling fine edge are
     dropped (Sec. 2.2.4, degree-reduction redundancy).
     """
@@ -147,7 +157,7 @@ class Constraints:
                     cols += list(self.off[c] + nzc) + list(self.off[e] + nzf)
                     vals += list(Rc[k, nzc]) + list(-Tf[k, nzf])
                     self.d.append(0.0)
-                    self.primal.append(k <= l)
+                    self.primal.append(k <= edge_l(l, ne, nc))
                     self.kind.append("edge")
                     self.row_edge.append(eid)
                     self.row_k.append(k)
@@ -195,7 +205,11 @@ def algorithm1(mesh, degrees, l, bc):
         n = int(degrees[e]) + 1
         for side in (1, 2, 3, 4):
             bnd = mesh.boundary_side(e, side)
-            first = side_modes(n, side)[: max(0, l - 1)]
+            nbrs = [] if bnd else mesh.neighbours(e, side)
+            le = l
+            if len(nbrs) == 1:
+                le = edge_l(l, n, int(degrees[nbrs[0][0]]) + 1)
+            first = side_modes(n, side)[: max(0, le - 1)]
             coarse_nbr = False
             if bnd:
                 if bc.get(bnd) == "dirichlet":
@@ -214,7 +228,7 @@ def algorithm1(mesh, degrees, l, bc):
                         if status[e][m] != 0:
                             status[e][m] = 2
                     nc = int(degrees[c]) + 1
-                    for m in side_modes(nc, sc)[: max(0, l - 1)]:
+                    for m in side_modes(nc, sc)[: max(0, le - 1)]:
                         status[c][m] = 0
                     visited_edge.add((c, sc))
                 elif len(nbrs) == 1 and mesh.leaves[nbrs[0][0]][0] < lev_e:
@@ -253,6 +267,20 @@ def algorithm1(mesh, degrees, l, bc):
     return status
 
 
+def pinv(M):
+    """Moore-Penrose pseudo-inverse by the SVD with the numerical-rank cutoff
+    max(rows, cols) * eps * sigma_max: constraint matrices with redundant rows
+    have exact zero singular values that rounding lifts to about 1e-15, and a
+    looser cutoff would invert them."""
+    M = np.asarray(M)
+    if M.size == 0:
+        return np.zeros(M.shape[::-1], M.dtype)
+    U, S, Vh = np.linalg.svd(M, full_matrices=False)
+    tol = max(M.shape) * np.finfo(float).eps * (S[0] if len(S) else 0.0)
+    r = int((S > tol).sum())
+    return (Vh[:r].conj().T / S[:r]) @ U[:, :r].conj().T
+
+
 def literal_Z(mesh, degrees, status, Cp):
     """Z = (I - C_p^+ C_p) B_z I(:, J), Sec. 2.3.2, with J ordered type 1 then
     type 2 (Z = [Z_1 Z_2]).  Dense; for small meshes.  Returns Z, the global
@@ -264,7 +292,7 @@ def literal_Z(mesh, degrees, status, Cp):
     J2 = [int(off[e]) + m for e in range(mesh.E) for m in np.nonzero(status[e] == 2)[0]]
     Cpd = Cp.toarray()
     if Cpd.shape[0]:
-        Pn = np.eye(ndof) - np.linalg.pinv(Cpd) @ Cpd
+        Pn = np.eye(ndof) - pinv(Cpd) @ Cpd
     else:
         Pn = np.eye(ndof)
     Z = Pn @ Bz[:, J1 + J2]

@@ -20,7 +20,7 @@ def conforming_solution(disc):
     con = cs.Constraints(disc.mesh, disc.degrees, 10 ** 6, disc.bc, disc.dirichlet_fun())
     C = con.C.toarray()
     if C.shape[0]:
-        phi_d = np.linalg.pinv(C) @ con.d
+        phi_d = cs.pinv(C) @ con.d
         Y = sla.null_space(C)
     else:
         phi_d = np.zeros(A.shape[0], complex)

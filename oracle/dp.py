@@ -42,7 +42,7 @@ class LiteralDP:
         n1 = len(J1)
         self.n1 = n1
         Cpd = Cp.toarray()
-        phi_z = np.linalg.pinv(Cpd) @ dp if Cpd.shape[0] else np.zeros(A.shape[0])
+        phi_z = cs.pinv(Cpd) @ dp if Cpd.shape[0] else np.zeros(A.shape[0])
         self.phi_z = phi_z
         Cdd = Cd.toarray()
         self.Cp, self.Cd = Cpd, Cdd

@@ -175,6 +175,29 @@ def test_nonconforming_dp_equals_direct_and_is_continuous(pvals):
                 _check_trace_match(mesh, disc.degrees, phis, e, side, f, sf)
 
 
+@pytest.mark.parametrize("pvals,l,seed", [((2, 5), 3, 1), ((3, 7), 5, 2)])
+def test_coarse_order_above_some_degrees(pvals, l, seed):
+    """l above the degree of some elements (hanging and conforming edges with
+    unequal degrees): primal rows stop at min(l, p_a, p_b), the reduced matrix
+    stays non-singular and the field is still the conforming Galerkin solution."""
+    w = _refined_small(pvals, seed=seed)
+    disc = pb.Discretisation(w)
+    assert min(disc.degrees) < l < max(disc.degrees)
+    D = dp.LiteralDP(disc, l)
+    assert np.abs(D.Cp @ D.Z).max() < 1e-12
+    assert np.linalg.matrix_rank(D.Z) == D.Z.shape[1]
+    assert np.linalg.cond(D.Ah) < 1e12
+    phis = D.solve(tol=1e-13, max_iter=500)
+    ref = direct.conforming_solution(disc)
+    assert max(np.abs(a - b).max() for a, b in zip(phis, ref)) < 1e-9
+    # l at the largest degree: every shared mode is primal, only rows above the
+    # smaller degree of an edge stay dual; Z still lies in null(C_p)
+    D2 = dp.LiteralDP(disc, int(max(disc.degrees)))
+    assert np.abs(D2.Cp @ D2.Z).max() < 1e-12
+    phis2 = D2.recover(D2.direct_interface())
+    assert max(np.abs(a - b).max() for a, b in zip(phis2, ref)) < 1e-9
+
+
 def _eval_at(mesh, deg, phis, e, x, y):
     n = int(deg[e]) + 1
     (ox, oy), (hx, hy) = mesh.origin(e), mesh.size(e)
