@@ -200,6 +200,18 @@ def algorithm1(mesh, degrees, l, bc):
                 cp = mesh.corner_points(e)
                 for pr in pairs:
                     dirichlet_points.add(cp[pr])
+    # vertex copies on a side that faces a coarser neighbour are discarded
+    # whichever side of the element is visited first, so that the one kept copy
+    # of every vertex is never such a copy
+    on_coarse_edge = set()
+    for e in range(mesh.E):
+        n = int(degrees[e]) + 1
+        for side in (1, 2, 3, 4):
+            if mesh.boundary_side(e, side):
+                continue
+            nbrs = mesh.neighbours(e, side)
+            if len(nbrs) == 1 and mesh.leaves[nbrs[0][0]][0] < mesh.leaves[e][0]:
+                on_coarse_edge.update((e, m) for m in side_vertices(n, side)[0])
     order = mesh.visit_order()
     for e in order:
         n = int(degrees[e]) + 1
@@ -250,7 +262,8 @@ def algorithm1(mesh, degrees, l, bc):
             cp = mesh.corner_points(e)
             for m, pr in zip(vids, pairs):
                 pt = cp[pr]
-                if coarse_nbr or pt in dirichlet_points or mesh.is_hanging_point(pt):
+                if coarse_nbr or pt in dirichlet_points or mesh.is_hanging_point(pt) \
+                        or (e, m) in on_coarse_edge:
                     status[e][m] = 0
                 elif pt not in kept_point and status[e][m] != 0:
                     status[e][m] = 2

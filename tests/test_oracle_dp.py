@@ -198,6 +198,34 @@ def test_coarse_order_above_some_degrees(pvals, l, seed):
     assert max(np.abs(a - b).max() for a, b in zip(phis2, ref)) < 1e-9
 
 
+def test_vertex_kept_once_where_fine_elements_meet_a_coarse_corner():
+    """A 4x4 mesh refined twice around its centre: level-2 elements whose bottom
+    sides face a level-0 element also share a same-level side that ends at that
+    element's corner.  Every non-hanging vertex keeps exactly one copy
+    (Algorithm 1), Z spans null(C_p) and the field is the conforming solution."""
+    lv = W.refine_where(W.morton_leaves(4, 4), 0, 1, 0, 1, 4, 4,
+                        lambda x, y: (x - 0.5) ** 2 + (y - 0.5) ** 2 < 0.05, 2)
+    deg = np.random.default_rng(2).integers(2, 6, len(lv))
+    w = dict(domain=(0.0, 1.0, 0.0, 1.0), base=(4, 4), leaves=lv, degree=deg, k=6.0,
+             bc="impedance", rhs=dict(kind="plane_wave_total", angles=[0.4]))
+    disc = pb.Discretisation(w)
+    mesh = disc.mesh
+    st = cs.algorithm1(mesh, disc.degrees, 3, disc.bc)
+    kept = {}
+    for e in range(mesh.E):
+        n = int(disc.degrees[e]) + 1
+        for (a, b), pt in mesh.corner_points(e).items():
+            if st[e][a + n * b] == 2:
+                kept[pt] = kept.get(pt, 0) + 1
+    points = {pt for e in range(mesh.E) for pt in mesh.corner_points(e).values()}
+    regular = {pt for pt in points if not mesh.is_hanging_point(pt)}
+    assert set(kept) == regular and set(kept.values()) == {1}
+    D = dp.LiteralDP(disc, 3)
+    ref = direct.conforming_solution(disc)
+    phis = D.recover(D.direct_interface())
+    assert max(np.abs(a - b).max() for a, b in zip(phis, ref)) < 1e-9
+
+
 def _eval_at(mesh, deg, phis, e, x, y):
     n = int(deg[e]) + 1
     (ox, oy), (hx, hy) = mesh.origin(e), mesh.size(e)
