@@ -59,7 +59,8 @@ std::vector<double2> pack_c(const std::vector<cd>& v) {
 const char* const KF_NAMES[KF_COUNT] = {"slot_apply_F", "slot_apply_P", "coarse_assemble", "coarse_gemv",
                                         "slot_coarse", "row_gather", "gmres_dots", "gmres_update",
                                         "gmres_norm_scale", "fdm_local_solve", "element_coarse_fix",
-                                        "gll_sample", "precision_cast", "gmres_givens", "far_field"};
+                                        "gll_sample", "precision_cast", "gmres_givens", "far_field",
+                                        "hanging_blocks"};
 
 static hipEvent_t prof_event(Handle& h) {
   if (!h.prof.pool.empty()) {
@@ -118,10 +119,30 @@ void build_device(Handle& h) {
   d.slot_row = upload(h, h.slot_row);
   d.slot_coef = upload(h, h.slot_coef);
   d.slot_mode = upload(h, h.slot_mode);
-  d.cm_dof = upload(h, h.cm_dof);
+  d.t_ptr = upload(h, h.t_ptr);
+  d.t_dof = upload(h, h.t_dof);
+  d.t_coef = upload(h, h.t_coef);
   d.cdof_ptr = upload(h, h.cdof_ptr);
   d.cdof_list = upload(h, h.cdof_list);
+  d.cdof_coef = upload(h, h.cdof_coef);
   d.cm_mode = upload(h, h.cm_mode);
+  d.c2_ptr = upload(h, h.c2_ptr);
+  d.c2_dof = upload(h, h.c2_dof);
+  d.c2_coef = upload(h, h.c2_coef);
+  d.c2t_ptr = upload(h, h.c2t_ptr);
+  d.c2t_row = upload(h, h.c2t_row);
+  d.c2t_coef = upload(h, h.c2t_coef);
+  if (h.nh > 0) {
+    std::vector<int> blk(h.nh);
+    for (size_t b = 0; b + 1 < h.hb_off.size(); ++b)
+      for (int i = h.hb_off[b]; i < h.hb_off[b + 1]; ++i) blk[i] = int(b);
+    d.hb_off = upload(h, h.hb_off);
+    d.hb_rows = upload(h, h.hb_rows);
+    d.hb_blk = upload(h, blk);
+    d.hb_moff = upload(h, h.hb_moff);
+    d.hb_xinv = upload(h, h.hb_xinv);
+    d.hb_y2 = upload(h, h.hb_y2);
+  }
   std::vector<int64_t> slot_pos(h.nslots), cm_pos(h.ncm);
   for (int e = 0; e < E; ++e) {
     for (int s = h.slot_off[e]; s < h.slot_off[e + 1]; ++s) slot_pos[s] = h.dof_off[e] + h.slot_mode[s];
@@ -211,10 +232,13 @@ void build_device(Handle& h) {
   std::vector<std::pair<int64_t, cd>> coo;
   for (int e = 0; e < E; ++e) {
     const ElemClass& C = h.classes[h.cls[e]];
+    const int co = h.cm_off[e];
     for (int b = 0; b < C.nr; ++b)
       for (int a = 0; a < C.nr; ++a) {
-        int64_t i = h.cm_dof[h.cm_off[e] + a], j = h.cm_dof[h.cm_off[e] + b];
-        coo.push_back({i + int64_t(h.nK) * j, C.Kc(a, b)});
+        cd kab = C.Kc(a, b);
+        for (int t = h.t_ptr[co + a]; t < h.t_ptr[co + a + 1]; ++t)
+          for (int u = h.t_ptr[co + b]; u < h.t_ptr[co + b + 1]; ++u)
+            coo.push_back({h.t_dof[t] + int64_t(h.nK) * h.t_dof[u], h.t_coef[t] * kab * h.t_coef[u]});
       }
   }
   std::sort(coo.begin(), coo.end(), [](auto& x, auto& y) { return x.first < y.first; });
@@ -300,6 +324,11 @@ void build_device(Handle& h) {
   d.status_host = static_cast<int*>(ph);
   d.nrm = dalloc<double>(h, Rp);
   d.ycoef = dalloc<double2>(h, (size_t(h.max_iter) + 1) * Rp);
+  if (h.nh > 0) d.hb_tmp = dalloc<double2>(h, size_t(h.nh) * Rp);
+  if (h.nonconforming) {
+    d.fv = dalloc<double2>(h, nl * Rp);
+    d.pv = dalloc<double2>(h, nl * Rp);
+  }
   HIPCHECK(hipStreamSynchronize(h.stream));
 }
 
@@ -341,8 +370,9 @@ static void apply_F_slots(Handle& h, const double2* v, int R, int prec) {
   }
   {
     Timed t(h, KF_ASSEMBLE, ncm * cw + nK * c, 0);
-    if (prec == HDP_FP64) launch_assemble<double2>(h, d.cmA, nullptr, d.gK, R, s);
-    else launch_assemble<float2>(h, d.cmA_f, nullptr, d.gK, R, s);
+    // g = Phi^T y_1 + C_2^T v
+    if (prec == HDP_FP64) launch_assemble<double2>(h, d.cmA, nullptr, v, 1.0, d.gK, R, s);
+    else launch_assemble<float2>(h, d.cmA_f, nullptr, v, 1.0, d.gK, R, s);
   }
   {
     Timed t(h, KF_COARSE, nK * nK * 16.0 + 2 * nK * c, 8.0 * nK * nK * R);
@@ -361,13 +391,22 @@ void apply_F(Handle& h, const double2* v, double2* u, int R, int prec) {
   const double cw = prec == HDP_FP64 ? 16.0 * R : 8.0 * R;
   apply_F_slots(h, v, R, prec);
   Timed t(h, KF_ROWGATHER, nsl * cw + nl * c, 0);
-  if (prec == HDP_FP64) launch_rowgather<double2>(h, d.slotB, false, false, u, R, h.stream);
-  else launch_rowgather<float2>(h, d.slotB_f, false, false, u, R, h.stream);
+  // u = C_1 z + C_2 w
+  if (prec == HDP_FP64) launch_rowgather<double2>(h, d.slotB, false, false, d.wK, u, R, h.stream);
+  else launch_rowgather<float2>(h, d.slotB_f, false, false, d.wK, u, R, h.stream);
 }
+
+void apply_P(Handle& h, const double2* v, double2* u, int R, int prec);
 
 // w = P^-1 F v with the preconditioner's gather reading F's slot values directly.
 void apply_PF(Handle& h, const double2* v, double2* w, int R, int prec) {
   auto& d = h.d;
+  if (h.nonconforming) {
+    // C_2 terms enter both operators: apply them one after the other
+    apply_F(h, v, d.fv, R, prec);
+    apply_P(h, d.fv, w, R, prec);
+    return;
+  }
   hipStream_t s = h.stream;
   const double c = 16.0 * R, nsl = h.nslots, nl = h.nlam;
   const double cw = prec == HDP_FP64 ? 16.0 * R : 8.0 * R;
@@ -380,17 +419,26 @@ void apply_PF(Handle& h, const double2* v, double2* w, int R, int prec) {
   }
   {
     Timed t(h, KF_ROWGATHER, nsl * cw + nl * c, 0);
-    if (prec == HDP_FP64) launch_rowgather<double2>(h, d.slotA, false, true, w, R, s);
-    else launch_rowgather<float2>(h, d.slotA_f, false, true, w, R, s);
+    if (prec == HDP_FP64) launch_rowgather<double2>(h, d.slotA, false, true, nullptr, w, R, s);
+    else launch_rowgather<float2>(h, d.slotA_f, false, true, nullptr, w, R, s);
   }
 }
 
 void apply_P(Handle& h, const double2* v, double2* u, int R, int prec) {
   auto& d = h.d;
   hipStream_t s = h.stream;
-  const double c = 16.0 * R, nsl = h.nslots, nl = h.nlam;
+  const double c = 16.0 * R, nsl = h.nslots, nl = h.nlam, nh = h.nh;
   const double cw = prec == HDP_FP64 ? 16.0 * R : 8.0 * R;
   const double ob = prec == HDP_FP64 ? 1.0 : 0.5;
+  const double hb_bytes = 8.0 * h.hb_xinv.size();
+  if (h.nh > 0) {
+    // P^-1 = X^-1 Y X^-1: X is diagonal except for dense blocks on the hanging
+    // rows, whose scale factor is 1 in row_xinv; first s = X^-1 v there
+    Timed t(h, KF_HBLOCK, hb_bytes + 2 * nh * c + nl * 2 * c, 2.0 * h.hb_xinv.size() * 2 * R);
+    HIPCHECK(hipMemcpyAsync(d.pv, v, size_t(h.nlam) * R * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    launch_hblock(h, false, v, true, nullptr, d.pv, true, R, s);
+    v = d.pv;
+  }
   if (prec != HDP_FP64) {
     Timed t(h, KF_CAST, nl * (c + cw), 0);
     launch_cast_f(v, d.vf, int64_t(h.nlam) * R, s);
@@ -402,15 +450,22 @@ void apply_P(Handle& h, const double2* v, double2* u, int R, int prec) {
   }
   {
     Timed t(h, KF_ROWGATHER, nsl * cw + nl * c, 0);
-    if (prec == HDP_FP64) launch_rowgather<double2>(h, d.slotA, false, true, u, R, s);
-    else launch_rowgather<float2>(h, d.slotA_f, false, true, u, R, s);
+    if (prec == HDP_FP64) launch_rowgather<double2>(h, d.slotA, false, true, nullptr, u, R, s);
+    else launch_rowgather<float2>(h, d.slotA_f, false, true, nullptr, u, R, s);
+  }
+  if (h.nh > 0) {
+    // hanging rows: u = X^-1 (C_1 S C_1^T s + Y_2 s)
+    Timed t(h, KF_HBLOCK, 2 * hb_bytes + 6 * nh * c, 2.0 * 2 * h.hb_xinv.size() * 2 * R);
+    launch_hblock(h, true, d.pv, true, u, d.hb_tmp, false, R, s);
+    launch_hblock(h, false, d.hb_tmp, false, nullptr, u, true, R, s);
   }
 }
 
 // Solve A^ [x_I; x_R] = [y_I; y_R] element-wise (eq. block_matrix_inversion):
 // X holds y_I on entry (coarse modes ignored) and the element solution on exit;
-// y_R is assembled from Bfull's coarse modes (or zero when Bfull is null).
-void element_solve(Handle& h, double2* X, const double2* Bfull, int R) {
+// y_R is assembled from Bfull's coarse modes (or zero when Bfull is null),
+// minus C_2^T nu when nu is given.
+void element_solve(Handle& h, double2* X, const double2* Bfull, const double2* nu, int R) {
   auto& d = h.d;
   hipStream_t s = h.stream;
   const double c = 16.0 * R, dof = double(h.dof), ncm = h.ncm, nK = h.nK;
@@ -428,7 +483,7 @@ void element_solve(Handle& h, double2* X, const double2* Bfull, int R) {
   }
   {
     Timed t(h, KF_ASSEMBLE, 2 * ncm * c + nK * c, 0);
-    launch_assemble<double2>(h, d.cmA, Bfull, d.gK, R, s);
+    launch_assemble<double2>(h, d.cmA, Bfull, nu, -1.0, d.gK, R, s);
   }
   {
     Timed t(h, KF_COARSE, nK * nK * 16.0 + 2 * nK * c, 8.0 * nK * nK * R);
@@ -445,9 +500,9 @@ void interface_rhs(Handle& h, double2* g, int R) {
   auto& d = h.d;
   HIPCHECK(hipMemcpyAsync(d.full1, d.full0, size_t(h.dof) * R * sizeof(double2), hipMemcpyDeviceToDevice,
                           h.stream));
-  element_solve(h, d.full1, d.full0, R);
+  element_solve(h, d.full1, d.full0, nullptr, R);
   Timed t(h, KF_ROWGATHER, h.nslots * 16.0 * R + h.nlam * 16.0 * R, 0);
-  launch_rowgather<double2>(h, d.full1, true, false, g, R, h.stream);
+  launch_rowgather<double2>(h, d.full1, true, false, d.wK, g, R, h.stream);   // C_1 x_1 + C_2 x_2
 }
 
 struct GmresResult {
@@ -605,8 +660,18 @@ void far_prepare(Handle& h, int n_far, const double* angles, const uint8_t* insi
   for (int e = 0; e < h.E; ++e) {
     if (in[e]) continue;
     for (int s = 1; s <= 4; ++s) {
-      int nb = h.nb_e[4 * e + s - 1];
-      if (nb < 0 || !in[nb]) continue;
+      const int si = 4 * e + s - 1;
+      bool facing_inside = false;
+      if (h.side_type[si] == 1 || h.side_type[si] == 2) {
+        facing_inside = in[h.nb_e[si]] != 0;
+      } else if (h.side_type[si] == 3) {
+        int n_in = 0;
+        for (int f : h.side_nbrs[si]) n_in += in[f] != 0;
+        if (n_in != 0 && n_in != int(h.side_nbrs[si].size()))
+          fail(HDP_E_ARG, "far-field boundary must follow whole element sides of the outside elements");
+        facing_inside = n_in != 0;
+      }
+      if (!facing_inside) continue;
       int n = h.deg[e] + 1, q = n + 12;
       std::vector<double> xq, wq;
       gauss_legendre(q, xq, wq);
@@ -945,7 +1010,7 @@ hdp_status hdp_solve(hdp_handle* H, const hdp_rhs* rhs, hdp_c64* field, int32_t 
   // recovery phi = A^-1 (b^ - C^T nu) (Sec. 2.3.1) and the field at GLL nodes
   HIPCHECK(hipMemcpyAsync(d.full1, d.full0, size_t(h.dof) * Rp * sizeof(double2), hipMemcpyDeviceToDevice, s));
   launch_sub_dual(h, d.full1, d.t2, Rp, s);
-  element_solve(h, d.full1, d.full0, Rp);
+  element_solve(h, d.full1, d.full0, d.t2, Rp);
   if (field) {
     Timed t(h, KF_GLL, 2.0 * h.dof * 16.0 * R, h.flops_gll * R);
     launch_gll(h, d.full1, reinterpret_cast<double2*>(field), Rp, h.dof, R, s);

@@ -28,7 +28,8 @@ struct ElemClass {
   int p = 0, n = 0;
   double hx = 0, hy = 0, eps = 1;
   int bmask = 0;               // bit (s-1): side s on the outer impedance boundary
-  int m = 0, nr = 0;           // dual slots, coarse modes (4l)
+  int top[4] = {1, 1, 1, 1};   // per side: bubbles 2..top are coarse modes
+  int m = 0, nr = 0;           // dual slots, coarse modes
   std::vector<int> R;          // coarse (removed, type-2) modes, canonical order
   std::vector<int> Gam;        // dual-touched type-1 edge modes, slot order
   MatC Ex, Ey;                 // generalised eigenvectors, E^T M~ E = I
@@ -36,8 +37,9 @@ struct ElemClass {
   MatC G;                      // A~^-1 E_R           (n^2 x nr)
   MatC Kc;                     // (E_R^T A~^-1 E_R)^-1 (nr x nr)
   MatC Op1;                    // [D_c ; Phi_c^T]      ((m+nr) x m)
-  MatC Phi;                    // Phi_c = -G_Gam Kc    (m x nr)
+  MatC Phi;                    // Phi_c = -A_11^-1 A_1R = G_Gam Kc on the slots (m x nr)
   MatD Se;                     // Laplace-only Schur complement on Gam (m x m)
+  MatD KL;                     // Laplace-only element coarse matrix on R (nr x nr)
   double margin = 0;           // min|Dg| / max|Dg|
   std::vector<int> elems;      // members, leaf indices
 };
@@ -52,7 +54,7 @@ struct DevOps {
 
 enum KernelFamily {
   KF_SLOT_F = 0, KF_SLOT_P, KF_ASSEMBLE, KF_COARSE, KF_SLOT_COARSE, KF_ROWGATHER, KF_DOTS, KF_UPDATE,
-  KF_NORM_SCALE, KF_FDM, KF_ELEMENT_MISC, KF_GLL, KF_CAST, KF_GIVENS, KF_FAR, KF_COUNT
+  KF_NORM_SCALE, KF_FDM, KF_ELEMENT_MISC, KF_GLL, KF_CAST, KF_GIVENS, KF_FAR, KF_HBLOCK, KF_COUNT
 };
 extern const char* const KF_NAMES[KF_COUNT];
 
@@ -81,7 +83,14 @@ struct Handle {
   std::vector<int> cls;                 // class of each element
   std::vector<ElemClass> classes;
   std::vector<int> bmask;
-  std::vector<int> nb_e;                // neighbour across each side (4 per element), -1 on the boundary
+  // per side (4 per element, index 4e + s - 1): 0 outer boundary, 1 conforming,
+  // 2 fine side of a hanging edge (one coarser neighbour), 3 coarse side of a
+  // hanging edge (several finer neighbours)
+  std::vector<int> side_type, side_le;   // side_le: primal rows 0..le on the edge
+  std::vector<int> nb_e, nb_s;           // the neighbour (types 1 and 2), -1 otherwise
+  std::vector<double> side_a, side_b;    // type 2: s -> t = a s + b into the neighbour's side
+  std::vector<std::vector<int>> side_nbrs;   // type 3: the finer neighbours (element indices)
+  bool nonconforming = false;
   // offsets
   std::vector<int64_t> dof_off;   // per element, n_e^2 blocks
   std::vector<int> slot_off;      // per element, dual slots
@@ -94,10 +103,23 @@ struct Handle {
   std::vector<int> slot_row;      // per slot
   std::vector<double> slot_coef;
   std::vector<int> slot_mode;     // per slot, local mode index (for full arrays)
-  // coarse map
-  std::vector<int> cm_dof;        // per coarse mode, global coarse unknown
-  std::vector<int> cdof_ptr, cdof_list;  // CSR: coarse unknown -> coarse modes
+  // coarse map: each coarse mode i (element-local removed mode) is a linear
+  // combination T of global coarse unknowns (a single unit entry except on
+  // the fine side of a hanging edge and at hanging points)
+  std::vector<int> t_ptr, t_dof;         // CSR over coarse modes
+  std::vector<double> t_coef;
+  std::vector<int> cdof_ptr, cdof_list;  // transpose: coarse unknown -> coarse modes
+  std::vector<double> cdof_coef;
   std::vector<int> cm_mode;       // per coarse mode, local mode index
+  // C_2 (dual rows x coarse unknowns), non-zero only on hanging edges
+  std::vector<int> c2_ptr, c2_dof, c2t_ptr, c2t_row;
+  std::vector<double> c2_coef, c2t_coef;
+  // preconditioner blocks on the dual rows that C_2 couples (hanging edges):
+  // per block the rows, X^-1 and Y_2, dense column-major
+  std::vector<int> hb_off, hb_rows;
+  std::vector<int64_t> hb_moff;
+  std::vector<double> hb_xinv, hb_y2;
+  int nh = 0;
   // class-sorted element order and launch tables
   std::vector<int> order;         // elements grouped by class
   // per degree n: Gauss-Legendre rule with n+40 nodes and the vertex basis there
@@ -117,7 +139,14 @@ struct Handle {
     int *row_slot = nullptr, *slot_row = nullptr, *slot_mode = nullptr;
     int64_t *slot_pos = nullptr, *cm_pos = nullptr;   // positions in full-element arrays
     double *row_coef = nullptr, *row_xinv = nullptr, *slot_coef = nullptr;
-    int *cm_dof = nullptr, *cdof_ptr = nullptr, *cdof_list = nullptr, *cm_mode = nullptr;
+    int *t_ptr = nullptr, *t_dof = nullptr, *cdof_ptr = nullptr, *cdof_list = nullptr, *cm_mode = nullptr;
+    double *t_coef = nullptr, *cdof_coef = nullptr;
+    int *c2_ptr = nullptr, *c2_dof = nullptr, *c2t_ptr = nullptr, *c2t_row = nullptr;
+    double *c2_coef = nullptr, *c2t_coef = nullptr;
+    int *hb_off = nullptr, *hb_rows = nullptr, *hb_blk = nullptr;
+    int64_t* hb_moff = nullptr;
+    double *hb_xinv = nullptr, *hb_y2 = nullptr;
+    double2 *hb_tmp = nullptr, *fv = nullptr, *pv = nullptr;
     // per-class tables
     int *cls_n = nullptr, *cls_m = nullptr, *cls_nr = nullptr;
     int64_t *cls_op1 = nullptr, *cls_phi = nullptr, *cls_se = nullptr;   // offsets

@@ -134,8 +134,9 @@ template <class T2>
 __global__ void __launch_bounds__(NT) k_slot_coarse(
     const int* __restrict__ order, const int* __restrict__ elem_cls, const int* __restrict__ slot_off,
     const int* __restrict__ cm_off, const int* __restrict__ cls_m, const int* __restrict__ cls_nr,
-    const int64_t* __restrict__ cls_phi, const T2* __restrict__ phi, const int* __restrict__ cm_dof,
-    const T2* __restrict__ X, const double2* __restrict__ w, T2* __restrict__ Z, int R) {
+    const int64_t* __restrict__ cls_phi, const T2* __restrict__ phi, const int* __restrict__ t_ptr,
+    const int* __restrict__ t_dof, const double* __restrict__ t_coef, const T2* __restrict__ X,
+    const double2* __restrict__ w, T2* __restrict__ Z, int R) {
   __shared__ T2 we[NRMAX * RC];
   const int e = order[blockIdx.x];
   const int c = elem_cls[e];
@@ -145,8 +146,13 @@ __global__ void __launch_bounds__(NT) k_slot_coarse(
   const int co = cm_off[e], so = slot_off[e];
   for (int idx = threadIdx.x; idx < nr * rc; idx += NT) {
     int j = idx / rc, r = idx - j * rc;
-    double2 a = w[(int64_t)cm_dof[co + j] * R + r0 + r];
-    we[j * RC + r] = mk<T2>(a.x, a.y);
+    double ax = 0, ay = 0;
+    for (int t = t_ptr[co + j]; t < t_ptr[co + j + 1]; ++t) {
+      double2 a = w[(int64_t)t_dof[t] * R + r0 + r];
+      ax += t_coef[t] * a.x;
+      ay += t_coef[t] * a.y;
+    }
+    we[j * RC + r] = mk<T2>(ax, ay);
   }
   __syncthreads();
   const T2* P = phi + cls_phi[c];
@@ -158,10 +164,13 @@ __global__ void __launch_bounds__(NT) k_slot_coarse(
   }
 }
 
+// u[row] = scale_row * (sum coef * src[pos(slot)] + sum_{C_2} coef * w[dof])
 template <class T2>
 __global__ void k_rowgather(int nlam, const int* __restrict__ row_slot, const double* __restrict__ row_coef,
                             const double* __restrict__ row_xinv, const int64_t* __restrict__ slot_pos,
-                            const T2* __restrict__ src, double2* __restrict__ u, int R) {
+                            const T2* __restrict__ src, const int* __restrict__ c2_ptr,
+                            const int* __restrict__ c2_dof, const double* __restrict__ c2_coef,
+                            const double2* __restrict__ w, double2* __restrict__ u, int R) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)nlam * R) return;
   int row = int(idx / R), r = int(idx - (int64_t)row * R);
@@ -176,6 +185,12 @@ __global__ void k_rowgather(int nlam, const int* __restrict__ row_slot, const do
     ax += cf * double(a.x);
     ay += cf * double(a.y);
   }
+  if (w)
+    for (int t = c2_ptr[row]; t < c2_ptr[row + 1]; ++t) {
+      double2 a = w[(int64_t)c2_dof[t] * R + r];
+      ax += c2_coef[t] * a.x;
+      ay += c2_coef[t] * a.y;
+    }
   if (row_xinv) {
     ax *= row_xinv[row];
     ay *= row_xinv[row];
@@ -183,28 +198,85 @@ __global__ void k_rowgather(int nlam, const int* __restrict__ row_slot, const do
   u[idx] = make_double2(ax, ay);
 }
 
+// g[d] = sum_{(i, c) in T^T} c (GL[i] + Bfull[pos(i)]) + csign sum_{(row, c) in C_2^T} c v[row]
 template <class T2>
 __global__ void k_assemble(int nK, const int* __restrict__ ptr, const int* __restrict__ list,
-                           const T2* __restrict__ GL, const int64_t* __restrict__ cm_pos,
-                           const double2* __restrict__ Bfull, double2* __restrict__ g, int R) {
+                           const double* __restrict__ coef, const T2* __restrict__ GL,
+                           const int64_t* __restrict__ cm_pos, const double2* __restrict__ Bfull,
+                           const int* __restrict__ c2t_ptr, const int* __restrict__ c2t_row,
+                           const double* __restrict__ c2t_coef, const double2* __restrict__ v, double csign,
+                           double2* __restrict__ g, int R) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)nK * R) return;
   int d = int(idx / R), r = int(idx - (int64_t)d * R);
   double ax = 0, ay = 0;
   for (int t = ptr[d]; t < ptr[d + 1]; ++t) {
     int i = list[t];
+    double c = coef[t];
     if (GL) {
       T2 a = GL[(int64_t)i * R + r];
-      ax += double(a.x);
-      ay += double(a.y);
+      ax += c * double(a.x);
+      ay += c * double(a.y);
     }
     if (Bfull) {
       double2 b = Bfull[cm_pos[i] * R + r];
-      ax += b.x;
-      ay += b.y;
+      ax += c * b.x;
+      ay += c * b.y;
     }
   }
+  if (v)
+    for (int t = c2t_ptr[d]; t < c2t_ptr[d + 1]; ++t) {
+      double2 a = v[(int64_t)c2t_row[t] * R + r];
+      ax += csign * c2t_coef[t] * a.x;
+      ay += csign * c2t_coef[t] * a.y;
+    }
   g[idx] = make_double2(ax, ay);
+}
+
+// Dense blocks over the dual rows that C_2 couples (hanging edges): one
+// wavefront per block row i, RHS in chunks of 8.
+//   out_i = (add ? add[row_i] : 0) + sum_j M_b[i, j] in_j
+// in_j is x[row_j] (gather) or x[off_b + j] (compact); out_i goes to
+// y[row_i] (scatter) or y[off_b + i] (compact).
+__global__ void __launch_bounds__(NT) k_hblock(int nh, const int* __restrict__ blk, const int* __restrict__ off,
+                                               const int* __restrict__ rows, const int64_t* __restrict__ moff,
+                                               const double* __restrict__ M, const double2* __restrict__ x,
+                                               int in_gather, const double2* __restrict__ add,
+                                               double2* __restrict__ y, int out_scatter, int R) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  if (i >= nh) return;
+  const int b = blk[i], o = off[b], nb = off[b + 1] - o, il = i - o;
+  const double* Mb = M + moff[b];
+  for (int r0 = 0; r0 < R; r0 += 8) {
+    int rc = min(8, R - r0);
+    double ax[8] = {0}, ay[8] = {0};
+    for (int j = lane; j < nb; j += 64) {
+      double m = Mb[il + (int64_t)nb * j];
+      int64_t src = in_gather ? (int64_t)rows[o + j] : (int64_t)(o + j);
+      for (int r = 0; r < rc; ++r) {
+        double2 v = x[src * R + r0 + r];
+        ax[r] += m * v.x;
+        ay[r] += m * v.y;
+      }
+    }
+    for (int r = 0; r < rc; ++r) {
+      double sx = ax[r], sy = ay[r];
+      for (int sh = 32; sh > 0; sh >>= 1) {
+        sx += __shfl_down(sx, sh, 64);
+        sy += __shfl_down(sy, sh, 64);
+      }
+      if (lane == 0) {
+        if (add) {
+          double2 a = add[(int64_t)rows[i] * R + r0 + r];
+          sx += a.x;
+          sy += a.y;
+        }
+        int64_t dst = out_scatter ? (int64_t)rows[i] : (int64_t)i;
+        y[dst * R + r0 + r] = make_double2(sx, sy);
+      }
+    }
+  }
 }
 
 // w = K^-1 g: one wavefront per row of the (symmetric) inverse, RHS in chunks of 8.
@@ -324,13 +396,15 @@ __global__ void k_extract_kc(const int* __restrict__ elem_cls, const int64_t* __
   }
 }
 
-// mu = Kc (c - T_e w); X -= G mu.  Afterwards X at the coarse modes equals T_e w.
+// mu = Kc (c - T_e w); X -= G mu.  Afterwards X at the coarse modes equals T_e w
+// (T_e w: each coarse mode's expansion over the global coarse unknowns).
 __global__ void __launch_bounds__(NT) k_correct(const int* __restrict__ elem_cls, const int64_t* __restrict__ dof_off,
                                                 const int* __restrict__ cm_off, const int* __restrict__ cls_n,
                                                 const int* __restrict__ cls_nr, const int* __restrict__ cls_R,
                                                 const int* __restrict__ r_modes, const int64_t* __restrict__ cls_Kc,
                                                 const double2* __restrict__ Kc, const int64_t* __restrict__ cls_G,
-                                                const double2* __restrict__ G, const int* __restrict__ cm_dof,
+                                                const double2* __restrict__ G, const int* __restrict__ t_ptr,
+                                                const int* __restrict__ t_dof, const double* __restrict__ t_coef,
                                                 double2* __restrict__ X, const double2* __restrict__ w, int R) {
   __shared__ double2 dv[NRMAX], mu[NRMAX];
   int e = blockIdx.x, r = blockIdx.y;
@@ -340,8 +414,13 @@ __global__ void __launch_bounds__(NT) k_correct(const int* __restrict__ elem_cls
   const int64_t base = dof_off[e];
   for (int a = threadIdx.x; a < nr; a += blockDim.x) {
     double2 x = X[(base + rm[a]) * R + r];
-    double2 ww = w[(int64_t)cm_dof[cm_off[e] + a] * R + r];
-    dv[a] = make_double2(x.x - ww.x, x.y - ww.y);
+    const int i = cm_off[e] + a;
+    for (int t = t_ptr[i]; t < t_ptr[i + 1]; ++t) {
+      double2 ww = w[(int64_t)t_dof[t] * R + r];
+      x.x -= t_coef[t] * ww.x;
+      x.y -= t_coef[t] * ww.y;
+    }
+    dv[a] = x;
   }
   __syncthreads();
   const double2* K = Kc + cls_Kc[c];
@@ -995,23 +1074,38 @@ void launch_slot_coarse(const Handle& h, const T2* X, const double2* w, T2* Z, i
   const T2* phi;
   if constexpr (std::is_same<T2, double2>::value) phi = d.phi; else phi = d.phi_f;
   hipLaunchKernelGGL((k_slot_coarse<T2>), grid, dim3(NT), 0, s, d.order, d.elem_cls, d.slot_off, d.cm_off, d.cls_m,
-                     d.cls_nr, d.cls_phi, phi, d.cm_dof, X, w, Z, R);
+                     d.cls_nr, d.cls_phi, phi, d.t_ptr, d.t_dof, d.t_coef, X, w, Z, R);
   HIPCHECK(hipGetLastError());
 }
 
 template <class T2>
-void launch_rowgather(const Handle& h, const T2* src, bool full, bool precond, double2* u, int R, hipStream_t s) {
+void launch_rowgather(const Handle& h, const T2* src, bool full, bool precond, const double2* w, double2* u, int R,
+                      hipStream_t s) {
   const auto& d = h.d;
+  if (!h.nonconforming) w = nullptr;
   hipLaunchKernelGGL((k_rowgather<T2>), dim3(nblocks(int64_t(h.nlam) * R)), dim3(NT), 0, s, h.nlam, d.row_slot,
-                     d.row_coef, precond ? d.row_xinv : nullptr, full ? d.slot_pos : nullptr, src, u, R);
+                     d.row_coef, precond ? d.row_xinv : nullptr, full ? d.slot_pos : nullptr, src, d.c2_ptr,
+                     d.c2_dof, d.c2_coef, w, u, R);
   HIPCHECK(hipGetLastError());
 }
 
 template <class T2>
-void launch_assemble(const Handle& h, const T2* GL, const double2* Bfull, double2* g, int R, hipStream_t s) {
+void launch_assemble(const Handle& h, const T2* GL, const double2* Bfull, const double2* v, double vsign, double2* g,
+                     int R, hipStream_t s) {
   const auto& d = h.d;
+  if (!h.nonconforming) v = nullptr;
   hipLaunchKernelGGL((k_assemble<T2>), dim3(nblocks(int64_t(h.nK) * R)), dim3(NT), 0, s, h.nK, d.cdof_ptr,
-                     d.cdof_list, GL, d.cm_pos, Bfull, g, R);
+                     d.cdof_list, d.cdof_coef, GL, d.cm_pos, Bfull, d.c2t_ptr, d.c2t_row, d.c2t_coef, v, vsign, g,
+                     R);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_hblock(const Handle& h, bool y2, const double2* x, bool in_gather, const double2* add, double2* y,
+                   bool out_scatter, int R, hipStream_t s) {
+  const auto& d = h.d;
+  if (h.nh == 0) return;
+  hipLaunchKernelGGL(k_hblock, dim3(nblocks(h.nh, NT / 64)), dim3(NT), 0, s, h.nh, d.hb_blk, d.hb_off, d.hb_rows,
+                     d.hb_moff, y2 ? d.hb_y2 : d.hb_xinv, x, int(in_gather), add, y, int(out_scatter), R);
   HIPCHECK(hipGetLastError());
 }
 
@@ -1019,10 +1113,14 @@ template void launch_slot_apply<double2>(const Handle&, int, const double2*, dou
 template void launch_slot_apply<float2>(const Handle&, int, const float2*, float2*, float2*, int, hipStream_t);
 template void launch_slot_coarse<double2>(const Handle&, const double2*, const double2*, double2*, int, hipStream_t);
 template void launch_slot_coarse<float2>(const Handle&, const float2*, const double2*, float2*, int, hipStream_t);
-template void launch_rowgather<double2>(const Handle&, const double2*, bool, bool, double2*, int, hipStream_t);
-template void launch_rowgather<float2>(const Handle&, const float2*, bool, bool, double2*, int, hipStream_t);
-template void launch_assemble<double2>(const Handle&, const double2*, const double2*, double2*, int, hipStream_t);
-template void launch_assemble<float2>(const Handle&, const float2*, const double2*, double2*, int, hipStream_t);
+template void launch_rowgather<double2>(const Handle&, const double2*, bool, bool, const double2*, double2*, int,
+                                        hipStream_t);
+template void launch_rowgather<float2>(const Handle&, const float2*, bool, bool, const double2*, double2*, int,
+                                       hipStream_t);
+template void launch_assemble<double2>(const Handle&, const double2*, const double2*, const double2*, double,
+                                       double2*, int, hipStream_t);
+template void launch_assemble<float2>(const Handle&, const float2*, const double2*, const double2*, double, double2*,
+                                      int, hipStream_t);
 
 void launch_coarse_solve(const Handle& h, const double2* g, double2* w, int R, hipStream_t s) {
   hipLaunchKernelGGL(k_coarse_gemv, dim3(nblocks(h.nK, NT / 64)), dim3(NT), 0, s, h.nK, h.d.Kinv, g, w, R);
@@ -1056,7 +1154,7 @@ void launch_extract_kc(const Handle& h, const double2* X, double2* GL, int R, hi
 void launch_correct(const Handle& h, double2* X, const double2* w, int R, hipStream_t s) {
   const auto& d = h.d;
   hipLaunchKernelGGL(k_correct, dim3(h.E, R), dim3(NT), 0, s, d.elem_cls, d.dof_off, d.cm_off, d.cls_n, d.cls_nr,
-                     d.cls_R, d.r_modes, d.cls_Kc, d.Kc, d.cls_G, d.G, d.cm_dof, X, w, R);
+                     d.cls_R, d.r_modes, d.cls_Kc, d.Kc, d.cls_G, d.G, d.t_ptr, d.t_dof, d.t_coef, X, w, R);
   HIPCHECK(hipGetLastError());
 }
 

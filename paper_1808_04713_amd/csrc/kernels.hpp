@@ -18,14 +18,19 @@ void launch_slot_apply(const Handle& h, int mode, const T2* v, T2* X, T2* GL, in
 // Z = X + Phi_c (T_e w)
 template <class T2>
 void launch_slot_coarse(const Handle& h, const T2* X, const double2* w, T2* Z, int R, hipStream_t s);
-// u[row] = scale_row * sum coef * src[pos(slot)]  (pos = slot if full == false)
+// u[row] = scale_row * (sum coef * src[pos(slot)] + (C_2 w)[row])  (pos = slot if full == false;
+// the C_2 term only on meshes with hanging edges and w != nullptr)
 template <class T2>
-void launch_rowgather(const Handle& h, const T2* src, bool full, bool precond, double2* u, int R,
+void launch_rowgather(const Handle& h, const T2* src, bool full, bool precond, const double2* w, double2* u, int R,
                       hipStream_t s);
-// g[d] = sum_{coarse modes of d} (GL[i] + (Bfull ? Bfull[pos(i)] : 0))
+// g = T^T (GL + Bfull at the coarse modes) + vsign C_2^T v   (T: coarse-mode expansions)
 template <class T2>
-void launch_assemble(const Handle& h, const T2* GL, const double2* Bfull, double2* g, int R,
-                     hipStream_t s);
+void launch_assemble(const Handle& h, const T2* GL, const double2* Bfull, const double2* v, double vsign, double2* g,
+                     int R, hipStream_t s);
+// Dense blocks over the hanging dual rows: y = add + M x with M = X^-1 (y2 false) or Y_2;
+// x gathered from a dual vector (in_gather) or compact [nh][R]; y scattered or compact
+void launch_hblock(const Handle& h, bool y2, const double2* x, bool in_gather, const double2* add, double2* y,
+                   bool out_scatter, int R, hipStream_t s);
 // w = K^-1 g (dense, FP64)
 void launch_coarse_solve(const Handle& h, const double2* g, double2* w, int R, hipStream_t s);
 

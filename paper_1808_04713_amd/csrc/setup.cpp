@@ -3,8 +3,11 @@
 // Paper Sec. 2.2.1 (element matrices), Sec. 2.2.4 (edge constraints),
 // Sec. 2.3.2 (Algorithm 1), Sec. 2.3.3 (block structure and preconditioner).
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <functional>
 #include <map>
+#include <set>
 #include <tuple>
 
 #include "basis.hpp"
@@ -100,9 +103,8 @@ void gen_eig(const MatC& A, const MatD& M, MatC& E, std::vector<cd>& lam) {
     fail(HDP_E_RESONANCE, "separable eigenbasis is ill-conditioned (defective 1-D pencil)");
 }
 
-void build_class(ElemClass& C, double k, int l) {
+void build_class(ElemClass& C, double k) {
   int n = C.n, p = C.p;
-  C.nr = 4 * l;
   MatD Mt = mass_vertex(n), Kt = stiffness_vertex(n);
   cd gamma(0.0, -k);
   double beta = -k * k * C.eps;
@@ -131,14 +133,17 @@ void build_class(ElemClass& C, double k, int l) {
     }
   C.margin = mn / mx;
   if (!(C.margin > 1e-13)) fail(HDP_E_RESONANCE, "element matrix singular at this wavenumber");
-  // coarse modes: vertices, then bubbles 2..l on sides left, right, bottom, top
+  // coarse modes: vertices, then on sides left, right, bottom, top the bubbles
+  // 2..top (top: the side's primal count, or p on the coarse side of a hanging edge)
   C.R = {1 + n, 0 + n, 1, 0};
   for (int s = 1; s <= 4; ++s)
-    for (int kk = 2; kk <= l; ++kk) C.R.push_back(side_mode(n, s, kk));
+    for (int kk = 2; kk <= C.top[s - 1]; ++kk) C.R.push_back(side_mode(n, s, kk));
+  C.nr = int(C.R.size());
+  // dual slots: the bubbles above top on every side that is not on the outer boundary
   C.Gam.clear();
   for (int s = 1; s <= 4; ++s) {
     if (C.bmask & (1 << (s - 1))) continue;
-    for (int kk = l + 1; kk <= p; ++kk) C.Gam.push_back(side_mode(n, s, kk));
+    for (int kk = C.top[s - 1] + 1; kk <= p; ++kk) C.Gam.push_back(side_mode(n, s, kk));
   }
   C.m = int(C.Gam.size());
   int nr = C.nr, m = C.m, n2 = n * n;
@@ -167,10 +172,10 @@ void build_class(ElemClass& C, double k, int l) {
     for (int a = 0; a < m; ++a) H(a, g) = X.a[C.Gam[a]];
     for (int r = 0; r < nr; ++r) GG(g, r) = C.G(C.Gam[g], r);
   }
-  MatC GK = matmul(GG, C.Kc);          // G_Gam Kc
-  C.Phi = MatC(m, nr);
-  for (int r = 0; r < nr; ++r)
-    for (int a = 0; a < m; ++a) C.Phi(a, r) = -GK(a, r);
+  // Phi = -A_11^-1 A_1R on the dual slots; by the block inverse of A~ this is
+  // G_Gam Kc (the type-1 block of A~^-1 E_R times the coarse Schur complement)
+  MatC GK = matmul(GG, C.Kc);
+  C.Phi = GK;
   MatC Dc = matmul(GK, transpose(GG));
   for (size_t i = 0; i < Dc.a.size(); ++i) Dc.a[i] = H.a[i] - Dc.a[i];
   C.Op1 = MatC(m + nr, m);
@@ -178,40 +183,155 @@ void build_class(ElemClass& C, double k, int l) {
     for (int a = 0; a < m; ++a) C.Op1(a, b) = Dc(a, b);
     for (int r = 0; r < nr; ++r) C.Op1(m + r, b) = C.Phi(b, r);
   }
-  // Laplace-only Dirichlet preconditioner block: Schur complement of A~_L
-  // restricted to the type-1 set onto its edge modes (interior eliminated).
-  std::vector<int> inR(n2, 0);
-  for (int r : C.R) inR[r] = 1;
-  std::vector<int> emodes, imodes;
+  // Laplace-only blocks of the preconditioner (Sec. 2.3.3).  S_b: Schur
+  // complement of A~_L onto the side modes (interior eliminated); its block on
+  // the dual slots is the Dirichlet block Se, and eliminating the remaining
+  // type-1 side modes from it leaves the element's Laplace coarse matrix KL.
+  std::vector<int> bmodes, imodes;
   for (int md = 0; md < n2; ++md) {
-    if (inR[md]) continue;
     int ix = md % n, iy = md / n;
     if (ix >= 2 && iy >= 2) imodes.push_back(md);
-    else emodes.push_back(md);
+    else bmodes.push_back(md);
   }
   auto AL = [&](int a, int b) {
     int i1 = a % n, i2 = a / n, j1 = b % n, j2 = b / n;
     return (C.hy / C.hx) * Mt(i2, j2) * Kt(i1, j1) + (C.hx / C.hy) * Kt(i2, j2) * Mt(i1, j1);
   };
-  int ne = int(emodes.size()), ni = int(imodes.size());
-  MatD Aee(ne, ne), Aei(ne, ni), Aii(ni, ni);
-  for (int b = 0; b < ne; ++b)
-    for (int a = 0; a < ne; ++a) Aee(a, b) = AL(emodes[a], emodes[b]);
+  int nb = int(bmodes.size()), ni = int(imodes.size());
+  MatD Abb(nb, nb), Abi(nb, ni), Aii(ni, ni);
+  for (int b = 0; b < nb; ++b)
+    for (int a = 0; a < nb; ++a) Abb(a, b) = AL(bmodes[a], bmodes[b]);
   for (int b = 0; b < ni; ++b)
-    for (int a = 0; a < ne; ++a) Aei(a, b) = AL(emodes[a], imodes[b]);
+    for (int a = 0; a < nb; ++a) Abi(a, b) = AL(bmodes[a], imodes[b]);
   for (int b = 0; b < ni; ++b)
     for (int a = 0; a < ni; ++a) Aii(a, b) = AL(imodes[a], imodes[b]);
-  MatD S = Aee;
+  MatD Sb = Abb;
   if (ni > 0) {
-    MatD X = solve(Aii, transpose(Aei));
-    MatD AX = matmul(Aei, X);
-    for (size_t i = 0; i < S.a.size(); ++i) S.a[i] -= AX.a[i];
+    MatD X = solve(Aii, transpose(Abi));
+    MatD AX = matmul(Abi, X);
+    for (size_t i = 0; i < Sb.a.size(); ++i) Sb.a[i] -= AX.a[i];
   }
-  std::vector<int> epos(n2, -1);
-  for (int a = 0; a < ne; ++a) epos[emodes[a]] = a;
+  std::vector<int> bpos(n2, -1), inR(n2, 0);
+  for (int a = 0; a < nb; ++a) bpos[bmodes[a]] = a;
+  for (int r : C.R) inR[r] = 1;
   C.Se = MatD(m, m);
   for (int b = 0; b < m; ++b)
-    for (int a = 0; a < m; ++a) C.Se(a, b) = S(epos[C.Gam[a]], epos[C.Gam[b]]);
+    for (int a = 0; a < m; ++a) C.Se(a, b) = Sb(bpos[C.Gam[a]], bpos[C.Gam[b]]);
+  std::vector<int> e1;
+  for (int md : bmodes)
+    if (!inR[md]) e1.push_back(md);
+  int ne = int(e1.size());
+  C.KL = MatD(nr, nr);
+  for (int b = 0; b < nr; ++b)
+    for (int a = 0; a < nr; ++a) C.KL(a, b) = Sb(bpos[C.R[a]], bpos[C.R[b]]);
+  if (ne > 0) {
+    MatD S11(ne, ne), S1R(ne, nr);
+    for (int b = 0; b < ne; ++b)
+      for (int a = 0; a < ne; ++a) S11(a, b) = Sb(bpos[e1[a]], bpos[e1[b]]);
+    for (int b = 0; b < nr; ++b)
+      for (int a = 0; a < ne; ++a) S1R(a, b) = Sb(bpos[e1[a]], bpos[C.R[b]]);
+    MatD X = solve(S11, S1R);
+    MatD RX = matmul(transpose(S1R), X);
+    for (size_t i = 0; i < C.KL.a.size(); ++i) C.KL.a[i] -= RX.a[i];
+  }
+}
+
+// Preconditioner blocks on the dual rows that C_2 touches (hanging edges).
+// The literal nullspace basis of Sec. 2.3.2 projects each kept unknown onto
+// null(C_p) orthogonally; in terms of the expansions T used here (kept
+// unknown = coarse unknown, T_2 = the type-2 part of the basis) that basis is
+// Z_2 = T_2 G^-1 with the Gram matrix G = T_2^T T_2.  So C_2 = C_2^T G^-1 and
+// the Laplace coarse matrix is G^-1 KL G^-1, and the terms C_2 C_2^T of
+// C W C^T and C_2 KL C_2^T of the preconditioner (Sec. 2.3.3) become dense
+// blocks over the hanging rows of each connected group of coarse unknowns.
+void build_hanging_blocks(Handle& h) {
+  const int nlam = h.nlam, nK = h.nK;
+  std::vector<char> is_h(nlam, 0);
+  h.row_xinv.assign(nlam, 0.0);
+  std::vector<double> D(nlam, 0.0);
+  for (int r = 0; r < nlam; ++r) {
+    is_h[r] = h.c2_ptr[r + 1] > h.c2_ptr[r];
+    D[r] = h.row_coef[2 * r] * h.row_coef[2 * r] + h.row_coef[2 * r + 1] * h.row_coef[2 * r + 1];
+    if (is_h[r]) h.row_xinv[r] = 1.0;
+    else if (D[r] > 0) h.row_xinv[r] = 1.0 / D[r];
+    else fail(HDP_E_MESH, "dual row without entries");
+  }
+  h.hb_off.assign(1, 0);
+  h.hb_rows.clear();
+  h.hb_moff.assign(1, 0);
+  h.hb_xinv.clear();
+  h.hb_y2.clear();
+  h.nh = 0;
+  // groups: coarse unknowns that share a coarse-mode expansion or a C_2 row
+  std::vector<int> par(nK);
+  for (int i = 0; i < nK; ++i) par[i] = i;
+  std::function<int(int)> find = [&](int x) { return par[x] == x ? x : par[x] = find(par[x]); };
+  auto unite = [&](int a, int b) { a = find(a); b = find(b); if (a != b) par[a] = b; };
+  for (int i = 0; i < h.ncm; ++i)
+    for (int t = h.t_ptr[i] + 1; t < h.t_ptr[i + 1]; ++t) unite(h.t_dof[h.t_ptr[i]], h.t_dof[t]);
+  for (int r = 0; r < nlam; ++r)
+    for (int t = h.c2_ptr[r] + 1; t < h.c2_ptr[r + 1]; ++t) unite(h.c2_dof[h.c2_ptr[r]], h.c2_dof[t]);
+  std::map<int, std::vector<int>> grp_rows;
+  for (int r = 0; r < nlam; ++r)
+    if (is_h[r]) grp_rows[find(h.c2_dof[h.c2_ptr[r]])].push_back(r);
+  if (grp_rows.empty()) return;
+  std::map<int, std::vector<int>> grp_dofs;
+  for (int d = 0; d < nK; ++d) {
+    int g = find(d);
+    if (grp_rows.count(g)) grp_dofs[g].push_back(d);
+  }
+  // element of each coarse mode
+  std::vector<int> cm_elem(h.ncm);
+  for (int e = 0; e < h.E; ++e)
+    for (int i = h.cm_off[e]; i < h.cm_off[e + 1]; ++i) cm_elem[i] = e;
+  for (auto& gr : grp_rows) {
+    const std::vector<int>& rows = gr.second;
+    const std::vector<int>& S = grp_dofs[gr.first];
+    int ns = int(S.size()), nr = int(rows.size());
+    std::map<int, int> pos;
+    for (int a = 0; a < ns; ++a) pos[S[a]] = a;
+    // Gram matrix and Laplace coarse matrix restricted to the group
+    MatD G(ns, ns), KL(ns, ns);
+    std::set<int> elems;
+    for (int d : S)
+      for (int t = h.cdof_ptr[d]; t < h.cdof_ptr[d + 1]; ++t) elems.insert(cm_elem[h.cdof_list[t]]);
+    for (int e : elems) {
+      const ElemClass& C = h.classes[h.cls[e]];
+      int co = h.cm_off[e];
+      for (int a = 0; a < C.nr; ++a) {
+        int ia = co + a;
+        bool in_a = pos.count(h.t_dof[h.t_ptr[ia]]) > 0;
+        if (in_a)
+          for (int t = h.t_ptr[ia]; t < h.t_ptr[ia + 1]; ++t)
+            for (int u = h.t_ptr[ia]; u < h.t_ptr[ia + 1]; ++u)
+              G(pos[h.t_dof[t]], pos[h.t_dof[u]]) += h.t_coef[t] * h.t_coef[u];
+        if (!in_a) continue;
+        for (int b = 0; b < C.nr; ++b) {
+          int ib = co + b;
+          if (!pos.count(h.t_dof[h.t_ptr[ib]])) continue;
+          double kab = C.KL(a, b);
+          for (int t = h.t_ptr[ia]; t < h.t_ptr[ia + 1]; ++t)
+            for (int u = h.t_ptr[ib]; u < h.t_ptr[ib + 1]; ++u)
+              KL(pos[h.t_dof[t]], pos[h.t_dof[u]]) += h.t_coef[t] * kab * h.t_coef[u];
+        }
+      }
+    }
+    MatD Gi = inverse(G);
+    MatD C2(nr, ns);
+    for (int i = 0; i < nr; ++i)
+      for (int t = h.c2_ptr[rows[i]]; t < h.c2_ptr[rows[i] + 1]; ++t) C2(i, pos[h.c2_dof[t]]) += h.c2_coef[t];
+    MatD M = matmul(C2, Gi);
+    MatD X = matmul(M, transpose(M));
+    for (int i = 0; i < nr; ++i) X(i, i) += D[rows[i]];
+    MatD Y2 = matmul(matmul(M, matmul(matmul(Gi, KL), Gi)), transpose(M));
+    MatD Xi = inverse(X);
+    h.hb_rows.insert(h.hb_rows.end(), rows.begin(), rows.end());
+    h.hb_off.push_back(int(h.hb_rows.size()));
+    h.hb_xinv.insert(h.hb_xinv.end(), Xi.a.begin(), Xi.a.end());
+    h.hb_y2.insert(h.hb_y2.end(), Y2.a.begin(), Y2.a.end());
+    h.hb_moff.push_back(int64_t(h.hb_xinv.size()));
+  }
+  h.nh = int(h.hb_rows.size());
 }
 
 }  // namespace
@@ -259,8 +379,11 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
     h.hy[e] = s * fhy;
   }
   if (area != NX * NY) fail(HDP_E_MESH, "leaves do not tile the domain");
-  // sides: match interior sides pairwise (conforming meshes only)
-  std::map<SideKey, std::vector<std::pair<int, int>>> sides;
+  // sides: neighbours along the same grid line.  A side either matches one
+  // neighbour side exactly (conforming), lies inside one longer neighbour side
+  // (fine side of a hanging edge) or holds several shorter ones (coarse side).
+  struct Seg { int64_t lo, hi; int e, s; };
+  std::map<std::pair<int, int64_t>, std::vector<Seg>> facing[2];   // [0]: sides 1,3; [1]: sides 2,4
   auto key_of = [&](int e, int s) {
     switch (s) {
       case 1: return SideKey{0, X0[e], Y0[e], Y1[e]};
@@ -270,24 +393,52 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
     }
   };
   for (int e = 0; e < E; ++e)
-    for (int s = 1; s <= 4; ++s) sides[key_of(e, s)].push_back({e, s});
-  std::vector<int> nb_e(4 * E, -1), nb_s(4 * E, 0);
+    for (int s = 1; s <= 4; ++s) {
+      SideKey k = key_of(e, s);
+      facing[(s - 1) % 2][{k.kind, k.c}].push_back({k.lo, k.hi, e, s});
+    }
+  h.side_type.assign(4 * E, 0);
+  h.side_le.assign(4 * E, 0);
+  h.nb_e.assign(4 * E, -1);
+  h.nb_s.assign(4 * E, 0);
+  h.side_a.assign(4 * E, 1.0);
+  h.side_b.assign(4 * E, 0.0);
+  h.side_nbrs.assign(4 * E, {});
   h.bmask.assign(E, 0);
   for (int e = 0; e < E; ++e)
     for (int s = 1; s <= 4; ++s) {
+      const int si = 4 * e + s - 1;
       SideKey key = key_of(e, s);
       bool bnd = (key.kind == 0 && (key.c == 0 || key.c == NX)) ||
                  (key.kind == 1 && (key.c == 0 || key.c == NY));
       if (bnd) { h.bmask[e] |= 1 << (s - 1); continue; }
-      auto& v = sides[key];
-      if (v.size() != 2)
-        fail(HDP_E_UNSUPPORTED, "non-conforming (hanging) edges are not supported by this build");
-      auto o = v[0].first == e ? v[1] : v[0];
-      if (o.first == e) fail(HDP_E_MESH, "duplicate leaf");
-      nb_e[4 * e + s - 1] = o.first;
-      nb_s[4 * e + s - 1] = o.second;
+      std::vector<Seg> ov;
+      for (const Seg& o : facing[s % 2][{key.kind, key.c}])
+        if (std::min(o.hi, key.hi) > std::max(o.lo, key.lo)) ov.push_back(o);
+      if (ov.empty()) fail(HDP_E_MESH, "interior side without a neighbour");
+      if (ov.size() == 1 && ov[0].lo == key.lo && ov[0].hi == key.hi) {
+        h.side_type[si] = 1;
+        h.nb_e[si] = ov[0].e;
+        h.nb_s[si] = ov[0].s;
+      } else if (ov.size() == 1 && ov[0].lo <= key.lo && ov[0].hi >= key.hi) {
+        h.side_type[si] = 2;
+        h.nb_e[si] = ov[0].e;
+        h.nb_s[si] = ov[0].s;
+        double L = double(ov[0].hi - ov[0].lo);
+        h.side_a[si] = double(key.hi - key.lo) / L;
+        h.side_b[si] = double(key.lo + key.hi - ov[0].lo - ov[0].hi) / L;
+      } else {
+        int64_t covered = 0;
+        for (const Seg& o : ov) {
+          if (o.lo < key.lo || o.hi > key.hi) fail(HDP_E_MESH, "overlapping leaves");
+          covered += o.hi - o.lo;
+          h.side_nbrs[si].push_back(o.e);
+        }
+        if (covered != key.hi - key.lo) fail(HDP_E_MESH, "side not covered by its neighbours");
+        h.side_type[si] = 3;
+      }
+      if (h.side_type[si] != 1) h.nonconforming = true;
     }
-  h.nb_e = nb_e;
   // coarse order l (Sec. 2.3.4): the criterion is evaluated for every element with
   // its longest edge and its local wavenumber k sqrt(eps_r), and the largest value
   // is used (with eps_r = 1 this is the free-space k and the longest edge)
@@ -295,20 +446,30 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
   for (int e = 0; e < E; ++e)
     khmax = std::max(khmax, prob->k * std::sqrt(std::max(h.eps[e], 0.0)) * std::max(h.hx[e], h.hy[e]));
   h.l = prob->l > 0 ? prob->l : dispersion_l(khmax, 1.0) + std::max(0, prob->l_safety);
+  const int l = h.l;
+  // per side: the primal count le = min(l, p, p_neighbour) of its edge and the
+  // highest bubble index among the element's coarse modes
+  std::vector<std::array<int, 4>> tops(E);
   for (int e = 0; e < E; ++e)
-    if (h.l >= h.deg[e])
-      fail(HDP_E_UNSUPPORTED, "coarse order l must be below every element degree in this build");
-  int l = h.l;
+    for (int s = 1; s <= 4; ++s) {
+      const int si = 4 * e + s - 1, p = h.deg[e];
+      int le = std::min(l, p), top = le;
+      if (h.side_type[si] == 1 || h.side_type[si] == 2) le = top = std::min(le, h.deg[h.nb_e[si]]);
+      else if (h.side_type[si] == 3) top = p;
+      h.side_le[si] = le;
+      tops[e][s - 1] = top;
+    }
   // classes
-  std::map<std::tuple<int, double, double, double, int>, int> cmap;
+  std::map<std::tuple<int, double, double, double, int, std::array<int, 4>>, int> cmap;
   h.cls.resize(E);
   for (int e = 0; e < E; ++e) {
-    auto key = std::make_tuple(h.deg[e], h.hx[e], h.hy[e], h.eps[e], h.bmask[e]);
+    auto key = std::make_tuple(h.deg[e], h.hx[e], h.hy[e], h.eps[e], h.bmask[e], tops[e]);
     auto it = cmap.find(key);
     if (it == cmap.end()) {
       ElemClass C;
       C.p = h.deg[e]; C.n = C.p + 1; C.hx = h.hx[e]; C.hy = h.hy[e];
       C.eps = h.eps[e]; C.bmask = h.bmask[e];
+      for (int s = 0; s < 4; ++s) C.top[s] = tops[e][s];
       it = cmap.emplace(key, int(h.classes.size())).first;
       h.classes.push_back(C);
     }
@@ -317,7 +478,7 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
   }
   h.min_margin = 1;
   for (auto& C : h.classes) {
-    build_class(C, h.k, l);
+    build_class(C, h.k);
     h.min_margin = std::min(h.min_margin, C.margin);
   }
   // offsets
@@ -338,43 +499,202 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
     const ElemClass& C = h.classes[h.cls[e]];
     int pos = 0;
     for (int t = 1; t < s; ++t)
-      if (!(C.bmask & (1 << (t - 1)))) pos += C.p - l;
-    return h.slot_off[e] + pos + (kk - l - 1);
+      if (!(C.bmask & (1 << (t - 1)))) pos += C.p - C.top[t - 1];
+    return h.slot_off[e] + pos + (kk - C.top[s - 1] - 1);
   };
-  // dual rows in Algorithm 1 visiting order
+  // ---- coarse unknowns and the coarse-mode expansions T ----------------------
+  // Geometric points on the finest grid.  A point strictly inside a side is a
+  // hanging point: its value is the trace of that (coarse) side there.
+  using Pt = std::pair<int64_t, int64_t>;
+  std::map<Pt, std::pair<int, int>> owner;   // hanging point -> (element, side) holding it
+  for (int e = 0; e < E; ++e)
+    for (int s = 1; s <= 4; ++s) {
+      const int si = 4 * e + s - 1;
+      if (h.side_type[si] != 3) continue;
+      SideKey k = key_of(e, s);
+      for (int f : h.side_nbrs[si]) {
+        int64_t ends[2] = {k.kind == 0 ? Y0[f] : X0[f], k.kind == 0 ? Y1[f] : X1[f]};
+        for (int64_t q : ends)
+          if (q > k.lo && q < k.hi) owner[k.kind == 0 ? Pt{k.c, q} : Pt{q, k.c}] = {e, s};
+      }
+    }
+  std::map<std::tuple<int, int64_t, int64_t, int64_t, int>, int> cids;
+  auto dof_id = [&](const std::tuple<int, int64_t, int64_t, int64_t, int>& key) {
+    auto it = cids.find(key);
+    if (it == cids.end()) it = cids.emplace(key, int(cids.size())).first;
+    return it->second;
+  };
+  auto bubble_dof = [&](int e, int s, int kk) {
+    SideKey sk = key_of(e, s);
+    return dof_id(std::make_tuple(sk.kind, sk.c, sk.lo, sk.hi, kk));
+  };
+  // corner (ix, iy) of element e: ix = 0 right, 1 left; iy = 0 top, 1 bottom
+  auto corner = [&](int e, int ix, int iy) { return Pt{ix == 0 ? X1[e] : X0[e], iy == 0 ? Y1[e] : Y0[e]}; };
+  // end of side s at parameter +1 / -1 (parameter along increasing x or y)
+  auto side_end = [&](int e, int s, bool plus) {
+    if (s <= 2) return corner(e, s == 2 ? 0 : 1, plus ? 0 : 1);
+    return corner(e, plus ? 0 : 1, s == 4 ? 0 : 1);
+  };
+  using Expansion = std::map<int, double>;
+  std::map<Pt, Expansion> memo;
+  std::function<Expansion(const Pt&)> expand = [&](const Pt& P) -> Expansion {
+    auto m = memo.find(P);
+    if (m != memo.end()) return m->second;
+    Expansion out;
+    auto o = owner.find(P);
+    if (o == owner.end()) {
+      out[dof_id(std::make_tuple(-1, P.first, P.second, int64_t(0), 0))] = 1.0;
+    } else {
+      int c = o->second.first, s = o->second.second;
+      SideKey k = key_of(c, s);
+      int64_t q = k.kind == 0 ? P.second : P.first;
+      double t = 2.0 * double(q - k.lo) / double(k.hi - k.lo) - 1.0;
+      int nc = h.deg[c] + 1;
+      std::vector<double> v(nc);
+      vertex_basis(nc, t, v.data());
+      for (auto& kv : expand(side_end(c, s, true))) out[kv.first] += v[0] * kv.second;
+      for (auto& kv : expand(side_end(c, s, false))) out[kv.first] += v[1] * kv.second;
+      for (int j = 2; j < nc; ++j) out[bubble_dof(c, s, j)] += v[j];
+    }
+    memo[P] = out;
+    return out;
+  };
+  // restriction of the coarse side's bubbles to a fine side: rho[k][j] is the
+  // fine vertex-basis coefficient k of N_j(a s + b) (exact polynomial
+  // interpolation at the Gauss-Lobatto nodes of the coarse degree)
+  auto restriction = [&](int e, int s) {
+    const int si = 4 * e + s - 1;
+    int c = h.nb_e[si];
+    int nc = h.deg[c] + 1;
+    double a = h.side_a[si], b = h.side_b[si];
+    std::vector<double> t = gll_nodes(nc), row(nc);
+    MatD V(nc, nc), Rh(nc, nc);
+    for (int i = 0; i < nc; ++i) {
+      vertex_basis(nc, t[i], row.data());
+      for (int m = 0; m < nc; ++m) V(i, m) = row[m];
+      vertex_basis(nc, a * t[i] + b, row.data());
+      for (int j = 0; j < nc; ++j) Rh(i, j) = row[j];
+    }
+    return solve(V, Rh);   // (nc x nc): [k][j]
+  };
+  std::map<int, MatD> rho;   // per fine side index si
+  for (int e = 0; e < E; ++e)
+    for (int s = 1; s <= 4; ++s)
+      if (h.side_type[4 * e + s - 1] == 2) rho[4 * e + s - 1] = restriction(e, s);
+  h.t_ptr.assign(h.ncm + 1, 0);
+  h.t_dof.clear();
+  h.t_coef.clear();
+  h.cm_mode.assign(h.ncm, 0);
+  for (int e = 0; e < E; ++e) {
+    const ElemClass& C = h.classes[h.cls[e]];
+    for (int r = 0; r < C.nr; ++r) {
+      int md = C.R[r], n = C.n, ix = md % n, iy = md / n;
+      Expansion ex;
+      if (ix < 2 && iy < 2) {
+        ex = expand(corner(e, ix, iy));
+      } else {
+        int s, kk;
+        if (ix == 0) { s = 2; kk = iy; }
+        else if (ix == 1) { s = 1; kk = iy; }
+        else if (iy == 0) { s = 4; kk = ix; }
+        else { s = 3; kk = ix; }
+        const int si = 4 * e + s - 1;
+        if (h.side_type[si] == 2) {
+          // fine side of a hanging edge: bubble kk of the restricted coarse trace
+          const MatD& rh = rho.at(si);
+          int c = h.nb_e[si], sc = h.nb_s[si];
+          for (int j = kk; j <= h.deg[c]; ++j) ex[bubble_dof(c, sc, j)] += rh(kk, j);
+        } else if (h.side_type[si] == 1) {
+          // shared edge: both elements name it by the same segment
+          ex[bubble_dof(e, s, kk)] = 1.0;
+        } else {
+          ex[bubble_dof(e, s, kk)] = 1.0;
+        }
+      }
+      int i = h.cm_off[e] + r;
+      h.cm_mode[i] = md;
+      for (auto& kv : ex)
+        if (kv.second != 0.0) {
+          h.t_dof.push_back(kv.first);
+          h.t_coef.push_back(kv.second);
+        }
+      h.t_ptr[i + 1] = int(h.t_dof.size());
+    }
+  }
+  h.nK = int(cids.size());
+  h.cdof_ptr.assign(h.nK + 1, 0);
+  for (int d : h.t_dof) h.cdof_ptr[d + 1]++;
+  for (int i = 0; i < h.nK; ++i) h.cdof_ptr[i + 1] += h.cdof_ptr[i];
+  h.cdof_list.assign(h.t_dof.size(), 0);
+  h.cdof_coef.assign(h.t_dof.size(), 0.0);
+  {
+    std::vector<int> fill(h.cdof_ptr.begin(), h.cdof_ptr.end() - 1);
+    for (int i = 0; i < h.ncm; ++i)
+      for (int t = h.t_ptr[i]; t < h.t_ptr[i + 1]; ++t) {
+        int d = h.t_dof[t], at = fill[d]++;
+        h.cdof_list[at] = i;
+        h.cdof_coef[at] = h.t_coef[t];
+      }
+  }
+  // ---- dual rows in Algorithm 1 visiting order -----------------------------
   std::vector<int> vorder(E);
   for (int e = 0; e < E; ++e) vorder[e] = e;
   std::stable_sort(vorder.begin(), vorder.end(), [&](int a, int b) { return level[a] > level[b]; });
   std::vector<char> visited(4 * E, 0);
+  std::map<std::pair<int, int>, std::set<int>> zeroed;   // coarse side -> rows already imposed
   h.row_slot.clear(); h.row_coef.clear();
+  h.c2_ptr.assign(1, 0); h.c2_dof.clear(); h.c2_coef.clear();
   h.slot_row.assign(h.nslots, -1);
   h.slot_coef.assign(h.nslots, 0.0);
   h.slot_mode.assign(h.nslots, 0);
+  auto add_row = [&](int a, double ca, int b, double cb) {
+    int row = int(h.row_coef.size() / 2);
+    h.row_slot.push_back(a);
+    h.row_coef.push_back(a >= 0 ? ca : 0.0);
+    h.row_slot.push_back(b);
+    h.row_coef.push_back(b >= 0 ? cb : 0.0);
+    if (a >= 0) { h.slot_row[a] = row; h.slot_coef[a] = ca; }
+    if (b >= 0) { h.slot_row[b] = row; h.slot_coef[b] = cb; }
+    return row;
+  };
   for (int e : vorder)
     for (int s = 1; s <= 4; ++s) {
-      if (h.bmask[e] & (1 << (s - 1))) continue;
-      if (visited[4 * e + s - 1]) continue;
-      int c = nb_e[4 * e + s - 1], sc = nb_s[4 * e + s - 1];
-      visited[4 * e + s - 1] = visited[4 * c + sc - 1] = 1;
+      const int si = 4 * e + s - 1;
+      const int type = h.side_type[si];
+      if (type == 0 || visited[si]) continue;
+      visited[si] = 1;
+      if (type == 3) continue;   // imposed from the finer sides
+      int c = h.nb_e[si], sc = h.nb_s[si];
+      int le = h.side_le[si];
       int L = std::max(h.deg[e], h.deg[c]);
-      for (int kk = l + 1; kk <= L; ++kk) {
-        int row = int(h.row_coef.size() / 2);
-        int a = kk <= h.deg[c] ? slot_of(c, sc, kk) : -1;
-        int b = kk <= h.deg[e] ? slot_of(e, s, kk) : -1;
-        h.row_slot.push_back(a);
-        h.row_coef.push_back(a >= 0 ? SQ2 : 0.0);
-        h.row_slot.push_back(b);
-        h.row_coef.push_back(b >= 0 ? -SQ2 : 0.0);
-        if (a >= 0) { h.slot_row[a] = row; h.slot_coef[a] = SQ2; }
-        if (b >= 0) { h.slot_row[b] = row; h.slot_coef[b] = -SQ2; }
+      if (type == 1) {
+        visited[4 * c + sc - 1] = 1;
+        for (int kk = le + 1; kk <= L; ++kk) {
+          add_row(kk <= h.deg[c] ? slot_of(c, sc, kk) : -1, SQ2, kk <= h.deg[e] ? slot_of(e, s, kk) : -1, -SQ2);
+          h.c2_ptr.push_back(int(h.c2_dof.size()));
+        }
+      } else {
+        // fine side: [restricted coarse trace]_k - [fine trace]_k; rows whose
+        // fine mode does not exist only involve the coarse side and are kept
+        // once per coarse side (degree-reduction redundancy)
+        const MatD& rh = rho.at(si);
+        auto& zs = zeroed[{c, sc}];
+        for (int kk = le + 1; kk <= L; ++kk) {
+          if (kk > h.deg[e]) {
+            if (zs.count(kk)) continue;
+            zs.insert(kk);
+          }
+          add_row(-1, 0.0, kk <= h.deg[e] ? slot_of(e, s, kk) : -1, -SQ2);
+          for (int j = kk; j <= h.deg[c]; ++j) {
+            h.c2_dof.push_back(bubble_dof(c, sc, j));
+            h.c2_coef.push_back(SQ2 * rh(kk, j));
+          }
+          h.c2_ptr.push_back(int(h.c2_dof.size()));
+        }
       }
     }
   h.nlam = int(h.row_coef.size() / 2);
-  h.row_xinv.resize(h.nlam);
-  for (int r = 0; r < h.nlam; ++r) {
-    double x = h.row_coef[2 * r] * h.row_coef[2 * r] + h.row_coef[2 * r + 1] * h.row_coef[2 * r + 1];
-    h.row_xinv[r] = 1.0 / x;
-  }
+  if (int(cids.size()) != h.nK) fail(HDP_E_MESH, "coarse unknown without a coarse mode");
   for (int e = 0; e < E; ++e) {
     const ElemClass& C = h.classes[h.cls[e]];
     for (int g = 0; g < C.m; ++g) {
@@ -382,40 +702,22 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
       if (h.slot_row[h.slot_off[e] + g] < 0) fail(HDP_E_MESH, "dual slot without a row");
     }
   }
-  // coarse unknowns: one per mesh vertex and per low-order bubble of every edge
-  std::map<std::tuple<int, int64_t, int64_t, int64_t, int>, int> cids;
-  h.cm_dof.assign(h.ncm, -1);
-  h.cm_mode.assign(h.ncm, 0);
-  for (int e = 0; e < E; ++e) {
-    const ElemClass& C = h.classes[h.cls[e]];
-    int64_t vx[2] = {X1[e], X0[e]}, vy[2] = {Y1[e], Y0[e]};
-    for (int r = 0; r < C.nr; ++r) {
-      int md = C.R[r], n = C.n, ix = md % n, iy = md / n;
-      std::tuple<int, int64_t, int64_t, int64_t, int> key;
-      if (ix < 2 && iy < 2) {
-        key = std::make_tuple(-1, vx[ix], vy[iy], int64_t(0), 0);
-      } else {
-        int s, kk;
-        if (ix == 0) { s = 2; kk = iy; }
-        else if (ix == 1) { s = 1; kk = iy; }
-        else if (iy == 0) { s = 4; kk = ix; }
-        else { s = 3; kk = ix; }
-        SideKey sk = key_of(e, s);
-        key = std::make_tuple(sk.kind, sk.c, sk.lo, sk.hi, kk);
+  // transpose of C_2
+  h.c2t_ptr.assign(h.nK + 1, 0);
+  for (int d : h.c2_dof) h.c2t_ptr[d + 1]++;
+  for (int i = 0; i < h.nK; ++i) h.c2t_ptr[i + 1] += h.c2t_ptr[i];
+  h.c2t_row.assign(h.c2_dof.size(), 0);
+  h.c2t_coef.assign(h.c2_dof.size(), 0.0);
+  {
+    std::vector<int> fill(h.c2t_ptr.begin(), h.c2t_ptr.end() - 1);
+    for (int r = 0; r < h.nlam; ++r)
+      for (int t = h.c2_ptr[r]; t < h.c2_ptr[r + 1]; ++t) {
+        int at = fill[h.c2_dof[t]]++;
+        h.c2t_row[at] = r;
+        h.c2t_coef[at] = h.c2_coef[t];
       }
-      auto it = cids.find(key);
-      if (it == cids.end()) it = cids.emplace(key, int(cids.size())).first;
-      h.cm_dof[h.cm_off[e] + r] = it->second;
-      h.cm_mode[h.cm_off[e] + r] = md;
-    }
   }
-  h.nK = int(cids.size());
-  h.cdof_ptr.assign(h.nK + 1, 0);
-  for (int i = 0; i < h.ncm; ++i) h.cdof_ptr[h.cm_dof[i] + 1]++;
-  for (int i = 0; i < h.nK; ++i) h.cdof_ptr[i + 1] += h.cdof_ptr[i];
-  h.cdof_list.assign(h.ncm, 0);
-  std::vector<int> fill(h.cdof_ptr.begin(), h.cdof_ptr.end() - 1);
-  for (int i = 0; i < h.ncm; ++i) h.cdof_list[fill[h.cm_dof[i]]++] = i;
+  build_hanging_blocks(h);
   // algorithmic work counts
   for (auto& C : h.classes) {
     h.op1_bytes += 16.0 * (C.m + C.nr) * C.m;

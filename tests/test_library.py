@@ -48,26 +48,44 @@ def test_inspect_matches_oracle_counts(n, p, k, l):
     assert st["dof"] == n * n * (p + 1) ** 2
 
 
+def _hanging(base, pvals, seed, l, k=6.0, passes=2):
+    lv = W.refine_where(W.morton_leaves(base, base), 0, 1, 0, 1, base, base,
+                        lambda x, y: (x - 0.5) ** 2 + (y - 0.5) ** 2 < (0.03 if base % 2 else 0.05), passes)
+    rng = np.random.default_rng(seed)
+    deg = rng.integers(pvals[0], pvals[1] + 1, len(lv))
+    return dict(domain=(0.0, 1.0, 0.0, 1.0), base=(base, base), leaves=lv, degree=deg, k=k, l=l,
+                bc="impedance", eps_r=np.ones(len(lv)), rhs=dict(kind="plane_wave_total", angles=[0.4]))
+
+
+@pytest.mark.parametrize("base,pvals,seed,l", [(3, (4, 4), 0, 1), (3, (3, 6), 1, 2), (4, (2, 5), 2, 3),
+                                                (3, (3, 7), 3, 7)])
+def test_inspect_matches_literal_oracle_on_hanging_meshes(base, pvals, seed, l):
+    """Dual rows and coarse unknowns on meshes with hanging edges (up to three
+    hanging nodes per edge), uneven degrees and l above some degrees: the
+    library's counts equal the literal oracle's (dual rows of C_d, type-2
+    columns of Z from Algorithm 1)."""
+    from oracle import constraints as cs
+    w = _hanging(base, pvals, seed, l)
+    disc = pb.Discretisation(w)
+    con = cs.Constraints(disc.mesh, disc.degrees, l, disc.bc)
+    n_dual = int((~con.primal).sum())
+    status = cs.algorithm1(disc.mesh, disc.degrees, l, disc.bc)
+    n_type2 = sum(int((st == 2).sum()) for st in status)
+    st = hdp.inspect(w)
+    assert disc.mesh.Lmax == 2
+    assert (st["l"], st["n_lambda"], st["n_coarse"]) == (l, n_dual, n_type2)
+
+
 def test_inspect_rejects_bad_input():
     w = W.plane_wave_4x4()
     bad = dict(w, k=float("nan"))
     with pytest.raises(hdp.HdpError) as e:
         hdp.inspect(bad)
     assert e.value.status == -1
-    # l not below the degree
-    with pytest.raises(hdp.HdpError) as e:
-        hdp.inspect(dict(w, l=8))
-    assert e.value.status == -7
     # leaves that do not tile the domain
     with pytest.raises(hdp.HdpError) as e:
         hdp.inspect(dict(w, leaves=w["leaves"][:-1], degree=w["degree"][:-1], eps_r=w["eps_r"][:-1]))
     assert e.value.status == -2
-    # hanging edges: outside this build
-    lv = W.refine_where(W.morton_leaves(2, 2), 0, 1, 0, 1, 2, 2, lambda x, y: x < 0.5 and y < 0.5, 1)
-    wh = dict(w, base=(2, 2), leaves=lv, degree=np.full(len(lv), 6), eps_r=np.ones(len(lv)))
-    with pytest.raises(hdp.HdpError) as e:
-        hdp.inspect(wh)
-    assert e.value.status == -7
 
 
 def test_inspect_reports_element_resonance():
