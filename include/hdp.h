@@ -90,6 +90,10 @@ typedef struct {
                                  evaluated with each element's longest edge and local
                                  wavenumber k sqrt(eps_r), the largest value taken */
   int32_t l_safety;           /* added to the rule's value (the paper adds 1 in Sec. 3.3) */
+  double discard_tol;         /* Sec. 2.2.4: a dual constraint of degree k on the fine side of
+                                 a hanging edge is dropped when the diagonal a^k of its change
+                                 of basis L_c^f is below this value (0 keeps every constraint;
+                                 primal constraints are always kept) */
 } hdp_problem;
 
 typedef struct {
@@ -123,6 +127,7 @@ typedef struct {
   /* host-side breakdown of solve_ms: loads and interface right-hand side,
    * GMRES (launch calls, waits for the device), recovery and sampling */
   double rhs_ms, gmres_ms, gmres_launch_ms, gmres_wait_ms, recover_ms;
+  double true_residual;       /* ||g - F nu|| / ||g|| in FP64 after the solve, max over RHS */
 } hdp_stats;
 
 typedef struct hdp_handle hdp_handle;

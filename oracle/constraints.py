@@ -75,10 +75,12 @@ class Constraints:
     side gives C_i phi = d_i.  Rows k <= min(l, p_c, p_f) are primal (C_p), the rest
     dual (C_d).
     Rows that only zero coarse modes already zeroed by a sibling fine edge are
-    dropped (Sec. 2.2.4, degree-reduction redundancy).
+    dropped (Sec. 2.2.4, degree-reduction redundancy), and so are dual rows
+    whose diagonal entry of L_c^f lies below tau (Sec. 2.2.4, discard
+    threshold for decayed constraints; tau = 0 keeps all).
     """
 
-    def __init__(self, mesh, degrees, l, bc, dirichlet_fun=None):
+    def __init__(self, mesh, degrees, l, bc, dirichlet_fun=None, tau=0.0):
         self.mesh, self.degrees, self.l = mesh, np.asarray(degrees), l
         self.off = offsets(degrees)
         self.ndof = int(self.off[-1])
@@ -146,6 +148,10 @@ class Constraints:
                 zkey = (c, sc)
                 zset = zeroed.setdefault(zkey, set())
                 for k in range(L):
+                    if k > edge_l(l, ne, nc) and abs(Lcf[k, k]) < tau:
+                        # decayed diagonal of L_c^f: the dual constraint is dropped
+                        # (Sec. 2.2.4 discard threshold; primal rows are kept)
+                        continue
                     if k >= ne:
                         # only coarse modes enter this row: it zeroes them
                         if k in zset:

@@ -32,7 +32,7 @@ class LiteralDP:
         AL = sp.block_diag([sp.csr_matrix(a) for a in disc.A_lap]).toarray()
         b = np.concatenate(disc.b)
         self.A, self.b = A, b
-        con = cs.Constraints(mesh, deg, l, disc.bc, disc.dirichlet_fun())
+        con = cs.Constraints(mesh, deg, l, disc.bc, disc.dirichlet_fun(), tau=disc.w.get("discard_tol", 0.0))
         self.con = con
         Cp, dp, Cd, dd, _ = con.split()
         status = cs.algorithm1(mesh, deg, l, disc.bc)

@@ -34,7 +34,7 @@ class _Mesh(ctypes.Structure):
 
 class _Problem(ctypes.Structure):
     _fields_ = [("k", ctypes.c_double), ("eps_r", ctypes.POINTER(ctypes.c_double)),
-                ("l", ctypes.c_int32), ("l_safety", ctypes.c_int32)]
+                ("l", ctypes.c_int32), ("l_safety", ctypes.c_int32), ("discard_tol", ctypes.c_double)]
 
 
 class _Options(ctypes.Structure):
@@ -54,7 +54,8 @@ class Stats(ctypes.Structure):
                 ("rel_residual", ctypes.c_double), ("min_element_margin", ctypes.c_double),
                 ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double), ("rhs_ms", ctypes.c_double),
                 ("gmres_ms", ctypes.c_double), ("gmres_launch_ms", ctypes.c_double),
-                ("gmres_wait_ms", ctypes.c_double), ("recover_ms", ctypes.c_double)]
+                ("gmres_wait_ms", ctypes.c_double), ("recover_ms", ctypes.c_double),
+                ("true_residual", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -127,7 +128,7 @@ def _structs(w, l_safety=0):
                  leaves.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                  deg.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
     prob = _Problem(float(w["k"]), eps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                    int(w.get("l", -1)), int(l_safety))
+                    int(w.get("l", -1)), int(l_safety), float(w.get("discard_tol", 0.0)))
     return mesh, prob, (leaves, deg, eps)
 
 

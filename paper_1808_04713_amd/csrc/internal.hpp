@@ -29,6 +29,7 @@ struct ElemClass {
   double hx = 0, hy = 0, eps = 1;
   int bmask = 0;               // bit (s-1): side s on the outer impedance boundary
   int top[4] = {1, 1, 1, 1};   // per side: bubbles 2..top are coarse modes
+  int gtop[4] = {0, 0, 0, 0};  // per side: bubbles top+1..gtop are dual slots
   int m = 0, nr = 0;           // dual slots, coarse modes
   std::vector<int> R;          // coarse (removed, type-2) modes, canonical order
   std::vector<int> Gam;        // dual-touched type-1 edge modes, slot order
@@ -71,7 +72,7 @@ struct Handle {
   // problem
   int E = 0, l = 0, nlam = 0, nK = 0;
   int64_t dof = 0;
-  double k = 0;
+  double k = 0, discard_tol = 0;
   int max_rhs = 1, max_iter = 100, precision = HDP_FP64;
   double tol = 1e-8;
   hipStream_t stream = nullptr;        // internal stream all work is issued on

@@ -139,12 +139,11 @@ void build_class(ElemClass& C, double k) {
   for (int s = 1; s <= 4; ++s)
     for (int kk = 2; kk <= C.top[s - 1]; ++kk) C.R.push_back(side_mode(n, s, kk));
   C.nr = int(C.R.size());
-  // dual slots: the bubbles above top on every side that is not on the outer boundary
+  // dual slots: the bubbles top+1..gtop of every side (none on the outer boundary;
+  // above gtop only where decayed hanging-edge constraints were dropped)
   C.Gam.clear();
-  for (int s = 1; s <= 4; ++s) {
-    if (C.bmask & (1 << (s - 1))) continue;
-    for (int kk = C.top[s - 1] + 1; kk <= p; ++kk) C.Gam.push_back(side_mode(n, s, kk));
-  }
+  for (int s = 1; s <= 4; ++s)
+    for (int kk = C.top[s - 1] + 1; kk <= C.gtop[s - 1]; ++kk) C.Gam.push_back(side_mode(n, s, kk));
   C.m = int(C.Gam.size());
   int nr = C.nr, m = C.m, n2 = n * n;
   auto unit_solve = [&](int mode) {
@@ -449,18 +448,27 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
   const int l = h.l;
   // per side: the primal count le = min(l, p, p_neighbour) of its edge and the
   // highest bubble index among the element's coarse modes
-  std::vector<std::array<int, 4>> tops(E);
+  // and the highest dual-slot bubble gtop: p, or on the fine side of a hanging
+  // edge the last degree whose constraint diagonal a^k stays above discard_tol
+  const double tau = std::max(0.0, prob->discard_tol);
+  if (!std::isfinite(prob->discard_tol)) fail(HDP_E_ARG, "discard_tol not finite");
+  h.discard_tol = tau;
+  std::vector<std::array<int, 8>> tops(E);
   for (int e = 0; e < E; ++e)
     for (int s = 1; s <= 4; ++s) {
       const int si = 4 * e + s - 1, p = h.deg[e];
-      int le = std::min(l, p), top = le;
+      int le = std::min(l, p), top = le, gtop = p;
       if (h.side_type[si] == 1 || h.side_type[si] == 2) le = top = std::min(le, h.deg[h.nb_e[si]]);
       else if (h.side_type[si] == 3) top = p;
+      if (h.side_type[si] == 0) gtop = top;
+      if (h.side_type[si] == 2)
+        while (gtop > le && std::pow(h.side_a[si], gtop) < tau) --gtop;
       h.side_le[si] = le;
       tops[e][s - 1] = top;
+      tops[e][4 + s - 1] = gtop;
     }
   // classes
-  std::map<std::tuple<int, double, double, double, int, std::array<int, 4>>, int> cmap;
+  std::map<std::tuple<int, double, double, double, int, std::array<int, 8>>, int> cmap;
   h.cls.resize(E);
   for (int e = 0; e < E; ++e) {
     auto key = std::make_tuple(h.deg[e], h.hx[e], h.hy[e], h.eps[e], h.bmask[e], tops[e]);
@@ -469,7 +477,10 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
       ElemClass C;
       C.p = h.deg[e]; C.n = C.p + 1; C.hx = h.hx[e]; C.hy = h.hy[e];
       C.eps = h.eps[e]; C.bmask = h.bmask[e];
-      for (int s = 0; s < 4; ++s) C.top[s] = tops[e][s];
+      for (int s = 0; s < 4; ++s) {
+        C.top[s] = tops[e][s];
+        C.gtop[s] = tops[e][4 + s];
+      }
       it = cmap.emplace(key, int(h.classes.size())).first;
       h.classes.push_back(C);
     }
@@ -498,8 +509,7 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
   auto slot_of = [&](int e, int s, int kk) {
     const ElemClass& C = h.classes[h.cls[e]];
     int pos = 0;
-    for (int t = 1; t < s; ++t)
-      if (!(C.bmask & (1 << (t - 1)))) pos += C.p - C.top[t - 1];
+    for (int t = 1; t < s; ++t) pos += C.gtop[t - 1] - C.top[t - 1];
     return h.slot_off[e] + pos + (kk - C.top[s - 1] - 1);
   };
   // ---- coarse unknowns and the coarse-mode expansions T ----------------------
@@ -680,6 +690,7 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
         const MatD& rh = rho.at(si);
         auto& zs = zeroed[{c, sc}];
         for (int kk = le + 1; kk <= L; ++kk) {
+          if (std::pow(h.side_a[si], kk) < tau) break;   // decayed constraint diagonal (Sec. 2.2.4)
           if (kk > h.deg[e]) {
             if (zs.count(kk)) continue;
             zs.insert(kk);

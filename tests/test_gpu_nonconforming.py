@@ -36,12 +36,28 @@ def hanging(base, pvals, seed, l, k=6.0, rhs="plane_wave_total"):
     return w
 
 
+def small_disk(base=6, pvals=(3, 6), seed=4, k=12.0, tau=1e-3):
+    """The refined-disk layout at a size the literal oracle handles: [-1,1]^2,
+    leaves with centre in r < 0.4 split twice, eps_r = 2.25 inside, uneven p."""
+    lv = W.refine_where(W.morton_leaves(base, base), -1, 1, -1, 1, base, base,
+                        lambda x, y: x * x + y * y < 0.16, 2)
+    deg = np.random.default_rng(seed).integers(pvals[0], pvals[1] + 1, len(lv))
+    w = dict(domain=(-1.0, 1.0, -1.0, 1.0), base=(base, base), leaves=lv, degree=deg, k=k, l=-1,
+             bc="impedance", rhs=dict(kind="plane_wave_scattered", angles=[0.0]), discard_tol=tau)
+    c = W.leaf_centres(w)
+    w["eps_r"] = np.where((c ** 2).sum(1) < 0.16, 2.25, 1.0)
+    return w
+
+
 CASES = {
     "h3_p4_l1": hanging(3, (4, 4), 0, 1),
     "h3_p3to6_l2": hanging(3, (3, 6), 1, 2),
     "h4_p2to5_l3": hanging(4, (2, 5), 2, 3),
     "h3_p3to7_l7": hanging(3, (3, 7), 3, 7),
     "h4_p4to6_l2_lens": hanging(4, (4, 6), 5, 2, k=9.0, rhs="plane_wave_scattered"),
+    "h3_p3to6_l2_tau": dict(hanging(3, (3, 6), 1, 2), discard_tol=1e-2),
+    "h4_p2to5_l3_tau": dict(hanging(4, (2, 5), 2, 3), discard_tol=3e-3),
+    "disk_6x6_p3to6": small_disk(),
 }
 
 
@@ -50,7 +66,7 @@ def literal():
     out = {}
     for name, w in CASES.items():
         disc = pb.Discretisation(w)
-        out[name] = (disc, dp.LiteralDP(disc, w["l"]))
+        out[name] = (disc, dp.LiteralDP(disc, pb.coarse_order(w, disc.mesh)))
     return out
 
 
@@ -98,19 +114,46 @@ def test_solve_fp64_matches_literal_and_direct(name, literal):
     assert st["converged"]
     assert rel(gpu, ref) < 1e-10
     assert abs(st["iterations"] - D.iters) <= 1
-    exact = np.concatenate(pb.gll_field(disc.mesh, disc.degrees, direct.conforming_solution(disc)))
-    assert rel(gpu, exact) < 1e-9
+    if w.get("discard_tol", 0.0) == 0.0:
+        # every constraint kept: the conforming Galerkin solution
+        exact = np.concatenate(pb.gll_field(disc.mesh, disc.degrees, direct.conforming_solution(disc)))
+        assert rel(gpu, exact) < 1e-9
+    # the stopping test is the preconditioned residual (1e-12 here); the true
+    # interface residual is larger by up to the conditioning of P on the
+    # decayed hanging-edge rows (6e-9 and 2e-7 seen with every constraint
+    # kept) while the field still matches to 1e-10
+    assert st["true_residual"] < 1e-5
     s.close()
 
 
-@pytest.mark.parametrize("name", ["h3_p3to6_l2", "h4_p4to6_l2_lens"])
+@pytest.mark.parametrize("name", ["h3_p3to6_l2", "h4_p4to6_l2_lens", "disk_6x6_p3to6"])
 def test_mixed_precision_solve(name, literal):
     disc, D = literal[name]
     w = CASES[name]
     s = hdp().Solver(w, precision="mixed", tol=1e-12, max_iter=400)
     kind, vals = hdp().rhs_values(w)
     field, st = s.solve(kind, vals)
-    exact = np.concatenate(pb.gll_field(disc.mesh, disc.degrees, direct.conforming_solution(disc)))
+    if w.get("discard_tol", 0.0) == 0.0:
+        ref = np.concatenate(pb.gll_field(disc.mesh, disc.degrees, direct.conforming_solution(disc)))
+    else:
+        ref = np.concatenate(pb.gll_field(disc.mesh, disc.degrees, D.recover(D.direct_interface())))
     assert st["converged"] and st["refinements"] >= 1
-    assert rel(field.cpu().numpy()[0], exact) < 1e-8
+    assert rel(field.cpu().numpy()[0], ref) < 1e-8
     s.close()
+
+
+def test_refined_disk_full_size():
+    """The 712-leaf refined disk (p 8..24, k = 200, l = 14): too large for the
+    oracle, so checked by properties that hold at any size: both paths reach
+    the tolerance in the true interface residual as well, and agree."""
+    w = W.refined_disk()
+    st0 = hdp().inspect(w)
+    fields = {}
+    for prec in ("fp64", "mixed"):
+        s = hdp().Solver(w, precision=prec, tol=1e-8, max_iter=400)
+        assert (s.n_lambda, s.n_coarse, s.info["l"]) == (st0["n_lambda"], st0["n_coarse"], st0["l"])
+        f, st = s.solve("plane_wave_scattered", [0.0])
+        assert st["converged"] and st["true_residual"] < 1e-6
+        fields[prec] = f.cpu().numpy()[0]
+        s.close()
+    assert rel(fields["mixed"], fields["fp64"]) < 1e-6

@@ -127,6 +127,9 @@ def refined_disk(seed=0):
     c = leaf_centres(w)
     w["eps_r"] = np.where((c ** 2).sum(1) < 0.16, 2.25, 1.0)
     w["rhs"] = dict(kind="plane_wave_scattered", angles=[0.0])
+    # dual constraints on hanging edges whose change-of-basis diagonal a^k has
+    # decayed below 1e-3 are dropped (the threshold is left to the user)
+    w["discard_tol"] = 1e-3
     return w
 
 
