@@ -157,6 +157,33 @@ def batched_scatterer(hdp, torch, steps, warmup):
     return out
 
 
+def refined_disk(hdp, torch, steps, warmup):
+    """The non-conforming workload: [-1,1]^2 from a 16x16 base, leaves with centre
+    in r < 0.4 split twice (up to three hanging nodes per edge), p ~ U{8..24},
+    k = 200, eps_r = 2.25 in the disk, one plane wave, FP64 and mixed paths."""
+    import workloads as W
+    w = W.refined_disk()
+    out = {"workload": "refined_disk_16x16_2levels_p8to24_k200", "discard_tol": w["discard_tol"]}
+    for prec in ("fp64", "mixed"):
+        s = hdp.Solver(w, precision=prec, tol=1e-8, max_iter=400)
+        for _ in range(max(1, warmup)):
+            s.solve("plane_wave_scattered", [0.0])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, st = s.solve("plane_wave_scattered", [0.0])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        out[prec] = dict(ms_per_solve=ms, dof_per_s=s.dof / (ms * 1e-3), iterations=st["iterations"],
+                         refinements=st["refinements"], rel_residual=st["rel_residual"],
+                         true_residual=st["true_residual"], converged=st["converged"], setup_ms=s.info["setup_ms"])
+        out.update(dof=s.dof, elements=s.info["n_elements"], l=s.info["l"], n_lambda=s.info["n_lambda"],
+                   n_coarse=s.info["n_coarse"], classes=s.info["n_classes"])
+        s.close()
+        print(f"bench: refined disk {prec} done ({ms:.1f} ms per solve)", file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline():
     """The oracle as it stands on a bounded sample of the same workload."""
     import numpy as np
@@ -231,6 +258,7 @@ def main():
     line["roofline"]["launches_per_step"] = next(
         k["launches"] for k in best["kernels"] if k["name"] == line["roofline"]["kernel"]) / args.steps
     if not args.no_batched:
+        line["nonconforming"] = refined_disk(hdp, torch, max(1, min(args.steps, 5)), min(args.warmup, 1))
         line["batched_rhs"] = batched_scatterer(hdp, torch, max(1, min(args.steps, 3)), min(args.warmup, 1))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()

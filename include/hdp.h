@@ -108,6 +108,10 @@ typedef struct {
 /* hdp_options.flags: replay each GMRES iteration as a captured HIP graph
  * instead of launching its kernels one by one. */
 #define HDP_FLAG_GRAPH 1
+/* coarse factor: by default a dense inverse up to 12,000 coarse unknowns and the
+   block-tridiagonal strip factor above; these flags force one of them */
+#define HDP_FLAG_COARSE_BLOCK 2
+#define HDP_FLAG_COARSE_DENSE 4
 
 typedef struct {
   int32_t kind;               /* HDP_RHS_* */
@@ -128,6 +132,9 @@ typedef struct {
    * GMRES (launch calls, waits for the device), recovery and sampling */
   double rhs_ms, gmres_ms, gmres_launch_ms, gmres_wait_ms, recover_ms;
   double true_residual;       /* ||g - F nu|| / ||g|| in FP64 after the solve, max over RHS */
+  double coarse_residual;     /* setup check of the coarse factor: ||K x - b|| / ||b|| */
+  int32_t coarse_mode;        /* 0 dense inverse, 1 block-tridiagonal strips */
+  int32_t coarse_blocks;      /* number of strips (1 for the dense inverse) */
 } hdp_stats;
 
 typedef struct hdp_handle hdp_handle;

@@ -55,7 +55,8 @@ class Stats(ctypes.Structure):
                 ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double), ("rhs_ms", ctypes.c_double),
                 ("gmres_ms", ctypes.c_double), ("gmres_launch_ms", ctypes.c_double),
                 ("gmres_wait_ms", ctypes.c_double), ("recover_ms", ctypes.c_double),
-                ("true_residual", ctypes.c_double)]
+                ("true_residual", ctypes.c_double), ("coarse_residual", ctypes.c_double),
+                ("coarse_mode", ctypes.c_int32), ("coarse_blocks", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -149,7 +150,7 @@ class Solver:
     """
 
     def __init__(self, w, precision="fp64", tol=1e-8, max_iter=300, max_rhs=1, l_safety=0, device=0,
-                 graphs=False):
+                 graphs=False, coarse="auto"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("hdp needs a ROCm GPU (torch.cuda.is_available() is False)")
@@ -160,8 +161,8 @@ class Solver:
         self.precision = HDP_MIXED if precision == "mixed" else HDP_FP64
         with torch.cuda.device(self.device):
             stream = torch.cuda.current_stream(self.device).cuda_stream
-            opt = _Options(self.precision, float(tol), int(max_iter), int(max_rhs), ctypes.c_void_p(stream),
-                           1 if graphs else 0)
+            flags = (1 if graphs else 0) | {"auto": 0, "block": 2, "dense": 4}[coarse]
+            opt = _Options(self.precision, float(tol), int(max_iter), int(max_rhs), ctypes.c_void_p(stream), flags)
             h = ctypes.c_void_p()
             _check(L.hdp_setup(ctypes.byref(mesh), ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(h)))
         self.h = h

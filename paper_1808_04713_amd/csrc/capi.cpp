@@ -105,6 +105,217 @@ void check_hip(hipError_t e, const char* what) {
   if (e != hipSuccess) fail(HDP_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Dense coarse inverse K^-1 (rocSOLVER getrf + getri), row-major n_K x n_K.
+static void build_coarse_dense(Handle& h, const std::vector<int64_t>& kidx, const std::vector<double2>& kval) {
+  auto& d = h.d;
+  size_t nK = size_t(h.nK);
+  // the dense coarse inverse is addressed with 32-bit sizes by the factorisation
+  // routines: refuse coarse spaces whose square does not fit that range
+  if (int64_t(h.nK) * int64_t(h.nK) >= (int64_t(1) << 31))
+    fail(HDP_E_UNSUPPORTED, "coarse space too large for the dense coarse inverse (n_K = " +
+                                std::to_string(h.nK) + ", n_K^2 >= 2^31)");
+  d.Kinv = dalloc<double2>(h, nK * nK);
+  HIPCHECK(hipMemsetAsync(d.Kinv, 0, nK * nK * sizeof(double2), h.stream));
+  int64_t* didx = upload(h, kidx);
+  double2* dval = upload(h, kval);
+  launch_dense_scatter(didx, dval, int64_t(kidx.size()), d.Kinv, h.stream);
+  rocblas_handle rb = static_cast<rocblas_handle>(h.rocblas);
+  int* ipiv = dalloc<int>(h, nK);
+  int* info = dalloc<int>(h, 1);
+  rocblas_status st = rocsolver_zgetrf(rb, h.nK, h.nK, (rocblas_double_complex*)d.Kinv, h.nK, ipiv, info);
+  int hinfo = 0;
+  if (st == rocblas_status_success) {
+    HIPCHECK(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, h.stream));
+    HIPCHECK(hipStreamSynchronize(h.stream));
+  }
+  if (st == rocblas_status_success && hinfo == 0)
+    st = rocsolver_zgetri(rb, h.nK, (rocblas_double_complex*)d.Kinv, h.nK, ipiv, info);
+  if (st == rocblas_status_success && hinfo == 0) {
+    HIPCHECK(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, h.stream));
+    HIPCHECK(hipStreamSynchronize(h.stream));
+  }
+  if (st != rocblas_status_success) fail(HDP_E_DEVICE, "rocsolver failed on the coarse matrix");
+  if (hinfo != 0) fail(HDP_E_COARSE, "coarse matrix K is singular");
+  h.coarse_mode = 0;
+  h.coarse_bytes = 16.0 * double(nK) * double(nK);
+  h.coarse_flops = 8.0 * double(nK) * double(nK);
+}
+
+static void zgemm(Handle& h, rocblas_operation tb, int m, int n, int k, double alpha, const double2* A, int lda,
+                  const double2* B, int ldb, double beta, double2* C, int ldc) {
+  rocblas_double_complex a(alpha, 0.0), b(beta, 0.0);
+  rocblas_status st = rocblas_zgemm(static_cast<rocblas_handle>(h.rocblas), rocblas_operation_none, tb, m, n, k, &a,
+                                    reinterpret_cast<const rocblas_double_complex*>(A), lda,
+                                    reinterpret_cast<const rocblas_double_complex*>(B), ldb, &b,
+                                    reinterpret_cast<rocblas_double_complex*>(C), ldc);
+  if (st != rocblas_status_success) fail(HDP_E_DEVICE, "rocblas_zgemm failed");
+}
+
+static void zgemv(Handle& h, int m, int n, double alpha, const double2* A, int lda, const double2* x, double beta,
+                  double2* y) {
+  rocblas_double_complex a(alpha, 0.0), b(beta, 0.0);
+  rocblas_status st = rocblas_zgemv(static_cast<rocblas_handle>(h.rocblas), rocblas_operation_none, m, n, &a,
+                                    reinterpret_cast<const rocblas_double_complex*>(A), lda,
+                                    reinterpret_cast<const rocblas_double_complex*>(x), 1, &b,
+                                    reinterpret_cast<rocblas_double_complex*>(y), 1);
+  if (st != rocblas_status_success) fail(HDP_E_DEVICE, "rocblas_zgemv failed");
+}
+
+// out (cols x rows, column-major) = in^T, in rows x cols column-major
+static void transpose_into(Handle& h, const double2* in, int rows, int cols, double2* out) {
+  rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+  rocblas_status st = rocblas_zgeam(static_cast<rocblas_handle>(h.rocblas), rocblas_operation_transpose,
+                                    rocblas_operation_none, cols, rows, &one,
+                                    reinterpret_cast<const rocblas_double_complex*>(in), rows, &zero,
+                                    reinterpret_cast<const rocblas_double_complex*>(out), cols,
+                                    reinterpret_cast<rocblas_double_complex*>(out), cols);
+  if (st != rocblas_status_success) fail(HDP_E_DEVICE, "rocblas_zgeam failed");
+}
+
+// a rows x cols block transposed in its own storage (through the scratch buffer)
+static void transpose_into_inplace(Handle& h, double2* a, int rows, int cols) {
+  HIPCHECK(hipMemcpyAsync(h.d.ctmp, a, size_t(rows) * cols * sizeof(double2), hipMemcpyDeviceToDevice, h.stream));
+  transpose_into(h, h.d.ctmp, rows, cols, a);
+}
+
+// Block-tridiagonal factor of K over the coarse strips (block LU, partial
+// pivoting inside each diagonal block): D_0 = K_00, D_i = K_ii - K_{i,i-1} U_{i-1};
+// stored D_i^-1 (symmetric, as K is), W_i^T and U_i^T with W_i = D_i^-1 K_{i,i-1}
+// and U_i = D_i^-1 K_{i,i+1} (column-major).
+static void build_coarse_blocks(Handle& h, const std::vector<int64_t>& kidx, const std::vector<double2>& kval) {
+  auto& d = h.d;
+  const int nb = int(h.cb_off.size()) - 1;
+  const int64_t nK = h.nK;
+  auto sz = [&](int b) { return (b < 0 || b >= nb) ? 0 : h.cb_off[b + 1] - h.cb_off[b]; };
+  std::vector<int> blk(h.nK);
+  for (int b = 0; b < nb; ++b)
+    for (int i = h.cb_off[b]; i < h.cb_off[b + 1]; ++i) blk[i] = b;
+  h.cb_D.assign(nb, 0); h.cb_W.assign(nb, 0); h.cb_U.assign(nb, 0);
+  int64_t tot = 0, tmpmax = 1;
+  int nmax = 1;
+  for (int b = 0; b < nb; ++b) {
+    int64_t n = sz(b);
+    h.cb_D[b] = tot; tot += n * n;
+    h.cb_W[b] = tot; tot += n * sz(b - 1);
+    h.cb_U[b] = tot; tot += n * sz(b + 1);
+    nmax = std::max(nmax, int(n));
+    tmpmax = std::max(tmpmax, n * std::max(sz(b - 1), sz(b + 1)));
+  }
+  std::vector<int64_t> bidx(kidx.size());
+  for (size_t t = 0; t < kidx.size(); ++t) {
+    int64_t i = kidx[t] % nK, j = kidx[t] / nK;
+    int bi = blk[i], bj = blk[j];
+    int64_t li = i - h.cb_off[bi], lj = j - h.cb_off[bj], n = sz(bi);
+    int64_t off;
+    if (bj == bi) off = h.cb_D[bi];
+    else if (bj == bi - 1) off = h.cb_W[bi];
+    else if (bj == bi + 1) off = h.cb_U[bi];
+    else fail(HDP_E_MESH, "coarse strips are not block tridiagonal");
+    bidx[t] = off + li + n * lj;
+  }
+  d.cblk = dalloc<double2>(h, size_t(tot));
+  d.ctmp = dalloc<double2>(h, size_t(tmpmax));
+  HIPCHECK(hipMemsetAsync(d.cblk, 0, size_t(tot) * sizeof(double2), h.stream));
+  int64_t* didx = upload(h, bidx);
+  double2* dval = upload(h, kval);
+  launch_dense_scatter(didx, dval, int64_t(bidx.size()), d.cblk, h.stream);
+  rocblas_handle rb = static_cast<rocblas_handle>(h.rocblas);
+  int* ipiv = dalloc<int>(h, size_t(nmax));
+  int* info = dalloc<int>(h, size_t(nb));
+  HIPCHECK(hipMemsetAsync(info, 0, size_t(nb) * sizeof(int), h.stream));
+  for (int b = 0; b < nb; ++b) {
+    const int n = sz(b), np = sz(b - 1), nn = sz(b + 1);
+    double2* Db = d.cblk + h.cb_D[b];
+    if (b > 0) zgemm(h, rocblas_operation_none, n, n, np, -1.0, d.cblk + h.cb_W[b], n, d.cblk + h.cb_U[b - 1], np, 1.0, Db, n);
+    if (rocsolver_zgetrf(rb, n, n, (rocblas_double_complex*)Db, n, ipiv, info + b) != rocblas_status_success ||
+        rocsolver_zgetri(rb, n, (rocblas_double_complex*)Db, n, ipiv, info + b) != rocblas_status_success)
+      fail(HDP_E_DEVICE, "rocsolver failed on a coarse block");
+    // W_b and U_b are kept transposed (np x n and nn x n) so that the sweeps are
+    // plain NN products on the [n_K][R] layout; U_b is needed untransposed by the
+    // next block's Schur complement first
+    if (np > 0) {
+      zgemm(h, rocblas_operation_none, n, np, n, 1.0, Db, n, d.cblk + h.cb_W[b], n, 0.0, d.ctmp, n);
+      transpose_into(h, d.ctmp, n, np, d.cblk + h.cb_W[b]);
+    }
+    if (b > 0) transpose_into_inplace(h, d.cblk + h.cb_U[b - 1], sz(b - 1), n);
+    if (nn > 0) {
+      zgemm(h, rocblas_operation_none, n, nn, n, 1.0, Db, n, d.cblk + h.cb_U[b], n, 0.0, d.ctmp, n);
+      HIPCHECK(hipMemcpyAsync(d.cblk + h.cb_U[b], d.ctmp, size_t(n) * nn * sizeof(double2), hipMemcpyDeviceToDevice,
+                              h.stream));
+    }
+  }
+  std::vector<int> hinfo(nb);
+  HIPCHECK(hipMemcpyAsync(hinfo.data(), info, size_t(nb) * sizeof(int), hipMemcpyDeviceToHost, h.stream));
+  HIPCHECK(hipStreamSynchronize(h.stream));
+  for (int b = 0; b < nb; ++b)
+    if (hinfo[b] != 0) fail(HDP_E_COARSE, "coarse Schur-complement block " + std::to_string(b) + " is singular");
+  h.coarse_mode = 1;
+  h.coarse_bytes = 16.0 * double(tot);
+  h.coarse_flops = 8.0 * double(tot);
+}
+
+static void zgemv_t(Handle& h, int m, int n, double alpha, const double2* A, int lda, const double2* x, double beta,
+                    double2* y) {
+  rocblas_double_complex a(alpha, 0.0), b(beta, 0.0);
+  rocblas_status st = rocblas_zgemv(static_cast<rocblas_handle>(h.rocblas), rocblas_operation_transpose, m, n, &a,
+                                    reinterpret_cast<const rocblas_double_complex*>(A), lda,
+                                    reinterpret_cast<const rocblas_double_complex*>(x), 1, &b,
+                                    reinterpret_cast<rocblas_double_complex*>(y), 1);
+  if (st != rocblas_status_success) fail(HDP_E_DEVICE, "rocblas_zgemv failed");
+}
+
+static void coarse_solve_blocks(Handle& h, const double2* g, double2* w, int R) {
+  auto& d = h.d;
+  const int nb = int(h.cb_off.size()) - 1;
+  auto sz = [&](int b) { return (b < 0 || b >= nb) ? 0 : h.cb_off[b + 1] - h.cb_off[b]; };
+  const rocblas_operation N = rocblas_operation_none;
+  // [n_K][R] row-major is the column-major R x n_K matrix: a block's rows are a
+  // contiguous R x n_b slice X_b, and D^-1 x becomes X_b D^-T = X_b D^-1
+  for (int b = 0; b < nb; ++b) {
+    const int64_t o = h.cb_off[b];
+    if (R == 1) zgemv(h, sz(b), sz(b), 1.0, d.cblk + h.cb_D[b], sz(b), g + o, 0.0, w + o);
+    else zgemm(h, N, R, sz(b), sz(b), 1.0, g + o * R, R, d.cblk + h.cb_D[b], sz(b), 0.0, w + o * R, R);
+  }
+  for (int b = 1; b < nb; ++b) {   // y_b -= W_b y_{b-1}: Y_b -= Y_{b-1} W_b^T
+    const int64_t o = h.cb_off[b], op = h.cb_off[b - 1];
+    if (R == 1) zgemv_t(h, sz(b - 1), sz(b), -1.0, d.cblk + h.cb_W[b], sz(b - 1), w + op, 1.0, w + o);
+    else zgemm(h, N, R, sz(b), sz(b - 1), -1.0, w + op * R, R, d.cblk + h.cb_W[b], sz(b - 1), 1.0, w + o * R, R);
+  }
+  for (int b = nb - 2; b >= 0; --b) {   // x_b = y_b - U_b x_{b+1}
+    const int64_t o = h.cb_off[b], on = h.cb_off[b + 1];
+    if (R == 1) zgemv_t(h, sz(b + 1), sz(b), -1.0, d.cblk + h.cb_U[b], sz(b + 1), w + on, 1.0, w + o);
+    else zgemm(h, N, R, sz(b), sz(b + 1), -1.0, w + on * R, R, d.cblk + h.cb_U[b], sz(b + 1), 1.0, w + o * R, R);
+  }
+}
+
+void coarse_solve(Handle& h, const double2* g, double2* w, int R);
+
+// ||K x - b|| / ||b|| for x from the coarse solve of a fixed pseudo-random b,
+// K applied on the host from its assembled entries.
+static double coarse_residual(Handle& h, const std::vector<int64_t>& kidx, const std::vector<double2>& kval) {
+  const int64_t nK = h.nK;
+  std::vector<double2> b(nK), x(nK);
+  uint64_t state = 0x9E3779B97F4A7C15ull;
+  auto next = [&]() {
+    state = state * 6364136223846793005ull + 1442695040888963407ull;
+    return double(state >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  };
+  for (auto& v : b) { v.x = next(); v.y = next(); }
+  HIPCHECK(hipMemcpyAsync(h.d.gK, b.data(), nK * sizeof(double2), hipMemcpyHostToDevice, h.stream));
+  coarse_solve(h, h.d.gK, h.d.wK, 1);
+  HIPCHECK(hipMemcpyAsync(x.data(), h.d.wK, nK * sizeof(double2), hipMemcpyDeviceToHost, h.stream));
+  HIPCHECK(hipStreamSynchronize(h.stream));
+  std::vector<cd> r(nK);
+  for (int64_t i = 0; i < nK; ++i) r[i] = -cd(b[i].x, b[i].y);
+  for (size_t t = 0; t < kidx.size(); ++t) {
+    int64_t i = kidx[t] % nK, j = kidx[t] / nK;
+    r[i] += cd(kval[t].x, kval[t].y) * cd(x[j].x, x[j].y);
+  }
+  double rn = 0, bn = 0;
+  for (int64_t i = 0; i < nK; ++i) { rn += std::norm(r[i]); bn += b[i].x * b[i].x + b[i].y * b[i].y; }
+  return std::sqrt(rn / bn);
+}
+
 void build_device(Handle& h) {
   auto& d = h.d;
   int E = h.E;
@@ -252,36 +463,15 @@ void build_device(Handle& h) {
     kval.push_back(make_double2(s.real(), s.imag()));
   }
   size_t nK = size_t(h.nK);
-  // the dense coarse inverse is addressed with 32-bit sizes by the factorisation
-  // routines: refuse coarse spaces whose square does not fit that range
-  if (int64_t(h.nK) * int64_t(h.nK) >= (int64_t(1) << 31))
-    fail(HDP_E_UNSUPPORTED, "coarse space too large for the dense coarse inverse (n_K = " +
-                                std::to_string(h.nK) + ", n_K^2 >= 2^31)");
-  d.Kinv = dalloc<double2>(h, nK * nK);
-  HIPCHECK(hipMemsetAsync(d.Kinv, 0, nK * nK * sizeof(double2), h.stream));
-  int64_t* didx = upload(h, kidx);
-  double2* dval = upload(h, kval);
-  launch_dense_scatter(didx, dval, int64_t(kidx.size()), d.Kinv, h.stream);
   rocblas_handle rb;
   if (rocblas_create_handle(&rb) != rocblas_status_success) fail(HDP_E_DEVICE, "rocblas_create_handle");
   rocblas_set_stream(rb, h.stream);
-  int* ipiv = dalloc<int>(h, nK);
-  int* info = dalloc<int>(h, 1);
-  rocblas_status st = rocsolver_zgetrf(rb, h.nK, h.nK, (rocblas_double_complex*)d.Kinv, h.nK, ipiv, info);
-  int hinfo = 0;
-  if (st == rocblas_status_success) {
-    HIPCHECK(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, h.stream));
-    HIPCHECK(hipStreamSynchronize(h.stream));
-  }
-  if (st == rocblas_status_success && hinfo == 0)
-    st = rocsolver_zgetri(rb, h.nK, (rocblas_double_complex*)d.Kinv, h.nK, ipiv, info);
-  if (st == rocblas_status_success && hinfo == 0) {
-    HIPCHECK(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, h.stream));
-    HIPCHECK(hipStreamSynchronize(h.stream));
-  }
-  h.rocblas = rb;   // kept for the batched coarse solve
-  if (st != rocblas_status_success) fail(HDP_E_DEVICE, "rocsolver failed on the coarse matrix");
-  if (hinfo != 0) fail(HDP_E_COARSE, "coarse matrix K is singular");
+  h.rocblas = rb;   // kept for the coarse solves
+  // dense inverse for small coarse spaces (one streaming GEMV per solve), the
+  // block-tridiagonal strip factor beyond 12,000 unknowns
+  if (h.coarse_mode < 0) h.coarse_mode = h.nK > 12000 ? 1 : 0;
+  if (h.coarse_mode == 1) build_coarse_blocks(h, kidx, kval);
+  else build_coarse_dense(h, kidx, kval);
   // work buffers sized for the largest RHS batch (padded to a power of two)
   size_t Rp = size_t(pow2ceil(h.max_rhs));
   size_t nl = size_t(h.nlam);
@@ -324,6 +514,14 @@ void build_device(Handle& h) {
   d.status_host = static_cast<int*>(ph);
   d.nrm = dalloc<double>(h, Rp);
   d.ycoef = dalloc<double2>(h, (size_t(h.max_iter) + 1) * Rp);
+  // a gross failure of the factor (an unstable pivot sequence) shows here; a
+  // residual at the level of cond(K) * eps is reported in the stats
+  h.coarse_check = coarse_residual(h, kidx, kval);
+  if (!(h.coarse_check < 1e-6)) {
+    char msg[96];
+    std::snprintf(msg, sizeof msg, "coarse factor inaccurate (relative residual %.3e)", h.coarse_check);
+    fail(HDP_E_COARSE, msg);
+  }
   if (h.nh > 0) d.hb_tmp = dalloc<double2>(h, size_t(h.nh) * Rp);
   if (h.nonconforming) {
     d.fv = dalloc<double2>(h, nl * Rp);
@@ -337,6 +535,10 @@ void build_device(Handle& h) {
 // w = K^-1 g for R right-hand sides ([n_K][R]): a streaming GEMV kernel for a
 // few columns, a plain library GEMM (rocBLAS zgemm) once R makes it compute-bound.
 void coarse_solve(Handle& h, const double2* g, double2* w, int R) {
+  if (h.coarse_mode == 1) {
+    coarse_solve_blocks(h, g, w, R);
+    return;
+  }
   if (R < 4) {
     launch_coarse_solve(h, g, w, R, h.stream);
     return;
@@ -375,7 +577,7 @@ static void apply_F_slots(Handle& h, const double2* v, int R, int prec) {
     else launch_assemble<float2>(h, d.cmA_f, nullptr, v, 1.0, d.gK, R, s);
   }
   {
-    Timed t(h, KF_COARSE, nK * nK * 16.0 + 2 * nK * c, 8.0 * nK * nK * R);
+    Timed t(h, KF_COARSE, h.coarse_bytes + 2 * nK * c, h.coarse_flops * R);
     coarse_solve(h, d.gK, d.wK, R);
   }
   {
@@ -486,7 +688,7 @@ void element_solve(Handle& h, double2* X, const double2* Bfull, const double2* n
     launch_assemble<double2>(h, d.cmA, Bfull, nu, -1.0, d.gK, R, s);
   }
   {
-    Timed t(h, KF_COARSE, nK * nK * 16.0 + 2 * nK * c, 8.0 * nK * nK * R);
+    Timed t(h, KF_COARSE, h.coarse_bytes + 2 * nK * c, h.coarse_flops * R);
     coarse_solve(h, d.gK, d.wK, R);
   }
   {
@@ -565,7 +767,8 @@ GmresResult gmres(Handle& h, const double2* rhs, double2* x, int R, int prec, do
     };
     // one GMRES iteration as a captured graph (every launch reads j on the device)
     hipGraphExec_t exec = nullptr;
-    const bool graph = h.use_graphs && !h.prof.on;
+    // captured only when no library routine is in the loop (dense GEMV coarse solve)
+    const bool graph = h.use_graphs && !h.prof.on && h.coarse_mode == 0 && R < 4;
     if (graph) {
       auto key = std::make_tuple(R, prec, tol);
       auto itg = h.graphs.find(key);
@@ -762,6 +965,9 @@ hdp_status hdp_setup(const hdp_mesh* mesh, const hdp_problem* prob, const hdp_op
   h.precision = opt->precision;
   h.user_stream = static_cast<hipStream_t>(opt->stream);
   h.use_graphs = (opt->flags & HDP_FLAG_GRAPH) != 0;
+  if ((opt->flags & HDP_FLAG_COARSE_BLOCK) && (opt->flags & HDP_FLAG_COARSE_DENSE))
+    fail(HDP_E_ARG, "HDP_FLAG_COARSE_BLOCK and HDP_FLAG_COARSE_DENSE are exclusive");
+  h.coarse_mode = (opt->flags & HDP_FLAG_COARSE_BLOCK) ? 1 : (opt->flags & HDP_FLAG_COARSE_DENSE) ? 0 : -1;
   try {
     // a stream of the handle's own (default priority): capturable, unlike the null stream
     HIPCHECK(hipStreamCreateWithFlags(&h.stream, hipStreamNonBlocking));
@@ -808,6 +1014,9 @@ hdp_status hdp_get_stats(const hdp_handle* H, hdp_stats* st) {
   st->n_classes = int(h.classes.size());
   st->min_element_margin = h.min_margin;
   st->setup_ms = h.setup_ms;
+  st->coarse_residual = h.coarse_check;
+  st->coarse_mode = h.coarse_mode >= 0 ? h.coarse_mode : (h.nK > 12000 ? 1 : 0);
+  st->coarse_blocks = st->coarse_mode == 1 ? int(h.cb_off.size()) - 1 : 1;
   return HDP_OK;
   API_END
 }

@@ -112,6 +112,15 @@ struct Handle {
   std::vector<int> cdof_ptr, cdof_list;  // transpose: coarse unknown -> coarse modes
   std::vector<double> cdof_coef;
   std::vector<int> cm_mode;       // per coarse mode, local mode index
+  std::vector<double> dof_y;      // per coarse unknown: y of its vertex or edge midpoint
+  // coarse factor: 0 dense inverse of K, 1 block-tridiagonal factor over the
+  // strips cb_off (consecutive coarse unknowns); per block i the inverse D_i^-1
+  // of the Schur-complement block and W_i = D_i^-1 K_{i,i-1}, U_i = D_i^-1 K_{i,i+1}
+  int coarse_mode = -1;            // -1: chosen by size at setup
+  std::vector<int> cb_off;
+  std::vector<int64_t> cb_D, cb_W, cb_U;
+  double coarse_check = 0;         // relative residual of the coarse factor on a test vector
+  double coarse_bytes = 0, coarse_flops = 0;   // per coarse solve and RHS column (flops), factor bytes
   // C_2 (dual rows x coarse unknowns), non-zero only on hanging edges
   std::vector<int> c2_ptr, c2_dof, c2t_ptr, c2t_row;
   std::vector<double> c2_coef, c2t_coef;
@@ -148,6 +157,7 @@ struct Handle {
     int64_t* hb_moff = nullptr;
     double *hb_xinv = nullptr, *hb_y2 = nullptr;
     double2 *hb_tmp = nullptr, *fv = nullptr, *pv = nullptr;
+    double2 *cblk = nullptr, *ctmp = nullptr;   // block-tridiagonal coarse factor
     // per-class tables
     int *cls_n = nullptr, *cls_m = nullptr, *cls_nr = nullptr;
     int64_t *cls_op1 = nullptr, *cls_phi = nullptr, *cls_se = nullptr;   // offsets

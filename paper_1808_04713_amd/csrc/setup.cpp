@@ -235,6 +235,96 @@ void build_class(ElemClass& C, double k) {
   }
 }
 
+// Coarse unknown -> coarse modes (transpose of T) and, with c2, the transpose of C_2.
+void build_transposes(Handle& h, bool c2) {
+  h.cdof_ptr.assign(h.nK + 1, 0);
+  for (int d : h.t_dof) h.cdof_ptr[d + 1]++;
+  for (int i = 0; i < h.nK; ++i) h.cdof_ptr[i + 1] += h.cdof_ptr[i];
+  h.cdof_list.assign(h.t_dof.size(), 0);
+  h.cdof_coef.assign(h.t_dof.size(), 0.0);
+  {
+    std::vector<int> fill(h.cdof_ptr.begin(), h.cdof_ptr.end() - 1);
+    for (int i = 0; i < h.ncm; ++i)
+      for (int t = h.t_ptr[i]; t < h.t_ptr[i + 1]; ++t) {
+        int d = h.t_dof[t], at = fill[d]++;
+        h.cdof_list[at] = i;
+        h.cdof_coef[at] = h.t_coef[t];
+      }
+  }
+  if (!c2) return;
+  h.c2t_ptr.assign(h.nK + 1, 0);
+  for (int d : h.c2_dof) h.c2t_ptr[d + 1]++;
+  for (int i = 0; i < h.nK; ++i) h.c2t_ptr[i + 1] += h.c2t_ptr[i];
+  h.c2t_row.assign(h.c2_dof.size(), 0);
+  h.c2t_coef.assign(h.c2_dof.size(), 0.0);
+  std::vector<int> fill(h.c2t_ptr.begin(), h.c2t_ptr.end() - 1);
+  for (int r = 0; r < h.nlam; ++r)
+    for (int t = h.c2_ptr[r]; t < h.c2_ptr[r + 1]; ++t) {
+      int at = fill[h.c2_dof[t]]++;
+      h.c2t_row[at] = r;
+      h.c2t_coef[at] = h.c2_coef[t];
+    }
+}
+
+// Renumber the coarse unknowns strip by strip: breadth-first level sets of the
+// coupling graph of K (unknowns sharing an element), started from the
+// unknowns of smallest y.  Level sets only couple to their two neighbours, so
+// K is block tridiagonal over consecutive levels; levels are merged into
+// blocks of at least 256 unknowns (32 when the block factor is forced).
+void order_coarse_strips(Handle& h) {
+  const int nK = h.nK, E = h.E;
+  std::vector<std::vector<int>> elem_dofs(E);
+  for (int e = 0; e < E; ++e) {
+    auto& v = elem_dofs[e];
+    for (int i = h.cm_off[e]; i < h.cm_off[e + 1]; ++i)
+      for (int t = h.t_ptr[i]; t < h.t_ptr[i + 1]; ++t) v.push_back(h.t_dof[t]);
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+  }
+  std::vector<std::vector<int>> dof_elems(nK);
+  for (int e = 0; e < E; ++e)
+    for (int d : elem_dofs[e]) dof_elems[d].push_back(e);
+  std::vector<int> lev(nK, -1), front;
+  double ymin = 1e300;
+  for (int d = 0; d < nK; ++d) ymin = std::min(ymin, h.dof_y[d]);
+  for (int d = 0; d < nK; ++d)
+    if (h.dof_y[d] == ymin) { lev[d] = 0; front.push_back(d); }
+  std::vector<std::vector<int>> levels{front};
+  while (!front.empty()) {
+    std::vector<int> next;
+    for (int d : front)
+      for (int e : dof_elems[d])
+        for (int o : elem_dofs[e])
+          if (lev[o] < 0) { lev[o] = int(levels.size()); next.push_back(o); }
+    if (!next.empty()) levels.push_back(next);
+    front.swap(next);
+  }
+  for (int d = 0; d < nK; ++d)
+    if (lev[d] < 0) fail(HDP_E_MESH, "coarse space not connected");
+  // strips of at least 256 unknowns; 32 when the block factor is requested
+  // explicitly (so that small meshes get several strips too)
+  const int bmin = h.coarse_mode == 1 ? 32 : 256;
+  std::vector<int> perm(nK);   // old -> new
+  h.cb_off.assign(1, 0);
+  int pos = 0, in_block = 0;
+  for (size_t L = 0; L < levels.size(); ++L) {
+    std::vector<int> lv = levels[L];
+    std::sort(lv.begin(), lv.end());
+    for (int d : lv) perm[d] = pos++;
+    in_block += int(lv.size());
+    if (in_block >= bmin || L + 1 == levels.size()) {
+      h.cb_off.push_back(pos);
+      in_block = 0;
+    }
+  }
+  for (auto& d : h.t_dof) d = perm[d];
+  for (auto& d : h.c2_dof) d = perm[d];
+  std::vector<double> y(nK);
+  for (int d = 0; d < nK; ++d) y[perm[d]] = h.dof_y[d];
+  h.dof_y.swap(y);
+  build_transposes(h, true);
+}
+
 // Preconditioner blocks on the dual rows that C_2 touches (hanging edges).
 // The literal nullspace basis of Sec. 2.3.2 projects each kept unknown onto
 // null(C_p) orthogonally; in terms of the expansions T used here (kept
@@ -632,20 +722,18 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
     }
   }
   h.nK = int(cids.size());
-  h.cdof_ptr.assign(h.nK + 1, 0);
-  for (int d : h.t_dof) h.cdof_ptr[d + 1]++;
-  for (int i = 0; i < h.nK; ++i) h.cdof_ptr[i + 1] += h.cdof_ptr[i];
-  h.cdof_list.assign(h.t_dof.size(), 0);
-  h.cdof_coef.assign(h.t_dof.size(), 0.0);
-  {
-    std::vector<int> fill(h.cdof_ptr.begin(), h.cdof_ptr.end() - 1);
-    for (int i = 0; i < h.ncm; ++i)
-      for (int t = h.t_ptr[i]; t < h.t_ptr[i + 1]; ++t) {
-        int d = h.t_dof[t], at = fill[d]++;
-        h.cdof_list[at] = i;
-        h.cdof_coef[at] = h.t_coef[t];
-      }
+  // position of each coarse unknown across the mesh (vertex, or edge midpoint) in
+  // fine-grid units: orders the coarse unknowns into strips for the coarse factor
+  h.dof_y.assign(h.nK, 0.0);
+  for (auto& kv : cids) {
+    const auto& key = kv.first;
+    int kind = std::get<0>(key);
+    double y = kind == -1 ? double(std::get<2>(key))
+               : kind == 0 ? 0.5 * double(std::get<2>(key) + std::get<3>(key))
+                           : double(std::get<1>(key));
+    h.dof_y[kv.second] = y;
   }
+  build_transposes(h, false);
   // ---- dual rows in Algorithm 1 visiting order -----------------------------
   std::vector<int> vorder(E);
   for (int e = 0; e < E; ++e) vorder[e] = e;
@@ -713,22 +801,9 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
       if (h.slot_row[h.slot_off[e] + g] < 0) fail(HDP_E_MESH, "dual slot without a row");
     }
   }
-  // transpose of C_2
-  h.c2t_ptr.assign(h.nK + 1, 0);
-  for (int d : h.c2_dof) h.c2t_ptr[d + 1]++;
-  for (int i = 0; i < h.nK; ++i) h.c2t_ptr[i + 1] += h.c2t_ptr[i];
-  h.c2t_row.assign(h.c2_dof.size(), 0);
-  h.c2t_coef.assign(h.c2_dof.size(), 0.0);
-  {
-    std::vector<int> fill(h.c2t_ptr.begin(), h.c2t_ptr.end() - 1);
-    for (int r = 0; r < h.nlam; ++r)
-      for (int t = h.c2_ptr[r]; t < h.c2_ptr[r + 1]; ++t) {
-        int at = fill[h.c2_dof[t]]++;
-        h.c2t_row[at] = r;
-        h.c2t_coef[at] = h.c2_coef[t];
-      }
-  }
+  build_transposes(h, true);
   build_hanging_blocks(h);
+  order_coarse_strips(h);
   // algorithmic work counts
   for (auto& C : h.classes) {
     h.op1_bytes += 16.0 * (C.m + C.nr) * C.m;

@@ -157,3 +157,22 @@ def test_refined_disk_full_size():
         fields[prec] = f.cpu().numpy()[0]
         s.close()
     assert rel(fields["mixed"], fields["fp64"]) < 1e-6
+
+
+@pytest.mark.parametrize("name", ["h4_p2to5_l3", "disk_6x6_p3to6"])
+def test_block_coarse_factor_on_hanging_meshes(name, literal):
+    """Strip (block-tridiagonal) coarse factor on quadtree meshes: same F and field."""
+    disc, D = literal[name]
+    w = CASES[name]
+    s = hdp().Solver(w, tol=1e-12, max_iter=400, max_rhs=2, coarse="block")
+    assert s.info["coarse_mode"] == 1 and s.info["coarse_blocks"] >= 2 and s.info["coarse_residual"] < 1e-11
+    rng = np.random.default_rng(9)
+    v = rng.standard_normal((s.n_lambda, 2)) + 1j * rng.standard_normal((s.n_lambda, 2))
+    Fv = s.apply_interface(torch.from_numpy(v).cuda(), "fp64").cpu().numpy()
+    for r in range(2):
+        assert rel(Fv[:, r], D.F @ v[:, r]) < 1e-12
+    kind, vals = hdp().rhs_values(w)
+    field, st = s.solve(kind, vals)
+    ref = np.concatenate(pb.gll_field(disc.mesh, disc.degrees, D.solve(tol=1e-12, max_iter=400)))
+    assert rel(field.cpu().numpy()[0], ref) < 1e-10
+    s.close()

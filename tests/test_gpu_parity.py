@@ -195,6 +195,31 @@ def test_batched_rhs_equal_single_solves():
     s.close()
 
 
+@pytest.mark.parametrize("name", ["uniform_5x5_p7_l3", "scatterer_6x6_p6"])
+def test_block_tridiagonal_coarse_factor(name, oracles):
+    """The strip (block-tridiagonal) coarse factor gives the same operator and
+    solution as the dense inverse, for one and for several right-hand sides."""
+    disc, l, E = oracles[name]
+    w = CASES[name]
+    sb = hdp().Solver(w, tol=1e-12, max_iter=400, max_rhs=5, coarse="block")
+    sd = hdp().Solver(w, tol=1e-12, max_iter=400, max_rhs=5, coarse="dense")
+    st = sb.info
+    assert st["coarse_mode"] == 1 and st["coarse_blocks"] >= 2 and st["coarse_residual"] < 1e-12
+    assert sd.info["coarse_mode"] == 0
+    rng = np.random.default_rng(5)
+    for R in (1, 5):
+        v = rng.standard_normal((E.nlam, R)) + 1j * rng.standard_normal((E.nlam, R))
+        vd = torch.from_numpy(v).cuda()
+        assert rel(sb.apply_interface(vd, "fp64").cpu().numpy(), sd.apply_interface(vd, "fp64").cpu().numpy()) < 1e-12
+    kind, vals = hdp().rhs_values(w)
+    fb, stb = sb.solve(kind, vals)
+    phis = E.solve(tol=1e-12, max_iter=400)
+    ref = np.concatenate(pb.gll_field(disc.mesh, disc.degrees, phis))
+    assert rel(fb.cpu().numpy()[0], ref) < 1e-10
+    sb.close()
+    sd.close()
+
+
 def test_point_source_32x32_against_stored_oracle_samples():
     """Full-size workload: sampled field values, F v and P^-1 v rows written by
     tests/golden/make_point_source_32x32.py from the oracle."""
