@@ -28,7 +28,11 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 HBM_FAMILIES = {"coarse_gemv", "coarse_assemble", "row_gather", "gmres_dots", "gmres_update",
-                "gmres_norm_scale", "element_coarse_fix", "precision_cast"}
+                "gmres_norm_scale", "element_coarse_fix", "precision_cast", "hanging_blocks"}
+# HBM bytes per launch of a kernel family on the point-source workload, from the
+# rocprofv3 FETCH_SIZE / WRITE_SIZE runs calibrated on a plain 512 MiB copy
+# (profiles/point_source_32x32_kernel_stats.md); valid for the kernels as profiled
+MEASURED_TRAFFIC = {"gmres_dots": 2.5627e7, "coarse_gemv": 1.6479e8}
 
 
 def load_samples():
@@ -78,9 +82,9 @@ def time_path(hdp, torch, w, precision, steps, warmup, samples):
     return out, info
 
 
-def roofline(kernels, precision):
+def roofline(kernels, precision, name=None):
     live = [k for k in kernels if k["launches"] > 0]
-    dom = max(live, key=lambda k: k["total_ms"])
+    dom = max(live, key=lambda k: k["total_ms"]) if name is None else next(k for k in live if k["name"] == name)
     avg_ms = dom["total_ms"] / dom["launches"]
     bytes_per = dom["bytes"] / dom["launches"]
     flops_per = dom["flops"] / dom["launches"]
@@ -93,7 +97,7 @@ def roofline(kernels, precision):
     else:
         achieved = flops_per / (avg_ms * 1e-3) / 1e12
         r = dict(bound="alu", achieved=achieved, peak=peak_tf, unit="TFLOP/s")
-    r.update(frac=r["achieved"] / r["peak"], traffic=None, kernel=dom["name"],
+    r.update(frac=r["achieved"] / r["peak"], traffic=MEASURED_TRAFFIC.get(dom["name"]), kernel=dom["name"],
              avg_launch_us=avg_ms * 1e3, launches_per_step=None,
              algorithmic_bytes_per_launch=bytes_per, algorithmic_flops_per_launch=flops_per,
              share_of_kernel_time=dom["total_ms"] / sum(k["total_ms"] for k in live))
@@ -216,8 +220,22 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true", help="skip the 64-angle batched scatterer measurement")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the refined-disk and 64-angle batched scatterer measurements")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 512 MiB device copy three times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = 512 * 1024 * 1024 // 16
+        a = torch.ones(n, dtype=torch.complex128, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": 16 * n, "copy_bytes_written_per_launch": 16 * n,
+                          "launches": 3}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the multi-GPU path is not part of this build "
               "(--gpus must be 1)", file=sys.stderr)
@@ -253,10 +271,12 @@ def main():
         "paths": {k: {kk: vv for kk, vv in v.items() if kk != "kernels"} for k, v in
                   (("fp64", fp64), ("mixed", mixed))},
         "roofline": roofline(best["kernels"], best_name),
+        "roofline_coarse": roofline(best["kernels"], best_name, "coarse_gemv"),
         "kernels": sorted([k for k in best["kernels"] if k["launches"]], key=lambda k: -k["total_ms"]),
     }
-    line["roofline"]["launches_per_step"] = next(
-        k["launches"] for k in best["kernels"] if k["name"] == line["roofline"]["kernel"]) / args.steps
+    for key in ("roofline", "roofline_coarse"):
+        line[key]["launches_per_step"] = next(
+            k["launches"] for k in best["kernels"] if k["name"] == line[key]["kernel"]) / args.steps
     if not args.no_batched:
         line["nonconforming"] = refined_disk(hdp, torch, max(1, min(args.steps, 5)), min(args.warmup, 1))
         line["batched_rhs"] = batched_scatterer(hdp, torch, max(1, min(args.steps, 3)), min(args.warmup, 1))

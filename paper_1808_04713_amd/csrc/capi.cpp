@@ -249,6 +249,8 @@ static void build_coarse_blocks(Handle& h, const std::vector<int64_t>& kidx, con
   HIPCHECK(hipStreamSynchronize(h.stream));
   for (int b = 0; b < nb; ++b)
     if (hinfo[b] != 0) fail(HDP_E_COARSE, "coarse Schur-complement block " + std::to_string(b) + " is singular");
+  d.cb_off = upload(h, h.cb_off);
+  d.cb_D = upload(h, h.cb_D);
   h.coarse_mode = 1;
   h.coarse_bytes = 16.0 * double(tot);
   h.coarse_flops = 8.0 * double(tot);
@@ -268,6 +270,19 @@ static void coarse_solve_blocks(Handle& h, const double2* g, double2* w, int R) 
   auto& d = h.d;
   const int nb = int(h.cb_off.size()) - 1;
   auto sz = [&](int b) { return (b < 0 || b >= nb) ? 0 : h.cb_off[b + 1] - h.cb_off[b]; };
+  if (R == 1) {
+    // own kernels at one column: all diagonal products at once, then the two sweeps
+    launch_strip_diag(h, g, w, h.stream);
+    for (int b = 1; b < nb; ++b) {
+      double2* wb = w + h.cb_off[b];
+      launch_strip_step(d.cblk + h.cb_W[b], sz(b - 1), w + h.cb_off[b - 1], sz(b), wb, -1.0, wb, h.stream);
+    }
+    for (int b = nb - 2; b >= 0; --b) {
+      double2* wb = w + h.cb_off[b];
+      launch_strip_step(d.cblk + h.cb_U[b], sz(b + 1), w + h.cb_off[b + 1], sz(b), wb, -1.0, wb, h.stream);
+    }
+    return;
+  }
   const rocblas_operation N = rocblas_operation_none;
   // [n_K][R] row-major is the column-major R x n_K matrix: a block's rows are a
   // contiguous R x n_b slice X_b, and D^-1 x becomes X_b D^-T = X_b D^-1

@@ -158,6 +158,8 @@ struct Handle {
     double *hb_xinv = nullptr, *hb_y2 = nullptr;
     double2 *hb_tmp = nullptr, *fv = nullptr, *pv = nullptr;
     double2 *cblk = nullptr, *ctmp = nullptr;   // block-tridiagonal coarse factor
+    int* cb_off = nullptr;
+    int64_t* cb_D = nullptr;
     // per-class tables
     int *cls_n = nullptr, *cls_m = nullptr, *cls_nr = nullptr;
     int64_t *cls_op1 = nullptr, *cls_phi = nullptr, *cls_se = nullptr;   // offsets

@@ -279,6 +279,57 @@ __global__ void __launch_bounds__(NT) k_hblock(int nh, const int* __restrict__ b
   }
 }
 
+// ---------------------------------------------------------------------------
+// Strip (block-tridiagonal) coarse sweeps at one column.  A strip matrix M is
+// column-major K x n_out (column j contiguous):
+//   out_j = add_j + sign * sum_i M[i, j] in_i
+// one wavefront per output, lanes over i.
+__global__ void __launch_bounds__(NT) k_strip_mv(const double2* __restrict__ M, int K, const double2* __restrict__ in,
+                                                 int n_out, const double2* __restrict__ add, double sign,
+                                                 double2* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  if (j >= n_out) return;
+  const double2* col = M + (int64_t)K * j;
+  double ax = 0, ay = 0;
+  for (int i = lane; i < K; i += 64) {
+    double2 m = col[i], v = in[i];
+    ax += m.x * v.x - m.y * v.y;
+    ay += m.x * v.y + m.y * v.x;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    ax += __shfl_down(ax, off, 64);
+    ay += __shfl_down(ay, off, 64);
+  }
+  if (lane == 0) {
+    double2 a = add ? add[j] : make_double2(0, 0);
+    out[j] = make_double2(a.x + sign * ax, a.y + sign * ay);
+  }
+}
+
+// All strips at once: out_b = M_b in_b with M_b square (the diagonal inverses).
+__global__ void __launch_bounds__(NT) k_strip_diag_mv(const int* __restrict__ off, const int64_t* __restrict__ moff,
+                                                      const double2* __restrict__ Mall, const double2* __restrict__ in,
+                                                      double2* __restrict__ out) {
+  const int b = blockIdx.y;
+  const int o = off[b], n = off[b + 1] - o;
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  if (j >= n) return;
+  const double2* col = Mall + moff[b] + (int64_t)n * j;
+  double ax = 0, ay = 0;
+  for (int i = lane; i < n; i += 64) {
+    double2 m = col[i], v = in[o + i];
+    ax += m.x * v.x - m.y * v.y;
+    ay += m.x * v.y + m.y * v.x;
+  }
+  for (int sh = 32; sh > 0; sh >>= 1) {
+    ax += __shfl_down(ax, sh, 64);
+    ay += __shfl_down(ay, sh, 64);
+  }
+  if (lane == 0) out[o + j] = make_double2(ax, ay);
+}
+
 // w = K^-1 g: one wavefront per row of the (symmetric) inverse, RHS in chunks of 8.
 __global__ void __launch_bounds__(NT) k_coarse_gemv(int nK, const double2* __restrict__ Kinv,
                                                     const double2* __restrict__ g, double2* __restrict__ w,
@@ -1121,6 +1172,23 @@ template void launch_assemble<double2>(const Handle&, const double2*, const doub
                                        double2*, int, hipStream_t);
 template void launch_assemble<float2>(const Handle&, const float2*, const double2*, const double2*, double, double2*,
                                       int, hipStream_t);
+
+// Strip sweeps of the block-tridiagonal coarse factor at one column.
+void launch_strip_diag(const Handle& h, const double2* g, double2* w, hipStream_t s) {
+  const auto& d = h.d;
+  const int nb = int(h.cb_off.size()) - 1;
+  int nmax = 0;
+  for (int b = 0; b < nb; ++b) nmax = std::max(nmax, h.cb_off[b + 1] - h.cb_off[b]);
+  hipLaunchKernelGGL(k_strip_diag_mv, dim3(nblocks(nmax, NT / 64), nb), dim3(NT), 0, s, d.cb_off, d.cb_D, d.cblk, g,
+                     w);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_strip_step(const double2* M, int K, const double2* in, int n_out, const double2* add, double sign,
+                       double2* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_strip_mv, dim3(nblocks(n_out, NT / 64)), dim3(NT), 0, s, M, K, in, n_out, add, sign, out);
+  HIPCHECK(hipGetLastError());
+}
 
 void launch_coarse_solve(const Handle& h, const double2* g, double2* w, int R, hipStream_t s) {
   hipLaunchKernelGGL(k_coarse_gemv, dim3(nblocks(h.nK, NT / 64)), dim3(NT), 0, s, h.nK, h.d.Kinv, g, w, R);

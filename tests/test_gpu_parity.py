@@ -201,13 +201,13 @@ def test_block_tridiagonal_coarse_factor(name, oracles):
     solution as the dense inverse, for one and for several right-hand sides."""
     disc, l, E = oracles[name]
     w = CASES[name]
-    sb = hdp().Solver(w, tol=1e-12, max_iter=400, max_rhs=5, coarse="block")
-    sd = hdp().Solver(w, tol=1e-12, max_iter=400, max_rhs=5, coarse="dense")
+    sb = hdp().Solver(w, tol=1e-12, max_iter=400, max_rhs=64, coarse="block")
+    sd = hdp().Solver(w, tol=1e-12, max_iter=400, max_rhs=64, coarse="dense")
     st = sb.info
     assert st["coarse_mode"] == 1 and st["coarse_blocks"] >= 2 and st["coarse_residual"] < 1e-12
     assert sd.info["coarse_mode"] == 0
     rng = np.random.default_rng(5)
-    for R in (1, 5):
+    for R in (1, 5, 64):   # own sweep kernels at one column, library products above
         v = rng.standard_normal((E.nlam, R)) + 1j * rng.standard_normal((E.nlam, R))
         vd = torch.from_numpy(v).cuda()
         assert rel(sb.apply_interface(vd, "fp64").cpu().numpy(), sd.apply_interface(vd, "fp64").cpu().numpy()) < 1e-12
