@@ -72,7 +72,8 @@ enum { HDP_FP64 = 0, HDP_MIXED = 1 };
 enum {
   HDP_RHS_PLANE_WAVE_TOTAL = 0,     /* total field e^{ik d.x} through impedance data g = ik(d.n-1)u */
   HDP_RHS_POINT = 1,                /* unit point source delta(x - x0) */
-  HDP_RHS_PLANE_WAVE_SCATTERED = 2  /* scattered field: f = k^2 (eps_r - 1) e^{ik d.x}, g = 0 */
+  HDP_RHS_PLANE_WAVE_SCATTERED = 2, /* scattered field: f = k^2 (eps_r - 1) e^{ik d.x}, g = 0 */
+  HDP_RHS_ELEMENT_LOADS = 3         /* caller's element load vectors b_e (vertex basis) */
 };
 
 typedef struct {
@@ -118,6 +119,9 @@ typedef struct {
   int32_t n_rhs;              /* 1 .. max_rhs */
   const double* angles;       /* host, n_rhs propagation angles (plane-wave kinds) */
   const double* points;       /* host, 2*n_rhs source points (HDP_RHS_POINT) */
+  const hdp_c64* loads;       /* device, dof * n_rhs values, [dof][n_rhs] (RHS index fastest):
+                                 per leaf the (p+1)^2 coefficients of int N~_a N~_b f + boundary
+                                 terms in the vertex basis, x index fastest (HDP_RHS_ELEMENT_LOADS) */
 } hdp_rhs;
 
 typedef struct {
@@ -139,15 +143,30 @@ typedef struct {
 
 typedef struct hdp_handle hdp_handle;
 
-/* Build the solver (paper Sec. 2.3.2-2.3.3): classify leaves into element
- * classes, compute each class's separable eigenbasis and boundary operators,
- * number dual rows and coarse unknowns (Algorithm 1), assemble the coarse
- * matrix K = A_22 - A_12^T A_11^-1 A_12 and invert it on the device.
- * Supported meshes: conforming quadtree leaves (every interior side shared
- * by exactly two leaves of equal size); others return HDP_E_UNSUPPORTED.
- * Requires l < p_e for every element. */
+/* Build the solver (paper Sec. 2.3.2-2.3.3): find conforming and hanging
+ * sides (Sec. 2.2.4, any number of hanging nodes per side), classify leaves
+ * into element classes, compute each class's separable eigenbasis and
+ * boundary operators, number dual rows and coarse unknowns (Algorithm 1),
+ * assemble the coarse matrix K = A_22 - A_12^T A_11^-1 A_12 and invert it
+ * (dense) or factor it strip by strip on the device.  Leaves must tile the
+ * domain (HDP_E_MESH otherwise). */
 hdp_status hdp_setup(const hdp_mesh* mesh, const hdp_problem* prob,
                      const hdp_options* opt, hdp_handle** out);
+
+/* Far-field intensity J = |E_far(far_angle)|^2 of the scattered field for the
+ * plane wave of propagation angle `incidence` (HDP_RHS_PLANE_WAVE_SCATTERED),
+ * and its gradient dJ/d eps_r,e for every leaf: the adjoint solve A lambda = g
+ * with g = dE_far/dphi reuses the same solver (the system is complex
+ * symmetric, Sec. 2.3.4), then per leaf
+ *   dJ/d eps_e = 2 Re( conj(E) lambda_e^T (db_e/d eps_e - dA_e/d eps_e phi_e) ),
+ * dA_e/d eps_e = -k^2 (h_x h_y / 4) M~ (x) M~, db_e/d eps_e = k^2 int N~ e^{ik d.x}.
+ * far_inside: host, one byte per leaf (the region whose boundary carries the
+ * far-field integral; its outside leaves give the traces).  J: host, 1 value;
+ * grad: host, n_leaves values.  stats (optional) describe the forward solve.
+ * Needs max_rhs >= 1; returns HDP_W_NOT_CONVERGED if a solve missed tol. */
+hdp_status hdp_far_intensity_gradient(hdp_handle* h, double incidence, double far_angle,
+                                      const uint8_t* far_inside, double* J, double* grad,
+                                      hdp_stats* stats);
 
 /* Solve for n_rhs right-hand sides at once (paper Sec. 2.3.1: interface
  * right-hand side, GMRES on the interface problem, recovery of phi).

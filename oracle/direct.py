@@ -14,9 +14,11 @@ import scipy.sparse as sp
 from . import constraints as cs
 
 
-def conforming_solution(disc):
+def conforming_solution(disc, loads=None):
+    """Element coefficient vectors of the conforming solution; ``loads`` (one
+    vector per element, paper basis) replaces the discretisation's loads."""
     A = sp.block_diag([sp.csr_matrix(a) for a in disc.A]).toarray()
-    b = np.concatenate(disc.b)
+    b = np.concatenate(disc.b if loads is None else loads)
     con = cs.Constraints(disc.mesh, disc.degrees, 10 ** 6, disc.bc, disc.dirichlet_fun())
     C = con.C.toarray()
     if C.shape[0]:

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhdp.so")
 
 HDP_FP64, HDP_MIXED = 0, 1
-RHS_KINDS = {"plane_wave_total": 0, "point": 1, "plane_wave_scattered": 2}
+RHS_KINDS = {"plane_wave_total": 0, "point": 1, "plane_wave_scattered": 2, "element_loads": 3}
 STATUS_OK, STATUS_NOT_CONVERGED = 0, 1
 
 
@@ -44,7 +44,8 @@ class _Options(ctypes.Structure):
 
 class _Rhs(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n_rhs", ctypes.c_int32),
-                ("angles", ctypes.POINTER(ctypes.c_double)), ("points", ctypes.POINTER(ctypes.c_double))]
+                ("angles", ctypes.POINTER(ctypes.c_double)), ("points", ctypes.POINTER(ctypes.c_double)),
+                ("loads", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -69,7 +70,7 @@ class KernelTime(ctypes.Structure):
 
 EXPORTS = ["hdp_inspect", "hdp_setup", "hdp_solve", "hdp_apply_interface", "hdp_apply_precond",
            "hdp_interface_rhs", "hdp_local_solve", "hdp_get_stats", "hdp_profile", "hdp_profile_read",
-           "hdp_residual_history",
+           "hdp_residual_history", "hdp_far_intensity_gradient",
            "hdp_destroy", "hdp_status_string", "hdp_last_error_detail"]
 
 _lib = None
@@ -97,13 +98,15 @@ def load_library():
     L.hdp_profile.argtypes = [vp, i32]
     L.hdp_residual_history.argtypes = [vp, i32, dp, i32, ctypes.POINTER(i32)]
     L.hdp_profile_read.argtypes = [vp, ctypes.POINTER(KernelTime), i32, ctypes.POINTER(i32)]
+    L.hdp_far_intensity_gradient.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_uint8),
+                                             dp, dp, ctypes.POINTER(Stats)]
     L.hdp_destroy.argtypes = [vp]
     L.hdp_destroy.restype = None
     L.hdp_status_string.restype = ctypes.c_char_p
     L.hdp_last_error_detail.restype = ctypes.c_char_p
     for name in ("hdp_inspect", "hdp_setup", "hdp_solve", "hdp_apply_interface", "hdp_apply_precond",
                  "hdp_interface_rhs", "hdp_local_solve", "hdp_get_stats", "hdp_profile", "hdp_profile_read",
-                 "hdp_residual_history"):
+                 "hdp_residual_history", "hdp_far_intensity_gradient"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -184,9 +187,14 @@ class Solver:
             pass
 
     def _rhs(self, kind, values):
+        if kind == "element_loads":
+            # values: (dof, n_rhs) complex128 device tensor of element load vectors
+            loads = values.contiguous()
+            r = _Rhs(RHS_KINDS[kind], loads.shape[1], None, None, ctypes.c_void_p(loads.data_ptr()))
+            return r, loads, loads.shape[1]
         vals = np.ascontiguousarray(np.asarray(values, dtype=np.float64))
         n = len(vals) if RHS_KINDS[kind] != 1 else len(vals.reshape(-1, 2))
-        r = _Rhs(RHS_KINDS[kind], n, None, None)
+        r = _Rhs(RHS_KINDS[kind], n, None, None, None)
         ptr = vals.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         if kind == "point":
             r.points = ptr
@@ -223,6 +231,21 @@ class Solver:
         if far_angles is not None:
             return field, far, d
         return field, d
+
+    def far_intensity_gradient(self, incidence, far_angle, far_inside):
+        """J = |E_far(far_angle)|^2 for the scattered field of the plane wave with
+        propagation angle `incidence`, and dJ/d eps_r per leaf (adjoint solve)."""
+        fi = np.ascontiguousarray(np.asarray(far_inside, dtype=np.uint8))
+        grad = np.zeros(self.info["n_elements"])
+        J = ctypes.c_double()
+        st = Stats()
+        status = load_library().hdp_far_intensity_gradient(
+            self.h, float(incidence), float(far_angle), fi.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+            ctypes.byref(J), grad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(st))
+        _check(status, allow_not_converged=True)
+        d = st.as_dict()
+        d["converged"] = status == STATUS_OK
+        return J.value, grad, d
 
     def apply_interface(self, v, precision=None):
         """u = F v; v is a (n_lambda, n_rhs) complex128 device tensor."""
@@ -282,3 +305,37 @@ def rhs_values(w):
     if rhs["kind"] == "point":
         return "point", np.asarray(rhs["points"], float).reshape(-1)
     return rhs["kind"], np.asarray(rhs["angles"], float)
+
+
+def _far_intensity_function():
+    import torch
+
+    class FarFieldIntensity(torch.autograd.Function):
+        """J(eps) = |E_far(far_angle)|^2 of the scattered field for one plane-wave
+        incidence, as a function of the per-leaf relative permittivity.  Forward
+        sets the solver up for eps and runs the forward and adjoint solves; the
+        backward pass returns the adjoint gradient (no further solve)."""
+
+        @staticmethod
+        def forward(ctx, eps, w, incidence, far_angle, far_inside, options):
+            e = eps.detach().to("cpu", torch.float64).numpy()
+            s = Solver(dict(w, eps_r=e), **(options or {}))
+            try:
+                J, grad, _ = s.far_intensity_gradient(incidence, far_angle, far_inside)
+            finally:
+                s.close()
+            ctx.save_for_backward(torch.as_tensor(grad, dtype=eps.dtype, device=eps.device))
+            return torch.as_tensor(J, dtype=eps.dtype, device=eps.device)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            (grad,) = ctx.saved_tensors
+            return gJ * grad, None, None, None, None, None
+
+    return FarFieldIntensity
+
+
+def far_intensity(eps, w, incidence, far_angle, far_inside, **options):
+    """Differentiable J = |E_far|^2 with respect to the permittivity tensor eps (one
+    value per leaf); options are passed to Solver (tol, max_iter, precision, ...)."""
+    return _far_intensity_function().apply(eps, w, incidence, far_angle, far_inside, options)

@@ -444,6 +444,15 @@ void build_device(Handle& h) {
     d.eps = upload(h, h.eps);
     d.bmask = upload(h, h.bmask);
     d.angles = dalloc<double>(h, size_t(h.max_rhs));
+    std::vector<double> Ms;
+    std::vector<int64_t> Mo(NC);
+    for (int c = 0; c < NC; ++c) {
+      Mo[c] = int64_t(Ms.size());
+      MatD M = mass_vertex(h.classes[c].n);
+      Ms.insert(Ms.end(), M.a.begin(), M.a.end());
+    }
+    d.cls_M = upload(h, Ms);
+    d.cls_Moff = upload(h, Mo);
   }
   d.op1 = upload(h, op1); d.phi = upload(h, phi); d.se = upload(h, se);
   std::vector<float2> op1f(op1.size()), phif(phi.size());
@@ -1085,6 +1094,8 @@ static void check_rhs(const Handle& h, const hdp_rhs* rhs) {
     if (!rhs->angles) fail(HDP_E_ARG, "angles missing");
     for (int i = 0; i < rhs->n_rhs; ++i)
       if (!std::isfinite(rhs->angles[i])) fail(HDP_E_ARG, "non-finite angle");
+  } else if (rhs->kind == HDP_RHS_ELEMENT_LOADS) {
+    if (!rhs->loads) fail(HDP_E_ARG, "element loads missing");
   } else {
     fail(HDP_E_ARG, "unknown rhs kind");
   }
@@ -1095,6 +1106,13 @@ static void check_rhs(const Handle& h, const hdp_rhs* rhs) {
 static void load_rhs(Handle& h, const hdp_rhs* rhs, int Rp) {
   auto& d = h.d;
   hipStream_t s = h.stream;
+  if (rhs->kind == HDP_RHS_ELEMENT_LOADS) {
+    // caller's [dof][n_rhs] loads into the [dof][Rp] work array (padding zeroed)
+    if (rhs->n_rhs < Rp) launch_fill_zero(d.full0, h.dof * Rp, s);
+    HIPCHECK(hipMemcpy2DAsync(d.full0, size_t(Rp) * sizeof(double2), rhs->loads, size_t(rhs->n_rhs) * sizeof(double2),
+                              size_t(rhs->n_rhs) * sizeof(double2), size_t(h.dof), hipMemcpyDeviceToDevice, s));
+    return;
+  }
   if (rhs->kind == HDP_RHS_PLANE_WAVE_TOTAL || rhs->kind == HDP_RHS_PLANE_WAVE_SCATTERED) {
     // computed on the device for the elements that carry a load
     const int kind = rhs->kind;
@@ -1158,23 +1176,25 @@ hdp_status hdp_interface_rhs(hdp_handle* H, const hdp_rhs* rhs, hdp_c64* g) {
   API_END
 }
 
-hdp_status hdp_solve(hdp_handle* H, const hdp_rhs* rhs, hdp_c64* field, int32_t n_far, const double* far_angles,
-                     const uint8_t* far_inside, hdp_c64* far, hdp_stats* stats) {
-  API_BEGIN
-  if (!H) fail(HDP_E_ARG, "null handle");
-  Handle& h = H->h;
-  check_rhs(h, rhs);
-  if (far && (n_far < 1 || !far_angles || !far_inside)) fail(HDP_E_ARG, "far-field arguments incomplete");
-  auto t0 = std::chrono::steady_clock::now();
+struct SolveOut {
+  int iters = 0, refinements = 0;
+  double rel = 0, true_res = 0, t_rhs = 0, t_gmres = 0;
+  bool conv = true;
+  std::chrono::steady_clock::time_point t_rec0;   // start of the recovery
+};
+
+// One solve of n_rhs systems: loads, interface right-hand side, GMRES (FP64 or
+// GMRES-IR), true residual and recovery; leaves the element coefficients of the
+// solutions in full1 ([dof][Rp], vertex basis) and nu in t2.
+static SolveOut solve_core(Handle& h, const hdp_rhs* rhs, int R, int Rp) {
+  SolveOut o;
   auto& d = h.d;
   hipStream_t s = h.stream;
-  int R = rhs->n_rhs, Rp = pow2ceil(R);
-  h.t_launch = h.t_wait = 0;
+  auto t0 = std::chrono::steady_clock::now();
   auto ms_since = [](std::chrono::steady_clock::time_point a) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count();
   };
   int64_t vs = int64_t(h.nlam) * Rp;
-  after_user(h);
   load_rhs(h, rhs, Rp);
   interface_rhs(h, d.t0, Rp);                       // g
   HIPCHECK(hipStreamSynchronize(s));
@@ -1244,11 +1264,35 @@ hdp_status hdp_solve(hdp_handle* H, const hdp_rhs* rhs, hdp_c64* field, int32_t 
     HIPCHECK(hipStreamSynchronize(s));
     for (int r = 0; r < R; ++r) true_res = std::max(true_res, gn[r] > 0 ? rn[r] / gn[r] : 0.0);
   }
-  auto tr = std::chrono::steady_clock::now();
-  // recovery phi = A^-1 (b^ - C^T nu) (Sec. 2.3.1) and the field at GLL nodes
+  o.t_rec0 = std::chrono::steady_clock::now();
+  // recovery phi = A^-1 (b^ - C^T nu) (Sec. 2.3.1)
   HIPCHECK(hipMemcpyAsync(d.full1, d.full0, size_t(h.dof) * Rp * sizeof(double2), hipMemcpyDeviceToDevice, s));
   launch_sub_dual(h, d.full1, d.t2, Rp, s);
   element_solve(h, d.full1, d.full0, d.t2, Rp);
+  o.iters = iters;
+  o.refinements = refinements;
+  o.rel = rel;
+  o.conv = conv;
+  o.true_res = true_res;
+  o.t_rhs = t_rhs;
+  o.t_gmres = t_gmres;
+  return o;
+}
+
+hdp_status hdp_solve(hdp_handle* H, const hdp_rhs* rhs, hdp_c64* field, int32_t n_far, const double* far_angles,
+                     const uint8_t* far_inside, hdp_c64* far, hdp_stats* stats) {
+  API_BEGIN
+  if (!H) fail(HDP_E_ARG, "null handle");
+  Handle& h = H->h;
+  check_rhs(h, rhs);
+  if (far && (n_far < 1 || !far_angles || !far_inside)) fail(HDP_E_ARG, "far-field arguments incomplete");
+  auto t0 = std::chrono::steady_clock::now();
+  auto& d = h.d;
+  hipStream_t s = h.stream;
+  int R = rhs->n_rhs, Rp = pow2ceil(R);
+  h.t_launch = h.t_wait = 0;
+  after_user(h);
+  SolveOut so = solve_core(h, rhs, R, Rp);
   if (field) {
     Timed t(h, KF_GLL, 2.0 * h.dof * 16.0 * R, h.flops_gll * R);
     launch_gll(h, d.full1, reinterpret_cast<double2*>(field), Rp, h.dof, R, s);
@@ -1263,18 +1307,129 @@ hdp_status hdp_solve(hdp_handle* H, const hdp_rhs* rhs, hdp_c64* field, int32_t 
   double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (stats) {
     hdp_get_stats(H, stats);
-    stats->iterations = iters;
-    stats->refinements = refinements;
-    stats->rel_residual = rel;
+    stats->iterations = so.iters;
+    stats->refinements = so.refinements;
+    stats->rel_residual = so.rel;
     stats->solve_ms = ms;
-    stats->rhs_ms = t_rhs;
-    stats->gmres_ms = t_gmres;
+    stats->rhs_ms = so.t_rhs;
+    stats->gmres_ms = so.t_gmres;
     stats->gmres_launch_ms = h.t_launch;
     stats->gmres_wait_ms = h.t_wait;
-    stats->recover_ms = ms_since(tr);
-    stats->true_residual = true_res;
+    stats->recover_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - so.t_rec0).count();
+    stats->true_residual = so.true_res;
   }
-  return conv ? HDP_OK : HDP_W_NOT_CONVERGED;
+  return so.conv ? HDP_OK : HDP_W_NOT_CONVERGED;
+  API_END
+}
+
+// dE_far(angle)/dphi as element vectors (vertex basis, x index fastest): the far
+// field is linear in the coefficients of the outside elements along Gamma,
+// E = sum_q c_q [(xhat.n') u(x_q) + (ik)^-1 d_n' u(x_q)], c_q = w_q e^{-ik xhat.x_q}.
+static std::vector<cd> far_functional(const Handle& h, double angle, const uint8_t* inside) {
+  std::vector<cd> g(size_t(h.dof), 0.0);
+  const double xh = std::cos(angle), yh = std::sin(angle);
+  const cd I(0.0, 1.0);
+  for (int e = 0; e < h.E; ++e) {
+    if (inside[e]) continue;
+    for (int s = 1; s <= 4; ++s) {
+      const int si = 4 * e + s - 1;
+      bool facing_inside = false;
+      if (h.side_type[si] == 1 || h.side_type[si] == 2) {
+        facing_inside = inside[h.nb_e[si]] != 0;
+      } else if (h.side_type[si] == 3) {
+        int n_in = 0;
+        for (int f : h.side_nbrs[si]) n_in += inside[f] != 0;
+        if (n_in != 0 && n_in != int(h.side_nbrs[si].size()))
+          fail(HDP_E_ARG, "far-field boundary must follow whole element sides of the outside elements");
+        facing_inside = n_in != 0;
+      }
+      if (!facing_inside) continue;
+      const int n = h.deg[e] + 1, q = n + 12;
+      std::vector<double> xq, wq, row(n), dend(n);
+      gauss_legendre(q, xq, wq);
+      const double ox = h.ox[e], oy = h.oy[e], hx = h.hx[e], hy = h.hy[e];
+      const double nx = s == 1 ? 1 : s == 2 ? -1 : 0, ny = s == 3 ? 1 : s == 4 ? -1 : 0;   // into e
+      const double xn = xh * nx + yh * ny;
+      const double dsc = s <= 2 ? nx * 2.0 / hx : ny * 2.0 / hy;
+      vertex_basis_dx(n, (s == 2 || s == 4) ? 1.0 : -1.0, dend.data());
+      std::vector<cd> T(n, 0.0);   // T_b = sum_q c_q N~_b(t_q)
+      for (int t = 0; t < q; ++t) {
+        double x, y;
+        if (s <= 2) { x = s == 1 ? ox : ox + hx; y = oy + (xq[t] + 1) * hy / 2; }
+        else { y = s == 3 ? oy : oy + hy; x = ox + (xq[t] + 1) * hx / 2; }
+        const cd c = wq[t] * ((s <= 2 ? hy : hx) / 2) * std::exp(-I * h.k * (xh * x + yh * y));
+        vertex_basis(n, xq[t], row.data());
+        for (int b = 0; b < n; ++b) T[b] += c * row[b];
+      }
+      const int a0 = (s == 2 || s == 4) ? 0 : 1;
+      const int64_t base = h.dof_off[e];
+      for (int b = 0; b < n; ++b)
+        for (int a = 0; a < n; ++a) {
+          const cd v = T[b] * ((a == a0 ? xn : 0.0) + dsc * dend[a] / (I * h.k));
+          const int64_t idx = s <= 2 ? a + int64_t(n) * b : b + int64_t(n) * a;
+          g[base + idx] += v;
+        }
+    }
+  }
+  return g;
+}
+
+hdp_status hdp_far_intensity_gradient(hdp_handle* H, double incidence, double far_angle, const uint8_t* far_inside,
+                                      double* J, double* grad, hdp_stats* stats) {
+  API_BEGIN
+  if (!H) fail(HDP_E_ARG, "null handle");
+  if (!far_inside || !J || !grad) fail(HDP_E_ARG, "null far_inside, J or grad");
+  if (!std::isfinite(incidence) || !std::isfinite(far_angle)) fail(HDP_E_ARG, "non-finite angle");
+  Handle& h = H->h;
+  auto& d = h.d;
+  hipStream_t s = h.stream;
+  auto t0 = std::chrono::steady_clock::now();
+  h.t_launch = h.t_wait = 0;
+  if (!d.adj_u) {
+    d.adj_u = dalloc<double2>(h, size_t(h.dof));
+    d.adj_g = dalloc<double2>(h, size_t(h.dof));
+    d.adj_grad = dalloc<double>(h, size_t(h.E));
+    d.adj_E = dalloc<double2>(h, 1);
+  }
+  after_user(h);
+  // forward: scattered field for the incidence, its far field E
+  hdp_rhs fw{};
+  fw.kind = HDP_RHS_PLANE_WAVE_SCATTERED;
+  fw.n_rhs = 1;
+  fw.angles = &incidence;
+  SolveOut so = solve_core(h, &fw, 1, 1);
+  HIPCHECK(hipMemcpyAsync(d.adj_u, d.full1, size_t(h.dof) * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  far_prepare(h, 1, &far_angle, far_inside, 1);
+  launch_far_field(h, d.full1, 1, 1, d.adj_E, s);
+  double2 E;
+  HIPCHECK(hipMemcpyAsync(&E, d.adj_E, sizeof(double2), hipMemcpyDeviceToHost, s));
+  // adjoint: A lambda = dE/dphi with the same solver (A is complex symmetric)
+  std::vector<cd> g = far_functional(h, far_angle, far_inside);
+  std::vector<double2> gp(g.size());
+  for (size_t i = 0; i < g.size(); ++i) gp[i] = make_double2(g[i].real(), g[i].imag());
+  HIPCHECK(hipMemcpyAsync(d.adj_g, gp.data(), gp.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  hdp_rhs ad{};
+  ad.kind = HDP_RHS_ELEMENT_LOADS;
+  ad.n_rhs = 1;
+  ad.loads = reinterpret_cast<const hdp_c64*>(d.adj_g);
+  SolveOut sa = solve_core(h, &ad, 1, 1);
+  launch_eps_gradient(h, d.adj_u, d.full1, E, incidence, d.adj_grad, s);
+  HIPCHECK(hipMemcpyAsync(grad, d.adj_grad, size_t(h.E) * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  prof_flush(h);
+  *J = E.x * E.x + E.y * E.y;
+  if (stats) {
+    hdp_get_stats(H, stats);
+    stats->iterations = so.iters;
+    stats->refinements = so.refinements;
+    stats->rel_residual = std::max(so.rel, sa.rel);
+    stats->true_residual = std::max(so.true_res, sa.true_res);
+    stats->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    stats->rhs_ms = so.t_rhs;
+    stats->gmres_ms = so.t_gmres + sa.t_gmres;
+  }
+  return (so.conv && sa.conv) ? HDP_OK : HDP_W_NOT_CONVERGED;
   API_END
 }
 

@@ -157,6 +157,10 @@ struct Handle {
     int64_t* hb_moff = nullptr;
     double *hb_xinv = nullptr, *hb_y2 = nullptr;
     double2 *hb_tmp = nullptr, *fv = nullptr, *pv = nullptr;
+    double2 *adj_u = nullptr, *adj_g = nullptr, *adj_E = nullptr;   // adjoint gradient work
+    double* adj_grad = nullptr;
+    double* cls_M = nullptr;   // per class the 1-D vertex mass matrix (n x n)
+    int64_t* cls_Moff = nullptr;
     double2 *cblk = nullptr, *ctmp = nullptr;   // block-tridiagonal coarse factor
     int* cb_off = nullptr;
     int64_t* cb_D = nullptr;

@@ -817,6 +817,87 @@ __global__ void __launch_bounds__(NT) k_plane_wave_loads(
   }
 }
 
+// Adjoint gradient with respect to each element's relative permittivity:
+//   dJ/d eps_e = 2 Re( conj(E) [ lambda_e^T db_e + k^2 (h_x h_y / 4) lambda_e^T (M~ (x) M~) u_e ] )
+// with db_e = k^2 (h_x/2)(h_y/2) a (x) b the scattered-field load per unit (eps_e - 1)
+// (a, b: the 1-D integrals of N~ e^{ik d x} as in the plane-wave loads).  One block per element.
+__global__ void __launch_bounds__(NT) k_eps_grad(
+    const int* __restrict__ elem_cls, const int* __restrict__ cls_n, const int64_t* __restrict__ dof_off,
+    const int* __restrict__ cls_q, const int64_t* __restrict__ cls_qoff, const double* __restrict__ qx,
+    const double* __restrict__ qw, const double* __restrict__ qN, const double* __restrict__ cls_M,
+    const int64_t* __restrict__ cls_Moff, const double* __restrict__ ox, const double* __restrict__ oy,
+    const double* __restrict__ hx, const double* __restrict__ hy, const double2* __restrict__ U,
+    const double2* __restrict__ Lam, double2 E, double k, double dx, double dy, double* __restrict__ grad) {
+  extern __shared__ double2 sm[];
+  __shared__ double2 red[NT];
+  const int e = blockIdx.x;
+  const int c = elem_cls[e], n = cls_n[c], n2 = n * n, q = cls_q[c];
+  double2* su = sm;
+  double2* sT = sm + n2;
+  double2* sa = sm + 2 * n2;
+  double2* sb = sa + 64;
+  const double* M = cls_M + cls_Moff[c];
+  const double* xq = qx + cls_qoff[c];
+  const double* wq = qw + cls_qoff[c];
+  const double* N = qN + cls_qoff[c] * 64;
+  const double X0 = ox[e], Y0 = oy[e], HX = hx[e], HY = hy[e];
+  const int64_t base = dof_off[e];
+  for (int t = threadIdx.x; t < n2; t += NT) su[t] = U[base + t];
+  for (int m = threadIdx.x; m < 2 * n; m += NT) {
+    const bool yd = m >= n;
+    const int mm = yd ? m - n : m;
+    double sx = 0, sy = 0;
+    for (int t = 0; t < q; ++t) {
+      double pos = yd ? Y0 + (xq[t] + 1) * HY / 2 : X0 + (xq[t] + 1) * HX / 2;
+      double ph = k * (yd ? dy : dx) * pos;
+      double wn = wq[t] * N[(int64_t)t * 64 + mm];
+      sx += wn * cos(ph);
+      sy += wn * sin(ph);
+    }
+    if (yd) sb[mm] = make_double2(sx, sy); else sa[mm] = make_double2(sx, sy);
+  }
+  __syncthreads();
+  // T = U M^T (U[c][d] = u[c + n d])
+  for (int t = threadIdx.x; t < n2; t += NT) {
+    const int cc = t % n, b = t / n;
+    double ax = 0, ay = 0;
+    for (int dd = 0; dd < n; ++dd) {
+      const double m = M[b + n * dd];
+      ax += m * su[cc + n * dd].x;
+      ay += m * su[cc + n * dd].y;
+    }
+    sT[t] = make_double2(ax, ay);
+  }
+  __syncthreads();
+  const double f0 = k * k * (HX / 2) * (HY / 2);
+  const double fm = k * k * (HX * HY / 4);
+  double vx = 0, vy = 0;
+  for (int t = threadIdx.x; t < n2; t += NT) {
+    const int a = t % n, b = t / n;
+    double wx = 0, wy = 0;   // (M U M^T)[a][b]
+    for (int cc = 0; cc < n; ++cc) {
+      const double m = M[a + n * cc];
+      wx += m * sT[cc + n * b].x;
+      wy += m * sT[cc + n * b].y;
+    }
+    const double2 l = Lam[base + t];
+    const double2 db = cmul(sa[a], sb[b]);
+    const double px = f0 * db.x + fm * wx, py = f0 * db.y + fm * wy;
+    vx += l.x * px - l.y * py;
+    vy += l.x * py + l.y * px;
+  }
+  red[threadIdx.x] = make_double2(vx, vy);
+  __syncthreads();
+  for (int off = NT / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      red[threadIdx.x].x += red[threadIdx.x + off].x;
+      red[threadIdx.x].y += red[threadIdx.x + off].y;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) grad[e] = 2.0 * (E.x * red[0].x + E.y * red[0].y);
+}
+
 __global__ void k_fill_zero(double2* __restrict__ x, int64_t count) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < count) x[idx] = make_double2(0.0, 0.0);
@@ -1385,6 +1466,18 @@ void launch_plane_wave_loads(const Handle& h, int kind, const int* elems, int ne
   const auto& d = h.d;
   hipLaunchKernelGGL(k_plane_wave_loads, dim3(nel, nrhs), dim3(NT), 0, s, kind, elems, d.elem_cls, d.cls_n, d.dof_off,
                      d.cls_q, d.cls_qoff, d.qx, d.qw, d.qN, d.ox, d.oy, d.hx, d.hy, d.eps, d.bmask, angles, h.k, B, R);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_eps_gradient(const Handle& h, const double2* U, const double2* Lam, double2 E, double incidence,
+                         double* grad, hipStream_t s) {
+  const auto& d = h.d;
+  int nmax = 0;
+  for (auto& C : h.classes) nmax = std::max(nmax, C.n);
+  const size_t shm = (size_t(2) * nmax * nmax + 128) * sizeof(double2);
+  hipLaunchKernelGGL(k_eps_grad, dim3(h.E), dim3(NT), shm, s, d.elem_cls, d.cls_n, d.dof_off, d.cls_q, d.cls_qoff,
+                     d.qx, d.qw, d.qN, d.cls_M, d.cls_Moff, d.ox, d.oy, d.hx, d.hy, U, Lam, E, h.k,
+                     std::cos(incidence), std::sin(incidence), grad);
   HIPCHECK(hipGetLastError());
 }
 

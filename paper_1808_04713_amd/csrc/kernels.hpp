@@ -67,6 +67,9 @@ void launch_dense_scatter(const int64_t* idx, const double2* val, int64_t nnz, d
 void launch_block_scatter(const int* elems, const int64_t* src_off, int nblk, const int64_t* dof_off,
                           const double2* src, double2* full, int R, hipStream_t s);
 void launch_fill_zero(double2* x, int64_t count, hipStream_t s);
+// per element dJ/d eps_e of J = |E|^2 from the forward field U and the adjoint Lam (one column each)
+void launch_eps_gradient(const Handle& h, const double2* U, const double2* Lam, double2 E, double incidence,
+                         double* grad, hipStream_t s);
 // plane-wave loads (kind 0 total field, 2 scattered field) of the listed elements into columns
 // 0..nrhs-1 of B ([dof][R]); the other columns and the other elements are left untouched
 void launch_plane_wave_loads(const Handle& h, int kind, const int* elems, int nel, const double* angles, double2* B,
