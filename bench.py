@@ -188,6 +188,33 @@ def refined_disk(hdp, torch, steps, warmup):
     return out
 
 
+def design_gradient(hdp, torch, steps, warmup):
+    """The 64x64 design block (p = 12, k = 150, eps_r ~ U[1,4] on the central 16x16
+    elements): J = |E_far(0)|^2 for normal incidence and dJ/d eps_r for all 4096
+    elements by one forward and one adjoint solve."""
+    import numpy as np
+    import workloads as W
+    w = W.design_block_64x64()
+    c = W.leaf_centres(w)
+    he = 2.0 / 64
+    inside = (np.abs(c[:, 0]) < 8 * he) & (np.abs(c[:, 1]) < 8 * he)
+    s = hdp.Solver(w, tol=1e-8, max_iter=300)
+    for _ in range(max(1, warmup)):
+        s.far_intensity_gradient(0.0, 0.0, inside)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        J, g, st = s.far_intensity_gradient(0.0, 0.0, inside)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    out = dict(workload="design_block_64x64_p12_k150_16x16_design", ms_forward_adjoint_gradient=ms, J=J,
+               parameters=int(inside.sum()), iterations_forward=st["iterations"], setup_ms=s.info["setup_ms"],
+               classes=s.info["n_classes"], converged=st["converged"])
+    s.close()
+    print(f"bench: design gradient done ({ms:.1f} ms for J and 4096 derivatives)", file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline():
     """The oracle as it stands on a bounded sample of the same workload."""
     import numpy as np
@@ -279,6 +306,7 @@ def main():
             k["launches"] for k in best["kernels"] if k["name"] == line[key]["kernel"]) / args.steps
     if not args.no_batched:
         line["nonconforming"] = refined_disk(hdp, torch, max(1, min(args.steps, 5)), min(args.warmup, 1))
+        line["adjoint_gradient"] = design_gradient(hdp, torch, max(1, min(args.steps, 5)), min(args.warmup, 1))
         line["batched_rhs"] = batched_scatterer(hdp, torch, max(1, min(args.steps, 3)), min(args.warmup, 1))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
