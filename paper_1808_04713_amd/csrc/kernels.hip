@@ -1329,7 +1329,9 @@ GmresDims gmres_dims(int n, int R, int maxvec) {
   GmresDims g;
   g.step = NT / R;
   int64_t want = (int64_t(n) * R + 4 * NT - 1) / (4 * NT);
-  g.nchunks = int(std::max<int64_t>(1, std::min<int64_t>(64, want)));
+  // up to 512 row chunks (the partial buffer holds 512): many right-hand sides need
+  // them to fill the chip when only a few Arnoldi vectors exist
+  g.nchunks = int(std::max<int64_t>(1, std::min<int64_t>(512, want)));
   g.chunk = int((int64_t(n) + g.nchunks - 1) / g.nchunks);
   g.nchunks = int((int64_t(n) + g.chunk - 1) / g.chunk);
   g.ngroups = (maxvec + GVEC - 1) / GVEC;
