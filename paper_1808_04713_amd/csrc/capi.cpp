@@ -270,6 +270,21 @@ static void coarse_solve_blocks(Handle& h, const double2* g, double2* w, int R) 
   auto& d = h.d;
   const int nb = int(h.cb_off.size()) - 1;
   auto sz = [&](int b) { return (b < 0 || b >= nb) ? 0 : h.cb_off[b + 1] - h.cb_off[b]; };
+  if (R == 64) {
+    // own batched kernel for the diagonal products of all strips; the sweeps'
+    // small products go to the library (NN)
+    launch_strip_diag64(h, g, w, h.stream);
+    const rocblas_operation N = rocblas_operation_none;
+    for (int b = 1; b < nb; ++b) {
+      const int64_t o = h.cb_off[b], op = h.cb_off[b - 1];
+      zgemm(h, N, R, sz(b), sz(b - 1), -1.0, w + op * R, R, d.cblk + h.cb_W[b], sz(b - 1), 1.0, w + o * R, R);
+    }
+    for (int b = nb - 2; b >= 0; --b) {
+      const int64_t o = h.cb_off[b], on = h.cb_off[b + 1];
+      zgemm(h, N, R, sz(b), sz(b + 1), -1.0, w + on * R, R, d.cblk + h.cb_U[b], sz(b + 1), 1.0, w + o * R, R);
+    }
+    return;
+  }
   if (R == 1) {
     // own kernels at one column: all diagonal products at once, then the two sweeps
     launch_strip_diag(h, g, w, h.stream);

@@ -307,6 +307,54 @@ __global__ void __launch_bounds__(NT) k_strip_mv(const double2* __restrict__ M, 
   }
 }
 
+// 64-column strip products C[j][r] = sum_i M[i, j] X[i][r] (M column-major K x n_out),
+// used for the diagonal products of all strips in one launch.
+// A workgroup owns 32 outputs x 64 columns over a chunk of i: 32-row tiles of M
+// go through LDS (read back as wave-wide broadcasts), X rows are read coalesced
+// (lane = column); each thread accumulates 8 outputs of its column.
+constexpr int SMJ = 32;   // outputs per workgroup
+constexpr int SMK = 32;   // rows of M staged per pass
+
+__device__ __forceinline__ void strip_mm64_core(const double2* __restrict__ M, int K, const double2* __restrict__ X,
+                                                int n_out, int j0, int i0, int i1, double2 (&acc)[8]) {
+  __shared__ double2 Ms[SMK][SMJ + 1];
+  const int r = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) acc[t] = make_double2(0, 0);
+  for (int ib = i0; ib < i1; ib += SMK) {
+    const int nk = min(SMK, i1 - ib);
+    for (int e = threadIdx.x; e < SMK * SMJ; e += NT) {
+      const int jj = e / SMK, kk = e % SMK;
+      Ms[kk][jj] = (kk < nk && j0 + jj < n_out) ? M[(ib + kk) + (int64_t)K * (j0 + jj)] : make_double2(0, 0);
+    }
+    __syncthreads();
+    for (int kk = 0; kk < nk; ++kk) {
+      const double2 x = X[(int64_t)(ib + kk) * 64 + r];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) acc[t] = cfma(Ms[kk][wv * 8 + t], x, acc[t]);
+    }
+    __syncthreads();
+  }
+}
+
+// All strips at once (blockIdx.z = strip): w_b = D_b^-1 g_b, D_b^-1 symmetric.
+__global__ void __launch_bounds__(NT) k_strip_diag_mm64(const int* __restrict__ off, const int64_t* __restrict__ moff,
+                                                        const double2* __restrict__ Mall, const double2* __restrict__ g,
+                                                        double2* __restrict__ w) {
+  const int b = blockIdx.z;
+  const int o = off[b], n = off[b + 1] - o;
+  const int j0 = blockIdx.x * SMJ;
+  if (j0 >= n) return;
+  double2 acc[8];
+  strip_mm64_core(Mall + moff[b], n, g + (int64_t)o * 64, n, j0, 0, n, acc);
+  const int r = threadIdx.x & 63, jw = j0 + (threadIdx.x >> 6) * 8;
+  for (int t = 0; t < 8; ++t) {
+    const int j = jw + t;
+    if (j >= n) break;
+    w[((int64_t)o + j) * 64 + r] = acc[t];
+  }
+}
+
 // All strips at once: out_b = M_b in_b with M_b square (the diagonal inverses).
 __global__ void __launch_bounds__(NT) k_strip_diag_mv(const int* __restrict__ off, const int64_t* __restrict__ moff,
                                                       const double2* __restrict__ Mall, const double2* __restrict__ in,
@@ -1261,6 +1309,16 @@ void launch_strip_diag(const Handle& h, const double2* g, double2* w, hipStream_
   int nmax = 0;
   for (int b = 0; b < nb; ++b) nmax = std::max(nmax, h.cb_off[b + 1] - h.cb_off[b]);
   hipLaunchKernelGGL(k_strip_diag_mv, dim3(nblocks(nmax, NT / 64), nb), dim3(NT), 0, s, d.cb_off, d.cb_D, d.cblk, g,
+                     w);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_strip_diag64(const Handle& h, const double2* g, double2* w, hipStream_t s) {
+  const auto& d = h.d;
+  const int nb = int(h.cb_off.size()) - 1;
+  int nmax = 0;
+  for (int b = 0; b < nb; ++b) nmax = std::max(nmax, h.cb_off[b + 1] - h.cb_off[b]);
+  hipLaunchKernelGGL(k_strip_diag_mm64, dim3(nblocks(nmax, SMJ), 1, nb), dim3(NT), 0, s, d.cb_off, d.cb_D, d.cblk, g,
                      w);
   HIPCHECK(hipGetLastError());
 }

@@ -38,6 +38,8 @@ void launch_coarse_solve(const Handle& h, const double2* g, double2* w, int R, h
 void launch_strip_diag(const Handle& h, const double2* g, double2* w, hipStream_t s);
 void launch_strip_step(const double2* M, int K, const double2* in, int n_out, const double2* add, double sign,
                        double2* out, hipStream_t s);
+// w_b = D_b^-1 g_b for every strip at once, 64 columns
+void launch_strip_diag64(const Handle& h, const double2* g, double2* w, hipStream_t s);
 
 // Full-element operations (arrays [dof][R])
 void launch_fdm(const Handle& h, const double2* in, double2* out, int R, hipStream_t s);
