@@ -1184,7 +1184,13 @@ __global__ void __launch_bounds__(NT) k_givens(int* __restrict__ jptr, const dou
     for (int i = threadIdx.x; i <= j; i += NT) H[((int64_t)j * maxvec + i) * R + r] = col[i];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && gridDim.x == 1) {
+    // a single system: no other block to wait for (device-wide fences are costly
+    // across the chip's separate L2 caches)
+    status[0] = done[0];
+    status[1] = j + 1;
+    *jptr = j + 1;
+  } else if (threadIdx.x == 0) {
     __threadfence();
     int prev = atomicAdd(counter, 1);
     if (prev == gridDim.x - 1) {
