@@ -13,7 +13,7 @@ FP64 GMRES-IR) are timed; `value` is the faster path that reaches 1e-8.  A
 second, profiled pass over the same K solves brackets each kernel launch with
 HIP events on the solver's stream to give the dominant kernel's average launch
 duration and its roofline fraction.  The CPU oracle is timed on a bounded
-sample (a 16x16 sub-square with the same h, p and k) on this host.
+sample (a 12x12 sub-square with the same h, p and k) on this host.
 """
 import argparse
 import json
@@ -225,7 +225,7 @@ def cpu_baseline():
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count()
-    n = 16
+    n = 12
     h = 1.0 / 32
     w = W.small_uniform(n, 16, 100.0, domain=(0.0, n * h, 0.0, n * h),
                         rhs=dict(kind="point", points=[(n * h / 2, n * h / 2)]))
@@ -236,7 +236,7 @@ def cpu_baseline():
     t = time.perf_counter() - t0
     dof = n * n * 17 * 17
     return dict(value=dof / t, unit="DOF/s", cores=int(threads), kind="oracle",
-                sample=f"16x16 sub-square of the 32x32 mesh (h=1/32, p=16, k=100, point source at its "
+                sample=f"12x12 sub-square of the 32x32 mesh (h=1/32, p=16, k=100, point source at its "
                        f"centre vertex, l=2): {dof} DOF, oracle setup+solve to 1e-8 in {t:.1f} s, "
                        f"{E.iters} iterations, host cpu_count={os.cpu_count()}")
 
@@ -251,6 +251,8 @@ def main():
                     help="skip the refined-disk and 64-angle batched scatterer measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy three times (HBM counter calibration)")
+    ap.add_argument("--only", choices=["refined_disk", "scatterer", "design"],
+                    help="profiling aid: run only this secondary workload and print its record")
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
@@ -270,6 +272,10 @@ def main():
     import torch
     import paper_1808_04713_amd as hdp
     import workloads as W
+    if args.only:
+        fn = {"refined_disk": refined_disk, "scatterer": batched_scatterer, "design": design_gradient}[args.only]
+        print(json.dumps(fn(hdp, torch, max(1, args.steps), args.warmup)), flush=True)
+        return
     w = W.point_source_32x32()
     samples = load_samples()
     fp64, info = time_path(hdp, torch, w, "fp64", args.steps, args.warmup, samples)
