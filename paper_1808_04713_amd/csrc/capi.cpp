@@ -533,7 +533,8 @@ void build_device(Handle& h) {
   d.hbuf = dalloc<double2>(h, (size_t(h.max_iter) + 1) * Rp);
   d.hsum = dalloc<double2>(h, (size_t(h.max_iter) + 1) * Rp);
   d.part = dalloc<double2>(h, size_t(512) * (h.max_iter + 1) * Rp);
-  d.npart = dalloc<double>(h, size_t(update_blocks(h.nlam, int(Rp)) + 512) * Rp);
+  // partial norms: at most one per 64 entries of a dual vector, or 512 blocks
+  d.npart = dalloc<double>(h, size_t((nl * Rp + 63) / 64 + 512) * Rp);
   size_t mv = size_t(h.max_iter) + 1;
   d.vcur = dalloc<double2>(h, nl * Rp);
   d.Hdev = dalloc<double2>(h, size_t(h.max_iter) * mv * Rp);

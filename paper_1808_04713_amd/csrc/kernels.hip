@@ -283,27 +283,43 @@ __global__ void __launch_bounds__(NT) k_hblock(int nh, const int* __restrict__ b
 // Strip (block-tridiagonal) coarse sweeps at one column.  A strip matrix M is
 // column-major K x n_out (column j contiguous):
 //   out_j = add_j + sign * sum_i M[i, j] in_i
-// one wavefront per output, lanes over i.
+// One workgroup per output: its four waves stride over i together (4 KiB of the
+// column per pass, four passes in flight per lane), so a sweep step of a few
+// hundred outputs still puts thousands of waves on the chip.
+__device__ __forceinline__ double2 block_dot_col(const double2* __restrict__ col, const double2* __restrict__ v,
+                                                 int K, double2* red) {
+  double ax = 0, ay = 0;
+#pragma unroll 4
+  for (int i = threadIdx.x; i < K; i += NT) {
+    const double2 m = col[i], x = v[i];
+    ax += m.x * x.x - m.y * x.y;
+    ay += m.x * x.y + m.y * x.x;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    ax += __shfl_xor(ax, off, 64);
+    ay += __shfl_xor(ay, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red[wv] = make_double2(ax, ay);
+  __syncthreads();
+  double2 t = make_double2(0, 0);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < NT / 64; ++q) {
+      t.x += red[q].x;
+      t.y += red[q].y;
+    }
+  return t;   // valid in thread 0
+}
+
 __global__ void __launch_bounds__(NT) k_strip_mv(const double2* __restrict__ M, int K, const double2* __restrict__ in,
                                                  int n_out, const double2* __restrict__ add, double sign,
                                                  double2* __restrict__ out) {
-  const int lane = threadIdx.x & 63;
-  const int j = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
-  if (j >= n_out) return;
-  const double2* col = M + (int64_t)K * j;
-  double ax = 0, ay = 0;
-  for (int i = lane; i < K; i += 64) {
-    double2 m = col[i], v = in[i];
-    ax += m.x * v.x - m.y * v.y;
-    ay += m.x * v.y + m.y * v.x;
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    ax += __shfl_down(ax, off, 64);
-    ay += __shfl_down(ay, off, 64);
-  }
-  if (lane == 0) {
-    double2 a = add ? add[j] : make_double2(0, 0);
-    out[j] = make_double2(a.x + sign * ax, a.y + sign * ay);
+  __shared__ double2 red[NT / 64];
+  const int j = blockIdx.x;
+  const double2 t = block_dot_col(M + (int64_t)K * j, in, K, red);
+  if (threadIdx.x == 0) {
+    const double2 a = add ? add[j] : make_double2(0, 0);
+    out[j] = make_double2(a.x + sign * t.x, a.y + sign * t.y);
   }
 }
 
@@ -355,27 +371,18 @@ __global__ void __launch_bounds__(NT) k_strip_diag_mm64(const int* __restrict__ 
   }
 }
 
-// All strips at once: out_b = M_b in_b with M_b square (the diagonal inverses).
+// All strips at once: out_b = M_b in_b with M_b square (the diagonal inverses),
+// one workgroup per output row of a strip (blockIdx.y = strip).
 __global__ void __launch_bounds__(NT) k_strip_diag_mv(const int* __restrict__ off, const int64_t* __restrict__ moff,
                                                       const double2* __restrict__ Mall, const double2* __restrict__ in,
                                                       double2* __restrict__ out) {
+  __shared__ double2 red[NT / 64];
   const int b = blockIdx.y;
   const int o = off[b], n = off[b + 1] - o;
-  const int lane = threadIdx.x & 63;
-  const int j = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  const int j = blockIdx.x;
   if (j >= n) return;
-  const double2* col = Mall + moff[b] + (int64_t)n * j;
-  double ax = 0, ay = 0;
-  for (int i = lane; i < n; i += 64) {
-    double2 m = col[i], v = in[o + i];
-    ax += m.x * v.x - m.y * v.y;
-    ay += m.x * v.y + m.y * v.x;
-  }
-  for (int sh = 32; sh > 0; sh >>= 1) {
-    ax += __shfl_down(ax, sh, 64);
-    ay += __shfl_down(ay, sh, 64);
-  }
-  if (lane == 0) out[o + j] = make_double2(ax, ay);
+  const double2 t = block_dot_col(Mall + moff[b] + (int64_t)n * j, in + o, n, red);
+  if (threadIdx.x == 0) out[o + j] = t;
 }
 
 // w = K^-1 g: one wavefront per row of the (symmetric) inverse, RHS in chunks of 8.
@@ -974,37 +981,87 @@ __global__ void k_dense_scatter(const int64_t* __restrict__ idx, const double2* 
 // launch has a fixed shape; R (RHS count) divides 64 and thread t owns RHS
 // column t % R.  nvec = j + 1 Arnoldi vectors take part in an iteration.
 
-// part[c][i][r] = sum over the rows of chunk c of conj(V_i) w, i in group blockIdx.y.
+// part[c][i][r] = sum over the rows of chunk c of conj(V_i) w.  The work items
+// (chunk c, group of GV vectors) are spread over a fixed grid, so that the launch
+// shape does not depend on the number of Arnoldi vectors held on the device.
 template <int GV>
 __global__ void __launch_bounds__(NT) k_mdot(const double2* __restrict__ V, int64_t vs, const int* __restrict__ jptr,
                                              int jfix, const double2* __restrict__ w, int n, int R, int chunk,
-                                             int maxvec, double2* __restrict__ part) {
+                                             int nchunks, int maxvec, double2* __restrict__ part) {
   __shared__ double2 red[NT];
   const int nvec = (jptr ? *jptr : jfix) + 1;
-  const int i0 = blockIdx.y * GV;
-  if (i0 >= nvec) return;
+  const int nitems = nchunks * ((nvec + GV - 1) / GV);
   const int r = threadIdx.x % R, rl = threadIdx.x / R, step = NT / R;
-  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min((int64_t)n, lo + chunk);
-  double ax[GV], ay[GV];
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int c = item % nchunks, i0 = (item / nchunks) * GV;
+    const int64_t lo = (int64_t)c * chunk, hi = min((int64_t)n, lo + chunk);
+    double ax[GV], ay[GV];
 #pragma unroll
-  for (int t = 0; t < GV; ++t) ax[t] = ay[t] = 0;
-  for (int64_t row = lo + rl; row < hi; row += step) {
-    const int64_t o = row * R + r;
-    double2 b = w[o];
+    for (int t = 0; t < GV; ++t) ax[t] = ay[t] = 0;
+    for (int64_t row = lo + rl; row < hi; row += step) {
+      const int64_t o = row * R + r;
+      const double2 b = w[o];
 #pragma unroll
-    for (int t = 0; t < GV; ++t) {
-      if (i0 + t < nvec) {
-        double2 a = V[(int64_t)(i0 + t) * vs + o];
-        ax[t] += a.x * b.x + a.y * b.y;
-        ay[t] += a.x * b.y - a.y * b.x;
+      for (int t = 0; t < GV; ++t) {
+        if (i0 + t < nvec) {
+          const double2 a = V[(int64_t)(i0 + t) * vs + o];
+          ax[t] += a.x * b.x + a.y * b.y;
+          ay[t] += a.x * b.y - a.y * b.x;
+        }
       }
     }
-  }
 #pragma unroll
-  for (int t = 0; t < GV; ++t) {
-    double2 s = block_sum_by_rhs(make_double2(ax[t], ay[t]), R, red);
-    if (threadIdx.x < R && i0 + t < nvec)
-      part[((int64_t)blockIdx.x * maxvec + i0 + t) * R + threadIdx.x] = s;
+    for (int t = 0; t < GV; ++t) {
+      const double2 sm = block_sum_by_rhs(make_double2(ax[t], ay[t]), R, red);
+      if (threadIdx.x < R && i0 + t < nvec)
+        part[((int64_t)c * maxvec + i0 + t) * R + threadIdx.x] = sm;
+    }
+  }
+}
+
+// The multi-dot for a few right-hand sides (R = 1, 2, 4): every wave works on
+// its own items (row chunk c, group of GVW vectors) and reduces with shuffles
+// only, so no workgroup barrier sits between the loads and the partial sums.
+// Lane l reads entries lo R + l + 64 t of the chunk; since 64 is a multiple of
+// R, its column is l % R throughout.
+constexpr int GVW = 4;
+
+__global__ void __launch_bounds__(NT) k_mdot_wave(const double2* __restrict__ V, int64_t vs,
+                                                  const int* __restrict__ jptr, int jfix,
+                                                  const double2* __restrict__ w, int n, int R, int chunk,
+                                                  int nchunks, int maxvec, double2* __restrict__ part) {
+  const int nvec = (jptr ? *jptr : jfix) + 1;
+  const int nitems = nchunks * ((nvec + GVW - 1) / GVW);
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  const int nwaves = gridDim.x * (NT / 64);
+  for (int item = wave; item < nitems; item += nwaves) {
+    const int c = item % nchunks, i0 = (item / nchunks) * GVW;
+    const int64_t lo = (int64_t)c * chunk * R, hi = min((int64_t)n, (int64_t)(c + 1) * chunk) * R;
+    double ax[GVW], ay[GVW];
+#pragma unroll
+    for (int t = 0; t < GVW; ++t) ax[t] = ay[t] = 0;
+#pragma unroll 4
+    for (int64_t e = lo + lane; e < hi; e += 64) {
+      const double2 b = w[e];
+#pragma unroll
+      for (int t = 0; t < GVW; ++t) {
+        if (i0 + t < nvec) {
+          const double2 a = V[(int64_t)(i0 + t) * vs + e];
+          ax[t] += a.x * b.x + a.y * b.y;
+          ay[t] += a.x * b.y - a.y * b.x;
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < GVW; ++t) {
+      for (int off = 32; off >= R; off >>= 1) {
+        ax[t] += __shfl_xor(ax[t], off, 64);
+        ay[t] += __shfl_xor(ay[t], off, 64);
+      }
+      if (lane < R && i0 + t < nvec)
+        part[((int64_t)c * maxvec + i0 + t) * R + lane] = make_double2(ax[t], ay[t]);
+    }
   }
 }
 
@@ -1069,6 +1126,52 @@ __global__ void __launch_bounds__(NT) k_mupdate(const double2* __restrict__ V, i
   }
 }
 
+// The same update for short vectors (few rows x RHS): a workgroup owns 64
+// entries and its four waves take every fourth Arnoldi vector, so that the
+// chip holds four times as many waves and each lane has fewer loads in a row.
+constexpr int UPD_SPLIT_MAX = 1 << 20;   // entries (rows x RHS) up to which the split form is used
+
+__global__ void __launch_bounds__(NT) k_mupdate_split(const double2* __restrict__ V, int64_t vs,
+                                                      const int* __restrict__ jptr, int jfix,
+                                                      const double2* __restrict__ hc, double2* __restrict__ w, int n,
+                                                      int R, double sign, double* __restrict__ npart) {
+  __shared__ double2 red[NT / 64][64];
+  const int nvec = (jptr ? *jptr : jfix) + 1;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
+  const bool live = idx < (int64_t)n * R;
+  const int r = lane % R;   // 64 is a multiple of R
+  double ax = 0, ay = 0;
+  if (live) {
+#pragma unroll 4
+    for (int i = wv; i < nvec; i += NT / 64) {
+      const double2 a = V[(int64_t)i * vs + idx], b = hc[i * R + r];
+      ax += a.x * b.x - a.y * b.y;
+      ay += a.x * b.y + a.y * b.x;
+    }
+  }
+  red[wv][lane] = make_double2(ax, ay);
+  __syncthreads();
+  if (wv == 0) {
+    double nx = 0;
+    if (live) {
+      double sx = 0, sy = 0;
+      for (int q = 0; q < NT / 64; ++q) {
+        sx += red[q][lane].x;
+        sy += red[q][lane].y;
+      }
+      const double2 c = w[idx];
+      const double2 o = make_double2(c.x + sign * sx, c.y + sign * sy);
+      w[idx] = o;
+      nx = o.x * o.x + o.y * o.y;
+    }
+    if (npart) {
+      for (int off = 32; off >= R && off > 0; off >>= 1) nx += __shfl_xor(nx, off, 64);
+      if (lane < R) npart[(int64_t)blockIdx.x * R + lane] = nx;
+    }
+  }
+}
+
 // Partial squared norms of w per block and RHS column.
 __global__ void __launch_bounds__(NT) k_norm2_part(const double2* __restrict__ w, int n, int R, double* __restrict__ part) {
   __shared__ double2 red[NT];
@@ -1123,6 +1226,18 @@ __global__ void __launch_bounds__(NT) k_normalize(const double2* __restrict__ w,
 // previous Givens rotations, form the new one, update the residual estimate.
 // The last block to finish publishes status = {all converged, j + 1} and
 // advances j.
+//
+// The j earlier rotations form a chain: with x_0 = h_0 and h_i the new column,
+// rotation i maps (x_i, h_{i+1}) to the rotated entry t_i = c_i x_i + s_i h_{i+1}
+// and the carried value x_{i+1} = -conj(s_i) x_i + c_i h_{i+1}.  The carry is a
+// first-order affine recurrence, so the first wave resolves it as a prefix scan
+// of affine maps (each lane composes a segment of consecutive rotations, the
+// segments are combined across lanes in six shuffle steps) instead of a chain
+// of j dependent steps on one lane.
+__device__ __forceinline__ double2 shfl_up2(double2 v, int d) {
+  return make_double2(__shfl_up(v.x, d, 64), __shfl_up(v.y, d, 64));
+}
+
 __global__ void __launch_bounds__(NT) k_givens(int* __restrict__ jptr, const double2* __restrict__ hsum,
                                                const double* __restrict__ nrm, double2* __restrict__ H,
                                                double2* __restrict__ cs, double2* __restrict__ sn,
@@ -1131,31 +1246,48 @@ __global__ void __launch_bounds__(NT) k_givens(int* __restrict__ jptr, const dou
                                                double* __restrict__ resid, double tol, int maxvec, int R,
                                                int* __restrict__ counter, int* __restrict__ status,
                                                double* __restrict__ hist) {
-  extern __shared__ double2 col[];   // column (maxvec + 1) then the rotations (2 * maxvec)
-  double2* csl = col + maxvec + 1;
-  double2* snl = csl + maxvec;
+  __shared__ double2 xj_sh;
   const int r = blockIdx.x;
   const int j = *jptr;
   if (!done[r]) {
-    for (int i = threadIdx.x; i <= j; i += NT) col[i] = hsum[i * R + r];
-    for (int i = threadIdx.x; i < j; i += NT) {
-      csl[i] = cs[i * R + r];
-      snl[i] = sn[i * R + r];
+    if (threadIdx.x < 64) {
+      const int lane = threadIdx.x;
+      const int seg = (j + 63) / 64;
+      const int s0 = min(j, lane * seg), s1 = min(j, s0 + seg);
+      // this lane's segment as one map x -> A x + B
+      double2 A = make_double2(1, 0), B = make_double2(0, 0);
+      for (int i = s0; i < s1; ++i) {
+        const double2 c = cs[i * R + r], s = sn[i * R + r], hb = hsum[(i + 1) * R + r];
+        const double2 al = make_double2(-s.x, s.y);   // -conj(s)
+        B = cfma(c, hb, cmul(al, B));
+        A = cmul(al, A);
+      }
+      // inclusive scan over the lanes, earlier segments applied first
+      for (int d = 1; d < 64; d <<= 1) {
+        const double2 Ap = shfl_up2(A, d), Bp = shfl_up2(B, d);
+        if (lane >= d) {
+          B = cfma(A, Bp, B);
+          A = cmul(A, Ap);
+        }
+      }
+      double2 Ae = shfl_up2(A, 1), Be = shfl_up2(B, 1);
+      if (lane == 0) {
+        Ae = make_double2(1, 0);
+        Be = make_double2(0, 0);
+      }
+      const double2 x0 = hsum[r];
+      double2 x = cfma(Ae, x0, Be);   // carried value entering this lane's segment
+      for (int i = s0; i < s1; ++i) {
+        const double2 c = cs[i * R + r], s = sn[i * R + r], hb = hsum[(i + 1) * R + r];
+        H[((int64_t)j * maxvec + i) * R + r] = cfma(c, x, cmul(s, hb));
+        x = cfma(c, hb, cmul(make_double2(-s.x, s.y), x));
+      }
+      if (j == 0 && lane == 0) xj_sh = x0;
+      if (j > 0 && s0 < s1 && s1 == j) xj_sh = x;
     }
-    if (threadIdx.x == 0) col[j + 1] = make_double2(nrm[r], 0.0);
     __syncthreads();
     if (threadIdx.x == 0) {
-      for (int i = 0; i < j; ++i) {
-        double2 c = csl[i], s = snl[i], a = col[i], b = col[i + 1];
-        // t = c a + s b ; b' = -conj(s) a + c b
-        double2 t = make_double2(c.x * a.x - c.y * a.y + s.x * b.x - s.y * b.y,
-                                 c.x * a.y + c.y * a.x + s.x * b.y + s.y * b.x);
-        double2 bn = make_double2(-(s.x * a.x + s.y * a.y) + c.x * b.x - c.y * b.y,
-                                  -(s.x * a.y - s.y * a.x) + c.x * b.y + c.y * b.x);
-        col[i] = t;
-        col[i + 1] = bn;
-      }
-      double2 a = col[j], b = col[j + 1];
+      const double2 a = xj_sh, b = make_double2(nrm[r], 0.0);
       double aa = sqrt(a.x * a.x + a.y * a.y), bb = sqrt(b.x * b.x + b.y * b.y);
       double den = sqrt(aa * aa + bb * bb);
       double2 c, s;
@@ -1168,8 +1300,8 @@ __global__ void __launch_bounds__(NT) k_givens(int* __restrict__ jptr, const dou
       }
       cs[j * R + r] = c;
       sn[j * R + r] = s;
-      col[j] = make_double2(c.x * a.x + s.x * b.x - s.y * b.y, c.x * a.y + s.x * b.y + s.y * b.x);
-      col[j + 1] = make_double2(0, 0);
+      H[((int64_t)j * maxvec + j) * R + r] =
+          make_double2(c.x * a.x + s.x * b.x - s.y * b.y, c.x * a.y + s.x * b.y + s.y * b.x);
       double2 gj = g[j * R + r];
       g[(j + 1) * R + r] = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
       g[j * R + r] = make_double2(c.x * gj.x, c.x * gj.y);
@@ -1180,8 +1312,6 @@ __global__ void __launch_bounds__(NT) k_givens(int* __restrict__ jptr, const dou
       iters[r] = j + 1;
       if (res <= tol || nrm[r] == 0.0) done[r] = 1;
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i <= j; i += NT) H[((int64_t)j * maxvec + i) * R + r] = col[i];
   }
   __syncthreads();
   if (threadIdx.x == 0 && gridDim.x == 1) {
@@ -1314,8 +1444,7 @@ void launch_strip_diag(const Handle& h, const double2* g, double2* w, hipStream_
   const int nb = int(h.cb_off.size()) - 1;
   int nmax = 0;
   for (int b = 0; b < nb; ++b) nmax = std::max(nmax, h.cb_off[b + 1] - h.cb_off[b]);
-  hipLaunchKernelGGL(k_strip_diag_mv, dim3(nblocks(nmax, NT / 64), nb), dim3(NT), 0, s, d.cb_off, d.cb_D, d.cblk, g,
-                     w);
+  hipLaunchKernelGGL(k_strip_diag_mv, dim3(nmax, nb), dim3(NT), 0, s, d.cb_off, d.cb_D, d.cblk, g, w);
   HIPCHECK(hipGetLastError());
 }
 
@@ -1331,7 +1460,8 @@ void launch_strip_diag64(const Handle& h, const double2* g, double2* w, hipStrea
 
 void launch_strip_step(const double2* M, int K, const double2* in, int n_out, const double2* add, double sign,
                        double2* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_strip_mv, dim3(nblocks(n_out, NT / 64)), dim3(NT), 0, s, M, K, in, n_out, add, sign, out);
+  if (n_out <= 0) return;
+  hipLaunchKernelGGL(k_strip_mv, dim3(n_out), dim3(NT), 0, s, M, K, in, n_out, add, sign, out);
   HIPCHECK(hipGetLastError());
 }
 
@@ -1392,21 +1522,34 @@ void launch_gll(const Handle& h, const double2* X, double2* field, int R, int64_
 GmresDims gmres_dims(int n, int R, int maxvec) {
   GmresDims g;
   g.step = NT / R;
-  int64_t want = (int64_t(n) * R + 4 * NT - 1) / (4 * NT);
-  // up to 512 row chunks (the partial buffer holds 512): many right-hand sides need
-  // them to fill the chip when only a few Arnoldi vectors exist
-  g.nchunks = int(std::max<int64_t>(1, std::min<int64_t>(512, want)));
-  g.chunk = int((int64_t(n) + g.nchunks - 1) / g.nchunks);
-  g.nchunks = int((int64_t(n) + g.chunk - 1) / g.chunk);
-  g.ngroups = (maxvec + GVEC - 1) / GVEC;
+  g.wave = R < 8;
+  if (g.wave) {
+    // one wave per (chunk, vector group): 256 entries per chunk (four per lane),
+    // more when the partial buffer's 512 chunks would not cover the rows
+    g.chunk = int(std::max<int64_t>(256 / R, (int64_t(n) + 511) / 512));
+    g.nchunks = int((int64_t(n) + g.chunk - 1) / g.chunk);
+    g.ngroups = (maxvec + GVW - 1) / GVW;
+    g.grid = int(std::max<int64_t>(1, std::min<int64_t>(1024, (int64_t(g.nchunks) * g.ngroups + 3) / 4)));
+  } else {
+    // up to 512 row chunks (the partial buffer holds 512) keep the chip busy with
+    // many right-hand sides while only a few Arnoldi vectors exist
+    g.chunk = int(std::max<int64_t>(g.step, (int64_t(n) + 511) / 512));
+    g.nchunks = int((int64_t(n) + g.chunk - 1) / g.chunk);
+    g.ngroups = (maxvec + GVEC - 1) / GVEC;
+    g.grid = int(std::max<int64_t>(1, std::min<int64_t>(2048, int64_t(g.nchunks) * g.ngroups)));
+  }
   g.nnorm = int(std::max<int64_t>(1, std::min<int64_t>(256, (int64_t(n) * R + NT - 1) / NT)));
   return g;
 }
 
 void launch_mdot(const double2* V, int64_t vs, const int* jptr, int jfix, const double2* w, int n, int R,
                  const GmresDims& g, int maxvec, double2* part, hipStream_t s) {
-  hipLaunchKernelGGL((k_mdot<GVEC>), dim3(g.nchunks, g.ngroups), dim3(NT), 0, s, V, vs, jptr, jfix, w, n, R, g.chunk,
-                     maxvec, part);
+  if (g.wave)
+    hipLaunchKernelGGL(k_mdot_wave, dim3(g.grid), dim3(NT), 0, s, V, vs, jptr, jfix, w, n, R, g.chunk, g.nchunks,
+                       maxvec, part);
+  else
+    hipLaunchKernelGGL((k_mdot<4>), dim3(g.grid), dim3(NT), 0, s, V, vs, jptr, jfix, w, n, R, g.chunk, g.nchunks,
+                       maxvec, part);
   HIPCHECK(hipGetLastError());
 }
 
@@ -1419,12 +1562,18 @@ void launch_mdot_reduce(const double2* part, const GmresDims& g, const int* jptr
 
 void launch_mupdate(const double2* V, int64_t vs, const int* jptr, int jfix, const double2* hc, double2* w, int n,
                     int R, double sign, double* npart, hipStream_t s) {
-  hipLaunchKernelGGL(k_mupdate, dim3(nblocks(int64_t(n) * R)), dim3(NT), 0, s, V, vs, jptr, jfix, hc, w, n, R, sign,
-                     npart);
+  if (int64_t(n) * R <= UPD_SPLIT_MAX)
+    hipLaunchKernelGGL(k_mupdate_split, dim3(nblocks(int64_t(n) * R, 64)), dim3(NT), 0, s, V, vs, jptr, jfix, hc, w, n,
+                       R, sign, npart);
+  else
+    hipLaunchKernelGGL(k_mupdate, dim3(nblocks(int64_t(n) * R)), dim3(NT), 0, s, V, vs, jptr, jfix, hc, w, n, R, sign,
+                       npart);
   HIPCHECK(hipGetLastError());
 }
 
-int update_blocks(int n, int R) { return int(nblocks(int64_t(n) * R)); }
+int update_blocks(int n, int R) {
+  return int64_t(n) * R <= UPD_SPLIT_MAX ? int(nblocks(int64_t(n) * R, 64)) : int(nblocks(int64_t(n) * R));
+}
 
 void launch_normalize_parts(const double2* w, int n, int R, const double* part, int nblk, double* nrm, double2* out,
                             const int* jptr, int64_t vs, double2* out2, int nout_blocks, hipStream_t s) {
@@ -1444,8 +1593,8 @@ void launch_normalize(const double2* w, int n, int R, const GmresDims& g, double
 void launch_givens(int* jptr, const double2* hsum, const double* nrm, double2* H, double2* cs, double2* sn, double2* g,
                    const double* beta, int* done, int* iters, double* resid, double tol, int maxvec, int R,
                    int* counter, int* status, double* hist, hipStream_t s) {
-  hipLaunchKernelGGL(k_givens, dim3(R), dim3(NT), size_t(3 * maxvec + 1) * sizeof(double2), s, jptr, hsum, nrm, H, cs, sn,
-                     g, beta, done, iters, resid, tol, maxvec, R, counter, status, hist);
+  hipLaunchKernelGGL(k_givens, dim3(R), dim3(NT), 0, s, jptr, hsum, nrm, H, cs, sn, g, beta, done, iters, resid, tol,
+                     maxvec, R, counter, status, hist);
   HIPCHECK(hipGetLastError());
 }
 

@@ -82,7 +82,8 @@ int dots_blocks(int n, int R);
 
 // Device-resident GMRES (R divides 64; j read from device memory when jptr != nullptr)
 struct GmresDims {
-  int nchunks = 1, chunk = 1, ngroups = 1, nnorm = 1, step = 1;
+  int nchunks = 1, chunk = 1, ngroups = 1, nnorm = 1, step = 1, grid = 1;
+  bool wave = false;   // wave-per-item multi-dot (few right-hand sides)
 };
 GmresDims gmres_dims(int n, int R, int maxvec);
 void launch_mdot(const double2* V, int64_t vs, const int* jptr, int jfix, const double2* w, int n, int R,
