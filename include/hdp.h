@@ -110,9 +110,11 @@ typedef struct {
  * instead of launching its kernels one by one. */
 #define HDP_FLAG_GRAPH 1
 /* coarse factor: by default a dense inverse up to 12,000 coarse unknowns and the
-   block-tridiagonal strip factor above; these flags force one of them */
+   nested-dissection multifrontal factor above; these flags force one of them, or
+   the block-tridiagonal strip factor (at most one of the three may be set) */
 #define HDP_FLAG_COARSE_BLOCK 2
 #define HDP_FLAG_COARSE_DENSE 4
+#define HDP_FLAG_COARSE_ND 8
 
 typedef struct {
   int32_t kind;               /* HDP_RHS_* */
@@ -137,8 +139,8 @@ typedef struct {
   double rhs_ms, gmres_ms, gmres_launch_ms, gmres_wait_ms, recover_ms;
   double true_residual;       /* ||g - F nu|| / ||g|| in FP64 after the solve, max over RHS */
   double coarse_residual;     /* setup check of the coarse factor: ||K x - b|| / ||b|| */
-  int32_t coarse_mode;        /* 0 dense inverse, 1 block-tridiagonal strips */
-  int32_t coarse_blocks;      /* number of strips (1 for the dense inverse) */
+  int32_t coarse_mode;        /* 0 dense inverse, 1 block-tridiagonal strips, 2 nested dissection */
+  int32_t coarse_blocks;      /* strips, or nested-dissection tree nodes (1 for the dense inverse) */
 } hdp_stats;
 
 typedef struct hdp_handle hdp_handle;

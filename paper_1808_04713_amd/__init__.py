@@ -164,7 +164,7 @@ class Solver:
         self.precision = HDP_MIXED if precision == "mixed" else HDP_FP64
         with torch.cuda.device(self.device):
             stream = torch.cuda.current_stream(self.device).cuda_stream
-            flags = (1 if graphs else 0) | {"auto": 0, "block": 2, "dense": 4}[coarse]
+            flags = (1 if graphs else 0) | {"auto": 0, "block": 2, "dense": 4, "nd": 8}[coarse]
             opt = _Options(self.precision, float(tol), int(max_iter), int(max_rhs), ctypes.c_void_p(stream), flags)
             h = ctypes.c_void_p()
             _check(L.hdp_setup(ctypes.byref(mesh), ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(h)))

@@ -256,6 +256,54 @@ static void build_coarse_blocks(Handle& h, const std::vector<int64_t>& kidx, con
   h.coarse_flops = 8.0 * double(tot);
 }
 
+// Nested-dissection factor: assembled on the host (coarse_nd.cpp), uploaded
+// with its per-depth front-assembly entries and row tasks.
+static void build_coarse_nd(Handle& h, const std::vector<int64_t>& kidx, const std::vector<double2>& kval) {
+  auto& d = h.d;
+  NDHost f;
+  nd_factor(h, kidx, kval, f);
+  d.nd_fac = upload(h, f.fac);
+  d.nd_off = upload(h, h.nd_off);
+  d.nd_boff = upload(h, h.nd_boff);
+  d.nd_bnd = upload(h, h.nd_bnd);
+  d.nd_uoff = upload(h, f.uoff);
+  d.nd_mD = upload(h, f.mD);
+  d.nd_mL = upload(h, f.mL);
+  d.nd_mLt = upload(h, f.mLt);
+  d.nd_asm_own = upload(h, f.asm_own);
+  d.nd_asm_bnd = upload(h, f.asm_bnd);
+  d.nd_t1f = upload(h, f.t1f);
+  d.nd_t1b = upload(h, f.t1b);
+  d.nd_tRf = upload(h, f.tRf);
+  d.nd_tRb = upload(h, f.tRb);
+  const size_t Rp = size_t(pow2ceil(h.max_rhs));
+  d.nd_Y = dalloc<double2>(h, size_t(h.nK) * Rp);
+  d.nd_U = dalloc<double2>(h, size_t(std::max<int64_t>(1, f.urows)) * Rp);
+  h.nd_levels = f.levels;
+  h.coarse_mode = 2;
+  h.coarse_bytes = 16.0 * double(f.fac.size());
+  h.coarse_flops = f.flops_per_col;
+}
+
+static void coarse_solve_nd(Handle& h, const double2* g, double2* w, int R) {
+  auto& d = h.d;
+  NDView v;
+  v.off = d.nd_off; v.boff = d.nd_boff; v.bnd = d.nd_bnd; v.uoff = d.nd_uoff;
+  v.mD = d.nd_mD; v.mL = d.nd_mL; v.mLt = d.nd_mLt; v.fac = d.nd_fac;
+  const int nd = int(h.nd_levels.size());
+  for (int L = nd - 1; L >= 0; --L) {   // leaves first
+    const NDLevel& lv = h.nd_levels[L];
+    launch_nd_asm(d.nd_asm_own + lv.own0, lv.nown, d.nd_asm_bnd + lv.bnd0, lv.nbnd, g, d.nd_Y, d.nd_U, R, h.stream);
+    if (R == 1) launch_nd_fwd(d.nd_t1f + lv.f1, lv.nf1, v, d.nd_Y, d.nd_U, R, h.stream);
+    else launch_nd_fwd(d.nd_tRf + lv.fR, lv.nfR, v, d.nd_Y, d.nd_U, R, h.stream);
+  }
+  for (int L = 0; L < nd; ++L) {   // root first
+    const NDLevel& lv = h.nd_levels[L];
+    if (R == 1) launch_nd_bwd(d.nd_t1b + lv.b1, lv.nb1, v, d.nd_Y, w, R, h.stream);
+    else launch_nd_bwd(d.nd_tRb + lv.bR, lv.nbR, v, d.nd_Y, w, R, h.stream);
+  }
+}
+
 static void zgemv_t(Handle& h, int m, int n, double alpha, const double2* A, int lda, const double2* x, double beta,
                     double2* y) {
   rocblas_double_complex a(alpha, 0.0), b(beta, 0.0);
@@ -478,38 +526,18 @@ void build_device(Handle& h) {
   d.op1_f = upload(h, op1f); d.phi_f = upload(h, phif); d.se_f = upload(h, sef);
   d.Ex = upload(h, Ex); d.Ey = upload(h, Ey); d.Dinv = upload(h, Dinv);
   d.G = upload(h, G); d.Kc = upload(h, Kc); d.V = upload(h, V);
-  // coarse matrix K = sum_e T_e^T Kc T_e (summed on the host, scattered densely)
-  std::vector<std::pair<int64_t, cd>> coo;
-  for (int e = 0; e < E; ++e) {
-    const ElemClass& C = h.classes[h.cls[e]];
-    const int co = h.cm_off[e];
-    for (int b = 0; b < C.nr; ++b)
-      for (int a = 0; a < C.nr; ++a) {
-        cd kab = C.Kc(a, b);
-        for (int t = h.t_ptr[co + a]; t < h.t_ptr[co + a + 1]; ++t)
-          for (int u = h.t_ptr[co + b]; u < h.t_ptr[co + b + 1]; ++u)
-            coo.push_back({h.t_dof[t] + int64_t(h.nK) * h.t_dof[u], h.t_coef[t] * kab * h.t_coef[u]});
-      }
-  }
-  std::sort(coo.begin(), coo.end(), [](auto& x, auto& y) { return x.first < y.first; });
   std::vector<int64_t> kidx;
   std::vector<double2> kval;
-  for (size_t t = 0; t < coo.size();) {
-    int64_t key = coo[t].first;
-    cd s = 0;
-    while (t < coo.size() && coo[t].first == key) s += coo[t++].second;
-    kidx.push_back(key);
-    kval.push_back(make_double2(s.real(), s.imag()));
-  }
+  coarse_coo(h, kidx, kval);
   size_t nK = size_t(h.nK);
   rocblas_handle rb;
   if (rocblas_create_handle(&rb) != rocblas_status_success) fail(HDP_E_DEVICE, "rocblas_create_handle");
   rocblas_set_stream(rb, h.stream);
   h.rocblas = rb;   // kept for the coarse solves
-  // dense inverse for small coarse spaces (one streaming GEMV per solve), the
-  // block-tridiagonal strip factor beyond 12,000 unknowns
-  if (h.coarse_mode < 0) h.coarse_mode = h.nK > 12000 ? 1 : 0;
+  // the coarse factor chosen at set-up: dense inverse (0), strips (1) or nested
+  // dissection (2)
   if (h.coarse_mode == 1) build_coarse_blocks(h, kidx, kval);
+  else if (h.coarse_mode == 2) build_coarse_nd(h, kidx, kval);
   else build_coarse_dense(h, kidx, kval);
   // work buffers sized for the largest RHS batch (padded to a power of two)
   size_t Rp = size_t(pow2ceil(h.max_rhs));
@@ -577,6 +605,10 @@ void build_device(Handle& h) {
 void coarse_solve(Handle& h, const double2* g, double2* w, int R) {
   if (h.coarse_mode == 1) {
     coarse_solve_blocks(h, g, w, R);
+    return;
+  }
+  if (h.coarse_mode == 2) {
+    coarse_solve_nd(h, g, w, R);
     return;
   }
   if (R < 4) {
@@ -1005,9 +1037,15 @@ hdp_status hdp_setup(const hdp_mesh* mesh, const hdp_problem* prob, const hdp_op
   h.precision = opt->precision;
   h.user_stream = static_cast<hipStream_t>(opt->stream);
   h.use_graphs = (opt->flags & HDP_FLAG_GRAPH) != 0;
-  if ((opt->flags & HDP_FLAG_COARSE_BLOCK) && (opt->flags & HDP_FLAG_COARSE_DENSE))
-    fail(HDP_E_ARG, "HDP_FLAG_COARSE_BLOCK and HDP_FLAG_COARSE_DENSE are exclusive");
-  h.coarse_mode = (opt->flags & HDP_FLAG_COARSE_BLOCK) ? 1 : (opt->flags & HDP_FLAG_COARSE_DENSE) ? 0 : -1;
+  {
+    const int nf = ((opt->flags & HDP_FLAG_COARSE_BLOCK) != 0) + ((opt->flags & HDP_FLAG_COARSE_DENSE) != 0) +
+                   ((opt->flags & HDP_FLAG_COARSE_ND) != 0);
+    if (nf > 1) fail(HDP_E_ARG, "HDP_FLAG_COARSE_BLOCK, _DENSE and _ND are exclusive");
+  }
+  h.coarse_mode = (opt->flags & HDP_FLAG_COARSE_BLOCK)   ? 1
+                  : (opt->flags & HDP_FLAG_COARSE_DENSE) ? 0
+                  : (opt->flags & HDP_FLAG_COARSE_ND)    ? 2
+                                                         : -1;
   try {
     // a stream of the handle's own (default priority): capturable, unlike the null stream
     HIPCHECK(hipStreamCreateWithFlags(&h.stream, hipStreamNonBlocking));
@@ -1055,8 +1093,10 @@ hdp_status hdp_get_stats(const hdp_handle* H, hdp_stats* st) {
   st->min_element_margin = h.min_margin;
   st->setup_ms = h.setup_ms;
   st->coarse_residual = h.coarse_check;
-  st->coarse_mode = h.coarse_mode >= 0 ? h.coarse_mode : (h.nK > 12000 ? 1 : 0);
-  st->coarse_blocks = st->coarse_mode == 1 ? int(h.cb_off.size()) - 1 : 1;
+  st->coarse_mode = h.coarse_mode >= 0 ? h.coarse_mode : (h.nK > 12000 ? 2 : 0);
+  st->coarse_blocks = st->coarse_mode == 1   ? int(h.cb_off.size()) - 1
+                      : st->coarse_mode == 2 ? int(h.nd_off.size()) - 1
+                                             : 1;
   return HDP_OK;
   API_END
 }

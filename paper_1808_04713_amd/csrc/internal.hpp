@@ -68,6 +68,13 @@ struct Prof {
   int64_t n[KF_COUNT] = {0};
 };
 
+// One depth of the nested-dissection tree: ranges in the assembly-entry and
+// task arrays (R = 1 tasks are rows, other tasks 32-row tiles).
+struct NDLevel {
+  int own0 = 0, nown = 0, bnd0 = 0, nbnd = 0;
+  int f1 = 0, nf1 = 0, b1 = 0, nb1 = 0, fR = 0, nfR = 0, bR = 0, nbR = 0;
+};
+
 struct Handle {
   // problem
   int E = 0, l = 0, nlam = 0, nK = 0;
@@ -112,11 +119,19 @@ struct Handle {
   std::vector<int> cdof_ptr, cdof_list;  // transpose: coarse unknown -> coarse modes
   std::vector<double> cdof_coef;
   std::vector<int> cm_mode;       // per coarse mode, local mode index
-  std::vector<double> dof_y;      // per coarse unknown: y of its vertex or edge midpoint
+  std::vector<double> dof_x, dof_y;   // per coarse unknown: position of its vertex or edge midpoint
+  std::vector<char> dof_vtx;          // per coarse unknown: 1 for a mesh vertex
   // coarse factor: 0 dense inverse of K, 1 block-tridiagonal factor over the
   // strips cb_off (consecutive coarse unknowns); per block i the inverse D_i^-1
   // of the Schur-complement block and W_i = D_i^-1 K_{i,i-1}, U_i = D_i^-1 K_{i,i+1}
+  // 2 nested-dissection multifrontal factor: tree nodes in postorder, node t
+  // owns the coarse unknowns [nd_off[t], nd_off[t+1]) and, after its subtree is
+  // eliminated, couples to the ancestor unknowns nd_bnd[nd_boff[t] .. nd_boff[t+1])
   int coarse_mode = -1;            // -1: chosen by size at setup
+  std::vector<int> nd_off, nd_depth, nd_child;
+  std::vector<int64_t> nd_boff;
+  std::vector<int> nd_bnd;
+  std::vector<NDLevel> nd_levels;   // per tree depth
   std::vector<int> cb_off;
   std::vector<int64_t> cb_D, cb_W, cb_U;
   double coarse_check = 0;         // relative residual of the coarse factor on a test vector
@@ -162,6 +177,12 @@ struct Handle {
     double* cls_M = nullptr;   // per class the 1-D vertex mass matrix (n x n)
     int64_t* cls_Moff = nullptr;
     double2 *cblk = nullptr, *ctmp = nullptr;   // block-tridiagonal coarse factor
+    // nested-dissection coarse factor
+    double2 *nd_fac = nullptr, *nd_Y = nullptr, *nd_U = nullptr;
+    int *nd_off = nullptr, *nd_bnd = nullptr;
+    int64_t *nd_boff = nullptr, *nd_uoff = nullptr, *nd_mD = nullptr, *nd_mL = nullptr, *nd_mLt = nullptr;
+    int3 *nd_asm_own = nullptr, *nd_asm_bnd = nullptr;
+    int2 *nd_t1f = nullptr, *nd_t1b = nullptr, *nd_tRf = nullptr, *nd_tRb = nullptr;
     int* cb_off = nullptr;
     int64_t* cb_D = nullptr;
     // per-class tables
@@ -240,6 +261,23 @@ void prof_flush(Handle& h);   // after a stream synchronisation
 
 // setup.cpp
 void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob);
+// Coarse matrix K = sum_e T_e^T Kc_e T_e as sorted COO (key = row + nK * col).
+void coarse_coo(const Handle& h, std::vector<int64_t>& kidx, std::vector<double2>& kval);
+
+// coarse_nd.cpp: the nested-dissection factor assembled on the host.  Per node
+// the blocks Dinv (nI x nI), L (nB x nI) and Lt = L^T, row-major, back to back in
+// fac; U rows hold the nodes' update vectors.  Per tree depth: the front
+// assembly entries and the row tasks of the device sweeps.
+struct NDHost {
+  std::vector<double2> fac;
+  std::vector<int64_t> uoff, mD, mL, mLt;
+  int64_t urows = 0;
+  std::vector<int3> asm_own, asm_bnd;
+  std::vector<int2> t1f, t1b, tRf, tRb;
+  std::vector<NDLevel> levels;
+  double flops_per_col = 0;   // 8 (nI^2 + 2 nB nI) summed over the nodes
+};
+void nd_factor(const Handle& h, const std::vector<int64_t>& kidx, const std::vector<double2>& kval, NDHost& f);
 void build_device(Handle& h);
 // Element loads of the elements with a non-zero load: elems lists them and
 // vals holds their blocks back to back, each [n_e^2][R].

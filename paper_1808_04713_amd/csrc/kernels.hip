@@ -385,6 +385,170 @@ __global__ void __launch_bounds__(NT) k_strip_diag_mv(const int* __restrict__ of
   if (threadIdx.x == 0) out[o + j] = t;
 }
 
+// ---------------------------------------------------------------------------
+// Nested-dissection coarse solve.  Node t owns the coarse unknowns
+// [off_t, off_t + nI_t) and has the boundary list bnd_t (nB_t ancestor unknowns);
+// its factor blocks are Dinv_t (nI x nI), L_t (nB x nI) and Lt_t = L_t^T (nI x nB),
+// all row-major.  Forward, deepest level first:
+//   front = [g_I; 0] + extend-add of the children's updates U_c
+//   Y_I = front_I,  U_t = front_B - L_t Y_I
+// backward, root first:  X_I = Dinv_t Y_I - Lt_t X_B.
+
+// front assembly: one thread per (entry, column)
+__global__ void k_nd_asm(const int3* __restrict__ own, int nown, const int3* __restrict__ bnd, int nbnd,
+                         const double2* __restrict__ g, double2* __restrict__ Y, double2* __restrict__ U, int R) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)(nown + nbnd) * R) return;
+  const int q = int(e / R), r = int(e % R);
+  const int3 t = q < nown ? own[q] : bnd[q - nown];
+  double2 a = q < nown ? g[(int64_t)t.x * R + r] : make_double2(0, 0);
+  if (t.y >= 0) {
+    const double2 u = U[(int64_t)t.y * R + r];
+    a.x += u.x; a.y += u.y;
+  }
+  if (t.z >= 0) {
+    const double2 u = U[(int64_t)t.z * R + r];
+    a.x += u.x; a.y += u.y;
+  }
+  if (q < nown) Y[(int64_t)t.x * R + r] = a;
+  else U[(int64_t)t.x * R + r] = a;
+}
+
+// Node tables on the device.
+struct NDNodes {
+  const int* off;          // [n + 1]
+  const int64_t* boff;     // [n + 1] into bnd
+  const int* bnd;
+  const int64_t* uoff;     // row offset of U_t
+  const int64_t* mD;       // factor offsets
+  const int64_t* mL;
+  const int64_t* mLt;
+  const double2* fac;
+};
+
+// One column: one wave per output row, lanes over the row.
+__global__ void __launch_bounds__(NT) k_nd_fwd1(const int2* __restrict__ task, int ntask, NDNodes nd,
+                                                const double2* __restrict__ Y, double2* __restrict__ U) {
+  const int lane = threadIdx.x & 63;
+  const int q = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  if (q >= ntask) return;
+  const int t = task[q].x, b = task[q].y;
+  const int o = nd.off[t], nI = nd.off[t + 1] - o;
+  const double2* Lr = nd.fac + nd.mL[t] + (int64_t)nI * b;
+  double ax = 0, ay = 0;
+  for (int i = lane; i < nI; i += 64) {
+    const double2 m = Lr[i], y = Y[o + i];
+    ax += m.x * y.x - m.y * y.y;
+    ay += m.x * y.y + m.y * y.x;
+  }
+  for (int sh = 32; sh > 0; sh >>= 1) {
+    ax += __shfl_xor(ax, sh, 64);
+    ay += __shfl_xor(ay, sh, 64);
+  }
+  if (lane == 0) {
+    double2* u = U + nd.uoff[t] + b;
+    const double2 f = *u;
+    *u = make_double2(f.x - ax, f.y - ay);
+  }
+}
+
+__global__ void __launch_bounds__(NT) k_nd_bwd1(const int2* __restrict__ task, int ntask, NDNodes nd,
+                                                const double2* __restrict__ Y, double2* __restrict__ X) {
+  const int lane = threadIdx.x & 63;
+  const int q = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  if (q >= ntask) return;
+  const int t = task[q].x, i = task[q].y;
+  const int o = nd.off[t], nI = nd.off[t + 1] - o;
+  const int64_t bo = nd.boff[t];
+  const int nB = int(nd.boff[t + 1] - bo);
+  const double2* Dr = nd.fac + nd.mD[t] + (int64_t)nI * i;
+  const double2* Lr = nd.fac + nd.mLt[t] + (int64_t)nB * i;
+  double ax = 0, ay = 0;
+  for (int k = lane; k < nI; k += 64) {
+    const double2 m = Dr[k], y = Y[o + k];
+    ax += m.x * y.x - m.y * y.y;
+    ay += m.x * y.y + m.y * y.x;
+  }
+  for (int b = lane; b < nB; b += 64) {
+    const double2 m = Lr[b], x = X[nd.bnd[bo + b]];
+    ax -= m.x * x.x - m.y * x.y;
+    ay -= m.x * x.y + m.y * x.x;
+  }
+  for (int sh = 32; sh > 0; sh >>= 1) {
+    ax += __shfl_xor(ax, sh, 64);
+    ay += __shfl_xor(ay, sh, 64);
+  }
+  if (lane == 0) X[o + i] = make_double2(ax, ay);
+}
+
+// Several columns (R <= 64, lane = column): a workgroup owns 32 outputs of a
+// node; 32-row tiles of the factor block go through LDS and are read back as
+// wave-wide broadcasts, the operand rows are read coalesced (gathered through
+// xidx when given).  acc += sum_i M[i + K j] X_row(i) for this thread's 8 outputs.
+__device__ __forceinline__ void nd_mm_core(const double2* __restrict__ M, int K, int n_out, int j0,
+                                           const double2* __restrict__ X, int64_t xbase,
+                                           const int* __restrict__ xidx, int R, double2 (&acc)[8]) {
+  __shared__ double2 Ms[SMK][SMJ + 1];
+  const int r = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const bool live = r < R;
+  for (int ib = 0; ib < K; ib += SMK) {
+    const int nk = min(SMK, K - ib);
+    for (int e = threadIdx.x; e < SMK * SMJ; e += NT) {
+      const int jj = e / SMK, kk = e % SMK;
+      Ms[kk][jj] = (kk < nk && j0 + jj < n_out) ? M[(ib + kk) + (int64_t)K * (j0 + jj)] : make_double2(0, 0);
+    }
+    __syncthreads();
+    if (live)
+      for (int kk = 0; kk < nk; ++kk) {
+        const int64_t row = xidx ? (int64_t)xidx[ib + kk] : xbase + ib + kk;
+        const double2 x = X[row * R + r];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc[t] = cfma(Ms[kk][wv * 8 + t], x, acc[t]);
+      }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(NT) k_nd_fwdR(const int2* __restrict__ task, NDNodes nd,
+                                                const double2* __restrict__ Y, double2* __restrict__ U, int R) {
+  const int t = task[blockIdx.x].x, j0 = task[blockIdx.x].y;
+  const int o = nd.off[t], nI = nd.off[t + 1] - o;
+  const int nB = int(nd.boff[t + 1] - nd.boff[t]);
+  double2 acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = make_double2(0, 0);
+  nd_mm_core(nd.fac + nd.mL[t], nI, nB, j0, Y, o, nullptr, R, acc);
+  const int r = threadIdx.x & 63, jw = j0 + (threadIdx.x >> 6) * 8;
+  if (r >= R) return;
+  for (int q = 0; q < 8; ++q) {
+    const int j = jw + q;
+    if (j >= nB) break;
+    double2* u = U + (nd.uoff[t] + j) * R + r;
+    const double2 f = *u;
+    *u = make_double2(f.x - acc[q].x, f.y - acc[q].y);
+  }
+}
+
+__global__ void __launch_bounds__(NT) k_nd_bwdR(const int2* __restrict__ task, NDNodes nd,
+                                                const double2* __restrict__ Y, double2* __restrict__ X, int R) {
+  const int t = task[blockIdx.x].x, j0 = task[blockIdx.x].y;
+  const int o = nd.off[t], nI = nd.off[t + 1] - o;
+  const int64_t bo = nd.boff[t];
+  const int nB = int(nd.boff[t + 1] - bo);
+  double2 a1[8], a2[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) a1[q] = a2[q] = make_double2(0, 0);
+  nd_mm_core(nd.fac + nd.mD[t], nI, nI, j0, Y, o, nullptr, R, a1);
+  if (nB > 0) nd_mm_core(nd.fac + nd.mLt[t], nB, nI, j0, X, 0, nd.bnd + bo, R, a2);
+  const int r = threadIdx.x & 63, jw = j0 + (threadIdx.x >> 6) * 8;
+  if (r >= R) return;
+  for (int q = 0; q < 8; ++q) {
+    const int j = jw + q;
+    if (j >= nI) break;
+    X[((int64_t)o + j) * R + r] = make_double2(a1[q].x - a2[q].x, a1[q].y - a2[q].y);
+  }
+}
+
 // w = K^-1 g: one wavefront per row of the (symmetric) inverse, RHS in chunks of 8.
 __global__ void __launch_bounds__(NT) k_coarse_gemv(int nK, const double2* __restrict__ Kinv,
                                                     const double2* __restrict__ g, double2* __restrict__ w,
@@ -1699,6 +1863,34 @@ void launch_eps_gradient(const Handle& h, const double2* U, const double2* Lam, 
 void launch_fill_zero(double2* x, int64_t count, hipStream_t s) {
   if (count == 0) return;
   hipLaunchKernelGGL(k_fill_zero, dim3(nblocks(count)), dim3(NT), 0, s, x, count);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_nd_asm(const int3* own, int nown, const int3* bnd, int nbnd, const double2* g, double2* Y, double2* U,
+                   int R, hipStream_t s) {
+  const int64_t n = int64_t(nown + nbnd) * R;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_nd_asm, dim3(nblocks(n)), dim3(NT), 0, s, own, nown, bnd, nbnd, g, Y, U, R);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_nd_fwd(const int2* task, int ntask, const NDView& v, const double2* Y, double2* U, int R, hipStream_t s) {
+  if (ntask == 0) return;
+  const NDNodes nd{v.off, v.boff, v.bnd, v.uoff, v.mD, v.mL, v.mLt, v.fac};
+  if (R == 1)
+    hipLaunchKernelGGL(k_nd_fwd1, dim3(nblocks(ntask, NT / 64)), dim3(NT), 0, s, task, ntask, nd, Y, U);
+  else
+    hipLaunchKernelGGL(k_nd_fwdR, dim3(ntask), dim3(NT), 0, s, task, nd, Y, U, R);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_nd_bwd(const int2* task, int ntask, const NDView& v, const double2* Y, double2* X, int R, hipStream_t s) {
+  if (ntask == 0) return;
+  const NDNodes nd{v.off, v.boff, v.bnd, v.uoff, v.mD, v.mL, v.mLt, v.fac};
+  if (R == 1)
+    hipLaunchKernelGGL(k_nd_bwd1, dim3(nblocks(ntask, NT / 64)), dim3(NT), 0, s, task, ntask, nd, Y, X);
+  else
+    hipLaunchKernelGGL(k_nd_bwdR, dim3(ntask), dim3(NT), 0, s, task, nd, Y, X, R);
   HIPCHECK(hipGetLastError());
 }
 

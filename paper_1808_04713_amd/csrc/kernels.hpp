@@ -63,6 +63,21 @@ void launch_axpby(const double2* x, const double2* y, double2* z, int64_t count,
                   hipStream_t s);
 void launch_cast_f(const double2* x, float2* y, int64_t count, hipStream_t s);
 void launch_cast_d(const float2* x, double2* y, int64_t count, hipStream_t s);
+// Nested-dissection coarse solve (device views of the node tables and the factor).
+struct NDView {
+  const int* off = nullptr;
+  const int64_t* boff = nullptr;
+  const int* bnd = nullptr;
+  const int64_t *uoff = nullptr, *mD = nullptr, *mL = nullptr, *mLt = nullptr;
+  const double2* fac = nullptr;
+};
+// front assembly of one level: own entries {row, child row 1, child row 2} write
+// Y[row] = g[row] + U[c1] + U[c2]; boundary entries {U row, c1, c2} write U[row] = U[c1] + U[c2]
+void launch_nd_asm(const int3* own, int nown, const int3* bnd, int nbnd, const double2* g, double2* Y, double2* U,
+                   int R, hipStream_t s);
+// tasks: {node, row} at R = 1, {node, first of 32 rows} otherwise
+void launch_nd_fwd(const int2* task, int ntask, const NDView& v, const double2* Y, double2* U, int R, hipStream_t s);
+void launch_nd_bwd(const int2* task, int ntask, const NDView& v, const double2* Y, double2* X, int R, hipStream_t s);
 void launch_dense_scatter(const int64_t* idx, const double2* val, int64_t nnz, double2* M,
                           hipStream_t s);
 

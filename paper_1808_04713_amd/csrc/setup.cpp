@@ -319,9 +319,185 @@ void order_coarse_strips(Handle& h) {
   }
   for (auto& d : h.t_dof) d = perm[d];
   for (auto& d : h.c2_dof) d = perm[d];
-  std::vector<double> y(nK);
-  for (int d = 0; d < nK; ++d) y[perm[d]] = h.dof_y[d];
+  std::vector<double> x(nK), y(nK);
+  std::vector<char> vt(nK);
+  for (int d = 0; d < nK; ++d) {
+    x[perm[d]] = h.dof_x[d];
+    y[perm[d]] = h.dof_y[d];
+    vt[perm[d]] = h.dof_vtx[d];
+  }
+  h.dof_x.swap(x);
   h.dof_y.swap(y);
+  h.dof_vtx.swap(vt);
+  build_transposes(h, true);
+}
+
+// Coarse unknowns that share an element (the sparsity of K), as sorted lists.
+static std::vector<std::vector<int>> coarse_adjacency(const Handle& h) {
+  std::vector<std::vector<int>> elem_dofs(h.E);
+  for (int e = 0; e < h.E; ++e) {
+    auto& v = elem_dofs[e];
+    for (int i = h.cm_off[e]; i < h.cm_off[e + 1]; ++i)
+      for (int t = h.t_ptr[i]; t < h.t_ptr[i + 1]; ++t) v.push_back(h.t_dof[t]);
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+  }
+  std::vector<std::vector<int>> adj(h.nK);
+  for (int e = 0; e < h.E; ++e)
+    for (int a : elem_dofs[e])
+      for (int b : elem_dofs[e])
+        if (a != b) adj[a].push_back(b);
+  for (auto& v : adj) {
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+  }
+  return adj;
+}
+
+// Nested-dissection order of the coarse unknowns for the multifrontal coarse
+// factor (recursive coordinate bisection).  A set is cut at the line through
+// a column (or row) of mesh vertices near its median, across its longer
+// extent; the unknowns on the far side that share an element with the near
+// side form the separator, so the two remaining parts share no element and are
+// eliminated independently.  Sets of at most `leaf` unknowns are leaves.
+// Nodes are numbered in postorder (children before parents); the unknowns a
+// node owns are consecutive in the new numbering, and its boundary lists the
+// later (ancestor) unknowns its subtree is coupled to after elimination.
+void order_coarse_nd(Handle& h, size_t leaf) {
+  const int nK = h.nK;
+  const auto adj = coarse_adjacency(h);
+  struct Node { std::vector<int> own; int child[2] = {-1, -1}; int depth = 0; };
+  std::vector<Node> nodes;
+  std::vector<int> side(nK, -1);
+  std::function<int(std::vector<int>&, int)> build = [&](std::vector<int>& S, int depth) -> int {
+    const int id = int(nodes.size());
+    nodes.emplace_back();
+    nodes[id].depth = depth;
+    if (S.size() <= leaf) {
+      nodes[id].own = S;
+      return id;
+    }
+    double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
+    for (int u : S) {
+      lo[0] = std::min(lo[0], h.dof_x[u]); hi[0] = std::max(hi[0], h.dof_x[u]);
+      lo[1] = std::min(lo[1], h.dof_y[u]); hi[1] = std::max(hi[1], h.dof_y[u]);
+    }
+    std::vector<int> best_sep, best_a, best_b;
+    double best_score = 1e300;
+    for (int axis : {hi[0] - lo[0] >= hi[1] - lo[1] ? 0 : 1, hi[0] - lo[0] >= hi[1] - lo[1] ? 1 : 0}) {
+      const std::vector<double>& c = axis == 0 ? h.dof_x : h.dof_y;
+      std::vector<double> cs;
+      for (int u : S) cs.push_back(c[u]);
+      std::sort(cs.begin(), cs.end());
+      std::vector<double> lines;   // vertex coordinates present in the set
+      for (int u : S)
+        if (h.dof_vtx[u]) lines.push_back(c[u]);
+      std::sort(lines.begin(), lines.end());
+      lines.erase(std::unique(lines.begin(), lines.end()), lines.end());
+      if (lines.empty()) continue;
+      // the vertex lines nearest to the median of the set, a few on each side
+      const double med = cs[cs.size() / 2];
+      const size_t at = size_t(std::lower_bound(lines.begin(), lines.end(), med) - lines.begin());
+      for (size_t q = at >= 3 ? at - 3 : 0; q < std::min(lines.size(), at + 4); ++q) {
+        const double m = lines[q];
+        for (int u : S) side[u] = c[u] < m ? 0 : 1;
+        std::vector<int> sep, a, b;
+        for (int u : S) {
+          if (side[u] == 0) { a.push_back(u); continue; }
+          bool touch = false;
+          for (int v : adj[u])
+            if (side[v] == 0) { touch = true; break; }
+          (touch ? sep : b).push_back(u);
+        }
+        for (int u : S) side[u] = -1;
+        if (a.empty() || b.empty()) continue;
+        const double imb = std::abs(double(a.size()) - double(b.size())) / double(S.size());
+        const double score = double(sep.size()) * (1.0 + 2.0 * imb);
+        if (score < best_score) {
+          best_score = score;
+          best_sep.swap(sep); best_a.swap(a); best_b.swap(b);
+        }
+      }
+      if (best_score < 1e300) break;   // the longer extent gave a cut
+    }
+    if (best_score >= 1e300 || best_sep.size() * 2 > S.size()) {
+      nodes[id].own = S;   // no useful cut: one dense node
+      return id;
+    }
+    S.clear();
+    S.shrink_to_fit();
+    nodes[id].own = best_sep;
+    const int ca = build(best_a, depth + 1);
+    const int cb = build(best_b, depth + 1);
+    nodes[id].child[0] = ca;
+    nodes[id].child[1] = cb;
+    return id;
+  };
+  std::vector<int> all(nK);
+  for (int u = 0; u < nK; ++u) all[u] = u;
+  const int root = build(all, 0);
+  // postorder numbering of nodes and unknowns
+  std::vector<int> post;   // node ids in postorder
+  std::function<void(int)> walk = [&](int t) {
+    for (int c : nodes[t].child)
+      if (c >= 0) walk(c);
+    post.push_back(t);
+  };
+  walk(root);
+  const int nn = int(post.size());
+  std::vector<int> pos_of(nodes.size());
+  for (int q = 0; q < nn; ++q) pos_of[post[q]] = q;
+  std::vector<int> perm(nK, -1);   // old -> new
+  h.nd_off.assign(nn + 1, 0);
+  h.nd_depth.assign(nn, 0);
+  h.nd_child.assign(2 * size_t(nn), -1);
+  int at = 0;
+  for (int q = 0; q < nn; ++q) {
+    const Node& N = nodes[post[q]];
+    std::vector<int> own = N.own;
+    std::sort(own.begin(), own.end());
+    for (int u : own) perm[u] = at++;
+    h.nd_off[q + 1] = at;
+    h.nd_depth[q] = N.depth;
+    for (int k = 0; k < 2; ++k) h.nd_child[2 * size_t(q) + k] = N.child[k] >= 0 ? pos_of[N.child[k]] : -1;
+  }
+  if (at != nK) fail(HDP_E_MESH, "nested dissection lost coarse unknowns");
+  // boundaries: own neighbours and children's boundaries beyond the node's range
+  std::vector<std::vector<int>> bnd(nn);
+  for (int q = 0; q < nn; ++q) {
+    const int end = h.nd_off[q + 1];
+    std::vector<int> b;
+    for (int u : nodes[post[q]].own)
+      for (int v : adj[u])
+        if (perm[v] >= end) b.push_back(perm[v]);
+    for (int k = 0; k < 2; ++k) {
+      const int c = h.nd_child[2 * size_t(q) + k];
+      if (c < 0) continue;
+      for (int v : bnd[c])
+        if (v >= end) b.push_back(v);
+    }
+    std::sort(b.begin(), b.end());
+    b.erase(std::unique(b.begin(), b.end()), b.end());
+    bnd[q].swap(b);
+  }
+  h.nd_boff.assign(nn + 1, 0);
+  h.nd_bnd.clear();
+  for (int q = 0; q < nn; ++q) {
+    h.nd_bnd.insert(h.nd_bnd.end(), bnd[q].begin(), bnd[q].end());
+    h.nd_boff[q + 1] = int64_t(h.nd_bnd.size());
+  }
+  for (auto& d : h.t_dof) d = perm[d];
+  for (auto& d : h.c2_dof) d = perm[d];
+  std::vector<double> x(nK), y(nK);
+  std::vector<char> vt(nK);
+  for (int d = 0; d < nK; ++d) {
+    x[perm[d]] = h.dof_x[d];
+    y[perm[d]] = h.dof_y[d];
+    vt[perm[d]] = h.dof_vtx[d];
+  }
+  h.dof_x.swap(x);
+  h.dof_y.swap(y);
+  h.dof_vtx.swap(vt);
   build_transposes(h, true);
 }
 
@@ -424,6 +600,31 @@ void build_hanging_blocks(Handle& h) {
 }
 
 }  // namespace
+
+void coarse_coo(const Handle& h, std::vector<int64_t>& kidx, std::vector<double2>& kval) {
+  std::vector<std::pair<int64_t, cd>> coo;
+  for (int e = 0; e < h.E; ++e) {
+    const ElemClass& C = h.classes[h.cls[e]];
+    const int co = h.cm_off[e];
+    for (int b = 0; b < C.nr; ++b)
+      for (int a = 0; a < C.nr; ++a) {
+        cd kab = C.Kc(a, b);
+        for (int t = h.t_ptr[co + a]; t < h.t_ptr[co + a + 1]; ++t)
+          for (int u = h.t_ptr[co + b]; u < h.t_ptr[co + b + 1]; ++u)
+            coo.push_back({h.t_dof[t] + int64_t(h.nK) * h.t_dof[u], h.t_coef[t] * kab * h.t_coef[u]});
+      }
+  }
+  std::sort(coo.begin(), coo.end(), [](auto& x, auto& y) { return x.first < y.first; });
+  kidx.clear();
+  kval.clear();
+  for (size_t t = 0; t < coo.size();) {
+    int64_t key = coo[t].first;
+    cd s = 0;
+    while (t < coo.size() && coo[t].first == key) s += coo[t++].second;
+    kidx.push_back(key);
+    kval.push_back(make_double2(s.real(), s.imag()));
+  }
+}
 
 void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
   if (!mesh || !prob || !mesh->leaf || !mesh->degree) fail(HDP_E_ARG, "null mesh or problem");
@@ -725,13 +926,18 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
   // position of each coarse unknown across the mesh (vertex, or edge midpoint) in
   // fine-grid units: orders the coarse unknowns into strips for the coarse factor
   h.dof_y.assign(h.nK, 0.0);
+  h.dof_x.assign(h.nK, 0.0);
+  h.dof_vtx.assign(h.nK, 0);
   for (auto& kv : cids) {
     const auto& key = kv.first;
-    int kind = std::get<0>(key);
+    int kind = std::get<0>(key);   // -1 vertex (x, y); 0 side x = c, y in [lo, hi]; 1 side y = c
     double y = kind == -1 ? double(std::get<2>(key))
                : kind == 0 ? 0.5 * double(std::get<2>(key) + std::get<3>(key))
                            : double(std::get<1>(key));
+    double x = kind == 1 ? 0.5 * double(std::get<2>(key) + std::get<3>(key)) : double(std::get<1>(key));
     h.dof_y[kv.second] = y;
+    h.dof_x[kv.second] = x;
+    h.dof_vtx[kv.second] = kind == -1;
   }
   build_transposes(h, false);
   // ---- dual rows in Algorithm 1 visiting order -----------------------------
@@ -803,7 +1009,13 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
   }
   build_transposes(h, true);
   build_hanging_blocks(h);
-  order_coarse_strips(h);
+  // coarse factor: dense inverse for small coarse spaces (one streaming GEMV per
+  // solve), the nested-dissection factor beyond 12,000 unknowns
+  // (a requested factor gets small blocks, so that small meshes exercise it too)
+  const bool requested = h.coarse_mode >= 0;
+  if (h.coarse_mode < 0) h.coarse_mode = h.nK > 12000 ? 2 : 0;
+  if (h.coarse_mode == 2) order_coarse_nd(h, requested ? 32 : 96);
+  else order_coarse_strips(h);
   // algorithmic work counts
   for (auto& C : h.classes) {
     h.op1_bytes += 16.0 * (C.m + C.nr) * C.m;

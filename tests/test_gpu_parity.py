@@ -195,19 +195,22 @@ def test_batched_rhs_equal_single_solves():
     s.close()
 
 
+@pytest.mark.parametrize("coarse", ["block", "nd"])
 @pytest.mark.parametrize("name", ["uniform_5x5_p7_l3", "scatterer_6x6_p6"])
-def test_block_tridiagonal_coarse_factor(name, oracles):
-    """The strip (block-tridiagonal) coarse factor gives the same operator and
-    solution as the dense inverse, for one and for several right-hand sides."""
+def test_factored_coarse_solvers(name, coarse, oracles):
+    """The strip (block-tridiagonal) and the nested-dissection coarse factors give
+    the same operator and solution as the dense inverse, for one and for several
+    right-hand sides."""
     disc, l, E = oracles[name]
     w = CASES[name]
-    sb = hdp().Solver(w, tol=1e-12, max_iter=400, max_rhs=64, coarse="block")
+    sb = hdp().Solver(w, tol=1e-12, max_iter=400, max_rhs=64, coarse=coarse)
     sd = hdp().Solver(w, tol=1e-12, max_iter=400, max_rhs=64, coarse="dense")
     st = sb.info
-    assert st["coarse_mode"] == 1 and st["coarse_blocks"] >= 2 and st["coarse_residual"] < 1e-12
+    mode, nblk = (1, 2) if coarse == "block" else (2, 3)
+    assert st["coarse_mode"] == mode and st["coarse_blocks"] >= nblk and st["coarse_residual"] < 1e-12
     assert sd.info["coarse_mode"] == 0
     rng = np.random.default_rng(5)
-    for R in (1, 5, 64):   # own sweep kernels at one column, library products above
+    for R in (1, 5, 64):   # one-column kernels, masked lanes, full 64-lane tiles / library products
         v = rng.standard_normal((E.nlam, R)) + 1j * rng.standard_normal((E.nlam, R))
         vd = torch.from_numpy(v).cuda()
         assert rel(sb.apply_interface(vd, "fp64").cpu().numpy(), sd.apply_interface(vd, "fp64").cpu().numpy()) < 1e-12
