@@ -267,18 +267,18 @@ static void build_coarse_nd(Handle& h, const std::vector<int64_t>& kidx, const s
   d.nd_boff = upload(h, h.nd_boff);
   d.nd_bnd = upload(h, h.nd_bnd);
   d.nd_uoff = upload(h, f.uoff);
+  d.nd_push = upload(h, f.push);
   d.nd_mD = upload(h, f.mD);
   d.nd_mL = upload(h, f.mL);
   d.nd_mLt = upload(h, f.mLt);
-  d.nd_asm_own = upload(h, f.asm_own);
-  d.nd_asm_bnd = upload(h, f.asm_bnd);
   d.nd_t1f = upload(h, f.t1f);
   d.nd_t1b = upload(h, f.t1b);
   d.nd_tRf = upload(h, f.tRf);
   d.nd_tRb = upload(h, f.tRb);
   const size_t Rp = size_t(pow2ceil(h.max_rhs));
-  d.nd_Y = dalloc<double2>(h, size_t(h.nK) * Rp);
-  d.nd_U = dalloc<double2>(h, size_t(std::max<int64_t>(1, f.urows)) * Rp);
+  if (Rp > 1 && f.part_tasks > 0) d.nd_P = dalloc<double2>(h, size_t(f.part_tasks) * 32 * 64);
+  d.nd_urows = f.urows;
+  d.nd_FA = dalloc<double2>(h, size_t(h.nK + f.urows) * Rp);
   h.nd_levels = f.levels;
   h.coarse_mode = 2;
   h.coarse_bytes = 16.0 * double(f.fac.size());
@@ -288,19 +288,21 @@ static void build_coarse_nd(Handle& h, const std::vector<int64_t>& kidx, const s
 static void coarse_solve_nd(Handle& h, const double2* g, double2* w, int R) {
   auto& d = h.d;
   NDView v;
-  v.off = d.nd_off; v.boff = d.nd_boff; v.bnd = d.nd_bnd; v.uoff = d.nd_uoff;
+  v.off = d.nd_off; v.boff = d.nd_boff; v.bnd = d.nd_bnd; v.uoff = d.nd_uoff; v.push = d.nd_push;
   v.mD = d.nd_mD; v.mL = d.nd_mL; v.mLt = d.nd_mLt; v.fac = d.nd_fac;
+  double2* F = d.nd_FA;
+  double2* A = d.nd_FA + int64_t(h.nK) * R;
+  launch_fill_zero(F, (int64_t(h.nK) + d.nd_urows) * R, h.stream);   // a fill kernel (capturable)
   const int nd = int(h.nd_levels.size());
   for (int L = nd - 1; L >= 0; --L) {   // leaves first
     const NDLevel& lv = h.nd_levels[L];
-    launch_nd_asm(d.nd_asm_own + lv.own0, lv.nown, d.nd_asm_bnd + lv.bnd0, lv.nbnd, g, d.nd_Y, d.nd_U, R, h.stream);
-    if (R == 1) launch_nd_fwd(d.nd_t1f + lv.f1, lv.nf1, v, d.nd_Y, d.nd_U, R, h.stream);
-    else launch_nd_fwd(d.nd_tRf + lv.fR, lv.nfR, v, d.nd_Y, d.nd_U, R, h.stream);
+    if (R == 1) launch_nd_fwd1(d.nd_t1f + lv.f1, lv.nf1, v, g, F, A, h.stream);
+    else launch_nd_tiles(false, d.nd_tRf + lv.fR, lv.nfR, lv.Sf, v, g, F, A, w, R, d.nd_P, h.stream);
   }
   for (int L = 0; L < nd; ++L) {   // root first
     const NDLevel& lv = h.nd_levels[L];
-    if (R == 1) launch_nd_bwd(d.nd_t1b + lv.b1, lv.nb1, v, d.nd_Y, w, R, h.stream);
-    else launch_nd_bwd(d.nd_tRb + lv.bR, lv.nbR, v, d.nd_Y, w, R, h.stream);
+    if (R == 1) launch_nd_bwd1(d.nd_t1b + lv.b1, lv.nb1, v, g, F, w, h.stream);
+    else launch_nd_tiles(true, d.nd_tRb + lv.bR, lv.nbR, lv.Sb, v, g, F, A, w, R, d.nd_P, h.stream);
   }
 }
 

@@ -227,43 +227,67 @@ void nd_factor(const Handle& h, const std::vector<int64_t>& kidx, const std::vec
     for (auto& th : pool) th.join();
     if (!err.empty()) fail(HDP_E_COARSE, err);
   }
-  // front assembly entries and row tasks, depth by depth
+  // where each update row goes in the parent's front
+  std::vector<int> parent(nn, -1);
+  for (int t = 0; t < nn; ++t)
+    for (int k = 0; k < 2; ++k)
+      if (h.nd_child[2 * size_t(t) + k] >= 0) parent[h.nd_child[2 * size_t(t) + k]] = t;
+  f.push.assign(size_t(std::max<int64_t>(1, urows)), 0);
+  for (int t = 0; t < nn; ++t) {
+    const int p = parent[t];
+    if (nB_of(t) > 0 && p < 0) fail(HDP_E_COARSE, "nested-dissection root with a boundary");
+    const int* Bt = h.nd_bnd.data() + h.nd_boff[t];
+    for (int a = 0; a < nB_of(t); ++a) {
+      const int g = Bt[a];
+      if (g >= h.nd_off[p] && g < h.nd_off[p + 1]) {
+        f.push[f.uoff[t] + a] = -1 - g;
+      } else {
+        const int* Bp = h.nd_bnd.data() + h.nd_boff[p];
+        const int* it = std::lower_bound(Bp, Bp + nB_of(p), g);
+        if (it == Bp + nB_of(p) || *it != g) fail(HDP_E_COARSE, "child boundary outside its parent's front");
+        f.push[f.uoff[t] + a] = int(f.uoff[p] + (it - Bp));
+      }
+    }
+  }
+  // row tasks, depth by depth
   f.levels.assign(maxd + 1, NDLevel{});
-  f.asm_own.clear(); f.asm_bnd.clear(); f.t1f.clear(); f.t1b.clear(); f.tRf.clear(); f.tRb.clear();
+  f.t1f.clear(); f.t1b.clear(); f.tRf.clear(); f.tRb.clear();
+  f.part_tasks = 0;
   for (int dpt = 0; dpt <= maxd; ++dpt) {
     NDLevel& L = f.levels[dpt];
-    L.own0 = int(f.asm_own.size()); L.bnd0 = int(f.asm_bnd.size());
-    L.f1 = int(f.t1f.size()); L.b1 = int(f.t1b.size()); L.fR = int(f.tRf.size()); L.bR = int(f.tRb.size());
+    L.f1 = int(f.t1f.size()); L.b1 = int(f.t1b.size());
     for (int t : by_depth[dpt]) {
-      const int off = h.nd_off[t], nI = nI_of(t), nB = nB_of(t);
-      const int* B = h.nd_bnd.data() + h.nd_boff[t];
-      std::vector<int3> own(nI), bnd(nB);
-      for (int i = 0; i < nI; ++i) own[i] = make_int3(off + i, -1, -1);
-      for (int b = 0; b < nB; ++b) bnd[b] = make_int3(int(f.uoff[t] + b), -1, -1);
-      for (int k = 0; k < 2; ++k) {
-        const int c = h.nd_child[2 * size_t(t) + k];
-        if (c < 0) continue;
-        const int* Bc = h.nd_bnd.data() + h.nd_boff[c];
-        for (int a = 0; a < nB_of(c); ++a) {
-          const int g = Bc[a];
-          const int src = int(f.uoff[c] + a);
-          int3* e;
-          if (g >= off && g < off + nI) e = &own[g - off];
-          else e = &bnd[std::lower_bound(B, B + nB, g) - B];
-          if (e->y < 0) e->y = src;
-          else e->z = src;
-        }
-      }
-      f.asm_own.insert(f.asm_own.end(), own.begin(), own.end());
-      f.asm_bnd.insert(f.asm_bnd.end(), bnd.begin(), bnd.end());
-      for (int b = 0; b < nB; ++b) f.t1f.push_back(make_int2(t, b));
-      for (int i = 0; i < nI; ++i) f.t1b.push_back(make_int2(t, i));
-      for (int j = 0; j < nB; j += 32) f.tRf.push_back(make_int2(t, j));
-      for (int j = 0; j < nI; j += 32) f.tRb.push_back(make_int2(t, j));
+      for (int b = 0; b < nB_of(t); ++b) f.t1f.push_back(make_int2(t, b));
+      for (int i = 0; i < nI_of(t); ++i) f.t1b.push_back(make_int2(t, i));
     }
-    L.nown = int(f.asm_own.size()) - L.own0; L.nbnd = int(f.asm_bnd.size()) - L.bnd0;
     L.nf1 = int(f.t1f.size()) - L.f1; L.nb1 = int(f.t1b.size()) - L.b1;
-    L.nfR = int(f.tRf.size()) - L.fR; L.nbR = int(f.tRb.size()) - L.bR;
+    // tiles of 32 outputs for several columns; levels with few tiles split each
+    // tile's sum so that about 1024 workgroups run
+    for (int bwd = 0; bwd < 2; ++bwd) {
+      int ntiles = 0, kmax = 0;
+      for (int t : by_depth[dpt]) {
+        const int nout = bwd ? nI_of(t) : nB_of(t);
+        ntiles += (nout + 31) / 32;
+        if (nout > 0) kmax = std::max(kmax, bwd ? nI_of(t) + nB_of(t) : nI_of(t));
+      }
+      int S = 1;
+      if (ntiles > 0) S = std::max(1, std::min((1024 + ntiles - 1) / ntiles, (kmax + 31) / 32));
+      std::vector<int4>& T = bwd ? f.tRb : f.tRf;
+      const int first = int(T.size());
+      for (int t : by_depth[dpt]) {
+        const int nout = bwd ? nI_of(t) : nB_of(t);
+        const int K = bwd ? nI_of(t) + nB_of(t) : nI_of(t);
+        const int chunk = (K + S - 1) / S;
+        for (int j = 0; j < nout; j += 32)
+          for (int c = 0; c < S; ++c) {
+            const int i0 = std::min(K, c * chunk), i1 = std::min(K, (c + 1) * chunk);
+            T.push_back(make_int4(t, j, i0, i1));
+          }
+      }
+      if (S > 1) f.part_tasks = std::max<int64_t>(f.part_tasks, int64_t(ntiles) * S);
+      if (bwd) { L.bR = first; L.nbR = ntiles; L.Sb = S; }
+      else { L.fR = first; L.nfR = ntiles; L.Sf = S; }
+    }
   }
 }
 

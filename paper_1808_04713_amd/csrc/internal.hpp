@@ -71,8 +71,8 @@ struct Prof {
 // One depth of the nested-dissection tree: ranges in the assembly-entry and
 // task arrays (R = 1 tasks are rows, other tasks 32-row tiles).
 struct NDLevel {
-  int own0 = 0, nown = 0, bnd0 = 0, nbnd = 0;
-  int f1 = 0, nf1 = 0, b1 = 0, nb1 = 0, fR = 0, nfR = 0, bR = 0, nbR = 0;
+  int f1 = 0, nf1 = 0, b1 = 0, nb1 = 0;
+  int fR = 0, nfR = 0, Sf = 1, bR = 0, nbR = 0, Sb = 1;   // first task, tiles, splits per tile
 };
 
 struct Handle {
@@ -178,11 +178,13 @@ struct Handle {
     int64_t* cls_Moff = nullptr;
     double2 *cblk = nullptr, *ctmp = nullptr;   // block-tridiagonal coarse factor
     // nested-dissection coarse factor
-    double2 *nd_fac = nullptr, *nd_Y = nullptr, *nd_U = nullptr;
-    int *nd_off = nullptr, *nd_bnd = nullptr;
+    double2 *nd_fac = nullptr, *nd_FA = nullptr;   // FA: front accumulators, n_K then update rows
+    int *nd_off = nullptr, *nd_bnd = nullptr, *nd_push = nullptr;
     int64_t *nd_boff = nullptr, *nd_uoff = nullptr, *nd_mD = nullptr, *nd_mL = nullptr, *nd_mLt = nullptr;
-    int3 *nd_asm_own = nullptr, *nd_asm_bnd = nullptr;
-    int2 *nd_t1f = nullptr, *nd_t1b = nullptr, *nd_tRf = nullptr, *nd_tRb = nullptr;
+    int64_t nd_urows = 0;
+    int2 *nd_t1f = nullptr, *nd_t1b = nullptr;
+    int4 *nd_tRf = nullptr, *nd_tRb = nullptr;
+    double2* nd_P = nullptr;   // partial tiles of the split top levels
     int* cb_off = nullptr;
     int64_t* cb_D = nullptr;
     // per-class tables
@@ -266,15 +268,19 @@ void coarse_coo(const Handle& h, std::vector<int64_t>& kidx, std::vector<double2
 
 // coarse_nd.cpp: the nested-dissection factor assembled on the host.  Per node
 // the blocks Dinv (nI x nI), L (nB x nI) and Lt = L^T, row-major, back to back in
-// fac; U rows hold the nodes' update vectors.  Per tree depth: the front
-// assembly entries and the row tasks of the device sweeps.
+// fac; update rows (uoff) hold the boundary entries of the nodes' fronts, and
+// push names each row's place in the parent's front (-1 - unknown for a row the
+// parent owns, else the parent's update row).  Per tree depth: the row tasks of
+// the device sweeps.
 struct NDHost {
   std::vector<double2> fac;
   std::vector<int64_t> uoff, mD, mL, mLt;
   int64_t urows = 0;
-  std::vector<int3> asm_own, asm_bnd;
-  std::vector<int2> t1f, t1b, tRf, tRb;
+  std::vector<int> push;
+  std::vector<int2> t1f, t1b;
+  std::vector<int4> tRf, tRb;
   std::vector<NDLevel> levels;
+  int64_t part_tasks = 0;     // largest split level (tiles x splits)
   double flops_per_col = 0;   // 8 (nI^2 + 2 nB nI) summed over the nodes
 };
 void nd_factor(const Handle& h, const std::vector<int64_t>& kidx, const std::vector<double2>& kval, NDHost& f);

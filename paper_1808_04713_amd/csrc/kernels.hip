@@ -389,29 +389,19 @@ __global__ void __launch_bounds__(NT) k_strip_diag_mv(const int* __restrict__ of
 // Nested-dissection coarse solve.  Node t owns the coarse unknowns
 // [off_t, off_t + nI_t) and has the boundary list bnd_t (nB_t ancestor unknowns);
 // its factor blocks are Dinv_t (nI x nI), L_t (nB x nI) and Lt_t = L_t^T (nI x nB),
-// all row-major.  Forward, deepest level first:
-//   front = [g_I; 0] + extend-add of the children's updates U_c
-//   Y_I = front_I,  U_t = front_B - L_t Y_I
+// all row-major.  Forward, deepest level first, with Y_I = g_I + F_I:
+//   U_t = A_t - L_t Y_I, added into the parent's front
+// where F (own rows) and A (boundary rows) collect the children's updates;
 // backward, root first:  X_I = Dinv_t Y_I - Lt_t X_B.
+// A front entry receives at most two additions onto zero (one per child), so
+// the atomic additions give the same sums in any order.  push[u] names where
+// update row u goes: the parent's own row -1 - push[u] of F, or row push[u] of A.
 
-// front assembly: one thread per (entry, column)
-__global__ void k_nd_asm(const int3* __restrict__ own, int nown, const int3* __restrict__ bnd, int nbnd,
-                         const double2* __restrict__ g, double2* __restrict__ Y, double2* __restrict__ U, int R) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)(nown + nbnd) * R) return;
-  const int q = int(e / R), r = int(e % R);
-  const int3 t = q < nown ? own[q] : bnd[q - nown];
-  double2 a = q < nown ? g[(int64_t)t.x * R + r] : make_double2(0, 0);
-  if (t.y >= 0) {
-    const double2 u = U[(int64_t)t.y * R + r];
-    a.x += u.x; a.y += u.y;
-  }
-  if (t.z >= 0) {
-    const double2 u = U[(int64_t)t.z * R + r];
-    a.x += u.x; a.y += u.y;
-  }
-  if (q < nown) Y[(int64_t)t.x * R + r] = a;
-  else U[(int64_t)t.x * R + r] = a;
+__device__ __forceinline__ void nd_push(double2* __restrict__ F, double2* __restrict__ A, int dst, int64_t col,
+                                        int R, double2 v) {
+  double2* p = dst < 0 ? F + (int64_t)(-1 - dst) * R + col : A + (int64_t)dst * R + col;
+  unsafeAtomicAdd(&p->x, v.x);
+  unsafeAtomicAdd(&p->y, v.y);
 }
 
 // Node tables on the device.
@@ -419,7 +409,8 @@ struct NDNodes {
   const int* off;          // [n + 1]
   const int64_t* boff;     // [n + 1] into bnd
   const int* bnd;
-  const int64_t* uoff;     // row offset of U_t
+  const int64_t* uoff;     // first update row of node t
+  const int* push;         // per update row
   const int64_t* mD;       // factor offsets
   const int64_t* mL;
   const int64_t* mLt;
@@ -428,7 +419,8 @@ struct NDNodes {
 
 // One column: one wave per output row, lanes over the row.
 __global__ void __launch_bounds__(NT) k_nd_fwd1(const int2* __restrict__ task, int ntask, NDNodes nd,
-                                                const double2* __restrict__ Y, double2* __restrict__ U) {
+                                                const double2* __restrict__ g, double2* __restrict__ F,
+                                                double2* __restrict__ A) {
   const int lane = threadIdx.x & 63;
   const int q = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
   if (q >= ntask) return;
@@ -437,23 +429,25 @@ __global__ void __launch_bounds__(NT) k_nd_fwd1(const int2* __restrict__ task, i
   const double2* Lr = nd.fac + nd.mL[t] + (int64_t)nI * b;
   double ax = 0, ay = 0;
   for (int i = lane; i < nI; i += 64) {
-    const double2 m = Lr[i], y = Y[o + i];
-    ax += m.x * y.x - m.y * y.y;
-    ay += m.x * y.y + m.y * y.x;
+    const double2 m = Lr[i], y0 = g[o + i], y1 = F[o + i];
+    const double yx = y0.x + y1.x, yy = y0.y + y1.y;
+    ax += m.x * yx - m.y * yy;
+    ay += m.x * yy + m.y * yx;
   }
   for (int sh = 32; sh > 0; sh >>= 1) {
     ax += __shfl_xor(ax, sh, 64);
     ay += __shfl_xor(ay, sh, 64);
   }
   if (lane == 0) {
-    double2* u = U + nd.uoff[t] + b;
-    const double2 f = *u;
-    *u = make_double2(f.x - ax, f.y - ay);
+    const int64_t u = nd.uoff[t] + b;
+    const double2 a = A[u];
+    nd_push(F, A, nd.push[u], 0, 1, make_double2(a.x - ax, a.y - ay));
   }
 }
 
 __global__ void __launch_bounds__(NT) k_nd_bwd1(const int2* __restrict__ task, int ntask, NDNodes nd,
-                                                const double2* __restrict__ Y, double2* __restrict__ X) {
+                                                const double2* __restrict__ g, const double2* __restrict__ F,
+                                                double2* __restrict__ X) {
   const int lane = threadIdx.x & 63;
   const int q = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
   if (q >= ntask) return;
@@ -465,9 +459,10 @@ __global__ void __launch_bounds__(NT) k_nd_bwd1(const int2* __restrict__ task, i
   const double2* Lr = nd.fac + nd.mLt[t] + (int64_t)nB * i;
   double ax = 0, ay = 0;
   for (int k = lane; k < nI; k += 64) {
-    const double2 m = Dr[k], y = Y[o + k];
-    ax += m.x * y.x - m.y * y.y;
-    ay += m.x * y.y + m.y * y.x;
+    const double2 m = Dr[k], y0 = g[o + k], y1 = F[o + k];
+    const double yx = y0.x + y1.x, yy = y0.y + y1.y;
+    ax += m.x * yx - m.y * yy;
+    ay += m.x * yy + m.y * yx;
   }
   for (int b = lane; b < nB; b += 64) {
     const double2 m = Lr[b], x = X[nd.bnd[bo + b]];
@@ -482,17 +477,20 @@ __global__ void __launch_bounds__(NT) k_nd_bwd1(const int2* __restrict__ task, i
 }
 
 // Several columns (R <= 64, lane = column): a workgroup owns 32 outputs of a
-// node; 32-row tiles of the factor block go through LDS and are read back as
-// wave-wide broadcasts, the operand rows are read coalesced (gathered through
-// xidx when given).  acc += sum_i M[i + K j] X_row(i) for this thread's 8 outputs.
-__device__ __forceinline__ void nd_mm_core(const double2* __restrict__ M, int K, int n_out, int j0,
-                                           const double2* __restrict__ X, int64_t xbase,
-                                           const int* __restrict__ xidx, int R, double2 (&acc)[8]) {
+// node and a range [i0, i1) of the summation (the top levels of the tree hold few
+// large nodes, so their sums are split over several workgroups and the partial
+// tiles added by k_nd_reduce).  32-row tiles of the factor block go through LDS
+// and are read back as wave-wide broadcasts; the operand rows are read coalesced
+// (gathered through xidx when given; X2, when given, is added to X).
+// acc += sum_i M[i + K j] X_row(i) for this thread's 8 outputs.
+__device__ __forceinline__ void nd_mm_core(const double2* __restrict__ M, int K, int i0, int i1, int n_out, int j0,
+                                           const double2* __restrict__ X, const double2* __restrict__ X2,
+                                           int64_t xbase, const int* __restrict__ xidx, int R, double2 (&acc)[8]) {
   __shared__ double2 Ms[SMK][SMJ + 1];
   const int r = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const bool live = r < R;
-  for (int ib = 0; ib < K; ib += SMK) {
-    const int nk = min(SMK, K - ib);
+  for (int ib = i0; ib < i1; ib += SMK) {
+    const int nk = min(SMK, i1 - ib);
     for (int e = threadIdx.x; e < SMK * SMJ; e += NT) {
       const int jj = e / SMK, kk = e % SMK;
       Ms[kk][jj] = (kk < nk && j0 + jj < n_out) ? M[(ib + kk) + (int64_t)K * (j0 + jj)] : make_double2(0, 0);
@@ -501,7 +499,12 @@ __device__ __forceinline__ void nd_mm_core(const double2* __restrict__ M, int K,
     if (live)
       for (int kk = 0; kk < nk; ++kk) {
         const int64_t row = xidx ? (int64_t)xidx[ib + kk] : xbase + ib + kk;
-        const double2 x = X[row * R + r];
+        double2 x = X[row * R + r];
+        if (X2) {
+          const double2 x2 = X2[row * R + r];
+          x.x += x2.x;
+          x.y += x2.y;
+        }
 #pragma unroll
         for (int t = 0; t < 8; ++t) acc[t] = cfma(Ms[kk][wv * 8 + t], x, acc[t]);
       }
@@ -509,43 +512,101 @@ __device__ __forceinline__ void nd_mm_core(const double2* __restrict__ M, int K,
   }
 }
 
-__global__ void __launch_bounds__(NT) k_nd_fwdR(const int2* __restrict__ task, NDNodes nd,
-                                                const double2* __restrict__ Y, double2* __restrict__ U, int R) {
-  const int t = task[blockIdx.x].x, j0 = task[blockIdx.x].y;
+// Partial tiles: P[task][32][64].  A task is {node, first output, i0, i1}.
+__device__ __forceinline__ void nd_store_part(double2* __restrict__ P, const double2 (&acc)[8], int R) {
+  const int r = threadIdx.x & 63, jw = (threadIdx.x >> 6) * 8;
+  if (r >= R) return;
+  double2* dst = P + (int64_t)blockIdx.x * SMJ * 64;
+  for (int q = 0; q < 8; ++q) dst[(jw + q) * 64 + r] = acc[q];
+}
+
+// U_t = A_t - L_t Y_I over the task's range of I (into P when the sum is split).
+__global__ void __launch_bounds__(NT) k_nd_fwdR(const int4* __restrict__ task, NDNodes nd,
+                                                const double2* __restrict__ g, double2* __restrict__ F,
+                                                double2* __restrict__ A, int R, double2* __restrict__ P) {
+  const int4 tk = task[blockIdx.x];
+  const int t = tk.x, j0 = tk.y;
   const int o = nd.off[t], nI = nd.off[t + 1] - o;
   const int nB = int(nd.boff[t + 1] - nd.boff[t]);
   double2 acc[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) acc[q] = make_double2(0, 0);
-  nd_mm_core(nd.fac + nd.mL[t], nI, nB, j0, Y, o, nullptr, R, acc);
+  nd_mm_core(nd.fac + nd.mL[t], nI, tk.z, tk.w, nB, j0, g, F, o, nullptr, R, acc);
+  if (P) {
+    nd_store_part(P, acc, R);
+    return;
+  }
   const int r = threadIdx.x & 63, jw = j0 + (threadIdx.x >> 6) * 8;
   if (r >= R) return;
   for (int q = 0; q < 8; ++q) {
     const int j = jw + q;
     if (j >= nB) break;
-    double2* u = U + (nd.uoff[t] + j) * R + r;
-    const double2 f = *u;
-    *u = make_double2(f.x - acc[q].x, f.y - acc[q].y);
+    const int64_t u = nd.uoff[t] + j;
+    const double2 a = A[u * R + r];
+    nd_push(F, A, nd.push[u], r, R, make_double2(a.x - acc[q].x, a.y - acc[q].y));
   }
 }
 
-__global__ void __launch_bounds__(NT) k_nd_bwdR(const int2* __restrict__ task, NDNodes nd,
-                                                const double2* __restrict__ Y, double2* __restrict__ X, int R) {
-  const int t = task[blockIdx.x].x, j0 = task[blockIdx.x].y;
+// X_I = Dinv_t Y_I - Lt_t X_B; the summation runs over [0, nI) for the first
+// product and [nI, nI + nB) for the second, of which the task takes [i0, i1).
+__global__ void __launch_bounds__(NT) k_nd_bwdR(const int4* __restrict__ task, NDNodes nd,
+                                                const double2* __restrict__ g, const double2* __restrict__ F,
+                                                double2* __restrict__ X, int R, double2* __restrict__ P) {
+  const int4 tk = task[blockIdx.x];
+  const int t = tk.x, j0 = tk.y;
   const int o = nd.off[t], nI = nd.off[t + 1] - o;
   const int64_t bo = nd.boff[t];
   const int nB = int(nd.boff[t + 1] - bo);
   double2 a1[8], a2[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) a1[q] = a2[q] = make_double2(0, 0);
-  nd_mm_core(nd.fac + nd.mD[t], nI, nI, j0, Y, o, nullptr, R, a1);
-  if (nB > 0) nd_mm_core(nd.fac + nd.mLt[t], nB, nI, j0, X, 0, nd.bnd + bo, R, a2);
+  const int e1 = min(tk.w, nI);
+  if (tk.z < e1) nd_mm_core(nd.fac + nd.mD[t], nI, tk.z, e1, nI, j0, g, F, o, nullptr, R, a1);
+  const int s2 = max(tk.z, nI) - nI, e2 = tk.w - nI;
+  if (s2 < e2) nd_mm_core(nd.fac + nd.mLt[t], nB, s2, e2, nI, j0, X, nullptr, 0, nd.bnd + bo, R, a2);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) a1[q] = make_double2(a1[q].x - a2[q].x, a1[q].y - a2[q].y);
+  if (P) {
+    nd_store_part(P, a1, R);
+    return;
+  }
   const int r = threadIdx.x & 63, jw = j0 + (threadIdx.x >> 6) * 8;
   if (r >= R) return;
   for (int q = 0; q < 8; ++q) {
     const int j = jw + q;
     if (j >= nI) break;
-    X[((int64_t)o + j) * R + r] = make_double2(a1[q].x - a2[q].x, a1[q].y - a2[q].y);
+    X[((int64_t)o + j) * R + r] = a1[q];
+  }
+}
+
+// Sums the S partial tiles of each output tile (tasks q S .. q S + S - 1 share
+// node and first output) and finishes the step: U = A - sum pushed to the
+// parent (forward) or X = sum (backward).
+__global__ void k_nd_reduce(const int4* __restrict__ task, int ntiles, int S, const double2* __restrict__ P,
+                            NDNodes nd, double2* __restrict__ F, double2* __restrict__ A, double2* __restrict__ X,
+                            int R, int bwd) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)ntiles * SMJ * R) return;
+  const int r = int(e % R);
+  const int jj = int((e / R) % SMJ);
+  const int q = int(e / ((int64_t)R * SMJ));
+  const int4 tk = task[(int64_t)q * S];
+  const int t = tk.x, j = tk.y + jj;
+  const int o = nd.off[t], nI = nd.off[t + 1] - o;
+  const int n_out = bwd ? nI : int(nd.boff[t + 1] - nd.boff[t]);
+  if (j >= n_out) return;
+  double sx = 0, sy = 0;
+  for (int c = 0; c < S; ++c) {
+    const double2 v = P[((int64_t)q * S + c) * SMJ * 64 + jj * 64 + r];
+    sx += v.x;
+    sy += v.y;
+  }
+  if (bwd) {
+    X[((int64_t)o + j) * R + r] = make_double2(sx, sy);
+  } else {
+    const int64_t u = nd.uoff[t] + j;
+    const double2 a = A[u * R + r];
+    nd_push(F, A, nd.push[u], r, R, make_double2(a.x - sx, a.y - sy));
   }
 }
 
@@ -1866,31 +1927,33 @@ void launch_fill_zero(double2* x, int64_t count, hipStream_t s) {
   HIPCHECK(hipGetLastError());
 }
 
-void launch_nd_asm(const int3* own, int nown, const int3* bnd, int nbnd, const double2* g, double2* Y, double2* U,
-                   int R, hipStream_t s) {
-  const int64_t n = int64_t(nown + nbnd) * R;
-  if (n == 0) return;
-  hipLaunchKernelGGL(k_nd_asm, dim3(nblocks(n)), dim3(NT), 0, s, own, nown, bnd, nbnd, g, Y, U, R);
+void launch_nd_fwd1(const int2* task, int ntask, const NDView& v, const double2* g, double2* F, double2* A,
+                    hipStream_t s) {
+  if (ntask == 0) return;
+  const NDNodes nd{v.off, v.boff, v.bnd, v.uoff, v.push, v.mD, v.mL, v.mLt, v.fac};
+  hipLaunchKernelGGL(k_nd_fwd1, dim3(nblocks(ntask, NT / 64)), dim3(NT), 0, s, task, ntask, nd, g, F, A);
   HIPCHECK(hipGetLastError());
 }
 
-void launch_nd_fwd(const int2* task, int ntask, const NDView& v, const double2* Y, double2* U, int R, hipStream_t s) {
+void launch_nd_bwd1(const int2* task, int ntask, const NDView& v, const double2* g, const double2* F, double2* X,
+                    hipStream_t s) {
   if (ntask == 0) return;
-  const NDNodes nd{v.off, v.boff, v.bnd, v.uoff, v.mD, v.mL, v.mLt, v.fac};
-  if (R == 1)
-    hipLaunchKernelGGL(k_nd_fwd1, dim3(nblocks(ntask, NT / 64)), dim3(NT), 0, s, task, ntask, nd, Y, U);
-  else
-    hipLaunchKernelGGL(k_nd_fwdR, dim3(ntask), dim3(NT), 0, s, task, nd, Y, U, R);
+  const NDNodes nd{v.off, v.boff, v.bnd, v.uoff, v.push, v.mD, v.mL, v.mLt, v.fac};
+  hipLaunchKernelGGL(k_nd_bwd1, dim3(nblocks(ntask, NT / 64)), dim3(NT), 0, s, task, ntask, nd, g, F, X);
   HIPCHECK(hipGetLastError());
 }
 
-void launch_nd_bwd(const int2* task, int ntask, const NDView& v, const double2* Y, double2* X, int R, hipStream_t s) {
-  if (ntask == 0) return;
-  const NDNodes nd{v.off, v.boff, v.bnd, v.uoff, v.mD, v.mL, v.mLt, v.fac};
-  if (R == 1)
-    hipLaunchKernelGGL(k_nd_bwd1, dim3(nblocks(ntask, NT / 64)), dim3(NT), 0, s, task, ntask, nd, Y, X);
-  else
-    hipLaunchKernelGGL(k_nd_bwdR, dim3(ntask), dim3(NT), 0, s, task, nd, Y, X, R);
+void launch_nd_tiles(bool bwd, const int4* task, int ntiles, int S, const NDView& v, const double2* g, double2* F,
+                     double2* A, double2* X, int R, double2* P, hipStream_t s) {
+  if (ntiles == 0) return;
+  const NDNodes nd{v.off, v.boff, v.bnd, v.uoff, v.push, v.mD, v.mL, v.mLt, v.fac};
+  double2* part = S > 1 ? P : nullptr;
+  const unsigned nt = unsigned(ntiles) * unsigned(S);
+  if (bwd) hipLaunchKernelGGL(k_nd_bwdR, dim3(nt), dim3(NT), 0, s, task, nd, g, F, X, R, part);
+  else hipLaunchKernelGGL(k_nd_fwdR, dim3(nt), dim3(NT), 0, s, task, nd, g, F, A, R, part);
+  if (S > 1)
+    hipLaunchKernelGGL(k_nd_reduce, dim3(nblocks(int64_t(ntiles) * SMJ * R)), dim3(NT), 0, s, task, ntiles, S, P, nd,
+                       F, A, X, R, bwd ? 1 : 0);
   HIPCHECK(hipGetLastError());
 }
 

@@ -64,20 +64,28 @@ void launch_axpby(const double2* x, const double2* y, double2* z, int64_t count,
 void launch_cast_f(const double2* x, float2* y, int64_t count, hipStream_t s);
 void launch_cast_d(const float2* x, double2* y, int64_t count, hipStream_t s);
 // Nested-dissection coarse solve (device views of the node tables and the factor).
+// F (n_K rows) and A (update rows) start at zero and collect the children's
+// updates; push[u] < 0 sends update row u to F row -1 - push[u], else to A row push[u].
 struct NDView {
   const int* off = nullptr;
   const int64_t* boff = nullptr;
   const int* bnd = nullptr;
-  const int64_t *uoff = nullptr, *mD = nullptr, *mL = nullptr, *mLt = nullptr;
+  const int64_t* uoff = nullptr;
+  const int* push = nullptr;
+  const int64_t *mD = nullptr, *mL = nullptr, *mLt = nullptr;
   const double2* fac = nullptr;
 };
-// front assembly of one level: own entries {row, child row 1, child row 2} write
-// Y[row] = g[row] + U[c1] + U[c2]; boundary entries {U row, c1, c2} write U[row] = U[c1] + U[c2]
-void launch_nd_asm(const int3* own, int nown, const int3* bnd, int nbnd, const double2* g, double2* Y, double2* U,
-                   int R, hipStream_t s);
-// tasks: {node, row} at R = 1, {node, first of 32 rows} otherwise
-void launch_nd_fwd(const int2* task, int ntask, const NDView& v, const double2* Y, double2* U, int R, hipStream_t s);
-void launch_nd_bwd(const int2* task, int ntask, const NDView& v, const double2* Y, double2* X, int R, hipStream_t s);
+// one column: tasks {node, row}; forward U = A - L (g + F)_I pushed to the parent,
+// backward X_I = Dinv (g + F)_I - Lt X_B
+void launch_nd_fwd1(const int2* task, int ntask, const NDView& v, const double2* g, double2* F, double2* A,
+                    hipStream_t s);
+void launch_nd_bwd1(const int2* task, int ntask, const NDView& v, const double2* g, const double2* F, double2* X,
+                    hipStream_t s);
+// several columns: ntiles output tiles of 32 rows, each split into S tasks
+// {node, first row, i0, i1} over the summation; with S > 1 the partial tiles go
+// to P (ntiles * S * 32 * 64 values) and a second kernel adds them
+void launch_nd_tiles(bool bwd, const int4* task, int ntiles, int S, const NDView& v, const double2* g, double2* F,
+                     double2* A, double2* X, int R, double2* P, hipStream_t s);
 void launch_dense_scatter(const int64_t* idx, const double2* val, int64_t nnz, double2* M,
                           hipStream_t s);
 
