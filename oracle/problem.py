@@ -33,6 +33,48 @@ def coarse_order(w, mesh=None):
     return lg.dispersion_l(kh, 1.0)
 
 
+def robin_labels(mesh):
+    """Signs for the Robin-modified local problems (Sec. 2.3.4): a breadth-first
+    spanning tree of the element adjacency graph from leaf 0, labelled +1 on even
+    and -1 on odd levels.  Neighbours are taken side by side (left, right, bottom,
+    top) and, across one side, in increasing leaf order, so that the labelling is
+    reproducible."""
+    lab = np.zeros(mesh.E, int)
+    depth = -np.ones(mesh.E, int)
+    depth[0] = 0
+    queue = [0]
+    while queue:
+        nxt = []
+        for e in queue:
+            for side in (1, 2, 3, 4):
+                for f, _ in sorted(mesh.neighbours(e, side)):
+                    if depth[f] < 0:
+                        depth[f] = depth[e] + 1
+                        nxt.append(f)
+        queue = nxt
+    if (depth < 0).any():
+        raise ValueError("mesh is not connected")
+    lab[:] = np.where(depth % 2 == 0, 1, -1)
+    return lab
+
+
+def robin_sides(mesh, e, lab):
+    """Interior sides of element e that carry the Robin term: those whose
+    neighbours all have the opposite label.  A side whose neighbours carry both
+    labels would need the term on part of the side only, which this
+    discretisation does not form."""
+    out = []
+    for side in (1, 2, 3, 4):
+        if mesh.boundary_side(e, side):
+            continue
+        others = {lab[f] for f, _ in mesh.neighbours(e, side)}
+        if others == {-lab[e]}:
+            out.append(side)
+        elif len(others) > 1:
+            raise NotImplementedError("Robin-modified local problems: a side whose neighbours carry both labels")
+    return out
+
+
 def edge_param(mesh, e, side):
     """Map s in [-1,1] along a side to (x, y)."""
     (ox, oy), (hx, hy) = mesh.origin(e), mesh.size(e)
@@ -46,10 +88,15 @@ def edge_param(mesh, e, side):
 class Discretisation:
     """A_e (paper basis N), the Laplace-only part, loads b_e, Dirichlet data."""
 
-    def __init__(self, w, mesh=None, bc=None, alpha=None, poisson=False):
+    def __init__(self, w, mesh=None, bc=None, alpha=None, poisson=False, modified=None):
         self.w = w
         self.mesh = mesh or make_mesh(w)
         m = self.mesh
+        # Robin-modified local problems (Sec. 2.3.4): gamma = +-ik on the interior
+        # sides between elements of opposite label; the two terms of a side cancel
+        # in the assembled system, which is therefore unchanged
+        self.modified = bool(w.get("robin_modified", False) if modified is None else modified)
+        self.labels = robin_labels(m) if self.modified else None
         self.k = float(w.get("k", 0.0))
         self.degrees = np.asarray(w["degree"])
         eps = np.asarray(w.get("eps_r", np.ones(m.E)))
@@ -69,7 +116,11 @@ class Discretisation:
                 bnd = m.boundary_side(e, side)
                 if bnd and bc[bnd] == "robin":
                     robin[side] = gamma
-            self.A.append(el.element_matrix(n, hx, hy, alpha=alpha[e], beta=beta, robin=robin))
+            terms = dict(robin)
+            if self.modified:
+                for side in robin_sides(m, e, self.labels):
+                    terms[side] = self.labels[e] * 1j * self.k
+            self.A.append(el.element_matrix(n, hx, hy, alpha=alpha[e], beta=beta, robin=terms))
             self.A_lap.append(el.element_matrix(n, hx, hy, alpha=alpha[e]))
             self.b.append(self._load(e, n, hx, hy, eps[e], rhs, robin))
 
