@@ -215,6 +215,37 @@ def design_gradient(hdp, torch, steps, warmup):
     return out
 
 
+def robin_modified(hdp, torch, steps, warmup):
+    """The point-source workload with Robin-modified local problems (gamma = +-ik
+    on the interior sides between elements of opposite label): same field, a
+    different interface problem; FP64 path, against the unmodified solve."""
+    import numpy as np
+    import workloads as W
+    w = W.point_source_32x32()
+    out = {"workload": "point_source_32x32_p16_k100_robin_modified"}
+    fields = {}
+    for mod in (False, True):
+        s = hdp.Solver(dict(w, robin_modified=mod), tol=1e-8, max_iter=600)
+        for _ in range(max(1, warmup)):
+            s.solve("point", [(0.5, 0.5)])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            f, st = s.solve("point", [(0.5, 0.5)])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        fields[mod] = f.cpu().numpy()[0]
+        out["modified" if mod else "unmodified"] = dict(
+            ms_per_solve=ms, dof_per_s=s.dof / (ms * 1e-3), iterations=st["iterations"],
+            true_residual=st["true_residual"], converged=st["converged"], setup_ms=s.info["setup_ms"],
+            classes=s.info["n_classes"])
+        s.close()
+    out["field_rel_diff"] = float(np.linalg.norm(fields[True] - fields[False]) / np.linalg.norm(fields[False]))
+    print(f"bench: robin-modified point source done ({out['modified']['ms_per_solve']:.1f} ms per solve)",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline():
     """The oracle as it stands on a bounded sample of the same workload."""
     import numpy as np
@@ -251,7 +282,7 @@ def main():
                     help="skip the refined-disk and 64-angle batched scatterer measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy three times (HBM counter calibration)")
-    ap.add_argument("--only", choices=["refined_disk", "scatterer", "design"],
+    ap.add_argument("--only", choices=["refined_disk", "scatterer", "design", "robin"],
                     help="profiling aid: run only this secondary workload and print its record")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -273,7 +304,8 @@ def main():
     import paper_1808_04713_amd as hdp
     import workloads as W
     if args.only:
-        fn = {"refined_disk": refined_disk, "scatterer": batched_scatterer, "design": design_gradient}[args.only]
+        fn = {"refined_disk": refined_disk, "scatterer": batched_scatterer, "design": design_gradient,
+              "robin": robin_modified}[args.only]
         print(json.dumps(fn(hdp, torch, max(1, args.steps), args.warmup)), flush=True)
         return
     w = W.point_source_32x32()
@@ -313,6 +345,7 @@ def main():
     if not args.no_batched:
         line["nonconforming"] = refined_disk(hdp, torch, max(1, min(args.steps, 5)), min(args.warmup, 1))
         line["adjoint_gradient"] = design_gradient(hdp, torch, max(1, min(args.steps, 5)), min(args.warmup, 1))
+        line["robin_modified"] = robin_modified(hdp, torch, max(1, min(args.steps, 3)), min(args.warmup, 1))
         line["batched_rhs"] = batched_scatterer(hdp, torch, max(1, min(args.steps, 3)), min(args.warmup, 1))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()

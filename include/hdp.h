@@ -95,6 +95,15 @@ typedef struct {
                                  a hanging edge is dropped when the diagonal a^k of its change
                                  of basis L_c^f is below this value (0 keeps every constraint;
                                  primal constraints are always kept) */
+  int32_t robin_modified;     /* Sec. 2.3.4: 1 adds Robin terms gamma = +-ik to the local
+                                 problems on the interior sides between elements of opposite
+                                 label (breadth-first levels from leaf 0, neighbours taken side
+                                 by side, left right bottom top, and across one side in leaf
+                                 order; even levels +ik, odd -ik).  The terms cancel in the
+                                 assembled system, so the solution is unchanged, while every
+                                 local problem becomes uniquely solvable at element resonances.
+                                 HDP_E_UNSUPPORTED when a side's neighbours carry both labels
+                                 (possible on hanging sides).  0: unmodified. */
 } hdp_problem;
 
 typedef struct {

@@ -34,7 +34,8 @@ class _Mesh(ctypes.Structure):
 
 class _Problem(ctypes.Structure):
     _fields_ = [("k", ctypes.c_double), ("eps_r", ctypes.POINTER(ctypes.c_double)),
-                ("l", ctypes.c_int32), ("l_safety", ctypes.c_int32), ("discard_tol", ctypes.c_double)]
+                ("l", ctypes.c_int32), ("l_safety", ctypes.c_int32), ("discard_tol", ctypes.c_double),
+                ("robin_modified", ctypes.c_int32)]
 
 
 class _Options(ctypes.Structure):
@@ -132,7 +133,8 @@ def _structs(w, l_safety=0):
                  leaves.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                  deg.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
     prob = _Problem(float(w["k"]), eps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                    int(w.get("l", -1)), int(l_safety), float(w.get("discard_tol", 0.0)))
+                    int(w.get("l", -1)), int(l_safety), float(w.get("discard_tol", 0.0)),
+                    int(bool(w.get("robin_modified", False))))
     return mesh, prob, (leaves, deg, eps)
 
 

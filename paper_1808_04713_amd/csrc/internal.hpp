@@ -28,6 +28,7 @@ struct ElemClass {
   int p = 0, n = 0;
   double hx = 0, hy = 0, eps = 1;
   int bmask = 0;               // bit (s-1): side s on the outer impedance boundary
+  int rmask = 0;               // bits 2(s-1)..: Robin-modified side s, 1 gamma = -ik, 2 gamma = +ik
   int top[4] = {1, 1, 1, 1};   // per side: bubbles 2..top are coarse modes
   int gtop[4] = {0, 0, 0, 0};  // per side: bubbles top+1..gtop are dual slots
   int m = 0, nr = 0;           // dual slots, coarse modes
@@ -91,6 +92,7 @@ struct Handle {
   std::vector<int> cls;                 // class of each element
   std::vector<ElemClass> classes;
   std::vector<int> bmask;
+  std::vector<int> rmask;          // per element, as ElemClass::rmask (zero unless Robin-modified)
   // per side (4 per element, index 4e + s - 1): 0 outer boundary, 1 conforming,
   // 2 fine side of a hanging edge (one coarser neighbour), 3 coarse side of a
   // hanging edge (several finer neighbours)

@@ -114,11 +114,17 @@ void build_class(ElemClass& C, double k) {
       Ax(i, j) = (2.0 / C.hx) * Kt(i, j) + beta * (C.hx / 2.0) * Mt(i, j);
       Ay(i, j) = (2.0 / C.hy) * Kt(i, j);
     }
-  // Robin terms gamma * |J_edge| * (trace mode)(trace mode)^T on boundary sides
-  if (C.bmask & 1) Ax(1, 1) += gamma;   // left: vertex mode at x=-1
-  if (C.bmask & 2) Ax(0, 0) += gamma;   // right
-  if (C.bmask & 4) Ay(1, 1) += gamma;   // bottom
-  if (C.bmask & 8) Ay(0, 0) += gamma;   // top
+  // Robin terms gamma * |J_edge| * (trace mode)(trace mode)^T: gamma = -ik on the
+  // impedance boundary, +-ik on Robin-modified interior sides (Sec. 2.3.4)
+  auto side_gamma = [&](int s) -> cd {
+    if (C.bmask & (1 << (s - 1))) return gamma;
+    const int code = (C.rmask >> (2 * (s - 1))) & 3;
+    return code == 1 ? cd(0.0, -k) : code == 2 ? cd(0.0, k) : cd(0.0, 0.0);
+  };
+  Ax(1, 1) += side_gamma(1);   // left: vertex mode at x=-1
+  Ax(0, 0) += side_gamma(2);   // right
+  Ay(1, 1) += side_gamma(3);   // bottom
+  Ay(0, 0) += side_gamma(4);   // top
   std::vector<cd> lx, ly;
   gen_eig(Ax, Mt, C.Ex, lx);
   gen_eig(Ay, Mt, C.Ey, ly);
@@ -758,16 +764,56 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
       tops[e][s - 1] = top;
       tops[e][4 + s - 1] = gtop;
     }
+  // Robin-modified local problems (Sec. 2.3.4): labels from the levels of a
+  // breadth-first spanning tree of the element adjacency; the term goes on an
+  // interior side when every neighbour across it has the opposite label
+  h.rmask.assign(E, 0);
+  if (prob->robin_modified) {
+    auto nbrs = [&](int e, int s) {
+      const int si = 4 * e + s - 1;
+      std::vector<int> v;
+      if (h.side_type[si] == 1 || h.side_type[si] == 2) v.push_back(h.nb_e[si]);
+      else if (h.side_type[si] == 3) v = h.side_nbrs[si];
+      std::sort(v.begin(), v.end());
+      return v;
+    };
+    std::vector<int> depth(E, -1);
+    std::vector<int> queue{0};
+    depth[0] = 0;
+    for (size_t q = 0; q < queue.size(); ++q) {
+      const int e = queue[q];
+      for (int s = 1; s <= 4; ++s)
+        for (int f : nbrs(e, s))
+          if (depth[f] < 0) {
+            depth[f] = depth[e] + 1;
+            queue.push_back(f);
+          }
+    }
+    for (int e = 0; e < E; ++e)
+      if (depth[e] < 0) fail(HDP_E_MESH, "mesh is not connected");
+    for (int e = 0; e < E; ++e)
+      for (int s = 1; s <= 4; ++s) {
+        const std::vector<int> v = nbrs(e, s);
+        if (v.empty()) continue;
+        int opp = 0;
+        for (int f : v) opp += (depth[f] % 2) != (depth[e] % 2);
+        if (opp == 0) continue;
+        if (opp != int(v.size()))
+          fail(HDP_E_UNSUPPORTED, "Robin-modified local problems: side " + std::to_string(s) + " of leaf " +
+                                      std::to_string(e) + " has neighbours of both labels");
+        h.rmask[e] |= (depth[e] % 2 == 0 ? 2 : 1) << (2 * (s - 1));
+      }
+  }
   // classes
-  std::map<std::tuple<int, double, double, double, int, std::array<int, 8>>, int> cmap;
+  std::map<std::tuple<int, double, double, double, int, int, std::array<int, 8>>, int> cmap;
   h.cls.resize(E);
   for (int e = 0; e < E; ++e) {
-    auto key = std::make_tuple(h.deg[e], h.hx[e], h.hy[e], h.eps[e], h.bmask[e], tops[e]);
+    auto key = std::make_tuple(h.deg[e], h.hx[e], h.hy[e], h.eps[e], h.bmask[e], h.rmask[e], tops[e]);
     auto it = cmap.find(key);
     if (it == cmap.end()) {
       ElemClass C;
       C.p = h.deg[e]; C.n = C.p + 1; C.hx = h.hx[e]; C.hy = h.hy[e];
-      C.eps = h.eps[e]; C.bmask = h.bmask[e];
+      C.eps = h.eps[e]; C.bmask = h.bmask[e]; C.rmask = h.rmask[e];
       for (int s = 0; s < 4; ++s) {
         C.top[s] = tops[e][s];
         C.gtop[s] = tops[e][4 + s];

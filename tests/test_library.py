@@ -100,3 +100,32 @@ def test_inspect_reports_element_resonance():
     near = hdp.inspect(W.small_uniform(3, 8, np.pi * 1.001, domain=(0.0, 3.0, 0.0, 3.0), l=1))
     far = hdp.inspect(W.small_uniform(3, 8, 2.0, domain=(0.0, 3.0, 0.0, 3.0), l=1))
     assert near["min_element_margin"] < 1e-2 * far["min_element_margin"]
+
+
+def test_robin_modified_local_problems_remove_the_element_resonance():
+    """Sec. 2.3.4: with +-ik Robin terms on the sides between elements of opposite
+    label every local problem is uniquely solvable, so the set-up that refuses
+    k = pi above accepts it, with a margin of the size found away from resonance."""
+    w = dict(W.small_uniform(3, 8, np.pi, domain=(0.0, 3.0, 0.0, 3.0), l=1), robin_modified=True)
+    st = hdp.inspect(w)
+    far = hdp.inspect(W.small_uniform(3, 8, 2.0, domain=(0.0, 3.0, 0.0, 3.0), l=1))
+    assert st["min_element_margin"] > 1e-2 * far["min_element_margin"]
+    # elements now also differ by label (the sign of their terms): on a 6x6 mesh
+    # the 4 corner, 4 side and 1 interior classes become 4 corners (one label
+    # each), 8 side classes and 2 interior ones
+    w6 = W.small_uniform(6, 5, 2.0, l=1)
+    assert hdp.inspect(w6)["n_classes"] == 9
+    assert hdp.inspect(dict(w6, robin_modified=True))["n_classes"] == 14
+
+
+def test_robin_modified_rejects_sides_with_both_labels():
+    """On a quadtree mesh a coarse side can meet fine leaves of both labels; its
+    term would cover part of the side, which the separable local solver cannot
+    take: the set-up reports an unsupported input."""
+    lv = W.refine_where(W.morton_leaves(3, 3), 0, 1, 0, 1, 3, 3,
+                        lambda x, y: (x - 0.5) ** 2 + (y - 0.5) ** 2 < 0.02, 1)
+    w = dict(domain=(0.0, 1.0, 0.0, 1.0), base=(3, 3), leaves=lv, degree=np.full(len(lv), 4), k=6.0,
+             eps_r=np.ones(len(lv)), l=-1, robin_modified=True)
+    with pytest.raises(hdp.HdpError) as e:
+        hdp.inspect(w)
+    assert e.value.status == -7
