@@ -21,7 +21,8 @@ def side_vector(n, side):
 
 
 def element_matrix(n, hx, hy, alpha=1.0, beta=0.0, robin=None):
-    """A_j for alpha = alpha*I and constant beta on an hx-by-hy rectangle.
+    """A_j for constant alpha = alpha*I, or alpha = diag(alpha[0], alpha[1]) when a
+    pair is given, and constant beta on an hx-by-hy rectangle.
 
     Volume terms from the Kronecker identity of Sec. 2.2.1 (eq. complicated_integral
     with the X_i of Table tab:volume_integrals); for constant coefficients only
@@ -35,7 +36,9 @@ def element_matrix(n, hx, hy, alpha=1.0, beta=0.0, robin=None):
     K = lg.stiffness_1d(n)
     M = lg.mass_1d(n)
     Jx, Jy = hx / 2.0, hy / 2.0
-    A = (alpha * (Jy / Jx) * np.kron(M, K) + alpha * (Jx / Jy) * np.kron(K, M)
+    axx, ayy = (alpha, alpha) if np.isscalar(alpha) else alpha
+    # vec order x fastest: kron(M, K) carries the x derivatives, kron(K, M) the y ones
+    A = (axx * (Jy / Jx) * np.kron(M, K) + ayy * (Jx / Jy) * np.kron(K, M)
          + beta * Jx * Jy * np.kron(M, M)).astype(complex)
     for side, gamma in (robin or {}).items():
         v = side_vector(n, side)

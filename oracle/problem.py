@@ -99,6 +99,15 @@ class Discretisation:
         self.labels = robin_labels(m) if self.modified else None
         self.k = float(w.get("k", 0.0))
         self.degrees = np.asarray(w["degree"])
+        # axis-aligned perfectly matched layers (Sec. 3.3): complex stretching
+        # s_i = 1 + i sigma_i / k (the paper's 1 - j sigma_i / omega in the e^{-i omega t}
+        # convention, omega = k in scaled units), piecewise constant per element;
+        # alpha = diag(s_y / s_x, s_x / s_y) and beta = -k^2 eps s_x s_y
+        sig = w.get("pml_sigma")
+        self.stretch = None
+        if sig is not None:
+            sig = np.asarray(sig, float).reshape(m.E, 2)
+            self.stretch = 1.0 + 1j * sig / self.k
         eps = np.asarray(w.get("eps_r", np.ones(m.E)))
         alpha = np.ones(m.E) if alpha is None else np.asarray(alpha)
         if bc is None:
@@ -111,6 +120,11 @@ class Discretisation:
             n = int(self.degrees[e]) + 1
             hx, hy = m.size(e)
             beta = 0.0 if poisson else -self.k ** 2 * eps[e]
+            al = alpha[e]
+            if self.stretch is not None:
+                sx, sy = self.stretch[e]
+                al = (alpha[e] * sy / sx, alpha[e] * sx / sy)
+                beta = beta * sx * sy
             robin = {}
             for side in (1, 2, 3, 4):
                 bnd = m.boundary_side(e, side)
@@ -120,8 +134,8 @@ class Discretisation:
             if self.modified:
                 for side in robin_sides(m, e, self.labels):
                     terms[side] = self.labels[e] * 1j * self.k
-            self.A.append(el.element_matrix(n, hx, hy, alpha=alpha[e], beta=beta, robin=terms))
-            self.A_lap.append(el.element_matrix(n, hx, hy, alpha=alpha[e]))
+            self.A.append(el.element_matrix(n, hx, hy, alpha=al, beta=beta, robin=terms))
+            self.A_lap.append(el.element_matrix(n, hx, hy, alpha=al))
             self.b.append(self._load(e, n, hx, hy, eps[e], rhs, robin))
 
     def _load(self, e, n, hx, hy, eps_e, rhs, robin):
