@@ -246,6 +246,38 @@ def robin_modified(hdp, torch, steps, warmup):
     return out
 
 
+def pml_scatterer(hdp, torch, steps, warmup):
+    """The square scatterer inside 8 rings of perfectly matched layers (80x80
+    elements, p = 12, k = 150, normal incidence, 360 far-field angles), FP64 path,
+    beside the same scatterer truncated by the impedance condition alone."""
+    import numpy as np
+    import workloads as W
+    out = {"workload": "pml_scatterer_64x64_p12_k150_8layers"}
+    fars = {}
+    for name, w in (("layers", W.pml_scatterer_64x64()), ("impedance_only", W.square_scatterer_64x64(1))):
+        fa = np.asarray(w["far_angles"])
+        inside = np.asarray(w["eps_r"]) != 1.0
+        s = hdp.Solver(w, tol=1e-8, max_iter=400)
+        for _ in range(max(1, warmup)):
+            s.solve("plane_wave_scattered", [0.0], want_field=False, far_angles=fa, far_inside=inside)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, far, st = s.solve("plane_wave_scattered", [0.0], want_field=False, far_angles=fa, far_inside=inside)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        fars[name] = far.cpu().numpy()[0]
+        out[name] = dict(ms_per_solve=ms, dof_per_s=s.dof / (ms * 1e-3), dof=s.dof, iterations=st["iterations"],
+                         true_residual=st["true_residual"], converged=st["converged"], setup_ms=s.info["setup_ms"],
+                         classes=s.info["n_classes"], n_coarse=s.info["n_coarse"])
+        s.close()
+    a, b = fars["layers"], fars["impedance_only"]
+    out["far_field_rel_diff_layers_vs_impedance_only"] = float(np.linalg.norm(a - b) / np.linalg.norm(a))
+    print(f"bench: layered scatterer done ({out['layers']['ms_per_solve']:.1f} ms per solve)", file=sys.stderr,
+          flush=True)
+    return out
+
+
 def cpu_baseline():
     """The oracle as it stands on a bounded sample of the same workload."""
     import numpy as np
@@ -282,7 +314,7 @@ def main():
                     help="skip the refined-disk and 64-angle batched scatterer measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy three times (HBM counter calibration)")
-    ap.add_argument("--only", choices=["refined_disk", "scatterer", "design", "robin"],
+    ap.add_argument("--only", choices=["refined_disk", "scatterer", "design", "robin", "pml"],
                     help="profiling aid: run only this secondary workload and print its record")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -305,7 +337,7 @@ def main():
     import workloads as W
     if args.only:
         fn = {"refined_disk": refined_disk, "scatterer": batched_scatterer, "design": design_gradient,
-              "robin": robin_modified}[args.only]
+              "robin": robin_modified, "pml": pml_scatterer}[args.only]
         print(json.dumps(fn(hdp, torch, max(1, args.steps), args.warmup)), flush=True)
         return
     w = W.point_source_32x32()
@@ -346,6 +378,7 @@ def main():
         line["nonconforming"] = refined_disk(hdp, torch, max(1, min(args.steps, 5)), min(args.warmup, 1))
         line["adjoint_gradient"] = design_gradient(hdp, torch, max(1, min(args.steps, 5)), min(args.warmup, 1))
         line["robin_modified"] = robin_modified(hdp, torch, max(1, min(args.steps, 3)), min(args.warmup, 1))
+        line["pml_scatterer"] = pml_scatterer(hdp, torch, max(1, min(args.steps, 3)), min(args.warmup, 1))
         line["batched_rhs"] = batched_scatterer(hdp, torch, max(1, min(args.steps, 3)), min(args.warmup, 1))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()

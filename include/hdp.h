@@ -104,6 +104,14 @@ typedef struct {
                                  local problem becomes uniquely solvable at element resonances.
                                  HDP_E_UNSUPPORTED when a side's neighbours carry both labels
                                  (possible on hanging sides).  0: unmodified. */
+  const double* pml_sigma;    /* Sec. 3.3: host, 2 per leaf (sigma_x, sigma_y) >= 0, or NULL for
+                                 none.  Axis-aligned perfectly matched layers by complex
+                                 stretching s = 1 + i sigma / k (e^{-i omega t}, omega = k):
+                                 alpha = diag(s_y/s_x, s_x/s_y), beta = -k^2 eps_r s_x s_y on the
+                                 leaf; the preconditioner's Laplace part takes the same alpha.
+                                 Loads stay those of the unstretched problem (a layer leaf with
+                                 eps_r = 1 carries no scattered-field source).  HDP_E_UNSUPPORTED
+                                 with hanging edges. */
 } hdp_problem;
 
 typedef struct {

@@ -35,7 +35,7 @@ class _Mesh(ctypes.Structure):
 class _Problem(ctypes.Structure):
     _fields_ = [("k", ctypes.c_double), ("eps_r", ctypes.POINTER(ctypes.c_double)),
                 ("l", ctypes.c_int32), ("l_safety", ctypes.c_int32), ("discard_tol", ctypes.c_double),
-                ("robin_modified", ctypes.c_int32)]
+                ("robin_modified", ctypes.c_int32), ("pml_sigma", ctypes.POINTER(ctypes.c_double))]
 
 
 class _Options(ctypes.Structure):
@@ -132,10 +132,14 @@ def _structs(w, l_safety=0):
     mesh = _Mesh(x0, x1, y0, y1, int(w["base"][0]), int(w["base"][1]), len(deg),
                  leaves.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                  deg.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    sig = None
+    if w.get("pml_sigma") is not None:
+        sig = np.ascontiguousarray(np.asarray(w["pml_sigma"], dtype=np.float64).reshape(len(deg), 2))
     prob = _Problem(float(w["k"]), eps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                     int(w.get("l", -1)), int(l_safety), float(w.get("discard_tol", 0.0)),
-                    int(bool(w.get("robin_modified", False))))
-    return mesh, prob, (leaves, deg, eps)
+                    int(bool(w.get("robin_modified", False))),
+                    sig.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if sig is not None else None)
+    return mesh, prob, (leaves, deg, eps, sig)
 
 
 def inspect(w, l_safety=0):

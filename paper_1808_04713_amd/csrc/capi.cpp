@@ -446,7 +446,8 @@ void build_device(Handle& h) {
   std::vector<int> cn(NC), cm(NC), cnr(NC), cgam(NC), cR(NC);
   std::vector<int64_t> o_op1(NC), o_phi(NC), o_se(NC), o_E(NC), o_D(NC), o_G(NC), o_Kc(NC), o_V(NC);
   std::vector<double2> op1, phi, Ex, Ey, Dinv, G, Kc;
-  std::vector<double> se, V;
+  std::vector<double2> se;
+  std::vector<double> V;
   std::vector<int> gam, rmod;
   for (int c = 0; c < NC; ++c) {
     const ElemClass& C = h.classes[c];
@@ -456,7 +457,7 @@ void build_device(Handle& h) {
     cgam[c] = gam.size(); cR[c] = rmod.size();
     for (auto& v : C.Op1.a) op1.push_back(make_double2(v.real(), v.imag()));
     for (auto& v : C.Phi.a) phi.push_back(make_double2(v.real(), v.imag()));
-    for (auto& v : C.Se.a) se.push_back(v);
+    for (auto& v : C.Se.a) se.push_back(make_double2(v.real(), v.imag()));
     for (auto& v : C.Ex.a) Ex.push_back(make_double2(v.real(), v.imag()));
     for (auto& v : C.Ey.a) Ey.push_back(make_double2(v.real(), v.imag()));
     for (auto& v : C.Dg) { cd iv = 1.0 / v; Dinv.push_back(make_double2(iv.real(), iv.imag())); }
@@ -521,11 +522,19 @@ void build_device(Handle& h) {
   }
   d.op1 = upload(h, op1); d.phi = upload(h, phi); d.se = upload(h, se);
   std::vector<float2> op1f(op1.size()), phif(phi.size());
-  std::vector<float> sef(se.size());
+  std::vector<float2> sef(se.size());
   for (size_t i = 0; i < op1.size(); ++i) op1f[i] = make_float2(float(op1[i].x), float(op1[i].y));
   for (size_t i = 0; i < phi.size(); ++i) phif[i] = make_float2(float(phi[i].x), float(phi[i].y));
-  for (size_t i = 0; i < se.size(); ++i) sef[i] = float(se[i]);
+  for (size_t i = 0; i < se.size(); ++i) sef[i] = make_float2(float(se[i].x), float(se[i].y));
   d.op1_f = upload(h, op1f); d.phi_f = upload(h, phif); d.se_f = upload(h, sef);
+  if (h.pml) {   // s_x s_y per element: the layers' factor on the mass term (adjoint gradient)
+    std::vector<double2> mf(E);
+    for (int e = 0; e < E; ++e) {
+      const cd f = cd(1.0, h.sigx[e] / h.k) * cd(1.0, h.sigy[e] / h.k);
+      mf[e] = make_double2(f.real(), f.imag());
+    }
+    d.mass_fac = upload(h, mf);
+  }
   d.Ex = upload(h, Ex); d.Ey = upload(h, Ey); d.Dinv = upload(h, Dinv);
   d.G = upload(h, G); d.Kc = upload(h, Kc); d.V = upload(h, V);
   std::vector<int64_t> kidx;

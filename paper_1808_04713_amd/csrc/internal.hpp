@@ -29,6 +29,7 @@ struct ElemClass {
   double hx = 0, hy = 0, eps = 1;
   int bmask = 0;               // bit (s-1): side s on the outer impedance boundary
   int rmask = 0;               // bits 2(s-1)..: Robin-modified side s, 1 gamma = -ik, 2 gamma = +ik
+  double sigx = 0, sigy = 0;   // layer stretching s = 1 + i sigma / k per axis
   int top[4] = {1, 1, 1, 1};   // per side: bubbles 2..top are coarse modes
   int gtop[4] = {0, 0, 0, 0};  // per side: bubbles top+1..gtop are dual slots
   int m = 0, nr = 0;           // dual slots, coarse modes
@@ -40,8 +41,8 @@ struct ElemClass {
   MatC Kc;                     // (E_R^T A~^-1 E_R)^-1 (nr x nr)
   MatC Op1;                    // [D_c ; Phi_c^T]      ((m+nr) x m)
   MatC Phi;                    // Phi_c = -A_11^-1 A_1R = G_Gam Kc on the slots (m x nr)
-  MatD Se;                     // Laplace-only Schur complement on Gam (m x m)
-  MatD KL;                     // Laplace-only element coarse matrix on R (nr x nr)
+  MatC Se;                     // Laplace-only Schur complement on Gam (m x m)
+  MatC KL;                     // Laplace-only element coarse matrix on R (nr x nr)
   double margin = 0;           // min|Dg| / max|Dg|
   std::vector<int> elems;      // members, leaf indices
 };
@@ -93,6 +94,8 @@ struct Handle {
   std::vector<ElemClass> classes;
   std::vector<int> bmask;
   std::vector<int> rmask;          // per element, as ElemClass::rmask (zero unless Robin-modified)
+  std::vector<double> sigx, sigy;  // per element layer stretching (zero outside layers)
+  bool pml = false;
   // per side (4 per element, index 4e + s - 1): 0 outer boundary, 1 conforming,
   // 2 fine side of a hanging edge (one coarser neighbour), 3 coarse side of a
   // hanging edge (several finer neighbours)
@@ -199,9 +202,10 @@ struct Handle {
     int* r_modes = nullptr;
     // operators
     double2 *op1 = nullptr, *phi = nullptr;   // FP64
-    double* se = nullptr;
+    double2* se = nullptr;
     float2 *op1_f = nullptr, *phi_f = nullptr; // FP32 copies
-    float* se_f = nullptr;
+    float2* se_f = nullptr;
+    double2* mass_fac = nullptr;   // per element s_x s_y (layers only; null without layers)
     double2 *Ex = nullptr, *Ey = nullptr, *Dinv = nullptr, *G = nullptr, *Kc = nullptr;
     double* V = nullptr;      // GLL sampling matrices per class
     double2* Kinv = nullptr;  // nK x nK, row-major

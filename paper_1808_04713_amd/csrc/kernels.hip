@@ -66,7 +66,7 @@ template <class T2, int MODE>
 __global__ void __launch_bounds__(NT) k_slot_apply(
     const int* __restrict__ order, const int* __restrict__ elem_cls, const int* __restrict__ slot_off,
     const int* __restrict__ cm_off, const int* __restrict__ cls_m, const int* __restrict__ cls_nr,
-    const int64_t* __restrict__ cls_op, const T2* __restrict__ op1, const typename Scal<T2>::T* __restrict__ se,
+    const int64_t* __restrict__ cls_op, const T2* __restrict__ op1, const T2* __restrict__ se,
     const int64_t* __restrict__ cls_se, const int* __restrict__ slot_row, const double* __restrict__ slot_coef,
     const double* __restrict__ row_xinv, const int* __restrict__ row_slot, const double* __restrict__ row_coef,
     const T2* __restrict__ v, T2* __restrict__ X, T2* __restrict__ GL, int R) {
@@ -115,17 +115,12 @@ __global__ void __launch_bounds__(NT) k_slot_apply(
       else GL[(int64_t)(cm_off[e] + i - m) * R + r0 + r] = acc;
     }
   } else {
-    const S* A = se + cls_se[c];
+    const T2* A = se + cls_se[c];
     for (int idx = threadIdx.x; idx < m * rc; idx += NT) {
       int i = idx / rc, r = idx - i * rc;
-      S ax = 0, ay = 0;
-      for (int kk = 0; kk < m; ++kk) {
-        S a = A[i + (int64_t)m * kk];
-        T2 b = y[kk * RC + r];
-        ax += a * b.x;
-        ay += a * b.y;
-      }
-      X[(int64_t)(so + i) * R + r0 + r] = mk<T2>(ax, ay);
+      T2 acc = mk<T2>(0, 0);
+      for (int kk = 0; kk < m; ++kk) acc = cfma(A[i + (int64_t)m * kk], y[kk * RC + r], acc);
+      X[(int64_t)(so + i) * R + r0 + r] = acc;
     }
   }
 }
@@ -1106,8 +1101,9 @@ __global__ void __launch_bounds__(NT) k_eps_grad(
     const int* __restrict__ cls_q, const int64_t* __restrict__ cls_qoff, const double* __restrict__ qx,
     const double* __restrict__ qw, const double* __restrict__ qN, const double* __restrict__ cls_M,
     const int64_t* __restrict__ cls_Moff, const double* __restrict__ ox, const double* __restrict__ oy,
-    const double* __restrict__ hx, const double* __restrict__ hy, const double2* __restrict__ U,
-    const double2* __restrict__ Lam, double2 E, double k, double dx, double dy, double* __restrict__ grad) {
+    const double* __restrict__ hx, const double* __restrict__ hy, const double2* __restrict__ mass_fac,
+    const double2* __restrict__ U, const double2* __restrict__ Lam, double2 E, double k, double dx, double dy,
+    double* __restrict__ grad) {
   extern __shared__ double2 sm[];
   __shared__ double2 red[NT];
   const int e = blockIdx.x;
@@ -1162,7 +1158,9 @@ __global__ void __launch_bounds__(NT) k_eps_grad(
     }
     const double2 l = Lam[base + t];
     const double2 db = cmul(sa[a], sb[b]);
-    const double px = f0 * db.x + fm * wx, py = f0 * db.y + fm * wy;
+    double2 mw = make_double2(wx, wy);
+    if (mass_fac) mw = cmul(mass_fac[e], mw);   // layers: the mass term carries s_x s_y
+    const double px = f0 * db.x + fm * mw.x, py = f0 * db.y + fm * mw.y;
     vx += l.x * px - l.y * py;
     vy += l.x * py + l.y * px;
   }
@@ -1593,7 +1591,7 @@ void launch_slot_apply(const Handle& h, int mode, const T2* v, T2* X, T2* GL, in
   dim3 grid(h.E, (R + RC - 1) / RC);
   const auto& d = h.d;
   const T2* op1;
-  const typename Scal<T2>::T* se;
+  const T2* se;
   if constexpr (std::is_same<T2, double2>::value) { op1 = d.op1; se = d.se; }
   else { op1 = d.op1_f; se = d.se_f; }
 #define HDP_SLOT_ARGS d.order, d.elem_cls, d.slot_off, d.cm_off, d.cls_m, d.cls_nr, d.cls_op1, op1, se, d.cls_se, \
@@ -1916,7 +1914,7 @@ void launch_eps_gradient(const Handle& h, const double2* U, const double2* Lam, 
   for (auto& C : h.classes) nmax = std::max(nmax, C.n);
   const size_t shm = (size_t(2) * nmax * nmax + 128) * sizeof(double2);
   hipLaunchKernelGGL(k_eps_grad, dim3(h.E), dim3(NT), shm, s, d.elem_cls, d.cls_n, d.dof_off, d.cls_q, d.cls_qoff,
-                     d.qx, d.qw, d.qN, d.cls_M, d.cls_Moff, d.ox, d.oy, d.hx, d.hy, U, Lam, E, h.k,
+                     d.qx, d.qw, d.qN, d.cls_M, d.cls_Moff, d.ox, d.oy, d.hx, d.hy, d.mass_fac, U, Lam, E, h.k,
                      std::cos(incidence), std::sin(incidence), grad);
   HIPCHECK(hipGetLastError());
 }

@@ -107,12 +107,16 @@ void build_class(ElemClass& C, double k) {
   int n = C.n, p = C.p;
   MatD Mt = mass_vertex(n), Kt = stiffness_vertex(n);
   cd gamma(0.0, -k);
-  double beta = -k * k * C.eps;
+  // layers (Sec. 3.3): s = 1 + i sigma / k per axis, alpha = diag(s_y/s_x, s_x/s_y),
+  // beta = -k^2 eps s_x s_y (all 1 and real outside the layers)
+  const cd sx(1.0, C.sigx / k), sy(1.0, C.sigy / k);
+  const cd axx = sy / sx, ayy = sx / sy;
+  const cd beta = -k * k * C.eps * sx * sy;
   MatC Ax(n, n), Ay(n, n);
   for (int j = 0; j < n; ++j)
     for (int i = 0; i < n; ++i) {
-      Ax(i, j) = (2.0 / C.hx) * Kt(i, j) + beta * (C.hx / 2.0) * Mt(i, j);
-      Ay(i, j) = (2.0 / C.hy) * Kt(i, j);
+      Ax(i, j) = axx * (2.0 / C.hx) * Kt(i, j) + beta * (C.hx / 2.0) * Mt(i, j);
+      Ay(i, j) = ayy * (2.0 / C.hy) * Kt(i, j);
     }
   // Robin terms gamma * |J_edge| * (trace mode)(trace mode)^T: gamma = -ik on the
   // impedance boundary, +-ik on Robin-modified interior sides (Sec. 2.3.4)
@@ -200,43 +204,43 @@ void build_class(ElemClass& C, double k) {
   }
   auto AL = [&](int a, int b) {
     int i1 = a % n, i2 = a / n, j1 = b % n, j2 = b / n;
-    return (C.hy / C.hx) * Mt(i2, j2) * Kt(i1, j1) + (C.hx / C.hy) * Kt(i2, j2) * Mt(i1, j1);
+    return axx * (C.hy / C.hx) * Mt(i2, j2) * Kt(i1, j1) + ayy * (C.hx / C.hy) * Kt(i2, j2) * Mt(i1, j1);
   };
   int nb = int(bmodes.size()), ni = int(imodes.size());
-  MatD Abb(nb, nb), Abi(nb, ni), Aii(ni, ni);
+  MatC Abb(nb, nb), Abi(nb, ni), Aii(ni, ni);
   for (int b = 0; b < nb; ++b)
     for (int a = 0; a < nb; ++a) Abb(a, b) = AL(bmodes[a], bmodes[b]);
   for (int b = 0; b < ni; ++b)
     for (int a = 0; a < nb; ++a) Abi(a, b) = AL(bmodes[a], imodes[b]);
   for (int b = 0; b < ni; ++b)
     for (int a = 0; a < ni; ++a) Aii(a, b) = AL(imodes[a], imodes[b]);
-  MatD Sb = Abb;
+  MatC Sb = Abb;
   if (ni > 0) {
-    MatD X = solve(Aii, transpose(Abi));
-    MatD AX = matmul(Abi, X);
+    MatC X = solve(Aii, transpose(Abi));
+    MatC AX = matmul(Abi, X);
     for (size_t i = 0; i < Sb.a.size(); ++i) Sb.a[i] -= AX.a[i];
   }
   std::vector<int> bpos(n2, -1), inR(n2, 0);
   for (int a = 0; a < nb; ++a) bpos[bmodes[a]] = a;
   for (int r : C.R) inR[r] = 1;
-  C.Se = MatD(m, m);
+  C.Se = MatC(m, m);
   for (int b = 0; b < m; ++b)
     for (int a = 0; a < m; ++a) C.Se(a, b) = Sb(bpos[C.Gam[a]], bpos[C.Gam[b]]);
   std::vector<int> e1;
   for (int md : bmodes)
     if (!inR[md]) e1.push_back(md);
   int ne = int(e1.size());
-  C.KL = MatD(nr, nr);
+  C.KL = MatC(nr, nr);
   for (int b = 0; b < nr; ++b)
     for (int a = 0; a < nr; ++a) C.KL(a, b) = Sb(bpos[C.R[a]], bpos[C.R[b]]);
   if (ne > 0) {
-    MatD S11(ne, ne), S1R(ne, nr);
+    MatC S11(ne, ne), S1R(ne, nr);
     for (int b = 0; b < ne; ++b)
       for (int a = 0; a < ne; ++a) S11(a, b) = Sb(bpos[e1[a]], bpos[e1[b]]);
     for (int b = 0; b < nr; ++b)
       for (int a = 0; a < ne; ++a) S1R(a, b) = Sb(bpos[e1[a]], bpos[C.R[b]]);
-    MatD X = solve(S11, S1R);
-    MatD RX = matmul(transpose(S1R), X);
+    MatC X = solve(S11, S1R);
+    MatC RX = matmul(transpose(S1R), X);
     for (size_t i = 0; i < C.KL.a.size(); ++i) C.KL.a[i] -= RX.a[i];
   }
 }
@@ -580,7 +584,7 @@ void build_hanging_blocks(Handle& h) {
         for (int b = 0; b < C.nr; ++b) {
           int ib = co + b;
           if (!pos.count(h.t_dof[h.t_ptr[ib]])) continue;
-          double kab = C.KL(a, b);
+          double kab = C.KL(a, b).real();   // real: layers are refused with hanging edges
           for (int t = h.t_ptr[ia]; t < h.t_ptr[ia + 1]; ++t)
             for (int u = h.t_ptr[ib]; u < h.t_ptr[ib + 1]; ++u)
               KL(pos[h.t_dof[t]], pos[h.t_dof[u]]) += h.t_coef[t] * kab * h.t_coef[u];
@@ -651,6 +655,17 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
   std::vector<int64_t> X0(E), X1(E), Y0(E), Y1(E);
   std::vector<int> level(E);
   h.deg.resize(E);
+  h.sigx.assign(E, 0.0);
+  h.sigy.assign(E, 0.0);
+  h.pml = false;
+  if (prob->pml_sigma)
+    for (int e = 0; e < E; ++e) {
+      const double a = prob->pml_sigma[2 * e], b = prob->pml_sigma[2 * e + 1];
+      if (!std::isfinite(a) || !std::isfinite(b) || a < 0 || b < 0) fail(HDP_E_ARG, "pml_sigma not finite or negative");
+      h.sigx[e] = a;
+      h.sigy[e] = b;
+      if (a != 0 || b != 0) h.pml = true;
+    }
   h.eps.assign(E, 1.0);
   h.ox.resize(E); h.oy.resize(E); h.hx.resize(E); h.hy.resize(E);
   int64_t area = 0;
@@ -804,16 +819,21 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
         h.rmask[e] |= (depth[e] % 2 == 0 ? 2 : 1) << (2 * (s - 1));
       }
   }
+  if (h.pml && h.nonconforming)
+    fail(HDP_E_UNSUPPORTED, "perfectly matched layers on a mesh with hanging edges");
   // classes
-  std::map<std::tuple<int, double, double, double, int, int, std::array<int, 8>>, int> cmap;
+  std::map<std::tuple<int, double, double, double, int, int, std::array<int, 8>, std::pair<double, double>>, int>
+      cmap;
   h.cls.resize(E);
   for (int e = 0; e < E; ++e) {
-    auto key = std::make_tuple(h.deg[e], h.hx[e], h.hy[e], h.eps[e], h.bmask[e], h.rmask[e], tops[e]);
+    auto key = std::make_tuple(h.deg[e], h.hx[e], h.hy[e], h.eps[e], h.bmask[e], h.rmask[e], tops[e],
+                               std::make_pair(h.sigx[e], h.sigy[e]));
     auto it = cmap.find(key);
     if (it == cmap.end()) {
       ElemClass C;
       C.p = h.deg[e]; C.n = C.p + 1; C.hx = h.hx[e]; C.hy = h.hy[e];
       C.eps = h.eps[e]; C.bmask = h.bmask[e]; C.rmask = h.rmask[e];
+      C.sigx = h.sigx[e]; C.sigy = h.sigy[e];
       for (int s = 0; s < 4; ++s) {
         C.top[s] = tops[e][s];
         C.gtop[s] = tops[e][4 + s];
@@ -1065,7 +1085,7 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
   // algorithmic work counts
   for (auto& C : h.classes) {
     h.op1_bytes += 16.0 * (C.m + C.nr) * C.m;
-    h.se_bytes += 8.0 * C.m * C.m;
+    h.se_bytes += 16.0 * C.m * C.m;
     h.phi_bytes += 16.0 * C.m * C.nr;
   }
   for (int e = 0; e < E; ++e) {

@@ -129,3 +129,25 @@ def test_robin_modified_rejects_sides_with_both_labels():
     with pytest.raises(hdp.HdpError) as e:
         hdp.inspect(w)
     assert e.value.status == -7
+
+
+def test_layers_are_checked_and_refused_with_hanging_edges():
+    w = W.small_uniform(8, 4, 10.0, domain=(-1.0, 1.0, -1.0, 1.0), l=2)
+    sig = W.pml_sigma(w["leaves"], (8, 8), 4, 2, 40.0)
+    st = hdp.inspect(dict(w, pml_sigma=sig))
+    # stretched elements differ from plain ones of the same position: the layer
+    # rings add classes to the 9 of the plain 8x8 mesh
+    assert hdp.inspect(w)["n_classes"] == 9
+    assert st["n_classes"] > 9
+    bad = sig.copy()
+    bad[3, 0] = -1.0
+    with pytest.raises(hdp.HdpError) as e:
+        hdp.inspect(dict(w, pml_sigma=bad))
+    assert e.value.status == -1
+    lv = W.refine_where(W.morton_leaves(3, 3), 0, 1, 0, 1, 3, 3,
+                        lambda x, y: (x - 0.5) ** 2 + (y - 0.5) ** 2 < 0.02, 1)
+    wh = dict(domain=(0.0, 1.0, 0.0, 1.0), base=(3, 3), leaves=lv, degree=np.full(len(lv), 4), k=6.0,
+              eps_r=np.ones(len(lv)), l=-1, pml_sigma=np.full((len(lv), 2), 1.0))
+    with pytest.raises(hdp.HdpError) as e:
+        hdp.inspect(wh)
+    assert e.value.status == -7

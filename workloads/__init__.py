@@ -4,10 +4,11 @@ This module only describes inputs (mesh leaves, per-element degrees and
 relative permittivities, wavenumber, boundary conditions and right-hand-side
 kind).  It holds none of the method's arithmetic.
 
-The five workloads stand in for the paper's test problems (whose meshes come
-from its own generator): a small plane-wave check, a 32x32 point-source case,
-a quadtree-refined dielectric disk with uneven degrees, a square dielectric
-scatterer lit from 64 directions, and a permittivity design block.
+The workloads stand in for the paper's test problems (whose meshes come from
+its own generator): a small plane-wave check, a 32x32 point-source case, a
+quadtree-refined dielectric disk with uneven degrees, a square dielectric
+scatterer lit from 64 directions, a permittivity design block, and the square
+scatterer inside perfectly matched layers.
 """
 import math
 
@@ -133,6 +134,36 @@ def refined_disk(seed=0):
     return w
 
 
+def pml_sigma(leaves, base, n_phys, n_layer, sigma_max):
+    """Per-leaf (sigma_x, sigma_y) for layers of n_layer element rings around an
+    n_phys x n_phys block of a uniform base grid: ring r (0 innermost) carries
+    sigma_max ((r + 1/2) / n_layer)^2 along the axis it crosses (both in corners)."""
+    sig = np.zeros((len(leaves), 2))
+    for e, (lev, ix, iy) in enumerate(leaves):
+        for a, i in enumerate((ix, iy)):
+            r = n_layer - 1 - i if i < n_layer else i - n_layer - n_phys if i >= n_layer + n_phys else -1
+            if r >= 0:
+                sig[e, a] = sigma_max * ((r + 0.5) / n_layer) ** 2
+    return sig
+
+
+def pml_scatterer_64x64(n_layer=8, sigma_max=144.0):
+    """The square scatterer (64x64 physical elements on [-1,1]^2, p=12, k=150,
+    eps_r=4 on [-1/4,1/4]^2, normal incidence, scattered field) surrounded by
+    n_layer rings of perfectly matched layers with a quadratic profile (about
+    e^{-12} attenuation across them), impedance condition outside."""
+    n = 64 + 2 * n_layer
+    h = 2.0 / 64
+    L = 1.0 + n_layer * h
+    w = _uniform(f"pml_scatterer_64x64_p12_k150_{n_layer}layers", (-L, L, -L, L), n, 12, 150.0, tol=1e-8)
+    c = leaf_centres(w)
+    w["eps_r"] = np.where((np.abs(c[:, 0]) < 0.25) & (np.abs(c[:, 1]) < 0.25), 4.0, 1.0)
+    w["pml_sigma"] = pml_sigma(w["leaves"], (n, n), 64, n_layer, sigma_max)
+    w["rhs"] = dict(kind="plane_wave_scattered", angles=[0.0])
+    w["far_angles"] = [2 * math.pi * q / 360 for q in range(360)]
+    return w
+
+
 def small_uniform(n=4, p=6, k=7.0, domain=(0.0, 1.0, 0.0, 1.0), l=-1, rhs=None, eps=None):
     """A small uniform mesh for parity tests at sizes the oracle finishes quickly."""
     w = _uniform(f"uniform_{n}x{n}_p{p}_k{k:g}", domain, n, p, k, l=l,
@@ -148,4 +179,5 @@ ALL = {
     "refined_disk": refined_disk,
     "square_scatterer_64x64": square_scatterer_64x64,
     "design_block_64x64": design_block_64x64,
+    "pml_scatterer_64x64": pml_scatterer_64x64,
 }
