@@ -55,6 +55,12 @@ def side_vertices(n, side):
     return [a + n * b for (a, b) in pairs], pairs
 
 
+def side_l(l, e, side):
+    """The coarse order of an element side: l itself, or l(e, side) when l is a
+    per-edge function (the same value on both sides of an edge)."""
+    return l(e, side) if callable(l) else l
+
+
 def edge_l(l, na, nb):
     """Number of primal rows minus one on an edge between elements with na and nb
     modes per direction: min(l, p_a, p_b).  A primal row above the smaller degree
@@ -114,7 +120,7 @@ class Constraints:
                         cols += list(self.off[e] + nz)
                         vals += list(T[k, nz])
                         self.d.append(dd[k])
-                        self.primal.append(k <= l)
+                        self.primal.append(k <= side_l(l, e, side))
                         self.kind.append("dirichlet")
                         self.row_edge.append(eid)
                         self.row_k.append(k)
@@ -147,8 +153,9 @@ class Constraints:
                 self.edges.append((e, side, c, sc, a, b))
                 zkey = (c, sc)
                 zset = zeroed.setdefault(zkey, set())
+                le = edge_l(side_l(l, e, side), ne, nc)
                 for k in range(L):
-                    if k > edge_l(l, ne, nc) and abs(Lcf[k, k]) < tau:
+                    if k > le and abs(Lcf[k, k]) < tau:
                         # decayed diagonal of L_c^f: the dual constraint is dropped
                         # (Sec. 2.2.4 discard threshold; primal rows are kept)
                         continue
@@ -163,7 +170,7 @@ class Constraints:
                     cols += list(self.off[c] + nzc) + list(self.off[e] + nzf)
                     vals += list(Rc[k, nzc]) + list(-Tf[k, nzf])
                     self.d.append(0.0)
-                    self.primal.append(k <= edge_l(l, ne, nc))
+                    self.primal.append(k <= le)
                     self.kind.append("edge")
                     self.row_edge.append(eid)
                     self.row_k.append(k)
@@ -224,9 +231,9 @@ def algorithm1(mesh, degrees, l, bc):
         for side in (1, 2, 3, 4):
             bnd = mesh.boundary_side(e, side)
             nbrs = [] if bnd else mesh.neighbours(e, side)
-            le = l
+            le = side_l(l, e, side)
             if len(nbrs) == 1:
-                le = edge_l(l, n, int(degrees[nbrs[0][0]]) + 1)
+                le = edge_l(le, n, int(degrees[nbrs[0][0]]) + 1)
             first = side_modes(n, side)[: max(0, le - 1)]
             coarse_nbr = False
             if bnd:

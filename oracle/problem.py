@@ -24,13 +24,48 @@ def make_mesh(w):
 def coarse_order(w, mesh=None):
     """l: explicit, or from the dispersion rule of Sec. 2.3.4 evaluated per element
     with its longest edge and its local wavenumber k sqrt(eps_r), taking the largest
-    (with eps_r = 1: the free-space k and the longest edge, as in Sec. 3.3.1)."""
+    (with eps_r = 1: the free-space k and the longest edge, as in Sec. 3.3.1); with
+    w["l_per_edge"] the per-edge orders of edge_orders (a function of (e, side))."""
     if w.get("l", -1) >= 1:
         return int(w["l"])
     mesh = mesh or make_mesh(w)
+    if w.get("l_per_edge", False):
+        return edge_orders(w, mesh)
     eps = np.asarray(w.get("eps_r", np.ones(mesh.E)))
     kh = max(w["k"] * np.sqrt(eps[e]) * max(mesh.size(e)) for e in range(mesh.E))
     return lg.dispersion_l(kh, 1.0)
+
+
+def edge_orders(w, mesh=None, safety=0):
+    """Per-edge coarse order (the non-uniform choice of l that the conclusions
+    propose for non-uniformly refined meshes): the dispersion rule of Sec. 2.3.4
+    evaluated on each edge with, for every element touching the edge, its own
+    side length along the edge and its local wavenumber k sqrt(eps_r), the
+    largest value taken.  A hanging edge is the coarse side with all the fine
+    leaves along it, so both of its sides get one value.  Returns l(e, side)."""
+    mesh = mesh or make_mesh(w)
+    eps = np.asarray(w.get("eps_r", np.ones(mesh.E)))
+    k = float(w["k"])
+
+    def side_len(e, side):
+        hx, hy = mesh.size(e)
+        return hy if side in (1, 2) else hx
+
+    def value(e, side):
+        if not mesh.boundary_side(e, side):
+            nbrs = mesh.neighbours(e, side)
+            if len(nbrs) == 1 and mesh.leaves[nbrs[0][0]][0] < mesh.leaves[e][0]:
+                e, side = nbrs[0]          # the coarse side holds the edge
+        touching = [(e, side)] + ([] if mesh.boundary_side(e, side) else mesh.neighbours(e, side))
+        return max(lg.dispersion_l(k * np.sqrt(eps[f]) * side_len(f, sf), 1.0) for f, sf in touching) + safety
+
+    cache = {}
+
+    def l_of(e, side):
+        if (e, side) not in cache:
+            cache[(e, side)] = value(e, side)
+        return cache[(e, side)]
+    return l_of
 
 
 def robin_labels(mesh):
