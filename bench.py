@@ -185,6 +185,22 @@ def refined_disk(hdp, torch, steps, warmup):
                    n_coarse=s.info["n_coarse"], classes=s.info["n_classes"])
         s.close()
         print(f"bench: refined disk {prec} done ({ms:.1f} ms per solve)", file=sys.stderr, flush=True)
+    # the per-edge coarse order (smaller coarse space on the refined part), FP64
+    s = hdp.Solver(dict(w, l_per_edge=True), tol=1e-8, max_iter=600)
+    for _ in range(max(1, warmup)):
+        s.solve("plane_wave_scattered", [0.0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, st = s.solve("plane_wave_scattered", [0.0])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    out["fp64_per_edge_l"] = dict(ms_per_solve=ms, dof_per_s=s.dof / (ms * 1e-3), iterations=st["iterations"],
+                                  true_residual=st["true_residual"], converged=st["converged"],
+                                  setup_ms=s.info["setup_ms"], n_lambda=s.info["n_lambda"],
+                                  n_coarse=s.info["n_coarse"], l_max=s.info["l"])
+    s.close()
+    print(f"bench: refined disk per-edge l done ({ms:.1f} ms per solve)", file=sys.stderr, flush=True)
     return out
 
 

@@ -112,6 +112,12 @@ typedef struct {
                                  Loads stay those of the unstretched problem (a layer leaf with
                                  eps_r = 1 carries no scattered-field source).  HDP_E_UNSUPPORTED
                                  with hanging edges. */
+  int32_t l_per_edge;         /* with l <= 0: 1 evaluates the dispersion rule edge by edge (the
+                                 non-uniform l the conclusions propose for non-uniformly refined
+                                 meshes): on each edge, for every leaf touching it, its own side
+                                 length along the edge and k sqrt(eps_r), the largest value taken
+                                 (plus l_safety); a hanging edge is the coarse side with its fine
+                                 leaves, so both sides agree.  hdp_stats.l reports the largest. */
 } hdp_problem;
 
 typedef struct {
@@ -126,9 +132,11 @@ typedef struct {
 /* hdp_options.flags: replay each GMRES iteration as a captured HIP graph
  * instead of launching its kernels one by one. */
 #define HDP_FLAG_GRAPH 1
-/* coarse factor: by default a dense inverse up to 12,000 coarse unknowns and the
+/* coarse factor: by default a dense inverse up to 6,000 coarse unknowns and the
    nested-dissection multifrontal factor above; these flags force one of them, or
-   the block-tridiagonal strip factor (at most one of the three may be set) */
+   the block-tridiagonal strip factor (at most one of the three may be set).  When the
+   set-up check of the factor (hdp_stats.coarse_residual) exceeds 1e-10, every coarse
+   solve is refined once against the assembled K (the check reports the refined solve). */
 #define HDP_FLAG_COARSE_BLOCK 2
 #define HDP_FLAG_COARSE_DENSE 4
 #define HDP_FLAG_COARSE_ND 8

@@ -35,7 +35,8 @@ class _Mesh(ctypes.Structure):
 class _Problem(ctypes.Structure):
     _fields_ = [("k", ctypes.c_double), ("eps_r", ctypes.POINTER(ctypes.c_double)),
                 ("l", ctypes.c_int32), ("l_safety", ctypes.c_int32), ("discard_tol", ctypes.c_double),
-                ("robin_modified", ctypes.c_int32), ("pml_sigma", ctypes.POINTER(ctypes.c_double))]
+                ("robin_modified", ctypes.c_int32), ("pml_sigma", ctypes.POINTER(ctypes.c_double)),
+                ("l_per_edge", ctypes.c_int32)]
 
 
 class _Options(ctypes.Structure):
@@ -138,7 +139,8 @@ def _structs(w, l_safety=0):
     prob = _Problem(float(w["k"]), eps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                     int(w.get("l", -1)), int(l_safety), float(w.get("discard_tol", 0.0)),
                     int(bool(w.get("robin_modified", False))),
-                    sig.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if sig is not None else None)
+                    sig.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if sig is not None else None,
+                    int(bool(w.get("l_per_edge", False))))
     return mesh, prob, (leaves, deg, eps, sig)
 
 

@@ -596,6 +596,31 @@ void build_device(Handle& h) {
   // a gross failure of the factor (an unstable pivot sequence) shows here; a
   // residual at the level of cond(K) * eps is reported in the stats
   h.coarse_check = coarse_residual(h, kidx, kval);
+  if (h.coarse_check > 1e-10) {
+    // an ill-conditioned K costs the factor accuracy (the explicit inverse, or
+    // block elimination that pivots only inside each block): every coarse solve
+    // is then refined once against the assembled K
+    std::vector<int64_t> ptr(size_t(h.nK) + 1, 0);
+    for (int64_t key : kidx) ptr[key % h.nK + 1]++;
+    for (int i = 0; i < h.nK; ++i) ptr[i + 1] += ptr[i];
+    std::vector<int> col(kidx.size());
+    std::vector<double2> val(kidx.size());
+    std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+    for (size_t t = 0; t < kidx.size(); ++t) {
+      const int64_t at = fill[kidx[t] % h.nK]++;
+      col[at] = int(kidx[t] / h.nK);
+      val[at] = kval[t];
+    }
+    d.k_ptr = upload(h, ptr);
+    d.k_col = upload(h, col);
+    d.k_val = upload(h, val);
+    d.nd_r = dalloc<double2>(h, size_t(h.nK) * Rp);
+    d.nd_dx = dalloc<double2>(h, size_t(h.nK) * Rp);
+    h.coarse_refine = true;
+    h.coarse_bytes = 2 * h.coarse_bytes + 20.0 * double(kidx.size()) + 8.0 * (h.nK + 1);
+    h.coarse_flops = 2 * h.coarse_flops + 8.0 * double(kidx.size());
+    h.coarse_check = coarse_residual(h, kidx, kval);
+  }
   if (!(h.coarse_check < 1e-6)) {
     char msg[96];
     std::snprintf(msg, sizeof msg, "coarse factor inaccurate (relative residual %.3e)", h.coarse_check);
@@ -613,7 +638,7 @@ void build_device(Handle& h) {
 // Operators on dual vectors ([nlam][R]).
 // w = K^-1 g for R right-hand sides ([n_K][R]): a streaming GEMV kernel for a
 // few columns, a plain library GEMM (rocBLAS zgemm) once R makes it compute-bound.
-void coarse_solve(Handle& h, const double2* g, double2* w, int R) {
+static void coarse_solve_once(Handle& h, const double2* g, double2* w, int R) {
   if (h.coarse_mode == 1) {
     coarse_solve_blocks(h, g, w, R);
     return;
@@ -634,6 +659,16 @@ void coarse_solve(Handle& h, const double2* g, double2* w, int R) {
                                     reinterpret_cast<const rocblas_double_complex*>(h.d.Kinv), h.nK, &zero,
                                     reinterpret_cast<rocblas_double_complex*>(w), R);
   if (st != rocblas_status_success) fail(HDP_E_DEVICE, "rocblas_zgemm failed in the coarse solve");
+}
+
+void coarse_solve(Handle& h, const double2* g, double2* w, int R) {
+  coarse_solve_once(h, g, w, R);
+  if (h.coarse_refine) {   // w += K^-1 (g - K w), once, against the assembled K
+    auto& d = h.d;
+    launch_csr_residual(h.nK, d.k_ptr, d.k_col, d.k_val, w, g, d.nd_r, R, h.stream);
+    coarse_solve_once(h, d.nd_r, d.nd_dx, R);
+    launch_axpby(w, d.nd_dx, w, int64_t(h.nK) * R, 1.0, 1.0, h.stream);
+  }
 }
 
 // F up to the element slots: z = A_11^-1 y + Phi K^-1 Phi^T y with y = C_1^T v,
@@ -1104,7 +1139,7 @@ hdp_status hdp_get_stats(const hdp_handle* H, hdp_stats* st) {
   st->min_element_margin = h.min_margin;
   st->setup_ms = h.setup_ms;
   st->coarse_residual = h.coarse_check;
-  st->coarse_mode = h.coarse_mode >= 0 ? h.coarse_mode : (h.nK > 12000 ? 2 : 0);
+  st->coarse_mode = h.coarse_mode >= 0 ? h.coarse_mode : (h.nK > 6000 ? 2 : 0);
   st->coarse_blocks = st->coarse_mode == 1   ? int(h.cb_off.size()) - 1
                       : st->coarse_mode == 2 ? int(h.nd_off.size()) - 1
                                              : 1;

@@ -137,6 +137,7 @@ struct Handle {
   std::vector<int64_t> nd_boff;
   std::vector<int> nd_bnd;
   std::vector<NDLevel> nd_levels;   // per tree depth
+  bool coarse_refine = false;       // refine each coarse solve once (set at setup from the check)
   std::vector<int> cb_off;
   std::vector<int64_t> cb_D, cb_W, cb_U;
   double coarse_check = 0;         // relative residual of the coarse factor on a test vector
@@ -188,6 +189,11 @@ struct Handle {
     int64_t *nd_boff = nullptr, *nd_uoff = nullptr, *nd_mD = nullptr, *nd_mL = nullptr, *nd_mLt = nullptr;
     int64_t nd_urows = 0;
     int2 *nd_t1f = nullptr, *nd_t1b = nullptr;
+    // one step of iterative refinement of the coarse solve (when the factor alone
+    // misses 1e-10): K in CSR by row, residual and correction buffers
+    int64_t* k_ptr = nullptr;
+    int* k_col = nullptr;
+    double2 *k_val = nullptr, *nd_r = nullptr, *nd_dx = nullptr;
     int4 *nd_tRf = nullptr, *nd_tRb = nullptr;
     double2* nd_P = nullptr;   // partial tiles of the split top levels
     int* cb_off = nullptr;

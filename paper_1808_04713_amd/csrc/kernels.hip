@@ -605,6 +605,42 @@ __global__ void k_nd_reduce(const int4* __restrict__ task, int ntiles, int S, co
   }
 }
 
+// r = g - K x with K in CSR by row: one wave per row; at one column the lanes
+// take the row's entries, otherwise the lanes are the columns.
+__global__ void __launch_bounds__(NT) k_csr_residual(int n, const int64_t* __restrict__ ptr,
+                                                     const int* __restrict__ col, const double2* __restrict__ val,
+                                                     const double2* __restrict__ x, const double2* __restrict__ g,
+                                                     double2* __restrict__ r, int R) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const int64_t a = ptr[i], b = ptr[i + 1];
+  if (R == 1) {
+    double ax = 0, ay = 0;
+    for (int64_t t = a + lane; t < b; t += 64) {
+      const double2 m = val[t], v = x[col[t]];
+      ax += m.x * v.x - m.y * v.y;
+      ay += m.x * v.y + m.y * v.x;
+    }
+    for (int sh = 32; sh > 0; sh >>= 1) {
+      ax += __shfl_xor(ax, sh, 64);
+      ay += __shfl_xor(ay, sh, 64);
+    }
+    if (lane == 0) r[i] = make_double2(g[i].x - ax, g[i].y - ay);
+    return;
+  }
+  for (int c = lane; c < R; c += 64) {
+    double ax = 0, ay = 0;
+    for (int64_t t = a; t < b; ++t) {
+      const double2 m = val[t], v = x[(int64_t)col[t] * R + c];
+      ax += m.x * v.x - m.y * v.y;
+      ay += m.x * v.y + m.y * v.x;
+    }
+    const double2 gg = g[(int64_t)i * R + c];
+    r[(int64_t)i * R + c] = make_double2(gg.x - ax, gg.y - ay);
+  }
+}
+
 // w = K^-1 g: one wavefront per row of the (symmetric) inverse, RHS in chunks of 8.
 __global__ void __launch_bounds__(NT) k_coarse_gemv(int nK, const double2* __restrict__ Kinv,
                                                     const double2* __restrict__ g, double2* __restrict__ w,
@@ -1952,6 +1988,12 @@ void launch_nd_tiles(bool bwd, const int4* task, int ntiles, int S, const NDView
   if (S > 1)
     hipLaunchKernelGGL(k_nd_reduce, dim3(nblocks(int64_t(ntiles) * SMJ * R)), dim3(NT), 0, s, task, ntiles, S, P, nd,
                        F, A, X, R, bwd ? 1 : 0);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_csr_residual(int n, const int64_t* ptr, const int* col, const double2* val, const double2* x,
+                         const double2* g, double2* r, int R, hipStream_t s) {
+  hipLaunchKernelGGL(k_csr_residual, dim3(nblocks(n, NT / 64)), dim3(NT), 0, s, n, ptr, col, val, x, g, r, R);
   HIPCHECK(hipGetLastError());
 }
 

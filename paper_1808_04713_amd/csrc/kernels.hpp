@@ -86,6 +86,9 @@ void launch_nd_bwd1(const int2* task, int ntask, const NDView& v, const double2*
 // to P (ntiles * S * 32 * 64 values) and a second kernel adds them
 void launch_nd_tiles(bool bwd, const int4* task, int ntiles, int S, const NDView& v, const double2* g, double2* F,
                      double2* A, double2* X, int R, double2* P, hipStream_t s);
+// r = g - K x, K in CSR by row (ptr[n + 1], col, val), [n][R] vectors
+void launch_csr_residual(int n, const int64_t* ptr, const int* col, const double2* val, const double2* x,
+                         const double2* g, double2* r, int R, hipStream_t s);
 void launch_dense_scatter(const int64_t* idx, const double2* val, int64_t nnz, double2* M,
                           hipStream_t s);
 

@@ -757,7 +757,31 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
   for (int e = 0; e < E; ++e)
     khmax = std::max(khmax, prob->k * std::sqrt(std::max(h.eps[e], 0.0)) * std::max(h.hx[e], h.hy[e]));
   h.l = prob->l > 0 ? prob->l : dispersion_l(khmax, 1.0) + std::max(0, prob->l_safety);
-  const int l = h.l;
+  // per-edge orders (l_per_edge): the rule on each edge with, for every leaf
+  // touching it, its own side length along the edge and k sqrt(eps_r); a fine
+  // side of a hanging edge takes the value of the coarse side that holds it
+  std::vector<int> l_side(4 * size_t(E), h.l);
+  if (prob->l <= 0 && prob->l_per_edge) {
+    auto len = [&](int f, int s) { return s <= 2 ? h.hy[f] : h.hx[f]; };
+    auto rule = [&](int f, int s) {
+      return dispersion_l(prob->k * std::sqrt(std::max(h.eps[f], 0.0)) * len(f, s), 1.0);
+    };
+    int lmax = 1;
+    for (int e = 0; e < E; ++e)
+      for (int s = 1; s <= 4; ++s) {
+        int ee = e, ss = s;
+        if (h.side_type[4 * e + s - 1] == 2) { ee = h.nb_e[4 * e + s - 1]; ss = h.nb_s[4 * e + s - 1]; }
+        const int sj = 4 * ee + ss - 1;
+        int v = rule(ee, ss);
+        if (h.side_type[sj] == 1) v = std::max(v, rule(h.nb_e[sj], h.nb_s[sj]));
+        if (h.side_type[sj] == 3)
+          for (int f : h.side_nbrs[sj]) v = std::max(v, rule(f, ss % 2 == 1 ? ss + 1 : ss - 1));
+        v += std::max(0, prob->l_safety);
+        l_side[4 * e + s - 1] = v;
+        lmax = std::max(lmax, v);
+      }
+    h.l = lmax;
+  }
   // per side: the primal count le = min(l, p, p_neighbour) of its edge and the
   // highest bubble index among the element's coarse modes
   // and the highest dual-slot bubble gtop: p, or on the fine side of a hanging
@@ -769,7 +793,7 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
   for (int e = 0; e < E; ++e)
     for (int s = 1; s <= 4; ++s) {
       const int si = 4 * e + s - 1, p = h.deg[e];
-      int le = std::min(l, p), top = le, gtop = p;
+      int le = std::min(l_side[si], p), top = le, gtop = p;
       if (h.side_type[si] == 1 || h.side_type[si] == 2) le = top = std::min(le, h.deg[h.nb_e[si]]);
       else if (h.side_type[si] == 3) top = p;
       if (h.side_type[si] == 0) gtop = top;
@@ -1076,10 +1100,10 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
   build_transposes(h, true);
   build_hanging_blocks(h);
   // coarse factor: dense inverse for small coarse spaces (one streaming GEMV per
-  // solve), the nested-dissection factor beyond 12,000 unknowns
+  // solve, 164 MB at 3,201 unknowns), the nested-dissection factor beyond 6,000
   // (a requested factor gets small blocks, so that small meshes exercise it too)
   const bool requested = h.coarse_mode >= 0;
-  if (h.coarse_mode < 0) h.coarse_mode = h.nK > 12000 ? 2 : 0;
+  if (h.coarse_mode < 0) h.coarse_mode = h.nK > 6000 ? 2 : 0;
   if (h.coarse_mode == 2) order_coarse_nd(h, requested ? 32 : 96);
   else order_coarse_strips(h);
   // algorithmic work counts

@@ -151,3 +151,24 @@ def test_layers_are_checked_and_refused_with_hanging_edges():
     with pytest.raises(hdp.HdpError) as e:
         hdp.inspect(wh)
     assert e.value.status == -7
+
+
+@pytest.mark.parametrize("k,seed", [(30.0, 0), (45.0, 1)])
+def test_per_edge_order_counts_match_the_oracle(k, seed):
+    """Per-edge coarse orders on a refined mesh with a dielectric disk: the
+    library's largest order, dual rows and coarse unknowns equal the oracle's
+    (its Constraints and Algorithm 1 with the same per-edge function), and the
+    coarse space is smaller than with the one global order."""
+    from oracle import constraints as cs
+    import test_oracle_edge_l as tel
+    w = dict(tel._disk(k=k, seed=seed), l_per_edge=True)
+    disc = pb.Discretisation(w)
+    lf = pb.edge_orders(w, disc.mesh)
+    con = cs.Constraints(disc.mesh, disc.degrees, lf, disc.bc)
+    status = cs.algorithm1(disc.mesh, disc.degrees, lf, disc.bc)
+    n_dual = int((~con.primal).sum())
+    n_type2 = sum(int((st == 2).sum()) for st in status)
+    st = hdp.inspect(w)
+    lmax = max(lf(e, s) for e in range(disc.mesh.E) for s in (1, 2, 3, 4))
+    assert (st["l"], st["n_lambda"], st["n_coarse"]) == (lmax, n_dual, n_type2)
+    assert st["n_coarse"] < hdp.inspect(dict(w, l_per_edge=False))["n_coarse"]
