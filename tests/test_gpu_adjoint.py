@@ -52,8 +52,8 @@ def test_full_size_design_block_against_central_differences():
     """64x64 elements, p = 12, k = 150, eps_r ~ U[1,4] on the central 16x16 block,
     J = |E_far(0)|^2 for normal incidence; central differences of the GPU's J on
     four random design parameters.  J (about 1.5) is reproducible to about 1e-10
-    between set-ups (the strip coarse factor's residual is 2e-11 on this mesh),
-    so a difference quotient carries about 1e-10/h of noise: at h = 1e-6 it is
+    between set-ups (each set-up factors the coarse matrix anew), so a difference
+    quotient carries about 1e-10/h of noise: at h = 1e-6 it is
     off by 6e-3 relative, at 1e-5 by 7e-4, at 1e-4 by 1e-4, at 1e-3 by 3e-5 on
     the first sampled element.  h = 3e-4 balances noise and truncation."""
     w = W.design_block_64x64()
