@@ -214,7 +214,7 @@ struct Handle {
     double2* mass_fac = nullptr;   // per element s_x s_y (layers only; null without layers)
     double2 *Ex = nullptr, *Ey = nullptr, *Dinv = nullptr, *G = nullptr, *Kc = nullptr;
     double* V = nullptr;      // GLL sampling matrices per class
-    double2* Kinv = nullptr;  // nK x nK, row-major
+    double2* Kinv = nullptr;  // nK x nK (symmetric)
     // work
     double2 *slotA = nullptr, *slotB = nullptr, *cmA = nullptr, *gK = nullptr, *wK = nullptr;
     float2 *slotA_f = nullptr, *slotB_f = nullptr, *cmA_f = nullptr;

@@ -1282,8 +1282,10 @@ __global__ void __launch_bounds__(NT) k_mdot(const double2* __restrict__ V, int6
 // its own items (row chunk c, group of GVW vectors) and reduces with shuffles
 // only, so no workgroup barrier sits between the loads and the partial sums.
 // Lane l reads entries lo R + l + 64 t of the chunk; since 64 is a multiple of
-// R, its column is l % R throughout.
-constexpr int GVW = 4;
+// R, its column is l % R throughout.  One vector per item and 256-entry chunks
+// (the 32x32 point source: 109 chunks x j items over 16,384 waves) measured
+// fastest among 1..8 vectors, 64..1024 entries and 4,096..32,768 waves.
+constexpr int GVW = 1;
 
 __global__ void __launch_bounds__(NT) k_mdot_wave(const double2* __restrict__ V, int64_t vs,
                                                   const int* __restrict__ jptr, int jfix,
@@ -1788,7 +1790,7 @@ GmresDims gmres_dims(int n, int R, int maxvec) {
     g.chunk = int(std::max<int64_t>(256 / R, (int64_t(n) + 511) / 512));
     g.nchunks = int((int64_t(n) + g.chunk - 1) / g.chunk);
     g.ngroups = (maxvec + GVW - 1) / GVW;
-    g.grid = int(std::max<int64_t>(1, std::min<int64_t>(1024, (int64_t(g.nchunks) * g.ngroups + 3) / 4)));
+    g.grid = int(std::max<int64_t>(1, std::min<int64_t>(4096, (int64_t(g.nchunks) * g.ngroups + 3) / 4)));
   } else {
     // up to 512 row chunks (the partial buffer holds 512) keep the chip busy with
     // many right-hand sides while only a few Arnoldi vectors exist
