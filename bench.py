@@ -32,7 +32,7 @@ HBM_FAMILIES = {"coarse_gemv", "coarse_assemble", "row_gather", "gmres_dots", "g
 # HBM bytes per launch of a kernel family on the point-source workload, from the
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs calibrated on a plain 512 MiB copy
 # (profiles/point_source_32x32_kernel_stats.md); valid for the kernels as profiled
-MEASURED_TRAFFIC = {"coarse_gemv": 1.6479e8}
+MEASURED_TRAFFIC = {"gmres_dots": 2.8477e7, "coarse_gemv": 1.6480e8}
 
 
 def load_samples():
