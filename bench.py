@@ -27,12 +27,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
-HBM_FAMILIES = {"coarse_gemv", "coarse_assemble", "row_gather", "gmres_dots", "gmres_update",
+HBM_FAMILIES = {"coarse_gemv", "coarse_reduce", "coarse_assemble", "row_gather", "gmres_dots", "gmres_update",
                 "gmres_norm_scale", "element_coarse_fix", "precision_cast", "hanging_blocks"}
 # HBM bytes per launch of a kernel family on the point-source workload, from the
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs calibrated on a plain 512 MiB copy
 # (profiles/point_source_32x32_kernel_stats.md); valid for the kernels as profiled
-MEASURED_TRAFFIC = {"gmres_dots": 2.8477e7, "coarse_gemv": 1.6480e8}
+MEASURED_TRAFFIC = {}
 
 
 def load_samples():

@@ -60,7 +60,7 @@ const char* const KF_NAMES[KF_COUNT] = {"slot_apply_F", "slot_apply_P", "coarse_
                                         "slot_coarse", "row_gather", "gmres_dots", "gmres_update",
                                         "gmres_norm_scale", "fdm_local_solve", "element_coarse_fix",
                                         "gll_sample", "precision_cast", "gmres_givens", "far_field",
-                                        "hanging_blocks"};
+                                        "hanging_blocks", "coarse_reduce"};
 
 static hipEvent_t prof_event(Handle& h) {
   if (!h.prof.pool.empty()) {
@@ -139,6 +139,20 @@ static void build_coarse_dense(Handle& h, const std::vector<int64_t>& kidx, cons
   h.coarse_mode = 0;
   h.coarse_bytes = 16.0 * double(nK) * double(nK);
   h.coarse_flops = 8.0 * double(nK) * double(nK);
+  // upper tiles for the one-RHS apply: each unique entry of the symmetric
+  // inverse read once
+  const int ts = sym_tile_size();
+  h.sym_nt = int((nK + ts - 1) / ts);
+  h.sym_ntiles = h.sym_nt * (h.sym_nt + 1) / 2;
+  std::vector<int2> tij;
+  tij.reserve(h.sym_ntiles);
+  for (int I = 0; I < h.sym_nt; ++I)
+    for (int J = I; J < h.sym_nt; ++J) tij.push_back(make_int2(I, J));
+  d.sym_tij = upload(h, tij);
+  d.Ksym = dalloc<double2>(h, size_t(h.sym_ntiles) * ts * ts);
+  d.sym_part = dalloc<double2>(h, size_t(h.sym_nt) * h.sym_nt * ts);
+  launch_pack_sym_tiles(h, h.stream);
+  h.coarse_bytes1 = 16.0 * double(nK) * double(nK + 1) / 2;
 }
 
 static void zgemm(Handle& h, rocblas_operation tb, int m, int n, int k, double alpha, const double2* A, int lda,
@@ -618,6 +632,7 @@ void build_device(Handle& h) {
     d.nd_dx = dalloc<double2>(h, size_t(h.nK) * Rp);
     h.coarse_refine = true;
     h.coarse_bytes = 2 * h.coarse_bytes + 20.0 * double(kidx.size()) + 8.0 * (h.nK + 1);
+    if (h.coarse_bytes1 > 0) h.coarse_bytes1 = 2 * h.coarse_bytes1 + 20.0 * double(kidx.size()) + 8.0 * (h.nK + 1);
     h.coarse_flops = 2 * h.coarse_flops + 8.0 * double(kidx.size());
     h.coarse_check = coarse_residual(h, kidx, kval);
   }
@@ -661,6 +676,23 @@ static void coarse_solve_once(Handle& h, const double2* g, double2* w, int R) {
   if (st != rocblas_status_success) fail(HDP_E_DEVICE, "rocblas_zgemm failed in the coarse solve");
 }
 
+// The coarse solve inside the operator applications, timed per kernel family:
+// the one-RHS symmetric-tile apply as its two kernels, everything else as one.
+static void coarse_solve_timed(Handle& h, const double2* g, double2* w, int R) {
+  const double vec = 32.0 * double(h.nK) * R;
+  if (R == 1 && h.coarse_mode == 0 && h.d.Ksym && !h.coarse_refine) {
+    {
+      Timed t(h, KF_COARSE, h.coarse_bytes1 + vec / 2, h.coarse_flops);
+      launch_coarse_symv_tiles(h, g, h.stream);
+    }
+    Timed t(h, KF_COARSE_RED, 16.0 * double(h.sym_nt) * h.sym_nt * sym_tile_size() + vec / 2, 0);
+    launch_coarse_symv_reduce(h, w, h.stream);
+    return;
+  }
+  Timed t(h, KF_COARSE, (R == 1 && h.coarse_bytes1 > 0 ? h.coarse_bytes1 : h.coarse_bytes) + vec, h.coarse_flops * R);
+  coarse_solve(h, g, w, R);
+}
+
 void coarse_solve(Handle& h, const double2* g, double2* w, int R) {
   coarse_solve_once(h, g, w, R);
   if (h.coarse_refine) {   // w += K^-1 (g - K w), once, against the assembled K
@@ -695,8 +727,7 @@ static void apply_F_slots(Handle& h, const double2* v, int R, int prec) {
     else launch_assemble<float2>(h, d.cmA_f, nullptr, v, 1.0, d.gK, R, s);
   }
   {
-    Timed t(h, KF_COARSE, h.coarse_bytes + 2 * nK * c, h.coarse_flops * R);
-    coarse_solve(h, d.gK, d.wK, R);
+    coarse_solve_timed(h, d.gK, d.wK, R);
   }
   {
     Timed t(h, KF_SLOT_COARSE, nsl * cw * 2 + ncm * c + ob * h.phi_bytes, h.flops_coarse * R);
@@ -806,8 +837,7 @@ void element_solve(Handle& h, double2* X, const double2* Bfull, const double2* n
     launch_assemble<double2>(h, d.cmA, Bfull, nu, -1.0, d.gK, R, s);
   }
   {
-    Timed t(h, KF_COARSE, h.coarse_bytes + 2 * nK * c, h.coarse_flops * R);
-    coarse_solve(h, d.gK, d.wK, R);
+    coarse_solve_timed(h, d.gK, d.wK, R);
   }
   {
     Timed t(h, KF_ELEMENT_MISC, 2 * dof * c + ncm * c, 0);
@@ -842,7 +872,6 @@ GmresResult gmres(Handle& h, const double2* rhs, double2* x, int R, int prec, do
   const int maxvec = h.max_iter + 1;
   max_iter = std::min(max_iter, h.max_iter);
   GmresDims gd = gmres_dims(n, R, maxvec);
-  const int nupd = update_blocks(n, R);
   const double vb = 16.0 * double(vs);
   GmresResult res;
   res.iters.assign(R, 0);
@@ -863,19 +892,20 @@ GmresResult gmres(Handle& h, const double2* rhs, double2* x, int R, int prec, do
       apply_PF(h, d.vcur, d.w, R, prec);
       for (int pass = 0; pass < 2; ++pass) {
         {
-          Timed t(h, KF_DOTS, (nv + 1) * vb, 8.0 * nv * double(vs));
-          launch_mdot(d.V_kry, vs, d.jdev, 0, d.w, n, R, gd, maxvec, d.part, s);
-          launch_mdot_reduce(d.part, gd, d.jdev, 0, maxvec, R, d.hbuf, d.hsum, pass == 0, s);
+          // the second pass also forms |w|^2
+          Timed t(h, KF_DOTS, (nv + 1) * vb, 8.0 * (nv + pass) * double(vs));
+          launch_mdot(d.V_kry, vs, d.jdev, 0, d.w, n, R, gd, maxvec, d.part, pass, s);
+          launch_mdot_reduce(d.part, gd, d.jdev, 0, maxvec, R, d.hbuf, d.hsum, pass == 0, pass, s);
         }
-        {
-          // the second pass also leaves the partial squared norms of w
+        if (pass == 0) {
           Timed t(h, KF_UPDATE, (nv + 2) * vb, 8.0 * nv * double(vs));
-          launch_mupdate(d.V_kry, vs, d.jdev, 0, d.hbuf, d.w, n, R, -1.0, pass == 1 ? d.npart : nullptr, s);
+          launch_mupdate(d.V_kry, vs, d.jdev, 0, d.hbuf, d.w, n, R, -1.0, nullptr, s);
+        } else {
+          // second update fused with the normalisation: V_{j+1} and the next
+          // operator input are written directly
+          Timed t(h, KF_UPDATE, (nv + 3) * vb, (8.0 * nv + 2.0) * double(vs));
+          launch_mupdate_normalize(d.V_kry, vs, d.jdev, d.hbuf, d.w, n, R, d.vcur, d.nrm, s);
         }
-      }
-      {
-        Timed t(h, KF_NORM_SCALE, 3 * vb, 2.0 * double(vs));
-        launch_normalize_parts(d.w, n, R, d.npart, nupd, d.nrm, d.V_kry, d.jdev, vs, d.vcur, gd.nnorm, s);
       }
       {
         Timed t(h, KF_GIVENS, 0, 0);

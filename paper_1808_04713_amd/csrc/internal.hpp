@@ -57,7 +57,7 @@ struct DevOps {
 
 enum KernelFamily {
   KF_SLOT_F = 0, KF_SLOT_P, KF_ASSEMBLE, KF_COARSE, KF_SLOT_COARSE, KF_ROWGATHER, KF_DOTS, KF_UPDATE,
-  KF_NORM_SCALE, KF_FDM, KF_ELEMENT_MISC, KF_GLL, KF_CAST, KF_GIVENS, KF_FAR, KF_HBLOCK, KF_COUNT
+  KF_NORM_SCALE, KF_FDM, KF_ELEMENT_MISC, KF_GLL, KF_CAST, KF_GIVENS, KF_FAR, KF_HBLOCK, KF_COARSE_RED, KF_COUNT
 };
 extern const char* const KF_NAMES[KF_COUNT];
 
@@ -141,6 +141,8 @@ struct Handle {
   std::vector<int> cb_off;
   std::vector<int64_t> cb_D, cb_W, cb_U;
   double coarse_check = 0;         // relative residual of the coarse factor on a test vector
+  int sym_nt = 0, sym_ntiles = 0;   // tile rows and upper tiles of the symmetric coarse inverse
+  double coarse_bytes1 = 0;         // factor bytes of a one-RHS coarse solve (half with the tiles)
   double coarse_bytes = 0, coarse_flops = 0;   // per coarse solve and RHS column (flops), factor bytes
   // C_2 (dual rows x coarse unknowns), non-zero only on hanging edges
   std::vector<int> c2_ptr, c2_dof, c2t_ptr, c2t_row;
@@ -215,6 +217,9 @@ struct Handle {
     double2 *Ex = nullptr, *Ey = nullptr, *Dinv = nullptr, *G = nullptr, *Kc = nullptr;
     double* V = nullptr;      // GLL sampling matrices per class
     double2* Kinv = nullptr;  // nK x nK (symmetric)
+    // the same inverse as its upper 64 x 64 tiles (one-RHS coarse apply)
+    double2 *Ksym = nullptr, *sym_part = nullptr;
+    int2* sym_tij = nullptr;
     // work
     double2 *slotA = nullptr, *slotB = nullptr, *cmA = nullptr, *gK = nullptr, *wK = nullptr;
     float2 *slotA_f = nullptr, *slotB_f = nullptr, *cmA_f = nullptr;

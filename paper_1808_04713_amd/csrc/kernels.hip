@@ -672,6 +672,153 @@ __global__ void __launch_bounds__(NT) k_coarse_gemv(int nK, const double2* __res
 }
 
 // ---------------------------------------------------------------------------
+// One right-hand side against the symmetric inverse held as its upper 64 x 64
+// tiles (I <= J): every tile is read once and serves both the block row I
+// (y_I += T x_J) and, transposed, the block row J (y_J += T^T x_I), so the
+// coarse step streams half of the dense inverse.  Tile t writes its two
+// contributions to fixed places of a partial buffer P[row tile][column tile][64];
+// a second kernel adds them per row in a fixed order (no atomics, so repeated
+// solves give identical results).
+constexpr int SYM_TILE = 64;
+
+// Packs the upper tiles of K^-1 from the dense row-major inverse, taking
+// (A_ij + A_ji) / 2 (the computed inverse is symmetric up to rounding) and
+// zero outside n_K.
+__global__ void __launch_bounds__(NT) k_pack_sym_tiles(int nK, const double2* __restrict__ A,
+                                                       const int2* __restrict__ tij, double2* __restrict__ tiles) {
+  const int t = blockIdx.x;
+  const int2 IJ = tij[t];
+  double2* T = tiles + (int64_t)t * SYM_TILE * SYM_TILE;
+  for (int e = threadIdx.x; e < SYM_TILE * SYM_TILE; e += NT) {
+    const int i = IJ.x * SYM_TILE + e / SYM_TILE, j = IJ.y * SYM_TILE + e % SYM_TILE;
+    double2 v = make_double2(0, 0);
+    if (i < nK && j < nK) {
+      const double2 a = A[(int64_t)i * nK + j], b = A[(int64_t)j * nK + i];
+      v = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y + b.y));
+    }
+    T[e] = v;
+  }
+}
+
+// SYM_WAVES waves per tile, rows in batches of SYM_KB: lane = column, the
+// batch's loads all in flight at once.
+constexpr int SYM_KB = 8;
+
+// Exchange steps of the transposed row reduction: with M values per lane the
+// partner is the lane across bit 32 M / SYM_KB, and that bit chooses the half
+// of the values a lane keeps (and adds the partner's copy to).  The choice is
+// made with weights 0 / 1 (exact for finite values) rather than selects, so
+// that the values stay in fixed registers.
+template <int M>
+__device__ __forceinline__ void halve(double* vx, double* vy, int lane) {
+  if constexpr (M > 1) {
+    constexpr int o = 32 * M / SYM_KB;
+    const double fh = (lane & o) ? 1.0 : 0.0, fl = 1.0 - fh;
+#pragma unroll
+    for (int i = 0; i < M / 2; ++i) {
+      const double sx = fh * vx[i] + fl * vx[i + M / 2], sy = fh * vy[i] + fl * vy[i + M / 2];
+      const double kx = fl * vx[i] + fh * vx[i + M / 2], ky = fl * vy[i] + fh * vy[i + M / 2];
+      vx[i] = kx + __shfl_xor(sx, o, 64);
+      vy[i] = ky + __shfl_xor(sy, o, 64);
+    }
+    halve<M / 2>(vx, vy, lane);
+  }
+}
+
+// value of lane l (uniform l) in every lane
+__device__ __forceinline__ double bcast_lane(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+constexpr int SYM_WAVES = 4;   // waves per tile, each taking SYM_TILE / SYM_WAVES rows
+
+__global__ void __launch_bounds__(SYM_WAVES * 64) k_coarse_symv_tiles(int nK, int nt, const int2* __restrict__ tij,
+                                                                      const double2* __restrict__ tiles,
+                                                                      const double2* __restrict__ g,
+                                                                      double2* __restrict__ P) {
+  __shared__ double2 red[SYM_WAVES][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int t = blockIdx.x;
+  const double2* T = tiles + (int64_t)t * SYM_TILE * SYM_TILE;
+  const int2 IJ = tij[t];
+  const int jc = IJ.y * SYM_TILE + lane;
+  const double2 xJ = jc < nK ? g[jc] : make_double2(0, 0);
+  const int ir = IJ.x * SYM_TILE + lane;
+  const double2 xIl = ir < nK ? g[ir] : make_double2(0, 0);   // x_I[lane], broadcast per row below
+  double cx = 0, cy = 0;
+  double2* Prow = P + ((int64_t)IJ.x * nt + IJ.y) * SYM_TILE;
+  constexpr int rows = SYM_TILE / SYM_WAVES;
+#pragma unroll 1
+  for (int r0 = wv * rows; r0 < (wv + 1) * rows; r0 += SYM_KB) {
+    double2 a[SYM_KB];
+#pragma unroll
+    for (int k = 0; k < SYM_KB; ++k) a[k] = T[(r0 + k) * SYM_TILE + lane];
+    double vx[SYM_KB], vy[SYM_KB];
+#pragma unroll
+    for (int k = 0; k < SYM_KB; ++k) {
+      vx[k] = a[k].x * xJ.x - a[k].y * xJ.y;
+      vy[k] = a[k].x * xJ.y + a[k].y * xJ.x;
+      const double xx = bcast_lane(xIl.x, r0 + k), xy = bcast_lane(xIl.y, r0 + k);
+      cx += a[k].x * xx - a[k].y * xy;
+      cy += a[k].x * xy + a[k].y * xx;
+    }
+    // row sums over the 64 lanes for the batch's rows at once: recursive halving
+    // (each exchange keeps half of the rows, chosen by one bit of the lane), then
+    // plain butterfly steps over the low lane bits; lane l ends with row
+    // l / (64 / SYM_KB) of the batch
+    halve<SYM_KB>(vx, vy, lane);
+#pragma unroll
+    for (int o = 32 / SYM_KB; o > 0; o >>= 1) {
+      vx[0] += __shfl_xor(vx[0], o, 64);
+      vy[0] += __shfl_xor(vy[0], o, 64);
+    }
+    constexpr int low = 64 / SYM_KB;   // lanes sharing one row sum
+    if ((lane & (low - 1)) == 0) Prow[r0 + lane / low] = make_double2(vx[0], vy[0]);
+  }
+  if (IJ.x == IJ.y) return;   // a diagonal tile serves its own block row only
+  red[wv][lane] = make_double2(cx, cy);
+  __syncthreads();
+  if (wv == 0) {
+    double sx = 0, sy = 0;
+#pragma unroll
+    for (int q = 0; q < SYM_WAVES; ++q) {
+      sx += red[q][lane].x;
+      sy += red[q][lane].y;
+    }
+    P[((int64_t)IJ.y * nt + IJ.x) * SYM_TILE + lane] = make_double2(sx, sy);
+  }
+}
+
+// w[I*64 + r] = sum_J P[I][J][r], J in increasing order within each wave's
+// share, the four shares added in a fixed order.
+__global__ void __launch_bounds__(NT) k_coarse_symv_reduce(int nK, int nt, const double2* __restrict__ P,
+                                                           double2* __restrict__ w) {
+  __shared__ double2 red[NT / 64][SYM_TILE];
+  const int I = blockIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double sx = 0, sy = 0;
+  for (int J = wv; J < nt; J += NT / 64) {
+    const double2 v = P[((int64_t)I * nt + J) * SYM_TILE + lane];
+    sx += v.x;
+    sy += v.y;
+  }
+  red[wv][lane] = make_double2(sx, sy);
+  __syncthreads();
+  if (wv == 0) {
+    double tx = 0, ty = 0;
+#pragma unroll
+    for (int q = 0; q < NT / 64; ++q) {
+      tx += red[q][lane].x;
+      ty += red[q][lane].y;
+    }
+    const int row = I * SYM_TILE + lane;
+    if (row < nK) w[row] = make_double2(tx, ty);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Full-element separable solve X = Ex [(Ex^T Y Ey) ./ D] Ey^T, one block per (element, RHS).
 __global__ void __launch_bounds__(NT) k_fdm(const int* __restrict__ elem_cls, const int64_t* __restrict__ dof_off,
                                             const int* __restrict__ cls_n, const int64_t* __restrict__ cls_E,
@@ -1243,12 +1390,14 @@ __global__ void k_dense_scatter(const int64_t* __restrict__ idx, const double2* 
 // part[c][i][r] = sum over the rows of chunk c of conj(V_i) w.  The work items
 // (chunk c, group of GV vectors) are spread over a fixed grid, so that the launch
 // shape does not depend on the number of Arnoldi vectors held on the device.
+// With self = 1 one more entry, i = nvec, holds the squared norm of w itself.
 template <int GV>
 __global__ void __launch_bounds__(NT) k_mdot(const double2* __restrict__ V, int64_t vs, const int* __restrict__ jptr,
                                              int jfix, const double2* __restrict__ w, int n, int R, int chunk,
-                                             int nchunks, int maxvec, double2* __restrict__ part) {
+                                             int nchunks, int maxvec, double2* __restrict__ part, int self) {
   __shared__ double2 red[NT];
-  const int nvec = (jptr ? *jptr : jfix) + 1;
+  const int nv0 = (jptr ? *jptr : jfix) + 1;
+  const int nvec = nv0 + self;
   const int nitems = nchunks * ((nvec + GV - 1) / GV);
   const int r = threadIdx.x % R, rl = threadIdx.x / R, step = NT / R;
   for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
@@ -1263,7 +1412,8 @@ __global__ void __launch_bounds__(NT) k_mdot(const double2* __restrict__ V, int6
 #pragma unroll
       for (int t = 0; t < GV; ++t) {
         if (i0 + t < nvec) {
-          const double2 a = V[(int64_t)(i0 + t) * vs + o];
+          const double2* src = i0 + t < nv0 ? V + (int64_t)(i0 + t) * vs : w;
+          const double2 a = src[o];
           ax[t] += a.x * b.x + a.y * b.y;
           ay[t] += a.x * b.y - a.y * b.x;
         }
@@ -1290,8 +1440,9 @@ constexpr int GVW = 1;
 __global__ void __launch_bounds__(NT) k_mdot_wave(const double2* __restrict__ V, int64_t vs,
                                                   const int* __restrict__ jptr, int jfix,
                                                   const double2* __restrict__ w, int n, int R, int chunk,
-                                                  int nchunks, int maxvec, double2* __restrict__ part) {
-  const int nvec = (jptr ? *jptr : jfix) + 1;
+                                                  int nchunks, int maxvec, double2* __restrict__ part, int self) {
+  const int nv0 = (jptr ? *jptr : jfix) + 1;
+  const int nvec = nv0 + self;
   const int nitems = nchunks * ((nvec + GVW - 1) / GVW);
   const int lane = threadIdx.x & 63;
   const int wave = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
@@ -1299,6 +1450,9 @@ __global__ void __launch_bounds__(NT) k_mdot_wave(const double2* __restrict__ V,
   for (int item = wave; item < nitems; item += nwaves) {
     const int c = item % nchunks, i0 = (item / nchunks) * GVW;
     const int64_t lo = (int64_t)c * chunk * R, hi = min((int64_t)n, (int64_t)(c + 1) * chunk) * R;
+    const double2* src[GVW];
+#pragma unroll
+    for (int t = 0; t < GVW; ++t) src[t] = i0 + t < nv0 ? V + (int64_t)(i0 + t) * vs : w;
     double ax[GVW], ay[GVW];
 #pragma unroll
     for (int t = 0; t < GVW; ++t) ax[t] = ay[t] = 0;
@@ -1308,7 +1462,7 @@ __global__ void __launch_bounds__(NT) k_mdot_wave(const double2* __restrict__ V,
 #pragma unroll
       for (int t = 0; t < GVW; ++t) {
         if (i0 + t < nvec) {
-          const double2 a = V[(int64_t)(i0 + t) * vs + e];
+          const double2 a = src[t][e];
           ax[t] += a.x * b.x + a.y * b.y;
           ay[t] += a.x * b.y - a.y * b.x;
         }
@@ -1328,14 +1482,15 @@ __global__ void __launch_bounds__(NT) k_mdot_wave(const double2* __restrict__ V,
 
 // h[i][r] = sum_c part[c][i][r]; hsum = h (first pass) or hsum += h.
 // One wavefront per (i, r): lanes stride over the chunks, then a shuffle tree.
+// With self = 1 the entry i = nvec (the squared norm of w) goes to hh only.
 __global__ void __launch_bounds__(NT) k_mdot_reduce(const double2* __restrict__ part, int nchunks,
                                                     const int* __restrict__ jptr, int jfix, int maxvec, int R,
                                                     double2* __restrict__ hh, double2* __restrict__ hsum,
-                                                    int first) {
+                                                    int first, int self) {
   const int nvec = (jptr ? *jptr : jfix) + 1;
   const int lane = threadIdx.x & 63;
   const int idx = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);   // i * R + r
-  if (idx >= nvec * R) return;
+  if (idx >= (nvec + self) * R) return;
   double ax = 0, ay = 0;
   for (int c = lane; c < nchunks; c += 64) {
     double2 a = part[(int64_t)c * maxvec * R + idx];
@@ -1348,7 +1503,7 @@ __global__ void __launch_bounds__(NT) k_mdot_reduce(const double2* __restrict__ 
   }
   if (lane == 0) {
     hh[idx] = make_double2(ax, ay);
-    if (hsum) {
+    if (hsum && idx < nvec * R) {
       if (first) hsum[idx] = make_double2(ax, ay);
       else {
         hsum[idx].x += ax;
@@ -1360,14 +1515,54 @@ __global__ void __launch_bounds__(NT) k_mdot_reduce(const double2* __restrict__ 
 
 // w[row][r] += sign * sum_{i < nvec} V_i[row][r] h[i][r]; when npart is given the
 // block also writes the partial squared norms of the updated w (per RHS column).
+//
+// NORM: the last Gram-Schmidt pass fused with the normalisation.  h[nvec] holds
+// |w|^2 (from the same multi-dot as the h_i), so the updated vector has
+// |w - V h|^2 = |w|^2 - sum_i |h_i|^2 for orthonormal V_i; every block forms
+// that norm from the same h in the same order, writes the scaled vector to
+// V_{j+1} (vout + (j + 1) vs) and out2, and block 0 publishes the norm.  w itself
+// is left as it was.
+__device__ __forceinline__ double scale_of(double nn, double* nrm) {
+  const double nv = nn > 0 ? sqrt(nn) : 0.0;
+  *nrm = nv;
+  return nv > 0 ? 1.0 / nv : 0.0;
+}
+
+template <bool NORM>
 __global__ void __launch_bounds__(NT) k_mupdate(const double2* __restrict__ V, int64_t vs, const int* __restrict__ jptr,
                                                 int jfix, const double2* __restrict__ hc, double2* __restrict__ w,
-                                                int n, int R, double sign, double* __restrict__ npart) {
+                                                int n, int R, double sign, double* __restrict__ npart,
+                                                double2* __restrict__ vout, double2* __restrict__ out2,
+                                                double* __restrict__ nrm_out) {
   __shared__ double2 red[NT];
   const int nvec = (jptr ? *jptr : jfix) + 1;
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int r = threadIdx.x % R;   // NT is a multiple of R, so idx % R == threadIdx.x % R
   double nx = 0;
+  if (NORM) {
+    double s2 = 0;
+    for (int i = 0; i < nvec; ++i) {
+      const double2 b = hc[i * R + r];
+      s2 += b.x * b.x + b.y * b.y;
+    }
+    double nrm;
+    const double f = scale_of(hc[nvec * R + r].x - s2, &nrm);
+    if (idx < (int64_t)n * R) {
+      double ax = 0, ay = 0;
+#pragma unroll 4
+      for (int i = 0; i < nvec; ++i) {
+        double2 a = V[(int64_t)i * vs + idx], b = hc[i * R + r];
+        ax += a.x * b.x - a.y * b.y;
+        ay += a.x * b.y + a.y * b.x;
+      }
+      const double2 c = w[idx];
+      const double2 o = make_double2((c.x + sign * ax) * f, (c.y + sign * ay) * f);
+      vout[(int64_t)nvec * vs + idx] = o;
+      if (out2) out2[idx] = o;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < R) nrm_out[threadIdx.x] = nrm;
+    return;
+  }
   if (idx < (int64_t)n * R) {
     double ax = 0, ay = 0;
 #pragma unroll 4
@@ -1392,35 +1587,59 @@ __global__ void __launch_bounds__(NT) k_mupdate(const double2* __restrict__ V, i
 // chip holds four times as many waves and each lane has fewer loads in a row.
 constexpr int UPD_SPLIT_MAX = 1 << 20;   // entries (rows x RHS) up to which the split form is used
 
+template <bool NORM>
 __global__ void __launch_bounds__(NT) k_mupdate_split(const double2* __restrict__ V, int64_t vs,
                                                       const int* __restrict__ jptr, int jfix,
                                                       const double2* __restrict__ hc, double2* __restrict__ w, int n,
-                                                      int R, double sign, double* __restrict__ npart) {
+                                                      int R, double sign, double* __restrict__ npart,
+                                                      double2* __restrict__ vout, double2* __restrict__ out2,
+                                                      double* __restrict__ nrm_out) {
   __shared__ double2 red[NT / 64][64];
+  __shared__ double red2[NT / 64][64];
   const int nvec = (jptr ? *jptr : jfix) + 1;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
   const bool live = idx < (int64_t)n * R;
   const int r = lane % R;   // 64 is a multiple of R
-  double ax = 0, ay = 0;
+  double ax = 0, ay = 0, s2 = 0;
   if (live) {
 #pragma unroll 4
     for (int i = wv; i < nvec; i += NT / 64) {
       const double2 a = V[(int64_t)i * vs + idx], b = hc[i * R + r];
       ax += a.x * b.x - a.y * b.y;
       ay += a.x * b.y + a.y * b.x;
+      if (NORM) s2 += b.x * b.x + b.y * b.y;
+    }
+  } else if (NORM) {
+    for (int i = wv; i < nvec; i += NT / 64) {
+      const double2 b = hc[i * R + r];
+      s2 += b.x * b.x + b.y * b.y;
     }
   }
   red[wv][lane] = make_double2(ax, ay);
+  if (NORM) red2[wv][lane] = s2;
   __syncthreads();
   if (wv == 0) {
+    double sx = 0, sy = 0, ss = 0;
+    for (int q = 0; q < NT / 64; ++q) {
+      sx += red[q][lane].x;
+      sy += red[q][lane].y;
+      if (NORM) ss += red2[q][lane];
+    }
+    if (NORM) {
+      double nrm;
+      const double f = scale_of(hc[nvec * R + r].x - ss, &nrm);
+      if (live) {
+        const double2 c = w[idx];
+        const double2 o = make_double2((c.x + sign * sx) * f, (c.y + sign * sy) * f);
+        vout[(int64_t)nvec * vs + idx] = o;
+        if (out2) out2[idx] = o;
+      }
+      if (blockIdx.x == 0 && lane < R) nrm_out[lane] = nrm;
+      return;
+    }
     double nx = 0;
     if (live) {
-      double sx = 0, sy = 0;
-      for (int q = 0; q < NT / 64; ++q) {
-        sx += red[q][lane].x;
-        sy += red[q][lane].y;
-      }
       const double2 c = w[idx];
       const double2 o = make_double2(c.x + sign * sx, c.y + sign * sy);
       w[idx] = o;
@@ -1726,8 +1945,31 @@ void launch_strip_step(const double2* M, int K, const double2* in, int n_out, co
   HIPCHECK(hipGetLastError());
 }
 
+void launch_coarse_symv_tiles(const Handle& h, const double2* g, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_symv_tiles, dim3(h.sym_ntiles), dim3(SYM_WAVES * 64), 0, s, h.nK, h.sym_nt,
+                     h.d.sym_tij, h.d.Ksym, g, h.d.sym_part);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_coarse_symv_reduce(const Handle& h, double2* w, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_symv_reduce, dim3(h.sym_nt), dim3(NT), 0, s, h.nK, h.sym_nt, h.d.sym_part, w);
+  HIPCHECK(hipGetLastError());
+}
+
 void launch_coarse_solve(const Handle& h, const double2* g, double2* w, int R, hipStream_t s) {
+  if (R == 1 && h.d.Ksym) {
+    launch_coarse_symv_tiles(h, g, s);
+    launch_coarse_symv_reduce(h, w, s);
+    return;
+  }
   hipLaunchKernelGGL(k_coarse_gemv, dim3(nblocks(h.nK, NT / 64)), dim3(NT), 0, s, h.nK, h.d.Kinv, g, w, R);
+  HIPCHECK(hipGetLastError());
+}
+
+int sym_tile_size() { return SYM_TILE; }
+
+void launch_pack_sym_tiles(const Handle& h, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_sym_tiles, dim3(h.sym_ntiles), dim3(NT), 0, s, h.nK, h.d.Kinv, h.d.sym_tij, h.d.Ksym);
   HIPCHECK(hipGetLastError());
 }
 
@@ -1804,42 +2046,42 @@ GmresDims gmres_dims(int n, int R, int maxvec) {
 }
 
 void launch_mdot(const double2* V, int64_t vs, const int* jptr, int jfix, const double2* w, int n, int R,
-                 const GmresDims& g, int maxvec, double2* part, hipStream_t s) {
+                 const GmresDims& g, int maxvec, double2* part, int self, hipStream_t s) {
   if (g.wave)
     hipLaunchKernelGGL(k_mdot_wave, dim3(g.grid), dim3(NT), 0, s, V, vs, jptr, jfix, w, n, R, g.chunk, g.nchunks,
-                       maxvec, part);
+                       maxvec, part, self);
   else
     hipLaunchKernelGGL((k_mdot<4>), dim3(g.grid), dim3(NT), 0, s, V, vs, jptr, jfix, w, n, R, g.chunk, g.nchunks,
-                       maxvec, part);
+                       maxvec, part, self);
   HIPCHECK(hipGetLastError());
 }
 
 void launch_mdot_reduce(const double2* part, const GmresDims& g, const int* jptr, int jfix, int maxvec, int R,
-                        double2* hh, double2* hsum, int first, hipStream_t s) {
+                        double2* hh, double2* hsum, int first, int self, hipStream_t s) {
   hipLaunchKernelGGL(k_mdot_reduce, dim3(nblocks(int64_t(maxvec) * R, NT / 64)), dim3(NT), 0, s, part, g.nchunks,
-                     jptr, jfix, maxvec, R, hh, hsum, first);
+                     jptr, jfix, maxvec, R, hh, hsum, first, self);
   HIPCHECK(hipGetLastError());
 }
 
 void launch_mupdate(const double2* V, int64_t vs, const int* jptr, int jfix, const double2* hc, double2* w, int n,
                     int R, double sign, double* npart, hipStream_t s) {
   if (int64_t(n) * R <= UPD_SPLIT_MAX)
-    hipLaunchKernelGGL(k_mupdate_split, dim3(nblocks(int64_t(n) * R, 64)), dim3(NT), 0, s, V, vs, jptr, jfix, hc, w, n,
-                       R, sign, npart);
+    hipLaunchKernelGGL(k_mupdate_split<false>, dim3(nblocks(int64_t(n) * R, 64)), dim3(NT), 0, s, V, vs, jptr, jfix,
+                       hc, w, n, R, sign, npart, nullptr, nullptr, nullptr);
   else
-    hipLaunchKernelGGL(k_mupdate, dim3(nblocks(int64_t(n) * R)), dim3(NT), 0, s, V, vs, jptr, jfix, hc, w, n, R, sign,
-                       npart);
+    hipLaunchKernelGGL(k_mupdate<false>, dim3(nblocks(int64_t(n) * R)), dim3(NT), 0, s, V, vs, jptr, jfix, hc, w, n,
+                       R, sign, npart, nullptr, nullptr, nullptr);
   HIPCHECK(hipGetLastError());
 }
 
-int update_blocks(int n, int R) {
-  return int64_t(n) * R <= UPD_SPLIT_MAX ? int(nblocks(int64_t(n) * R, 64)) : int(nblocks(int64_t(n) * R));
-}
-
-void launch_normalize_parts(const double2* w, int n, int R, const double* part, int nblk, double* nrm, double2* out,
-                            const int* jptr, int64_t vs, double2* out2, int nout_blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_norm_reduce, dim3(R), dim3(NT), 0, s, part, nblk, R, nrm);
-  hipLaunchKernelGGL(k_normalize, dim3(nout_blocks), dim3(NT), 0, s, w, nrm, n, R, out, jptr, vs, out2);
+void launch_mupdate_normalize(double2* V, int64_t vs, const int* jptr, const double2* hc, const double2* w, int n,
+                              int R, double2* out2, double* nrm, hipStream_t s) {
+  if (int64_t(n) * R <= UPD_SPLIT_MAX)
+    hipLaunchKernelGGL(k_mupdate_split<true>, dim3(nblocks(int64_t(n) * R, 64)), dim3(NT), 0, s, V, vs, jptr, 0, hc,
+                       const_cast<double2*>(w), n, R, -1.0, nullptr, V, out2, nrm);
+  else
+    hipLaunchKernelGGL(k_mupdate<true>, dim3(nblocks(int64_t(n) * R)), dim3(NT), 0, s, V, vs, jptr, 0, hc,
+                       const_cast<double2*>(w), n, R, -1.0, nullptr, V, out2, nrm);
   HIPCHECK(hipGetLastError());
 }
 

@@ -111,17 +111,25 @@ struct GmresDims {
   int nchunks = 1, chunk = 1, ngroups = 1, nnorm = 1, step = 1, grid = 1;
   bool wave = false;   // wave-per-item multi-dot (few right-hand sides)
 };
+// symmetric tiled coarse apply (one right-hand side): tile edge, packing of
+// the upper tiles from the dense inverse
+int sym_tile_size();
+void launch_pack_sym_tiles(const Handle& h, hipStream_t s);
+// w = K^-1 g in two steps: per-tile partial products, then their sum per row
+void launch_coarse_symv_tiles(const Handle& h, const double2* g, hipStream_t s);
+void launch_coarse_symv_reduce(const Handle& h, double2* w, hipStream_t s);
 GmresDims gmres_dims(int n, int R, int maxvec);
+// self = 1 appends |w|^2 as entry nvec of the multi-dot (hh only, not hsum)
 void launch_mdot(const double2* V, int64_t vs, const int* jptr, int jfix, const double2* w, int n, int R,
-                 const GmresDims& g, int maxvec, double2* part, hipStream_t s);
+                 const GmresDims& g, int maxvec, double2* part, int self, hipStream_t s);
 void launch_mdot_reduce(const double2* part, const GmresDims& g, const int* jptr, int jfix, int maxvec, int R,
-                        double2* hh, double2* hsum, int first, hipStream_t s);
+                        double2* hh, double2* hsum, int first, int self, hipStream_t s);
 void launch_mupdate(const double2* V, int64_t vs, const int* jptr, int jfix, const double2* hc, double2* w, int n,
                     int R, double sign, double* npart, hipStream_t s);
-int update_blocks(int n, int R);
-// normalisation from partial squared norms already in part ([nblk][R])
-void launch_normalize_parts(const double2* w, int n, int R, const double* part, int nblk, double* nrm, double2* out,
-                            const int* jptr, int64_t vs, double2* out2, int nout_blocks, hipStream_t s);
+// V_{j+1} = out2 = (w - sum_{i<=j} V_i h_i) / nrm with nrm^2 = h_{j+1} - sum |h_i|^2
+// (hc from a multi-dot with self = 1); nrm is written per RHS column
+void launch_mupdate_normalize(double2* V, int64_t vs, const int* jptr, const double2* hc, const double2* w, int n,
+                              int R, double2* out2, double* nrm, hipStream_t s);
 void launch_normalize(const double2* w, int n, int R, const GmresDims& g, double* part, double* nrm, double2* out,
                       const int* jptr, int64_t vs, double2* out2, hipStream_t s);
 void launch_givens(int* jptr, const double2* hsum, const double* nrm, double2* H, double2* cs, double2* sn, double2* g,
