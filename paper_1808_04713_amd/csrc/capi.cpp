@@ -577,20 +577,27 @@ void build_device(Handle& h) {
   d.wK = dalloc<double2>(h, nK * Rp);
   d.full0 = dalloc<double2>(h, size_t(h.dof) * Rp);
   d.full1 = dalloc<double2>(h, size_t(h.dof) * Rp);
-  d.V_kry = dalloc<double2>(h, (size_t(h.max_iter) + 1) * nl * Rp);
+  // basis vectors q_0..q_{max_iter} and one tentative vector beyond them
+  d.V_kry = dalloc<double2>(h, (size_t(h.max_iter) + 2) * nl * Rp);
   d.w = dalloc<double2>(h, nl * Rp);
   d.t0 = dalloc<double2>(h, nl * Rp);
   d.t1 = dalloc<double2>(h, nl * Rp);
   d.t2 = dalloc<double2>(h, nl * Rp);
   d.vf = dalloc<float2>(h, nl * Rp);
-  d.hbuf = dalloc<double2>(h, (size_t(h.max_iter) + 1) * Rp);
-  d.hsum = dalloc<double2>(h, (size_t(h.max_iter) + 1) * Rp);
-  d.part = dalloc<double2>(h, size_t(512) * (h.max_iter + 1) * Rp);
+  // multi-dot partials: up to 512 row chunks x (2 max_iter + 4) entries
+  const size_t dstride = 2 * (size_t(h.max_iter) + 1) + 2;
+  d.part = dalloc<double2>(h, size_t(512) * dstride * Rp);
+  d.dots = dalloc<double2>(h, dstride * Rp);
+  d.ucoef = dalloc<double2>(h, dstride * Rp);
   // partial norms: at most one per 64 entries of a dual vector, or 512 blocks
   d.npart = dalloc<double>(h, size_t((nl * Rp + 63) / 64 + 512) * Rp);
   size_t mv = size_t(h.max_iter) + 1;
   d.vcur = dalloc<double2>(h, nl * Rp);
   d.Hdev = dalloc<double2>(h, size_t(h.max_iter) * mv * Rp);
+  d.Hraw = dalloc<double2>(h, size_t(h.max_iter) * mv * Rp);
+  d.hprev = dalloc<double2>(h, (mv + 1) * Rp);
+  d.hcol = dalloc<double2>(h, (mv + 1) * Rp);
+  d.rho = dalloc<double>(h, Rp);
   d.cs = dalloc<double2>(h, mv * Rp);
   d.sn = dalloc<double2>(h, mv * Rp);
   d.gvec = dalloc<double2>(h, (mv + 1) * Rp);
@@ -860,8 +867,11 @@ struct GmresResult {
   std::vector<double> rel;
 };
 
-// Left-preconditioned GMRES with CGS2 on R systems at once (x0 = 0); stops
-// each system when ||P^-1 r_k|| / ||P^-1 r_0|| <= tol.  x receives the iterate.
+// Left-preconditioned GMRES on R systems at once (x0 = 0); stops each system
+// when ||P^-1 r_k|| / ||P^-1 r_0|| <= tol.  x receives the iterate.  The
+// Arnoldi basis is orthogonalised twice (classical Gram-Schmidt with one
+// reorthogonalisation), the second pass delayed into the next iteration so that
+// each iteration makes one pass over the basis for dots and one for updates.
 // The Arnoldi step, the Hessenberg column and the Givens rotations stay on the
 // device; the host reads a two-word status one iteration behind the GPU.
 GmresResult gmres(Handle& h, const double2* rhs, double2* x, int R, int prec, double tol, int max_iter) {
@@ -888,29 +898,25 @@ GmresResult gmres(Handle& h, const double2* rhs, double2* x, int R, int prec, do
   HIPCHECK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
   int launched = 0;
   try {
+    const int dstride = 2 * maxvec + 2;
+    // one Arnoldi step with delayed reorthogonalisation; nv - 1 = j basis
+    // vectors are final when it starts
     auto issue = [&](int nv) {
+      const double jv = nv - 1;
       apply_PF(h, d.vcur, d.w, R, prec);
-      for (int pass = 0; pass < 2; ++pass) {
-        {
-          // the second pass also forms |w|^2
-          Timed t(h, KF_DOTS, (nv + 1) * vb, 8.0 * (nv + pass) * double(vs));
-          launch_mdot(d.V_kry, vs, d.jdev, 0, d.w, n, R, gd, maxvec, d.part, pass, s);
-          launch_mdot_reduce(d.part, gd, d.jdev, 0, maxvec, R, d.hbuf, d.hsum, pass == 0, pass, s);
-        }
-        if (pass == 0) {
-          Timed t(h, KF_UPDATE, (nv + 2) * vb, 8.0 * nv * double(vs));
-          launch_mupdate(d.V_kry, vs, d.jdev, 0, d.hbuf, d.w, n, R, -1.0, nullptr, s);
-        } else {
-          // second update fused with the normalisation: V_{j+1} and the next
-          // operator input are written directly
-          Timed t(h, KF_UPDATE, (nv + 3) * vb, (8.0 * nv + 2.0) * double(vs));
-          launch_mupdate_normalize(d.V_kry, vs, d.jdev, d.hbuf, d.w, n, R, d.vcur, d.nrm, s);
-        }
+      {
+        Timed t(h, KF_DOTS, (jv + 2) * vb, (16.0 * jv + 24.0) * double(vs));
+        launch_dmdot(d.V_kry, vs, d.jdev, d.w, n, R, gd, dstride, d.part, s);
+        launch_dmdot_reduce(d.part, gd, d.jdev, dstride, R, d.dots, s);
       }
       {
         Timed t(h, KF_GIVENS, 0, 0);
-        launch_givens(d.jdev, d.hsum, d.nrm, d.Hdev, d.cs, d.sn, d.gvec, d.beta, d.done, d.iters, d.resid, tol,
-                      maxvec, R, d.counter, d.status, d.hist, s);
+        launch_dcgs_scalar(d.jdev, d.dots, d.Hraw, d.hprev, d.rho, d.hcol, d.ucoef, d.Hdev, d.cs, d.sn, d.gvec,
+                           d.beta, d.done, d.iters, d.resid, tol, maxvec, R, d.counter, d.status, d.hist, s);
+      }
+      {
+        Timed t(h, KF_UPDATE, (jv + 5) * vb, (16.0 * jv + 20.0) * double(vs));
+        launch_dupdate(d.V_kry, vs, d.jdev, d.ucoef, d.w, n, R, d.vcur, d.Hraw, d.hprev, maxvec, s);
       }
     };
     // one GMRES iteration as a captured graph (every launch reads j on the device)
@@ -934,7 +940,8 @@ GmresResult gmres(Handle& h, const double2* rhs, double2* x, int R, int prec, do
       exec = itg->second;
     }
     using clk = std::chrono::steady_clock;
-    for (int it = 0; it < max_iter; ++it) {
+    // column j - 1 of H is completed in iteration j: max_iter + 1 iterations
+    for (int it = 0; it <= max_iter; ++it) {
       auto t0 = clk::now();
       if (graph) HIPCHECK(hipGraphLaunch(exec, s));
       else issue(it + 1);

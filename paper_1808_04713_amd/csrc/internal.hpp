@@ -226,7 +226,12 @@ struct Handle {
     double2 *full0 = nullptr, *full1 = nullptr;   // [dof][R]
     double2 *V_kry = nullptr;                      // (max_iter+1) x nlam x R
     double2 *w = nullptr, *t0 = nullptr, *t1 = nullptr, *t2 = nullptr;
-    double2 *hbuf = nullptr, *hsum = nullptr, *part = nullptr;
+    double2* part = nullptr;
+    // Arnoldi with delayed reorthogonalisation: reduced dots, unrotated
+    // Hessenberg columns, first-pass coefficients, column scratch, update
+    // coefficients, scale of the tentative vector
+    double2 *dots = nullptr, *Hraw = nullptr, *hprev = nullptr, *hcol = nullptr, *ucoef = nullptr;
+    double* rho = nullptr;
     double *nrm = nullptr, *npart = nullptr;
     float2* vf = nullptr;
     double2 *vcur = nullptr, *Hdev = nullptr, *cs = nullptr, *sn = nullptr, *gvec = nullptr;

@@ -17,7 +17,6 @@ constexpr int NT = 256;      // threads per block
 constexpr int RC = 8;        // RHS columns per block in the slot kernels
 constexpr int MMAX = 160;    // max dual slots per element (4 sides x 40 modes)
 constexpr int NRMAX = 160;   // max coarse modes per element
-constexpr int GVEC = 4;      // Arnoldi vectors per block in the multi-dot
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -1387,182 +1386,16 @@ __global__ void k_dense_scatter(const int64_t* __restrict__ idx, const double2* 
 // launch has a fixed shape; R (RHS count) divides 64 and thread t owns RHS
 // column t % R.  nvec = j + 1 Arnoldi vectors take part in an iteration.
 
-// part[c][i][r] = sum over the rows of chunk c of conj(V_i) w.  The work items
-// (chunk c, group of GV vectors) are spread over a fixed grid, so that the launch
-// shape does not depend on the number of Arnoldi vectors held on the device.
-// With self = 1 one more entry, i = nvec, holds the squared norm of w itself.
-template <int GV>
-__global__ void __launch_bounds__(NT) k_mdot(const double2* __restrict__ V, int64_t vs, const int* __restrict__ jptr,
-                                             int jfix, const double2* __restrict__ w, int n, int R, int chunk,
-                                             int nchunks, int maxvec, double2* __restrict__ part, int self) {
-  __shared__ double2 red[NT];
-  const int nv0 = (jptr ? *jptr : jfix) + 1;
-  const int nvec = nv0 + self;
-  const int nitems = nchunks * ((nvec + GV - 1) / GV);
-  const int r = threadIdx.x % R, rl = threadIdx.x / R, step = NT / R;
-  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
-    const int c = item % nchunks, i0 = (item / nchunks) * GV;
-    const int64_t lo = (int64_t)c * chunk, hi = min((int64_t)n, lo + chunk);
-    double ax[GV], ay[GV];
-#pragma unroll
-    for (int t = 0; t < GV; ++t) ax[t] = ay[t] = 0;
-    for (int64_t row = lo + rl; row < hi; row += step) {
-      const int64_t o = row * R + r;
-      const double2 b = w[o];
-#pragma unroll
-      for (int t = 0; t < GV; ++t) {
-        if (i0 + t < nvec) {
-          const double2* src = i0 + t < nv0 ? V + (int64_t)(i0 + t) * vs : w;
-          const double2 a = src[o];
-          ax[t] += a.x * b.x + a.y * b.y;
-          ay[t] += a.x * b.y - a.y * b.x;
-        }
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < GV; ++t) {
-      const double2 sm = block_sum_by_rhs(make_double2(ax[t], ay[t]), R, red);
-      if (threadIdx.x < R && i0 + t < nvec)
-        part[((int64_t)c * maxvec + i0 + t) * R + threadIdx.x] = sm;
-    }
-  }
-}
-
-// The multi-dot for a few right-hand sides (R = 1, 2, 4): every wave works on
-// its own items (row chunk c, group of GVW vectors) and reduces with shuffles
-// only, so no workgroup barrier sits between the loads and the partial sums.
-// Lane l reads entries lo R + l + 64 t of the chunk; since 64 is a multiple of
-// R, its column is l % R throughout.  One vector per item and 256-entry chunks
-// (the 32x32 point source: 109 chunks x j items over 16,384 waves) measured
-// fastest among 1..8 vectors, 64..1024 entries and 4,096..32,768 waves.
-constexpr int GVW = 1;
-
-__global__ void __launch_bounds__(NT) k_mdot_wave(const double2* __restrict__ V, int64_t vs,
-                                                  const int* __restrict__ jptr, int jfix,
-                                                  const double2* __restrict__ w, int n, int R, int chunk,
-                                                  int nchunks, int maxvec, double2* __restrict__ part, int self) {
-  const int nv0 = (jptr ? *jptr : jfix) + 1;
-  const int nvec = nv0 + self;
-  const int nitems = nchunks * ((nvec + GVW - 1) / GVW);
-  const int lane = threadIdx.x & 63;
-  const int wave = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
-  const int nwaves = gridDim.x * (NT / 64);
-  for (int item = wave; item < nitems; item += nwaves) {
-    const int c = item % nchunks, i0 = (item / nchunks) * GVW;
-    const int64_t lo = (int64_t)c * chunk * R, hi = min((int64_t)n, (int64_t)(c + 1) * chunk) * R;
-    const double2* src[GVW];
-#pragma unroll
-    for (int t = 0; t < GVW; ++t) src[t] = i0 + t < nv0 ? V + (int64_t)(i0 + t) * vs : w;
-    double ax[GVW], ay[GVW];
-#pragma unroll
-    for (int t = 0; t < GVW; ++t) ax[t] = ay[t] = 0;
-#pragma unroll 4
-    for (int64_t e = lo + lane; e < hi; e += 64) {
-      const double2 b = w[e];
-#pragma unroll
-      for (int t = 0; t < GVW; ++t) {
-        if (i0 + t < nvec) {
-          const double2 a = src[t][e];
-          ax[t] += a.x * b.x + a.y * b.y;
-          ay[t] += a.x * b.y - a.y * b.x;
-        }
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < GVW; ++t) {
-      for (int off = 32; off >= R; off >>= 1) {
-        ax[t] += __shfl_xor(ax[t], off, 64);
-        ay[t] += __shfl_xor(ay[t], off, 64);
-      }
-      if (lane < R && i0 + t < nvec)
-        part[((int64_t)c * maxvec + i0 + t) * R + lane] = make_double2(ax[t], ay[t]);
-    }
-  }
-}
-
-// h[i][r] = sum_c part[c][i][r]; hsum = h (first pass) or hsum += h.
-// One wavefront per (i, r): lanes stride over the chunks, then a shuffle tree.
-// With self = 1 the entry i = nvec (the squared norm of w) goes to hh only.
-__global__ void __launch_bounds__(NT) k_mdot_reduce(const double2* __restrict__ part, int nchunks,
-                                                    const int* __restrict__ jptr, int jfix, int maxvec, int R,
-                                                    double2* __restrict__ hh, double2* __restrict__ hsum,
-                                                    int first, int self) {
-  const int nvec = (jptr ? *jptr : jfix) + 1;
-  const int lane = threadIdx.x & 63;
-  const int idx = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);   // i * R + r
-  if (idx >= (nvec + self) * R) return;
-  double ax = 0, ay = 0;
-  for (int c = lane; c < nchunks; c += 64) {
-    double2 a = part[(int64_t)c * maxvec * R + idx];
-    ax += a.x;
-    ay += a.y;
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    ax += __shfl_xor(ax, off, 64);
-    ay += __shfl_xor(ay, off, 64);
-  }
-  if (lane == 0) {
-    hh[idx] = make_double2(ax, ay);
-    if (hsum && idx < nvec * R) {
-      if (first) hsum[idx] = make_double2(ax, ay);
-      else {
-        hsum[idx].x += ax;
-        hsum[idx].y += ay;
-      }
-    }
-  }
-}
-
 // w[row][r] += sign * sum_{i < nvec} V_i[row][r] h[i][r]; when npart is given the
 // block also writes the partial squared norms of the updated w (per RHS column).
-//
-// NORM: the last Gram-Schmidt pass fused with the normalisation.  h[nvec] holds
-// |w|^2 (from the same multi-dot as the h_i), so the updated vector has
-// |w - V h|^2 = |w|^2 - sum_i |h_i|^2 for orthonormal V_i; every block forms
-// that norm from the same h in the same order, writes the scaled vector to
-// V_{j+1} (vout + (j + 1) vs) and out2, and block 0 publishes the norm.  w itself
-// is left as it was.
-__device__ __forceinline__ double scale_of(double nn, double* nrm) {
-  const double nv = nn > 0 ? sqrt(nn) : 0.0;
-  *nrm = nv;
-  return nv > 0 ? 1.0 / nv : 0.0;
-}
-
-template <bool NORM>
 __global__ void __launch_bounds__(NT) k_mupdate(const double2* __restrict__ V, int64_t vs, const int* __restrict__ jptr,
                                                 int jfix, const double2* __restrict__ hc, double2* __restrict__ w,
-                                                int n, int R, double sign, double* __restrict__ npart,
-                                                double2* __restrict__ vout, double2* __restrict__ out2,
-                                                double* __restrict__ nrm_out) {
+                                                int n, int R, double sign, double* __restrict__ npart) {
   __shared__ double2 red[NT];
   const int nvec = (jptr ? *jptr : jfix) + 1;
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int r = threadIdx.x % R;   // NT is a multiple of R, so idx % R == threadIdx.x % R
   double nx = 0;
-  if (NORM) {
-    double s2 = 0;
-    for (int i = 0; i < nvec; ++i) {
-      const double2 b = hc[i * R + r];
-      s2 += b.x * b.x + b.y * b.y;
-    }
-    double nrm;
-    const double f = scale_of(hc[nvec * R + r].x - s2, &nrm);
-    if (idx < (int64_t)n * R) {
-      double ax = 0, ay = 0;
-#pragma unroll 4
-      for (int i = 0; i < nvec; ++i) {
-        double2 a = V[(int64_t)i * vs + idx], b = hc[i * R + r];
-        ax += a.x * b.x - a.y * b.y;
-        ay += a.x * b.y + a.y * b.x;
-      }
-      const double2 c = w[idx];
-      const double2 o = make_double2((c.x + sign * ax) * f, (c.y + sign * ay) * f);
-      vout[(int64_t)nvec * vs + idx] = o;
-      if (out2) out2[idx] = o;
-    }
-    if (blockIdx.x == 0 && threadIdx.x < R) nrm_out[threadIdx.x] = nrm;
-    return;
-  }
   if (idx < (int64_t)n * R) {
     double ax = 0, ay = 0;
 #pragma unroll 4
@@ -1587,59 +1420,35 @@ __global__ void __launch_bounds__(NT) k_mupdate(const double2* __restrict__ V, i
 // chip holds four times as many waves and each lane has fewer loads in a row.
 constexpr int UPD_SPLIT_MAX = 1 << 20;   // entries (rows x RHS) up to which the split form is used
 
-template <bool NORM>
 __global__ void __launch_bounds__(NT) k_mupdate_split(const double2* __restrict__ V, int64_t vs,
                                                       const int* __restrict__ jptr, int jfix,
                                                       const double2* __restrict__ hc, double2* __restrict__ w, int n,
-                                                      int R, double sign, double* __restrict__ npart,
-                                                      double2* __restrict__ vout, double2* __restrict__ out2,
-                                                      double* __restrict__ nrm_out) {
+                                                      int R, double sign, double* __restrict__ npart) {
   __shared__ double2 red[NT / 64][64];
-  __shared__ double red2[NT / 64][64];
   const int nvec = (jptr ? *jptr : jfix) + 1;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
   const bool live = idx < (int64_t)n * R;
   const int r = lane % R;   // 64 is a multiple of R
-  double ax = 0, ay = 0, s2 = 0;
+  double ax = 0, ay = 0;
   if (live) {
 #pragma unroll 4
     for (int i = wv; i < nvec; i += NT / 64) {
       const double2 a = V[(int64_t)i * vs + idx], b = hc[i * R + r];
       ax += a.x * b.x - a.y * b.y;
       ay += a.x * b.y + a.y * b.x;
-      if (NORM) s2 += b.x * b.x + b.y * b.y;
-    }
-  } else if (NORM) {
-    for (int i = wv; i < nvec; i += NT / 64) {
-      const double2 b = hc[i * R + r];
-      s2 += b.x * b.x + b.y * b.y;
     }
   }
   red[wv][lane] = make_double2(ax, ay);
-  if (NORM) red2[wv][lane] = s2;
   __syncthreads();
   if (wv == 0) {
-    double sx = 0, sy = 0, ss = 0;
-    for (int q = 0; q < NT / 64; ++q) {
-      sx += red[q][lane].x;
-      sy += red[q][lane].y;
-      if (NORM) ss += red2[q][lane];
-    }
-    if (NORM) {
-      double nrm;
-      const double f = scale_of(hc[nvec * R + r].x - ss, &nrm);
-      if (live) {
-        const double2 c = w[idx];
-        const double2 o = make_double2((c.x + sign * sx) * f, (c.y + sign * sy) * f);
-        vout[(int64_t)nvec * vs + idx] = o;
-        if (out2) out2[idx] = o;
-      }
-      if (blockIdx.x == 0 && lane < R) nrm_out[lane] = nrm;
-      return;
-    }
     double nx = 0;
     if (live) {
+      double sx = 0, sy = 0;
+      for (int q = 0; q < NT / 64; ++q) {
+        sx += red[q][lane].x;
+        sy += red[q][lane].y;
+      }
       const double2 c = w[idx];
       const double2 o = make_double2(c.x + sign * sx, c.y + sign * sy);
       w[idx] = o;
@@ -1718,88 +1527,89 @@ __device__ __forceinline__ double2 shfl_up2(double2 v, int d) {
   return make_double2(__shfl_up(v.x, d, 64), __shfl_up(v.y, d, 64));
 }
 
-__global__ void __launch_bounds__(NT) k_givens(int* __restrict__ jptr, const double2* __restrict__ hsum,
-                                               const double* __restrict__ nrm, double2* __restrict__ H,
-                                               double2* __restrict__ cs, double2* __restrict__ sn,
-                                               double2* __restrict__ g, const double* __restrict__ beta,
-                                               int* __restrict__ done, int* __restrict__ iters,
-                                               double* __restrict__ resid, double tol, int maxvec, int R,
-                                               int* __restrict__ counter, int* __restrict__ status,
-                                               double* __restrict__ hist) {
-  __shared__ double2 xj_sh;
-  const int r = blockIdx.x;
-  const int j = *jptr;
-  if (!done[r]) {
-    if (threadIdx.x < 64) {
-      const int lane = threadIdx.x;
-      const int seg = (j + 63) / 64;
-      const int s0 = min(j, lane * seg), s1 = min(j, s0 + seg);
-      // this lane's segment as one map x -> A x + B
-      double2 A = make_double2(1, 0), B = make_double2(0, 0);
-      for (int i = s0; i < s1; ++i) {
-        const double2 c = cs[i * R + r], s = sn[i * R + r], hb = hsum[(i + 1) * R + r];
-        const double2 al = make_double2(-s.x, s.y);   // -conj(s)
-        B = cfma(c, hb, cmul(al, B));
-        A = cmul(al, A);
-      }
-      // inclusive scan over the lanes, earlier segments applied first
-      for (int d = 1; d < 64; d <<= 1) {
-        const double2 Ap = shfl_up2(A, d), Bp = shfl_up2(B, d);
-        if (lane >= d) {
-          B = cfma(A, Bp, B);
-          A = cmul(A, Ap);
-        }
-      }
-      double2 Ae = shfl_up2(A, 1), Be = shfl_up2(B, 1);
-      if (lane == 0) {
-        Ae = make_double2(1, 0);
-        Be = make_double2(0, 0);
-      }
-      const double2 x0 = hsum[r];
-      double2 x = cfma(Ae, x0, Be);   // carried value entering this lane's segment
-      for (int i = s0; i < s1; ++i) {
-        const double2 c = cs[i * R + r], s = sn[i * R + r], hb = hsum[(i + 1) * R + r];
-        H[((int64_t)j * maxvec + i) * R + r] = cfma(c, x, cmul(s, hb));
-        x = cfma(c, hb, cmul(make_double2(-s.x, s.y), x));
-      }
-      if (j == 0 && lane == 0) xj_sh = x0;
-      if (j > 0 && s0 < s1 && s1 == j) xj_sh = x;
+// Column j of the Hessenberg matrix for system r: entries 0..j in hcol (stride
+// R) and the subdiagonal entry sub (real, >= 0).  Called by every thread of the
+// block; xj_sh is block-shared scratch.
+__device__ void givens_column(int j, int r, const double2* __restrict__ hcol, double sub, double2* __restrict__ H,
+                              double2* __restrict__ cs, double2* __restrict__ sn, double2* __restrict__ g,
+                              const double* __restrict__ beta, int* __restrict__ done, int* __restrict__ iters,
+                              double* __restrict__ resid, double tol, int maxvec, int R, double* __restrict__ hist,
+                              double2* xj_sh) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const int seg = (j + 63) / 64;
+    const int s0 = min(j, lane * seg), s1 = min(j, s0 + seg);
+    // this lane's segment as one map x -> A x + B
+    double2 A = make_double2(1, 0), B = make_double2(0, 0);
+    for (int i = s0; i < s1; ++i) {
+      const double2 c = cs[i * R + r], s = sn[i * R + r], hb = hcol[(i + 1) * R + r];
+      const double2 al = make_double2(-s.x, s.y);   // -conj(s)
+      B = cfma(c, hb, cmul(al, B));
+      A = cmul(al, A);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const double2 a = xj_sh, b = make_double2(nrm[r], 0.0);
-      double aa = sqrt(a.x * a.x + a.y * a.y), bb = sqrt(b.x * b.x + b.y * b.y);
-      double den = sqrt(aa * aa + bb * bb);
-      double2 c, s;
-      if (den == 0) { c = make_double2(1, 0); s = make_double2(0, 0); }
-      else if (aa == 0) { c = make_double2(0, 0); s = make_double2(b.x / den, -b.y / den); }
-      else {
-        c = make_double2(aa / den, 0);
-        double2 ph = make_double2(a.x / aa, a.y / aa);          // a / |a|
-        s = make_double2((ph.x * b.x + ph.y * b.y) / den, (ph.y * b.x - ph.x * b.y) / den);  // ph conj(b) / den
+    // inclusive scan over the lanes, earlier segments applied first
+    for (int d = 1; d < 64; d <<= 1) {
+      const double2 Ap = shfl_up2(A, d), Bp = shfl_up2(B, d);
+      if (lane >= d) {
+        B = cfma(A, Bp, B);
+        A = cmul(A, Ap);
       }
-      cs[j * R + r] = c;
-      sn[j * R + r] = s;
-      H[((int64_t)j * maxvec + j) * R + r] =
-          make_double2(c.x * a.x + s.x * b.x - s.y * b.y, c.x * a.y + s.x * b.y + s.y * b.x);
-      double2 gj = g[j * R + r];
-      g[(j + 1) * R + r] = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
-      g[j * R + r] = make_double2(c.x * gj.x, c.x * gj.y);
-      double2 gn = g[(j + 1) * R + r];
-      double res = sqrt(gn.x * gn.x + gn.y * gn.y) / beta[r];
-      resid[r] = res;
-      if (hist) hist[(int64_t)(j + 1) * R + r] = res;
-      iters[r] = j + 1;
-      if (res <= tol || nrm[r] == 0.0) done[r] = 1;
     }
+    double2 Ae = shfl_up2(A, 1), Be = shfl_up2(B, 1);
+    if (lane == 0) {
+      Ae = make_double2(1, 0);
+      Be = make_double2(0, 0);
+    }
+    const double2 x0 = hcol[r];
+    double2 x = cfma(Ae, x0, Be);   // carried value entering this lane's segment
+    for (int i = s0; i < s1; ++i) {
+      const double2 c = cs[i * R + r], s = sn[i * R + r], hb = hcol[(i + 1) * R + r];
+      H[((int64_t)j * maxvec + i) * R + r] = cfma(c, x, cmul(s, hb));
+      x = cfma(c, hb, cmul(make_double2(-s.x, s.y), x));
+    }
+    if (j == 0 && lane == 0) *xj_sh = x0;
+    if (j > 0 && s0 < s1 && s1 == j) *xj_sh = x;
   }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double2 a = *xj_sh, b = make_double2(sub, 0.0);
+    double aa = sqrt(a.x * a.x + a.y * a.y), bb = sqrt(b.x * b.x + b.y * b.y);
+    double den = sqrt(aa * aa + bb * bb);
+    double2 c, s;
+    if (den == 0) { c = make_double2(1, 0); s = make_double2(0, 0); }
+    else if (aa == 0) { c = make_double2(0, 0); s = make_double2(b.x / den, -b.y / den); }
+    else {
+      c = make_double2(aa / den, 0);
+      double2 ph = make_double2(a.x / aa, a.y / aa);          // a / |a|
+      s = make_double2((ph.x * b.x + ph.y * b.y) / den, (ph.y * b.x - ph.x * b.y) / den);  // ph conj(b) / den
+    }
+    cs[j * R + r] = c;
+    sn[j * R + r] = s;
+    H[((int64_t)j * maxvec + j) * R + r] =
+        make_double2(c.x * a.x + s.x * b.x - s.y * b.y, c.x * a.y + s.x * b.y + s.y * b.x);
+    double2 gj = g[j * R + r];
+    g[(j + 1) * R + r] = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
+    g[j * R + r] = make_double2(c.x * gj.x, c.x * gj.y);
+    double2 gn = g[(j + 1) * R + r];
+    double res = sqrt(gn.x * gn.x + gn.y * gn.y) / beta[r];
+    resid[r] = res;
+    if (hist) hist[(int64_t)(j + 1) * R + r] = res;
+    iters[r] = j + 1;
+    if (res <= tol || sub == 0.0) done[r] = 1;
+  }
+}
+
+// End of an iteration's scalar step: the last block to finish publishes
+// status = {all converged, jnext} and sets j = jnext.
+__device__ void publish_step(int jnext, int* __restrict__ jptr, const int* __restrict__ done, int R,
+                             int* __restrict__ counter, int* __restrict__ status) {
   __syncthreads();
   if (threadIdx.x == 0 && gridDim.x == 1) {
     // a single system: no other block to wait for (device-wide fences are costly
     // across the chip's separate L2 caches)
     status[0] = done[0];
-    status[1] = j + 1;
-    *jptr = j + 1;
+    status[1] = jnext;
+    *jptr = jnext;
   } else if (threadIdx.x == 0) {
     __threadfence();
     int prev = atomicAdd(counter, 1);
@@ -1808,11 +1618,366 @@ __global__ void __launch_bounds__(NT) k_givens(int* __restrict__ jptr, const dou
       int all = 1;
       for (int q = 0; q < R; ++q) all &= __hip_atomic_load(done + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       status[0] = all;
-      status[1] = j + 1;
-      *jptr = j + 1;
+      status[1] = jnext;
+      *jptr = jnext;
       *counter = 0;
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Arnoldi with delayed reorthogonalisation (one multi-dot and one update per
+// iteration).  At iteration j the basis q_0..q_{j-1} is final and V_j holds a
+// tentative vector u (projected once, scaled); z = P^-1 F u has just been
+// formed.  One pass over the basis gives s = Q^H u, t = Q^H z, u^H z, |u|^2 and
+// |z|^2, from which
+//   q_j   = (u - Q s) / nu,                 nu^2 = |u|^2 - |s|^2,
+//   column j-1 of H: h' + rho s on rows 0..j-1 and rho nu on row j, where h'
+//          and rho are the first-pass coefficients and scale of u,
+//   A q_j = (z - Q_{j+1} H s) / nu, so the first-pass coefficients of column j
+//          are ([t; tau] - H s) / nu with tau = q_j^H z = (u^H z - s^H t) / nu,
+//   u_next = (z - Q t - q_j tau) / sigma,   sigma^2 = |z|^2 - |t|^2 - |tau|^2,
+//          and its scale rho_next = sigma / nu.
+// The norms come from the dot products (exact for orthonormal Q); the scale of
+// u only has to be the one used, since nu and the column entries are formed
+// from the dots of the stored u itself.  Dot entries per chunk: s at 0..j-1, t
+// at j..2j-1, then u^H z, |u|^2, |z|^2.
+
+__device__ __forceinline__ void cdot_acc(double2 a, double2 b, double& x, double& y) {  // += conj(a) b
+  x += a.x * b.x + a.y * b.y;
+  y += a.x * b.y - a.y * b.x;
+}
+
+// few right-hand sides: one wave per (row chunk, basis vector or the extra item)
+__global__ void __launch_bounds__(NT) k_dmdot_wave(const double2* __restrict__ V, int64_t vs,
+                                                   const int* __restrict__ jptr, const double2* __restrict__ z, int n,
+                                                   int R, int chunk, int nchunks, int dstride,
+                                                   double2* __restrict__ part) {
+  const int j = *jptr;
+  const int nitems = nchunks * (j + 1);
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  const int nwaves = gridDim.x * (NT / 64);
+  const double2* u = V + (int64_t)j * vs;
+  for (int item = wave; item < nitems; item += nwaves) {
+    const int c = item % nchunks, i = item / nchunks;
+    const int64_t lo = (int64_t)c * chunk * R, hi = min((int64_t)n, (int64_t)(c + 1) * chunk) * R;
+    double x0 = 0, y0 = 0, x1 = 0, y1 = 0, x2 = 0, y2 = 0;
+    if (i < j) {
+      const double2* q = V + (int64_t)i * vs;
+#pragma unroll 4
+      for (int64_t e = lo + lane; e < hi; e += 64) {
+        const double2 a = q[e];
+        cdot_acc(a, u[e], x0, y0);
+        cdot_acc(a, z[e], x1, y1);
+      }
+    } else {
+#pragma unroll 4
+      for (int64_t e = lo + lane; e < hi; e += 64) {
+        const double2 a = u[e], b = z[e];
+        cdot_acc(a, b, x0, y0);
+        x1 += a.x * a.x + a.y * a.y;
+        x2 += b.x * b.x + b.y * b.y;
+      }
+    }
+    for (int off = 32; off >= R; off >>= 1) {
+      x0 += __shfl_xor(x0, off, 64);
+      y0 += __shfl_xor(y0, off, 64);
+      x1 += __shfl_xor(x1, off, 64);
+      y1 += __shfl_xor(y1, off, 64);
+      x2 += __shfl_xor(x2, off, 64);
+    }
+    if (lane < R) {
+      double2* pc = part + (int64_t)c * dstride * R + lane;
+      if (i < j) {
+        pc[(int64_t)i * R] = make_double2(x0, y0);
+        pc[(int64_t)(j + i) * R] = make_double2(x1, y1);
+      } else {
+        pc[(int64_t)(2 * j) * R] = make_double2(x0, y0);
+        pc[(int64_t)(2 * j + 1) * R] = make_double2(x1, 0);
+        pc[(int64_t)(2 * j + 2) * R] = make_double2(x2, 0);
+      }
+    }
+  }
+}
+
+// many right-hand sides: one block per (row chunk, group of DGV basis vectors
+// or the extra item), threads own RHS column t % R; grouping the vectors reads
+// the long u and z once per group instead of once per vector
+constexpr int DGV = 4;
+
+__global__ void __launch_bounds__(NT) k_dmdot_blk(const double2* __restrict__ V, int64_t vs,
+                                                  const int* __restrict__ jptr, const double2* __restrict__ z, int n,
+                                                  int R, int chunk, int nchunks, int dstride,
+                                                  double2* __restrict__ part) {
+  __shared__ double2 red[NT];
+  const int j = *jptr;
+  const int ng = (j + DGV - 1) / DGV;   // vector groups; group ng is the extra item
+  const int nitems = nchunks * (ng + 1);
+  const int r = threadIdx.x % R, rl = threadIdx.x / R, step = NT / R;
+  const double2* u = V + (int64_t)j * vs;
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int c = item % nchunks, gi = item / nchunks;
+    const int64_t lo = (int64_t)c * chunk, hi = min((int64_t)n, lo + chunk);
+    double2* pc = part + (int64_t)c * dstride * R + r;
+    if (gi < ng) {
+      const int i0 = gi * DGV;
+      double sx[DGV], sy[DGV], tx[DGV], ty[DGV];
+#pragma unroll
+      for (int t = 0; t < DGV; ++t) sx[t] = sy[t] = tx[t] = ty[t] = 0;
+      for (int64_t row = lo + rl; row < hi; row += step) {
+        const int64_t o = row * R + r;
+        const double2 uo = u[o], zo = z[o];
+#pragma unroll
+        for (int t = 0; t < DGV; ++t) {
+          if (i0 + t < j) {
+            const double2 a = V[(int64_t)(i0 + t) * vs + o];
+            cdot_acc(a, uo, sx[t], sy[t]);
+            cdot_acc(a, zo, tx[t], ty[t]);
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < DGV; ++t) {
+        if (i0 + t >= j) break;   // uniform over the block
+        const double2 s0 = block_sum_by_rhs(make_double2(sx[t], sy[t]), R, red);
+        const double2 s1 = block_sum_by_rhs(make_double2(tx[t], ty[t]), R, red);
+        if (threadIdx.x < R) {
+          pc[(int64_t)(i0 + t) * R] = s0;
+          pc[(int64_t)(j + i0 + t) * R] = s1;
+        }
+      }
+    } else {
+      double x0 = 0, y0 = 0, x1 = 0, x2 = 0;
+      for (int64_t row = lo + rl; row < hi; row += step) {
+        const int64_t o = row * R + r;
+        const double2 a = u[o], b = z[o];
+        cdot_acc(a, b, x0, y0);
+        x1 += a.x * a.x + a.y * a.y;
+        x2 += b.x * b.x + b.y * b.y;
+      }
+      const double2 s0 = block_sum_by_rhs(make_double2(x0, y0), R, red);
+      const double2 s1 = block_sum_by_rhs(make_double2(x1, x2), R, red);
+      if (threadIdx.x < R) {
+        pc[(int64_t)(2 * j) * R] = s0;
+        pc[(int64_t)(2 * j + 1) * R] = make_double2(s1.x, 0);
+        pc[(int64_t)(2 * j + 2) * R] = make_double2(s1.y, 0);
+      }
+    }
+  }
+}
+
+// D[k][r] = sum_c part[c][k][r] for k < 2j + 3: one wave per (k, r)
+__global__ void __launch_bounds__(NT) k_dmdot_reduce(const double2* __restrict__ part, int nchunks,
+                                                     const int* __restrict__ jptr, int dstride, int R,
+                                                     double2* __restrict__ D) {
+  const int j = *jptr;
+  const int lane = threadIdx.x & 63;
+  const int idx = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);   // k * R + r
+  if (idx >= (2 * j + 3) * R) return;
+  double ax = 0, ay = 0;
+  for (int c = lane; c < nchunks; c += 64) {
+    const double2 a = part[(int64_t)c * dstride * R + idx];
+    ax += a.x;
+    ay += a.y;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    ax += __shfl_xor(ax, off, 64);
+    ay += __shfl_xor(ay, off, 64);
+  }
+  if (lane == 0) D[idx] = make_double2(ax, ay);
+}
+
+// block-wide sum of (x, y) over all threads; valid in every thread
+__device__ __forceinline__ double2 block_sum_all(double x, double y, double2* red) {
+  for (int off = 32; off > 0; off >>= 1) {
+    x += __shfl_xor(x, off, 64);
+    y += __shfl_xor(y, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wv] = make_double2(x, y);
+  __syncthreads();
+  double2 t = make_double2(0, 0);
+  for (int q = 0; q < NT / 64; ++q) {
+    t.x += red[q].x;
+    t.y += red[q].y;
+  }
+  return t;
+}
+
+// The scalar step of an iteration, one block per system r: finishes column j-1
+// of H (stored unrotated in Hraw, then rotated by givens_column), forms the
+// update coefficients uc = [s (j), t (j), tau, 1/nu, 1/sigma] and advances j.
+// The first-pass coefficients of column j, which need H s, are formed by the
+// update kernel that follows (they are first used in the next scalar step).
+__global__ void __launch_bounds__(NT) k_dcgs_scalar(int* __restrict__ jptr, const double2* __restrict__ D,
+                                                    double2* __restrict__ Hraw, double2* __restrict__ hprev,
+                                                    double* __restrict__ rho, double2* __restrict__ hcol,
+                                                    double2* __restrict__ uc, double2* __restrict__ H,
+                                                    double2* __restrict__ cs, double2* __restrict__ sn,
+                                                    double2* __restrict__ g, const double* __restrict__ beta,
+                                                    int* __restrict__ done, int* __restrict__ iters,
+                                                    double* __restrict__ resid, double tol, int maxvec, int R,
+                                                    int* __restrict__ counter, int* __restrict__ status,
+                                                    double* __restrict__ hist) {
+  __shared__ double2 red[NT / 64];
+  __shared__ double2 xj_sh;
+  const int r = blockIdx.x;
+  const int j = *jptr;
+  auto Dv = [&](int k) { return D[(int64_t)k * R + r]; };
+  double ss = 0, tt = 0, stx = 0, sty = 0;
+  for (int i = threadIdx.x; i < j; i += NT) {
+    const double2 a = Dv(i), b = Dv(j + i);
+    ss += a.x * a.x + a.y * a.y;
+    tt += b.x * b.x + b.y * b.y;
+    cdot_acc(a, b, stx, sty);   // s^H t
+  }
+  const double2 sum_ss_tt = block_sum_all(ss, tt, red);
+  const double2 st = block_sum_all(stx, sty, red);
+  const double2 uz = Dv(2 * j);
+  const double uu = Dv(2 * j + 1).x, zz = Dv(2 * j + 2).x;
+  const double nu2 = uu - sum_ss_tt.x;
+  const double nu = nu2 > 0 ? sqrt(nu2) : 0.0;
+  const double inu = nu > 0 ? 1.0 / nu : 0.0;
+  const double rho_prev = rho[r];
+  if (j >= 1) {
+    // column j-1, unrotated
+    for (int i = threadIdx.x; i <= j; i += NT) {
+      double2 v;
+      if (i < j) {
+        const double2 hp = hprev[(int64_t)i * R + r], si = Dv(i);
+        v = make_double2(hp.x + rho_prev * si.x, hp.y + rho_prev * si.y);
+      } else {
+        v = make_double2(rho_prev * nu, 0);
+      }
+      Hraw[((int64_t)(j - 1) * maxvec + i) * R + r] = v;
+      hcol[(int64_t)i * R + r] = v;
+    }
+    __syncthreads();
+    if (!done[r]) givens_column(j - 1, r, hcol, rho_prev * nu, H, cs, sn, g, beta, done, iters, resid, tol, maxvec,
+                                R, hist, &xj_sh);
+    __syncthreads();
+  }
+  // tau = (u^H z - s^H t) / nu
+  const double2 tau = make_double2((uz.x - st.x) * inu, (uz.y - st.y) * inu);
+  for (int i = threadIdx.x; i < 2 * j; i += NT) uc[(int64_t)i * R + r] = Dv(i);
+  if (threadIdx.x == 0) {
+    const double sg2 = zz - sum_ss_tt.y - (tau.x * tau.x + tau.y * tau.y);
+    const double sg = sg2 > 0 ? sqrt(sg2) : 0.0;
+    const double isg = sg > 0 ? 1.0 / sg : 0.0;
+    uc[(int64_t)(2 * j) * R + r] = tau;
+    uc[(int64_t)(2 * j + 1) * R + r] = make_double2(inu, 0);
+    uc[(int64_t)(2 * j + 2) * R + r] = make_double2(isg, 0);
+    rho[r] = sg * inu;
+  }
+  publish_step(j + 1, jptr, done, R, counter, status);
+}
+
+// First-pass coefficients of column j, hprev = ([t; tau] - H s) / nu with H the
+// unrotated (j+1) x j Hessenberg matrix: one (row, system) item per block in
+// turn, a block-wide dot over the row.  Every block of the update kernels
+// takes part, so that the rows cost no launch of their own.
+__device__ void first_pass_rows(int j, int R, int maxvec, const double2* __restrict__ Hraw,
+                                const double2* __restrict__ uc, double2* __restrict__ hprev, double2* red) {
+  for (int item = blockIdx.x; item < (j + 1) * R; item += gridDim.x) {
+    const int i = item / R, r = item - i * R;
+    double x = 0, y = 0;
+    for (int k = max(0, i - 1) + (int)threadIdx.x; k < j; k += NT) {
+      const double2 a = Hraw[((int64_t)k * maxvec + i) * R + r], b = uc[(int64_t)k * R + r];
+      x += a.x * b.x - a.y * b.y;
+      y += a.x * b.y + a.y * b.x;
+    }
+    const double2 hs = block_sum_all(x, y, red);
+    if (threadIdx.x == 0) {
+      const double2 c = uc[(int64_t)(i < j ? j + i : 2 * j) * R + r];
+      const double inu = uc[(int64_t)(2 * j + 1) * R + r].x;
+      hprev[(int64_t)i * R + r] = make_double2((c.x - hs.x) * inu, (c.y - hs.y) * inu);
+    }
+  }
+}
+
+// The update of iteration j (read as *jptr - 1, after the scalar step):
+// V_j = q_j = (u - Q s) / nu and V_{j+1} = out2 = (z - Q t - q_j tau) / sigma.
+// Short vectors: a workgroup owns 64 entries and its four waves take every
+// fourth basis vector.
+__global__ void __launch_bounds__(NT) k_dupdate_split(double2* __restrict__ V, int64_t vs,
+                                                      const int* __restrict__ jptr, const double2* __restrict__ uc,
+                                                      const double2* __restrict__ z, int n, int R,
+                                                      double2* __restrict__ out2, const double2* __restrict__ Hraw,
+                                                      double2* __restrict__ hprev, int maxvec) {
+  __shared__ double2 red[2][NT / 64][64];
+  __shared__ double2 red1[NT / 64];
+  const int j = *jptr - 1;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
+  const bool live = idx < (int64_t)n * R;
+  const int r = lane % R;   // 64 is a multiple of R
+  double sx = 0, sy = 0, tx = 0, ty = 0;
+  if (live) {
+#pragma unroll 4
+    for (int i = wv; i < j; i += NT / 64) {
+      const double2 a = V[(int64_t)i * vs + idx], b = uc[(int64_t)i * R + r], c = uc[(int64_t)(j + i) * R + r];
+      sx += a.x * b.x - a.y * b.y;
+      sy += a.x * b.y + a.y * b.x;
+      tx += a.x * c.x - a.y * c.y;
+      ty += a.x * c.y + a.y * c.x;
+    }
+  }
+  red[0][wv][lane] = make_double2(sx, sy);
+  red[1][wv][lane] = make_double2(tx, ty);
+  __syncthreads();
+  if (wv == 0 && live) {
+    double ax = 0, ay = 0, bx = 0, by = 0;
+    for (int q = 0; q < NT / 64; ++q) {
+      ax += red[0][q][lane].x;
+      ay += red[0][q][lane].y;
+      bx += red[1][q][lane].x;
+      by += red[1][q][lane].y;
+    }
+    const double2 tau = uc[(int64_t)(2 * j) * R + r];
+    const double inu = uc[(int64_t)(2 * j + 1) * R + r].x, isg = uc[(int64_t)(2 * j + 2) * R + r].x;
+    const double2 u = V[(int64_t)j * vs + idx], zv = z[idx];
+    const double2 q = make_double2((u.x - ax) * inu, (u.y - ay) * inu);
+    const double2 un = make_double2((zv.x - bx - (q.x * tau.x - q.y * tau.y)) * isg,
+                                    (zv.y - by - (q.x * tau.y + q.y * tau.x)) * isg);
+    V[(int64_t)j * vs + idx] = q;
+    V[(int64_t)(j + 1) * vs + idx] = un;
+    if (out2) out2[idx] = un;
+  }
+  first_pass_rows(j, R, maxvec, Hraw, uc, hprev, red1);
+}
+
+// the same for long vectors: one thread per entry over all basis vectors
+__global__ void __launch_bounds__(NT) k_dupdate(double2* __restrict__ V, int64_t vs, const int* __restrict__ jptr,
+                                                const double2* __restrict__ uc, const double2* __restrict__ z, int n,
+                                                int R, double2* __restrict__ out2, const double2* __restrict__ Hraw,
+                                                double2* __restrict__ hprev, int maxvec) {
+  __shared__ double2 red1[NT / 64];
+  const int j = *jptr - 1;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < (int64_t)n * R) {
+    const int r = threadIdx.x % R;   // NT is a multiple of R
+    double ax = 0, ay = 0, bx = 0, by = 0;
+#pragma unroll 4
+    for (int i = 0; i < j; ++i) {
+      const double2 a = V[(int64_t)i * vs + idx], b = uc[(int64_t)i * R + r], c = uc[(int64_t)(j + i) * R + r];
+      ax += a.x * b.x - a.y * b.y;
+      ay += a.x * b.y + a.y * b.x;
+      bx += a.x * c.x - a.y * c.y;
+      by += a.x * c.y + a.y * c.x;
+    }
+    const double2 tau = uc[(int64_t)(2 * j) * R + r];
+    const double inu = uc[(int64_t)(2 * j + 1) * R + r].x, isg = uc[(int64_t)(2 * j + 2) * R + r].x;
+    const double2 u = V[(int64_t)j * vs + idx], zv = z[idx];
+    const double2 q = make_double2((u.x - ax) * inu, (u.y - ay) * inu);
+    const double2 un = make_double2((zv.x - bx - (q.x * tau.x - q.y * tau.y)) * isg,
+                                    (zv.y - by - (q.x * tau.y + q.y * tau.x)) * isg);
+    V[(int64_t)j * vs + idx] = q;
+    V[(int64_t)(j + 1) * vs + idx] = un;
+    if (out2) out2[idx] = un;
+  }
+  first_pass_rows(j, R, maxvec, Hraw, uc, hprev, red1);
 }
 
 // Start of a GMRES run: g_0 = beta = ||P^-1 rhs||, flags cleared, j = 0.
@@ -2026,62 +2191,33 @@ GmresDims gmres_dims(int n, int R, int maxvec) {
   GmresDims g;
   g.step = NT / R;
   g.wave = R < 8;
+  g.ngroups = maxvec;   // one basis vector per multi-dot item
   if (g.wave) {
-    // one wave per (chunk, vector group): 256 entries per chunk (four per lane),
-    // more when the partial buffer's 512 chunks would not cover the rows
+    // one wave per (chunk, basis vector): 256 entries per chunk (four per lane),
+    // more when the partial buffer's 512 chunks would not cover the rows; a
+    // grid of up to 4,096 workgroups (16,384 waves) strides over the items
     g.chunk = int(std::max<int64_t>(256 / R, (int64_t(n) + 511) / 512));
     g.nchunks = int((int64_t(n) + g.chunk - 1) / g.chunk);
-    g.ngroups = (maxvec + GVW - 1) / GVW;
     g.grid = int(std::max<int64_t>(1, std::min<int64_t>(4096, (int64_t(g.nchunks) * g.ngroups + 3) / 4)));
   } else {
     // up to 512 row chunks (the partial buffer holds 512) keep the chip busy with
     // many right-hand sides while only a few Arnoldi vectors exist
     g.chunk = int(std::max<int64_t>(g.step, (int64_t(n) + 511) / 512));
     g.nchunks = int((int64_t(n) + g.chunk - 1) / g.chunk);
-    g.ngroups = (maxvec + GVEC - 1) / GVEC;
-    g.grid = int(std::max<int64_t>(1, std::min<int64_t>(2048, int64_t(g.nchunks) * g.ngroups)));
+    g.grid = int(std::max<int64_t>(1, std::min<int64_t>(2048, int64_t(g.nchunks) * ((maxvec + DGV - 1) / DGV + 1))));
   }
   g.nnorm = int(std::max<int64_t>(1, std::min<int64_t>(256, (int64_t(n) * R + NT - 1) / NT)));
   return g;
 }
 
-void launch_mdot(const double2* V, int64_t vs, const int* jptr, int jfix, const double2* w, int n, int R,
-                 const GmresDims& g, int maxvec, double2* part, int self, hipStream_t s) {
-  if (g.wave)
-    hipLaunchKernelGGL(k_mdot_wave, dim3(g.grid), dim3(NT), 0, s, V, vs, jptr, jfix, w, n, R, g.chunk, g.nchunks,
-                       maxvec, part, self);
-  else
-    hipLaunchKernelGGL((k_mdot<4>), dim3(g.grid), dim3(NT), 0, s, V, vs, jptr, jfix, w, n, R, g.chunk, g.nchunks,
-                       maxvec, part, self);
-  HIPCHECK(hipGetLastError());
-}
-
-void launch_mdot_reduce(const double2* part, const GmresDims& g, const int* jptr, int jfix, int maxvec, int R,
-                        double2* hh, double2* hsum, int first, int self, hipStream_t s) {
-  hipLaunchKernelGGL(k_mdot_reduce, dim3(nblocks(int64_t(maxvec) * R, NT / 64)), dim3(NT), 0, s, part, g.nchunks,
-                     jptr, jfix, maxvec, R, hh, hsum, first, self);
-  HIPCHECK(hipGetLastError());
-}
-
 void launch_mupdate(const double2* V, int64_t vs, const int* jptr, int jfix, const double2* hc, double2* w, int n,
                     int R, double sign, double* npart, hipStream_t s) {
   if (int64_t(n) * R <= UPD_SPLIT_MAX)
-    hipLaunchKernelGGL(k_mupdate_split<false>, dim3(nblocks(int64_t(n) * R, 64)), dim3(NT), 0, s, V, vs, jptr, jfix,
-                       hc, w, n, R, sign, npart, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(k_mupdate_split, dim3(nblocks(int64_t(n) * R, 64)), dim3(NT), 0, s, V, vs, jptr, jfix, hc, w, n,
+                       R, sign, npart);
   else
-    hipLaunchKernelGGL(k_mupdate<false>, dim3(nblocks(int64_t(n) * R)), dim3(NT), 0, s, V, vs, jptr, jfix, hc, w, n,
-                       R, sign, npart, nullptr, nullptr, nullptr);
-  HIPCHECK(hipGetLastError());
-}
-
-void launch_mupdate_normalize(double2* V, int64_t vs, const int* jptr, const double2* hc, const double2* w, int n,
-                              int R, double2* out2, double* nrm, hipStream_t s) {
-  if (int64_t(n) * R <= UPD_SPLIT_MAX)
-    hipLaunchKernelGGL(k_mupdate_split<true>, dim3(nblocks(int64_t(n) * R, 64)), dim3(NT), 0, s, V, vs, jptr, 0, hc,
-                       const_cast<double2*>(w), n, R, -1.0, nullptr, V, out2, nrm);
-  else
-    hipLaunchKernelGGL(k_mupdate<true>, dim3(nblocks(int64_t(n) * R)), dim3(NT), 0, s, V, vs, jptr, 0, hc,
-                       const_cast<double2*>(w), n, R, -1.0, nullptr, V, out2, nrm);
+    hipLaunchKernelGGL(k_mupdate, dim3(nblocks(int64_t(n) * R)), dim3(NT), 0, s, V, vs, jptr, jfix, hc, w, n, R, sign,
+                       npart);
   HIPCHECK(hipGetLastError());
 }
 
@@ -2093,11 +2229,41 @@ void launch_normalize(const double2* w, int n, int R, const GmresDims& g, double
   HIPCHECK(hipGetLastError());
 }
 
-void launch_givens(int* jptr, const double2* hsum, const double* nrm, double2* H, double2* cs, double2* sn, double2* g,
-                   const double* beta, int* done, int* iters, double* resid, double tol, int maxvec, int R,
-                   int* counter, int* status, double* hist, hipStream_t s) {
-  hipLaunchKernelGGL(k_givens, dim3(R), dim3(NT), 0, s, jptr, hsum, nrm, H, cs, sn, g, beta, done, iters, resid, tol,
-                     maxvec, R, counter, status, hist);
+void launch_dmdot(const double2* V, int64_t vs, const int* jptr, const double2* z, int n, int R, const GmresDims& g,
+                  int dstride, double2* part, hipStream_t s) {
+  if (g.wave)
+    hipLaunchKernelGGL(k_dmdot_wave, dim3(g.grid), dim3(NT), 0, s, V, vs, jptr, z, n, R, g.chunk, g.nchunks, dstride,
+                       part);
+  else
+    hipLaunchKernelGGL(k_dmdot_blk, dim3(g.grid), dim3(NT), 0, s, V, vs, jptr, z, n, R, g.chunk, g.nchunks, dstride,
+                       part);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_dmdot_reduce(const double2* part, const GmresDims& g, const int* jptr, int dstride, int R, double2* D,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_dmdot_reduce, dim3(nblocks(int64_t(dstride) * R, NT / 64)), dim3(NT), 0, s, part, g.nchunks,
+                     jptr, dstride, R, D);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_dcgs_scalar(int* jptr, const double2* D, double2* Hraw, double2* hprev, double* rho, double2* hcol,
+                        double2* uc, double2* H, double2* cs, double2* sn, double2* g, const double* beta, int* done,
+                        int* iters, double* resid, double tol, int maxvec, int R, int* counter, int* status,
+                        double* hist, hipStream_t s) {
+  hipLaunchKernelGGL(k_dcgs_scalar, dim3(R), dim3(NT), 0, s, jptr, D, Hraw, hprev, rho, hcol, uc, H, cs, sn, g, beta,
+                     done, iters, resid, tol, maxvec, R, counter, status, hist);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_dupdate(double2* V, int64_t vs, const int* jptr, const double2* uc, const double2* z, int n, int R,
+                    double2* out2, const double2* Hraw, double2* hprev, int maxvec, hipStream_t s) {
+  if (int64_t(n) * R <= UPD_SPLIT_MAX)
+    hipLaunchKernelGGL(k_dupdate_split, dim3(nblocks(int64_t(n) * R, 64)), dim3(NT), 0, s, V, vs, jptr, uc, z, n, R,
+                       out2, Hraw, hprev, maxvec);
+  else
+    hipLaunchKernelGGL(k_dupdate, dim3(nblocks(int64_t(n) * R)), dim3(NT), 0, s, V, vs, jptr, uc, z, n, R, out2, Hraw,
+                       hprev, maxvec);
   HIPCHECK(hipGetLastError());
 }
 

@@ -119,22 +119,25 @@ void launch_pack_sym_tiles(const Handle& h, hipStream_t s);
 void launch_coarse_symv_tiles(const Handle& h, const double2* g, hipStream_t s);
 void launch_coarse_symv_reduce(const Handle& h, double2* w, hipStream_t s);
 GmresDims gmres_dims(int n, int R, int maxvec);
-// self = 1 appends |w|^2 as entry nvec of the multi-dot (hh only, not hsum)
-void launch_mdot(const double2* V, int64_t vs, const int* jptr, int jfix, const double2* w, int n, int R,
-                 const GmresDims& g, int maxvec, double2* part, int self, hipStream_t s);
-void launch_mdot_reduce(const double2* part, const GmresDims& g, const int* jptr, int jfix, int maxvec, int R,
-                        double2* hh, double2* hsum, int first, int self, hipStream_t s);
 void launch_mupdate(const double2* V, int64_t vs, const int* jptr, int jfix, const double2* hc, double2* w, int n,
                     int R, double sign, double* npart, hipStream_t s);
-// V_{j+1} = out2 = (w - sum_{i<=j} V_i h_i) / nrm with nrm^2 = h_{j+1} - sum |h_i|^2
-// (hc from a multi-dot with self = 1); nrm is written per RHS column
-void launch_mupdate_normalize(double2* V, int64_t vs, const int* jptr, const double2* hc, const double2* w, int n,
-                              int R, double2* out2, double* nrm, hipStream_t s);
 void launch_normalize(const double2* w, int n, int R, const GmresDims& g, double* part, double* nrm, double2* out,
                       const int* jptr, int64_t vs, double2* out2, hipStream_t s);
-void launch_givens(int* jptr, const double2* hsum, const double* nrm, double2* H, double2* cs, double2* sn, double2* g,
-                   const double* beta, int* done, int* iters, double* resid, double tol, int maxvec, int R,
-                   int* counter, int* status, double* hist, hipStream_t s);
+// Arnoldi with delayed reorthogonalisation: multi-dot of the basis, the
+// tentative vector V_j and z (2j + 3 entries per chunk, stride dstride), its
+// reduction into D, the scalar step (Hessenberg column j-1, Givens, update
+// coefficients, j += 1) and the update forming q_j and the next tentative
+// vector (also copied to out2)
+void launch_dmdot(const double2* V, int64_t vs, const int* jptr, const double2* z, int n, int R, const GmresDims& g,
+                  int dstride, double2* part, hipStream_t s);
+void launch_dmdot_reduce(const double2* part, const GmresDims& g, const int* jptr, int dstride, int R, double2* D,
+                         hipStream_t s);
+void launch_dcgs_scalar(int* jptr, const double2* D, double2* Hraw, double2* hprev, double* rho, double2* hcol,
+                        double2* uc, double2* H, double2* cs, double2* sn, double2* g, const double* beta, int* done,
+                        int* iters, double* resid, double tol, int maxvec, int R, int* counter, int* status,
+                        double* hist, hipStream_t s);
+void launch_dupdate(double2* V, int64_t vs, const int* jptr, const double2* uc, const double2* z, int n, int R,
+                    double2* out2, const double2* Hraw, double2* hprev, int maxvec, hipStream_t s);
 void launch_gmres_init(const double* nrm, double* beta, double2* g, int* done, int* iters, double* resid, int* jptr,
                        int* counter, int* status, int R, double* hist, hipStream_t s);
 
