@@ -489,6 +489,28 @@ void build_device(Handle& h) {
   }
   d.cls_n = upload(h, cn); d.cls_m = upload(h, cm); d.cls_nr = upload(h, cnr);
   d.cls_op1 = upload(h, o_op1); d.cls_phi = upload(h, o_phi); d.cls_se = upload(h, o_se);
+  {
+    // flattened per-block and per-slot tables of the slot kernels
+    std::vector<SlotBlock> blk(E);
+    for (int b = 0; b < E; ++b) {
+      const int e = h.order[b], c = h.cls[e];
+      blk[b] = SlotBlock{o_op1[c], o_se[c], o_phi[c], e, c, h.slot_off[e], h.cm_off[e], cm[c], cnr[c], 0, 0};
+    }
+    d.slot_blk = upload(h, blk);
+    const size_t ns = h.slot_row.size();
+    std::vector<SlotIn> in0(ns), in1(ns), in2(ns);
+    for (size_t sl = 0; sl < ns; ++sl) {
+      const int row = h.slot_row[sl];
+      const double f = h.slot_coef[sl], fx = f * h.row_xinv[row];
+      in0[sl] = SlotIn{f, 0.0, row, -1};
+      in1[sl] = SlotIn{fx, 0.0, row, -1};
+      in2[sl] = SlotIn{h.row_coef[2 * size_t(row)] * fx, h.row_coef[2 * size_t(row) + 1] * fx,
+                       h.row_slot[2 * size_t(row)], h.row_slot[2 * size_t(row) + 1]};
+    }
+    d.slot_in[0] = upload(h, in0);
+    d.slot_in[1] = upload(h, in1);
+    d.slot_in[2] = upload(h, in2);
+  }
   d.cls_E = upload(h, o_E); d.cls_D = upload(h, o_D); d.cls_G = upload(h, o_G);
   d.cls_Kc = upload(h, o_Kc); d.cls_V = upload(h, o_V);
   d.cls_gam = upload(h, cgam); d.gam_modes = upload(h, gam);

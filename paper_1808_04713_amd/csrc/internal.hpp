@@ -77,6 +77,20 @@ struct NDLevel {
   int fR = 0, nfR = 0, Sf = 1, bR = 0, nbR = 0, Sb = 1;   // first task, tiles, splits per tile
 };
 
+// Per-block record of the slot kernels (blocks follow the class-grouped element
+// order): the element, its class, slot and coarse-mode offsets and counts, and
+// the class's operator offsets, so that a block starts with one load.
+struct SlotBlock {
+  int64_t op1, se, phi;
+  int e, c, so, cmo, m, nr, pad0, pad1;
+};
+// Per-slot input gather of the slot kernels: value = a0 v[s0] + a1 v[s1] (an
+// index < 0 contributes nothing), the row scalings already multiplied in.
+struct SlotIn {
+  double a0, a1;
+  int s0, s1;
+};
+
 struct Handle {
   // problem
   int E = 0, l = 0, nlam = 0, nK = 0;
@@ -168,6 +182,8 @@ struct Handle {
   struct Dev {
     // maps
     int *elem_cls = nullptr, *order = nullptr, *slot_off = nullptr, *cm_off = nullptr;
+    SlotBlock* slot_blk = nullptr;
+    SlotIn* slot_in[3] = {nullptr, nullptr, nullptr};   // modes 0 (F), 1 (P, rows), 2 (P, slots)
     int64_t* dof_off = nullptr;
     int *row_slot = nullptr, *slot_row = nullptr, *slot_mode = nullptr;
     int64_t *slot_pos = nullptr, *cm_pos = nullptr;   // positions in full-element arrays

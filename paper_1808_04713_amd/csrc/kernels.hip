@@ -62,59 +62,47 @@ __device__ __forceinline__ double2 block_sum_by_rhs(double2 v, int R, double2* r
 // ---------------------------------------------------------------------------
 // Slot kernels: one block per element (class-grouped order), RC RHS per block.
 template <class T2, int MODE>
-__global__ void __launch_bounds__(NT) k_slot_apply(
-    const int* __restrict__ order, const int* __restrict__ elem_cls, const int* __restrict__ slot_off,
-    const int* __restrict__ cm_off, const int* __restrict__ cls_m, const int* __restrict__ cls_nr,
-    const int64_t* __restrict__ cls_op, const T2* __restrict__ op1, const T2* __restrict__ se,
-    const int64_t* __restrict__ cls_se, const int* __restrict__ slot_row, const double* __restrict__ slot_coef,
-    const double* __restrict__ row_xinv, const int* __restrict__ row_slot, const double* __restrict__ row_coef,
-    const T2* __restrict__ v, T2* __restrict__ X, T2* __restrict__ GL, int R) {
+__global__ void __launch_bounds__(NT) k_slot_apply(const SlotBlock* __restrict__ blk, const SlotIn* __restrict__ sin,
+                                                   const T2* __restrict__ op1, const T2* __restrict__ se,
+                                                   const T2* __restrict__ v, T2* __restrict__ X, T2* __restrict__ GL,
+                                                   int R) {
   using S = typename Scal<T2>::T;
   __shared__ T2 y[MMAX * RC];
-  const int e = order[blockIdx.x];
-  const int c = elem_cls[e];
-  const int m = cls_m[c];
-  const int nr = cls_nr[c];
+  const SlotBlock B = blk[blockIdx.x];
+  const int m = B.m, nr = B.nr, so = B.so;
   const int r0 = blockIdx.y * RC;
   const int rc = min(RC, R - r0);
-  const int so = slot_off[e];
   for (int idx = threadIdx.x; idx < m * rc; idx += NT) {
-    int s = idx / rc, r = idx - s * rc;
-    int slot = so + s;
-    int row = slot_row[slot];
-    S f = S(slot_coef[slot]);
-    if (MODE >= 1) f *= S(row_xinv[row]);
-    T2 a;
-    if (MODE == 2) {
-      // v holds dual slots: the row value is the jump C_1 z of its two slots
-      S ax = 0, ay = 0;
-      for (int t = 0; t < 2; ++t) {
-        int sl = row_slot[2 * row + t];
-        if (sl < 0) continue;
-        S cf = S(row_coef[2 * row + t]);
-        T2 z = v[(int64_t)sl * R + r0 + r];
-        ax += cf * z.x;
-        ay += cf * z.y;
-      }
-      a = mk<T2>(ax, ay);
-    } else {
-      a = v[(int64_t)row * R + r0 + r];
+    const int s = idx / rc, r = idx - s * rc;
+    // MODE 0/1: v holds dual rows; MODE 2: dual slots, the row value being the
+    // jump C_1 z of its two slots
+    const SlotIn g = sin[so + s];
+    S ax = 0, ay = 0;
+    if (g.s0 >= 0) {
+      const T2 z = v[(int64_t)g.s0 * R + r0 + r];
+      ax += S(g.a0) * z.x;
+      ay += S(g.a0) * z.y;
     }
-    y[s * RC + r] = mk<T2>(f * a.x, f * a.y);
+    if (MODE == 2 && g.s1 >= 0) {
+      const T2 z = v[(int64_t)g.s1 * R + r0 + r];
+      ax += S(g.a1) * z.x;
+      ay += S(g.a1) * z.y;
+    }
+    y[s * RC + r] = mk<T2>(ax, ay);
   }
   __syncthreads();
   if (MODE == 0) {
     const int nrow = m + nr;
-    const T2* A = op1 + cls_op[c];
+    const T2* A = op1 + B.op1;
     for (int idx = threadIdx.x; idx < nrow * rc; idx += NT) {
       int i = idx / rc, r = idx - i * rc;
       T2 acc = mk<T2>(0, 0);
       for (int kk = 0; kk < m; ++kk) acc = cfma(A[i + (int64_t)nrow * kk], y[kk * RC + r], acc);
       if (i < m) X[(int64_t)(so + i) * R + r0 + r] = acc;
-      else GL[(int64_t)(cm_off[e] + i - m) * R + r0 + r] = acc;
+      else GL[(int64_t)(B.cmo + i - m) * R + r0 + r] = acc;
     }
   } else {
-    const T2* A = se + cls_se[c];
+    const T2* A = se + B.se;
     for (int idx = threadIdx.x; idx < m * rc; idx += NT) {
       int i = idx / rc, r = idx - i * rc;
       T2 acc = mk<T2>(0, 0);
@@ -125,19 +113,15 @@ __global__ void __launch_bounds__(NT) k_slot_apply(
 }
 
 template <class T2>
-__global__ void __launch_bounds__(NT) k_slot_coarse(
-    const int* __restrict__ order, const int* __restrict__ elem_cls, const int* __restrict__ slot_off,
-    const int* __restrict__ cm_off, const int* __restrict__ cls_m, const int* __restrict__ cls_nr,
-    const int64_t* __restrict__ cls_phi, const T2* __restrict__ phi, const int* __restrict__ t_ptr,
-    const int* __restrict__ t_dof, const double* __restrict__ t_coef, const T2* __restrict__ X,
-    const double2* __restrict__ w, T2* __restrict__ Z, int R) {
+__global__ void __launch_bounds__(NT) k_slot_coarse(const SlotBlock* __restrict__ blk, const T2* __restrict__ phi,
+                                                    const int* __restrict__ t_ptr, const int* __restrict__ t_dof,
+                                                    const double* __restrict__ t_coef, const T2* __restrict__ X,
+                                                    const double2* __restrict__ w, T2* __restrict__ Z, int R) {
   __shared__ T2 we[NRMAX * RC];
-  const int e = order[blockIdx.x];
-  const int c = elem_cls[e];
-  const int m = cls_m[c], nr = cls_nr[c];
+  const SlotBlock B = blk[blockIdx.x];
+  const int m = B.m, nr = B.nr, co = B.cmo, so = B.so;
   const int r0 = blockIdx.y * RC;
   const int rc = min(RC, R - r0);
-  const int co = cm_off[e], so = slot_off[e];
   for (int idx = threadIdx.x; idx < nr * rc; idx += NT) {
     int j = idx / rc, r = idx - j * rc;
     double ax = 0, ay = 0;
@@ -149,7 +133,7 @@ __global__ void __launch_bounds__(NT) k_slot_coarse(
     we[j * RC + r] = mk<T2>(ax, ay);
   }
   __syncthreads();
-  const T2* P = phi + cls_phi[c];
+  const T2* P = phi + B.phi;
   for (int idx = threadIdx.x; idx < m * rc; idx += NT) {
     int i = idx / rc, r = idx - i * rc;
     T2 acc = X[(int64_t)(so + i) * R + r0 + r];
@@ -2016,8 +2000,7 @@ void launch_slot_apply(const Handle& h, int mode, const T2* v, T2* X, T2* GL, in
   const T2* se;
   if constexpr (std::is_same<T2, double2>::value) { op1 = d.op1; se = d.se; }
   else { op1 = d.op1_f; se = d.se_f; }
-#define HDP_SLOT_ARGS d.order, d.elem_cls, d.slot_off, d.cm_off, d.cls_m, d.cls_nr, d.cls_op1, op1, se, d.cls_se, \
-                      d.slot_row, d.slot_coef, d.row_xinv, d.row_slot, d.row_coef, v, X, GL, R
+#define HDP_SLOT_ARGS d.slot_blk, d.slot_in[mode], op1, se, v, X, GL, R
   if (mode == 0)
     hipLaunchKernelGGL((k_slot_apply<T2, 0>), grid, dim3(NT), 0, s, HDP_SLOT_ARGS);
   else if (mode == 1)
@@ -2034,8 +2017,8 @@ void launch_slot_coarse(const Handle& h, const T2* X, const double2* w, T2* Z, i
   const auto& d = h.d;
   const T2* phi;
   if constexpr (std::is_same<T2, double2>::value) phi = d.phi; else phi = d.phi_f;
-  hipLaunchKernelGGL((k_slot_coarse<T2>), grid, dim3(NT), 0, s, d.order, d.elem_cls, d.slot_off, d.cm_off, d.cls_m,
-                     d.cls_nr, d.cls_phi, phi, d.t_ptr, d.t_dof, d.t_coef, X, w, Z, R);
+  hipLaunchKernelGGL((k_slot_coarse<T2>), grid, dim3(NT), 0, s, d.slot_blk, phi, d.t_ptr, d.t_dof, d.t_coef, X, w, Z,
+                     R);
   HIPCHECK(hipGetLastError());
 }
 
