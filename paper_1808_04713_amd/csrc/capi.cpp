@@ -631,9 +631,14 @@ void build_device(Handle& h) {
   d.status = dalloc<int>(h, 2);
   d.done = dalloc<int>(h, Rp);
   d.iters = dalloc<int>(h, Rp);
+  // the iteration status: written by the device straight into coherent pinned
+  // host memory, read by the host after the iteration's event
   void* ph = nullptr;
-  HIPCHECK(hipHostMalloc(&ph, 4 * sizeof(int), hipHostMallocDefault));
+  HIPCHECK(hipHostMalloc(&ph, 4 * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
   d.status_host = static_cast<int*>(ph);
+  void* pd = nullptr;
+  HIPCHECK(hipHostGetDevicePointer(&pd, ph, 0));
+  d.status_hdev = static_cast<int*>(pd);
   d.nrm = dalloc<double>(h, Rp);
   d.ycoef = dalloc<double2>(h, (size_t(h.max_iter) + 1) * Rp);
   // a gross failure of the factor (an unstable pivot sequence) shows here; a
@@ -915,6 +920,7 @@ GmresResult gmres(Handle& h, const double2* rhs, double2* x, int R, int prec, do
     launch_normalize(d.w, n, R, gd, d.npart, d.nrm, d.V_kry, nullptr, vs, d.vcur, s);
   }
   launch_gmres_init(d.nrm, d.beta, d.gvec, d.done, d.iters, d.resid, d.jdev, d.counter, d.status, R, d.hist, s);
+  for (int q = 0; q < 4; ++q) d.status_host[q] = 0;   // no kernel of this stream writes it before the loop
   hipEvent_t ev[2];
   HIPCHECK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
   HIPCHECK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
@@ -934,7 +940,7 @@ GmresResult gmres(Handle& h, const double2* rhs, double2* x, int R, int prec, do
       {
         Timed t(h, KF_GIVENS, 0, 0);
         launch_dcgs_scalar(d.jdev, d.dots, d.Hraw, d.hprev, d.rho, d.hcol, d.ucoef, d.Hdev, d.cs, d.sn, d.gvec,
-                           d.beta, d.done, d.iters, d.resid, tol, maxvec, R, d.counter, d.status, d.hist, s);
+                           d.beta, d.done, d.iters, d.resid, tol, maxvec, R, d.counter, d.status_hdev, d.hist, s);
       }
       {
         Timed t(h, KF_UPDATE, (jv + 5) * vb, (16.0 * jv + 20.0) * double(vs));
@@ -967,7 +973,6 @@ GmresResult gmres(Handle& h, const double2* rhs, double2* x, int R, int prec, do
       auto t0 = clk::now();
       if (graph) HIPCHECK(hipGraphLaunch(exec, s));
       else issue(it + 1);
-      HIPCHECK(hipMemcpyAsync(d.status_host + 2 * (it & 1), d.status, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHECK(hipEventRecord(ev[it & 1], s));
       auto t1 = clk::now();
       h.t_launch += std::chrono::duration<double, std::milli>(t1 - t0).count();

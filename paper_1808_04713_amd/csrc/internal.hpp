@@ -253,7 +253,8 @@ struct Handle {
     double2 *vcur = nullptr, *Hdev = nullptr, *cs = nullptr, *sn = nullptr, *gvec = nullptr;
     double *beta = nullptr, *resid = nullptr, *hist = nullptr;   // hist: (max_iter+1) x R
     int *jdev = nullptr, *counter = nullptr, *status = nullptr, *done = nullptr, *iters = nullptr;
-    int* status_host = nullptr;   // pinned, 4 ints (two in-flight status slots)
+    int* status_host = nullptr;   // pinned, mapped, coherent: 4 ints (two in-flight status slots)
+    int* status_hdev = nullptr;   // the same memory as the device addresses it
     int* load_elems = nullptr;
     int64_t* load_off = nullptr;
     double2* load_vals = nullptr;

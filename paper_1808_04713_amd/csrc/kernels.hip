@@ -1584,15 +1584,18 @@ __device__ void givens_column(int j, int r, const double2* __restrict__ hcol, do
 }
 
 // End of an iteration's scalar step: the last block to finish publishes
-// status = {all converged, jnext} and sets j = jnext.
+// status = {all converged, jnext} and sets j = jnext.  The status goes to
+// host-mapped coherent memory (two slots, alternating with the iteration), so
+// the host reads it without a copy in the stream.
 __device__ void publish_step(int jnext, int* __restrict__ jptr, const int* __restrict__ done, int R,
                              int* __restrict__ counter, int* __restrict__ status) {
   __syncthreads();
+  int* st = status + 2 * ((jnext - 1) & 1);
   if (threadIdx.x == 0 && gridDim.x == 1) {
     // a single system: no other block to wait for (device-wide fences are costly
     // across the chip's separate L2 caches)
-    status[0] = done[0];
-    status[1] = jnext;
+    st[0] = done[0];
+    st[1] = jnext;
     *jptr = jnext;
   } else if (threadIdx.x == 0) {
     __threadfence();
@@ -1601,8 +1604,8 @@ __device__ void publish_step(int jnext, int* __restrict__ jptr, const int* __res
       __threadfence();
       int all = 1;
       for (int q = 0; q < R; ++q) all &= __hip_atomic_load(done + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      status[0] = all;
-      status[1] = jnext;
+      st[0] = all;
+      st[1] = jnext;
       *jptr = jnext;
       *counter = 0;
     }
