@@ -618,7 +618,6 @@ void build_device(Handle& h) {
   d.Hdev = dalloc<double2>(h, size_t(h.max_iter) * mv * Rp);
   d.Hraw = dalloc<double2>(h, size_t(h.max_iter) * mv * Rp);
   d.hprev = dalloc<double2>(h, (mv + 1) * Rp);
-  d.hcol = dalloc<double2>(h, (mv + 1) * Rp);
   d.rho = dalloc<double>(h, Rp);
   d.cs = dalloc<double2>(h, mv * Rp);
   d.sn = dalloc<double2>(h, mv * Rp);
@@ -939,8 +938,8 @@ GmresResult gmres(Handle& h, const double2* rhs, double2* x, int R, int prec, do
       }
       {
         Timed t(h, KF_GIVENS, 0, 0);
-        launch_dcgs_scalar(d.jdev, d.dots, d.Hraw, d.hprev, d.rho, d.hcol, d.ucoef, d.Hdev, d.cs, d.sn, d.gvec,
-                           d.beta, d.done, d.iters, d.resid, tol, maxvec, R, d.counter, d.status_hdev, d.hist, s);
+        launch_dcgs_scalar(d.jdev, d.dots, d.Hraw, d.hprev, d.rho, d.ucoef, d.Hdev, d.cs, d.sn, d.gvec, d.beta,
+                           d.done, d.iters, d.resid, tol, maxvec, R, d.counter, d.status_hdev, d.hist, s);
       }
       {
         Timed t(h, KF_UPDATE, (jv + 5) * vb, (16.0 * jv + 20.0) * double(vs));

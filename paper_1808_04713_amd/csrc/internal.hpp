@@ -244,9 +244,9 @@ struct Handle {
     double2 *w = nullptr, *t0 = nullptr, *t1 = nullptr, *t2 = nullptr;
     double2* part = nullptr;
     // Arnoldi with delayed reorthogonalisation: reduced dots, unrotated
-    // Hessenberg columns, first-pass coefficients, column scratch, update
-    // coefficients, scale of the tentative vector
-    double2 *dots = nullptr, *Hraw = nullptr, *hprev = nullptr, *hcol = nullptr, *ucoef = nullptr;
+    // Hessenberg columns, first-pass coefficients, update coefficients, scale
+    // of the tentative vector
+    double2 *dots = nullptr, *Hraw = nullptr, *hprev = nullptr, *ucoef = nullptr;
     double* rho = nullptr;
     double *nrm = nullptr, *npart = nullptr;
     float2* vf = nullptr;

@@ -1495,10 +1495,15 @@ __global__ void __launch_bounds__(NT) k_normalize(const double2* __restrict__ w,
   }
 }
 
-// One block per RHS column: append column j of the Hessenberg matrix, apply the
-// previous Givens rotations, form the new one, update the residual estimate.
-// The last block to finish publishes status = {all converged, j + 1} and
-// advances j.
+__device__ __forceinline__ double2 shfl_up2(double2 v, int d) {
+  return make_double2(__shfl_up(v.x, d, 64), __shfl_up(v.y, d, 64));
+}
+
+// Column j of the Hessenberg matrix for system r: entries 0..j in hc and the
+// subdiagonal entry sub (real, >= 0); the earlier rotations in csl, snl and
+// g_j in gj, all in shared memory or registers.  Applies the earlier
+// rotations, forms rotation j, updates g and the residual estimate.  Called
+// by every thread of the block; xj_sh is block-shared scratch.
 //
 // The j earlier rotations form a chain: with x_0 = h_0 and h_i the new column,
 // rotation i maps (x_i, h_{i+1}) to the rotated entry t_i = c_i x_i + s_i h_{i+1}
@@ -1507,18 +1512,11 @@ __global__ void __launch_bounds__(NT) k_normalize(const double2* __restrict__ w,
 // of affine maps (each lane composes a segment of consecutive rotations, the
 // segments are combined across lanes in six shuffle steps) instead of a chain
 // of j dependent steps on one lane.
-__device__ __forceinline__ double2 shfl_up2(double2 v, int d) {
-  return make_double2(__shfl_up(v.x, d, 64), __shfl_up(v.y, d, 64));
-}
-
-// Column j of the Hessenberg matrix for system r: entries 0..j in hcol (stride
-// R) and the subdiagonal entry sub (real, >= 0).  Called by every thread of the
-// block; xj_sh is block-shared scratch.
-__device__ void givens_column(int j, int r, const double2* __restrict__ hcol, double sub, double2* __restrict__ H,
-                              double2* __restrict__ cs, double2* __restrict__ sn, double2* __restrict__ g,
-                              const double* __restrict__ beta, int* __restrict__ done, int* __restrict__ iters,
-                              double* __restrict__ resid, double tol, int maxvec, int R, double* __restrict__ hist,
-                              double2* xj_sh) {
+__device__ void givens_column(int j, int r, const double2* hc, double sub, const double2* csl, const double2* snl,
+                              double2 gj, double2* __restrict__ H, double2* __restrict__ cs, double2* __restrict__ sn,
+                              double2* __restrict__ g, const double* __restrict__ beta, int* __restrict__ done,
+                              int* __restrict__ iters, double* __restrict__ resid, double tol, int maxvec, int R,
+                              double* __restrict__ hist, double2* xj_sh) {
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     const int seg = (j + 63) / 64;
@@ -1526,7 +1524,7 @@ __device__ void givens_column(int j, int r, const double2* __restrict__ hcol, do
     // this lane's segment as one map x -> A x + B
     double2 A = make_double2(1, 0), B = make_double2(0, 0);
     for (int i = s0; i < s1; ++i) {
-      const double2 c = cs[i * R + r], s = sn[i * R + r], hb = hcol[(i + 1) * R + r];
+      const double2 c = csl[i], s = snl[i], hb = hc[i + 1];
       const double2 al = make_double2(-s.x, s.y);   // -conj(s)
       B = cfma(c, hb, cmul(al, B));
       A = cmul(al, A);
@@ -1544,10 +1542,10 @@ __device__ void givens_column(int j, int r, const double2* __restrict__ hcol, do
       Ae = make_double2(1, 0);
       Be = make_double2(0, 0);
     }
-    const double2 x0 = hcol[r];
+    const double2 x0 = hc[0];
     double2 x = cfma(Ae, x0, Be);   // carried value entering this lane's segment
     for (int i = s0; i < s1; ++i) {
-      const double2 c = cs[i * R + r], s = sn[i * R + r], hb = hcol[(i + 1) * R + r];
+      const double2 c = csl[i], s = snl[i], hb = hc[i + 1];
       H[((int64_t)j * maxvec + i) * R + r] = cfma(c, x, cmul(s, hb));
       x = cfma(c, hb, cmul(make_double2(-s.x, s.y), x));
     }
@@ -1571,10 +1569,9 @@ __device__ void givens_column(int j, int r, const double2* __restrict__ hcol, do
     sn[j * R + r] = s;
     H[((int64_t)j * maxvec + j) * R + r] =
         make_double2(c.x * a.x + s.x * b.x - s.y * b.y, c.x * a.y + s.x * b.y + s.y * b.x);
-    double2 gj = g[j * R + r];
-    g[(j + 1) * R + r] = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
+    const double2 gn = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
+    g[(j + 1) * R + r] = gn;
     g[j * R + r] = make_double2(c.x * gj.x, c.x * gj.y);
-    double2 gn = g[(j + 1) * R + r];
     double res = sqrt(gn.x * gn.x + gn.y * gn.y) / beta[r];
     resid[r] = res;
     if (hist) hist[(int64_t)(j + 1) * R + r] = res;
@@ -1798,58 +1795,61 @@ __device__ __forceinline__ double2 block_sum_all(double x, double y, double2* re
 // update coefficients uc = [s (j), t (j), tau, 1/nu, 1/sigma] and advances j.
 // The first-pass coefficients of column j, which need H s, are formed by the
 // update kernel that follows (they are first used in the next scalar step).
+// Every global value the step needs is loaded up front; the column and the
+// earlier rotations are kept in shared memory ((3 maxvec + 1) entries).
 __global__ void __launch_bounds__(NT) k_dcgs_scalar(int* __restrict__ jptr, const double2* __restrict__ D,
-                                                    double2* __restrict__ Hraw, double2* __restrict__ hprev,
-                                                    double* __restrict__ rho, double2* __restrict__ hcol,
-                                                    double2* __restrict__ uc, double2* __restrict__ H,
-                                                    double2* __restrict__ cs, double2* __restrict__ sn,
-                                                    double2* __restrict__ g, const double* __restrict__ beta,
-                                                    int* __restrict__ done, int* __restrict__ iters,
-                                                    double* __restrict__ resid, double tol, int maxvec, int R,
-                                                    int* __restrict__ counter, int* __restrict__ status,
-                                                    double* __restrict__ hist) {
+                                                    double2* __restrict__ Hraw, const double2* __restrict__ hprev,
+                                                    double* __restrict__ rho, double2* __restrict__ uc,
+                                                    double2* __restrict__ H, double2* __restrict__ cs,
+                                                    double2* __restrict__ sn, double2* __restrict__ g,
+                                                    const double* __restrict__ beta, int* __restrict__ done,
+                                                    int* __restrict__ iters, double* __restrict__ resid, double tol,
+                                                    int maxvec, int R, int* __restrict__ counter,
+                                                    int* __restrict__ status, double* __restrict__ hist) {
+  extern __shared__ double2 shm[];
+  double2* col = shm;                  // column j-1: maxvec + 1 entries
+  double2* csl = col + maxvec + 1;     // rotations 0..j-2
+  double2* snl = csl + maxvec;
   __shared__ double2 red[NT / 64];
   __shared__ double2 xj_sh;
   const int r = blockIdx.x;
   const int j = *jptr;
-  auto Dv = [&](int k) { return D[(int64_t)k * R + r]; };
+  const double rho_prev = rho[r];
+  const int is_done = done[r];
+  const double2 gj = j >= 1 ? g[(j - 1) * R + r] : make_double2(0, 0);
+  const double2 uz = D[(int64_t)(2 * j) * R + r];
+  const double uu = D[(int64_t)(2 * j + 1) * R + r].x, zz = D[(int64_t)(2 * j + 2) * R + r].x;
   double ss = 0, tt = 0, stx = 0, sty = 0;
   for (int i = threadIdx.x; i < j; i += NT) {
-    const double2 a = Dv(i), b = Dv(j + i);
+    const double2 a = D[(int64_t)i * R + r], b = D[(int64_t)(j + i) * R + r];
+    const double2 hp = hprev[(int64_t)i * R + r];
+    if (i < j - 1) {
+      csl[i] = cs[(int64_t)i * R + r];
+      snl[i] = sn[(int64_t)i * R + r];
+    }
+    uc[(int64_t)i * R + r] = a;
+    uc[(int64_t)(j + i) * R + r] = b;
+    col[i] = make_double2(hp.x + rho_prev * a.x, hp.y + rho_prev * a.y);
     ss += a.x * a.x + a.y * a.y;
     tt += b.x * b.x + b.y * b.y;
     cdot_acc(a, b, stx, sty);   // s^H t
   }
   const double2 sum_ss_tt = block_sum_all(ss, tt, red);
   const double2 st = block_sum_all(stx, sty, red);
-  const double2 uz = Dv(2 * j);
-  const double uu = Dv(2 * j + 1).x, zz = Dv(2 * j + 2).x;
   const double nu2 = uu - sum_ss_tt.x;
   const double nu = nu2 > 0 ? sqrt(nu2) : 0.0;
   const double inu = nu > 0 ? 1.0 / nu : 0.0;
-  const double rho_prev = rho[r];
   if (j >= 1) {
-    // column j-1, unrotated
-    for (int i = threadIdx.x; i <= j; i += NT) {
-      double2 v;
-      if (i < j) {
-        const double2 hp = hprev[(int64_t)i * R + r], si = Dv(i);
-        v = make_double2(hp.x + rho_prev * si.x, hp.y + rho_prev * si.y);
-      } else {
-        v = make_double2(rho_prev * nu, 0);
-      }
-      Hraw[((int64_t)(j - 1) * maxvec + i) * R + r] = v;
-      hcol[(int64_t)i * R + r] = v;
-    }
+    // column j-1, unrotated, to Hraw (rows 0..j), then rotated
+    if (threadIdx.x == 0) col[j] = make_double2(rho_prev * nu, 0);
     __syncthreads();
-    if (!done[r]) givens_column(j - 1, r, hcol, rho_prev * nu, H, cs, sn, g, beta, done, iters, resid, tol, maxvec,
-                                R, hist, &xj_sh);
-    __syncthreads();
+    for (int i = threadIdx.x; i <= j; i += NT) Hraw[((int64_t)(j - 1) * maxvec + i) * R + r] = col[i];
+    if (!is_done) givens_column(j - 1, r, col, rho_prev * nu, csl, snl, gj, H, cs, sn, g, beta, done, iters, resid,
+                                tol, maxvec, R, hist, &xj_sh);
   }
-  // tau = (u^H z - s^H t) / nu
-  const double2 tau = make_double2((uz.x - st.x) * inu, (uz.y - st.y) * inu);
-  for (int i = threadIdx.x; i < 2 * j; i += NT) uc[(int64_t)i * R + r] = Dv(i);
   if (threadIdx.x == 0) {
+    // tau = (u^H z - s^H t) / nu; sigma^2 = |z|^2 - |t|^2 - |tau|^2
+    const double2 tau = make_double2((uz.x - st.x) * inu, (uz.y - st.y) * inu);
     const double sg2 = zz - sum_ss_tt.y - (tau.x * tau.x + tau.y * tau.y);
     const double sg = sg2 > 0 ? sqrt(sg2) : 0.0;
     const double isg = sg > 0 ? 1.0 / sg : 0.0;
@@ -2233,11 +2233,12 @@ void launch_dmdot_reduce(const double2* part, const GmresDims& g, const int* jpt
   HIPCHECK(hipGetLastError());
 }
 
-void launch_dcgs_scalar(int* jptr, const double2* D, double2* Hraw, double2* hprev, double* rho, double2* hcol,
-                        double2* uc, double2* H, double2* cs, double2* sn, double2* g, const double* beta, int* done,
-                        int* iters, double* resid, double tol, int maxvec, int R, int* counter, int* status,
-                        double* hist, hipStream_t s) {
-  hipLaunchKernelGGL(k_dcgs_scalar, dim3(R), dim3(NT), 0, s, jptr, D, Hraw, hprev, rho, hcol, uc, H, cs, sn, g, beta,
+void launch_dcgs_scalar(int* jptr, const double2* D, double2* Hraw, const double2* hprev, double* rho, double2* uc,
+                        double2* H, double2* cs, double2* sn, double2* g, const double* beta, int* done, int* iters,
+                        double* resid, double tol, int maxvec, int R, int* counter, int* status, double* hist,
+                        hipStream_t s) {
+  const size_t shm = (3 * size_t(maxvec) + 1) * sizeof(double2);
+  hipLaunchKernelGGL(k_dcgs_scalar, dim3(R), dim3(NT), shm, s, jptr, D, Hraw, hprev, rho, uc, H, cs, sn, g, beta,
                      done, iters, resid, tol, maxvec, R, counter, status, hist);
   HIPCHECK(hipGetLastError());
 }

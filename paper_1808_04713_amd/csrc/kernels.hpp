@@ -132,10 +132,10 @@ void launch_dmdot(const double2* V, int64_t vs, const int* jptr, const double2* 
                   int dstride, double2* part, hipStream_t s);
 void launch_dmdot_reduce(const double2* part, const GmresDims& g, const int* jptr, int dstride, int R, double2* D,
                          hipStream_t s);
-void launch_dcgs_scalar(int* jptr, const double2* D, double2* Hraw, double2* hprev, double* rho, double2* hcol,
-                        double2* uc, double2* H, double2* cs, double2* sn, double2* g, const double* beta, int* done,
-                        int* iters, double* resid, double tol, int maxvec, int R, int* counter, int* status,
-                        double* hist, hipStream_t s);
+void launch_dcgs_scalar(int* jptr, const double2* D, double2* Hraw, const double2* hprev, double* rho, double2* uc,
+                        double2* H, double2* cs, double2* sn, double2* g, const double* beta, int* done, int* iters,
+                        double* resid, double tol, int maxvec, int R, int* counter, int* status, double* hist,
+                        hipStream_t s);
 void launch_dupdate(double2* V, int64_t vs, const int* jptr, const double2* uc, const double2* z, int n, int R,
                     double2* out2, const double2* Hraw, double2* hprev, int maxvec, hipStream_t s);
 void launch_gmres_init(const double* nrm, double* beta, double2* g, int* done, int* iters, double* resid, int* jptr,
