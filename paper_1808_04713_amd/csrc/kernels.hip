@@ -803,54 +803,64 @@ __global__ void __launch_bounds__(NT) k_coarse_symv_reduce(int nK, int nt, const
 
 // ---------------------------------------------------------------------------
 // Full-element separable solve X = Ex [(Ex^T Y Ey) ./ D] Ey^T, one block per (element, RHS).
+// One block per (element, chunk of rc right-hand sides): the chunk's n^2 x rc
+// entries are staged in shared memory with the right-hand side fastest, so the
+// global reads and writes are contiguous runs of rc entries and the four
+// products read the shared arrays without bank conflicts.
 __global__ void __launch_bounds__(NT) k_fdm(const int* __restrict__ elem_cls, const int64_t* __restrict__ dof_off,
                                             const int* __restrict__ cls_n, const int64_t* __restrict__ cls_E,
                                             const int64_t* __restrict__ cls_D, const double2* __restrict__ Ex,
                                             const double2* __restrict__ Ey, const double2* __restrict__ Dinv,
-                                            const double2* __restrict__ in, double2* __restrict__ out, int R) {
+                                            const double2* __restrict__ in, double2* __restrict__ out, int R,
+                                            int RCH) {
   extern __shared__ double2 sm[];
   const int e = blockIdx.x;
-  const int r = blockIdx.y;
+  const int r0 = blockIdx.y * RCH;
+  const int rc = min(RCH, R - r0);
   const int c = elem_cls[e];
-  const int n = cls_n[c], n2 = n * n;
+  const int n = cls_n[c], n2 = n * n, nt = n2 * rc;
   double2* A = sm;
-  double2* B = sm + n2;
+  double2* B = sm + (size_t)n2 * RCH;
   const double2* ex = Ex + cls_E[c];
   const double2* ey = Ey + cls_E[c];
   const double2* di = Dinv + cls_D[c];
   const int64_t base = dof_off[e];
-  for (int t = threadIdx.x; t < n2; t += NT) A[t] = in[(base + t) * R + r];
+  // entry (t, r) of a stage lives at t * rc + r
+  for (int idx = threadIdx.x; idx < nt; idx += NT) {
+    const int t = idx / rc, r = idx - t * rc;
+    A[idx] = in[(base + t) * R + r0 + r];
+  }
   __syncthreads();
   // B = Ex^T A
-  for (int t = threadIdx.x; t < n2; t += NT) {
-    int i = t % n, j = t / n;
+  for (int idx = threadIdx.x; idx < nt; idx += NT) {
+    const int t = idx / rc, r = idx - t * rc, i = t % n, j = t / n;
     double2 acc = make_double2(0, 0);
-    for (int k = 0; k < n; ++k) acc = cfma(ex[k + n * i], A[k + n * j], acc);
-    B[t] = acc;
+    for (int k = 0; k < n; ++k) acc = cfma(ex[k + n * i], A[(k + n * j) * rc + r], acc);
+    B[idx] = acc;
   }
   __syncthreads();
   // A = (B Ey) .* Dinv
-  for (int t = threadIdx.x; t < n2; t += NT) {
-    int i = t % n, j = t / n;
+  for (int idx = threadIdx.x; idx < nt; idx += NT) {
+    const int t = idx / rc, r = idx - t * rc, i = t % n, j = t / n;
     double2 acc = make_double2(0, 0);
-    for (int k = 0; k < n; ++k) acc = cfma(B[i + n * k], ey[k + n * j], acc);
-    A[t] = cmul(acc, di[t]);
+    for (int k = 0; k < n; ++k) acc = cfma(B[(i + n * k) * rc + r], ey[k + n * j], acc);
+    A[idx] = cmul(acc, di[t]);
   }
   __syncthreads();
   // B = Ex A
-  for (int t = threadIdx.x; t < n2; t += NT) {
-    int i = t % n, j = t / n;
+  for (int idx = threadIdx.x; idx < nt; idx += NT) {
+    const int t = idx / rc, r = idx - t * rc, i = t % n, j = t / n;
     double2 acc = make_double2(0, 0);
-    for (int k = 0; k < n; ++k) acc = cfma(ex[i + n * k], A[k + n * j], acc);
-    B[t] = acc;
+    for (int k = 0; k < n; ++k) acc = cfma(ex[i + n * k], A[(k + n * j) * rc + r], acc);
+    B[idx] = acc;
   }
   __syncthreads();
   // out = B Ey^T
-  for (int t = threadIdx.x; t < n2; t += NT) {
-    int i = t % n, j = t / n;
+  for (int idx = threadIdx.x; idx < nt; idx += NT) {
+    const int t = idx / rc, r = idx - t * rc, i = t % n, j = t / n;
     double2 acc = make_double2(0, 0);
-    for (int k = 0; k < n; ++k) acc = cfma(B[i + n * k], ey[j + n * k], acc);
-    out[(base + t) * R + r] = acc;
+    for (int k = 0; k < n; ++k) acc = cfma(B[(i + n * k) * rc + r], ey[j + n * k], acc);
+    out[(base + t) * R + r0 + r] = acc;
   }
 }
 
@@ -890,6 +900,9 @@ __global__ void k_extract_kc(const int* __restrict__ elem_cls, const int64_t* __
 
 // mu = Kc (c - T_e w); X -= G mu.  Afterwards X at the coarse modes equals T_e w
 // (T_e w: each coarse mode's expansion over the global coarse unknowns).
+// Woodbury correction of the full-element solves, one block per (element, chunk
+// of rc right-hand sides), right-hand side fastest as in k_fdm: the removed
+// modes' values minus their coarse parts, times K_e, then X -= G mu.
 __global__ void __launch_bounds__(NT) k_correct(const int* __restrict__ elem_cls, const int64_t* __restrict__ dof_off,
                                                 const int* __restrict__ cm_off, const int* __restrict__ cls_n,
                                                 const int* __restrict__ cls_nr, const int* __restrict__ cls_R,
@@ -897,40 +910,48 @@ __global__ void __launch_bounds__(NT) k_correct(const int* __restrict__ elem_cls
                                                 const double2* __restrict__ Kc, const int64_t* __restrict__ cls_G,
                                                 const double2* __restrict__ G, const int* __restrict__ t_ptr,
                                                 const int* __restrict__ t_dof, const double* __restrict__ t_coef,
-                                                double2* __restrict__ X, const double2* __restrict__ w, int R) {
-  __shared__ double2 dv[NRMAX], mu[NRMAX];
-  int e = blockIdx.x, r = blockIdx.y;
-  int c = elem_cls[e];
-  int n = cls_n[c], n2 = n * n, nr = cls_nr[c];
+                                                double2* __restrict__ X, const double2* __restrict__ w, int R,
+                                                int RCH) {
+  extern __shared__ double2 sm[];
+  const int e = blockIdx.x;
+  const int r0 = blockIdx.y * RCH;
+  const int rc = min(RCH, R - r0);
+  const int c = elem_cls[e];
+  const int n = cls_n[c], n2 = n * n, nr = cls_nr[c];
+  double2* dv = sm;                          // nr x rc
+  double2* mu = sm + (size_t)NRMAX * RCH;    // nr x rc
   const int* rm = r_modes + cls_R[c];
   const int64_t base = dof_off[e];
-  for (int a = threadIdx.x; a < nr; a += blockDim.x) {
-    double2 x = X[(base + rm[a]) * R + r];
+  for (int idx = threadIdx.x; idx < nr * rc; idx += NT) {
+    const int a = idx / rc, r = idx - a * rc;
+    double2 x = X[(base + rm[a]) * R + r0 + r];
     const int i = cm_off[e] + a;
     for (int t = t_ptr[i]; t < t_ptr[i + 1]; ++t) {
-      double2 ww = w[(int64_t)t_dof[t] * R + r];
+      const double2 ww = w[(int64_t)t_dof[t] * R + r0 + r];
       x.x -= t_coef[t] * ww.x;
       x.y -= t_coef[t] * ww.y;
     }
-    dv[a] = x;
+    dv[idx] = x;
   }
   __syncthreads();
   const double2* K = Kc + cls_Kc[c];
-  for (int a = threadIdx.x; a < nr; a += blockDim.x) {
+  for (int idx = threadIdx.x; idx < nr * rc; idx += NT) {
+    const int a = idx / rc, r = idx - a * rc;
     double2 acc = make_double2(0, 0);
-    for (int b = 0; b < nr; ++b) acc = cfma(K[a + nr * b], dv[b], acc);
-    mu[a] = acc;
+    for (int b = 0; b < nr; ++b) acc = cfma(K[a + nr * b], dv[b * rc + r], acc);
+    mu[idx] = acc;
   }
   __syncthreads();
   const double2* Gc = G + cls_G[c];
-  for (int t = threadIdx.x; t < n2; t += NT) {
-    double2 acc = X[(base + t) * R + r];
+  for (int idx = threadIdx.x; idx < n2 * rc; idx += NT) {
+    const int t = idx / rc, r = idx - t * rc;
+    double2 acc = X[(base + t) * R + r0 + r];
     for (int a = 0; a < nr; ++a) {
-      double2 gm = cmul(Gc[t + (int64_t)n2 * a], mu[a]);
+      const double2 gm = cmul(Gc[t + (int64_t)n2 * a], mu[a * rc + r]);
       acc.x -= gm.x;
       acc.y -= gm.y;
     }
-    X[(base + t) * R + r] = acc;
+    X[(base + t) * R + r0 + r] = acc;
   }
 }
 
@@ -2124,13 +2145,24 @@ void launch_pack_sym_tiles(const Handle& h, hipStream_t s) {
   HIPCHECK(hipGetLastError());
 }
 
+// right-hand sides per block of the full-element kernels: the largest power of
+// two <= R whose two n^2 stages fit 64 KB of shared memory
+static int fdm_chunk(const Handle& h, int R) {
+  int nmax = 0;
+  for (auto& C : h.classes) nmax = std::max(nmax, C.n);
+  int rch = 1;
+  while (rch * 2 <= R && size_t(2) * nmax * nmax * (rch * 2) * sizeof(double2) <= 65536) rch *= 2;
+  return rch;
+}
+
 void launch_fdm(const Handle& h, const double2* in, double2* out, int R, hipStream_t s) {
   int nmax = 0;
   for (auto& C : h.classes) nmax = std::max(nmax, C.n);
-  size_t shm = size_t(2) * nmax * nmax * sizeof(double2);
+  const int rch = fdm_chunk(h, R);
+  const size_t shm = size_t(2) * nmax * nmax * rch * sizeof(double2);
   const auto& d = h.d;
-  hipLaunchKernelGGL(k_fdm, dim3(h.E, R), dim3(NT), shm, s, d.elem_cls, d.dof_off, d.cls_n, d.cls_E, d.cls_D, d.Ex,
-                     d.Ey, d.Dinv, in, out, R);
+  hipLaunchKernelGGL(k_fdm, dim3(h.E, (R + rch - 1) / rch), dim3(NT), shm, s, d.elem_cls, d.dof_off, d.cls_n, d.cls_E,
+                     d.cls_D, d.Ex, d.Ey, d.Dinv, in, out, R, rch);
   HIPCHECK(hipGetLastError());
 }
 
@@ -2150,8 +2182,11 @@ void launch_extract_kc(const Handle& h, const double2* X, double2* GL, int R, hi
 
 void launch_correct(const Handle& h, double2* X, const double2* w, int R, hipStream_t s) {
   const auto& d = h.d;
-  hipLaunchKernelGGL(k_correct, dim3(h.E, R), dim3(NT), 0, s, d.elem_cls, d.dof_off, d.cm_off, d.cls_n, d.cls_nr,
-                     d.cls_R, d.r_modes, d.cls_Kc, d.Kc, d.cls_G, d.G, d.t_ptr, d.t_dof, d.t_coef, X, w, R);
+  const int rch = std::min(fdm_chunk(h, R), 8);
+  const size_t shm = size_t(2) * NRMAX * rch * sizeof(double2);
+  hipLaunchKernelGGL(k_correct, dim3(h.E, (R + rch - 1) / rch), dim3(NT), shm, s, d.elem_cls, d.dof_off, d.cm_off,
+                     d.cls_n, d.cls_nr, d.cls_R, d.r_modes, d.cls_Kc, d.Kc, d.cls_G, d.G, d.t_ptr, d.t_dof, d.t_coef, X,
+                     w, R, rch);
   HIPCHECK(hipGetLastError());
 }
 
