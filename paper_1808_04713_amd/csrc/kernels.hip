@@ -490,6 +490,85 @@ __device__ __forceinline__ void nd_mm_core(const double2* __restrict__ M, int K,
   }
 }
 
+// The same product on the matrix cores for R = 16, 32, 64 columns: each wave
+// owns 16 outputs (j tile jt = wave & 1) and two 16-column tiles of R, and
+// accumulates complex products as four real FP64 16x16x4 matrix operations per
+// step of 4 summation rows (A operand: the 16 operand columns x 4 rows, B
+// operand: 4 rows x the 16 outputs of M).  In the result, lane l holds entry
+// (row (l >> 4) + 4 v, column l & 15) in its v-th value; the tiles go through
+// Dt to the thread-per-column layout of acc used by the callers.
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void nd_mm_core_mfma(const double2* __restrict__ M, int K, int i0, int i1, int n_out,
+                                                int j0, const double2* __restrict__ X,
+                                                const double2* __restrict__ X2, int64_t xbase,
+                                                const int* __restrict__ xidx, int R, double2 (&acc)[8],
+                                                double2* Dt) {
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int jl = l & 15, kq = l >> 4;
+  const int jt = wv & 1, rt0 = (wv >> 1) * 2;
+  const int nrt = R >> 4;
+  const bool act0 = rt0 < nrt, act1 = rt0 + 1 < nrt;
+  const int j = j0 + 16 * jt + jl;
+  const bool jv = j < n_out;
+  const double2* mcol = M + (int64_t)K * (jv ? j : 0);
+  d4 cr0 = {0, 0, 0, 0}, ci0 = {0, 0, 0, 0}, cr1 = {0, 0, 0, 0}, ci1 = {0, 0, 0, 0};
+  if (act0) {
+    // unrolled so that the loads of several steps are in flight together
+#pragma unroll 4
+    for (int k = i0; k < i1; k += 4) {
+      const int kk = k + kq;
+      const bool kv = kk < i1;
+      const double2 b = (kv && jv) ? mcol[kk] : make_double2(0, 0);
+      double2 a0 = make_double2(0, 0), a1 = make_double2(0, 0);
+      if (kv) {
+        const int64_t row = xidx ? (int64_t)xidx[kk] : xbase + kk;
+        const double2* xr = X + row * R + jl;
+        a0 = xr[16 * rt0];
+        if (act1) a1 = xr[16 * (rt0 + 1)];
+        if (X2) {
+          const double2* x2 = X2 + row * R + jl;
+          const double2 c0 = x2[16 * rt0];
+          a0.x += c0.x;
+          a0.y += c0.y;
+          if (act1) {
+            const double2 c1 = x2[16 * (rt0 + 1)];
+            a1.x += c1.x;
+            a1.y += c1.y;
+          }
+        }
+      }
+      cr0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, b.x, cr0, 0, 0, 0);
+      ci0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, b.y, ci0, 0, 0, 0);
+      cr0 = __builtin_amdgcn_mfma_f64_16x16x4f64(-a0.y, b.y, cr0, 0, 0, 0);
+      ci0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.y, b.x, ci0, 0, 0, 0);
+      if (act1) {
+        cr1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.x, b.x, cr1, 0, 0, 0);
+        ci1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.x, b.y, ci1, 0, 0, 0);
+        cr1 = __builtin_amdgcn_mfma_f64_16x16x4f64(-a1.y, b.y, cr1, 0, 0, 0);
+        ci1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.y, b.x, ci1, 0, 0, 0);
+      }
+    }
+    double2* dj = Dt + (16 * jt + jl) * 64;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dj[16 * rt0 + kq + 4 * v] = make_double2(cr0[v], ci0[v]);
+    if (act1) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dj[16 * (rt0 + 1) + kq + 4 * v] = make_double2(cr1[v], ci1[v]);
+    }
+  }
+  __syncthreads();
+  if (l < R) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double2 d = Dt[(wv * 8 + q) * 64 + l];
+      acc[q].x += d.x;
+      acc[q].y += d.y;
+    }
+  }
+  __syncthreads();
+}
+
 // Partial tiles: P[task][32][64].  A task is {node, first output, i0, i1}.
 __device__ __forceinline__ void nd_store_part(double2* __restrict__ P, const double2 (&acc)[8], int R) {
   const int r = threadIdx.x & 63, jw = (threadIdx.x >> 6) * 8;
@@ -499,9 +578,11 @@ __device__ __forceinline__ void nd_store_part(double2* __restrict__ P, const dou
 }
 
 // U_t = A_t - L_t Y_I over the task's range of I (into P when the sum is split).
+template <bool MF>
 __global__ void __launch_bounds__(NT) k_nd_fwdR(const int4* __restrict__ task, NDNodes nd,
                                                 const double2* __restrict__ g, double2* __restrict__ F,
                                                 double2* __restrict__ A, int R, double2* __restrict__ P) {
+  __shared__ double2 Dt[MF ? SMJ * 64 : 1];
   const int4 tk = task[blockIdx.x];
   const int t = tk.x, j0 = tk.y;
   const int o = nd.off[t], nI = nd.off[t + 1] - o;
@@ -509,7 +590,8 @@ __global__ void __launch_bounds__(NT) k_nd_fwdR(const int4* __restrict__ task, N
   double2 acc[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) acc[q] = make_double2(0, 0);
-  nd_mm_core(nd.fac + nd.mL[t], nI, tk.z, tk.w, nB, j0, g, F, o, nullptr, R, acc);
+  if (MF) nd_mm_core_mfma(nd.fac + nd.mL[t], nI, tk.z, tk.w, nB, j0, g, F, o, nullptr, R, acc, Dt);
+  else nd_mm_core(nd.fac + nd.mL[t], nI, tk.z, tk.w, nB, j0, g, F, o, nullptr, R, acc);
   if (P) {
     nd_store_part(P, acc, R);
     return;
@@ -527,9 +609,11 @@ __global__ void __launch_bounds__(NT) k_nd_fwdR(const int4* __restrict__ task, N
 
 // X_I = Dinv_t Y_I - Lt_t X_B; the summation runs over [0, nI) for the first
 // product and [nI, nI + nB) for the second, of which the task takes [i0, i1).
+template <bool MF>
 __global__ void __launch_bounds__(NT) k_nd_bwdR(const int4* __restrict__ task, NDNodes nd,
                                                 const double2* __restrict__ g, const double2* __restrict__ F,
                                                 double2* __restrict__ X, int R, double2* __restrict__ P) {
+  __shared__ double2 Dt[MF ? SMJ * 64 : 1];
   const int4 tk = task[blockIdx.x];
   const int t = tk.x, j0 = tk.y;
   const int o = nd.off[t], nI = nd.off[t + 1] - o;
@@ -539,9 +623,14 @@ __global__ void __launch_bounds__(NT) k_nd_bwdR(const int4* __restrict__ task, N
 #pragma unroll
   for (int q = 0; q < 8; ++q) a1[q] = a2[q] = make_double2(0, 0);
   const int e1 = min(tk.w, nI);
-  if (tk.z < e1) nd_mm_core(nd.fac + nd.mD[t], nI, tk.z, e1, nI, j0, g, F, o, nullptr, R, a1);
   const int s2 = max(tk.z, nI) - nI, e2 = tk.w - nI;
-  if (s2 < e2) nd_mm_core(nd.fac + nd.mLt[t], nB, s2, e2, nI, j0, X, nullptr, 0, nd.bnd + bo, R, a2);
+  if (MF) {
+    if (tk.z < e1) nd_mm_core_mfma(nd.fac + nd.mD[t], nI, tk.z, e1, nI, j0, g, F, o, nullptr, R, a1, Dt);
+    if (s2 < e2) nd_mm_core_mfma(nd.fac + nd.mLt[t], nB, s2, e2, nI, j0, X, nullptr, 0, nd.bnd + bo, R, a2, Dt);
+  } else {
+    if (tk.z < e1) nd_mm_core(nd.fac + nd.mD[t], nI, tk.z, e1, nI, j0, g, F, o, nullptr, R, a1);
+    if (s2 < e2) nd_mm_core(nd.fac + nd.mLt[t], nB, s2, e2, nI, j0, X, nullptr, 0, nd.bnd + bo, R, a2);
+  }
 #pragma unroll
   for (int q = 0; q < 8; ++q) a1[q] = make_double2(a1[q].x - a2[q].x, a1[q].y - a2[q].y);
   if (P) {
@@ -2415,8 +2504,15 @@ void launch_nd_tiles(bool bwd, const int4* task, int ntiles, int S, const NDView
   const NDNodes nd{v.off, v.boff, v.bnd, v.uoff, v.push, v.mD, v.mL, v.mLt, v.fac};
   double2* part = S > 1 ? P : nullptr;
   const unsigned nt = unsigned(ntiles) * unsigned(S);
-  if (bwd) hipLaunchKernelGGL(k_nd_bwdR, dim3(nt), dim3(NT), 0, s, task, nd, g, F, X, R, part);
-  else hipLaunchKernelGGL(k_nd_fwdR, dim3(nt), dim3(NT), 0, s, task, nd, g, F, A, R, part);
+  // 16, 32 or 64 columns go to the matrix cores
+  const bool mf = R >= 16 && R % 16 == 0;
+  if (bwd) {
+    if (mf) hipLaunchKernelGGL(k_nd_bwdR<true>, dim3(nt), dim3(NT), 0, s, task, nd, g, F, X, R, part);
+    else hipLaunchKernelGGL(k_nd_bwdR<false>, dim3(nt), dim3(NT), 0, s, task, nd, g, F, X, R, part);
+  } else {
+    if (mf) hipLaunchKernelGGL(k_nd_fwdR<true>, dim3(nt), dim3(NT), 0, s, task, nd, g, F, A, R, part);
+    else hipLaunchKernelGGL(k_nd_fwdR<false>, dim3(nt), dim3(NT), 0, s, task, nd, g, F, A, R, part);
+  }
   if (S > 1)
     hipLaunchKernelGGL(k_nd_reduce, dim3(nblocks(int64_t(ntiles) * SMJ * R)), dim3(NT), 0, s, task, ntiles, S, P, nd,
                        F, A, X, R, bwd ? 1 : 0);
