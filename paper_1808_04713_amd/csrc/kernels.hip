@@ -514,8 +514,6 @@ __device__ __forceinline__ void nd_mm_core_mfma(const double2* __restrict__ M, i
   const double2* mcol = M + (int64_t)K * (jv ? j : 0);
   d4 cr0 = {0, 0, 0, 0}, ci0 = {0, 0, 0, 0}, cr1 = {0, 0, 0, 0}, ci1 = {0, 0, 0, 0};
   if (act0) {
-    // unrolled so that the loads of several steps are in flight together
-#pragma unroll 4
     for (int k = i0; k < i1; k += 4) {
       const int kk = k + kq;
       const bool kv = kk < i1;
@@ -896,6 +894,7 @@ __global__ void __launch_bounds__(NT) k_coarse_symv_reduce(int nK, int nt, const
 // entries are staged in shared memory with the right-hand side fastest, so the
 // global reads and writes are contiguous runs of rc entries and the four
 // products read the shared arrays without bank conflicts.
+template <bool SE>
 __global__ void __launch_bounds__(NT) k_fdm(const int* __restrict__ elem_cls, const int64_t* __restrict__ dof_off,
                                             const int* __restrict__ cls_n, const int64_t* __restrict__ cls_E,
                                             const int64_t* __restrict__ cls_D, const double2* __restrict__ Ex,
@@ -910,9 +909,24 @@ __global__ void __launch_bounds__(NT) k_fdm(const int* __restrict__ elem_cls, co
   const int n = cls_n[c], n2 = n * n, nt = n2 * rc;
   double2* A = sm;
   double2* B = sm + (size_t)n2 * RCH;
+  // with SE the class's E_x, E_y and 1/(lambda_x + lambda_y) are staged next to
+  // the two stages (the degrees up to 27 let them fit)
   const double2* ex = Ex + cls_E[c];
   const double2* ey = Ey + cls_E[c];
   const double2* di = Dinv + cls_D[c];
+  if (SE) {
+    double2* exs = B + (size_t)n2 * RCH;
+    double2* eys = exs + n2;
+    double2* dis = eys + n2;
+    for (int idx = threadIdx.x; idx < n2; idx += NT) {
+      exs[idx] = ex[idx];
+      eys[idx] = ey[idx];
+      dis[idx] = di[idx];
+    }
+    ex = exs;
+    ey = eys;
+    di = dis;
+  }
   const int64_t base = dof_off[e];
   // entry (t, r) of a stage lives at t * rc + r
   for (int idx = threadIdx.x; idx < nt; idx += NT) {
@@ -2235,23 +2249,31 @@ void launch_pack_sym_tiles(const Handle& h, hipStream_t s) {
 }
 
 // right-hand sides per block of the full-element kernels: the largest power of
-// two <= R whose two n^2 stages fit 64 KB of shared memory
-static int fdm_chunk(const Handle& h, int R) {
+// two <= R whose two n^2 stages and the three n^2 class operators fit 64 KB of
+// shared memory
+static int fdm_chunk(const Handle& h, int R, bool staged) {
   int nmax = 0;
   for (auto& C : h.classes) nmax = std::max(nmax, C.n);
+  const int extra = staged ? 3 : 0;
   int rch = 1;
-  while (rch * 2 <= R && size_t(2) * nmax * nmax * (rch * 2) * sizeof(double2) <= 65536) rch *= 2;
+  while (rch * 2 <= R && size_t(nmax) * nmax * (2 * (rch * 2) + extra) * sizeof(double2) <= 65536) rch *= 2;
   return rch;
 }
 
 void launch_fdm(const Handle& h, const double2* in, double2* out, int R, hipStream_t s) {
   int nmax = 0;
   for (auto& C : h.classes) nmax = std::max(nmax, C.n);
-  const int rch = fdm_chunk(h, R);
-  const size_t shm = size_t(2) * nmax * nmax * rch * sizeof(double2);
+  const bool staged = size_t(nmax) * nmax * 5 * sizeof(double2) <= 65536;
+  const int rch = fdm_chunk(h, R, staged);
+  const size_t shm = size_t(nmax) * nmax * (2 * rch + (staged ? 3 : 0)) * sizeof(double2);
   const auto& d = h.d;
-  hipLaunchKernelGGL(k_fdm, dim3(h.E, (R + rch - 1) / rch), dim3(NT), shm, s, d.elem_cls, d.dof_off, d.cls_n, d.cls_E,
-                     d.cls_D, d.Ex, d.Ey, d.Dinv, in, out, R, rch);
+  const dim3 grid(h.E, (R + rch - 1) / rch);
+  if (staged)
+    hipLaunchKernelGGL(k_fdm<true>, grid, dim3(NT), shm, s, d.elem_cls, d.dof_off, d.cls_n, d.cls_E, d.cls_D, d.Ex,
+                       d.Ey, d.Dinv, in, out, R, rch);
+  else
+    hipLaunchKernelGGL(k_fdm<false>, grid, dim3(NT), shm, s, d.elem_cls, d.dof_off, d.cls_n, d.cls_E, d.cls_D, d.Ex,
+                       d.Ey, d.Dinv, in, out, R, rch);
   HIPCHECK(hipGetLastError());
 }
 
@@ -2271,7 +2293,7 @@ void launch_extract_kc(const Handle& h, const double2* X, double2* GL, int R, hi
 
 void launch_correct(const Handle& h, double2* X, const double2* w, int R, hipStream_t s) {
   const auto& d = h.d;
-  const int rch = std::min(fdm_chunk(h, R), 8);
+  const int rch = std::min(fdm_chunk(h, R, false), 8);
   const size_t shm = size_t(2) * NRMAX * rch * sizeof(double2);
   hipLaunchKernelGGL(k_correct, dim3(h.E, (R + rch - 1) / rch), dim3(NT), shm, s, d.elem_cls, d.dof_off, d.cm_off,
                      d.cls_n, d.cls_nr, d.cls_R, d.r_modes, d.cls_Kc, d.Kc, d.cls_G, d.G, d.t_ptr, d.t_dof, d.t_coef, X,
