@@ -142,6 +142,115 @@ __global__ void __launch_bounds__(NT) k_slot_coarse(const SlotBlock* __restrict_
   }
 }
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// The slot operators at 16, 32 or 64 right-hand sides on the FP64 matrix
+// cores.  Per element (block): the K x R operand (gathered dual slots, or the
+// element's coarse values for MODE 3) goes to LDS with R fastest; out = Mat
+// operand, Mat column-major nrow x K (op1 for MODE 0, S_e for MODEs 1/2, Phi for
+// MODE 3, which also adds X).  Wave w owns output tiles (16 rows of Mat) x (16
+// columns of R) in turn; a step of 4 summation rows is four real 16x16x4
+// operations per complex tile (A operand: 16 columns of R x 4 rows from LDS, B
+// operand: 4 rows x 16 rows of Mat).  Lane l holds result (column (l >> 4) + 4 v,
+// row l & 15) in value v; the tiles are written back to the LDS buffer and
+// copied out with R fastest.  The LDS buffer holds max(K, nrow) x R entries
+// (at most the largest such count over the classes, times R).
+constexpr int SLOT_MF_LDS = 65536;
+
+template <int MODE>
+__global__ void __launch_bounds__(NT) k_slot_mfma(const SlotBlock* __restrict__ blk,
+                                                  const SlotIn* __restrict__ sin, const double2* __restrict__ op1,
+                                                  const double2* __restrict__ se, const double2* __restrict__ phi,
+                                                  const int* __restrict__ t_ptr, const int* __restrict__ t_dof,
+                                                  const double* __restrict__ t_coef, const double2* __restrict__ v,
+                                                  const double2* __restrict__ Xin, double2* __restrict__ X,
+                                                  double2* __restrict__ GL, int R) {
+  extern __shared__ double2 buf[];
+  const SlotBlock B = blk[blockIdx.x];
+  const int m = B.m, nr = B.nr, so = B.so;
+  const int K = MODE == 3 ? nr : m;
+  const int nrow = MODE == 0 ? m + nr : m;
+  const double2* Mat = MODE == 0 ? op1 + B.op1 : (MODE == 3 ? phi + B.phi : se + B.se);
+  // operand rows kk x R
+  for (int idx = threadIdx.x; idx < K * R; idx += NT) {
+    const int kk = idx / R, r = idx - kk * R;
+    double ax = 0, ay = 0;
+    if (MODE == 3) {
+      const int co = B.cmo + kk;
+      for (int t = t_ptr[co]; t < t_ptr[co + 1]; ++t) {
+        const double2 a = v[(int64_t)t_dof[t] * R + r];
+        ax += t_coef[t] * a.x;
+        ay += t_coef[t] * a.y;
+      }
+    } else {
+      const SlotIn g = sin[so + kk];
+      if (g.s0 >= 0) {
+        const double2 z = v[(int64_t)g.s0 * R + r];
+        ax += g.a0 * z.x;
+        ay += g.a0 * z.y;
+      }
+      if (MODE == 2 && g.s1 >= 0) {
+        const double2 z = v[(int64_t)g.s1 * R + r];
+        ax += g.a1 * z.x;
+        ay += g.a1 * z.y;
+      }
+    }
+    buf[idx] = make_double2(ax, ay);
+  }
+  __syncthreads();
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int jl = l & 15, kq = l >> 4;
+  const int nit = (nrow + 15) >> 4, nrt = R >> 4, ntile = nit * nrt;
+  // at most 4 row tiles x 4 column tiles: each wave keeps up to 4 tiles
+  d4 cr[4], ci[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    cr[q] = (d4){0, 0, 0, 0};
+    ci[q] = (d4){0, 0, 0, 0};
+  }
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const int kk = k0 + kq;
+    const bool kv = kk < K;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int tile = wv + 4 * q;
+      if (tile >= ntile) break;   // uniform over the wave
+      const int it = tile / nrt, rt = tile - it * nrt;
+      const int i = 16 * it + jl;
+      const double2 b = (kv && i < nrow) ? Mat[i + (int64_t)nrow * kk] : make_double2(0, 0);
+      const double2 a = kv ? buf[kk * R + 16 * rt + jl] : make_double2(0, 0);
+      cr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr[q], 0, 0, 0);
+      ci[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ci[q], 0, 0, 0);
+      cr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cr[q], 0, 0, 0);
+      ci[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, ci[q], 0, 0, 0);
+    }
+  }
+  __syncthreads();   // every wave is done with the operand
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int tile = wv + 4 * q;
+    if (tile >= ntile) break;
+    const int it = tile / nrt, rt = tile - it * nrt;
+    const int i = 16 * it + jl;
+    if (i < nrow) {
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) buf[i * R + 16 * rt + kq + 4 * vv] = make_double2(cr[q][vv], ci[q][vv]);
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < nrow * R; idx += NT) {
+    const int i = idx / R, r = idx - i * R;
+    double2 o = buf[idx];
+    if (MODE == 3) {
+      const double2 x = Xin[(int64_t)(so + i) * R + r];
+      o.x += x.x;
+      o.y += x.y;
+    }
+    if (MODE != 0 || i < m) X[(int64_t)(so + i) * R + r] = o;
+    else GL[(int64_t)(B.cmo + i - m) * R + r] = o;
+  }
+}
+
 // u[row] = scale_row * (sum coef * src[pos(slot)] + sum_{C_2} coef * w[dof])
 template <class T2>
 __global__ void k_rowgather(int nlam, const int* __restrict__ row_slot, const double* __restrict__ row_coef,
@@ -497,7 +606,6 @@ __device__ __forceinline__ void nd_mm_core(const double2* __restrict__ M, int K,
 // operand: 4 rows x the 16 outputs of M).  In the result, lane l holds entry
 // (row (l >> 4) + 4 v, column l & 15) in its v-th value; the tiles go through
 // Dt to the thread-per-column layout of acc used by the callers.
-typedef double d4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void nd_mm_core_mfma(const double2* __restrict__ M, int K, int i0, int i1, int n_out,
                                                 int j0, const double2* __restrict__ X,
@@ -2119,10 +2227,33 @@ inline unsigned nblocks(int64_t n, int t = NT) { return unsigned((n + t - 1) / t
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// shared memory of the matrix-core slot kernels at R columns, or 0 when they do
+// not apply (R not 16, 32 or 64, or an element's operand or output rows do not
+// fit: at most 64 KB and 16 output tiles per element)
+static size_t slot_mfma_lds(const Handle& h, int R, int mode) {
+  if (R < 16 || R % 16 != 0) return 0;
+  int rows = 0;   // operand and output rows: m + nr (interface operator) or max(m, nr)
+  for (auto& C : h.classes) rows = std::max(rows, mode == 0 ? C.m + C.nr : std::max(C.m, C.nr));
+  const size_t lds = size_t(rows) * R * sizeof(double2);
+  if (lds > SLOT_MF_LDS || ((rows + 15) / 16) * (R / 16) > 16) return 0;
+  return lds;
+}
+
 template <class T2>
 void launch_slot_apply(const Handle& h, int mode, const T2* v, T2* X, T2* GL, int R, hipStream_t s) {
   dim3 grid(h.E, (R + RC - 1) / RC);
   const auto& d = h.d;
+  if constexpr (std::is_same<T2, double2>::value) {
+    if (const size_t lds = slot_mfma_lds(h, R, mode)) {
+#define HDP_MF_ARGS d.slot_blk, d.slot_in[mode], d.op1, d.se, d.phi, d.t_ptr, d.t_dof, d.t_coef, v, nullptr, X, GL, R
+      if (mode == 0) hipLaunchKernelGGL(k_slot_mfma<0>, dim3(h.E), dim3(NT), lds, s, HDP_MF_ARGS);
+      else if (mode == 1) hipLaunchKernelGGL(k_slot_mfma<1>, dim3(h.E), dim3(NT), lds, s, HDP_MF_ARGS);
+      else hipLaunchKernelGGL(k_slot_mfma<2>, dim3(h.E), dim3(NT), lds, s, HDP_MF_ARGS);
+#undef HDP_MF_ARGS
+      HIPCHECK(hipGetLastError());
+      return;
+    }
+  }
   const T2* op1;
   const T2* se;
   if constexpr (std::is_same<T2, double2>::value) { op1 = d.op1; se = d.se; }
@@ -2142,6 +2273,14 @@ template <class T2>
 void launch_slot_coarse(const Handle& h, const T2* X, const double2* w, T2* Z, int R, hipStream_t s) {
   dim3 grid(h.E, (R + RC - 1) / RC);
   const auto& d = h.d;
+  if constexpr (std::is_same<T2, double2>::value) {
+    if (const size_t lds = slot_mfma_lds(h, R, 3)) {
+      hipLaunchKernelGGL(k_slot_mfma<3>, dim3(h.E), dim3(NT), lds, s, d.slot_blk, nullptr, d.op1, d.se, d.phi,
+                         d.t_ptr, d.t_dof, d.t_coef, w, X, Z, nullptr, R);
+      HIPCHECK(hipGetLastError());
+      return;
+    }
+  }
   const T2* phi;
   if constexpr (std::is_same<T2, double2>::value) phi = d.phi; else phi = d.phi_f;
   hipLaunchKernelGGL((k_slot_coarse<T2>), grid, dim3(NT), 0, s, d.slot_blk, phi, d.t_ptr, d.t_dof, d.t_coef, X, w, Z,

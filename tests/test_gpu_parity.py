@@ -79,6 +79,24 @@ def test_local_solve_separable(name, oracles):
     s.close()
 
 
+@pytest.mark.parametrize("R", [16, 32, 64])
+@pytest.mark.parametrize("name", ["uniform_4x4_p6_l2", "uniform_5x5_p7_l3"])
+def test_operators_at_many_columns(name, R, oracles):
+    """F v and P^-1 v at 16, 32 and 64 columns (the matrix-core slot kernels)
+    against the oracle column by column."""
+    disc, l, E = oracles[name]
+    s = hdp().Solver(CASES[name], max_rhs=R)
+    rng = np.random.default_rng(R)
+    v = rng.standard_normal((E.nlam, R)) + 1j * rng.standard_normal((E.nlam, R))
+    vd = torch.from_numpy(v).cuda()
+    Fv = s.apply_interface(vd, "fp64").cpu().numpy()
+    Pv = s.apply_precond(vd, "fp64").cpu().numpy()
+    for r in range(R):
+        assert rel(Fv[:, r], E.apply_F(v[:, r])) < 1e-12
+        assert rel(Pv[:, r], E.apply_P(v[:, r])) < 1e-12
+    s.close()
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_interface_operator_and_preconditioner(name, oracles):
     disc, l, E = oracles[name]
