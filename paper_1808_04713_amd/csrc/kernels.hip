@@ -164,33 +164,34 @@ __global__ void __launch_bounds__(NT) k_slot_mfma(const SlotBlock* __restrict__ 
                                                   const int* __restrict__ t_ptr, const int* __restrict__ t_dof,
                                                   const double* __restrict__ t_coef, const double2* __restrict__ v,
                                                   const double2* __restrict__ Xin, double2* __restrict__ X,
-                                                  double2* __restrict__ GL, int R) {
+                                                  double2* __restrict__ GL, int R, int RB) {
   extern __shared__ double2 buf[];
+  const int r0 = blockIdx.y * RB;   // this block's RB columns of the R
   const SlotBlock B = blk[blockIdx.x];
   const int m = B.m, nr = B.nr, so = B.so;
   const int K = MODE == 3 ? nr : m;
   const int nrow = MODE == 0 ? m + nr : m;
   const double2* Mat = MODE == 0 ? op1 + B.op1 : (MODE == 3 ? phi + B.phi : se + B.se);
   // operand rows kk x R
-  for (int idx = threadIdx.x; idx < K * R; idx += NT) {
-    const int kk = idx / R, r = idx - kk * R;
+  for (int idx = threadIdx.x; idx < K * RB; idx += NT) {
+    const int kk = idx / RB, r = idx - kk * RB;
     double ax = 0, ay = 0;
     if (MODE == 3) {
       const int co = B.cmo + kk;
       for (int t = t_ptr[co]; t < t_ptr[co + 1]; ++t) {
-        const double2 a = v[(int64_t)t_dof[t] * R + r];
+        const double2 a = v[(int64_t)t_dof[t] * R + r0 + r];
         ax += t_coef[t] * a.x;
         ay += t_coef[t] * a.y;
       }
     } else {
       const SlotIn g = sin[so + kk];
       if (g.s0 >= 0) {
-        const double2 z = v[(int64_t)g.s0 * R + r];
+        const double2 z = v[(int64_t)g.s0 * R + r0 + r];
         ax += g.a0 * z.x;
         ay += g.a0 * z.y;
       }
       if (MODE == 2 && g.s1 >= 0) {
-        const double2 z = v[(int64_t)g.s1 * R + r];
+        const double2 z = v[(int64_t)g.s1 * R + r0 + r];
         ax += g.a1 * z.x;
         ay += g.a1 * z.y;
       }
@@ -200,7 +201,7 @@ __global__ void __launch_bounds__(NT) k_slot_mfma(const SlotBlock* __restrict__ 
   __syncthreads();
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int jl = l & 15, kq = l >> 4;
-  const int nit = (nrow + 15) >> 4, nrt = R >> 4, ntile = nit * nrt;
+  const int nit = (nrow + 15) >> 4, nrt = RB >> 4, ntile = nit * nrt;
   // at most 4 row tiles x 4 column tiles: each wave keeps up to 4 tiles
   d4 cr[4], ci[4];
 #pragma unroll
@@ -218,7 +219,7 @@ __global__ void __launch_bounds__(NT) k_slot_mfma(const SlotBlock* __restrict__ 
       const int it = tile / nrt, rt = tile - it * nrt;
       const int i = 16 * it + jl;
       const double2 b = (kv && i < nrow) ? Mat[i + (int64_t)nrow * kk] : make_double2(0, 0);
-      const double2 a = kv ? buf[kk * R + 16 * rt + jl] : make_double2(0, 0);
+      const double2 a = kv ? buf[kk * RB + 16 * rt + jl] : make_double2(0, 0);
       cr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr[q], 0, 0, 0);
       ci[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ci[q], 0, 0, 0);
       cr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cr[q], 0, 0, 0);
@@ -234,20 +235,20 @@ __global__ void __launch_bounds__(NT) k_slot_mfma(const SlotBlock* __restrict__ 
     const int i = 16 * it + jl;
     if (i < nrow) {
 #pragma unroll
-      for (int vv = 0; vv < 4; ++vv) buf[i * R + 16 * rt + kq + 4 * vv] = make_double2(cr[q][vv], ci[q][vv]);
+      for (int vv = 0; vv < 4; ++vv) buf[i * RB + 16 * rt + kq + 4 * vv] = make_double2(cr[q][vv], ci[q][vv]);
     }
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < nrow * R; idx += NT) {
-    const int i = idx / R, r = idx - i * R;
+  for (int idx = threadIdx.x; idx < nrow * RB; idx += NT) {
+    const int i = idx / RB, r = idx - i * RB;
     double2 o = buf[idx];
     if (MODE == 3) {
-      const double2 x = Xin[(int64_t)(so + i) * R + r];
+      const double2 x = Xin[(int64_t)(so + i) * R + r0 + r];
       o.x += x.x;
       o.y += x.y;
     }
-    if (MODE != 0 || i < m) X[(int64_t)(so + i) * R + r] = o;
-    else GL[(int64_t)(B.cmo + i - m) * R + r] = o;
+    if (MODE != 0 || i < m) X[(int64_t)(so + i) * R + r0 + r] = o;
+    else GL[(int64_t)(B.cmo + i - m) * R + r0 + r] = o;
   }
 }
 
@@ -2230,12 +2231,15 @@ inline unsigned nblocks(int64_t n, int t = NT) { return unsigned((n + t - 1) / t
 // shared memory of the matrix-core slot kernels at R columns, or 0 when they do
 // not apply (R not 16, 32 or 64, or an element's operand or output rows do not
 // fit: at most 64 KB and 16 output tiles per element)
+constexpr int SLOT_MF_RB = 32;   // columns per block (two blocks per element at 64)
+
 static size_t slot_mfma_lds(const Handle& h, int R, int mode) {
   if (R < 16 || R % 16 != 0) return 0;
+  const int rb = std::min(R, SLOT_MF_RB);
   int rows = 0;   // operand and output rows: m + nr (interface operator) or max(m, nr)
   for (auto& C : h.classes) rows = std::max(rows, mode == 0 ? C.m + C.nr : std::max(C.m, C.nr));
-  const size_t lds = size_t(rows) * R * sizeof(double2);
-  if (lds > SLOT_MF_LDS || ((rows + 15) / 16) * (R / 16) > 16) return 0;
+  const size_t lds = size_t(rows) * rb * sizeof(double2);
+  if (lds > SLOT_MF_LDS || ((rows + 15) / 16) * (rb / 16) > 16) return 0;
   return lds;
 }
 
@@ -2245,10 +2249,12 @@ void launch_slot_apply(const Handle& h, int mode, const T2* v, T2* X, T2* GL, in
   const auto& d = h.d;
   if constexpr (std::is_same<T2, double2>::value) {
     if (const size_t lds = slot_mfma_lds(h, R, mode)) {
-#define HDP_MF_ARGS d.slot_blk, d.slot_in[mode], d.op1, d.se, d.phi, d.t_ptr, d.t_dof, d.t_coef, v, nullptr, X, GL, R
-      if (mode == 0) hipLaunchKernelGGL(k_slot_mfma<0>, dim3(h.E), dim3(NT), lds, s, HDP_MF_ARGS);
-      else if (mode == 1) hipLaunchKernelGGL(k_slot_mfma<1>, dim3(h.E), dim3(NT), lds, s, HDP_MF_ARGS);
-      else hipLaunchKernelGGL(k_slot_mfma<2>, dim3(h.E), dim3(NT), lds, s, HDP_MF_ARGS);
+      const int rb = std::min(R, SLOT_MF_RB);
+      const dim3 g(h.E, R / rb);
+#define HDP_MF_ARGS d.slot_blk, d.slot_in[mode], d.op1, d.se, d.phi, d.t_ptr, d.t_dof, d.t_coef, v, nullptr, X, GL, R, rb
+      if (mode == 0) hipLaunchKernelGGL(k_slot_mfma<0>, g, dim3(NT), lds, s, HDP_MF_ARGS);
+      else if (mode == 1) hipLaunchKernelGGL(k_slot_mfma<1>, g, dim3(NT), lds, s, HDP_MF_ARGS);
+      else hipLaunchKernelGGL(k_slot_mfma<2>, g, dim3(NT), lds, s, HDP_MF_ARGS);
 #undef HDP_MF_ARGS
       HIPCHECK(hipGetLastError());
       return;
@@ -2275,8 +2281,9 @@ void launch_slot_coarse(const Handle& h, const T2* X, const double2* w, T2* Z, i
   const auto& d = h.d;
   if constexpr (std::is_same<T2, double2>::value) {
     if (const size_t lds = slot_mfma_lds(h, R, 3)) {
-      hipLaunchKernelGGL(k_slot_mfma<3>, dim3(h.E), dim3(NT), lds, s, d.slot_blk, nullptr, d.op1, d.se, d.phi,
-                         d.t_ptr, d.t_dof, d.t_coef, w, X, Z, nullptr, R);
+      const int rb = std::min(R, SLOT_MF_RB);
+      hipLaunchKernelGGL(k_slot_mfma<3>, dim3(h.E, R / rb), dim3(NT), lds, s, d.slot_blk, nullptr, d.op1, d.se,
+                         d.phi, d.t_ptr, d.t_dof, d.t_coef, w, X, Z, nullptr, R, rb);
       HIPCHECK(hipGetLastError());
       return;
     }

@@ -163,6 +163,29 @@ def test_solve_fp64_matches_oracle(name, oracles):
     s.close()
 
 
+@pytest.mark.parametrize("cap", [1, 6])
+def test_iteration_cap_matches_the_oracle_partial_solution(cap, oracles):
+    """Stopped at the iteration cap (max_iter, no convergence) the GPU returns the
+    GMRES iterate of that many steps: the same residual history and field as the
+    oracle's GMRES with the same cap (the Krylov basis holds max_iter + 1 vectors
+    and one more candidate at the end)."""
+    name = "uniform_5x5_p7_l3"
+    disc, l, E = oracles[name]
+    w = CASES[name]
+    s = hdp().Solver(w, tol=1e-14, max_iter=cap)
+    kind, vals = hdp().rhs_values(w)
+    field, st = s.solve(kind, vals)
+    assert not st["converged"]
+    assert st["iterations"] == cap
+    hist = np.asarray(s.residual_history())
+    phis = E.solve(tol=1e-14, max_iter=cap)
+    assert E.iters == cap
+    assert np.abs(hist[:cap + 1] - np.asarray(E.hist[:cap + 1])).max() < 1e-10
+    ref = np.concatenate(pb.gll_field(disc.mesh, disc.degrees, phis))
+    assert rel(field.cpu().numpy()[0], ref) < 1e-10
+    s.close()
+
+
 def test_plane_wave_against_literal_method_and_exact_solution():
     w = W.plane_wave_4x4()
     disc = pb.Discretisation(w)
