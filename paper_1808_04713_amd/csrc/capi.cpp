@@ -510,6 +510,17 @@ void build_device(Handle& h) {
     d.slot_in[0] = upload(h, in0);
     d.slot_in[1] = upload(h, in1);
     d.slot_in[2] = upload(h, in2);
+    // row scatter of the preconditioner output: row scaling times the row's
+    // coefficient for this slot
+    std::vector<SlotOut> out(ns);
+    for (size_t sl = 0; sl < ns; ++sl) {
+      const int row = h.slot_row[sl];
+      double c = 0;
+      for (int t = 0; t < 2; ++t)
+        if (h.row_slot[2 * size_t(row) + t] == int(sl)) c = h.row_coef[2 * size_t(row) + t];
+      out[sl] = SlotOut{h.row_xinv[row] * c, row, 0};
+    }
+    d.slot_out = upload(h, out);
   }
   d.cls_E = upload(h, o_E); d.cls_D = upload(h, o_D); d.cls_G = upload(h, o_G);
   d.cls_Kc = upload(h, o_Kc); d.cls_V = upload(h, o_V);
@@ -796,6 +807,13 @@ void apply_PF(Handle& h, const double2* v, double2* w, int R, int prec) {
   const double cw = prec == HDP_FP64 ? 16.0 * R : 8.0 * R;
   const double ob = prec == HDP_FP64 ? 1.0 : 0.5;
   apply_F_slots(h, v, R, prec);
+  if (prec == HDP_FP64 && slot_rows_fused(h, R)) {
+    // preconditioner with the row gather fused: w must be zero on entry (the
+    // GMRES update clears it after its last read)
+    Timed t(h, KF_SLOT_P, nsl * cw * 2 + ob * h.se_bytes + nl * c, h.flops_P * R);
+    launch_slot_apply_rows(h, d.slotB, w, R, s);
+    return;
+  }
   {
     Timed t(h, KF_SLOT_P, nsl * cw * 2 + ob * h.se_bytes, h.flops_P * R);
     if (prec == HDP_FP64) launch_slot_apply<double2>(h, 2, d.slotB, d.slotA, nullptr, R, s);
@@ -920,6 +938,8 @@ GmresResult gmres(Handle& h, const double2* rhs, double2* x, int R, int prec, do
   }
   launch_gmres_init(d.nrm, d.beta, d.gvec, d.done, d.iters, d.resid, d.jdev, d.counter, d.status, R, d.hist, s);
   for (int q = 0; q < 4; ++q) d.status_host[q] = 0;   // no kernel of this stream writes it before the loop
+  // the fused preconditioner adds into w; later iterations find it cleared by the update
+  HIPCHECK(hipMemsetAsync(d.w, 0, size_t(vs) * sizeof(double2), s));
   hipEvent_t ev[2];
   HIPCHECK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
   HIPCHECK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));

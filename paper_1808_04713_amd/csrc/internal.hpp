@@ -90,6 +90,13 @@ struct SlotIn {
   double a0, a1;
   int s0, s1;
 };
+// Per-slot output scatter of the preconditioner fused with the row gather: the
+// slot's value times coef is added to dual row `row` (each row has at most two
+// slots, so two additions onto zero give the same sum in either order).
+struct SlotOut {
+  double coef;
+  int row, pad;
+};
 
 struct Handle {
   // problem
@@ -184,6 +191,7 @@ struct Handle {
     int *elem_cls = nullptr, *order = nullptr, *slot_off = nullptr, *cm_off = nullptr;
     SlotBlock* slot_blk = nullptr;
     SlotIn* slot_in[3] = {nullptr, nullptr, nullptr};   // modes 0 (F), 1 (P, rows), 2 (P, slots)
+    SlotOut* slot_out = nullptr;
     int64_t* dof_off = nullptr;
     int *row_slot = nullptr, *slot_row = nullptr, *slot_mode = nullptr;
     int64_t *slot_pos = nullptr, *cm_pos = nullptr;   // positions in full-element arrays

@@ -112,6 +112,50 @@ __global__ void __launch_bounds__(NT) k_slot_apply(const SlotBlock* __restrict__
   }
 }
 
+// The preconditioner on dual slots (S_e on the jumps C_1 z of each element's
+// slots) with the row gather fused: every output slot adds its value times its
+// row coefficient into the dual row.  A row has at most two slots and out is
+// zero on entry, so the two additions give the same sum in either order.
+__global__ void __launch_bounds__(NT) k_slot_apply_rows(const SlotBlock* __restrict__ blk,
+                                                        const SlotIn* __restrict__ sin,
+                                                        const SlotOut* __restrict__ sout,
+                                                        const double2* __restrict__ se,
+                                                        const double2* __restrict__ v, double2* __restrict__ out,
+                                                        int R) {
+  __shared__ double2 y[MMAX * RC];
+  const SlotBlock B = blk[blockIdx.x];
+  const int m = B.m, so = B.so;
+  const int r0 = blockIdx.y * RC;
+  const int rc = min(RC, R - r0);
+  for (int idx = threadIdx.x; idx < m * rc; idx += NT) {
+    const int sl = idx / rc, r = idx - sl * rc;
+    const SlotIn g = sin[so + sl];
+    double ax = 0, ay = 0;
+    if (g.s0 >= 0) {
+      const double2 z = v[(int64_t)g.s0 * R + r0 + r];
+      ax += g.a0 * z.x;
+      ay += g.a0 * z.y;
+    }
+    if (g.s1 >= 0) {
+      const double2 z = v[(int64_t)g.s1 * R + r0 + r];
+      ax += g.a1 * z.x;
+      ay += g.a1 * z.y;
+    }
+    y[sl * RC + r] = make_double2(ax, ay);
+  }
+  __syncthreads();
+  const double2* A = se + B.se;
+  for (int idx = threadIdx.x; idx < m * rc; idx += NT) {
+    const int i = idx / rc, r = idx - i * rc;
+    double2 acc = make_double2(0, 0);
+    for (int kk = 0; kk < m; ++kk) acc = cfma(A[i + (int64_t)m * kk], y[kk * RC + r], acc);
+    const SlotOut o = sout[so + i];
+    double2* p = out + (int64_t)o.row * R + r0 + r;
+    unsafeAtomicAdd(&p->x, o.coef * acc.x);
+    unsafeAtomicAdd(&p->y, o.coef * acc.y);
+  }
+}
+
 template <class T2>
 __global__ void __launch_bounds__(NT) k_slot_coarse(const SlotBlock* __restrict__ blk, const T2* __restrict__ phi,
                                                     const int* __restrict__ t_ptr, const int* __restrict__ t_dof,
@@ -2123,7 +2167,7 @@ __device__ void first_pass_rows(int j, int R, int maxvec, const double2* __restr
 // fourth basis vector.
 __global__ void __launch_bounds__(NT) k_dupdate_split(double2* __restrict__ V, int64_t vs,
                                                       const int* __restrict__ jptr, const double2* __restrict__ uc,
-                                                      const double2* __restrict__ z, int n, int R,
+                                                      double2* __restrict__ z, int n, int R,
                                                       double2* __restrict__ out2, const double2* __restrict__ Hraw,
                                                       double2* __restrict__ hprev, int maxvec) {
   __shared__ double2 red[2][NT / 64][64];
@@ -2164,13 +2208,14 @@ __global__ void __launch_bounds__(NT) k_dupdate_split(double2* __restrict__ V, i
     V[(int64_t)j * vs + idx] = q;
     V[(int64_t)(j + 1) * vs + idx] = un;
     if (out2) out2[idx] = un;
+    z[idx] = make_double2(0, 0);   // cleared for the next operator output (added into)
   }
   first_pass_rows(j, R, maxvec, Hraw, uc, hprev, red1);
 }
 
 // the same for long vectors: one thread per entry over all basis vectors
 __global__ void __launch_bounds__(NT) k_dupdate(double2* __restrict__ V, int64_t vs, const int* __restrict__ jptr,
-                                                const double2* __restrict__ uc, const double2* __restrict__ z, int n,
+                                                const double2* __restrict__ uc, double2* __restrict__ z, int n,
                                                 int R, double2* __restrict__ out2, const double2* __restrict__ Hraw,
                                                 double2* __restrict__ hprev, int maxvec) {
   __shared__ double2 red1[NT / 64];
@@ -2196,6 +2241,7 @@ __global__ void __launch_bounds__(NT) k_dupdate(double2* __restrict__ V, int64_t
     V[(int64_t)j * vs + idx] = q;
     V[(int64_t)(j + 1) * vs + idx] = un;
     if (out2) out2[idx] = un;
+    z[idx] = make_double2(0, 0);
   }
   first_pass_rows(j, R, maxvec, Hraw, uc, hprev, red1);
 }
@@ -2241,6 +2287,15 @@ static size_t slot_mfma_lds(const Handle& h, int R, int mode) {
   const size_t lds = size_t(rows) * rb * sizeof(double2);
   if (lds > SLOT_MF_LDS || ((rows + 15) / 16) * (rb / 16) > 16) return 0;
   return lds;
+}
+
+bool slot_rows_fused(const Handle& h, int R) { return !h.nonconforming && R < 16; }
+
+void launch_slot_apply_rows(const Handle& h, const double2* v, double2* out, int R, hipStream_t s) {
+  const auto& d = h.d;
+  hipLaunchKernelGGL(k_slot_apply_rows, dim3(h.E, (R + RC - 1) / RC), dim3(NT), 0, s, d.slot_blk, d.slot_in[2],
+                     d.slot_out, d.se, v, out, R);
+  HIPCHECK(hipGetLastError());
 }
 
 template <class T2>
@@ -2535,7 +2590,7 @@ void launch_dcgs_scalar(int* jptr, const double2* D, double2* Hraw, const double
   HIPCHECK(hipGetLastError());
 }
 
-void launch_dupdate(double2* V, int64_t vs, const int* jptr, const double2* uc, const double2* z, int n, int R,
+void launch_dupdate(double2* V, int64_t vs, const int* jptr, const double2* uc, double2* z, int n, int R,
                     double2* out2, const double2* Hraw, double2* hprev, int maxvec, hipStream_t s) {
   if (int64_t(n) * R <= UPD_SPLIT_MAX)
     hipLaunchKernelGGL(k_dupdate_split, dim3(nblocks(int64_t(n) * R, 64)), dim3(NT), 0, s, V, vs, jptr, uc, z, n, R,

@@ -13,6 +13,10 @@ struct Handle;
 // mode 0: X = D_c y, GL = Phi_c^T y, with y_s = coef_s v[row_s]            (F, first half)
 // mode 1: X = Se y with y_s = coef_s v[row_s] / (C1 C1^T)_row              (P^-1, first half)
 // mode 2: as mode 1 with v a dual-slot array z and v[row] = (C_1 z)[row]     (P^-1 F, fused)
+// the preconditioner on dual slots with its row gather fused (FP64, R < 16,
+// conforming meshes): out must be zero on entry
+bool slot_rows_fused(const Handle& h, int R);
+void launch_slot_apply_rows(const Handle& h, const double2* v, double2* out, int R, hipStream_t s);
 template <class T2>
 void launch_slot_apply(const Handle& h, int mode, const T2* v, T2* X, T2* GL, int R, hipStream_t s);
 // Z = X + Phi_c (T_e w)
@@ -136,7 +140,7 @@ void launch_dcgs_scalar(int* jptr, const double2* D, double2* Hraw, const double
                         double2* H, double2* cs, double2* sn, double2* g, const double* beta, int* done, int* iters,
                         double* resid, double tol, int maxvec, int R, int* counter, int* status, double* hist,
                         hipStream_t s);
-void launch_dupdate(double2* V, int64_t vs, const int* jptr, const double2* uc, const double2* z, int n, int R,
+void launch_dupdate(double2* V, int64_t vs, const int* jptr, const double2* uc, double2* z, int n, int R,
                     double2* out2, const double2* Hraw, double2* hprev, int maxvec, hipStream_t s);
 void launch_gmres_init(const double* nrm, double* beta, double2* g, int* done, int* iters, double* resid, int* jptr,
                        int* counter, int* status, int R, double* hist, hipStream_t s);
