@@ -771,6 +771,18 @@ static void apply_F_slots(Handle& h, const double2* v, int R, int prec) {
     else launch_assemble<float2>(h, d.cmA_f, nullptr, v, 1.0, d.gK, R, s);
   }
   {
+    if (slot_coarse_from_tiles(h, R)) {
+      // the tiled coarse apply's partial sums go straight into the coarse
+      // correction of the slots (no row-sum kernel)
+      {
+        Timed t(h, KF_COARSE, h.coarse_bytes1 + 16.0 * nK, h.coarse_flops);
+        launch_coarse_symv_tiles(h, d.gK, s);
+      }
+      Timed t(h, KF_SLOT_COARSE, nsl * cw * 2 + ncm * c + ob * h.phi_bytes, h.flops_coarse * R);
+      if (prec == HDP_FP64) launch_slot_coarse_sym<double2>(h, d.slotA, d.slotB, s);
+      else launch_slot_coarse_sym<float2>(h, d.slotA_f, d.slotB_f, s);
+      return;
+    }
     coarse_solve_timed(h, d.gK, d.wK, R);
   }
   {

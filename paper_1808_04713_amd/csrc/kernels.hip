@@ -296,6 +296,58 @@ __global__ void __launch_bounds__(NT) k_slot_mfma(const SlotBlock* __restrict__ 
   }
 }
 
+// k_slot_coarse with the coarse solution taken straight from the partial sums
+// of the tiled coarse apply (one right-hand side): w[d] = sum_J P[d / 64][J][d % 64],
+// each coarse mode's sum split over SCP thread groups and added in a fixed
+// order, so the row-sum kernel is not needed.
+constexpr int SCP = 16;
+constexpr int SYM_TILE = 64;   // tile edge of the symmetric coarse inverse
+
+template <class T2>
+__global__ void __launch_bounds__(NT) k_slot_coarse_sym(const SlotBlock* __restrict__ blk, const T2* __restrict__ phi,
+                                                        const int* __restrict__ t_ptr, const int* __restrict__ t_dof,
+                                                        const double* __restrict__ t_coef,
+                                                        const T2* __restrict__ X, const double2* __restrict__ P,
+                                                        int nt, T2* __restrict__ Z) {
+  extern __shared__ double2 part[];   // nr x SCP partial sums of the largest class
+  __shared__ T2 we[NRMAX];
+  const SlotBlock B = blk[blockIdx.x];
+  const int m = B.m, nr = B.nr, co = B.cmo, so = B.so;
+  for (int idx = threadIdx.x; idx < nr * SCP; idx += NT) {
+    const int j = idx / SCP, q = idx - j * SCP;
+    double ax = 0, ay = 0;
+    for (int t = t_ptr[co + j]; t < t_ptr[co + j + 1]; ++t) {
+      const int dof = t_dof[t];
+      const double2* Pr = P + (int64_t)(dof / SYM_TILE) * nt * SYM_TILE + dof % SYM_TILE;
+      double sx = 0, sy = 0;
+      for (int J = q; J < nt; J += SCP) {
+        const double2 a = Pr[(int64_t)J * SYM_TILE];
+        sx += a.x;
+        sy += a.y;
+      }
+      ax += t_coef[t] * sx;
+      ay += t_coef[t] * sy;
+    }
+    part[idx] = make_double2(ax, ay);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < nr; j += NT) {
+    double ax = 0, ay = 0;
+    for (int q = 0; q < SCP; ++q) {
+      ax += part[j * SCP + q].x;
+      ay += part[j * SCP + q].y;
+    }
+    we[j] = mk<T2>(ax, ay);
+  }
+  __syncthreads();
+  const T2* Pm = phi + B.phi;
+  for (int i = threadIdx.x; i < m; i += NT) {
+    T2 acc = X[so + i];
+    for (int j = 0; j < nr; ++j) acc = cfma(Pm[i + (int64_t)m * j], we[j], acc);
+    Z[so + i] = acc;
+  }
+}
+
 // u[row] = scale_row * (sum coef * src[pos(slot)] + sum_{C_2} coef * w[dof])
 template <class T2>
 __global__ void k_rowgather(int nlam, const int* __restrict__ row_slot, const double* __restrict__ row_coef,
@@ -902,7 +954,6 @@ __global__ void __launch_bounds__(NT) k_coarse_gemv(int nK, const double2* __res
 // contributions to fixed places of a partial buffer P[row tile][column tile][64];
 // a second kernel adds them per row in a fixed order (no atomics, so repeated
 // solves give identical results).
-constexpr int SYM_TILE = 64;
 
 // Packs the upper tiles of K^-1 from the dense row-major inverse, taking
 // (A_ij + A_ji) / 2 (the computed inverse is symmetric up to rounding) and
@@ -2329,6 +2380,25 @@ void launch_slot_apply(const Handle& h, int mode, const T2* v, T2* X, T2* GL, in
 #undef HDP_SLOT_ARGS
   HIPCHECK(hipGetLastError());
 }
+
+bool slot_coarse_from_tiles(const Handle& h, int R) {
+  return R == 1 && h.coarse_mode == 0 && h.d.Ksym && !h.coarse_refine && !h.nonconforming;
+}
+
+template <class T2>
+void launch_slot_coarse_sym(const Handle& h, const T2* X, T2* Z, hipStream_t s) {
+  const auto& d = h.d;
+  const T2* phi;
+  if constexpr (std::is_same<T2, double2>::value) phi = d.phi; else phi = d.phi_f;
+  int nrmax = 1;
+  for (auto& C : h.classes) nrmax = std::max(nrmax, C.nr);
+  const size_t shm = size_t(nrmax) * SCP * sizeof(double2);
+  hipLaunchKernelGGL((k_slot_coarse_sym<T2>), dim3(h.E), dim3(NT), shm, s, d.slot_blk, phi, d.t_ptr, d.t_dof,
+                     d.t_coef, X, d.sym_part, h.sym_nt, Z);
+  HIPCHECK(hipGetLastError());
+}
+template void launch_slot_coarse_sym<double2>(const Handle&, const double2*, double2*, hipStream_t);
+template void launch_slot_coarse_sym<float2>(const Handle&, const float2*, float2*, hipStream_t);
 
 template <class T2>
 void launch_slot_coarse(const Handle& h, const T2* X, const double2* w, T2* Z, int R, hipStream_t s) {

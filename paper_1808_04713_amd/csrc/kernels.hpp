@@ -17,6 +17,12 @@ struct Handle;
 // conforming meshes): out must be zero on entry
 bool slot_rows_fused(const Handle& h, int R);
 void launch_slot_apply_rows(const Handle& h, const double2* v, double2* out, int R, hipStream_t s);
+// k_slot_coarse reading the coarse solution from the partial sums of the tiled
+// coarse apply (one right-hand side, dense coarse inverse, no refinement,
+// conforming mesh): the row-sum kernel is skipped
+bool slot_coarse_from_tiles(const Handle& h, int R);
+template <class T2>
+void launch_slot_coarse_sym(const Handle& h, const T2* X, T2* Z, hipStream_t s);
 template <class T2>
 void launch_slot_apply(const Handle& h, int mode, const T2* v, T2* X, T2* GL, int R, hipStream_t s);
 // Z = X + Phi_c (T_e w)
