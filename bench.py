@@ -32,7 +32,7 @@ HBM_FAMILIES = {"coarse_gemv", "coarse_reduce", "coarse_assemble", "row_gather",
 # HBM bytes per launch of a kernel family on the point-source workload, from the
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs calibrated on a plain 512 MiB copy
 # (profiles/point_source_32x32_kernel_stats.md); valid for the kernels as profiled
-MEASURED_TRAFFIC = {"coarse_gemv": 9.0395e7, "gmres_dots": 3.1974e7}
+MEASURED_TRAFFIC = {"coarse_gemv": 9.0412e7, "gmres_dots": 3.1957e7}
 
 
 def load_samples():
