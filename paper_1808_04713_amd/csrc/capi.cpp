@@ -849,7 +849,7 @@ void apply_P(Handle& h, const double2* v, double2* u, int R, int prec) {
     // P^-1 = X^-1 Y X^-1: X is diagonal except for dense blocks on the hanging
     // rows, whose scale factor is 1 in row_xinv; first s = X^-1 v there
     Timed t(h, KF_HBLOCK, hb_bytes + 2 * nh * c + nl * 2 * c, 2.0 * h.hb_xinv.size() * 2 * R);
-    HIPCHECK(hipMemcpyAsync(d.pv, v, size_t(h.nlam) * R * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    launch_axpby(v, v, d.pv, int64_t(h.nlam) * R, 1.0, 0.0, s);   // a copy by kernel (capturable)
     launch_hblock(h, false, v, true, nullptr, d.pv, true, R, s);
     v = d.pv;
   }
@@ -980,8 +980,9 @@ GmresResult gmres(Handle& h, const double2* rhs, double2* x, int R, int prec, do
     };
     // one GMRES iteration as a captured graph (every launch reads j on the device)
     hipGraphExec_t exec = nullptr;
-    // captured only when no library routine is in the loop (dense GEMV coarse solve)
-    const bool graph = h.use_graphs && !h.prof.on && h.coarse_mode == 0 && R < 4;
+    // captured only when no library routine is in the loop: the dense inverse at
+    // fewer than 4 columns and the nested-dissection sweeps
+    const bool graph = h.use_graphs && !h.prof.on && (h.coarse_mode == 0 || h.coarse_mode == 2) && R < 4;
     if (graph) {
       auto key = std::make_tuple(R, prec, tol);
       auto itg = h.graphs.find(key);

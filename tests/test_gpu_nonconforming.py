@@ -179,3 +179,26 @@ def test_factored_coarse_on_hanging_meshes(name, coarse, literal):
     ref = np.concatenate(pb.gll_field(disc.mesh, disc.degrees, D.solve(tol=1e-12, max_iter=400)))
     assert rel(field.cpu().numpy()[0], ref) < 1e-10
     s.close()
+
+
+def test_graph_replays_match_eager_launches_with_nested_dissection():
+    """On a hanging mesh with the nested-dissection coarse factor the GMRES
+    iteration is replayed as a captured graph (fill kernels, no library calls):
+    the same iterations and field as launching every kernel, over several solves
+    with other work in between."""
+    w = CASES["disk_6x6_p3to6"]
+    kind, vals = hdp().rhs_values(w)
+    sg = hdp().Solver(w, tol=1e-11, max_iter=400, coarse="nd", graphs=True)
+    se = hdp().Solver(w, tol=1e-11, max_iter=400, coarse="nd", graphs=False)
+    ref, st_ref = se.solve(kind, vals)
+    ref = ref.cpu().numpy()
+    rng = np.random.default_rng(5)
+    for rep in range(3):
+        v = torch.from_numpy(rng.standard_normal((sg.n_lambda, 1)) + 0j).cuda()
+        sg.apply_interface(v)
+        torch.cuda.synchronize()
+        f, st = sg.solve(kind, vals)
+        assert st["iterations"] == st_ref["iterations"]
+        assert rel(f.cpu().numpy(), ref) < 1e-13
+    sg.close()
+    se.close()
