@@ -644,7 +644,7 @@ void build_device(Handle& h) {
   // the iteration status: written by the device straight into coherent pinned
   // host memory, read by the host after the iteration's event
   void* ph = nullptr;
-  HIPCHECK(hipHostMalloc(&ph, 4 * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
+  HIPCHECK(hipHostMalloc(&ph, 2 * STATUS_SLOTS * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
   d.status_host = static_cast<int*>(ph);
   void* pd = nullptr;
   HIPCHECK(hipHostGetDevicePointer(&pd, ph, 0));
@@ -949,12 +949,14 @@ GmresResult gmres(Handle& h, const double2* rhs, double2* x, int R, int prec, do
     launch_normalize(d.w, n, R, gd, d.npart, d.nrm, d.V_kry, nullptr, vs, d.vcur, s);
   }
   launch_gmres_init(d.nrm, d.beta, d.gvec, d.done, d.iters, d.resid, d.jdev, d.counter, d.status, R, d.hist, s);
-  for (int q = 0; q < 4; ++q) d.status_host[q] = 0;   // no kernel of this stream writes it before the loop
+  for (int q = 0; q < 2 * STATUS_SLOTS; ++q) d.status_host[q] = 0;   // no kernel of this stream writes it yet
   // the fused preconditioner adds into w; later iterations find it cleared by the update
   HIPCHECK(hipMemsetAsync(d.w, 0, size_t(vs) * sizeof(double2), s));
-  hipEvent_t ev[2];
-  HIPCHECK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-  HIPCHECK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  // up to GMRES_AHEAD iterations are queued beyond the one whose status the
+  // host reads; the device writes the status of iteration j to slot j mod
+  // STATUS_SLOTS (more slots than iterations in flight)
+  hipEvent_t ev[STATUS_SLOTS];
+  for (int q = 0; q < STATUS_SLOTS; ++q) HIPCHECK(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming));
   int launched = 0;
   try {
     const int dstride = 2 * maxvec + 2;
@@ -1005,25 +1007,23 @@ GmresResult gmres(Handle& h, const double2* rhs, double2* x, int R, int prec, do
       auto t0 = clk::now();
       if (graph) HIPCHECK(hipGraphLaunch(exec, s));
       else issue(it + 1);
-      HIPCHECK(hipEventRecord(ev[it & 1], s));
+      HIPCHECK(hipEventRecord(ev[it % STATUS_SLOTS], s));
       auto t1 = clk::now();
       h.t_launch += std::chrono::duration<double, std::milli>(t1 - t0).count();
       launched = it + 1;
-      if (it >= 1) {
-        HIPCHECK(hipEventSynchronize(ev[(it - 1) & 1]));
+      if (it >= GMRES_AHEAD) {
+        HIPCHECK(hipEventSynchronize(ev[(it - GMRES_AHEAD) % STATUS_SLOTS]));
         h.t_wait += std::chrono::duration<double, std::milli>(clk::now() - t1).count();
-        if (d.status_host[2 * ((it - 1) & 1)]) break;
+        if (d.status_host[2 * ((it - GMRES_AHEAD) % STATUS_SLOTS)]) break;
       }
     }
     HIPCHECK(hipStreamSynchronize(s));
   } catch (...) {
     (void)hipStreamSynchronize(s);
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
+    for (int q = 0; q < STATUS_SLOTS; ++q) (void)hipEventDestroy(ev[q]);
     throw;
   }
-  (void)hipEventDestroy(ev[0]);
-  (void)hipEventDestroy(ev[1]);
+  for (int q = 0; q < STATUS_SLOTS; ++q) (void)hipEventDestroy(ev[q]);
   prof_flush(h);
   std::vector<int> iters(R);
   std::vector<double> resid(R);

@@ -77,6 +77,14 @@ struct NDLevel {
   int fR = 0, nfR = 0, Sf = 1, bR = 0, nbR = 0, Sb = 1;   // first task, tiles, splits per tile
 };
 
+// GMRES on the device: iterations queued beyond the one whose status the host
+// reads (one keeps the GPU busy on the point source; two measured no faster and
+// cost one more iteration past convergence), and status slots in mapped host
+// memory (iteration j writes slot j mod STATUS_SLOTS; more slots than
+// iterations in flight).
+constexpr int GMRES_AHEAD = 1;
+constexpr int STATUS_SLOTS = 4;
+
 // Per-block record of the slot kernels (blocks follow the class-grouped element
 // order): the element, its class, slot and coarse-mode offsets and counts, and
 // the class's operator offsets, so that a block starts with one load.
@@ -261,7 +269,7 @@ struct Handle {
     double2 *vcur = nullptr, *Hdev = nullptr, *cs = nullptr, *sn = nullptr, *gvec = nullptr;
     double *beta = nullptr, *resid = nullptr, *hist = nullptr;   // hist: (max_iter+1) x R
     int *jdev = nullptr, *counter = nullptr, *status = nullptr, *done = nullptr, *iters = nullptr;
-    int* status_host = nullptr;   // pinned, mapped, coherent: 4 ints (two in-flight status slots)
+    int* status_host = nullptr;   // pinned, mapped, coherent: STATUS_SLOTS pairs of ints
     int* status_hdev = nullptr;   // the same memory as the device addresses it
     int* load_elems = nullptr;
     int64_t* load_off = nullptr;

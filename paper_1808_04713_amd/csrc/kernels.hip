@@ -1910,12 +1910,12 @@ __device__ void givens_column(int j, int r, const double2* hc, double sub, const
 
 // End of an iteration's scalar step: the last block to finish publishes
 // status = {all converged, jnext} and sets j = jnext.  The status goes to
-// host-mapped coherent memory (two slots, alternating with the iteration), so
-// the host reads it without a copy in the stream.
+// host-mapped coherent memory (slot jnext - 1 mod STATUS_SLOTS), so the host
+// reads it without a copy in the stream.
 __device__ void publish_step(int jnext, int* __restrict__ jptr, const int* __restrict__ done, int R,
                              int* __restrict__ counter, int* __restrict__ status) {
   __syncthreads();
-  int* st = status + 2 * ((jnext - 1) & 1);
+  int* st = status + 2 * ((jnext - 1) % STATUS_SLOTS);
   if (threadIdx.x == 0 && gridDim.x == 1) {
     // a single system: no other block to wait for (device-wide fences are costly
     // across the chip's separate L2 caches)
