@@ -285,8 +285,26 @@ static void build_coarse_nd(Handle& h, const std::vector<int64_t>& kidx, const s
   d.nd_mD = upload(h, f.mD);
   d.nd_mL = upload(h, f.mL);
   d.nd_mLt = upload(h, f.mLt);
-  d.nd_t1f = upload(h, f.t1f);
-  d.nd_t1b = upload(h, f.t1b);
+  {
+    // the one-column sweeps read flattened task records (same order as t1f / t1b)
+    std::vector<ND1Fwd> f1(f.t1f.size());
+    for (size_t q = 0; q < f.t1f.size(); ++q) {
+      const int t = f.t1f[q].x, b = f.t1f[q].y;
+      const int o = h.nd_off[t], nI = h.nd_off[t + 1] - o;
+      const int64_t u = f.uoff[t] + b;
+      f1[q] = ND1Fwd{f.mL[t] + int64_t(nI) * b, u, o, nI, f.push[u], 0};
+    }
+    std::vector<ND1Bwd> b1(f.t1b.size());
+    for (size_t q = 0; q < f.t1b.size(); ++q) {
+      const int t = f.t1b[q].x, i = f.t1b[q].y;
+      const int o = h.nd_off[t], nI = h.nd_off[t + 1] - o;
+      const int64_t bo = h.nd_boff[t];
+      const int nB = int(h.nd_boff[t + 1] - bo);
+      b1[q] = ND1Bwd{f.mD[t] + int64_t(nI) * i, f.mLt[t] + int64_t(nB) * i, bo, o, nI, nB, i};
+    }
+    d.nd_f1 = upload(h, f1);
+    d.nd_b1 = upload(h, b1);
+  }
   d.nd_tRf = upload(h, f.tRf);
   d.nd_tRb = upload(h, f.tRb);
   const size_t Rp = size_t(pow2ceil(h.max_rhs));
@@ -310,12 +328,12 @@ static void coarse_solve_nd(Handle& h, const double2* g, double2* w, int R) {
   const int nd = int(h.nd_levels.size());
   for (int L = nd - 1; L >= 0; --L) {   // leaves first
     const NDLevel& lv = h.nd_levels[L];
-    if (R == 1) launch_nd_fwd1(d.nd_t1f + lv.f1, lv.nf1, v, g, F, A, h.stream);
+    if (R == 1) launch_nd_fwd1(d.nd_f1 + lv.f1, lv.nf1, v, g, F, A, h.stream);
     else launch_nd_tiles(false, d.nd_tRf + lv.fR, lv.nfR, lv.Sf, v, g, F, A, w, R, d.nd_P, h.stream);
   }
   for (int L = 0; L < nd; ++L) {   // root first
     const NDLevel& lv = h.nd_levels[L];
-    if (R == 1) launch_nd_bwd1(d.nd_t1b + lv.b1, lv.nb1, v, g, F, w, h.stream);
+    if (R == 1) launch_nd_bwd1(d.nd_b1 + lv.b1, lv.nb1, v, g, F, w, h.stream);
     else launch_nd_tiles(true, d.nd_tRb + lv.bR, lv.nbR, lv.Sb, v, g, F, A, w, R, d.nd_P, h.stream);
   }
 }

@@ -77,6 +77,21 @@ struct NDLevel {
   int fR = 0, nfR = 0, Sf = 1, bR = 0, nbR = 0, Sb = 1;   // first task, tiles, splits per tile
 };
 
+// One-column sweep tasks with the node tables already looked up, so that a
+// wave starts from one record: forward (row b of node t's L and where its
+// update goes) and backward (row i of node t's D^-1 and L^T).
+struct ND1Fwd {
+  int64_t lrow;   // offset of L_t row b in the factor
+  int64_t u;      // update row of (t, b)
+  int o, nI;      // node's first unknown and count
+  int push, pad;  // destination of the update (as NDHost::push)
+};
+struct ND1Bwd {
+  int64_t drow, lrow;   // offsets of D^-1_t row i and L^T_t row i in the factor
+  int64_t bo;           // node's boundary list offset
+  int o, nI, nB, i;     // first unknown, count, boundary count, the row
+};
+
 // GMRES on the device: iterations queued beyond the one whose status the host
 // reads (one keeps the GPU busy on the point source; two measured no faster and
 // cost one more iteration past convergence), and status slots in mapped host
@@ -222,7 +237,8 @@ struct Handle {
     int *nd_off = nullptr, *nd_bnd = nullptr, *nd_push = nullptr;
     int64_t *nd_boff = nullptr, *nd_uoff = nullptr, *nd_mD = nullptr, *nd_mL = nullptr, *nd_mLt = nullptr;
     int64_t nd_urows = 0;
-    int2 *nd_t1f = nullptr, *nd_t1b = nullptr;
+    ND1Fwd* nd_f1 = nullptr;
+    ND1Bwd* nd_b1 = nullptr;
     // one step of iterative refinement of the coarse solve (when the factor alone
     // misses 1e-10): K in CSR by row, residual and correction buffers
     int64_t* k_ptr = nullptr;

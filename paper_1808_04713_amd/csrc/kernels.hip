@@ -602,15 +602,15 @@ struct NDNodes {
 };
 
 // One column: one wave per output row, lanes over the row.
-__global__ void __launch_bounds__(NT) k_nd_fwd1(const int2* __restrict__ task, int ntask, NDNodes nd,
-                                                const double2* __restrict__ g, double2* __restrict__ F,
-                                                double2* __restrict__ A) {
+__global__ void __launch_bounds__(NT) k_nd_fwd1(const ND1Fwd* __restrict__ task, int ntask,
+                                                const double2* __restrict__ fac, const double2* __restrict__ g,
+                                                double2* __restrict__ F, double2* __restrict__ A) {
   const int lane = threadIdx.x & 63;
   const int q = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
   if (q >= ntask) return;
-  const int t = task[q].x, b = task[q].y;
-  const int o = nd.off[t], nI = nd.off[t + 1] - o;
-  const double2* Lr = nd.fac + nd.mL[t] + (int64_t)nI * b;
+  const ND1Fwd tk = task[q];
+  const int o = tk.o, nI = tk.nI;
+  const double2* Lr = fac + tk.lrow;
   double ax = 0, ay = 0;
   for (int i = lane; i < nI; i += 64) {
     const double2 m = Lr[i], y0 = g[o + i], y1 = F[o + i];
@@ -623,24 +623,22 @@ __global__ void __launch_bounds__(NT) k_nd_fwd1(const int2* __restrict__ task, i
     ay += __shfl_xor(ay, sh, 64);
   }
   if (lane == 0) {
-    const int64_t u = nd.uoff[t] + b;
-    const double2 a = A[u];
-    nd_push(F, A, nd.push[u], 0, 1, make_double2(a.x - ax, a.y - ay));
+    const double2 a = A[tk.u];
+    nd_push(F, A, tk.push, 0, 1, make_double2(a.x - ax, a.y - ay));
   }
 }
 
-__global__ void __launch_bounds__(NT) k_nd_bwd1(const int2* __restrict__ task, int ntask, NDNodes nd,
+__global__ void __launch_bounds__(NT) k_nd_bwd1(const ND1Bwd* __restrict__ task, int ntask,
+                                                const double2* __restrict__ fac, const int* __restrict__ bnd,
                                                 const double2* __restrict__ g, const double2* __restrict__ F,
                                                 double2* __restrict__ X) {
   const int lane = threadIdx.x & 63;
   const int q = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
   if (q >= ntask) return;
-  const int t = task[q].x, i = task[q].y;
-  const int o = nd.off[t], nI = nd.off[t + 1] - o;
-  const int64_t bo = nd.boff[t];
-  const int nB = int(nd.boff[t + 1] - bo);
-  const double2* Dr = nd.fac + nd.mD[t] + (int64_t)nI * i;
-  const double2* Lr = nd.fac + nd.mLt[t] + (int64_t)nB * i;
+  const ND1Bwd tk = task[q];
+  const int o = tk.o, nI = tk.nI, nB = tk.nB;
+  const double2* Dr = fac + tk.drow;
+  const double2* Lr = fac + tk.lrow;
   double ax = 0, ay = 0;
   for (int k = lane; k < nI; k += 64) {
     const double2 m = Dr[k], y0 = g[o + k], y1 = F[o + k];
@@ -649,7 +647,7 @@ __global__ void __launch_bounds__(NT) k_nd_bwd1(const int2* __restrict__ task, i
     ay += m.x * yy + m.y * yx;
   }
   for (int b = lane; b < nB; b += 64) {
-    const double2 m = Lr[b], x = X[nd.bnd[bo + b]];
+    const double2 m = Lr[b], x = X[bnd[tk.bo + b]];
     ax -= m.x * x.x - m.y * x.y;
     ay -= m.x * x.y + m.y * x.x;
   }
@@ -657,7 +655,7 @@ __global__ void __launch_bounds__(NT) k_nd_bwd1(const int2* __restrict__ task, i
     ax += __shfl_xor(ax, sh, 64);
     ay += __shfl_xor(ay, sh, 64);
   }
-  if (lane == 0) X[o + i] = make_double2(ax, ay);
+  if (lane == 0) X[o + tk.i] = make_double2(ax, ay);
 }
 
 // Several columns (R <= 64, lane = column): a workgroup owns 32 outputs of a
@@ -2775,19 +2773,17 @@ void launch_fill_zero(double2* x, int64_t count, hipStream_t s) {
   HIPCHECK(hipGetLastError());
 }
 
-void launch_nd_fwd1(const int2* task, int ntask, const NDView& v, const double2* g, double2* F, double2* A,
+void launch_nd_fwd1(const ND1Fwd* task, int ntask, const NDView& v, const double2* g, double2* F, double2* A,
                     hipStream_t s) {
   if (ntask == 0) return;
-  const NDNodes nd{v.off, v.boff, v.bnd, v.uoff, v.push, v.mD, v.mL, v.mLt, v.fac};
-  hipLaunchKernelGGL(k_nd_fwd1, dim3(nblocks(ntask, NT / 64)), dim3(NT), 0, s, task, ntask, nd, g, F, A);
+  hipLaunchKernelGGL(k_nd_fwd1, dim3(nblocks(ntask, NT / 64)), dim3(NT), 0, s, task, ntask, v.fac, g, F, A);
   HIPCHECK(hipGetLastError());
 }
 
-void launch_nd_bwd1(const int2* task, int ntask, const NDView& v, const double2* g, const double2* F, double2* X,
+void launch_nd_bwd1(const ND1Bwd* task, int ntask, const NDView& v, const double2* g, const double2* F, double2* X,
                     hipStream_t s) {
   if (ntask == 0) return;
-  const NDNodes nd{v.off, v.boff, v.bnd, v.uoff, v.push, v.mD, v.mL, v.mLt, v.fac};
-  hipLaunchKernelGGL(k_nd_bwd1, dim3(nblocks(ntask, NT / 64)), dim3(NT), 0, s, task, ntask, nd, g, F, X);
+  hipLaunchKernelGGL(k_nd_bwd1, dim3(nblocks(ntask, NT / 64)), dim3(NT), 0, s, task, ntask, v.fac, v.bnd, g, F, X);
   HIPCHECK(hipGetLastError());
 }
 

@@ -87,9 +87,9 @@ struct NDView {
 };
 // one column: tasks {node, row}; forward U = A - L (g + F)_I pushed to the parent,
 // backward X_I = Dinv (g + F)_I - Lt X_B
-void launch_nd_fwd1(const int2* task, int ntask, const NDView& v, const double2* g, double2* F, double2* A,
+void launch_nd_fwd1(const ND1Fwd* task, int ntask, const NDView& v, const double2* g, double2* F, double2* A,
                     hipStream_t s);
-void launch_nd_bwd1(const int2* task, int ntask, const NDView& v, const double2* g, const double2* F, double2* X,
+void launch_nd_bwd1(const ND1Bwd* task, int ntask, const NDView& v, const double2* g, const double2* F, double2* X,
                     hipStream_t s);
 // several columns: ntiles output tiles of 32 rows, each split into S tasks
 // {node, first row, i0, i1} over the summation; with S > 1 the partial tiles go
