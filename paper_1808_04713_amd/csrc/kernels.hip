@@ -382,6 +382,50 @@ __global__ void k_rowgather(int nlam, const int* __restrict__ row_slot, const do
   u[idx] = make_double2(ax, ay);
 }
 
+// The same at one right-hand side with one wave per coarse unknown, for meshes
+// with hanging edges: the lanes split the unknown's expansion and C_2 entries
+// (long there) and add them with shuffles, so no lane walks a long list alone.
+// (On conforming meshes the lists hold one to four entries and a thread per
+// unknown is faster.)
+template <class T2>
+__global__ void __launch_bounds__(NT) k_assemble1(int nK, const int* __restrict__ ptr, const int* __restrict__ list,
+                                                  const double* __restrict__ coef, const T2* __restrict__ GL,
+                                                  const int64_t* __restrict__ cm_pos,
+                                                  const double2* __restrict__ Bfull, const int* __restrict__ c2t_ptr,
+                                                  const int* __restrict__ c2t_row,
+                                                  const double* __restrict__ c2t_coef, const double2* __restrict__ v,
+                                                  double csign, double2* __restrict__ g) {
+  const int lane = threadIdx.x & 63;
+  const int d = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  if (d >= nK) return;
+  double ax = 0, ay = 0;
+  for (int t = ptr[d] + lane; t < ptr[d + 1]; t += 64) {
+    const int i = list[t];
+    const double c = coef[t];
+    if (GL) {
+      const T2 a = GL[i];
+      ax += c * double(a.x);
+      ay += c * double(a.y);
+    }
+    if (Bfull) {
+      const double2 b = Bfull[cm_pos[i]];
+      ax += c * b.x;
+      ay += c * b.y;
+    }
+  }
+  if (v)
+    for (int t = c2t_ptr[d] + lane; t < c2t_ptr[d + 1]; t += 64) {
+      const double2 a = v[c2t_row[t]];
+      ax += csign * c2t_coef[t] * a.x;
+      ay += csign * c2t_coef[t] * a.y;
+    }
+  for (int off = 32; off > 0; off >>= 1) {
+    ax += __shfl_xor(ax, off, 64);
+    ay += __shfl_xor(ay, off, 64);
+  }
+  if (lane == 0) g[d] = make_double2(ax, ay);
+}
+
 // g[d] = sum_{(i, c) in T^T} c (GL[i] + Bfull[pos(i)]) + csign sum_{(row, c) in C_2^T} c v[row]
 template <class T2>
 __global__ void k_assemble(int nK, const int* __restrict__ ptr, const int* __restrict__ list,
@@ -2434,6 +2478,12 @@ void launch_assemble(const Handle& h, const T2* GL, const double2* Bfull, const 
                      int R, hipStream_t s) {
   const auto& d = h.d;
   if (!h.nonconforming) v = nullptr;
+  if (R == 1 && h.nonconforming) {   // long expansion and C_2 lists on hanging edges
+    hipLaunchKernelGGL((k_assemble1<T2>), dim3(nblocks(h.nK, NT / 64)), dim3(NT), 0, s, h.nK, d.cdof_ptr, d.cdof_list,
+                       d.cdof_coef, GL, d.cm_pos, Bfull, d.c2t_ptr, d.c2t_row, d.c2t_coef, v, vsign, g);
+    HIPCHECK(hipGetLastError());
+    return;
+  }
   hipLaunchKernelGGL((k_assemble<T2>), dim3(nblocks(int64_t(h.nK) * R)), dim3(NT), 0, s, h.nK, d.cdof_ptr,
                      d.cdof_list, d.cdof_coef, GL, d.cm_pos, Bfull, d.c2t_ptr, d.c2t_row, d.c2t_coef, v, vsign, g,
                      R);
