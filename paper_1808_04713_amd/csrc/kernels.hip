@@ -166,15 +166,41 @@ __global__ void __launch_bounds__(NT) k_slot_coarse(const SlotBlock* __restrict_
   const int m = B.m, nr = B.nr, co = B.cmo, so = B.so;
   const int r0 = blockIdx.y * RC;
   const int rc = min(RC, R - r0);
-  for (int idx = threadIdx.x; idx < nr * rc; idx += NT) {
-    int j = idx / rc, r = idx - j * rc;
-    double ax = 0, ay = 0;
-    for (int t = t_ptr[co + j]; t < t_ptr[co + j + 1]; ++t) {
-      double2 a = w[(int64_t)t_dof[t] * R + r0 + r];
-      ax += t_coef[t] * a.x;
-      ay += t_coef[t] * a.y;
+  if (rc == 1) {
+    // one column: each coarse mode's expansion (long on hanging edges) is split
+    // over RC threads whose partial sums sit in we[j RC .. j RC + RC) and are
+    // added in order into we[j RC]
+    for (int idx = threadIdx.x; idx < nr * RC; idx += NT) {
+      const int j = idx / RC, q = idx - j * RC;
+      double ax = 0, ay = 0;
+      for (int t = t_ptr[co + j] + q; t < t_ptr[co + j + 1]; t += RC) {
+        const double2 a = w[(int64_t)t_dof[t] * R + r0];
+        ax += t_coef[t] * a.x;
+        ay += t_coef[t] * a.y;
+      }
+      we[idx] = mk<T2>(ax, ay);
     }
-    we[j * RC + r] = mk<T2>(ax, ay);
+    __syncthreads();
+    for (int j = threadIdx.x; j < nr; j += NT) {
+      T2 sum = we[j * RC];
+      for (int q = 1; q < RC; ++q) {
+        const T2 p = we[j * RC + q];
+        sum.x += p.x;
+        sum.y += p.y;
+      }
+      we[j * RC] = sum;
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < nr * rc; idx += NT) {
+      int j = idx / rc, r = idx - j * rc;
+      double ax = 0, ay = 0;
+      for (int t = t_ptr[co + j]; t < t_ptr[co + j + 1]; ++t) {
+        double2 a = w[(int64_t)t_dof[t] * R + r0 + r];
+        ax += t_coef[t] * a.x;
+        ay += t_coef[t] * a.y;
+      }
+      we[j * RC + r] = mk<T2>(ax, ay);
+    }
   }
   __syncthreads();
   const T2* P = phi + B.phi;
