@@ -676,11 +676,15 @@ __global__ void __launch_bounds__(NT) k_nd_fwd1(const ND1Fwd* __restrict__ task,
                                                 const double2* __restrict__ fac, const double2* __restrict__ g,
                                                 double2* __restrict__ F, double2* __restrict__ A) {
   const int lane = threadIdx.x & 63;
-  const int q = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  // the row is uniform over the wave: its record comes in through scalar loads
+  const int q = __builtin_amdgcn_readfirstlane(blockIdx.x * (NT / 64) + (threadIdx.x >> 6));
   if (q >= ntask) return;
   const ND1Fwd tk = task[q];
   const int o = tk.o, nI = tk.nI;
   const double2* Lr = fac + tk.lrow;
+  // the accumulated update row is read alongside the operands, not after the sum
+  double2 a = make_double2(0.0, 0.0);
+  if (lane == 0) a = A[tk.u];
   double ax = 0, ay = 0;
   for (int i = lane; i < nI; i += 64) {
     const double2 m = Lr[i], y0 = g[o + i], y1 = F[o + i];
@@ -692,10 +696,7 @@ __global__ void __launch_bounds__(NT) k_nd_fwd1(const ND1Fwd* __restrict__ task,
     ax += __shfl_xor(ax, sh, 64);
     ay += __shfl_xor(ay, sh, 64);
   }
-  if (lane == 0) {
-    const double2 a = A[tk.u];
-    nd_push(F, A, tk.push, 0, 1, make_double2(a.x - ax, a.y - ay));
-  }
+  if (lane == 0) nd_push(F, A, tk.push, 0, 1, make_double2(a.x - ax, a.y - ay));
 }
 
 __global__ void __launch_bounds__(NT) k_nd_bwd1(const ND1Bwd* __restrict__ task, int ntask,
@@ -703,20 +704,28 @@ __global__ void __launch_bounds__(NT) k_nd_bwd1(const ND1Bwd* __restrict__ task,
                                                 const double2* __restrict__ g, const double2* __restrict__ F,
                                                 double2* __restrict__ X) {
   const int lane = threadIdx.x & 63;
-  const int q = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  const int q = __builtin_amdgcn_readfirstlane(blockIdx.x * (NT / 64) + (threadIdx.x >> 6));
   if (q >= ntask) return;
   const ND1Bwd tk = task[q];
   const int o = tk.o, nI = tk.nI, nB = tk.nB;
   const double2* Dr = fac + tk.drow;
   const double2* Lr = fac + tk.lrow;
   double ax = 0, ay = 0;
+  // the first boundary gather (index, then value) is the longest chain: start it first
+  double2 m0 = make_double2(0.0, 0.0), x0 = make_double2(0.0, 0.0);
+  if (lane < nB) {
+    m0 = Lr[lane];
+    x0 = X[bnd[tk.bo + lane]];
+  }
   for (int k = lane; k < nI; k += 64) {
     const double2 m = Dr[k], y0 = g[o + k], y1 = F[o + k];
     const double yx = y0.x + y1.x, yy = y0.y + y1.y;
     ax += m.x * yx - m.y * yy;
     ay += m.x * yy + m.y * yx;
   }
-  for (int b = lane; b < nB; b += 64) {
+  ax -= m0.x * x0.x - m0.y * x0.y;
+  ay -= m0.x * x0.y + m0.y * x0.x;
+  for (int b = lane + 64; b < nB; b += 64) {
     const double2 m = Lr[b], x = X[bnd[tk.bo + b]];
     ax -= m.x * x.x - m.y * x.y;
     ay -= m.x * x.y + m.y * x.x;
