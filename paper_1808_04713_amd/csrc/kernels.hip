@@ -796,37 +796,52 @@ __device__ __forceinline__ void nd_mm_core_mfma(const double2* __restrict__ M, i
   const double2* mcol = M + (int64_t)K * (jv ? j : 0);
   d4 cr0 = {0, 0, 0, 0}, ci0 = {0, 0, 0, 0}, cr1 = {0, 0, 0, 0}, ci1 = {0, 0, 0, 0};
   if (act0) {
-    for (int k = i0; k < i1; k += 4) {
-      const int kk = k + kq;
-      const bool kv = kk < i1;
-      const double2 b = (kv && jv) ? mcol[kk] : make_double2(0, 0);
-      double2 a0 = make_double2(0, 0), a1 = make_double2(0, 0);
-      if (kv) {
-        const int64_t row = xidx ? (int64_t)xidx[kk] : xbase + kk;
+    // NU steps of 4 summation rows per pass: every operand load of the pass is
+    // issued before its matrix operations (rows past i1 read row i1 - 1, an
+    // entry in range, and are zeroed); the operations keep the one-step order
+    constexpr int NU = 2;
+    for (int k = i0; k < i1; k += 4 * NU) {
+      double2 b[NU], a0[NU], a1[NU];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const int kk = k + 4 * u + kq;
+        const bool kv = kk < i1;
+        const int kc = kv ? kk : i1 - 1;
+        b[u] = mcol[kc];
+        const int64_t row = xidx ? (int64_t)xidx[kc] : xbase + kc;
         const double2* xr = X + row * R + jl;
-        a0 = xr[16 * rt0];
-        if (act1) a1 = xr[16 * (rt0 + 1)];
+        a0[u] = xr[16 * rt0];
+        a1[u] = act1 ? xr[16 * (rt0 + 1)] : make_double2(0, 0);
         if (X2) {
           const double2* x2 = X2 + row * R + jl;
           const double2 c0 = x2[16 * rt0];
-          a0.x += c0.x;
-          a0.y += c0.y;
+          a0[u].x += c0.x;
+          a0[u].y += c0.y;
           if (act1) {
             const double2 c1 = x2[16 * (rt0 + 1)];
-            a1.x += c1.x;
-            a1.y += c1.y;
+            a1[u].x += c1.x;
+            a1[u].y += c1.y;
           }
         }
+        if (!(kv && jv)) b[u] = make_double2(0, 0);
+        if (!kv) {
+          a0[u] = make_double2(0, 0);
+          a1[u] = make_double2(0, 0);
+        }
       }
-      cr0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, b.x, cr0, 0, 0, 0);
-      ci0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, b.y, ci0, 0, 0, 0);
-      cr0 = __builtin_amdgcn_mfma_f64_16x16x4f64(-a0.y, b.y, cr0, 0, 0, 0);
-      ci0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.y, b.x, ci0, 0, 0, 0);
-      if (act1) {
-        cr1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.x, b.x, cr1, 0, 0, 0);
-        ci1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.x, b.y, ci1, 0, 0, 0);
-        cr1 = __builtin_amdgcn_mfma_f64_16x16x4f64(-a1.y, b.y, cr1, 0, 0, 0);
-        ci1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.y, b.x, ci1, 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        if (k + 4 * u >= i1) break;   // a step wholly past the range (uniform)
+        cr0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u].x, b[u].x, cr0, 0, 0, 0);
+        ci0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u].x, b[u].y, ci0, 0, 0, 0);
+        cr0 = __builtin_amdgcn_mfma_f64_16x16x4f64(-a0[u].y, b[u].y, cr0, 0, 0, 0);
+        ci0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u].y, b[u].x, ci0, 0, 0, 0);
+        if (act1) {
+          cr1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u].x, b[u].x, cr1, 0, 0, 0);
+          ci1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u].x, b[u].y, ci1, 0, 0, 0);
+          cr1 = __builtin_amdgcn_mfma_f64_16x16x4f64(-a1[u].y, b[u].y, cr1, 0, 0, 0);
+          ci1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u].y, b[u].x, ci1, 0, 0, 0);
+        }
       }
     }
     double2* dj = Dt + (16 * jt + jl) * 64;
