@@ -894,20 +894,22 @@ void apply_P(Handle& h, const double2* v, double2* u, int R, int prec) {
 }
 
 // Solve A^ [x_I; x_R] = [y_I; y_R] element-wise (eq. block_matrix_inversion):
-// X holds y_I on entry (coarse modes ignored) and the element solution on exit;
-// y_R is assembled from Bfull's coarse modes (or zero when Bfull is null),
-// minus C_2^T nu when nu is given.
-void element_solve(Handle& h, double2* X, const double2* Bfull, const double2* nu, int R) {
+// y_I is read from Y (coarse modes ignored), or from X itself when Y is null;
+// X receives the element solution; y_R is assembled from Bfull's coarse modes
+// (or zero when Bfull is null), minus C_2^T nu when nu is given.
+void element_solve(Handle& h, double2* X, const double2* Bfull, const double2* nu, int R,
+                   const double2* Y = nullptr) {
   auto& d = h.d;
   hipStream_t s = h.stream;
   const double c = 16.0 * R, dof = double(h.dof), ncm = h.ncm, nK = h.nK;
-  {
+  if (!Y) {
     Timed t(h, KF_ELEMENT_MISC, ncm * c, 0);
     launch_zero_R(h, X, R, s);
   }
   {
     Timed t(h, KF_FDM, 2 * dof * c, h.flops_fdm * R);
-    launch_fdm(h, X, X, R, s);
+    if (Y) launch_fdm(h, Y, X, R, s, true);   // out of place, coarse modes read as zero
+    else launch_fdm(h, X, X, R, s);
   }
   {
     Timed t(h, KF_ELEMENT_MISC, 2 * ncm * c, 0);
@@ -929,9 +931,7 @@ void element_solve(Handle& h, double2* X, const double2* Bfull, const double2* n
 // Interface right-hand side g = C_1 x_I with x_I from the element loads in full0.
 void interface_rhs(Handle& h, double2* g, int R) {
   auto& d = h.d;
-  HIPCHECK(hipMemcpyAsync(d.full1, d.full0, size_t(h.dof) * R * sizeof(double2), hipMemcpyDeviceToDevice,
-                          h.stream));
-  element_solve(h, d.full1, d.full0, nullptr, R);
+  element_solve(h, d.full1, d.full0, nullptr, R, d.full0);
   Timed t(h, KF_ROWGATHER, h.nslots * 16.0 * R + h.nlam * 16.0 * R, 0);
   launch_rowgather<double2>(h, d.full1, true, false, d.wK, g, R, h.stream);   // C_1 x_1 + C_2 x_2
 }

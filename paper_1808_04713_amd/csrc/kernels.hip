@@ -1196,7 +1196,9 @@ __global__ void __launch_bounds__(NT) k_fdm(const int* __restrict__ elem_cls, co
                                             const int64_t* __restrict__ cls_D, const double2* __restrict__ Ex,
                                             const double2* __restrict__ Ey, const double2* __restrict__ Dinv,
                                             const double2* __restrict__ in, double2* __restrict__ out, int R,
-                                            int RCH) {
+                                            int RCH, const int* __restrict__ cls_nr,
+                                            const int* __restrict__ cls_Rm, const int* __restrict__ r_modes,
+                                            int zero_coarse) {
   extern __shared__ double2 sm[];
   const int e = blockIdx.x;
   const int r0 = blockIdx.y * RCH;
@@ -1230,6 +1232,15 @@ __global__ void __launch_bounds__(NT) k_fdm(const int* __restrict__ elem_cls, co
     A[idx] = in[(base + t) * R + r0 + r];
   }
   __syncthreads();
+  if (zero_coarse) {   // uniform over the grid
+    const int nr = cls_nr[c];
+    const int* rm = r_modes + cls_Rm[c];
+    for (int idx = threadIdx.x; idx < nr * rc; idx += NT) {
+      const int a = idx / rc, r = idx - a * rc;
+      A[rm[a] * rc + r] = make_double2(0, 0);
+    }
+    __syncthreads();
+  }
   // B = Ex^T A
   for (int idx = threadIdx.x; idx < nt; idx += NT) {
     const int t = idx / rc, r = idx - t * rc, i = t % n, j = t / n;
@@ -2629,7 +2640,7 @@ static int fdm_chunk(const Handle& h, int R, bool staged) {
   return rch;
 }
 
-void launch_fdm(const Handle& h, const double2* in, double2* out, int R, hipStream_t s) {
+void launch_fdm(const Handle& h, const double2* in, double2* out, int R, hipStream_t s, bool zero_coarse) {
   int nmax = 0;
   for (auto& C : h.classes) nmax = std::max(nmax, C.n);
   const bool staged = size_t(nmax) * nmax * 5 * sizeof(double2) <= 65536;
@@ -2637,12 +2648,13 @@ void launch_fdm(const Handle& h, const double2* in, double2* out, int R, hipStre
   const size_t shm = size_t(nmax) * nmax * (2 * rch + (staged ? 3 : 0)) * sizeof(double2);
   const auto& d = h.d;
   const dim3 grid(h.E, (R + rch - 1) / rch);
+  const int zc = zero_coarse ? 1 : 0;
   if (staged)
     hipLaunchKernelGGL(k_fdm<true>, grid, dim3(NT), shm, s, d.elem_cls, d.dof_off, d.cls_n, d.cls_E, d.cls_D, d.Ex,
-                       d.Ey, d.Dinv, in, out, R, rch);
+                       d.Ey, d.Dinv, in, out, R, rch, d.cls_nr, d.cls_R, d.r_modes, zc);
   else
     hipLaunchKernelGGL(k_fdm<false>, grid, dim3(NT), shm, s, d.elem_cls, d.dof_off, d.cls_n, d.cls_E, d.cls_D, d.Ex,
-                       d.Ey, d.Dinv, in, out, R, rch);
+                       d.Ey, d.Dinv, in, out, R, rch, d.cls_nr, d.cls_R, d.r_modes, zc);
   HIPCHECK(hipGetLastError());
 }
 

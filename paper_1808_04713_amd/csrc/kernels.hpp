@@ -52,7 +52,9 @@ void launch_strip_step(const double2* M, int K, const double2* in, int n_out, co
 void launch_strip_diag64(const Handle& h, const double2* g, double2* w, hipStream_t s);
 
 // Full-element operations (arrays [dof][R])
-void launch_fdm(const Handle& h, const double2* in, double2* out, int R, hipStream_t s);
+// With zero_coarse the element's coarse-mode entries of `in` are read as zero
+// (the solve of the interior problem from a full load vector, out of place).
+void launch_fdm(const Handle& h, const double2* in, double2* out, int R, hipStream_t s, bool zero_coarse = false);
 void launch_zero_R(const Handle& h, double2* X, int R, hipStream_t s);
 void launch_extract_kc(const Handle& h, const double2* X, double2* GL, int R, hipStream_t s);
 void launch_correct(const Handle& h, double2* X, const double2* w, int R, hipStream_t s);
