@@ -894,9 +894,10 @@ void apply_P(Handle& h, const double2* v, double2* u, int R, int prec) {
 }
 
 // Solve A^ [x_I; x_R] = [y_I; y_R] element-wise (eq. block_matrix_inversion):
-// y_I is read from Y (coarse modes ignored), or from X itself when Y is null;
-// X receives the element solution; y_R is assembled from Bfull's coarse modes
-// (or zero when Bfull is null), minus C_2^T nu when nu is given.
+// y_I is read from Y (coarse modes ignored; with nu, C_1^T nu subtracted at the
+// dual slots), or from X itself when Y is null; X receives the element
+// solution; y_R is assembled from Bfull's coarse modes (or zero when Bfull is
+// null), minus C_2^T nu when nu is given.
 void element_solve(Handle& h, double2* X, const double2* Bfull, const double2* nu, int R,
                    const double2* Y = nullptr) {
   auto& d = h.d;
@@ -908,7 +909,7 @@ void element_solve(Handle& h, double2* X, const double2* Bfull, const double2* n
   }
   {
     Timed t(h, KF_FDM, 2 * dof * c, h.flops_fdm * R);
-    if (Y) launch_fdm(h, Y, X, R, s, true);   // out of place, coarse modes read as zero
+    if (Y) launch_fdm(h, Y, X, R, s, true, nu);   // out of place, coarse modes read as zero
     else launch_fdm(h, X, X, R, s);
   }
   {
@@ -1484,9 +1485,7 @@ static SolveOut solve_core(Handle& h, const hdp_rhs* rhs, int R, int Rp) {
   }
   o.t_rec0 = std::chrono::steady_clock::now();
   // recovery phi = A^-1 (b^ - C^T nu) (Sec. 2.3.1)
-  HIPCHECK(hipMemcpyAsync(d.full1, d.full0, size_t(h.dof) * Rp * sizeof(double2), hipMemcpyDeviceToDevice, s));
-  launch_sub_dual(h, d.full1, d.t2, Rp, s);
-  element_solve(h, d.full1, d.full0, d.t2, Rp);
+  element_solve(h, d.full1, d.full0, d.t2, Rp, d.full0);
   o.iters = iters;
   o.refinements = refinements;
   o.rel = rel;

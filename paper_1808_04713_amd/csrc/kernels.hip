@@ -1198,7 +1198,9 @@ __global__ void __launch_bounds__(NT) k_fdm(const int* __restrict__ elem_cls, co
                                             const double2* __restrict__ in, double2* __restrict__ out, int R,
                                             int RCH, const int* __restrict__ cls_nr,
                                             const int* __restrict__ cls_Rm, const int* __restrict__ r_modes,
-                                            int zero_coarse) {
+                                            int zero_coarse, const int* __restrict__ slot_off,
+                                            const int64_t* __restrict__ slot_pos, const int* __restrict__ slot_row,
+                                            const double* __restrict__ slot_coef, const double2* __restrict__ nu) {
   extern __shared__ double2 sm[];
   const int e = blockIdx.x;
   const int r0 = blockIdx.y * RCH;
@@ -1238,6 +1240,17 @@ __global__ void __launch_bounds__(NT) k_fdm(const int* __restrict__ elem_cls, co
     for (int idx = threadIdx.x; idx < nr * rc; idx += NT) {
       const int a = idx / rc, r = idx - a * rc;
       A[rm[a] * rc + r] = make_double2(0, 0);
+    }
+    if (nu) {   // the element's dual slots (distinct modes, none of them coarse)
+      const int s0 = slot_off[e], ns = slot_off[e + 1] - s0;
+      for (int idx = threadIdx.x; idx < ns * rc; idx += NT) {
+        const int q = idx / rc, r = idx - q * rc, sl = s0 + q;
+        const double2 a = nu[(int64_t)slot_row[sl] * R + r0 + r];
+        const double cf = slot_coef[sl];
+        double2& y = A[(int)(slot_pos[sl] - base) * rc + r];
+        y.x -= cf * a.x;
+        y.y -= cf * a.y;
+      }
     }
     __syncthreads();
   }
@@ -1363,20 +1376,6 @@ __global__ void __launch_bounds__(NT) k_correct(const int* __restrict__ elem_cls
     }
     X[(base + t) * R + r0 + r] = acc;
   }
-}
-
-// Y[pos(slot)] -= coef * nu[row(slot)]   (y_I = b_1 - C_1^T nu)
-__global__ void k_sub_dual(int nslots, const int64_t* __restrict__ slot_pos, const int* __restrict__ slot_row,
-                           const double* __restrict__ slot_coef, double2* __restrict__ Y,
-                           const double2* __restrict__ nu, int R) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)nslots * R) return;
-  int s = int(idx / R), r = int(idx - (int64_t)s * R);
-  double2 a = nu[(int64_t)slot_row[s] * R + r];
-  double cf = slot_coef[s];
-  double2& y = Y[slot_pos[s] * R + r];
-  y.x -= cf * a.x;
-  y.y -= cf * a.y;
 }
 
 // field = V X V^T at the GLL nodes of each element (V[i,a] = N~_a(t_i)).
@@ -2640,7 +2639,8 @@ static int fdm_chunk(const Handle& h, int R, bool staged) {
   return rch;
 }
 
-void launch_fdm(const Handle& h, const double2* in, double2* out, int R, hipStream_t s, bool zero_coarse) {
+void launch_fdm(const Handle& h, const double2* in, double2* out, int R, hipStream_t s, bool zero_coarse,
+                const double2* nu) {
   int nmax = 0;
   for (auto& C : h.classes) nmax = std::max(nmax, C.n);
   const bool staged = size_t(nmax) * nmax * 5 * sizeof(double2) <= 65536;
@@ -2651,10 +2651,12 @@ void launch_fdm(const Handle& h, const double2* in, double2* out, int R, hipStre
   const int zc = zero_coarse ? 1 : 0;
   if (staged)
     hipLaunchKernelGGL(k_fdm<true>, grid, dim3(NT), shm, s, d.elem_cls, d.dof_off, d.cls_n, d.cls_E, d.cls_D, d.Ex,
-                       d.Ey, d.Dinv, in, out, R, rch, d.cls_nr, d.cls_R, d.r_modes, zc);
+                       d.Ey, d.Dinv, in, out, R, rch, d.cls_nr, d.cls_R, d.r_modes, zc, d.slot_off, d.slot_pos,
+                       d.slot_row, d.slot_coef, zero_coarse ? nu : nullptr);
   else
     hipLaunchKernelGGL(k_fdm<false>, grid, dim3(NT), shm, s, d.elem_cls, d.dof_off, d.cls_n, d.cls_E, d.cls_D, d.Ex,
-                       d.Ey, d.Dinv, in, out, R, rch, d.cls_nr, d.cls_R, d.r_modes, zc);
+                       d.Ey, d.Dinv, in, out, R, rch, d.cls_nr, d.cls_R, d.r_modes, zc, d.slot_off, d.slot_pos,
+                       d.slot_row, d.slot_coef, zero_coarse ? nu : nullptr);
   HIPCHECK(hipGetLastError());
 }
 
@@ -2679,13 +2681,6 @@ void launch_correct(const Handle& h, double2* X, const double2* w, int R, hipStr
   hipLaunchKernelGGL(k_correct, dim3(h.E, (R + rch - 1) / rch), dim3(NT), shm, s, d.elem_cls, d.dof_off, d.cm_off,
                      d.cls_n, d.cls_nr, d.cls_R, d.r_modes, d.cls_Kc, d.Kc, d.cls_G, d.G, d.t_ptr, d.t_dof, d.t_coef, X,
                      w, R, rch);
-  HIPCHECK(hipGetLastError());
-}
-
-void launch_sub_dual(const Handle& h, double2* Y, const double2* nu, int R, hipStream_t s) {
-  const auto& d = h.d;
-  hipLaunchKernelGGL(k_sub_dual, dim3(nblocks(int64_t(h.nslots) * R)), dim3(NT), 0, s, h.nslots, d.slot_pos,
-                     d.slot_row, d.slot_coef, Y, nu, R);
   HIPCHECK(hipGetLastError());
 }
 

@@ -53,12 +53,13 @@ void launch_strip_diag64(const Handle& h, const double2* g, double2* w, hipStrea
 
 // Full-element operations (arrays [dof][R])
 // With zero_coarse the element's coarse-mode entries of `in` are read as zero
-// (the solve of the interior problem from a full load vector, out of place).
-void launch_fdm(const Handle& h, const double2* in, double2* out, int R, hipStream_t s, bool zero_coarse = false);
+// (the solve of the interior problem from a full load vector, out of place);
+// with nu ([nlam][R]) the dual slots read in - C^T nu as well.
+void launch_fdm(const Handle& h, const double2* in, double2* out, int R, hipStream_t s, bool zero_coarse = false,
+                const double2* nu = nullptr);
 void launch_zero_R(const Handle& h, double2* X, int R, hipStream_t s);
 void launch_extract_kc(const Handle& h, const double2* X, double2* GL, int R, hipStream_t s);
 void launch_correct(const Handle& h, double2* X, const double2* w, int R, hipStream_t s);
-void launch_sub_dual(const Handle& h, double2* Y, const double2* nu, int R, hipStream_t s);
 void launch_gll(const Handle& h, const double2* X, double2* field, int R, int64_t rhs_stride,
                 int nrhs_out, hipStream_t s);
 
