@@ -219,6 +219,23 @@ hdp_status hdp_apply_interface(hdp_handle* h, const hdp_c64* v, hdp_c64* u,
 hdp_status hdp_apply_precond(hdp_handle* h, const hdp_c64* v, hdp_c64* u,
                              int32_t n_rhs, int32_t precision);
 
+/* Allocation-free variant of hdp_apply_precond, for callers that cannot
+ * allocate device memory during the call (tight serving loops, code that must
+ * not call hipMalloc).  Same operation, arguments, layout and result as
+ * hdp_apply_precond; the work buffers (slot values, and on meshes with hanging
+ * edges the intermediate dual vectors; FP32 copies in the mixed precision) come
+ * from one fixed 32 MiB array per device that the library holds until the
+ * process ends, resolved at hdp_setup.  The call allocates nothing and creates
+ * no profiling events (hdp_profile does not see it).
+ * Limit: the work buffers must fit 32 MiB, about 16 n_rhs (n_slots + 2 n_lambda)
+ * bytes; larger requests return HDP_E_ARG with the needed size in
+ * hdp_last_error_detail().  Every call on one GPU shares that GPU's array (it
+ * keeps the last call's contents; nothing in it needs to start at zero), so
+ * calls that overlap in time on one GPU, from any handles or threads, race:
+ * callers must serialise them. */
+hdp_status hdp_apply_precond_noalloc(hdp_handle* h, const hdp_c64* v, hdp_c64* u,
+                                     int32_t n_rhs, int32_t precision);
+
 /* g = C^ A^-1 b^ (the interface right-hand side) for the given RHS.
  * g: device, [n_lambda][n_rhs]. */
 hdp_status hdp_interface_rhs(hdp_handle* h, const hdp_rhs* rhs, hdp_c64* g);

@@ -71,6 +71,7 @@ class KernelTime(ctypes.Structure):
 
 
 EXPORTS = ["hdp_inspect", "hdp_setup", "hdp_solve", "hdp_apply_interface", "hdp_apply_precond",
+           "hdp_apply_precond_noalloc",
            "hdp_interface_rhs", "hdp_local_solve", "hdp_get_stats", "hdp_profile", "hdp_profile_read",
            "hdp_residual_history", "hdp_far_intensity_gradient",
            "hdp_destroy", "hdp_status_string", "hdp_last_error_detail"]
@@ -93,6 +94,7 @@ def load_library():
                             ctypes.POINTER(Stats)]
     L.hdp_apply_interface.argtypes = [vp, vp, vp, i32, i32]
     L.hdp_apply_precond.argtypes = [vp, vp, vp, i32, i32]
+    L.hdp_apply_precond_noalloc.argtypes = [vp, vp, vp, i32, i32]
     L.hdp_interface_rhs.argtypes = [vp, ctypes.POINTER(_Rhs), vp]
     L.hdp_local_solve.argtypes = [vp, vp, vp, i32]
     L.hdp_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -107,7 +109,7 @@ def load_library():
     L.hdp_status_string.restype = ctypes.c_char_p
     L.hdp_last_error_detail.restype = ctypes.c_char_p
     for name in ("hdp_inspect", "hdp_setup", "hdp_solve", "hdp_apply_interface", "hdp_apply_precond",
-                 "hdp_interface_rhs", "hdp_local_solve", "hdp_get_stats", "hdp_profile", "hdp_profile_read",
+                 "hdp_apply_precond_noalloc", "hdp_interface_rhs", "hdp_local_solve", "hdp_get_stats", "hdp_profile", "hdp_profile_read",
                  "hdp_residual_history", "hdp_far_intensity_gradient"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L

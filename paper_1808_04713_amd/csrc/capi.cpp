@@ -74,7 +74,7 @@ static hipEvent_t prof_event(Handle& h) {
 }
 
 Timed::Timed(Handle& h_, int fam_, double bytes_, double flops_) : h(h_), fam(fam_), bytes(bytes_), flops(flops_) {
-  if (!h.prof.on) return;
+  if (!h.prof.on || h.prof.suspended) return;
   a = prof_event(h);
   HIPCHECK(hipEventRecord(a, h.stream));
 }
@@ -856,7 +856,9 @@ void apply_PF(Handle& h, const double2* v, double2* w, int R, int prec) {
   }
 }
 
-void apply_P(Handle& h, const double2* v, double2* u, int R, int prec) {
+// P^-1 v with the work buffers of w (the handle's own, or the caller-free
+// scratch of the allocation-free entry point).
+void apply_P_ws(Handle& h, const double2* v, double2* u, int R, int prec, const PWork& w) {
   auto& d = h.d;
   hipStream_t s = h.stream;
   const double c = 16.0 * R, nsl = h.nslots, nl = h.nlam, nh = h.nh;
@@ -867,30 +869,35 @@ void apply_P(Handle& h, const double2* v, double2* u, int R, int prec) {
     // P^-1 = X^-1 Y X^-1: X is diagonal except for dense blocks on the hanging
     // rows, whose scale factor is 1 in row_xinv; first s = X^-1 v there
     Timed t(h, KF_HBLOCK, hb_bytes + 2 * nh * c + nl * 2 * c, 2.0 * h.hb_xinv.size() * 2 * R);
-    launch_axpby(v, v, d.pv, int64_t(h.nlam) * R, 1.0, 0.0, s);   // a copy by kernel (capturable)
-    launch_hblock(h, false, v, true, nullptr, d.pv, true, R, s);
-    v = d.pv;
+    launch_axpby(v, v, w.pv, int64_t(h.nlam) * R, 1.0, 0.0, s);   // a copy by kernel (capturable)
+    launch_hblock(h, false, v, true, nullptr, w.pv, true, R, s);
+    v = w.pv;
   }
   if (prec != HDP_FP64) {
     Timed t(h, KF_CAST, nl * (c + cw), 0);
-    launch_cast_f(v, d.vf, int64_t(h.nlam) * R, s);
+    launch_cast_f(v, w.vf, int64_t(h.nlam) * R, s);
   }
   {
     Timed t(h, KF_SLOT_P, nsl * cw * 2 + ob * h.se_bytes, h.flops_P * R);
-    if (prec == HDP_FP64) launch_slot_apply<double2>(h, 1, v, d.slotA, nullptr, R, s);
-    else launch_slot_apply<float2>(h, 1, d.vf, d.slotA_f, nullptr, R, s);
+    if (prec == HDP_FP64) launch_slot_apply<double2>(h, 1, v, w.slot, nullptr, R, s);
+    else launch_slot_apply<float2>(h, 1, w.vf, w.slot_f, nullptr, R, s);
   }
   {
     Timed t(h, KF_ROWGATHER, nsl * cw + nl * c, 0);
-    if (prec == HDP_FP64) launch_rowgather<double2>(h, d.slotA, false, true, nullptr, u, R, s);
-    else launch_rowgather<float2>(h, d.slotA_f, false, true, nullptr, u, R, s);
+    if (prec == HDP_FP64) launch_rowgather<double2>(h, w.slot, false, true, nullptr, u, R, s);
+    else launch_rowgather<float2>(h, w.slot_f, false, true, nullptr, u, R, s);
   }
   if (h.nh > 0) {
     // hanging rows: u = X^-1 (C_1 S C_1^T s + Y_2 s)
     Timed t(h, KF_HBLOCK, 2 * hb_bytes + 6 * nh * c, 2.0 * 2 * h.hb_xinv.size() * 2 * R);
-    launch_hblock(h, true, d.pv, true, u, d.hb_tmp, false, R, s);
-    launch_hblock(h, false, d.hb_tmp, false, nullptr, u, true, R, s);
+    launch_hblock(h, true, w.pv, true, u, w.hb_tmp, false, R, s);
+    launch_hblock(h, false, w.hb_tmp, false, nullptr, u, true, R, s);
   }
+}
+
+void apply_P(Handle& h, const double2* v, double2* u, int R, int prec) {
+  auto& d = h.d;
+  apply_P_ws(h, v, u, R, prec, PWork{d.slotA, d.slotA_f, d.vf, d.pv, d.hb_tmp});
 }
 
 // Solve A^ [x_I; x_R] = [y_I; y_R] element-wise (eq. block_matrix_inversion):
@@ -1208,6 +1215,8 @@ hdp_status hdp_setup(const hdp_mesh* mesh, const hdp_problem* prob, const hdp_op
                   : (opt->flags & HDP_FLAG_COARSE_ND)    ? 2
                                                          : -1;
   try {
+    HIPCHECK(hipGetDevice(&h.device));
+    scratch_init(h.device);   // the allocation-free entry point's array on this device
     // a stream of the handle's own (default priority): capturable, unlike the null stream
     HIPCHECK(hipStreamCreateWithFlags(&h.stream, hipStreamNonBlocking));
     HIPCHECK(hipEventCreateWithFlags(&h.order_ev, hipEventDisableTiming));
@@ -1284,6 +1293,51 @@ hdp_status hdp_apply_precond(hdp_handle* H, const hdp_c64* v, hdp_c64* u, int32_
   apply_P(h, reinterpret_cast<const double2*>(v), reinterpret_cast<double2*>(u), n_rhs, precision);
   HIPCHECK(hipStreamSynchronize(h.stream));
   prof_flush(h);
+  return HDP_OK;
+  API_END
+}
+
+hdp_status hdp_apply_precond_noalloc(hdp_handle* H, const hdp_c64* v, hdp_c64* u, int32_t n_rhs,
+                                     int32_t precision) {
+  API_BEGIN
+  if (!H || !v || !u) fail(HDP_E_ARG, "null argument");
+  Handle& h = H->h;
+  if (n_rhs < 1 || n_rhs > pow2ceil(h.max_rhs)) fail(HDP_E_ARG, "n_rhs out of range");
+  if (precision != HDP_FP64 && precision != HDP_MIXED) fail(HDP_E_ARG, "unknown precision");
+  // carve the work buffers out of the device's scratch array, 256-byte aligned
+  const size_t R = size_t(n_rhs);
+  const bool mixed = precision == HDP_MIXED, hanging = h.nh > 0;
+  const size_t sizes[5] = {mixed ? 0 : size_t(h.nslots) * R * sizeof(double2),
+                           mixed ? size_t(h.nslots) * R * sizeof(float2) : 0,
+                           mixed ? size_t(h.nlam) * R * sizeof(float2) : 0,
+                           hanging ? size_t(h.nlam) * R * sizeof(double2) : 0,
+                           hanging ? size_t(h.nh) * R * sizeof(double2) : 0};
+  size_t off[5], need = 0;
+  for (int i = 0; i < 5; ++i) {
+    off[i] = need;
+    need += (sizes[i] + 255) / 256 * 256;
+  }
+  if (need > SCRATCH_BYTES) {
+    char msg[160];
+    std::snprintf(msg, sizeof msg, "hdp_apply_precond_noalloc needs %zu bytes of scratch at n_rhs = %d; the limit is %zu",
+                  need, n_rhs, SCRATCH_BYTES);
+    fail(HDP_E_ARG, msg);
+  }
+  char* base = static_cast<char*>(scratch_ptr(h.device));
+  if (!base) fail(HDP_E_DEVICE, "scratch array not resolved on the handle's device");
+  auto at = [&](int i) { return sizes[i] ? static_cast<void*>(base + off[i]) : nullptr; };
+  const PWork w{static_cast<double2*>(at(0)), static_cast<float2*>(at(1)), static_cast<float2*>(at(2)),
+                static_cast<double2*>(at(3)), static_cast<double2*>(at(4))};
+  after_user(h);
+  h.prof.suspended = true;   // no profiling events inside this call
+  try {
+    apply_P_ws(h, reinterpret_cast<const double2*>(v), reinterpret_cast<double2*>(u), n_rhs, precision, w);
+  } catch (...) {
+    h.prof.suspended = false;
+    throw;
+  }
+  h.prof.suspended = false;
+  HIPCHECK(hipStreamSynchronize(h.stream));
   return HDP_OK;
   API_END
 }

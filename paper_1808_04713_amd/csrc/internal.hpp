@@ -63,6 +63,7 @@ extern const char* const KF_NAMES[KF_COUNT];
 
 struct Prof {
   bool on = false;
+  bool suspended = false;   // set while an allocation-free call runs (no events created)
   struct Pending { int fam; hipEvent_t a, b; double bytes, flops; };
   std::vector<Pending> pend;
   std::vector<hipEvent_t> pool;
@@ -128,6 +129,7 @@ struct Handle {
   double k = 0, discard_tol = 0;
   int max_rhs = 1, max_iter = 100, precision = HDP_FP64;
   double tol = 1e-8;
+  int device = 0;                      // the device current at set-up
   hipStream_t stream = nullptr;        // internal stream all work is issued on
   hipStream_t user_stream = nullptr;   // caller's stream; work is ordered after it
   hipEvent_t order_ev = nullptr;
@@ -331,6 +333,26 @@ struct Timed {
   ~Timed();
 };
 void prof_flush(Handle& h);   // after a stream synchronisation
+
+// Work buffers of the preconditioner application (P^-1 v at R columns): slot
+// values in FP64 or FP32, the FP32 copy of v, and on meshes with hanging edges
+// X^-1 v and the hanging-block intermediate.
+struct PWork {
+  double2* slot;     // [nslots][R]
+  float2* slot_f;    // [nslots][R] (mixed precision)
+  float2* vf;        // [nlam][R]   (mixed precision)
+  double2* pv;       // [nlam][R]   (hanging edges)
+  double2* hb_tmp;   // [nh][R]     (hanging edges)
+};
+void apply_P_ws(Handle& h, const double2* v, double2* u, int R, int prec, const PWork& w);
+
+// noalloc.hip: the device-resident scratch array of the allocation-free entry
+// point.  scratch_init resolves its address on the current device (once per
+// device; called at set-up); scratch_ptr returns it for a device (null if not
+// resolved); SCRATCH_BYTES is its size.
+extern const size_t SCRATCH_BYTES;
+void scratch_init(int device);
+void* scratch_ptr(int device);
 
 // setup.cpp
 void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob);
