@@ -58,6 +58,11 @@ typedef struct { double re, im; } hdp_c64;
 typedef enum {
   HDP_OK = 0,
   HDP_W_NOT_CONVERGED = 1,  /* outputs hold the last iterate */
+  HDP_W_TRUE_RESIDUAL = 2,  /* the preconditioned residual reached tol but the true interface
+                               residual ||g - F nu|| / ||g|| (hdp_stats.true_residual) exceeds
+                               max(1e3 tol, 1e-6): the preconditioner's row scaling hides the
+                               error, as with hanging-edge constraints of tiny diagonal a^k kept
+                               by discard_tol = 0 (Sec. 2.2.4); outputs hold the iterate */
   HDP_E_ARG = -1,           /* invalid argument (null pointer, size, NaN) */
   HDP_E_MESH = -2,          /* leaves do not tile the domain, or unsupported topology */
   HDP_E_RESONANCE = -3,     /* an element block A_11 is (near) singular at this k */
@@ -174,9 +179,12 @@ typedef struct hdp_handle hdp_handle;
  * sides (Sec. 2.2.4, any number of hanging nodes per side), classify leaves
  * into element classes, compute each class's separable eigenbasis and
  * boundary operators, number dual rows and coarse unknowns (Algorithm 1),
- * assemble the coarse matrix K = A_22 - A_12^T A_11^-1 A_12 and invert it
- * (dense) or factor it strip by strip on the device.  Leaves must tile the
- * domain (HDP_E_MESH otherwise). */
+ * assemble the coarse matrix K = A_22 - A_12^T A_11^-1 A_12 and factor it in
+ * FP64: by default a dense inverse up to 6,000 coarse unknowns and a
+ * nested-dissection multifrontal factor above (fronts factored on the host,
+ * sweeps on the device); HDP_FLAG_COARSE_* select one of the factors,
+ * including the block-tridiagonal strip factor.  Leaves must tile the domain
+ * (HDP_E_MESH otherwise). */
 hdp_status hdp_setup(const hdp_mesh* mesh, const hdp_problem* prob,
                      const hdp_options* opt, hdp_handle** out);
 
@@ -190,7 +198,8 @@ hdp_status hdp_setup(const hdp_mesh* mesh, const hdp_problem* prob,
  * far_inside: host, one byte per leaf (the region whose boundary carries the
  * far-field integral; its outside leaves give the traces).  J: host, 1 value;
  * grad: host, n_leaves values.  stats (optional) describe the forward solve.
- * Needs max_rhs >= 1; returns HDP_W_NOT_CONVERGED if a solve missed tol. */
+ * Needs max_rhs >= 1; returns HDP_W_NOT_CONVERGED if a solve missed tol, or
+ * HDP_W_TRUE_RESIDUAL as hdp_solve. */
 hdp_status hdp_far_intensity_gradient(hdp_handle* h, double incidence, double far_angle,
                                       const uint8_t* far_inside, double* J, double* grad,
                                       hdp_stats* stats);
@@ -202,7 +211,9 @@ hdp_status hdp_far_intensity_gradient(hdp_handle* h, double incidence, double fa
  *        e^{-i w t} convention) over the boundary of the leaves with
  *        far_inside[e] != 0, or NULL.  far_angles: host, n_far observation
  *        angles.  far_inside: host, one byte per leaf.
- * Returns HDP_W_NOT_CONVERGED if some RHS did not reach tol in max_iter. */
+ * Returns HDP_W_NOT_CONVERGED if some RHS did not reach tol in max_iter, else
+ * HDP_W_TRUE_RESIDUAL if some RHS's true interface residual exceeds
+ * max(1e3 tol, 1e-6). */
 hdp_status hdp_solve(hdp_handle* h, const hdp_rhs* rhs, hdp_c64* field,
                      int32_t n_far, const double* far_angles, const uint8_t* far_inside,
                      hdp_c64* far, hdp_stats* stats);
@@ -214,7 +225,11 @@ hdp_status hdp_apply_interface(hdp_handle* h, const hdp_c64* v, hdp_c64* u,
                                int32_t n_rhs, int32_t precision);
 
 /* u = P^-1 v with the Dirichlet preconditioner built from the Laplace-only
- * part (eq. general_preconditioner with W_1 of eq. weight_matrix, W_2 = 0).
+ * part (eq. general_preconditioner with W_1 of eq. weight_matrix).  On a
+ * conforming mesh C_2 = 0 and P^-1 = X^-1 C_1 S_e C_1^T X^-1 with X = C_1 C_1^T;
+ * with hanging edges W_2 = I, the cross term is dropped and C_2 K_L C_2^T kept
+ * (the remark after the preconditioner): X = C_1 C_1^T + C_2 C_2^T (dense
+ * blocks on the rows C_2 couples) and Y = C_1 S_e C_1^T + C_2 K_L C_2^T.
  * Layout as hdp_apply_interface. */
 hdp_status hdp_apply_precond(hdp_handle* h, const hdp_c64* v, hdp_c64* u,
                              int32_t n_rhs, int32_t precision);

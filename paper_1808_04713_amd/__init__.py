@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libhdp.so")
 
 HDP_FP64, HDP_MIXED = 0, 1
 RHS_KINDS = {"plane_wave_total": 0, "point": 1, "plane_wave_scattered": 2, "element_loads": 3}
-STATUS_OK, STATUS_NOT_CONVERGED = 0, 1
+STATUS_OK, STATUS_NOT_CONVERGED, STATUS_TRUE_RESIDUAL = 0, 1, 2
 
 
 class HdpError(RuntimeError):
@@ -117,7 +117,7 @@ def load_library():
 
 
 def _check(status, allow_not_converged=False):
-    if status == STATUS_OK or (allow_not_converged and status == STATUS_NOT_CONVERGED):
+    if status == STATUS_OK or (allow_not_converged and status in (STATUS_NOT_CONVERGED, STATUS_TRUE_RESIDUAL)):
         return status
     L = load_library()
     raise HdpError(status, L.hdp_last_error_detail().decode())
@@ -125,6 +125,31 @@ def _check(status, allow_not_converged=False):
 
 def _dptr(t):
     return ctypes.c_void_p(t.data_ptr())
+
+
+def check_operand(t, rows, max_cols, device, what):
+    """Validate a tensor passed to the library as [rows][n_rhs] complex128
+    memory of the handle's device (the library reads rows * n_rhs values
+    through the raw pointer); returns it contiguous."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != torch.complex128:
+        raise ValueError(f"{what}: dtype must be complex128, got {t.dtype}")
+    if t.device != device:
+        raise ValueError(f"{what}: tensor on {t.device}, the solver's device is {device}")
+    if t.ndim != 2 or t.shape[0] != rows:
+        raise ValueError(f"{what}: shape must be ({rows}, n_rhs), got {tuple(t.shape)}")
+    if not 1 <= t.shape[1] <= max_cols:
+        raise ValueError(f"{what}: n_rhs = {t.shape[1]} outside 1..{max_cols}")
+    return t.contiguous()
+
+
+def _pow2ceil(x):
+    p = 1
+    while p < x:
+        p <<= 1
+    return p
 
 
 def _structs(w, l_safety=0):
@@ -199,7 +224,7 @@ class Solver:
     def _rhs(self, kind, values):
         if kind == "element_loads":
             # values: (dof, n_rhs) complex128 device tensor of element load vectors
-            loads = values.contiguous()
+            loads = check_operand(values, self.dof, self.max_rhs, self.device, "element loads")
             r = _Rhs(RHS_KINDS[kind], loads.shape[1], None, None, ctypes.c_void_p(loads.data_ptr()))
             return r, loads, loads.shape[1]
         vals = np.ascontiguousarray(np.asarray(values, dtype=np.float64))
@@ -238,6 +263,7 @@ class Solver:
         _check(status, allow_not_converged=True)
         d = st.as_dict()
         d["converged"] = status == STATUS_OK
+        d["status"] = status
         if far_angles is not None:
             return field, far, d
         return field, d
@@ -255,18 +281,20 @@ class Solver:
         _check(status, allow_not_converged=True)
         d = st.as_dict()
         d["converged"] = status == STATUS_OK
+        d["status"] = status
         return J.value, grad, d
 
     def apply_interface(self, v, precision=None):
         """u = F v; v is a (n_lambda, n_rhs) complex128 device tensor."""
-        v = v.contiguous()
+        v = check_operand(v, self.n_lambda, _pow2ceil(self.max_rhs), self.device, "v")
         u = self.torch.empty_like(v)
         p = self.precision if precision is None else (HDP_MIXED if precision == "mixed" else HDP_FP64)
         _check(load_library().hdp_apply_interface(self.h, _dptr(v), _dptr(u), v.shape[1], p))
         return u
 
     def apply_precond(self, v, precision=None):
-        v = v.contiguous()
+        """u = P^-1 v; v is a (n_lambda, n_rhs) complex128 device tensor."""
+        v = check_operand(v, self.n_lambda, _pow2ceil(self.max_rhs), self.device, "v")
         u = self.torch.empty_like(v)
         p = self.precision if precision is None else (HDP_MIXED if precision == "mixed" else HDP_FP64)
         _check(load_library().hdp_apply_precond(self.h, _dptr(v), _dptr(u), v.shape[1], p))
@@ -303,7 +331,7 @@ class Solver:
 
     def local_solve(self, y):
         """x_e = A_e^-1 y_e by the separable fast solver; y is (dof, n_rhs)."""
-        y = y.contiguous()
+        y = check_operand(y, self.dof, 1 << 20, self.device, "y")
         x = self.torch.empty_like(y)
         _check(load_library().hdp_local_solve(self.h, _dptr(y), _dptr(x), y.shape[1]))
         return x

@@ -1447,10 +1447,21 @@ hdp_status hdp_interface_rhs(hdp_handle* H, const hdp_rhs* rhs, hdp_c64* g) {
   API_END
 }
 
+// The preconditioned residual (the stopping test) can reach tol while the true
+// interface residual ||g - F nu|| / ||g|| stays large: rows of tiny scale (the
+// decayed change of basis on hanging edges) dominate X^-1.  A solve whose true
+// residual exceeds this bound is reported as HDP_W_TRUE_RESIDUAL.
+static double true_residual_bound(double tol) { return std::max(1e3 * tol, 1e-6); }
+
+static hdp_status solve_status(bool conv, bool true_ok) {
+  if (!conv) return HDP_W_NOT_CONVERGED;
+  return true_ok ? HDP_OK : HDP_W_TRUE_RESIDUAL;
+}
+
 struct SolveOut {
   int iters = 0, refinements = 0;
   double rel = 0, true_res = 0, t_rhs = 0, t_gmres = 0;
-  bool conv = true;
+  bool conv = true, true_ok = true;
   std::chrono::steady_clock::time_point t_rec0;   // start of the recovery
 };
 
@@ -1545,6 +1556,7 @@ static SolveOut solve_core(Handle& h, const hdp_rhs* rhs, int R, int Rp) {
   o.rel = rel;
   o.conv = conv;
   o.true_res = true_res;
+  o.true_ok = true_res <= true_residual_bound(h.tol);
   o.t_rhs = t_rhs;
   o.t_gmres = t_gmres;
   return o;
@@ -1589,7 +1601,7 @@ hdp_status hdp_solve(hdp_handle* H, const hdp_rhs* rhs, hdp_c64* field, int32_t 
     stats->recover_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - so.t_rec0).count();
     stats->true_residual = so.true_res;
   }
-  return so.conv ? HDP_OK : HDP_W_NOT_CONVERGED;
+  return solve_status(so.conv, so.true_ok);
   API_END
 }
 
@@ -1700,7 +1712,7 @@ hdp_status hdp_far_intensity_gradient(hdp_handle* H, double incidence, double fa
     stats->rhs_ms = so.t_rhs;
     stats->gmres_ms = so.t_gmres + sa.t_gmres;
   }
-  return (so.conv && sa.conv) ? HDP_OK : HDP_W_NOT_CONVERGED;
+  return solve_status(so.conv && sa.conv, so.true_ok && sa.true_ok);
   API_END
 }
 
@@ -1766,6 +1778,7 @@ const char* hdp_status_string(hdp_status s) {
   switch (s) {
     case HDP_OK: return "ok";
     case HDP_W_NOT_CONVERGED: return "not converged";
+    case HDP_W_TRUE_RESIDUAL: return "true residual above bound";
     case HDP_E_ARG: return "invalid argument";
     case HDP_E_MESH: return "invalid mesh";
     case HDP_E_RESONANCE: return "element resonance";

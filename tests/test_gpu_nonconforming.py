@@ -202,3 +202,29 @@ def test_graph_replays_match_eager_launches_with_nested_dissection():
         assert rel(f.cpu().numpy(), ref) < 1e-13
     sg.close()
     se.close()
+
+
+def test_true_residual_warning_on_decayed_hanging_rows():
+    """tau = 0 on a hanging mesh of degree 10..12: the preconditioned residual
+    reaches the tolerance while the true interface residual stays above 1e-3
+    (the literal oracle behaves the same way, test_oracle_dp); the solve
+    returns HDP_W_TRUE_RESIDUAL instead of success.  With tau = 1e-3 the same
+    mesh solves with status 0."""
+    m = hdp()
+    for tau, want in ((0.0, m.STATUS_TRUE_RESIDUAL), (1e-3, m.STATUS_OK)):
+        lv = W.refine_where(W.morton_leaves(3, 3), 0, 1, 0, 1, 3, 3,
+                            lambda x, y: (x - 0.5) ** 2 + (y - 0.5) ** 2 < 0.03, 2)
+        deg = np.random.default_rng(0).integers(10, 13, len(lv))
+        w = dict(domain=(0.0, 1.0, 0.0, 1.0), base=(3, 3), leaves=lv, degree=deg, k=6.0, l=2,
+                 bc="impedance", eps_r=np.ones(len(lv)), rhs=dict(kind="plane_wave_total", angles=[0.4]),
+                 discard_tol=tau)
+        print(f"true-residual status case tau={tau}", flush=True)
+        s = m.Solver(w, tol=1e-8, max_iter=300)
+        _, st = s.solve("plane_wave_total", [0.4])
+        s.close()
+        assert st["rel_residual"] <= 1e-8
+        assert st["status"] == want, (tau, st["status"], st["true_residual"])
+        if tau == 0.0:
+            assert st["true_residual"] > 1e-3
+        else:
+            assert st["true_residual"] < 1e-6

@@ -277,3 +277,31 @@ def test_far_field_of_an_outgoing_cylindrical_wave():
     ref = 4 / k * np.exp(-1j * k * (np.cos(ang) * x0[0] + np.sin(ang) * x0[1]))
     assert np.abs(E - ref).max() < 1e-11
     assert np.allclose(ff.rcs(ref, k), 4.0 / k)
+
+
+def _hanging_high_p(tau):
+    lv = W.refine_where(W.morton_leaves(3, 3), 0, 1, 0, 1, 3, 3,
+                        lambda x, y: (x - 0.5) ** 2 + (y - 0.5) ** 2 < 0.03, 2)
+    deg = np.random.default_rng(0).integers(10, 13, len(lv))
+    return dict(domain=(0.0, 1.0, 0.0, 1.0), base=(3, 3), leaves=lv, degree=deg, k=6.0, l=2,
+                bc="impedance", eps_r=np.ones(len(lv)), rhs=dict(kind="plane_wave_total", angles=[0.4]),
+                discard_tol=tau)
+
+
+def test_preconditioned_residual_hides_decayed_hanging_rows():
+    """Sec. 2.2.4 leaves the discard threshold to the user.  With every
+    constraint kept (tau = 0) on a twice-refined hanging mesh of degree 10..12,
+    the diagonals a^k of L_c^f reach 4^-12 = 6e-8 and the weight X = C_1 C_1^T +
+    C_2 C_2^T of eq. (general_preconditioner) scales those rows by up to a^-2k:
+    the literal method's preconditioned residual reaches 1e-8 in a few
+    iterations while the true interface residual stays above 1e-3.  Dropping
+    rows with a^k < 1e-3 restores a true residual at the tolerance.  (The
+    library reports the first case with its own warning status.)"""
+    out = {}
+    for tau in (0.0, 1e-3):
+        disc = pb.Discretisation(_hanging_high_p(tau))
+        D = dp.LiteralDP(disc, 2)
+        D.solve(tol=1e-8, max_iter=300)
+        out[tau] = (D.hist[-1], np.linalg.norm(D.g - D.F @ D.nu) / np.linalg.norm(D.g), D.iters)
+    assert out[0.0][0] <= 1e-8 and out[0.0][1] > 1e-3 and out[0.0][2] <= 8
+    assert out[1e-3][0] <= 1e-8 and out[1e-3][1] < 1e-7
