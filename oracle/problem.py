@@ -25,13 +25,17 @@ def coarse_order(w, mesh=None):
     """l: explicit, or from the dispersion rule of Sec. 2.3.4 evaluated per element
     with its longest edge and its local wavenumber k sqrt(eps_r), taking the largest
     (with eps_r = 1: the free-space k and the longest edge, as in Sec. 3.3.1); with
-    w["l_per_edge"] the per-edge orders of edge_orders (a function of (e, side))."""
+    w["l_free_space"] the free-space k everywhere (the reading of the dielectric
+    cylinder of Sec. 3.3.1); with w["l_per_edge"] the per-edge orders of
+    edge_orders (a function of (e, side))."""
     if w.get("l", -1) >= 1:
         return int(w["l"])
     mesh = mesh or make_mesh(w)
     if w.get("l_per_edge", False):
         return edge_orders(w, mesh)
     eps = np.asarray(w.get("eps_r", np.ones(mesh.E)))
+    if w.get("l_free_space", False):
+        eps = np.ones(mesh.E)
     kh = max(w["k"] * np.sqrt(eps[e]) * max(mesh.size(e)) for e in range(mesh.E))
     return lg.dispersion_l(kh, 1.0)
 
@@ -45,6 +49,8 @@ def edge_orders(w, mesh=None, safety=0):
     leaves along it, so both of its sides get one value.  Returns l(e, side)."""
     mesh = mesh or make_mesh(w)
     eps = np.asarray(w.get("eps_r", np.ones(mesh.E)))
+    if w.get("l_free_space", False):
+        eps = np.ones(mesh.E)
     k = float(w["k"])
 
     def side_len(e, side):

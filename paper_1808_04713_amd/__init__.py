@@ -36,7 +36,7 @@ class _Problem(ctypes.Structure):
     _fields_ = [("k", ctypes.c_double), ("eps_r", ctypes.POINTER(ctypes.c_double)),
                 ("l", ctypes.c_int32), ("l_safety", ctypes.c_int32), ("discard_tol", ctypes.c_double),
                 ("robin_modified", ctypes.c_int32), ("pml_sigma", ctypes.POINTER(ctypes.c_double)),
-                ("l_per_edge", ctypes.c_int32)]
+                ("l_per_edge", ctypes.c_int32), ("l_free_space", ctypes.c_int32)]
 
 
 class _Options(ctypes.Structure):
@@ -167,7 +167,7 @@ def _structs(w, l_safety=0):
                     int(w.get("l", -1)), int(l_safety), float(w.get("discard_tol", 0.0)),
                     int(bool(w.get("robin_modified", False))),
                     sig.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if sig is not None else None,
-                    int(bool(w.get("l_per_edge", False))))
+                    int(bool(w.get("l_per_edge", False))), int(bool(w.get("l_free_space", False))))
     return mesh, prob, (leaves, deg, eps, sig)
 
 

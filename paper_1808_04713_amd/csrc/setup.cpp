@@ -752,10 +752,13 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
     }
   // coarse order l (Sec. 2.3.4): the criterion is evaluated for every element with
   // its longest edge and its local wavenumber k sqrt(eps_r), and the largest value
-  // is used (with eps_r = 1 this is the free-space k and the longest edge)
+  // is used (with eps_r = 1 this is the free-space k and the longest edge); with
+  // l_free_space the free-space k everywhere (the longest edge of the mesh, as in
+  // the paper's dielectric-cylinder example)
+  const bool free_k = prob->l_free_space != 0;
+  auto k_of = [&](int f) { return free_k ? prob->k : prob->k * std::sqrt(std::max(h.eps[f], 0.0)); };
   double khmax = 0;
-  for (int e = 0; e < E; ++e)
-    khmax = std::max(khmax, prob->k * std::sqrt(std::max(h.eps[e], 0.0)) * std::max(h.hx[e], h.hy[e]));
+  for (int e = 0; e < E; ++e) khmax = std::max(khmax, k_of(e) * std::max(h.hx[e], h.hy[e]));
   h.l = prob->l > 0 ? prob->l : dispersion_l(khmax, 1.0) + std::max(0, prob->l_safety);
   // per-edge orders (l_per_edge): the rule on each edge with, for every leaf
   // touching it, its own side length along the edge and k sqrt(eps_r); a fine
@@ -764,7 +767,7 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
   if (prob->l <= 0 && prob->l_per_edge) {
     auto len = [&](int f, int s) { return s <= 2 ? h.hy[f] : h.hx[f]; };
     auto rule = [&](int f, int s) {
-      return dispersion_l(prob->k * std::sqrt(std::max(h.eps[f], 0.0)) * len(f, s), 1.0);
+      return dispersion_l(k_of(f) * len(f, s), 1.0);
     };
     int lmax = 1;
     for (int e = 0; e < E; ++e)

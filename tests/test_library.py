@@ -172,3 +172,14 @@ def test_per_edge_order_counts_match_the_oracle(k, seed):
     lmax = max(lf(e, s) for e in range(disc.mesh.E) for s in (1, 2, 3, 4))
     assert (st["l"], st["n_lambda"], st["n_coarse"]) == (lmax, n_dual, n_type2)
     assert st["n_coarse"] < hdp.inspect(dict(w, l_per_edge=False))["n_coarse"]
+
+
+def test_inspect_free_space_reading_of_the_rule():
+    """l_free_space evaluates the dispersion rule with k instead of k sqrt(eps_r):
+    on the 64x64 dielectric-square scatterer (h = 1/32, k = 150, eps_r = 4) the
+    local reading gives l = 6 and the free-space reading l = 3, matching the
+    oracle's rule in both readings."""
+    w = W.square_scatterer_64x64()
+    for free, l in ((False, 6), (True, 3)):
+        ww = dict(w, l_free_space=free)
+        assert hdp.inspect(ww)["l"] == l == pb.coarse_order(ww)

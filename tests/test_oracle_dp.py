@@ -305,3 +305,37 @@ def test_preconditioned_residual_hides_decayed_hanging_rows():
         out[tau] = (D.hist[-1], np.linalg.norm(D.g - D.F @ D.nu) / np.linalg.norm(D.g), D.iters)
     assert out[0.0][0] <= 1e-8 and out[0.0][1] > 1e-3 and out[0.0][2] <= 8
     assert out[1e-3][0] <= 1e-8 and out[1e-3][1] < 1e-7
+
+
+def _dielectric_block(k, free_space):
+    w = W.small_uniform(10, 8, k, domain=(-1.0, 1.0, -1.0, 1.0),
+                        rhs=dict(kind="plane_wave_scattered", angles=[0.0]))
+    c = W.leaf_centres(w)
+    w["eps_r"] = np.where((np.abs(c[:, 0]) < 0.41) & (np.abs(c[:, 1]) < 0.41), 4.0, 1.0)
+    w["l_free_space"] = free_space
+    return w
+
+
+def test_local_wavenumber_reading_of_the_dispersion_rule():
+    """Sec. 2.3.4 chooses l so that the coarse problem leaves the O(1)
+    dispersion-error regime, which keeps the iteration count small and weakly
+    dependent on k (Table 2: 10-11 iterations where the rule holds at p = 8).
+    Inside a dielectric the wavelength is shorter by sqrt(eps_r); with the
+    free-space k the rule gives l = 3 on a 10x10 mesh (h = 1/5, p = 8) with a
+    4x4-element eps_r = 4 block at k = 25, and GMRES needs 59 iterations; with
+    the local wavenumber k sqrt(eps_r) it gives l = 6 and 8 iterations, in the
+    range Table 2 reports.  Both readings coincide where eps_r = 1."""
+    out = {}
+    for free in (True, False):
+        w = _dielectric_block(25.0, free)
+        disc = pb.Discretisation(w)
+        l = pb.coarse_order(w, disc.mesh)
+        E = dpe.ElementwiseDP(disc, l)
+        E.solve(tol=1e-8, max_iter=300)
+        out[free] = (l, E.iters)
+    assert out[True][0] == 3 and out[False][0] == 6
+    assert out[False][1] <= 12
+    assert out[True][1] >= 4 * out[False][1]
+    w1 = dict(_dielectric_block(25.0, True), eps_r=np.ones(100))
+    w2 = dict(_dielectric_block(25.0, False), eps_r=np.ones(100))
+    assert pb.coarse_order(w1) == pb.coarse_order(w2) == 3
