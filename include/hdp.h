@@ -140,6 +140,11 @@ typedef struct {
   int32_t max_rhs;            /* largest n_rhs that hdp_solve will receive, 1..64 */
   void* stream;               /* caller's hipStream_t (NULL: null stream) the solver orders after */
   int32_t flags;              /* HDP_FLAG_* bits, 0 for defaults */
+  int32_t tile_fdm;           /* right-hand sides per workgroup of the separable element solve on
+                                 the matrix cores (1, 2, 4, 8 or 16; 0: the autotuner's choice
+                                 with HDP_FLAG_AUTOTUNE, else a shared-memory heuristic) */
+  int32_t tile_slot;          /* right-hand sides per workgroup of the matrix-core slot operators
+                                 at 16 or more columns (16, 32 or 64; 0: autotuned or 32) */
 } hdp_options;
 
 /* hdp_options.flags: replay each GMRES iteration as a captured HIP graph
@@ -153,6 +158,11 @@ typedef struct {
 #define HDP_FLAG_COARSE_BLOCK 2
 #define HDP_FLAG_COARSE_DENSE 4
 #define HDP_FLAG_COARSE_ND 8
+/* time every candidate tile width of the separable element solve and of the
+   matrix-core slot operators at set-up, on the handle's own mesh at max_rhs
+   columns, and keep the fastest (hdp_autotune_table lists the measurements);
+   tile_fdm / tile_slot, when non-zero, take precedence */
+#define HDP_FLAG_AUTOTUNE 16
 
 typedef struct {
   int32_t kind;               /* HDP_RHS_* */
@@ -302,6 +312,19 @@ typedef struct {
 } hdp_kernel_time;
 hdp_status hdp_profile(hdp_handle* h, int32_t enable);
 hdp_status hdp_profile_read(const hdp_handle* h, hdp_kernel_time* out, int32_t max, int32_t* count);
+
+/* The set-up autotuner's measurements (HDP_FLAG_AUTOTUNE): one entry per
+ * candidate, the kernel family, the candidate's right-hand sides per workgroup,
+ * its mean launch time over three launches at max_rhs columns (ms) and whether
+ * it was chosen.  count receives the number of entries; at most max are written
+ * to out (host). */
+typedef struct {
+  char kernel[32];
+  int32_t cols;
+  int32_t chosen;
+  double ms;
+} hdp_tune_entry;
+hdp_status hdp_autotune_table(const hdp_handle* h, hdp_tune_entry* out, int32_t max, int32_t* count);
 
 void hdp_destroy(hdp_handle* h);
 const char* hdp_status_string(hdp_status s);

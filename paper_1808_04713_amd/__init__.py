@@ -41,7 +41,8 @@ class _Problem(ctypes.Structure):
 
 class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
-                ("max_rhs", ctypes.c_int32), ("stream", ctypes.c_void_p), ("flags", ctypes.c_int32)]
+                ("max_rhs", ctypes.c_int32), ("stream", ctypes.c_void_p), ("flags", ctypes.c_int32),
+                ("tile_fdm", ctypes.c_int32), ("tile_slot", ctypes.c_int32)]
 
 
 class _Rhs(ctypes.Structure):
@@ -65,6 +66,11 @@ class Stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_char * 32), ("cols", ctypes.c_int32), ("chosen", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
+
+
 class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
                 ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
@@ -73,7 +79,7 @@ class KernelTime(ctypes.Structure):
 EXPORTS = ["hdp_inspect", "hdp_setup", "hdp_solve", "hdp_apply_interface", "hdp_apply_precond",
            "hdp_apply_precond_noalloc",
            "hdp_interface_rhs", "hdp_local_solve", "hdp_get_stats", "hdp_profile", "hdp_profile_read",
-           "hdp_residual_history", "hdp_far_intensity_gradient",
+           "hdp_residual_history", "hdp_far_intensity_gradient", "hdp_autotune_table",
            "hdp_destroy", "hdp_status_string", "hdp_last_error_detail"]
 
 _lib = None
@@ -104,13 +110,14 @@ def load_library():
     L.hdp_profile_read.argtypes = [vp, ctypes.POINTER(KernelTime), i32, ctypes.POINTER(i32)]
     L.hdp_far_intensity_gradient.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_uint8),
                                              dp, dp, ctypes.POINTER(Stats)]
+    L.hdp_autotune_table.argtypes = [vp, ctypes.POINTER(TuneEntry), i32, ctypes.POINTER(i32)]
     L.hdp_destroy.argtypes = [vp]
     L.hdp_destroy.restype = None
     L.hdp_status_string.restype = ctypes.c_char_p
     L.hdp_last_error_detail.restype = ctypes.c_char_p
     for name in ("hdp_inspect", "hdp_setup", "hdp_solve", "hdp_apply_interface", "hdp_apply_precond",
                  "hdp_apply_precond_noalloc", "hdp_interface_rhs", "hdp_local_solve", "hdp_get_stats", "hdp_profile", "hdp_profile_read",
-                 "hdp_residual_history", "hdp_far_intensity_gradient"):
+                 "hdp_residual_history", "hdp_far_intensity_gradient", "hdp_autotune_table"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -188,7 +195,7 @@ class Solver:
     """
 
     def __init__(self, w, precision="fp64", tol=1e-8, max_iter=300, max_rhs=1, l_safety=0, device=0,
-                 graphs=False, coarse="auto"):
+                 graphs=False, coarse="auto", autotune=False, tile_fdm=0, tile_slot=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("hdp needs a ROCm GPU (torch.cuda.is_available() is False)")
@@ -199,8 +206,10 @@ class Solver:
         self.precision = HDP_MIXED if precision == "mixed" else HDP_FP64
         with torch.cuda.device(self.device):
             stream = torch.cuda.current_stream(self.device).cuda_stream
-            flags = (1 if graphs else 0) | {"auto": 0, "block": 2, "dense": 4, "nd": 8}[coarse]
-            opt = _Options(self.precision, float(tol), int(max_iter), int(max_rhs), ctypes.c_void_p(stream), flags)
+            flags = ((1 if graphs else 0) | {"auto": 0, "block": 2, "dense": 4, "nd": 8}[coarse]
+                     | (16 if autotune else 0))
+            opt = _Options(self.precision, float(tol), int(max_iter), int(max_rhs), ctypes.c_void_p(stream), flags,
+                           int(tile_fdm), int(tile_slot))
             h = ctypes.c_void_p()
             _check(L.hdp_setup(ctypes.byref(mesh), ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(h)))
         self.h = h
@@ -328,6 +337,15 @@ class Solver:
         _check(L.hdp_profile_read(self.h, buf, 64, ctypes.byref(n)))
         return [dict(name=buf[i].name.decode(), launches=buf[i].launches, total_ms=buf[i].total_ms,
                      bytes=buf[i].bytes, flops=buf[i].flops) for i in range(n.value)]
+
+    def autotune_table(self):
+        """The set-up autotuner's measurements: kernel, columns per workgroup, ms, chosen."""
+        L = load_library()
+        buf = (TuneEntry * 64)()
+        n = ctypes.c_int32()
+        _check(L.hdp_autotune_table(self.h, buf, 64, ctypes.byref(n)))
+        return [dict(kernel=buf[i].kernel.decode(), cols=buf[i].cols, ms=buf[i].ms, chosen=bool(buf[i].chosen))
+                for i in range(n.value)]
 
     def local_solve(self, y):
         """x_e = A_e^-1 y_e by the separable fast solver; y is (dof, n_rhs)."""

@@ -475,7 +475,7 @@ void build_device(Handle& h) {
   d.cm_pos = upload(h, cm_pos);
   // class tables and operators
   int NC = int(h.classes.size());
-  std::vector<int> cn(NC), cm(NC), cnr(NC), cgam(NC), cR(NC);
+  std::vector<int> cn(NC), cm(NC), cnr(NC), cgam(NC), cR(NC), creal(NC);
   std::vector<int64_t> o_op1(NC), o_phi(NC), o_se(NC), o_E(NC), o_D(NC), o_G(NC), o_Kc(NC), o_V(NC);
   std::vector<double2> op1, phi, Ex, Ey, Dinv, G, Kc;
   std::vector<double2> se;
@@ -492,6 +492,10 @@ void build_device(Handle& h) {
     for (auto& v : C.Se.a) se.push_back(make_double2(v.real(), v.imag()));
     for (auto& v : C.Ex.a) Ex.push_back(make_double2(v.real(), v.imag()));
     for (auto& v : C.Ey.a) Ey.push_back(make_double2(v.real(), v.imag()));
+    // a real pencil (no impedance or layer terms) gives an exactly real eigenbasis
+    creal[c] = 1;
+    for (auto& v : C.Ex.a) if (v.imag() != 0.0) creal[c] = 0;
+    for (auto& v : C.Ey.a) if (v.imag() != 0.0) creal[c] = 0;
     for (auto& v : C.Dg) { cd iv = 1.0 / v; Dinv.push_back(make_double2(iv.real(), iv.imag())); }
     for (auto& v : C.G.a) G.push_back(make_double2(v.real(), v.imag()));
     for (auto& v : C.Kc.a) Kc.push_back(make_double2(v.real(), v.imag()));
@@ -541,6 +545,17 @@ void build_device(Handle& h) {
     d.slot_out = upload(h, out);
   }
   d.cls_E = upload(h, o_E); d.cls_D = upload(h, o_D); d.cls_G = upload(h, o_G);
+  d.cls_real = upload(h, creal);
+  {
+    std::vector<FdmRec> fr(size_t(h.E));
+    for (int e = 0; e < h.E; ++e) {
+      const int c = h.cls[e];
+      const ElemClass& C = h.classes[c];
+      fr[e] = FdmRec{h.dof_off[e], o_E[c], o_D[c], o_Kc[c], C.n, C.nr, cR[c], h.cm_off[e],
+                     h.slot_off[e], h.slot_off[e + 1], creal[c], c};
+    }
+    d.fdm_rec = upload(h, fr);
+  }
   d.cls_Kc = upload(h, o_Kc); d.cls_V = upload(h, o_V);
   d.cls_gam = upload(h, cgam); d.gam_modes = upload(h, gam);
   d.cls_R = upload(h, cR); d.r_modes = upload(h, rmod);
@@ -623,6 +638,7 @@ void build_device(Handle& h) {
   d.slotA_f = dalloc<float2>(h, size_t(h.nslots) * Rp);
   d.slotB_f = dalloc<float2>(h, size_t(h.nslots) * Rp);
   d.cmA = dalloc<double2>(h, size_t(h.ncm) * Rp);
+  d.cmX = dalloc<double2>(h, size_t(h.ncm) * Rp);
   d.cmA_f = dalloc<float2>(h, size_t(h.ncm) * Rp);
   d.gK = dalloc<double2>(h, nK * Rp);
   d.wK = dalloc<double2>(h, nK * Rp);
@@ -910,6 +926,25 @@ void element_solve(Handle& h, double2* X, const double2* Bfull, const double2* n
   auto& d = h.d;
   hipStream_t s = h.stream;
   const double c = 16.0 * R, dof = double(h.dof), ncm = h.ncm, nK = h.nK;
+  if (Y && fdm_mf_ok(h, true)) {
+    // matrix cores: a coarse pass (x_R and K_e x_R) and, after the coarse
+    // solve, the full solve of y - E_R mu, which folds the Woodbury correction
+    // into the separable solve
+    {
+      Timed t(h, KF_FDM, dof * c + 2 * ncm * c, h.flops_fdm_coarse * R);
+      launch_fdm_mf(h, 1, Y, nullptr, R, s, nu, nullptr);
+    }
+    {
+      Timed t(h, KF_ASSEMBLE, 2 * ncm * c + nK * c, 0);
+      launch_assemble<double2>(h, d.cmA, Bfull, nu, -1.0, d.gK, R, s);
+    }
+    coarse_solve_timed(h, d.gK, d.wK, R);
+    {
+      Timed t(h, KF_FDM, 2 * dof * c + ncm * c + nK * c, h.flops_fdm * R);
+      launch_fdm_mf(h, 2, Y, X, R, s, nu, d.wK);
+    }
+    return;
+  }
   if (!Y) {
     Timed t(h, KF_ELEMENT_MISC, ncm * c, 0);
     launch_zero_R(h, X, R, s);
@@ -1164,6 +1199,74 @@ void far_prepare(Handle& h, int n_far, const double* angles, const uint8_t* insi
   f.DU = dalloc<double2>(h, size_t(std::max(1, f.nq)) * f.capR);
 }
 
+// Set-up autotuner: each candidate tile width of the matrix-core element solve
+// and of the slot operators runs three times on the handle's own mesh at max_rhs
+// columns (after one untimed launch); the fastest is kept.  The element solve
+// is timed as its two passes (coarse pass and corrected solve) on a zero input
+// (its time does not depend on the values), the slot operators as the interface
+// operator's first product.
+static void autotune(Handle& h, bool fdm, bool slot) {
+  auto& d = h.d;
+  hipStream_t s = h.stream;
+  const int R = pow2ceil(h.max_rhs);
+  hipEvent_t a, b;
+  HIPCHECK(hipEventCreate(&a));
+  HIPCHECK(hipEventCreate(&b));
+  auto time3 = [&](auto&& launch) {
+    launch();
+    HIPCHECK(hipEventRecord(a, s));
+    for (int q = 0; q < 3; ++q) launch();
+    HIPCHECK(hipEventRecord(b, s));
+    HIPCHECK(hipEventSynchronize(b));
+    float ms = 0;
+    HIPCHECK(hipEventElapsedTime(&ms, a, b));
+    return double(ms) / 3.0;
+  };
+  try {
+    launch_fill_zero(d.full0, int64_t(h.dof) * R, s);
+    launch_fill_zero(d.w, int64_t(h.nlam) * R, s);
+    if (fdm && fdm_mf_ok(h, true)) {
+      int best = 0;
+      double tbest = 1e300;
+      const size_t first = h.tune.size();
+      for (int rc : {1, 2, 4, 8, 16}) {
+        if (rc > std::min(16, R)) break;
+        h.fdm_rc = rc;
+        if (fdm_mf_rc(h, R) != rc) continue;   // does not fit shared memory
+        launch_fill_zero(d.wK, int64_t(h.nK) * R, s);
+        const double ms = time3([&] {
+          launch_fdm_mf(h, 1, d.full0, nullptr, R, s, nullptr, nullptr, rc);
+          launch_fdm_mf(h, 2, d.full0, d.full1, R, s, nullptr, d.wK, rc);
+        });
+        h.tune.push_back({"fdm_element_solve", rc, ms, false});
+        if (ms < tbest) { tbest = ms; best = rc; }
+      }
+      h.fdm_rc = best;
+      for (size_t i = first; i < h.tune.size(); ++i) h.tune[i].chosen = h.tune[i].cols == best;
+    }
+    if (slot && R >= 16) {
+      int best = h.slot_rb;
+      double tbest = 1e300;
+      const size_t first = h.tune.size();
+      for (int rb : {16, 32, 64}) {
+        if (rb > R) break;
+        h.slot_rb = rb;
+        const double ms = time3([&] { launch_slot_apply<double2>(h, 0, d.w, d.slotA, d.cmA, R, s); });
+        h.tune.push_back({"slot_operator", rb, ms, false});
+        if (ms < tbest) { tbest = ms; best = rb; }
+      }
+      h.slot_rb = best;
+      for (size_t i = first; i < h.tune.size(); ++i) h.tune[i].chosen = h.tune[i].cols == best;
+    }
+  } catch (...) {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    throw;
+  }
+  HIPCHECK(hipEventDestroy(a));
+  HIPCHECK(hipEventDestroy(b));
+}
+
 // Order the handle's stream after everything already issued on the caller's stream.
 void after_user(Handle& h) {
   HIPCHECK(hipEventRecord(h.order_ev, h.user_stream));
@@ -1205,6 +1308,13 @@ hdp_status hdp_setup(const hdp_mesh* mesh, const hdp_problem* prob, const hdp_op
   h.precision = opt->precision;
   h.user_stream = static_cast<hipStream_t>(opt->stream);
   h.use_graphs = (opt->flags & HDP_FLAG_GRAPH) != 0;
+  if (opt->tile_fdm != 0 && opt->tile_fdm != 1 && opt->tile_fdm != 2 && opt->tile_fdm != 4 && opt->tile_fdm != 8 &&
+      opt->tile_fdm != 16)
+    fail(HDP_E_ARG, "tile_fdm must be 0, 1, 2, 4, 8 or 16");
+  if (opt->tile_slot != 0 && opt->tile_slot != 16 && opt->tile_slot != 32 && opt->tile_slot != 64)
+    fail(HDP_E_ARG, "tile_slot must be 0, 16, 32 or 64");
+  h.fdm_rc = opt->tile_fdm;
+  if (opt->tile_slot) h.slot_rb = opt->tile_slot;
   {
     const int nf = ((opt->flags & HDP_FLAG_COARSE_BLOCK) != 0) + ((opt->flags & HDP_FLAG_COARSE_DENSE) != 0) +
                    ((opt->flags & HDP_FLAG_COARSE_ND) != 0);
@@ -1224,6 +1334,7 @@ hdp_status hdp_setup(const hdp_mesh* mesh, const hdp_problem* prob, const hdp_op
     HIPCHECK(hipStreamWaitEvent(h.stream, h.order_ev, 0));
     build_host(h, mesh, prob);
     build_device(h);
+    if (opt->flags & HDP_FLAG_AUTOTUNE) autotune(h, opt->tile_fdm == 0, opt->tile_slot == 0);
   } catch (...) {
     if (h.stream) (void)hipStreamSynchronize(h.stream);
     for (void* p : h.allocations) (void)hipFree(p);
@@ -1348,7 +1459,9 @@ hdp_status hdp_local_solve(hdp_handle* H, const hdp_c64* y, hdp_c64* x, int32_t 
   Handle& h = H->h;
   if (n_rhs < 1) fail(HDP_E_ARG, "n_rhs out of range");
   after_user(h);
-  launch_fdm(h, reinterpret_cast<const double2*>(y), reinterpret_cast<double2*>(x), n_rhs, h.stream);
+  if (fdm_mf_ok(h, false)) launch_fdm_mf(h, 0, reinterpret_cast<const double2*>(y), reinterpret_cast<double2*>(x), n_rhs,
+                                   h.stream, nullptr, nullptr);
+  else launch_fdm(h, reinterpret_cast<const double2*>(y), reinterpret_cast<double2*>(x), n_rhs, h.stream);
   HIPCHECK(hipStreamSynchronize(h.stream));
   return HDP_OK;
   API_END
@@ -1723,6 +1836,22 @@ hdp_status hdp_residual_history(const hdp_handle* H, int32_t rhs, double* out, i
   if (rhs < 0 || (h.last_hist_R && rhs >= h.last_hist_R)) fail(HDP_E_ARG, "rhs index out of range");
   *count = h.last_hist_len;
   for (int i = 0; i < h.last_hist_len && i < max && out; ++i) out[i] = h.last_hist[size_t(i) * h.last_hist_R + rhs];
+  return HDP_OK;
+  API_END
+}
+
+hdp_status hdp_autotune_table(const hdp_handle* H, hdp_tune_entry* out, int32_t max, int32_t* count) {
+  API_BEGIN
+  if (!H || !count) fail(HDP_E_ARG, "null handle or count");
+  const Handle& h = H->h;
+  *count = int32_t(h.tune.size());
+  for (int32_t i = 0; i < std::min<int32_t>(max, *count); ++i) {
+    std::memset(&out[i], 0, sizeof(out[i]));
+    std::snprintf(out[i].kernel, sizeof(out[i].kernel), "%s", h.tune[size_t(i)].kernel.c_str());
+    out[i].cols = h.tune[size_t(i)].cols;
+    out[i].ms = h.tune[size_t(i)].ms;
+    out[i].chosen = h.tune[size_t(i)].chosen ? 1 : 0;
+  }
   return HDP_OK;
   API_END
 }

@@ -108,6 +108,12 @@ struct SlotBlock {
   int64_t op1, se, phi;
   int e, c, so, cmo, m, nr, pad0, pad1;
 };
+// Per-element record of the matrix-core element solves, read with one load.
+struct FdmRec {
+  int64_t base, eoff, doff, kc;   // element's first coefficient; class's E, 1/D and K_e offsets
+  int n, nr, roff, cmo;           // modes per direction, coarse modes, coarse-mode list offset, first coarse mode
+  int s0, s1, real, cls;          // dual slots [s0, s1); 1 for a real eigenbasis; the class
+};
 // Per-slot input gather of the slot kernels: value = a0 v[s0] + a1 v[s1] (an
 // index < 0 contributes nothing), the row scalings already multiplied in.
 struct SlotIn {
@@ -208,7 +214,7 @@ struct Handle {
   // algorithmic work per right-hand side (bytes of class operators are
   // counted once per launch, like any operand read from memory once)
   double op1_bytes = 0, se_bytes = 0, phi_bytes = 0;
-  double flops_F = 0, flops_P = 0, flops_coarse = 0, flops_fdm = 0, flops_gll = 0;
+  double flops_F = 0, flops_P = 0, flops_coarse = 0, flops_fdm = 0, flops_gll = 0, flops_fdm_coarse = 0;
 
   // device buffers --------------------------------------------------------
   struct Dev {
@@ -252,6 +258,8 @@ struct Handle {
     int64_t* cb_D = nullptr;
     // per-class tables
     int *cls_n = nullptr, *cls_m = nullptr, *cls_nr = nullptr;
+    int* cls_real = nullptr;   // 1 when the class's eigenbasis is real
+    FdmRec* fdm_rec = nullptr; // per element
     int64_t *cls_op1 = nullptr, *cls_phi = nullptr, *cls_se = nullptr;   // offsets
     int64_t *cls_E = nullptr, *cls_D = nullptr, *cls_G = nullptr, *cls_Kc = nullptr, *cls_V = nullptr;
     int* cls_gam = nullptr;   // per class offset into gam_modes
@@ -272,6 +280,7 @@ struct Handle {
     int2* sym_tij = nullptr;
     // work
     double2 *slotA = nullptr, *slotB = nullptr, *cmA = nullptr, *gK = nullptr, *wK = nullptr;
+    double2* cmX = nullptr;   // [ncm][R]: coarse-mode values x_R of the element solve's first pass
     float2 *slotA_f = nullptr, *slotB_f = nullptr, *cmA_f = nullptr;
     double2 *full0 = nullptr, *full1 = nullptr;   // [dof][R]
     double2 *V_kry = nullptr;                      // (max_iter+1) x nlam x R
@@ -316,6 +325,15 @@ struct Handle {
   } far;
   void* rocblas = nullptr;   // rocblas_handle for the batched coarse solve
   bool use_graphs = false;
+  int fdm_rc = 0;    // right-hand sides per block of the matrix-core element solve (0: heuristic)
+  int slot_rb = 32;  // right-hand sides per block of the matrix-core slot operators (16, 32, 64)
+  struct Tune {
+    std::string kernel;
+    int cols;
+    double ms;
+    bool chosen;
+  };
+  std::vector<Tune> tune;   // the set-up autotuner's measurements
   std::vector<double> last_hist;   // residual history of the last GMRES run, [iteration][R]
   int last_hist_R = 0, last_hist_len = 0;
   double t_launch = 0, t_wait = 0;

@@ -1287,6 +1287,424 @@ __global__ void __launch_bounds__(NT) k_fdm(const int* __restrict__ elem_cls, co
   }
 }
 
+// ---------------------------------------------------------------------------
+// The separable element solve on the FP64 matrix cores (n <= 32 modes per
+// direction).  One block per (element, RC right-hand sides); the element's
+// n^2 x RC coefficients sit in shared memory (entry (a, b, r) of a stage at
+// (a + n b) RC + r).  X = Ex [(Ex^T Y Ey) ./ D] Ey^T is four contractions of the
+// form D(m, q, r) = sum_k M(m, k) S(k, q, r) over one mode index, each a product
+// of a 16 x 4 tile of M (rows m, columns k) with a 4 x 16 tile of the stage
+// (rows k, columns (q, r), 16 / RC modes q times RC columns r) on 16x16x4 FP64
+// matrix operations: two real operations per step when the class's eigenbasis is
+// real (interior elements, the usual case), four when it is complex (impedance
+// or layer terms).  Lane l supplies M(m0 + (l & 15), k0 + (l >> 4)) and
+// S(k0 + (l >> 4), (q, r) of column l & 15); it receives D(m0 + (l >> 4) + 4 v,
+// column l & 15) in value v.  Rows and columns past n are zero operands.
+//
+// MODE 0: out = A~^-1 in on every element.
+// MODE 1: the coarse pass of the element solve of eq. block_matrix_inversion:
+//   y = in with the coarse-mode rows zeroed and C_1^T nu subtracted at the dual
+//   slots; only the coarse-mode values x_R of A~^-1 y are formed (two full
+//   contractions, then the lines i < 2 and j < 2 of the last two on the vector
+//   ALUs) and written to Xr, and GL = K_e x_R (the element's share of -Phi^T y)
+//   to GL, both [coarse mode][R].
+// MODE 2: the full solve with the Woodbury correction folded in: mu =
+//   K_e (x_R - T_e w), and out = A~^-1 (y - E_R mu) (y's coarse rows are zero,
+//   so they become -mu), which equals A~^-1 y - G mu.
+struct FdmArgs {
+  const FdmRec* rec;
+  const int* order;   // elements grouped by class
+  const int* elem_cls;
+  const int64_t* dof_off;
+  const int* cls_n;
+  const int64_t* cls_E;
+  const int64_t* cls_D;
+  const double2* Ex;
+  const double2* Ey;
+  const double2* Dinv;
+  const int* cls_real;   // per class: 1 when Ex and Ey are real
+  const double2* in;
+  double2* out;
+  int R;
+  const int* cls_nr;
+  const int* cls_R;
+  const int* r_modes;
+  int zero_coarse;
+  const int* slot_off;
+  const int64_t* slot_pos;
+  const int* slot_row;
+  const double* slot_coef;
+  const double2* nu;
+  const int* cm_off;
+  const int64_t* cls_Kc;
+  const double2* Kc;
+  double2* Xr;
+  double2* GL;
+  const int* t_ptr;
+  const int* t_dof;
+  const double* t_coef;
+  const double2* w;
+};
+
+// D = M S over one mode index (see above), for classes of n <= NP modes (NP 16
+// or 32).  KF_IN: the contraction index is the fast index of S's positions;
+// KF_OUT: m is the fast index of D's positions; MFAST: M(m, k) = mat[m + LD k],
+// else mat[m LD + k] with LD = NP + 1 (the eigenbases are staged zero-padded to
+// NP x NP in columns of NP + 1 entries, which keeps the operand reads free of
+// shared-memory bank conflicts; rows
+// and columns past n multiply by zero; every stage position up to NP^2 holds a
+// finite value, so no operand needs a bounds test).  With scale, D is
+// multiplied entrywise by scale at position (q + n m) (1 / (lambda_x + lambda_y)
+// in the second contraction, whose output keeps i = q fast).
+template <int RC, int NP, bool CPLX, bool KF_IN, bool KF_OUT, bool MFAST>
+__device__ __forceinline__ void fdm_contract(const double2* __restrict__ mat, const double2* __restrict__ S,
+                                             double2* __restrict__ D, int n, const double2* __restrict__ scale) {
+  constexpr int QT = 16 / RC;                   // modes q per column tile
+  constexpr int MT = NP / 16;                   // row tiles
+  constexpr int KS = NP / 4;                    // steps of four summation indices
+  constexpr int TMAX = MT * (NP / QT);          // tiles when n = NP
+  constexpr int TPW = (TMAX + 3) / 4;           // tiles per wave (every wave runs all of its
+                                                // slots in straight-line code; a slot past the
+                                                // last tile repeats it and is not stored)
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c16 = l & 15, kq = l >> 4;
+  const int qo = c16 / RC, r = c16 % RC;
+  const int ntiles = (n + QT - 1) / QT, T = MT * ntiles;
+  constexpr int LD = NP + 1;                    // eigenbasis leading dimension (odd: no bank conflicts)
+  const int sstep = KF_IN ? 4 * RC : 4 * n * RC;   // operand step per four summation indices
+  d4 cr[TPW], ci[TPW];
+  const double2* ap[TPW];
+  const double2* bp[TPW];
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) {
+    cr[u] = (d4){0, 0, 0, 0};
+    ci[u] = (d4){0, 0, 0, 0};
+    const int tile = min(wv + 4 * u, T - 1);
+    const int nt = tile / MT, mt = tile - nt * MT;
+    const int m = 16 * mt + c16, q = nt * QT + qo;
+    ap[u] = mat + (MFAST ? m + LD * kq : m * LD + kq);
+    bp[u] = S + (KF_IN ? kq + n * q : q + n * kq) * RC + r;
+  }
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+      const double2 a = ap[u][MFAST ? 4 * ks * LD : 4 * ks];
+      const double2 b = bp[u][ks * sstep];
+      cr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr[u], 0, 0, 0);
+      ci[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ci[u], 0, 0, 0);
+      if (CPLX) {
+        cr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cr[u], 0, 0, 0);
+        ci[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, ci[u], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) {
+    const int tile = wv + 4 * u;
+    const int nt = tile / MT, mt = tile - nt * MT;
+    const int q = nt * QT + qo;
+    if (tile < T && q < n) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = 16 * mt + kq + 4 * v;
+        if (m < n) {
+          const int pos = KF_OUT ? m + n * q : q + n * m;
+          double2 o = make_double2(cr[u][v], ci[u][v]);
+          if (scale) o = cmul(o, scale[pos]);
+          D[pos * RC + r] = o;
+        }
+      }
+    }
+  }
+}
+
+// W = (Ex^T Y Ey) ./ D from A into A (B as the intermediate stage).
+template <int RC, int NP, bool CPLX>
+__device__ __forceinline__ void fdm_forward(const double2* ex, const double2* ey, const double2* di, double2* A,
+                                            double2* B, int n) {
+  // B(i, iy) = sum_ix Ex(ix, i) Y(ix, iy): M(m = i, k = ix) = Ex(ix, i) at ix + LD i
+  fdm_contract<RC, NP, CPLX, true, true, false>(ex, A, B, n, nullptr);
+  __syncthreads();
+  // W(i, j) = sum_iy B(i, iy) Ey(iy, j): M(m = j, k = iy) = Ey(iy, j) at iy + LD j
+  fdm_contract<RC, NP, CPLX, false, false, false>(ey, B, A, n, di);
+  __syncthreads();
+}
+
+// X = Ex W Ey^T from A into A.
+template <int RC, int NP, bool CPLX>
+__device__ __forceinline__ void fdm_backward(const double2* ex, const double2* ey, double2* A, double2* B, int n) {
+  // Z(i', j) = sum_i Ex(i', i) W(i, j): M(m = i', k = i) at i' + LD i
+  fdm_contract<RC, NP, CPLX, true, true, true>(ex, A, B, n, nullptr);
+  __syncthreads();
+  // X(i', j') = sum_j Z(i', j) Ey(j', j): M(m = j', k = j) at j' + LD j
+  fdm_contract<RC, NP, CPLX, false, false, true>(ey, B, A, n, nullptr);
+  __syncthreads();
+}
+
+template <int RC, int NP>
+__device__ __forceinline__ void fdm_forward_any(bool real_e, const double2* ex, const double2* ey,
+                                                const double2* di, double2* A, double2* B, int n) {
+  if (real_e) fdm_forward<RC, NP, false>(ex, ey, di, A, B, n);
+  else fdm_forward<RC, NP, true>(ex, ey, di, A, B, n);
+}
+
+template <int RC, int NP>
+__device__ __forceinline__ void fdm_backward_any(bool real_e, const double2* ex, const double2* ey, double2* A,
+                                                 double2* B, int n) {
+  if (real_e) fdm_backward<RC, NP, false>(ex, ey, A, B, n);
+  else fdm_backward<RC, NP, true>(ex, ey, A, B, n);
+}
+
+// Shared memory of k_fdm_mf (double2 entries): two stages, the padded Ex and Ey
+// (NPMAX (NPMAX + 1) each), 1 / D (nmax^2), x_R (nrmax RC) and, for the two
+// passes of the element solve, K_e (nrmax^2).
+// Stage entries per column: the operand reads of a contraction reach position
+// n NP + NP + 16 at most (summation indices up to NP - 1, modes q up to the last
+// column tile), so a stage of that many positions per column, zero past n^2,
+// needs no bounds tests.
+__host__ __device__ inline int fdm_stage(int nmax, int npmax) { return nmax * npmax + npmax + 16; }
+
+__host__ __device__ inline size_t fdm_mf_entries(int nmax, int npmax, int nrmax, int rc, bool coarse) {
+  return size_t(2) * fdm_stage(nmax, npmax) * rc + size_t(2) * npmax * (npmax + 1) + size_t(nmax) * nmax +
+         size_t(nrmax) * rc + (coarse ? size_t(nrmax) * nrmax : 0);
+}
+
+// Loads of one item's coefficients kept in registers: entry i = threadIdx.x +
+// u NT of the item's n^2 x RC stage (the batch covers n^2 RC <= FDM_FB NT; larger
+// stages load the rest when they are staged).
+constexpr int FDM_FB = 8;
+
+template <int RC>
+__device__ __forceinline__ void fdm_prefetch(const FdmArgs& g, int e, int r0, double2 (&v)[FDM_FB]) {
+  const FdmRec fr = g.rec[e];
+  const int ny = fr.n * fr.n * RC, R = g.R, rc = min(RC, R - r0);
+  const double2* __restrict__ in = g.in + fr.base * R + r0;
+#pragma unroll
+  for (int u = 0; u < FDM_FB; ++u) {
+    const int i = threadIdx.x + u * NT;
+    const int t = i / RC, r = i - t * RC;
+    v[u] = (i < ny && r < rc) ? in[(int64_t)t * R + r] : make_double2(0, 0);
+  }
+}
+
+// One (element, RC columns) item of k_fdm_mf.  v holds the item's prefetched
+// coefficients and receives the next item's (next_e >= 0) once they are staged;
+// load_e: stage the class's eigenbases (skipped when the block's previous item
+// had the same class).
+template <int RC, int MODE, int NPMAX>
+__device__ __forceinline__ void fdm_item(const FdmArgs& g, int nmax, int nrmax, double2* sm, int e, int r0,
+                                         bool load_e, double2 (&v)[FDM_FB], int next_e, int next_r0) {
+  const int R = g.R;
+  const int rc = min(RC, R - r0);
+  const FdmRec fr = g.rec[e];   // one record per element: offsets and sizes of its class
+  const int n = fr.n, n2 = n * n;
+  const int np = (NPMAX == 32 && n > 16) ? 32 : 16;   // padding of this element's class
+  const int ld = np + 1;
+  const int nst = fdm_stage(nmax, NPMAX) * RC;
+  double2* A = sm;
+  double2* B = sm + nst;
+  double2* exs = B + nst;
+  double2* eys = exs + NPMAX * (NPMAX + 1);
+  double2* dis = eys + NPMAX * (NPMAX + 1);
+  double2* xs = dis + nmax * nmax;     // nrmax x RC: x_R (pass 1) or x_R - T w (pass 2)
+  double2* ks = xs + nrmax * RC;       // nrmax x nrmax: K_e (passes 1 and 2)
+  const bool real_e = fr.real != 0;
+  const int64_t base = fr.base;
+  const int nr = fr.nr;
+  const int cmo = fr.cmo;
+  // pass 2: x_R - T_e w of the thread's coarse-mode entries (formed by
+  // k_coarse_minus_tw), loaded before the staging
+  double2 gx[2] = {make_double2(0, 0), make_double2(0, 0)};
+  if (MODE == 2) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int idx = threadIdx.x + u * NT, a = idx / RC, r = idx - a * RC;
+      if (a < nr && r < rc) gx[u] = g.Xr[(int64_t)(cmo + a) * R + r0 + r];
+    }
+  }
+  const int ny = n2 * RC;
+  // the prefetched coefficients, then (only for stages larger than the
+  // prefetch) the rest, loads batched; the stage tails past n^2 are zero
+#pragma unroll
+  for (int u = 0; u < FDM_FB; ++u) {
+    const int i = threadIdx.x + u * NT;
+    if (i < ny) A[i] = v[u];
+  }
+  {
+    const double2* __restrict__ in = g.in + base * R + r0;
+    for (int i0 = threadIdx.x + FDM_FB * NT; i0 < ny; i0 += NT * FDM_FB) {
+      double2 w[FDM_FB];
+#pragma unroll
+      for (int u = 0; u < FDM_FB; ++u) {
+        const int i = i0 + u * NT;
+        const int t = i / RC, r = i - t * RC;
+        w[u] = (i < ny && r < rc) ? in[(int64_t)t * R + r] : make_double2(0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < FDM_FB; ++u) {
+        const int i = i0 + u * NT;
+        if (i < ny) A[i] = w[u];
+      }
+    }
+  }
+  if (load_e) {
+    // eigenbases zero-padded to np x np in columns of ld entries, 1 / D and,
+    // for the two passes, K_e
+    const double2* __restrict__ ex = g.Ex + fr.eoff;
+    const double2* __restrict__ ey = g.Ey + fr.eoff;
+    const double2* __restrict__ di = g.Dinv + fr.doff;
+    const double2* __restrict__ kc = g.Kc + fr.kc;
+    const int ne = np * ld, count = 2 * ne + n2 + (MODE != 0 ? nr * nr : 0);
+    for (int i0 = threadIdx.x; i0 < count; i0 += NT * FDM_FB) {
+      double2 w[FDM_FB];
+#pragma unroll
+      for (int u = 0; u < FDM_FB; ++u) {
+        const int j = i0 + u * NT;
+        w[u] = make_double2(0, 0);
+        if (j < 2 * ne) {
+          const int w2 = j >= ne, jj = j - w2 * ne;
+          const int a = jj % ld, b = jj / ld;
+          if (a < n && b < n) w[u] = (w2 ? ey : ex)[a + n * b];
+        } else if (j < 2 * ne + n2) {
+          w[u] = di[j - 2 * ne];
+        } else if (j < count) {
+          w[u] = kc[j - 2 * ne - n2];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < FDM_FB; ++u) {
+        const int j = i0 + u * NT;
+        if (j < ne) exs[j] = w[u];
+        else if (j < 2 * ne) eys[j - ne] = w[u];
+        else if (j < 2 * ne + n2) dis[j - 2 * ne] = w[u];
+        else if (j < count) ks[j - 2 * ne - n2] = w[u];
+      }
+    }
+  }
+  for (int i = ny + threadIdx.x; i < fdm_stage(n, np) * RC; i += NT) {
+    A[i] = make_double2(0, 0);
+    B[i] = make_double2(0, 0);
+  }
+  // the next item's coefficients are loaded while this one computes
+  if (next_e >= 0) fdm_prefetch<RC>(g, next_e, next_r0, v);
+  const int* rm = g.r_modes + fr.roff;
+  if (MODE == 2) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int idx = threadIdx.x + u * NT;
+      if (idx < nr * RC) xs[idx] = gx[u];
+    }
+    for (int idx = threadIdx.x + 2 * NT; idx < nr * RC; idx += NT) {
+      const int a = idx / RC, r = idx - a * RC;
+      xs[idx] = r < rc ? g.Xr[(int64_t)(cmo + a) * R + r0 + r] : make_double2(0, 0);
+    }
+  }
+  __syncthreads();
+  if (g.zero_coarse) {   // uniform over the grid
+    for (int idx = threadIdx.x; idx < nr * RC; idx += NT) {
+      const int a = idx / RC, r = idx - a * RC;
+      double2 y = make_double2(0, 0);
+      if (MODE == 2) {   // -mu = -K_e (x_R - T_e w)
+        for (int b = 0; b < nr; ++b) y = cfma(ks[a + nr * b], xs[b * RC + r], y);
+        y.x = -y.x;
+        y.y = -y.y;
+      }
+      A[rm[a] * RC + r] = y;
+    }
+    if (g.nu) {   // the element's dual slots (distinct modes, none of them coarse)
+      const int s0 = fr.s0, ns = fr.s1 - s0;
+      for (int idx = threadIdx.x; idx < ns * rc; idx += NT) {
+        const int q = idx / rc, r = idx - q * rc, sl = s0 + q;
+        const double2 a = g.nu[(int64_t)g.slot_row[sl] * R + r0 + r];
+        const double cf = g.slot_coef[sl];
+        double2& y = A[(int)(g.slot_pos[sl] - base) * RC + r];
+        y.x -= cf * a.x;
+        y.y -= cf * a.y;
+      }
+    }
+    __syncthreads();
+  }
+  if (NPMAX == 32 && np == 32) fdm_forward_any<RC, NPMAX>(real_e, exs, eys, dis, A, B, n);
+  else fdm_forward_any<RC, 16>(real_e, exs, eys, dis, A, B, n);
+  if (NPMAX == 32 && np == 32) fdm_backward_any<RC, NPMAX>(real_e, exs, eys, A, B, n);
+  else fdm_backward_any<RC, 16>(real_e, exs, eys, A, B, n);
+  if (MODE == 1) {
+    // x_R (the coarse-mode values of A~^-1 y) and GL = K_e x_R
+    for (int idx = threadIdx.x; idx < nr * RC; idx += NT) {
+      const int a = idx / RC, r = idx - a * RC;
+      const double2 x = A[rm[a] * RC + r];
+      xs[idx] = x;
+      if (r < rc) g.Xr[(int64_t)(cmo + a) * R + r0 + r] = x;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nr * rc; idx += NT) {
+      const int a = idx / rc, r = idx - a * rc;
+      double2 acc = make_double2(0, 0);
+      for (int b = 0; b < nr; ++b) acc = cfma(ks[a + nr * b], xs[b * RC + r], acc);
+      g.GL[(int64_t)(cmo + a) * R + r0 + r] = acc;
+    }
+    return;
+  }
+  double2* __restrict__ out = g.out + base * R + r0;
+  for (int idx = threadIdx.x; idx < n2 * rc; idx += NT) {
+    const int t = idx / rc, r = idx - t * rc;
+    out[(int64_t)t * R + r] = A[t * RC + r];
+  }
+}
+
+// The element solves as a persistent grid: each block takes the items (element
+// in class order, chunk of RC columns) blockIdx.x, blockIdx.x + gridDim.x, ...
+// (short-lived blocks would leave most compute units waiting on workgroup
+// dispatch); a block re-stages the eigenbases only when the class changes.
+template <int RC, int MODE, int NPMAX>
+__global__ void __launch_bounds__(NT) k_fdm_mf(FdmArgs g, int nmax, int nrmax, int nitems, int nchunk) {
+  extern __shared__ double2 sm[];
+  int cur = -1;
+  double2 v[FDM_FB];
+  int it = blockIdx.x;
+  int e = -1, r0 = 0;
+  if (it < nitems) {
+    const int pos = it / nchunk;
+    e = g.order[pos];
+    r0 = (it - pos * nchunk) * RC;
+    fdm_prefetch<RC>(g, e, r0, v);
+  }
+  for (; it < nitems; it += gridDim.x) {
+    const int itn = it + gridDim.x;
+    int ne = -1, nr0 = 0;
+    if (itn < nitems) {
+      const int pos = itn / nchunk;
+      ne = g.order[pos];
+      nr0 = (itn - pos * nchunk) * RC;
+    }
+    const int c = g.rec[e].cls;
+    fdm_item<RC, MODE, NPMAX>(g, nmax, nrmax, sm, e, r0, c != cur, v, ne, nr0);
+    cur = c;
+    e = ne;
+    r0 = nr0;
+    __syncthreads();   // the next item overwrites the stages
+  }
+}
+
+// Xr[i][r] -= sum_t T(i, t) w[t][r] for every coarse mode i (its expansion over
+// the coarse unknowns): the x_R - T_e w of the corrected element solve.
+__global__ void __launch_bounds__(NT) k_coarse_minus_tw(int ncm, int R, const int* __restrict__ t_ptr,
+                                                        const int* __restrict__ t_dof,
+                                                        const double* __restrict__ t_coef,
+                                                        const double2* __restrict__ w, double2* __restrict__ Xr) {
+  const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (idx >= (int64_t)ncm * R) return;
+  const int i = int(idx / R), r = int(idx - (int64_t)i * R);
+  double2 x = Xr[idx];
+  for (int t = t_ptr[i]; t < t_ptr[i + 1]; ++t) {
+    const double2 ww = w[(int64_t)t_dof[t] * R + r];
+    x.x -= t_coef[t] * ww.x;
+    x.y -= t_coef[t] * ww.y;
+  }
+  Xr[idx] = x;
+}
+
 __global__ void k_zero_R(int E, const int* __restrict__ elem_cls, const int64_t* __restrict__ dof_off,
                          const int* __restrict__ cls_nr, const int* __restrict__ cls_R,
                          const int* __restrict__ r_modes, double2* __restrict__ X, int R) {
@@ -2423,6 +2841,11 @@ __global__ void k_gmres_init(const double* __restrict__ nrm, double* __restrict_
 }
 
 inline unsigned nblocks(int64_t n, int t = NT) { return unsigned((n + t - 1) / t); }
+inline int pow2_at_least(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
 
 }  // namespace
 
@@ -2430,11 +2853,14 @@ inline unsigned nblocks(int64_t n, int t = NT) { return unsigned((n + t - 1) / t
 // shared memory of the matrix-core slot kernels at R columns, or 0 when they do
 // not apply (R not 16, 32 or 64, or an element's operand or output rows do not
 // fit: at most 64 KB and 16 output tiles per element)
-constexpr int SLOT_MF_RB = 32;   // columns per block (two blocks per element at 64)
+
+// columns per block of the matrix-core slot operators: the handle's choice
+// (16, 32 or 64; 32 unless tuned), at most R
+static int slot_rb(const Handle& h, int R) { return std::min(R, h.slot_rb); }
 
 static size_t slot_mfma_lds(const Handle& h, int R, int mode) {
   if (R < 16 || R % 16 != 0) return 0;
-  const int rb = std::min(R, SLOT_MF_RB);
+  const int rb = slot_rb(h, R);
   int rows = 0;   // operand and output rows: m + nr (interface operator) or max(m, nr)
   for (auto& C : h.classes) rows = std::max(rows, mode == 0 ? C.m + C.nr : std::max(C.m, C.nr));
   const size_t lds = size_t(rows) * rb * sizeof(double2);
@@ -2457,7 +2883,7 @@ void launch_slot_apply(const Handle& h, int mode, const T2* v, T2* X, T2* GL, in
   const auto& d = h.d;
   if constexpr (std::is_same<T2, double2>::value) {
     if (const size_t lds = slot_mfma_lds(h, R, mode)) {
-      const int rb = std::min(R, SLOT_MF_RB);
+      const int rb = slot_rb(h, R);
       const dim3 g(h.E, R / rb);
 #define HDP_MF_ARGS d.slot_blk, d.slot_in[mode], d.op1, d.se, d.phi, d.t_ptr, d.t_dof, d.t_coef, v, nullptr, X, GL, R, rb
       if (mode == 0) hipLaunchKernelGGL(k_slot_mfma<0>, g, dim3(NT), lds, s, HDP_MF_ARGS);
@@ -2508,7 +2934,7 @@ void launch_slot_coarse(const Handle& h, const T2* X, const double2* w, T2* Z, i
   const auto& d = h.d;
   if constexpr (std::is_same<T2, double2>::value) {
     if (const size_t lds = slot_mfma_lds(h, R, 3)) {
-      const int rb = std::min(R, SLOT_MF_RB);
+      const int rb = slot_rb(h, R);
       hipLaunchKernelGGL(k_slot_mfma<3>, dim3(h.E, R / rb), dim3(NT), lds, s, d.slot_blk, nullptr, d.op1, d.se,
                          d.phi, d.t_ptr, d.t_dof, d.t_coef, w, X, Z, nullptr, R, rb);
       HIPCHECK(hipGetLastError());
@@ -2657,6 +3083,99 @@ void launch_fdm(const Handle& h, const double2* in, double2* out, int R, hipStre
     hipLaunchKernelGGL(k_fdm<false>, grid, dim3(NT), shm, s, d.elem_cls, d.dof_off, d.cls_n, d.cls_E, d.cls_D, d.Ex,
                        d.Ey, d.Dinv, in, out, R, rch, d.cls_nr, d.cls_R, d.r_modes, zc, d.slot_off, d.slot_pos,
                        d.slot_row, d.slot_coef, zero_coarse ? nu : nullptr);
+  HIPCHECK(hipGetLastError());
+}
+
+static size_t fdm_mf_lds(const Handle& h, int rc, bool coarse);
+
+// Matrix-core element solves: classes of at most 32 modes per direction, and
+// (coarse: the two passes, which keep K_e in shared memory) one column's
+// shared memory within the 160 KiB of a compute unit.
+bool fdm_mf_ok(const Handle& h, bool coarse) {
+  for (auto& C : h.classes)
+    if (C.n > 32) return false;
+  return fdm_mf_lds(h, 1, coarse) <= 160 * 1024;
+}
+
+static int fdm_npmax(const Handle& h) {
+  int nmax = 1;
+  for (auto& C : h.classes) nmax = std::max(nmax, C.n);
+  return nmax <= 16 ? 16 : 32;
+}
+
+static int fdm_nrmax(const Handle& h) {
+  int nrmax = 1;
+  for (auto& C : h.classes) nrmax = std::max(nrmax, C.nr);
+  return nrmax;
+}
+
+static int fdm_nmax(const Handle& h) {
+  int nmax = 1;
+  for (auto& C : h.classes) nmax = std::max(nmax, C.n);
+  return nmax;
+}
+
+static size_t fdm_mf_lds(const Handle& h, int rc, bool coarse) {
+  return fdm_mf_entries(fdm_nmax(h), fdm_npmax(h), fdm_nrmax(h), rc, coarse) * sizeof(double2);
+}
+
+// Columns per block: the autotuned or requested choice when one is set, else
+// the largest power of two up to 8 (and up to R) whose shared memory stays
+// within 80 KiB (two blocks per compute unit).
+int fdm_mf_rc(const Handle& h, int R) {
+  const int cap = std::min(16, pow2_at_least(R));
+  const bool coarse = fdm_mf_ok(h, true);
+  if (h.fdm_rc > 0 && h.fdm_rc <= cap && fdm_mf_lds(h, h.fdm_rc, coarse) <= 160 * 1024) return h.fdm_rc;
+  int rc = 1;
+  while (rc * 2 <= std::min(cap, 8) && fdm_mf_lds(h, rc * 2, coarse) <= 80 * 1024) rc *= 2;
+  return rc;
+}
+
+void launch_fdm_mf(const Handle& h, int mode, const double2* in, double2* out, int R, hipStream_t s,
+                   const double2* nu, const double2* w, int rc) {
+  const int np = fdm_npmax(h), nrmax = fdm_nrmax(h), nmax = fdm_nmax(h);
+  if (!fdm_mf_ok(h, mode != 0)) fail(HDP_E_UNSUPPORTED, "matrix-core element solve: class too large");
+  if (rc <= 0) rc = fdm_mf_rc(h, R);
+  const size_t shm = fdm_mf_lds(h, rc, mode != 0);
+  if (shm > 160 * 1024) rc = 1;
+  const size_t shm1 = fdm_mf_lds(h, rc, mode != 0);
+  if (shm1 > 160 * 1024) fail(HDP_E_UNSUPPORTED, "matrix-core element solve: shared memory exceeded");
+  const auto& d = h.d;
+  if (mode == 2) {   // x_R - T_e w in place, before the corrected solve
+    hipLaunchKernelGGL(k_coarse_minus_tw, dim3(nblocks(int64_t(h.ncm) * R)), dim3(NT), 0, s, h.ncm, R, d.t_ptr,
+                       d.t_dof, d.t_coef, w, d.cmX);
+    HIPCHECK(hipGetLastError());
+  }
+  FdmArgs a{d.fdm_rec, d.order, d.elem_cls, d.dof_off, d.cls_n, d.cls_E, d.cls_D, d.Ex, d.Ey, d.Dinv, d.cls_real, in, out, R,
+            d.cls_nr, d.cls_R, d.r_modes, mode != 0 ? 1 : 0, d.slot_off, d.slot_pos, d.slot_row, d.slot_coef,
+            mode != 0 ? nu : nullptr, d.cm_off, d.cls_Kc, d.Kc, d.cmX, d.cmA, d.t_ptr, d.t_dof, d.t_coef, w};
+  const int nchunk = (R + rc - 1) / rc, nitems = h.E * nchunk;
+  // blocks resident at once: shared memory and 3 waves per SIMD allow this many per compute unit
+  const int per_cu = std::max(1, std::min(3, int((160 * 1024) / shm1)));
+  const dim3 grid(std::min(nitems, 256 * per_cu));
+#define HDP_FDM_LAUNCH(RCV, NPV)                                                                                 \
+  if (mode == 0) hipLaunchKernelGGL((k_fdm_mf<RCV, 0, NPV>), grid, dim3(NT), shm1, s, a, nmax, nrmax, nitems, nchunk);  \
+  else if (mode == 1)                                                                                            \
+    hipLaunchKernelGGL((k_fdm_mf<RCV, 1, NPV>), grid, dim3(NT), shm1, s, a, nmax, nrmax, nitems, nchunk);               \
+  else hipLaunchKernelGGL((k_fdm_mf<RCV, 2, NPV>), grid, dim3(NT), shm1, s, a, nmax, nrmax, nitems, nchunk);
+#define HDP_FDM_CASE(RCV)            \
+  case RCV:                          \
+    if (np == 16) {                  \
+      HDP_FDM_LAUNCH(RCV, 16)        \
+    } else {                         \
+      HDP_FDM_LAUNCH(RCV, 32)        \
+    }                                \
+    break;
+  switch (rc) {
+    HDP_FDM_CASE(1)
+    HDP_FDM_CASE(2)
+    HDP_FDM_CASE(4)
+    HDP_FDM_CASE(8)
+    HDP_FDM_CASE(16)
+    default: fail(HDP_E_ARG, "element solve: columns per block must be 1, 2, 4, 8 or 16");
+  }
+#undef HDP_FDM_CASE
+#undef HDP_FDM_LAUNCH
   HIPCHECK(hipGetLastError());
 }
 

@@ -1120,7 +1120,15 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
     h.flops_F += 8.0 * (C.m + C.nr) * C.m;
     h.flops_P += 4.0 * C.m * C.m;
     h.flops_coarse += 8.0 * C.m * C.nr;
-    h.flops_fdm += 4.0 * 8.0 * double(C.n) * C.n * C.n;
+    // the separable solve: four one-index contractions, 4 n^3 flops each with a
+    // real eigenbasis acting on complex coefficients, 8 n^3 with a complex one
+    bool real_e = true;
+    for (auto& v : C.Ex.a) real_e = real_e && v.imag() == 0.0;
+    for (auto& v : C.Ey.a) real_e = real_e && v.imag() == 0.0;
+    const double n3 = double(C.n) * C.n * C.n;
+    h.flops_fdm += (real_e ? 16.0 : 32.0) * n3;
+    // its coarse pass: two contractions, the lines i < 2 and j < 2, K_e x_R
+    h.flops_fdm_coarse += (real_e ? 8.0 : 16.0) * n3 + 64.0 * C.n * C.n + 8.0 * C.nr * (C.n + C.nr);
     h.flops_gll += 2.0 * 4.0 * double(C.n) * C.n * C.n;
   }
   // quadrature tables for the loads, one per degree present
