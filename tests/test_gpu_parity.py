@@ -282,7 +282,7 @@ def test_point_source_32x32_against_stored_oracle_samples():
         else:
             meta[t[0]] = int(t[1])
     w = W.point_source_32x32()
-    s = hdp().Solver(w, tol=1e-12, max_iter=400)
+    s = hdp().Solver(w, tol=1e-13, max_iter=400)
     assert (s.n_lambda, s.n_coarse, s.info["l"]) == (meta["n_lambda"], meta["n_coarse"], meta["l"])
     rng = np.random.default_rng(meta["vector_seed"])
     v = rng.standard_normal(s.n_lambda) + 1j * rng.standard_normal(s.n_lambda)
@@ -296,13 +296,17 @@ def test_point_source_32x32_against_stored_oracle_samples():
     f, st = s.solve("point", [0.5, 0.5])
     g = f.cpu().numpy()[0]
     idx, vals = zip(*field)
-    assert rel(g[list(idx)], vals) < 1e-9
+    # both sides driven to a preconditioned residual of 1e-13
+    assert rel(g[list(idx)], vals) < 1e-10
     assert st["converged"]
     # At this size the residual history is sensitive at the rounding level:
     # the oracle itself needs 111 -> 120 iterations (to 1e-8) and 149 -> 157
     # (to 1e-12) when F's output carries 1e-11 relative noise.  Iteration
     # counts are therefore compared within that measured band.
-    assert abs(st["iterations"] - meta["iterations_1e-12"]) <= 10
+    hist = s.residual_history(0)
+    it12 = next(i for i, h in enumerate(hist) if h <= 1e-12)
+    assert abs(it12 - meta["iterations_1e-12"]) <= 10
+    assert abs(st["iterations"] - meta["iterations_1e-13"]) <= 10
     s.close()
     s8 = hdp().Solver(w, tol=1e-8, max_iter=400)
     _, st8 = s8.solve("point", [0.5, 0.5], want_field=False)
