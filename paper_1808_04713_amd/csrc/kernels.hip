@@ -322,6 +322,112 @@ __global__ void __launch_bounds__(NT) k_slot_mfma(const SlotBlock* __restrict__ 
   }
 }
 
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// The slot operators of the mixed-precision path at 16, 32 or 64 right-hand
+// sides on the FP32 matrix cores (FP32 operators and operands, FP32
+// accumulation), laid out as k_slot_mfma: the K x RB operand in shared memory
+// with R fastest, out = Mat operand, a step of 4 summation rows as four real
+// 16x16x4 FP32 operations per complex tile.  The FP32 operation returns, in lane
+// l and value v, row 4 (l >> 4) + v (the operand column) and column l & 15 (the
+// row of Mat) of its 16 x 16 tile.  VT is the operand source type: FP32 dual or
+// slot values, or (MODE 3) the FP64 coarse solution gathered through T.
+template <int MODE, class VT>
+__global__ void __launch_bounds__(NT) k_slot_mfma32(const SlotBlock* __restrict__ blk,
+                                                    const SlotIn* __restrict__ sin, const float2* __restrict__ op1,
+                                                    const float2* __restrict__ se, const float2* __restrict__ phi,
+                                                    const int* __restrict__ t_ptr, const int* __restrict__ t_dof,
+                                                    const double* __restrict__ t_coef, const VT* __restrict__ v,
+                                                    const float2* __restrict__ Xin, float2* __restrict__ X,
+                                                    float2* __restrict__ GL, int R, int RB) {
+  extern __shared__ float2 buf32[];
+  const int r0 = blockIdx.y * RB;
+  const SlotBlock B = blk[blockIdx.x];
+  const int m = B.m, nr = B.nr, so = B.so;
+  const int K = MODE == 3 ? nr : m;
+  const int nrow = MODE == 0 ? m + nr : m;
+  const float2* Mat = MODE == 0 ? op1 + B.op1 : (MODE == 3 ? phi + B.phi : se + B.se);
+  for (int idx = threadIdx.x; idx < K * RB; idx += NT) {
+    const int kk = idx / RB, r = idx - kk * RB;
+    float ax = 0, ay = 0;
+    if (MODE == 3) {
+      const int co = B.cmo + kk;
+      double sx = 0, sy = 0;
+      for (int t = t_ptr[co]; t < t_ptr[co + 1]; ++t) {
+        const VT a = v[(int64_t)t_dof[t] * R + r0 + r];
+        sx += t_coef[t] * a.x;
+        sy += t_coef[t] * a.y;
+      }
+      ax = float(sx);
+      ay = float(sy);
+    } else {
+      const SlotIn g = sin[so + kk];
+      if (g.s0 >= 0) {
+        const VT z = v[(int64_t)g.s0 * R + r0 + r];
+        ax += float(g.a0) * z.x;
+        ay += float(g.a0) * z.y;
+      }
+      if (MODE == 2 && g.s1 >= 0) {
+        const VT z = v[(int64_t)g.s1 * R + r0 + r];
+        ax += float(g.a1) * z.x;
+        ay += float(g.a1) * z.y;
+      }
+    }
+    buf32[idx] = make_float2(ax, ay);
+  }
+  __syncthreads();
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int jl = l & 15, kq = l >> 4;
+  const int nit = (nrow + 15) >> 4, nrt = RB >> 4, ntile = nit * nrt;
+  f4 cr[4], ci[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    cr[q] = (f4){0, 0, 0, 0};
+    ci[q] = (f4){0, 0, 0, 0};
+  }
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const int kk = k0 + kq;
+    const bool kv = kk < K;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int tile = wv + 4 * q;
+      if (tile >= ntile) break;   // uniform over the wave
+      const int it = tile / nrt, rt = tile - it * nrt;
+      const int i = 16 * it + jl;
+      const float2 b = (kv && i < nrow) ? Mat[i + (int64_t)nrow * kk] : make_float2(0, 0);
+      const float2 a = kv ? buf32[kk * RB + 16 * rt + jl] : make_float2(0, 0);
+      cr[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, cr[q], 0, 0, 0);
+      ci[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, ci[q], 0, 0, 0);
+      cr[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, cr[q], 0, 0, 0);
+      ci[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, ci[q], 0, 0, 0);
+    }
+  }
+  __syncthreads();   // every wave is done with the operand
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int tile = wv + 4 * q;
+    if (tile >= ntile) break;
+    const int it = tile / nrt, rt = tile - it * nrt;
+    const int i = 16 * it + jl;
+    if (i < nrow) {
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) buf32[i * RB + 16 * rt + 4 * kq + vv] = make_float2(cr[q][vv], ci[q][vv]);
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < nrow * RB; idx += NT) {
+    const int i = idx / RB, r = idx - i * RB;
+    float2 o = buf32[idx];
+    if (MODE == 3) {
+      const float2 x = Xin[(int64_t)(so + i) * R + r0 + r];
+      o.x += x.x;
+      o.y += x.y;
+    }
+    if (MODE != 0 || i < m) X[(int64_t)(so + i) * R + r0 + r] = o;
+    else GL[(int64_t)(B.cmo + i - m) * R + r0 + r] = o;
+  }
+}
+
 // k_slot_coarse with the coarse solution taken straight from the partial sums
 // of the tiled coarse apply (one right-hand side): w[d] = sum_J P[d / 64][J][d % 64],
 // each coarse mode's sum split over SCP thread groups and added in a fixed
@@ -2894,6 +3000,19 @@ void launch_slot_apply(const Handle& h, int mode, const T2* v, T2* X, T2* GL, in
       return;
     }
   }
+  if constexpr (std::is_same<T2, float2>::value) {
+    if (const size_t lds = slot_mfma_lds(h, R, mode)) {   // FP32 operands: half the bytes of the FP64 sizing
+      const int rb = slot_rb(h, R);
+      const dim3 g(h.E, R / rb);
+#define HDP_MF32_ARGS d.slot_blk, d.slot_in[mode], d.op1_f, d.se_f, d.phi_f, d.t_ptr, d.t_dof, d.t_coef, v, nullptr, X, GL, R, rb
+      if (mode == 0) hipLaunchKernelGGL((k_slot_mfma32<0, float2>), g, dim3(NT), lds / 2, s, HDP_MF32_ARGS);
+      else if (mode == 1) hipLaunchKernelGGL((k_slot_mfma32<1, float2>), g, dim3(NT), lds / 2, s, HDP_MF32_ARGS);
+      else hipLaunchKernelGGL((k_slot_mfma32<2, float2>), g, dim3(NT), lds / 2, s, HDP_MF32_ARGS);
+#undef HDP_MF32_ARGS
+      HIPCHECK(hipGetLastError());
+      return;
+    }
+  }
   const T2* op1;
   const T2* se;
   if constexpr (std::is_same<T2, double2>::value) { op1 = d.op1; se = d.se; }
@@ -2937,6 +3056,15 @@ void launch_slot_coarse(const Handle& h, const T2* X, const double2* w, T2* Z, i
       const int rb = slot_rb(h, R);
       hipLaunchKernelGGL(k_slot_mfma<3>, dim3(h.E, R / rb), dim3(NT), lds, s, d.slot_blk, nullptr, d.op1, d.se,
                          d.phi, d.t_ptr, d.t_dof, d.t_coef, w, X, Z, nullptr, R, rb);
+      HIPCHECK(hipGetLastError());
+      return;
+    }
+  }
+  if constexpr (std::is_same<T2, float2>::value) {
+    if (const size_t lds = slot_mfma_lds(h, R, 3)) {
+      const int rb = slot_rb(h, R);
+      hipLaunchKernelGGL((k_slot_mfma32<3, double2>), dim3(h.E, R / rb), dim3(NT), lds / 2, s, d.slot_blk, nullptr,
+                         d.op1_f, d.se_f, d.phi_f, d.t_ptr, d.t_dof, d.t_coef, w, X, Z, nullptr, R, rb);
       HIPCHECK(hipGetLastError());
       return;
     }

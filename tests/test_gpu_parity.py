@@ -80,6 +80,25 @@ def test_local_solve_separable(name, oracles):
 
 
 @pytest.mark.parametrize("R", [16, 32, 64])
+@pytest.mark.parametrize("name", ["uniform_4x4_p6_l2", "scatterer_6x6_p6"])
+def test_fp32_operators_at_many_columns(name, R, oracles):
+    """F v and P^-1 v of the mixed path at 16, 32 and 64 columns (the FP32
+    matrix-core slot kernels, FP32 accumulation) against the oracle column by
+    column, at FP32 accuracy."""
+    disc, l, E = oracles[name]
+    s = hdp().Solver(CASES[name], max_rhs=R)
+    rng = np.random.default_rng(R + 1)
+    v = rng.standard_normal((E.nlam, R)) + 1j * rng.standard_normal((E.nlam, R))
+    vd = torch.from_numpy(v).cuda()
+    Fv = s.apply_interface(vd, "mixed").cpu().numpy()
+    Pv = s.apply_precond(vd, "mixed").cpu().numpy()
+    for r in range(R):
+        assert rel(Fv[:, r], E.apply_F(v[:, r])) < 1e-5
+        assert rel(Pv[:, r], E.apply_P(v[:, r])) < 1e-5
+    s.close()
+
+
+@pytest.mark.parametrize("R", [16, 32, 64])
 @pytest.mark.parametrize("name", ["uniform_4x4_p6_l2", "uniform_5x5_p7_l3"])
 def test_operators_at_many_columns(name, R, oracles):
     """F v and P^-1 v at 16, 32 and 64 columns (the matrix-core slot kernels)
