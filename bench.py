@@ -29,10 +29,30 @@ FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 HBM_FAMILIES = {"coarse_gemv", "coarse_reduce", "coarse_assemble", "row_gather", "gmres_dots", "gmres_update",
                 "gmres_norm_scale", "element_coarse_fix", "precision_cast", "hanging_blocks"}
-# HBM bytes per launch of a kernel family on the point-source workload, from the
-# rocprofv3 FETCH_SIZE / WRITE_SIZE runs calibrated on a plain 512 MiB copy
-# (profiles/point_source_32x32_kernel_stats.md); valid for the kernels as profiled
-MEASURED_TRAFFIC = {"coarse_gemv": 9.0412e7, "gmres_dots": 3.1957e7}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "point_source_32x32_hbm_counters.md")
+
+
+def kernels_digest():
+    """Digest of the kernel source; counter figures taken on another source are stale."""
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1808_04713_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the kernel families recorded in the point-source
+    counter summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), if that
+    summary was taken on the current kernel source; else {}."""
+    out, digest = {}, None
+    if not os.path.exists(TRAFFIC_FILE):
+        return out
+    for line in open(TRAFFIC_FILE):
+        t = line.split()
+        if len(t) == 3 and t[0] == "traffic_per_launch":
+            out[t[1]] = float(t[2])
+        elif len(t) == 2 and t[0] == "kernels_sha256_16":
+            digest = t[1]
+    return out if digest == kernels_digest() else {}
 
 
 def load_samples():
@@ -82,24 +102,35 @@ def time_path(hdp, torch, w, precision, steps, warmup, samples):
     return out, info
 
 
-def roofline(kernels, precision, name=None):
+def roofline(kernels, precision, info, name=None):
+    """Roofline of the dominant kernel family (or `name`).  The coarse solve is
+    credited with the bytes of the method's own coarse factor (a banded LU of K
+    in its natural order, from the library's set-up statistics), not with the
+    dense inverse this build streams; other families with their algorithmic
+    bytes and flops."""
     live = [k for k in kernels if k["launches"] > 0]
     dom = max(live, key=lambda k: k["total_ms"]) if name is None else next(k for k in live if k["name"] == name)
     avg_ms = dom["total_ms"] / dom["launches"]
     bytes_per = dom["bytes"] / dom["launches"]
     flops_per = dom["flops"] / dom["launches"]
+    method_bytes = bytes_per
+    if dom["name"] == "coarse_gemv":
+        method_bytes = info["coarse_band_bytes"] + 32.0 * info["n_coarse"]   # factor + g and w
     ai = flops_per / bytes_per if bytes_per else float("inf")
     peak_tf = FP64_PEAK_TFLOPS if precision == "fp64" else FP32_PEAK_TFLOPS
     ridge = peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9)
     if dom["name"] in HBM_FAMILIES or ai < ridge:
-        achieved = bytes_per / (avg_ms * 1e-3) / 1e9
+        achieved = method_bytes / (avg_ms * 1e-3) / 1e9
         r = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s")
     else:
         achieved = flops_per / (avg_ms * 1e-3) / 1e12
-        r = dict(bound="alu", achieved=achieved, peak=peak_tf, unit="TFLOP/s")
-    r.update(frac=r["achieved"] / r["peak"], traffic=MEASURED_TRAFFIC.get(dom["name"]), kernel=dom["name"],
+        r = dict(bound="mfma", achieved=achieved, peak=peak_tf, unit="TFLOP/s")
+    traffic = measured_traffic().get(dom["name"])
+    r.update(frac=r["achieved"] / r["peak"], traffic=traffic, kernel=dom["name"],
              avg_launch_us=avg_ms * 1e3, launches_per_step=None,
-             algorithmic_bytes_per_launch=bytes_per, algorithmic_flops_per_launch=flops_per,
+             algorithmic_bytes_per_launch=method_bytes, kernel_bytes_per_launch=bytes_per,
+             kernel_stream_frac=bytes_per / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+             algorithmic_flops_per_launch=flops_per,
              share_of_kernel_time=dom["total_ms"] / sum(k["total_ms"] for k in live))
     return r
 
@@ -320,6 +351,32 @@ def cpu_baseline():
                        f"{E.iters} iterations, host cpu_count={os.cpu_count()}")
 
 
+def cpu_baseline_full():
+    """The oracle on whole workloads (not part of the default run): the 4x4
+    plane wave and the 32x32 point source, set-up and solve to 1e-8 timed
+    separately, on this host's cores."""
+    import workloads as W
+    from oracle import dp_elementwise as dpe, problem as pb
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    out = {"cores": int(threads), "cpu_count": os.cpu_count(), "kind": "oracle"}
+    for name, w in (("plane_wave_4x4", W.plane_wave_4x4()), ("point_source_32x32", W.point_source_32x32())):
+        t0 = time.perf_counter()
+        disc = pb.Discretisation(w)
+        E = dpe.ElementwiseDP(disc, pb.coarse_order(w, disc.mesh))
+        t1 = time.perf_counter()
+        E.solve(tol=1e-8, max_iter=400)
+        t2 = time.perf_counter()
+        dof = int(sum((int(p) + 1) ** 2 for p in w["degree"]))
+        out[name] = dict(dof=dof, setup_s=t1 - t0, solve_s=t2 - t1, iterations=E.iters,
+                         dof_per_s_solve=dof / (t2 - t1), dof_per_s_setup_and_solve=dof / (t2 - t0))
+        print(f"bench: oracle {name} done ({t2 - t0:.1f} s)", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -330,6 +387,8 @@ def main():
                     help="skip the refined-disk and 64-angle batched scatterer measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy three times (HBM counter calibration)")
+    ap.add_argument("--cpu-baseline-full", action="store_true",
+                    help="only time the oracle on the whole 4x4 and 32x32 workloads (minutes) and print the record")
     ap.add_argument("--only", choices=["refined_disk", "scatterer", "design", "robin", "pml"],
                     help="profiling aid: run only this secondary workload and print its record")
     args = ap.parse_args()
@@ -343,6 +402,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read_per_launch": 16 * n, "copy_bytes_written_per_launch": 16 * n,
                           "launches": 3}), flush=True)
+        return
+    if args.cpu_baseline_full:
+        print(json.dumps(cpu_baseline_full()), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the multi-GPU path is not part of this build "
@@ -383,13 +445,12 @@ def main():
         "mixed_vs_fp64_speedup": fp64["ms_per_solve"] / mixed["ms_per_solve"],
         "paths": {k: {kk: vv for kk, vv in v.items() if kk != "kernels"} for k, v in
                   (("fp64", fp64), ("mixed", mixed))},
-        "roofline": roofline(best["kernels"], best_name),
-        "roofline_coarse": roofline(best["kernels"], best_name, "coarse_gemv"),
+        "roofline": roofline(best["kernels"], best_name, info),
+        "roofline_krylov": {k: roofline(best["kernels"], best_name, info, k) for k in ("gmres_dots", "gmres_update")},
         "kernels": sorted([k for k in best["kernels"] if k["launches"]], key=lambda k: -k["total_ms"]),
     }
-    for key in ("roofline", "roofline_coarse"):
-        line[key]["launches_per_step"] = next(
-            k["launches"] for k in best["kernels"] if k["name"] == line[key]["kernel"]) / args.steps
+    for r in [line["roofline"]] + list(line["roofline_krylov"].values()):
+        r["launches_per_step"] = next(k["launches"] for k in best["kernels"] if k["name"] == r["kernel"]) / args.steps
     if not args.no_batched:
         line["nonconforming"] = refined_disk(hdp, torch, max(1, min(args.steps, 5)), min(args.warmup, 1))
         line["adjoint_gradient"] = design_gradient(hdp, torch, max(1, min(args.steps, 5)), min(args.warmup, 1))

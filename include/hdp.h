@@ -189,6 +189,10 @@ typedef struct {
   double coarse_residual;     /* setup check of the coarse factor: ||K x - b|| / ||b|| */
   int32_t coarse_mode;        /* 0 dense inverse, 1 block-tridiagonal strips, 2 nested dissection */
   int32_t coarse_blocks;      /* strips, or nested-dissection tree nodes (1 for the dense inverse) */
+  double coarse_factor_bytes; /* bytes of the coarse factor as stored (dense inverse, strips or
+                                 nested-dissection fronts) */
+  double coarse_band_bytes;   /* bytes of a banded (envelope) LU factor of K in its natural order:
+                                 what one coarse solve with the paper's plain factorisation reads */
 } hdp_stats;
 
 typedef struct hdp_handle hdp_handle;

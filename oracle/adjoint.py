@@ -47,17 +47,27 @@ def far_functional(mesh, degrees, k, inside, angle, extra_nodes=12):
     return g
 
 
-def eps_gradient(w, incidence, far_angle, inside):
+def eps_gradient(w, incidence, far_angle, inside, solver="direct", tol=1e-13):
     """(J, dJ/d eps_r per element) for the scattered field of the plane wave with
     propagation angle ``incidence``; ``inside`` marks the region whose boundary
-    carries the far-field integral."""
+    carries the far-field integral.  solver: "direct" (dense null-space solve of
+    the conforming system, small meshes) or "elementwise" (the element-by-element
+    dual-primal method driven to ``tol``, conforming meshes of any size; the
+    adjoint solve reuses its factorisations)."""
     w = dict(w, rhs=dict(kind="plane_wave_scattered", angles=[incidence]))
     disc = pb.Discretisation(w)
     mesh, k = disc.mesh, disc.k
-    phi = conforming_solution(disc)
     g = far_functional(mesh, disc.degrees, k, inside, far_angle)
+    if solver == "direct":
+        phi = conforming_solution(disc)
+        lam = conforming_solution(disc, loads=g)
+    else:
+        from .dp_elementwise import ElementwiseDP
+        D = ElementwiseDP(disc, pb.coarse_order(w, mesh))
+        phi = D.solve(tol=tol, max_iter=400)
+        D.set_loads(g)
+        lam = D.solve(tol=tol, max_iter=400)
     E = sum(ge @ pe for ge, pe in zip(g, phi))
-    lam = conforming_solution(disc, loads=g)
     d = np.array([np.cos(incidence), np.sin(incidence)])
     grad = np.zeros(mesh.E)
     for e in range(mesh.E):

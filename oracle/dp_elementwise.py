@@ -81,6 +81,15 @@ class ElementwiseDP:
         self.nlam = self.C1.shape[0]
         self.X = np.asarray(self.C1.multiply(self.C1).sum(axis=1)).ravel()
 
+    def set_loads(self, loads):
+        """Replace the element loads (one vector per element, paper basis) while
+        keeping every factorisation: the right-hand side of an adjoint solve."""
+        for e in range(self.mesh.E):
+            n = int(self.deg[e]) + 1
+            bt = el.to_vertex_basis(n) @ loads[e]
+            self.b1[e] = bt[self.I[e]]
+            self.bR[e] = bt[self.R[e]]
+
     def _coarse_maps(self, status):
         mesh, deg = self.mesh, self.deg
         ids = {}

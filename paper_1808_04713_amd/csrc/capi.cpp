@@ -621,6 +621,7 @@ void build_device(Handle& h) {
   std::vector<double2> kval;
   coarse_coo(h, kidx, kval);
   size_t nK = size_t(h.nK);
+  h.coarse_band_bytes = coarse_band_bytes(h.nK, kidx);
   rocblas_handle rb;
   if (rocblas_create_handle(&rb) != rocblas_status_success) fail(HDP_E_DEVICE, "rocblas_create_handle");
   rocblas_set_stream(rb, h.stream);
@@ -1356,6 +1357,12 @@ hdp_status hdp_inspect(const hdp_mesh* mesh, const hdp_problem* prob, hdp_stats*
   if (!st) fail(HDP_E_ARG, "null stats");
   hdp_handle H;
   build_host(H.h, mesh, prob);
+  {
+    std::vector<int64_t> kidx;
+    std::vector<double2> kval;
+    coarse_coo(H.h, kidx, kval);
+    H.h.coarse_band_bytes = coarse_band_bytes(H.h.nK, kidx);
+  }
   return hdp_get_stats(&H, st);
   API_END
 }
@@ -1375,6 +1382,8 @@ hdp_status hdp_get_stats(const hdp_handle* H, hdp_stats* st) {
   st->setup_ms = h.setup_ms;
   st->coarse_residual = h.coarse_check;
   st->coarse_mode = h.coarse_mode >= 0 ? h.coarse_mode : (h.nK > 6000 ? 2 : 0);
+  st->coarse_band_bytes = h.coarse_band_bytes;
+  st->coarse_factor_bytes = h.coarse_bytes;
   st->coarse_blocks = st->coarse_mode == 1   ? int(h.cb_off.size()) - 1
                       : st->coarse_mode == 2 ? int(h.nd_off.size()) - 1
                                              : 1;

@@ -196,6 +196,7 @@ struct Handle {
   int sym_nt = 0, sym_ntiles = 0;   // tile rows and upper tiles of the symmetric coarse inverse
   double coarse_bytes1 = 0;         // factor bytes of a one-RHS coarse solve (half with the tiles)
   double coarse_bytes = 0, coarse_flops = 0;   // per coarse solve and RHS column (flops), factor bytes
+  double coarse_band_bytes = 0;   // a banded (envelope) LU factor of K in natural order, bytes
   // C_2 (dual rows x coarse unknowns), non-zero only on hanging edges
   std::vector<int> c2_ptr, c2_dof, c2t_ptr, c2t_row;
   std::vector<double> c2_coef, c2t_coef;
@@ -376,6 +377,7 @@ void* scratch_ptr(int device);
 void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob);
 // Coarse matrix K = sum_e T_e^T Kc_e T_e as sorted COO (key = row + nK * col).
 void coarse_coo(const Handle& h, std::vector<int64_t>& kidx, std::vector<double2>& kval);
+double coarse_band_bytes(int nK, const std::vector<int64_t>& kidx);
 
 // coarse_nd.cpp: the nested-dissection factor assembled on the host.  Per node
 // the blocks Dinv (nI x nI), L (nB x nI) and Lt = L^T, row-major, back to back in

@@ -636,6 +636,21 @@ void coarse_coo(const Handle& h, std::vector<int64_t>& kidx, std::vector<double2
   }
 }
 
+// Bytes of a banded (envelope) LU factor of K in its natural order: row i of L
+// spans columns first_i..i, and U mirrors it (K is structurally symmetric); what
+// one coarse solve with such a factor reads.  kidx: sorted COO keys row + nK col.
+double coarse_band_bytes(int nK, const std::vector<int64_t>& kidx) {
+  std::vector<int> first(static_cast<size_t>(nK));
+  for (int i = 0; i < nK; ++i) first[size_t(i)] = i;
+  for (int64_t key : kidx) {
+    const int64_t r = key % nK, c = key / nK;
+    first[size_t(r)] = std::min(first[size_t(r)], int(c));
+  }
+  double env = 0;
+  for (int i = 0; i < nK; ++i) env += double(i - first[size_t(i)] + 1);
+  return 16.0 * (2.0 * env - double(nK));
+}
+
 void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
   if (!mesh || !prob || !mesh->leaf || !mesh->degree) fail(HDP_E_ARG, "null mesh or problem");
   int E = mesh->n_leaves;

@@ -42,3 +42,18 @@ def test_adjoint_gradient_equals_central_differences():
         assert abs(fd - grad[e]) < 1e-6 * max(abs(grad).max(), 1e-30)
     # elements outside the design region get gradients too (eps enters every element)
     assert np.abs(grad[~inside]).max() > 0
+
+
+def test_elementwise_adjoint_equals_direct_adjoint():
+    """The element-by-element dual-primal solves (forward and adjoint, the latter
+    reusing the factorisations) give the direct solves' J and gradient."""
+    import workloads as W
+    from oracle import adjoint as adj
+    w = W.small_uniform(6, 4, 6.0, domain=(-1.0, 1.0, -1.0, 1.0), l=2)
+    c = W.leaf_centres(w)
+    inside = (np.abs(c[:, 0]) < 0.4) & (np.abs(c[:, 1]) < 0.4)
+    w["eps_r"] = np.where(inside, np.random.default_rng(3).uniform(1.0, 4.0, len(c)), 1.0)
+    J0, g0, _ = adj.eps_gradient(w, 0.0, 0.0, inside)
+    J1, g1, _ = adj.eps_gradient(w, 0.0, 0.0, inside, solver="elementwise", tol=1e-14)
+    assert abs(J1 - J0) < 1e-10 * J0
+    assert np.linalg.norm(g1 - g0) < 1e-9 * np.linalg.norm(g0)
