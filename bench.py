@@ -150,7 +150,7 @@ def batched_scatterer(hdp, torch, steps, warmup):
     out = {}
     fars = {}
     for prec in ("fp64", "mixed"):
-        s = hdp.Solver(w, precision=prec, tol=1e-8, max_iter=300, max_rhs=len(ang))
+        s = hdp.Solver(w, precision=prec, tol=1e-8, max_iter=300, max_rhs=len(ang), autotune=True)
         if prec == "fp64":
             n1 = 4
             for _ in range(max(1, warmup)):
@@ -175,7 +175,24 @@ def batched_scatterer(hdp, torch, steps, warmup):
         out[prec + "_batched_64"] = dict(ms_per_solve=ms, dof_per_s=s.dof * len(ang) / (ms * 1e-3),
                                          iterations=st["iterations"], refinements=st["refinements"],
                                          converged=st["converged"], rhs_ms=st["rhs_ms"], gmres_ms=st["gmres_ms"],
-                                         recover_ms=st["recover_ms"], setup_ms=s.info["setup_ms"])
+                                         recover_ms=st["recover_ms"], setup_ms=s.info["setup_ms"],
+                                         autotune=s.autotune_table())
+        # one profiled solve: per-family HIP-event times, algorithmic bytes and flops
+        s.profile(True)
+        s.solve("plane_wave_scattered", ang, want_field=False, far_angles=fa, far_inside=inside)
+        torch.cuda.synchronize()
+        kt = [k for k in s.kernel_times() if k["launches"]]
+        s.profile(False)
+        peak = FP64_PEAK_TFLOPS * 1e12
+        fams = {}
+        for k in kt:
+            sec = k["total_ms"] * 1e-3
+            fams[k["name"]] = dict(launches=k["launches"], ms=k["total_ms"],
+                                   tflops=k["flops"] / sec / 1e12 if sec else None,
+                                   gbs=k["bytes"] / sec / 1e9 if sec else None,
+                                   mfma_frac_fp64=k["flops"] / sec / peak if sec else None,
+                                   hbm_frac=k["bytes"] / sec / (HBM_PEAK_GBS * 1e9) if sec else None)
+        out[prec + "_batched_64"]["kernels"] = fams
         out["dof"] = s.dof
         out["l"] = s.info["l"]
         out["n_lambda"] = s.info["n_lambda"]
@@ -211,7 +228,9 @@ def refined_disk(hdp, torch, steps, warmup):
         ms = (time.perf_counter() - t0) * 1e3 / steps
         out[prec] = dict(ms_per_solve=ms, dof_per_s=s.dof / (ms * 1e-3), iterations=st["iterations"],
                          refinements=st["refinements"], rel_residual=st["rel_residual"],
-                         true_residual=st["true_residual"], converged=st["converged"], setup_ms=s.info["setup_ms"])
+                         true_residual=st["true_residual"], converged=st["converged"], setup_ms=s.info["setup_ms"],
+                         setup_host_ms=s.info["setup_host_ms"], setup_classes_ms=s.info["setup_classes_ms"],
+                         setup_coarse_ms=s.info["setup_coarse_ms"])
         out.update(dof=s.dof, elements=s.info["n_elements"], l=s.info["l"], n_lambda=s.info["n_lambda"],
                    n_coarse=s.info["n_coarse"], classes=s.info["n_classes"])
         s.close()

@@ -193,6 +193,10 @@ typedef struct {
                                  nested-dissection fronts) */
   double coarse_band_bytes;   /* bytes of a banded (envelope) LU factor of K in its natural order:
                                  what one coarse solve with the paper's plain factorisation reads */
+  /* set-up breakdown (host wall clock, ms): the host analysis as a whole (constraints,
+   * element classes, coarse maps), its element-class operators (eigenbases, unit solves,
+   * Schur blocks; built on up to 16 host threads), and the coarse factor */
+  double setup_host_ms, setup_classes_ms, setup_coarse_ms;
 } hdp_stats;
 
 typedef struct hdp_handle hdp_handle;

@@ -61,7 +61,9 @@ class Stats(ctypes.Structure):
                 ("gmres_wait_ms", ctypes.c_double), ("recover_ms", ctypes.c_double),
                 ("true_residual", ctypes.c_double), ("coarse_residual", ctypes.c_double),
                 ("coarse_mode", ctypes.c_int32), ("coarse_blocks", ctypes.c_int32),
-                ("coarse_factor_bytes", ctypes.c_double), ("coarse_band_bytes", ctypes.c_double)]
+                ("coarse_factor_bytes", ctypes.c_double), ("coarse_band_bytes", ctypes.c_double),
+                ("setup_host_ms", ctypes.c_double), ("setup_classes_ms", ctypes.c_double),
+                ("setup_coarse_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

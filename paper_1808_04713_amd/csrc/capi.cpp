@@ -628,9 +628,11 @@ void build_device(Handle& h) {
   h.rocblas = rb;   // kept for the coarse solves
   // the coarse factor chosen at set-up: dense inverse (0), strips (1) or nested
   // dissection (2)
+  const auto tk = std::chrono::steady_clock::now();
   if (h.coarse_mode == 1) build_coarse_blocks(h, kidx, kval);
   else if (h.coarse_mode == 2) build_coarse_nd(h, kidx, kval);
   else build_coarse_dense(h, kidx, kval);
+  h.setup_coarse_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tk).count();
   // work buffers sized for the largest RHS batch (padded to a power of two)
   size_t Rp = size_t(pow2ceil(h.max_rhs));
   size_t nl = size_t(h.nlam);
@@ -1333,7 +1335,11 @@ hdp_status hdp_setup(const hdp_mesh* mesh, const hdp_problem* prob, const hdp_op
     HIPCHECK(hipEventCreateWithFlags(&h.order_ev, hipEventDisableTiming));
     HIPCHECK(hipEventRecord(h.order_ev, h.user_stream));
     HIPCHECK(hipStreamWaitEvent(h.stream, h.order_ev, 0));
-    build_host(h, mesh, prob);
+    {
+      const auto th = std::chrono::steady_clock::now();
+      build_host(h, mesh, prob);
+      h.setup_host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - th).count();
+    }
     build_device(h);
     if (opt->flags & HDP_FLAG_AUTOTUNE) autotune(h, opt->tile_fdm == 0, opt->tile_slot == 0);
   } catch (...) {
@@ -1383,6 +1389,9 @@ hdp_status hdp_get_stats(const hdp_handle* H, hdp_stats* st) {
   st->coarse_residual = h.coarse_check;
   st->coarse_mode = h.coarse_mode >= 0 ? h.coarse_mode : (h.nK > 6000 ? 2 : 0);
   st->coarse_band_bytes = h.coarse_band_bytes;
+  st->setup_host_ms = h.setup_host_ms;
+  st->setup_classes_ms = h.setup_classes_ms;
+  st->setup_coarse_ms = h.setup_coarse_ms;
   st->coarse_factor_bytes = h.coarse_bytes;
   st->coarse_blocks = st->coarse_mode == 1   ? int(h.cb_off.size()) - 1
                       : st->coarse_mode == 2 ? int(h.nd_off.size()) - 1

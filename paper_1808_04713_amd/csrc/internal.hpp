@@ -212,6 +212,8 @@ struct Handle {
   std::map<int, std::vector<double>> quad_x, quad_w, quad_N;
   double min_margin = 1;
   double setup_ms = 0;
+  double setup_host_ms = 0, setup_classes_ms = 0, setup_coarse_ms = 0;   // set-up phases (host analysis in total,
+                                                                         // its class operators, the coarse factor)
   // algorithmic work per right-hand side (bytes of class operators are
   // counted once per launch, like any operand read from memory once)
   double op1_bytes = 0, se_bytes = 0, phi_bytes = 0;

@@ -4,10 +4,15 @@
 // Sec. 2.3.2 (Algorithm 1), Sec. 2.3.3 (block structure and preconditioner).
 #include <algorithm>
 #include <array>
+#include <atomic>
+#include <chrono>
 #include <cmath>
+#include <exception>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <set>
+#include <thread>
 #include <tuple>
 
 #include "basis.hpp"
@@ -886,11 +891,33 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
     h.cls[e] = it->second;
     h.classes[it->second].elems.push_back(e);
   }
-  h.min_margin = 1;
-  for (auto& C : h.classes) {
-    build_class(C, h.k);
-    h.min_margin = std::min(h.min_margin, C.margin);
+  // classes are independent: build them on host threads (an error in any
+  // class is rethrown after all threads have joined)
+  {
+    const auto tc = std::chrono::steady_clock::now();
+    const int nthreads = int(std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+    std::atomic<int> next{0};
+    std::exception_ptr err;
+    std::mutex err_mu;
+    auto work = [&] {
+      for (int c = next++; c < int(h.classes.size()); c = next++) {
+        try {
+          build_class(h.classes[c], h.k);
+        } catch (...) {
+          std::lock_guard<std::mutex> lock(err_mu);
+          if (!err) err = std::current_exception();
+        }
+      }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < std::min<int>(nthreads, int(h.classes.size())); ++t) pool.emplace_back(work);
+    work();
+    for (auto& t : pool) t.join();
+    if (err) std::rethrow_exception(err);
+    h.setup_classes_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tc).count();
   }
+  h.min_margin = 1;
+  for (auto& C : h.classes) h.min_margin = std::min(h.min_margin, C.margin);
   // offsets
   h.dof_off.assign(E + 1, 0);
   h.slot_off.assign(E + 1, 0);
