@@ -310,7 +310,17 @@ static void build_coarse_nd(Handle& h, const std::vector<int64_t>& kidx, const s
   const size_t Rp = size_t(pow2ceil(h.max_rhs));
   if (Rp > 1 && f.part_tasks > 0) d.nd_P = dalloc<double2>(h, size_t(f.part_tasks) * 32 * 64);
   d.nd_urows = f.urows;
-  d.nd_FA = dalloc<double2>(h, size_t(h.nK + f.urows) * Rp);
+  // one column: accumulators cleared per solve; several: the child slots,
+  // cleared once here (a slot row is either rewritten by every solve or never)
+  d.nd_FA = dalloc<double2>(h, size_t(h.nK + f.urows));
+  if (Rp > 1) {
+    d.nd_ld = int64_t(Rp);
+    const size_t ns = 2 * size_t(h.nK + f.urows) * Rp;
+    d.nd_slot = dalloc<double2>(h, ns);
+    HIPCHECK(hipMemsetAsync(d.nd_slot, 0, ns * sizeof(double2), h.stream));
+    d.nd_push2 = upload(h, f.push2);
+    d.nd_childv = upload(h, h.nd_child);
+  }
   h.nd_levels = f.levels;
   h.coarse_mode = 2;
   h.coarse_bytes = 16.0 * double(f.fac.size());
@@ -322,19 +332,30 @@ static void coarse_solve_nd(Handle& h, const double2* g, double2* w, int R) {
   NDView v;
   v.off = d.nd_off; v.boff = d.nd_boff; v.bnd = d.nd_bnd; v.uoff = d.nd_uoff; v.push = d.nd_push;
   v.mD = d.nd_mD; v.mL = d.nd_mL; v.mLt = d.nd_mLt; v.fac = d.nd_fac;
-  double2* F = d.nd_FA;
-  double2* A = d.nd_FA + int64_t(h.nK) * R;
-  launch_fill_zero(F, (int64_t(h.nK) + d.nd_urows) * R, h.stream);   // a fill kernel (capturable)
   const int nd = int(h.nd_levels.size());
+  if (R == 1) {
+    double2* F = d.nd_FA;
+    double2* A = d.nd_FA + h.nK;
+    launch_fill_zero(F, int64_t(h.nK) + d.nd_urows, h.stream);   // a fill kernel (capturable)
+    for (int L = nd - 1; L >= 0; --L) {   // leaves first
+      const NDLevel& lv = h.nd_levels[L];
+      launch_nd_fwd1(d.nd_f1 + lv.f1, lv.nf1, v, g, F, A, h.stream);
+    }
+    for (int L = 0; L < nd; ++L) {   // root first
+      const NDLevel& lv = h.nd_levels[L];
+      launch_nd_bwd1(d.nd_b1 + lv.b1, lv.nb1, v, g, F, w, h.stream);
+    }
+    return;
+  }
+  v.push2 = d.nd_push2; v.child = d.nd_childv; v.slot = d.nd_slot; v.ld = d.nd_ld;
+  v.srows = int64_t(h.nK) + d.nd_urows; v.nK = h.nK;
   for (int L = nd - 1; L >= 0; --L) {   // leaves first
     const NDLevel& lv = h.nd_levels[L];
-    if (R == 1) launch_nd_fwd1(d.nd_f1 + lv.f1, lv.nf1, v, g, F, A, h.stream);
-    else launch_nd_tiles(false, d.nd_tRf + lv.fR, lv.nfR, lv.Sf, v, g, F, A, w, R, d.nd_P, h.stream);
+    launch_nd_tiles(false, d.nd_tRf + lv.fR, lv.nfR, lv.Sf, v, g, w, R, d.nd_P, h.stream);
   }
   for (int L = 0; L < nd; ++L) {   // root first
     const NDLevel& lv = h.nd_levels[L];
-    if (R == 1) launch_nd_bwd1(d.nd_b1 + lv.b1, lv.nb1, v, g, F, w, h.stream);
-    else launch_nd_tiles(true, d.nd_tRb + lv.bR, lv.nbR, lv.Sb, v, g, F, A, w, R, d.nd_P, h.stream);
+    launch_nd_tiles(true, d.nd_tRb + lv.bR, lv.nbR, lv.Sb, v, g, w, R, d.nd_P, h.stream);
   }
 }
 

@@ -232,20 +232,28 @@ void nd_factor(const Handle& h, const std::vector<int64_t>& kidx, const std::vec
   for (int t = 0; t < nn; ++t)
     for (int k = 0; k < 2; ++k)
       if (h.nd_child[2 * size_t(t) + k] >= 0) parent[h.nd_child[2 * size_t(t) + k]] = t;
+  // several columns: slot k of the parent's rows for child k (interior rows
+  // first, then update rows from nK on)
   f.push.assign(size_t(std::max<int64_t>(1, urows)), 0);
+  f.push2.assign(size_t(std::max<int64_t>(1, urows)), 0);
+  const int64_t srows = nK + urows;
+  if (2 * srows >= (int64_t(1) << 31)) fail(HDP_E_COARSE, "nested-dissection slot index overflows");
   for (int t = 0; t < nn; ++t) {
     const int p = parent[t];
     if (nB_of(t) > 0 && p < 0) fail(HDP_E_COARSE, "nested-dissection root with a boundary");
+    const int k = p >= 0 && h.nd_child[2 * size_t(p)] == t ? 0 : 1;
     const int* Bt = h.nd_bnd.data() + h.nd_boff[t];
     for (int a = 0; a < nB_of(t); ++a) {
       const int g = Bt[a];
       if (g >= h.nd_off[p] && g < h.nd_off[p + 1]) {
         f.push[f.uoff[t] + a] = -1 - g;
+        f.push2[f.uoff[t] + a] = int(k * srows + g);
       } else {
         const int* Bp = h.nd_bnd.data() + h.nd_boff[p];
         const int* it = std::lower_bound(Bp, Bp + nB_of(p), g);
         if (it == Bp + nB_of(p) || *it != g) fail(HDP_E_COARSE, "child boundary outside its parent's front");
         f.push[f.uoff[t] + a] = int(f.uoff[p] + (it - Bp));
+        f.push2[f.uoff[t] + a] = int(k * srows + nK + f.uoff[p] + (it - Bp));
       }
     }
   }

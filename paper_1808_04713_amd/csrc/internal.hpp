@@ -257,6 +257,9 @@ struct Handle {
     double2 *k_val = nullptr, *nd_r = nullptr, *nd_dx = nullptr;
     int4 *nd_tRf = nullptr, *nd_tRb = nullptr;
     double2* nd_P = nullptr;   // partial tiles of the split top levels
+    double2* nd_slot = nullptr;   // two child slots per front row, [2][nK + urows][Rp], zero from set-up
+    int *nd_push2 = nullptr, *nd_childv = nullptr;
+    int64_t nd_ld = 0;
     int* cb_off = nullptr;
     int64_t* cb_D = nullptr;
     // per-class tables
@@ -392,6 +395,7 @@ struct NDHost {
   std::vector<int64_t> uoff, mD, mL, mLt;
   int64_t urows = 0;
   std::vector<int> push;
+  std::vector<int> push2;     // slot row of each update row (several columns)
   std::vector<int2> t1f, t1b;
   std::vector<int4> tRf, tRb;
   std::vector<NDLevel> levels;

@@ -775,6 +775,15 @@ struct NDNodes {
   const int64_t* mL;
   const int64_t* mLt;
   const double2* fac;
+  // several columns: each front row has two slots (one per child) at a fixed
+  // column stride ld; update row u of a node goes by a plain store to slot row
+  // push2[u] (slot k of the parent's interior row, or of its update row nK + a);
+  // slot rows no child writes stay zero from set-up
+  const int* push2;
+  const int* child;      // [2 n], -1 where absent
+  double2* slot;         // [2][nK + urows][ld]
+  int64_t ld, srows;     // column stride, rows per slot (nK + urows)
+  int nK;
 };
 
 // One column: one wave per output row, lanes over the row.
@@ -852,7 +861,8 @@ __global__ void __launch_bounds__(NT) k_nd_bwd1(const ND1Bwd* __restrict__ task,
 // acc += sum_i M[i + K j] X_row(i) for this thread's 8 outputs.
 __device__ __forceinline__ void nd_mm_core(const double2* __restrict__ M, int K, int i0, int i1, int n_out, int j0,
                                            const double2* __restrict__ X, const double2* __restrict__ X2,
-                                           int64_t xbase, const int* __restrict__ xidx, int R, double2 (&acc)[8]) {
+                                           int64_t xbase, const int* __restrict__ xidx, int R, double2 (&acc)[8],
+                                           int64_t ld2 = 0, int64_t sst = 0) {
   __shared__ double2 Ms[SMK][SMJ + 1];
   const int r = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const bool live = r < R;
@@ -868,9 +878,9 @@ __device__ __forceinline__ void nd_mm_core(const double2* __restrict__ M, int K,
         const int64_t row = xidx ? (int64_t)xidx[ib + kk] : xbase + ib + kk;
         double2 x = X[row * R + r];
         if (X2) {
-          const double2 x2 = X2[row * R + r];
-          x.x += x2.x;
-          x.y += x2.y;
+          const double2 x2 = X2[row * ld2 + r], x3 = X2[sst + row * ld2 + r];
+          x.x += x2.x + x3.x;
+          x.y += x2.y + x3.y;
         }
 #pragma unroll
         for (int t = 0; t < 8; ++t) acc[t] = cfma(Ms[kk][wv * 8 + t], x, acc[t]);
@@ -891,7 +901,7 @@ __device__ __forceinline__ void nd_mm_core_mfma(const double2* __restrict__ M, i
                                                 int j0, const double2* __restrict__ X,
                                                 const double2* __restrict__ X2, int64_t xbase,
                                                 const int* __restrict__ xidx, int R, double2 (&acc)[8],
-                                                double2* Dt) {
+                                                double2* Dt, int64_t ld2 = 0, int64_t sst = 0) {
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int jl = l & 15, kq = l >> 4;
   const int jt = wv & 1, rt0 = (wv >> 1) * 2;
@@ -919,14 +929,15 @@ __device__ __forceinline__ void nd_mm_core_mfma(const double2* __restrict__ M, i
         a0[u] = xr[16 * rt0];
         a1[u] = act1 ? xr[16 * (rt0 + 1)] : make_double2(0, 0);
         if (X2) {
-          const double2* x2 = X2 + row * R + jl;
-          const double2 c0 = x2[16 * rt0];
-          a0[u].x += c0.x;
-          a0[u].y += c0.y;
+          // the two child slots of the row
+          const double2* x2 = X2 + row * ld2 + jl;
+          const double2 c0 = x2[16 * rt0], c1 = x2[sst + 16 * rt0];
+          a0[u].x += c0.x + c1.x;
+          a0[u].y += c0.y + c1.y;
           if (act1) {
-            const double2 c1 = x2[16 * (rt0 + 1)];
-            a1[u].x += c1.x;
-            a1[u].y += c1.y;
+            const double2 d0 = x2[16 * (rt0 + 1)], d1 = x2[sst + 16 * (rt0 + 1)];
+            a1[u].x += d0.x + d1.x;
+            a1[u].y += d0.y + d1.y;
           }
         }
         if (!(kv && jv)) b[u] = make_double2(0, 0);
@@ -978,21 +989,38 @@ __device__ __forceinline__ void nd_store_part(double2* __restrict__ P, const dou
   for (int q = 0; q < 8; ++q) dst[(jw + q) * 64 + r] = acc[q];
 }
 
-// U_t = A_t - L_t Y_I over the task's range of I (into P when the sum is split).
+// The child slots of front row `row` (interior rows [0, nK), update rows after):
+// their sum, or zero at a leaf (no child writes there).
+__device__ __forceinline__ double2 nd_slots(const NDNodes& nd, bool leaf, int64_t row, int r) {
+  if (leaf) return make_double2(0, 0);
+  const double2* p = nd.slot + row * nd.ld + r;
+  const double2 a = p[0], b = p[nd.srows * nd.ld];
+  return make_double2(a.x + b.x, a.y + b.y);
+}
+
+__device__ __forceinline__ bool nd_leaf(const NDNodes& nd, int t) {
+  return nd.child[2 * t] < 0 && nd.child[2 * t + 1] < 0;
+}
+
+// U_t = A_t - L_t Y_I over the task's range of I (into P when the sum is split);
+// Y_I = g_I plus the children's slots, A_t the children's slots of t's update
+// rows; U_t goes by plain stores into t's slot of its parent's rows.
 template <bool MF>
 __global__ void __launch_bounds__(NT) k_nd_fwdR(const int4* __restrict__ task, NDNodes nd,
-                                                const double2* __restrict__ g, double2* __restrict__ F,
-                                                double2* __restrict__ A, int R, double2* __restrict__ P) {
+                                                const double2* __restrict__ g, int R, double2* __restrict__ P) {
   __shared__ double2 Dt[MF ? SMJ * 64 : 1];
   const int4 tk = task[blockIdx.x];
   const int t = tk.x, j0 = tk.y;
   const int o = nd.off[t], nI = nd.off[t + 1] - o;
   const int nB = int(nd.boff[t + 1] - nd.boff[t]);
+  const bool leaf = nd_leaf(nd, t);
+  const double2* Ys = leaf ? nullptr : nd.slot;
+  const int64_t sst = nd.srows * nd.ld;
   double2 acc[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) acc[q] = make_double2(0, 0);
-  if (MF) nd_mm_core_mfma(nd.fac + nd.mL[t], nI, tk.z, tk.w, nB, j0, g, F, o, nullptr, R, acc, Dt);
-  else nd_mm_core(nd.fac + nd.mL[t], nI, tk.z, tk.w, nB, j0, g, F, o, nullptr, R, acc);
+  if (MF) nd_mm_core_mfma(nd.fac + nd.mL[t], nI, tk.z, tk.w, nB, j0, g, Ys, o, nullptr, R, acc, Dt, nd.ld, sst);
+  else nd_mm_core(nd.fac + nd.mL[t], nI, tk.z, tk.w, nB, j0, g, Ys, o, nullptr, R, acc, nd.ld, sst);
   if (P) {
     nd_store_part(P, acc, R);
     return;
@@ -1003,8 +1031,8 @@ __global__ void __launch_bounds__(NT) k_nd_fwdR(const int4* __restrict__ task, N
     const int j = jw + q;
     if (j >= nB) break;
     const int64_t u = nd.uoff[t] + j;
-    const double2 a = A[u * R + r];
-    nd_push(F, A, nd.push[u], r, R, make_double2(a.x - acc[q].x, a.y - acc[q].y));
+    const double2 a = nd_slots(nd, leaf, nd.nK + u, r);
+    nd.slot[(int64_t)nd.push2[u] * nd.ld + r] = make_double2(a.x - acc[q].x, a.y - acc[q].y);
   }
 }
 
@@ -1012,24 +1040,26 @@ __global__ void __launch_bounds__(NT) k_nd_fwdR(const int4* __restrict__ task, N
 // product and [nI, nI + nB) for the second, of which the task takes [i0, i1).
 template <bool MF>
 __global__ void __launch_bounds__(NT) k_nd_bwdR(const int4* __restrict__ task, NDNodes nd,
-                                                const double2* __restrict__ g, const double2* __restrict__ F,
-                                                double2* __restrict__ X, int R, double2* __restrict__ P) {
+                                                const double2* __restrict__ g, double2* __restrict__ X, int R,
+                                                double2* __restrict__ P) {
   __shared__ double2 Dt[MF ? SMJ * 64 : 1];
   const int4 tk = task[blockIdx.x];
   const int t = tk.x, j0 = tk.y;
   const int o = nd.off[t], nI = nd.off[t + 1] - o;
   const int64_t bo = nd.boff[t];
   const int nB = int(nd.boff[t + 1] - bo);
+  const double2* Ys = nd_leaf(nd, t) ? nullptr : nd.slot;
+  const int64_t sst = nd.srows * nd.ld;
   double2 a1[8], a2[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) a1[q] = a2[q] = make_double2(0, 0);
   const int e1 = min(tk.w, nI);
   const int s2 = max(tk.z, nI) - nI, e2 = tk.w - nI;
   if (MF) {
-    if (tk.z < e1) nd_mm_core_mfma(nd.fac + nd.mD[t], nI, tk.z, e1, nI, j0, g, F, o, nullptr, R, a1, Dt);
+    if (tk.z < e1) nd_mm_core_mfma(nd.fac + nd.mD[t], nI, tk.z, e1, nI, j0, g, Ys, o, nullptr, R, a1, Dt, nd.ld, sst);
     if (s2 < e2) nd_mm_core_mfma(nd.fac + nd.mLt[t], nB, s2, e2, nI, j0, X, nullptr, 0, nd.bnd + bo, R, a2, Dt);
   } else {
-    if (tk.z < e1) nd_mm_core(nd.fac + nd.mD[t], nI, tk.z, e1, nI, j0, g, F, o, nullptr, R, a1);
+    if (tk.z < e1) nd_mm_core(nd.fac + nd.mD[t], nI, tk.z, e1, nI, j0, g, Ys, o, nullptr, R, a1, nd.ld, sst);
     if (s2 < e2) nd_mm_core(nd.fac + nd.mLt[t], nB, s2, e2, nI, j0, X, nullptr, 0, nd.bnd + bo, R, a2);
   }
 #pragma unroll
@@ -1048,11 +1078,10 @@ __global__ void __launch_bounds__(NT) k_nd_bwdR(const int4* __restrict__ task, N
 }
 
 // Sums the S partial tiles of each output tile (tasks q S .. q S + S - 1 share
-// node and first output) and finishes the step: U = A - sum pushed to the
-// parent (forward) or X = sum (backward).
+// node and first output) and finishes the step: U = A - sum stored into the
+// parent's slot (forward) or X = sum (backward).
 __global__ void k_nd_reduce(const int4* __restrict__ task, int ntiles, int S, const double2* __restrict__ P,
-                            NDNodes nd, double2* __restrict__ F, double2* __restrict__ A, double2* __restrict__ X,
-                            int R, int bwd) {
+                            NDNodes nd, double2* __restrict__ X, int R, int bwd) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)ntiles * SMJ * R) return;
   const int r = int(e % R);
@@ -1073,8 +1102,8 @@ __global__ void k_nd_reduce(const int4* __restrict__ task, int ntiles, int S, co
     X[((int64_t)o + j) * R + r] = make_double2(sx, sy);
   } else {
     const int64_t u = nd.uoff[t] + j;
-    const double2 a = A[u * R + r];
-    nd_push(F, A, nd.push[u], r, R, make_double2(a.x - sx, a.y - sy));
+    const double2 a = nd_slots(nd, nd_leaf(nd, t), nd.nK + u, r);
+    nd.slot[(int64_t)nd.push2[u] * nd.ld + r] = make_double2(a.x - sx, a.y - sy);
   }
 }
 
@@ -3541,24 +3570,26 @@ void launch_nd_bwd1(const ND1Bwd* task, int ntask, const NDView& v, const double
   HIPCHECK(hipGetLastError());
 }
 
-void launch_nd_tiles(bool bwd, const int4* task, int ntiles, int S, const NDView& v, const double2* g, double2* F,
-                     double2* A, double2* X, int R, double2* P, hipStream_t s) {
+void launch_nd_tiles(bool bwd, const int4* task, int ntiles, int S, const NDView& v, const double2* g, double2* X,
+                     int R, double2* P, hipStream_t s) {
   if (ntiles == 0) return;
-  const NDNodes nd{v.off, v.boff, v.bnd, v.uoff, v.push, v.mD, v.mL, v.mLt, v.fac};
+  if (R > v.ld) fail(HDP_E_ARG, "nested-dissection sweep: more columns than the slot stride");
+  const NDNodes nd{v.off, v.boff, v.bnd, v.uoff, v.push, v.mD, v.mL, v.mLt, v.fac,
+                   v.push2, v.child, v.slot, v.ld, v.srows, v.nK};
   double2* part = S > 1 ? P : nullptr;
   const unsigned nt = unsigned(ntiles) * unsigned(S);
   // 16, 32 or 64 columns go to the matrix cores
   const bool mf = R >= 16 && R % 16 == 0;
   if (bwd) {
-    if (mf) hipLaunchKernelGGL(k_nd_bwdR<true>, dim3(nt), dim3(NT), 0, s, task, nd, g, F, X, R, part);
-    else hipLaunchKernelGGL(k_nd_bwdR<false>, dim3(nt), dim3(NT), 0, s, task, nd, g, F, X, R, part);
+    if (mf) hipLaunchKernelGGL(k_nd_bwdR<true>, dim3(nt), dim3(NT), 0, s, task, nd, g, X, R, part);
+    else hipLaunchKernelGGL(k_nd_bwdR<false>, dim3(nt), dim3(NT), 0, s, task, nd, g, X, R, part);
   } else {
-    if (mf) hipLaunchKernelGGL(k_nd_fwdR<true>, dim3(nt), dim3(NT), 0, s, task, nd, g, F, A, R, part);
-    else hipLaunchKernelGGL(k_nd_fwdR<false>, dim3(nt), dim3(NT), 0, s, task, nd, g, F, A, R, part);
+    if (mf) hipLaunchKernelGGL(k_nd_fwdR<true>, dim3(nt), dim3(NT), 0, s, task, nd, g, R, part);
+    else hipLaunchKernelGGL(k_nd_fwdR<false>, dim3(nt), dim3(NT), 0, s, task, nd, g, R, part);
   }
   if (S > 1)
     hipLaunchKernelGGL(k_nd_reduce, dim3(nblocks(int64_t(ntiles) * SMJ * R)), dim3(NT), 0, s, task, ntiles, S, P, nd,
-                       F, A, X, R, bwd ? 1 : 0);
+                       X, R, bwd ? 1 : 0);
   HIPCHECK(hipGetLastError());
 }
 

@@ -97,6 +97,14 @@ struct NDView {
   const int* push = nullptr;
   const int64_t *mD = nullptr, *mL = nullptr, *mLt = nullptr;
   const double2* fac = nullptr;
+  // several columns: two child slots per front row at column stride ld (rows
+  // [0, nK) interior, then the update rows; srows = nK + update rows), written by
+  // plain stores at push2[u] and zero wherever no child writes
+  const int* push2 = nullptr;
+  const int* child = nullptr;
+  double2* slot = nullptr;
+  int64_t ld = 0, srows = 0;
+  int nK = 0;
 };
 // one column: tasks {node, row}; forward U = A - L (g + F)_I pushed to the parent,
 // backward X_I = Dinv (g + F)_I - Lt X_B
@@ -104,11 +112,11 @@ void launch_nd_fwd1(const ND1Fwd* task, int ntask, const NDView& v, const double
                     hipStream_t s);
 void launch_nd_bwd1(const ND1Bwd* task, int ntask, const NDView& v, const double2* g, const double2* F, double2* X,
                     hipStream_t s);
-// several columns: ntiles output tiles of 32 rows, each split into S tasks
-// {node, first row, i0, i1} over the summation; with S > 1 the partial tiles go
-// to P (ntiles * S * 32 * 64 values) and a second kernel adds them
-void launch_nd_tiles(bool bwd, const int4* task, int ntiles, int S, const NDView& v, const double2* g, double2* F,
-                     double2* A, double2* X, int R, double2* P, hipStream_t s);
+// several columns (R <= ld): ntiles output tiles of 32 rows, each split into S
+// tasks {node, first row, i0, i1} over the summation; with S > 1 the partial
+// tiles go to P (ntiles * S * 32 * 64 values) and a second kernel adds them
+void launch_nd_tiles(bool bwd, const int4* task, int ntiles, int S, const NDView& v, const double2* g, double2* X,
+                     int R, double2* P, hipStream_t s);
 // r = g - K x, K in CSR by row (ptr[n + 1], col, val), [n][R] vectors
 void launch_csr_residual(int n, const int64_t* ptr, const int* col, const double2* val, const double2* x,
                          const double2* g, double2* r, int R, hipStream_t s);
