@@ -305,10 +305,28 @@ static void build_coarse_nd(Handle& h, const std::vector<int64_t>& kidx, const s
     d.nd_f1 = upload(h, f1);
     d.nd_b1 = upload(h, b1);
   }
-  d.nd_tRf = upload(h, f.tRf);
-  d.nd_tRb = upload(h, f.tRb);
   const size_t Rp = size_t(pow2ceil(h.max_rhs));
-  if (Rp > 1 && f.part_tasks > 0) d.nd_P = dalloc<double2>(h, size_t(f.part_tasks) * 32 * 64);
+  {
+    // task lists and partial tiles sized for every split the autotuner may try
+    size_t nf = f.tRf.size(), nb = f.tRb.size();
+    int64_t most = f.part_tasks;
+    if (Rp > 1)
+      for (int target : ND_SPLITS) {
+        NDHost g;
+        nd_tasks(h, g, target);
+        nf = std::max(nf, g.tRf.size());
+        nb = std::max(nb, g.tRb.size());
+        most = std::max(most, g.part_tasks);
+      }
+    d.nd_tRf = dalloc<int4>(h, std::max<size_t>(1, nf));
+    d.nd_tRb = dalloc<int4>(h, std::max<size_t>(1, nb));
+    h.nd_tR_cap[0] = nf;
+    h.nd_tR_cap[1] = nb;
+    if (!f.tRf.empty()) HIPCHECK(hipMemcpy(d.nd_tRf, f.tRf.data(), f.tRf.size() * sizeof(int4), hipMemcpyHostToDevice));
+    if (!f.tRb.empty()) HIPCHECK(hipMemcpy(d.nd_tRb, f.tRb.data(), f.tRb.size() * sizeof(int4), hipMemcpyHostToDevice));
+    h.nd_P_tasks = Rp > 1 ? most : 0;
+    if (Rp > 1 && most > 0) d.nd_P = dalloc<double2>(h, size_t(most) * 32 * 64);
+  }
   d.nd_urows = f.urows;
   // one column: accumulators cleared per solve; several: the child slots,
   // cleared once here (a slot row is either rewritten by every solve or never)
@@ -325,6 +343,24 @@ static void build_coarse_nd(Handle& h, const std::vector<int64_t>& kidx, const s
   h.coarse_mode = 2;
   h.coarse_bytes = 16.0 * double(f.fac.size());
   h.coarse_flops = f.flops_per_col;
+}
+
+// Re-cut the several-column tasks for another split target (the factor and the
+// one-column tasks do not depend on it).
+static void set_nd_split(Handle& h, int target) {
+  NDHost g;
+  nd_tasks(h, g, target);
+  if (g.part_tasks > h.nd_P_tasks || g.tRf.size() > h.nd_tR_cap[0] || g.tRb.size() > h.nd_tR_cap[1])
+    fail(HDP_E_DEVICE, "nested-dissection split beyond its task or partial-tile buffers");
+  auto put = [&](int4* dst, const std::vector<int4>& src) {
+    if (!src.empty())
+      HIPCHECK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(int4), hipMemcpyHostToDevice, h.stream));
+  };
+  put(h.d.nd_tRf, g.tRf);
+  put(h.d.nd_tRb, g.tRb);
+  HIPCHECK(hipStreamSynchronize(h.stream));
+  h.nd_levels = g.levels;
+  h.nd_split = target;
 }
 
 static void coarse_solve_nd(Handle& h, const double2* g, double2* w, int R) {
@@ -1229,6 +1265,9 @@ void far_prepare(Handle& h, int n_far, const double* angles, const uint8_t* insi
 // is timed as its two passes (coarse pass and corrected solve) on a zero input
 // (its time does not depend on the values), the slot operators as the interface
 // operator's first product.
+static void set_nd_split(Handle& h, int target);
+static void coarse_solve_nd(Handle& h, const double2* g, double2* w, int R);
+
 static void autotune(Handle& h, bool fdm, bool slot) {
   auto& d = h.d;
   hipStream_t s = h.stream;
@@ -1280,6 +1319,21 @@ static void autotune(Handle& h, bool fdm, bool slot) {
         if (ms < tbest) { tbest = ms; best = rb; }
       }
       h.slot_rb = best;
+      for (size_t i = first; i < h.tune.size(); ++i) h.tune[i].chosen = h.tune[i].cols == best;
+    }
+    if (h.coarse_mode == 2 && R > 1) {
+      // nested-dissection split target: one coarse solve at max_rhs columns
+      int best = h.nd_split;
+      double tbest = 1e300;
+      const size_t first = h.tune.size();
+      launch_fill_zero(d.gK, int64_t(h.nK) * R, s);
+      for (int target : ND_SPLITS) {
+        set_nd_split(h, target);
+        const double ms = time3([&] { coarse_solve_nd(h, d.gK, d.wK, R); });
+        h.tune.push_back({"coarse_nd_split", target, ms, false});
+        if (ms < tbest) { tbest = ms; best = target; }
+      }
+      set_nd_split(h, best);
       for (size_t i = first; i < h.tune.size(); ++i) h.tune[i].chosen = h.tune[i].cols == best;
     }
   } catch (...) {

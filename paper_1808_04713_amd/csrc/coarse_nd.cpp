@@ -257,7 +257,20 @@ void nd_factor(const Handle& h, const std::vector<int64_t>& kidx, const std::vec
       }
     }
   }
-  // row tasks, depth by depth
+  nd_tasks(h, f, 1024);
+}
+
+// Row tasks of the device sweeps, depth by depth.  Several columns: tiles of 32
+// outputs; a depth with few tiles splits each tile's sum so that about `target`
+// workgroups run (the set-up autotuner tries several targets).
+void nd_tasks(const Handle& h, NDHost& f, int target) {
+  const int nn = int(h.nd_off.size()) - 1;
+  int maxd = 0;
+  for (int t = 0; t < nn; ++t) maxd = std::max(maxd, h.nd_depth[t]);
+  std::vector<std::vector<int>> by_depth(maxd + 1);
+  for (int t = 0; t < nn; ++t) by_depth[h.nd_depth[t]].push_back(t);
+  auto nI_of = [&](int t) { return h.nd_off[t + 1] - h.nd_off[t]; };
+  auto nB_of = [&](int t) { return int(h.nd_boff[t + 1] - h.nd_boff[t]); };
   f.levels.assign(maxd + 1, NDLevel{});
   f.t1f.clear(); f.t1b.clear(); f.tRf.clear(); f.tRb.clear();
   f.part_tasks = 0;
@@ -269,8 +282,6 @@ void nd_factor(const Handle& h, const std::vector<int64_t>& kidx, const std::vec
       for (int i = 0; i < nI_of(t); ++i) f.t1b.push_back(make_int2(t, i));
     }
     L.nf1 = int(f.t1f.size()) - L.f1; L.nb1 = int(f.t1b.size()) - L.b1;
-    // tiles of 32 outputs for several columns; levels with few tiles split each
-    // tile's sum so that about 1024 workgroups run
     for (int bwd = 0; bwd < 2; ++bwd) {
       int ntiles = 0, kmax = 0;
       for (int t : by_depth[dpt]) {
@@ -279,7 +290,7 @@ void nd_factor(const Handle& h, const std::vector<int64_t>& kidx, const std::vec
         if (nout > 0) kmax = std::max(kmax, bwd ? nI_of(t) + nB_of(t) : nI_of(t));
       }
       int S = 1;
-      if (ntiles > 0) S = std::max(1, std::min((1024 + ntiles - 1) / ntiles, (kmax + 31) / 32));
+      if (ntiles > 0) S = std::max(1, std::min((target + ntiles - 1) / ntiles, (kmax + 31) / 32));
       std::vector<int4>& T = bwd ? f.tRb : f.tRf;
       const int first = int(T.size());
       for (int t : by_depth[dpt]) {

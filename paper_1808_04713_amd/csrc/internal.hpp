@@ -189,6 +189,9 @@ struct Handle {
   std::vector<int64_t> nd_boff;
   std::vector<int> nd_bnd;
   std::vector<NDLevel> nd_levels;   // per tree depth
+  int nd_split = 1024;              // workgroups a depth's split tiles aim at (several columns)
+  int64_t nd_P_tasks = 0;           // partial tiles nd_P holds
+  size_t nd_tR_cap[2] = {0, 0};     // capacity of nd_tRf / nd_tRb
   bool coarse_refine = false;       // refine each coarse solve once (set at setup from the check)
   std::vector<int> cb_off;
   std::vector<int64_t> cb_D, cb_W, cb_U;
@@ -403,6 +406,10 @@ struct NDHost {
   double flops_per_col = 0;   // 8 (nI^2 + 2 nB nI) summed over the nodes
 };
 void nd_factor(const Handle& h, const std::vector<int64_t>& kidx, const std::vector<double2>& kval, NDHost& f);
+// the row tasks alone (levels, t1f/t1b, tRf/tRb, part_tasks) for a split target;
+// ND_SPLITS are the targets the set-up autotuner tries
+void nd_tasks(const Handle& h, NDHost& f, int target);
+constexpr int ND_SPLITS[] = {256, 512, 1024, 2048};
 void build_device(Handle& h);
 // Element loads of the elements with a non-zero load: elems lists them and
 // vals holds their blocks back to back, each [n_e^2][R].

@@ -283,6 +283,27 @@ def test_factored_coarse_solvers(name, coarse, oracles):
     sd.close()
 
 
+def test_autotuned_nested_dissection_split(oracles):
+    """The set-up autotuner times the nested-dissection sweeps at every split
+    target and keeps the fastest; the interface operator with the chosen task
+    cut equals the dense-inverse one at 5, 16 and 64 columns."""
+    disc, l, E = oracles["scatterer_6x6_p6"]
+    w = CASES["scatterer_6x6_p6"]
+    sa = hdp().Solver(w, tol=1e-12, max_iter=400, max_rhs=64, coarse="nd", autotune=True)
+    sd = hdp().Solver(w, tol=1e-12, max_iter=400, max_rhs=64, coarse="dense")
+    rows = [t for t in sa.autotune_table() if t["kernel"] == "coarse_nd_split"]
+    assert sorted(t["cols"] for t in rows) == [256, 512, 1024, 2048]
+    assert sum(t["chosen"] for t in rows) == 1
+    assert min(rows, key=lambda t: t["ms"])["chosen"]
+    rng = np.random.default_rng(6)
+    for R in (5, 16, 64):
+        v = rng.standard_normal((E.nlam, R)) + 1j * rng.standard_normal((E.nlam, R))
+        vd = torch.from_numpy(v).cuda()
+        assert rel(sa.apply_interface(vd, "fp64").cpu().numpy(), sd.apply_interface(vd, "fp64").cpu().numpy()) < 1e-12
+    sa.close()
+    sd.close()
+
+
 def test_point_source_32x32_against_stored_oracle_samples():
     """Full-size workload: sampled field values, F v and P^-1 v rows written by
     tests/golden/make_point_source_32x32.py from the oracle."""
