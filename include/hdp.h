@@ -159,9 +159,10 @@ typedef struct {
 #define HDP_FLAG_COARSE_DENSE 4
 #define HDP_FLAG_COARSE_ND 8
 /* time every candidate tile width of the separable element solve and of the
-   matrix-core slot operators at set-up, on the handle's own mesh at max_rhs
-   columns, and keep the fastest (hdp_autotune_table lists the measurements);
-   tile_fdm / tile_slot, when non-zero, take precedence */
+   matrix-core slot operators, and (nested-dissection coarse factor, max_rhs > 1)
+   every split target of the coarse sweeps, at set-up, on the handle's own mesh
+   at max_rhs columns, and keep the fastest (hdp_autotune_table lists the
+   measurements); tile_fdm / tile_slot, when non-zero, take precedence */
 #define HDP_FLAG_AUTOTUNE 16
 
 typedef struct {
@@ -322,10 +323,12 @@ hdp_status hdp_profile(hdp_handle* h, int32_t enable);
 hdp_status hdp_profile_read(const hdp_handle* h, hdp_kernel_time* out, int32_t max, int32_t* count);
 
 /* The set-up autotuner's measurements (HDP_FLAG_AUTOTUNE): one entry per
- * candidate, the kernel family, the candidate's right-hand sides per workgroup,
- * its mean launch time over three launches at max_rhs columns (ms) and whether
- * it was chosen.  count receives the number of entries; at most max are written
- * to out (host). */
+ * candidate, the kernel family ("fdm_element_solve", "slot_operator",
+ * "coarse_nd_split"), the candidate's parameter (right-hand sides per workgroup;
+ * for coarse_nd_split the workgroups each split tree depth aims at), its mean
+ * time over three launches at max_rhs columns (ms; one coarse solve for
+ * coarse_nd_split) and whether it was chosen.  count receives the number of
+ * entries; at most max are written to out (host). */
 typedef struct {
   char kernel[32];
   int32_t cols;
