@@ -15,6 +15,10 @@ step by step and without blocking or fusion:
   constraints-- hierarchical moment constraints and Algorithm 1 (Sec. 2.2.4, 2.3.2)
   dp         -- literal partial-nullspace dual-primal method (Sec. 2.3.1-2.3.4)
   dp_elementwise -- the same method written element by element (Sec. 2.3.3)
+  dp_nonconforming -- element by element on quadtree meshes with hanging edges
+                (Sec. 2.2.4, 2.3.1-2.3.3; basis of the kept modes)
+  independent -- saddle-point sparse LU and a nodal C0 spectral-element solve
+  adjoint    -- far-field intensity and its permittivity gradient by an adjoint solve
   direct     -- globally conforming Galerkin solution by a direct solve
   gmres      -- left-preconditioned GMRES (Sec. 2.3.4, 3.2)
   farfield   -- far-field integral and RCS (Sec. 3.3.1)

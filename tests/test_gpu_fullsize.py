@@ -9,7 +9,10 @@ only oracle/):
   on the mixed path; single applications of F and P^-1 to 1e-12; iterations to
   1e-8 within one of the oracle's (the per-column residual history);
 - the 32x32 point source (p = 16, k = 100, 295,936 unknowns): the mixed path's
-  field equals the oracle's to 1e-8.
+  field equals the oracle's to 1e-8;
+- the refined disk (712 leaves, up to three hanging nodes per edge, p 8..24,
+  230,391 unknowns): F v and the interface right-hand side to 1e-11, the field
+  to 1e-10 (FP64) and 1e-8 (mixed), against the quadtree element-wise oracle.
 """
 import os
 
@@ -110,4 +113,52 @@ def test_point_source_mixed_full_size():
     assert st["converged"]
     idx, vals = zip(*field)
     assert rel(f.cpu().numpy()[0][list(idx)], vals) < 1e-8
+    s.close()
+
+
+def _disk_samples():
+    meta, field, Fv, g = {}, [], [], []
+    for line in open(os.path.join(GOLD, "refined_disk_samples.txt")):
+        if line.startswith("#"):
+            continue
+        t = line.split()
+        if t[0] in ("field", "Fv", "g"):
+            {"field": field, "Fv": Fv, "g": g}[t[0]].append((int(t[1]), float(t[2]) + 1j * float(t[3])))
+        else:
+            meta[t[0]] = int(t[1])
+    return meta, field, Fv, g
+
+
+def test_refined_disk_full_size_against_the_oracle():
+    """The 712-leaf refined disk (p 8..24, k = 200, l = 14, discard threshold
+    1e-3, up to three hanging nodes per edge) against the element-wise oracle on
+    quadtree meshes (samples by tests/golden/make_refined_disk.py): rows of F v
+    to 1e-11, of the interface right-hand side to 1e-10 (it carries one coarse
+    solve by itself, and the nested-dissection factor's set-up check on this
+    mesh, ||K x - b|| / ||b||, is about 1e-10), the field to 1e-10 (FP64, GMRES
+    to 1e-12) and to 1e-8 (mixed, to 1e-10)."""
+    meta, field, Fv_ref, g_ref = _disk_samples()
+    w = W.refined_disk()
+    kind, vals = hdp().rhs_values(w)
+    s = hdp().Solver(w, tol=1e-12, max_iter=800)
+    assert (s.n_lambda, s.n_coarse, s.info["l"]) == (meta["n_lambda"], meta["n_coarse"], meta["l"])
+    rng = np.random.default_rng(meta["vector_seed"])
+    v = rng.standard_normal(s.n_lambda) + 1j * rng.standard_normal(s.n_lambda)
+    Fv = s.apply_interface(torch.from_numpy(v[:, None].copy()).cuda(), "fp64").cpu().numpy()[:, 0]
+    idx, ref = zip(*Fv_ref)
+    assert rel(Fv[list(idx)], ref) < 1e-11
+    g = s.interface_rhs(kind, vals).cpu().numpy()[:, 0]
+    idx, ref = zip(*g_ref)
+    print("coarse check", s.info["coarse_residual"], "g", rel(g[list(idx)], ref), flush=True)
+    assert rel(g[list(idx)], ref) < 1e-10
+    f, st = s.solve(kind, vals)
+    assert st["converged"]
+    idx, ref = zip(*field)
+    print("iterations", st["iterations"], "field", rel(f.cpu().numpy()[0][list(idx)], ref), flush=True)
+    assert rel(f.cpu().numpy()[0][list(idx)], ref) < 1e-10
+    s.close()
+    s = hdp().Solver(w, precision="mixed", tol=1e-10, max_iter=800)
+    f, st = s.solve(kind, vals)
+    assert st["converged"]
+    assert rel(f.cpu().numpy()[0][list(idx)], ref) < 1e-8
     s.close()

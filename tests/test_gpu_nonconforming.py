@@ -24,41 +24,7 @@ def rel(a, b):
     return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
 
 
-def hanging(base, pvals, seed, l, k=6.0, rhs="plane_wave_total"):
-    lv = W.refine_where(W.morton_leaves(base, base), 0, 1, 0, 1, base, base,
-                        lambda x, y: (x - 0.5) ** 2 + (y - 0.5) ** 2 < (0.03 if base % 2 else 0.05), 2)
-    deg = np.random.default_rng(seed).integers(pvals[0], pvals[1] + 1, len(lv))
-    w = dict(domain=(0.0, 1.0, 0.0, 1.0), base=(base, base), leaves=lv, degree=deg, k=k, l=l,
-             bc="impedance", eps_r=np.ones(len(lv)), rhs=dict(kind=rhs, angles=[0.4]))
-    if rhs == "plane_wave_scattered":
-        c = W.leaf_centres(w)
-        w["eps_r"] = np.where((c[:, 0] - 0.5) ** 2 + (c[:, 1] - 0.5) ** 2 < 0.04, 2.25, 1.0)
-    return w
-
-
-def small_disk(base=6, pvals=(3, 6), seed=4, k=12.0, tau=1e-3):
-    """The refined-disk layout at a size the literal oracle handles: [-1,1]^2,
-    leaves with centre in r < 0.4 split twice, eps_r = 2.25 inside, uneven p."""
-    lv = W.refine_where(W.morton_leaves(base, base), -1, 1, -1, 1, base, base,
-                        lambda x, y: x * x + y * y < 0.16, 2)
-    deg = np.random.default_rng(seed).integers(pvals[0], pvals[1] + 1, len(lv))
-    w = dict(domain=(-1.0, 1.0, -1.0, 1.0), base=(base, base), leaves=lv, degree=deg, k=k, l=-1,
-             bc="impedance", rhs=dict(kind="plane_wave_scattered", angles=[0.0]), discard_tol=tau)
-    c = W.leaf_centres(w)
-    w["eps_r"] = np.where((c ** 2).sum(1) < 0.16, 2.25, 1.0)
-    return w
-
-
-CASES = {
-    "h3_p4_l1": hanging(3, (4, 4), 0, 1),
-    "h3_p3to6_l2": hanging(3, (3, 6), 1, 2),
-    "h4_p2to5_l3": hanging(4, (2, 5), 2, 3),
-    "h3_p3to7_l7": hanging(3, (3, 7), 3, 7),
-    "h4_p4to6_l2_lens": hanging(4, (4, 6), 5, 2, k=9.0, rhs="plane_wave_scattered"),
-    "h3_p3to6_l2_tau": dict(hanging(3, (3, 6), 1, 2), discard_tol=1e-2),
-    "h4_p2to5_l3_tau": dict(hanging(4, (2, 5), 2, 3), discard_tol=3e-3),
-    "disk_6x6_p3to6": small_disk(),
-}
+CASES = W.hanging_cases()
 
 
 @pytest.fixture(scope="module")

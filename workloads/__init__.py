@@ -181,3 +181,46 @@ ALL = {
     "design_block_64x64": design_block_64x64,
     "pml_scatterer_64x64": pml_scatterer_64x64,
 }
+
+
+def hanging_square(base, pvals, seed, l, k=6.0, rhs="plane_wave_total"):
+    """[0,1]^2 from a base x base grid, leaves near the centre split twice (up to
+    three hanging nodes per edge), p ~ U{pvals} per leaf (seeded); with a
+    scattered-field right-hand side, eps_r = 2.25 in a disk of radius 0.2."""
+    lv = refine_where(morton_leaves(base, base), 0, 1, 0, 1, base, base,
+                      lambda x, y: (x - 0.5) ** 2 + (y - 0.5) ** 2 < (0.03 if base % 2 else 0.05), 2)
+    deg = np.random.default_rng(seed).integers(pvals[0], pvals[1] + 1, len(lv))
+    w = dict(domain=(0.0, 1.0, 0.0, 1.0), base=(base, base), leaves=lv, degree=deg, k=k, l=l,
+             bc="impedance", eps_r=np.ones(len(lv)), rhs=dict(kind=rhs, angles=[0.4]))
+    if rhs == "plane_wave_scattered":
+        c = leaf_centres(w)
+        w["eps_r"] = np.where((c[:, 0] - 0.5) ** 2 + (c[:, 1] - 0.5) ** 2 < 0.04, 2.25, 1.0)
+    return w
+
+
+def small_disk(base=6, pvals=(3, 6), seed=4, k=12.0, tau=1e-3):
+    """The refined-disk layout at a small size: [-1,1]^2, leaves with centre in
+    r < 0.4 split twice, eps_r = 2.25 inside, uneven p, discard threshold tau."""
+    lv = refine_where(morton_leaves(base, base), -1, 1, -1, 1, base, base,
+                      lambda x, y: x * x + y * y < 0.16, 2)
+    deg = np.random.default_rng(seed).integers(pvals[0], pvals[1] + 1, len(lv))
+    w = dict(domain=(-1.0, 1.0, -1.0, 1.0), base=(base, base), leaves=lv, degree=deg, k=k, l=-1,
+             bc="impedance", rhs=dict(kind="plane_wave_scattered", angles=[0.0]), discard_tol=tau)
+    c = leaf_centres(w)
+    w["eps_r"] = np.where((c ** 2).sum(1) < 0.16, 2.25, 1.0)
+    return w
+
+
+def hanging_cases():
+    """The quadtree meshes of the parity tests, by name."""
+    return {
+        "h3_p4_l1": hanging_square(3, (4, 4), 0, 1),
+        "h3_p3to6_l2": hanging_square(3, (3, 6), 1, 2),
+        "h4_p2to5_l3": hanging_square(4, (2, 5), 2, 3),
+        "h3_p3to7_l7": hanging_square(3, (3, 7), 3, 7),
+        "h4_p4to6_l2_lens": hanging_square(4, (4, 6), 5, 2, k=9.0, rhs="plane_wave_scattered"),
+        "h3_p3to6_l2_tau": dict(hanging_square(3, (3, 6), 1, 2), discard_tol=1e-2),
+        "h4_p2to5_l3_tau": dict(hanging_square(4, (2, 5), 2, 3), discard_tol=3e-3),
+        "disk_6x6_p3to6": small_disk(),
+    }
+
