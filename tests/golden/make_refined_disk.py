@@ -11,7 +11,10 @@ a seeded random dual vector v, of the interface right-hand side g, and of the
 field at GLL nodes.  The preconditioner depends on the basis of the
 constrained space and the iteration count on the preconditioner, so neither is
 stored.
-Run: python tests/golden/make_refined_disk.py   (about six minutes)
+The same for the per-edge coarse order (the dispersion rule edge by edge, the
+conclusions' proposal) in refined_disk_per_edge_samples.txt.
+Run: python tests/golden/make_refined_disk.py [plain|per_edge]   (about six
+minutes each; both without an argument)
 """
 import os
 import sys
@@ -24,15 +27,14 @@ sys.path.insert(0, ROOT)
 import workloads as W  # noqa: E402
 from oracle import dp_nonconforming as dnc, problem as pb  # noqa: E402
 
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "refined_disk_samples.txt")
+GOLD = os.path.dirname(os.path.abspath(__file__))
 
 
-def main():
-    w = W.refined_disk()
+def write(w, out, seed):
     disc = pb.Discretisation(w)
     l = pb.coarse_order(w, disc.mesh)
     N = dnc.NonconformingDP(disc, l)
-    rng = np.random.default_rng(4321)
+    rng = np.random.default_rng(seed)
     v = rng.standard_normal(N.nlam) + 1j * rng.standard_normal(N.nlam)
     Fv = N.apply_F(v)
     g = N.interface_rhs()
@@ -40,16 +42,27 @@ def main():
     field = np.concatenate(pb.gll_field(disc.mesh, disc.degrees, phis))
     fidx = np.sort(rng.choice(field.size, 400, replace=False))
     ridx = np.sort(rng.choice(N.nlam, 200, replace=False))
-    with open(OUT, "w") as f:
-        f.write("# oracle samples for refined_disk (see make_refined_disk.py)\n")
-        f.write(f"l {l}\nn_lambda {N.nlam}\nn_coarse {N.nK}\nvector_seed 4321\n")
+    with open(out, "w") as f:
+        f.write(f"# oracle samples for {os.path.basename(out)[:-12]} (see make_refined_disk.py)\n")
+        if not callable(l):
+            f.write(f"l {l}\n")
+        f.write(f"n_lambda {N.nlam}\nn_coarse {N.nK}\nvector_seed {seed}\n")
         f.write(f"oracle_iterations_1e-13 {N.iters}\n")
         for i in fidx:
             f.write(f"field {i} {field[i].real:.17e} {field[i].imag:.17e}\n")
         for i in ridx:
             f.write(f"Fv {i} {Fv[i].real:.17e} {Fv[i].imag:.17e}\n")
             f.write(f"g {i} {g[i].real:.17e} {g[i].imag:.17e}\n")
-    print("wrote", OUT, "oracle iterations to 1e-13:", N.iters)
+    print("wrote", out, "oracle iterations to 1e-13:", N.iters, flush=True)
+
+
+def main():
+    which = sys.argv[1:] or ["plain", "per_edge"]
+    w = W.refined_disk()
+    if "plain" in which:
+        write(w, os.path.join(GOLD, "refined_disk_samples.txt"), 4321)
+    if "per_edge" in which:
+        write(dict(w, l_per_edge=True), os.path.join(GOLD, "refined_disk_per_edge_samples.txt"), 4322)
 
 
 if __name__ == "__main__":

@@ -116,9 +116,9 @@ def test_point_source_mixed_full_size():
     s.close()
 
 
-def _disk_samples():
+def _disk_samples(name):
     meta, field, Fv, g = {}, [], [], []
-    for line in open(os.path.join(GOLD, "refined_disk_samples.txt")):
+    for line in open(os.path.join(GOLD, name + "_samples.txt")):
         if line.startswith("#"):
             continue
         t = line.split()
@@ -129,19 +129,24 @@ def _disk_samples():
     return meta, field, Fv, g
 
 
-def test_refined_disk_full_size_against_the_oracle():
-    """The 712-leaf refined disk (p 8..24, k = 200, l = 14, discard threshold
-    1e-3, up to three hanging nodes per edge) against the element-wise oracle on
-    quadtree meshes (samples by tests/golden/make_refined_disk.py): rows of F v
+@pytest.mark.parametrize("name", ["refined_disk", "refined_disk_per_edge"])
+def test_refined_disk_full_size_against_the_oracle(name):
+    """The 712-leaf refined disk (p 8..24, k = 200, l = 14 or the per-edge
+    orders, discard threshold 1e-3, up to three hanging nodes per edge) against
+    the element-wise oracle on quadtree meshes (samples by
+    tests/golden/make_refined_disk.py): rows of F v
     to 1e-11, of the interface right-hand side to 1e-10 (it carries one coarse
     solve by itself, and the nested-dissection factor's set-up check on this
     mesh, ||K x - b|| / ||b||, is about 1e-10), the field to 1e-10 (FP64, GMRES
     to 1e-12) and to 1e-8 (mixed, to 1e-10)."""
-    meta, field, Fv_ref, g_ref = _disk_samples()
+    meta, field, Fv_ref, g_ref = _disk_samples(name)
     w = W.refined_disk()
+    if name.endswith("per_edge"):
+        w = dict(w, l_per_edge=True)
     kind, vals = hdp().rhs_values(w)
     s = hdp().Solver(w, tol=1e-12, max_iter=800)
-    assert (s.n_lambda, s.n_coarse, s.info["l"]) == (meta["n_lambda"], meta["n_coarse"], meta["l"])
+    assert (s.n_lambda, s.n_coarse) == (meta["n_lambda"], meta["n_coarse"])
+    assert "l" not in meta or s.info["l"] == meta["l"]
     rng = np.random.default_rng(meta["vector_seed"])
     v = rng.standard_normal(s.n_lambda) + 1j * rng.standard_normal(s.n_lambda)
     Fv = s.apply_interface(torch.from_numpy(v[:, None].copy()).cuda(), "fp64").cpu().numpy()[:, 0]
