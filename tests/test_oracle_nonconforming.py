@@ -73,3 +73,30 @@ def test_conforming_mesh_equals_the_conforming_element_wise_oracle():
     v = np.random.default_rng(3).standard_normal(N.nlam) + 0j
     assert rel(N.apply_F(v), Ew.apply_F(v)) < 1e-12
     assert rel(N.interface_rhs(), Ew.interface_rhs()) < 1e-12
+
+
+def test_what_the_discard_threshold_changes():
+    """Sec. 2.2.4 drops the dual rows of a hanging edge whose L_c^f diagonal a^k
+    has decayed below a user threshold tau; the rows are part of the discrete
+    problem, so dropping them changes the solution.  On the small refined disk
+    (p 3..6, two refinement levels, a = 1/4): tau = 1e-8 and 1e-4 drop nothing
+    and give the Galerkin solution of the conforming space (direct solve, every
+    row); tau = 1e-3 drops the rows of degree 5 and 6 (427 -> 389 dual rows) and
+    moves the field by 2.7e-3 relative; tau = 1e-2 drops degree 4 too (359) and
+    moves it by 1.5e-2.  The refined-disk workload uses tau = 1e-3."""
+    from oracle import direct
+    w0 = W.small_disk(tau=0.0)
+    d0 = pb.Discretisation(w0)
+    exact = np.concatenate(pb.gll_field(d0.mesh, d0.degrees, direct.conforming_solution(d0)))
+    got = {}
+    for tau in (1e-8, 1e-4, 1e-3, 1e-2):
+        w = W.small_disk(tau=tau)
+        disc = pb.Discretisation(w)
+        N = dnc.NonconformingDP(disc, pb.coarse_order(w, disc.mesh))
+        Fd = np.stack([N.apply_F(e) for e in np.eye(N.nlam, dtype=complex)], axis=1)
+        nu = np.linalg.solve(Fd, N.interface_rhs())
+        got[tau] = (N.nlam, rel(np.concatenate(pb.gll_field(disc.mesh, disc.degrees, N.recover(nu))), exact))
+    assert got[1e-8][0] == got[1e-4][0] == 427 and got[1e-3][0] == 389 and got[1e-2][0] == 359
+    assert got[1e-8][1] < 1e-12 and got[1e-4][1] < 1e-12
+    assert 2e-3 < got[1e-3][1] < 4e-3
+    assert 1e-2 < got[1e-2][1] < 2e-2
