@@ -372,20 +372,23 @@ def cpu_baseline():
 
 def cpu_baseline_full():
     """The oracle on whole workloads (not part of the default run): the 4x4
-    plane wave and the 32x32 point source, set-up and solve to 1e-8 timed
-    separately, on this host's cores."""
+    plane wave, the 32x32 point source and the refined disk (the quadtree
+    element-wise oracle), set-up and solve to 1e-8 timed separately, on this
+    host's cores."""
     import workloads as W
-    from oracle import dp_elementwise as dpe, problem as pb
+    from oracle import dp_elementwise as dpe, dp_nonconforming as dnc, problem as pb
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count()
     out = {"cores": int(threads), "cpu_count": os.cpu_count(), "kind": "oracle"}
-    for name, w in (("plane_wave_4x4", W.plane_wave_4x4()), ("point_source_32x32", W.point_source_32x32())):
+    for name, w in (("plane_wave_4x4", W.plane_wave_4x4()), ("point_source_32x32", W.point_source_32x32()),
+                    ("refined_disk", W.refined_disk())):
         t0 = time.perf_counter()
         disc = pb.Discretisation(w)
-        E = dpe.ElementwiseDP(disc, pb.coarse_order(w, disc.mesh))
+        oracle = dnc.NonconformingDP if name == "refined_disk" else dpe.ElementwiseDP
+        E = oracle(disc, pb.coarse_order(w, disc.mesh))
         t1 = time.perf_counter()
         E.solve(tol=1e-8, max_iter=400)
         t2 = time.perf_counter()
