@@ -151,10 +151,11 @@ typedef struct {
  * instead of launching its kernels one by one. */
 #define HDP_FLAG_GRAPH 1
 /* coarse factor: by default a dense inverse up to 6,000 coarse unknowns and the
-   nested-dissection multifrontal factor above; these flags force one of them, or
-   the block-tridiagonal strip factor (at most one of the three may be set).  When the
-   set-up check of the factor (hdp_stats.coarse_residual) exceeds 1e-10, every coarse
-   solve is refined once against the assembled K (the check reports the refined solve). */
+   nested-dissection multifrontal factor above; these flags force one of them (at most
+   one may be set).  When the set-up check of the factor (hdp_stats.coarse_residual)
+   exceeds 1e-10, every coarse solve is refined once against the assembled K (the
+   check reports the refined solve).  HDP_FLAG_COARSE_BLOCK named a block-tridiagonal
+   strip factor that is no longer provided: setting it is HDP_E_ARG. */
 #define HDP_FLAG_COARSE_BLOCK 2
 #define HDP_FLAG_COARSE_DENSE 4
 #define HDP_FLAG_COARSE_ND 8
@@ -188,12 +189,13 @@ typedef struct {
   double rhs_ms, gmres_ms, gmres_launch_ms, gmres_wait_ms, recover_ms;
   double true_residual;       /* ||g - F nu|| / ||g|| in FP64 after the solve, max over RHS */
   double coarse_residual;     /* setup check of the coarse factor: ||K x - b|| / ||b|| */
-  int32_t coarse_mode;        /* 0 dense inverse, 1 block-tridiagonal strips, 2 nested dissection */
-  int32_t coarse_blocks;      /* strips, or nested-dissection tree nodes (1 for the dense inverse) */
-  double coarse_factor_bytes; /* bytes of the coarse factor as stored (dense inverse, strips or
+  int32_t coarse_mode;        /* 0 dense inverse, 2 nested dissection */
+  int32_t coarse_blocks;      /* nested-dissection tree nodes (1 for the dense inverse) */
+  double coarse_factor_bytes; /* bytes of the coarse factor as stored (dense inverse or
                                  nested-dissection fronts) */
-  double coarse_band_bytes;   /* bytes of a banded (envelope) LU factor of K in its natural order:
-                                 what one coarse solve with the paper's plain factorisation reads */
+  double coarse_band_bytes;   /* bytes of a banded (envelope) LU factor of K with the coarse unknowns
+                                 in breadth-first level order (bandwidth-reducing, from the bottom
+                                 edge): what one coarse solve with a plain factorisation reads */
   /* set-up breakdown (host wall clock, ms): the host analysis as a whole (constraints,
    * element classes, coarse maps), its element-class operators (eigenbases, unit solves,
    * Schur blocks; built on up to 16 host threads), and the coarse factor */
@@ -209,8 +211,10 @@ typedef struct hdp_handle hdp_handle;
  * assemble the coarse matrix K = A_22 - A_12^T A_11^-1 A_12 and factor it in
  * FP64: by default a dense inverse up to 6,000 coarse unknowns and a
  * nested-dissection multifrontal factor above (fronts factored on the host,
- * sweeps on the device); HDP_FLAG_COARSE_* select one of the factors,
- * including the block-tridiagonal strip factor.  Leaves must tile the domain
+ * sweeps on the device); HDP_FLAG_COARSE_DENSE / _ND select one of them.
+ * Every coarse solve runs in the library's own kernels (a streamed symmetric
+ * inverse or tile products of the inverse; the nested-dissection sweeps).
+ * Leaves must tile the domain
  * (HDP_E_MESH otherwise). */
 hdp_status hdp_setup(const hdp_mesh* mesh, const hdp_problem* prob,
                      const hdp_options* opt, hdp_handle** out);

@@ -209,7 +209,7 @@ class Solver:
         self.precision = HDP_MIXED if precision == "mixed" else HDP_FP64
         with torch.cuda.device(self.device):
             stream = torch.cuda.current_stream(self.device).cuda_stream
-            flags = ((1 if graphs else 0) | {"auto": 0, "block": 2, "dense": 4, "nd": 8}[coarse]
+            flags = ((1 if graphs else 0) | {"auto": 0, "dense": 4, "nd": 8}[coarse]
                      | (16 if autotune else 0))
             opt = _Options(self.precision, float(tol), int(max_iter), int(max_rhs), ctypes.c_void_p(stream), flags,
                            int(tile_fdm), int(tile_slot))

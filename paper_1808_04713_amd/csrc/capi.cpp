@@ -153,121 +153,36 @@ static void build_coarse_dense(Handle& h, const std::vector<int64_t>& kidx, cons
   d.sym_part = dalloc<double2>(h, size_t(h.sym_nt) * h.sym_nt * ts);
   launch_pack_sym_tiles(h, h.stream);
   h.coarse_bytes1 = 16.0 * double(nK) * double(nK + 1) / 2;
+  // several columns: w = K^-T g by the nested-dissection tile kernels, the inverse
+  // taken as the diagonal block of a one-node tree (no boundary, no children);
+  // 32-row output tiles, each tile's sum split so that about 1024 workgroups run
+  if (pow2ceil(h.max_rhs) >= 4) {
+    const int ntiles = int((nK + 31) / 32);
+    const int S = std::max(1, std::min((1024 + ntiles - 1) / ntiles, ntiles));
+    const int chunk = int((nK + S - 1) / S);
+    std::vector<int4> tasks;
+    for (int j = 0; j < int(nK); j += 32)
+      for (int c = 0; c < S; ++c)
+        tasks.push_back(make_int4(0, j, std::min(int(nK), c * chunk), std::min(int(nK), (c + 1) * chunk)));
+    d.dn_tasks = upload(h, tasks);
+    d.dn_off = upload(h, std::vector<int>{0, int(nK)});
+    d.dn_boff = upload(h, std::vector<int64_t>{0, 0});
+    d.dn_zero64 = upload(h, std::vector<int64_t>{0});
+    d.dn_int = upload(h, std::vector<int>{-1, -1, 0});
+    h.dn_ntiles = ntiles;
+    h.dn_S = S;
+    if (S > 1) d.dn_P = dalloc<double2>(h, size_t(ntiles) * S * 32 * 64);
+  }
 }
 
-static void zgemm(Handle& h, rocblas_operation tb, int m, int n, int k, double alpha, const double2* A, int lda,
-                  const double2* B, int ldb, double beta, double2* C, int ldc) {
-  rocblas_double_complex a(alpha, 0.0), b(beta, 0.0);
-  rocblas_status st = rocblas_zgemm(static_cast<rocblas_handle>(h.rocblas), rocblas_operation_none, tb, m, n, k, &a,
-                                    reinterpret_cast<const rocblas_double_complex*>(A), lda,
-                                    reinterpret_cast<const rocblas_double_complex*>(B), ldb, &b,
-                                    reinterpret_cast<rocblas_double_complex*>(C), ldc);
-  if (st != rocblas_status_success) fail(HDP_E_DEVICE, "rocblas_zgemm failed");
-}
-
-static void zgemv(Handle& h, int m, int n, double alpha, const double2* A, int lda, const double2* x, double beta,
-                  double2* y) {
-  rocblas_double_complex a(alpha, 0.0), b(beta, 0.0);
-  rocblas_status st = rocblas_zgemv(static_cast<rocblas_handle>(h.rocblas), rocblas_operation_none, m, n, &a,
-                                    reinterpret_cast<const rocblas_double_complex*>(A), lda,
-                                    reinterpret_cast<const rocblas_double_complex*>(x), 1, &b,
-                                    reinterpret_cast<rocblas_double_complex*>(y), 1);
-  if (st != rocblas_status_success) fail(HDP_E_DEVICE, "rocblas_zgemv failed");
-}
-
-// out (cols x rows, column-major) = in^T, in rows x cols column-major
-static void transpose_into(Handle& h, const double2* in, int rows, int cols, double2* out) {
-  rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
-  rocblas_status st = rocblas_zgeam(static_cast<rocblas_handle>(h.rocblas), rocblas_operation_transpose,
-                                    rocblas_operation_none, cols, rows, &one,
-                                    reinterpret_cast<const rocblas_double_complex*>(in), rows, &zero,
-                                    reinterpret_cast<const rocblas_double_complex*>(out), cols,
-                                    reinterpret_cast<rocblas_double_complex*>(out), cols);
-  if (st != rocblas_status_success) fail(HDP_E_DEVICE, "rocblas_zgeam failed");
-}
-
-// a rows x cols block transposed in its own storage (through the scratch buffer)
-static void transpose_into_inplace(Handle& h, double2* a, int rows, int cols) {
-  HIPCHECK(hipMemcpyAsync(h.d.ctmp, a, size_t(rows) * cols * sizeof(double2), hipMemcpyDeviceToDevice, h.stream));
-  transpose_into(h, h.d.ctmp, rows, cols, a);
-}
-
-// Block-tridiagonal factor of K over the coarse strips (block LU, partial
-// pivoting inside each diagonal block): D_0 = K_00, D_i = K_ii - K_{i,i-1} U_{i-1};
-// stored D_i^-1 (symmetric, as K is), W_i^T and U_i^T with W_i = D_i^-1 K_{i,i-1}
-// and U_i = D_i^-1 K_{i,i+1} (column-major).
-static void build_coarse_blocks(Handle& h, const std::vector<int64_t>& kidx, const std::vector<double2>& kval) {
+// w = K^-T g at several columns with the tile kernels (see build_coarse_dense).
+static void coarse_solve_dense_tiles(Handle& h, const double2* g, double2* w, int R) {
   auto& d = h.d;
-  const int nb = int(h.cb_off.size()) - 1;
-  const int64_t nK = h.nK;
-  auto sz = [&](int b) { return (b < 0 || b >= nb) ? 0 : h.cb_off[b + 1] - h.cb_off[b]; };
-  std::vector<int> blk(h.nK);
-  for (int b = 0; b < nb; ++b)
-    for (int i = h.cb_off[b]; i < h.cb_off[b + 1]; ++i) blk[i] = b;
-  h.cb_D.assign(nb, 0); h.cb_W.assign(nb, 0); h.cb_U.assign(nb, 0);
-  int64_t tot = 0, tmpmax = 1;
-  int nmax = 1;
-  for (int b = 0; b < nb; ++b) {
-    int64_t n = sz(b);
-    h.cb_D[b] = tot; tot += n * n;
-    h.cb_W[b] = tot; tot += n * sz(b - 1);
-    h.cb_U[b] = tot; tot += n * sz(b + 1);
-    nmax = std::max(nmax, int(n));
-    tmpmax = std::max(tmpmax, n * std::max(sz(b - 1), sz(b + 1)));
-  }
-  std::vector<int64_t> bidx(kidx.size());
-  for (size_t t = 0; t < kidx.size(); ++t) {
-    int64_t i = kidx[t] % nK, j = kidx[t] / nK;
-    int bi = blk[i], bj = blk[j];
-    int64_t li = i - h.cb_off[bi], lj = j - h.cb_off[bj], n = sz(bi);
-    int64_t off;
-    if (bj == bi) off = h.cb_D[bi];
-    else if (bj == bi - 1) off = h.cb_W[bi];
-    else if (bj == bi + 1) off = h.cb_U[bi];
-    else fail(HDP_E_MESH, "coarse strips are not block tridiagonal");
-    bidx[t] = off + li + n * lj;
-  }
-  d.cblk = dalloc<double2>(h, size_t(tot));
-  d.ctmp = dalloc<double2>(h, size_t(tmpmax));
-  HIPCHECK(hipMemsetAsync(d.cblk, 0, size_t(tot) * sizeof(double2), h.stream));
-  int64_t* didx = upload(h, bidx);
-  double2* dval = upload(h, kval);
-  launch_dense_scatter(didx, dval, int64_t(bidx.size()), d.cblk, h.stream);
-  rocblas_handle rb = static_cast<rocblas_handle>(h.rocblas);
-  int* ipiv = dalloc<int>(h, size_t(nmax));
-  int* info = dalloc<int>(h, size_t(nb));
-  HIPCHECK(hipMemsetAsync(info, 0, size_t(nb) * sizeof(int), h.stream));
-  for (int b = 0; b < nb; ++b) {
-    const int n = sz(b), np = sz(b - 1), nn = sz(b + 1);
-    double2* Db = d.cblk + h.cb_D[b];
-    if (b > 0) zgemm(h, rocblas_operation_none, n, n, np, -1.0, d.cblk + h.cb_W[b], n, d.cblk + h.cb_U[b - 1], np, 1.0, Db, n);
-    if (rocsolver_zgetrf(rb, n, n, (rocblas_double_complex*)Db, n, ipiv, info + b) != rocblas_status_success ||
-        rocsolver_zgetri(rb, n, (rocblas_double_complex*)Db, n, ipiv, info + b) != rocblas_status_success)
-      fail(HDP_E_DEVICE, "rocsolver failed on a coarse block");
-    // W_b and U_b are kept transposed (np x n and nn x n) so that the sweeps are
-    // plain NN products on the [n_K][R] layout; U_b is needed untransposed by the
-    // next block's Schur complement first
-    if (np > 0) {
-      zgemm(h, rocblas_operation_none, n, np, n, 1.0, Db, n, d.cblk + h.cb_W[b], n, 0.0, d.ctmp, n);
-      transpose_into(h, d.ctmp, n, np, d.cblk + h.cb_W[b]);
-    }
-    if (b > 0) transpose_into_inplace(h, d.cblk + h.cb_U[b - 1], sz(b - 1), n);
-    if (nn > 0) {
-      zgemm(h, rocblas_operation_none, n, nn, n, 1.0, Db, n, d.cblk + h.cb_U[b], n, 0.0, d.ctmp, n);
-      HIPCHECK(hipMemcpyAsync(d.cblk + h.cb_U[b], d.ctmp, size_t(n) * nn * sizeof(double2), hipMemcpyDeviceToDevice,
-                              h.stream));
-    }
-  }
-  std::vector<int> hinfo(nb);
-  HIPCHECK(hipMemcpyAsync(hinfo.data(), info, size_t(nb) * sizeof(int), hipMemcpyDeviceToHost, h.stream));
-  HIPCHECK(hipStreamSynchronize(h.stream));
-  for (int b = 0; b < nb; ++b)
-    if (hinfo[b] != 0) fail(HDP_E_COARSE, "coarse Schur-complement block " + std::to_string(b) + " is singular");
-  d.cb_off = upload(h, h.cb_off);
-  d.cb_D = upload(h, h.cb_D);
-  h.coarse_mode = 1;
-  h.coarse_bytes = 16.0 * double(tot);
-  h.coarse_flops = 8.0 * double(tot);
+  NDView v;
+  v.off = d.dn_off; v.boff = d.dn_boff; v.bnd = d.dn_int + 2; v.uoff = d.dn_zero64; v.push = d.dn_int + 2;
+  v.mD = d.dn_zero64; v.mL = d.dn_zero64; v.mLt = d.dn_zero64; v.fac = d.Kinv;
+  v.push2 = d.dn_int + 2; v.child = d.dn_int; v.slot = nullptr; v.ld = pow2ceil(h.max_rhs); v.srows = 0; v.nK = h.nK;
+  launch_nd_tiles(true, d.dn_tasks, h.dn_ntiles, h.dn_S, v, g, w, R, d.dn_P, h.stream);
 }
 
 // Nested-dissection factor: assembled on the host (coarse_nd.cpp), uploaded
@@ -392,68 +307,6 @@ static void coarse_solve_nd(Handle& h, const double2* g, double2* w, int R) {
   for (int L = 0; L < nd; ++L) {   // root first
     const NDLevel& lv = h.nd_levels[L];
     launch_nd_tiles(true, d.nd_tRb + lv.bR, lv.nbR, lv.Sb, v, g, w, R, d.nd_P, h.stream);
-  }
-}
-
-static void zgemv_t(Handle& h, int m, int n, double alpha, const double2* A, int lda, const double2* x, double beta,
-                    double2* y) {
-  rocblas_double_complex a(alpha, 0.0), b(beta, 0.0);
-  rocblas_status st = rocblas_zgemv(static_cast<rocblas_handle>(h.rocblas), rocblas_operation_transpose, m, n, &a,
-                                    reinterpret_cast<const rocblas_double_complex*>(A), lda,
-                                    reinterpret_cast<const rocblas_double_complex*>(x), 1, &b,
-                                    reinterpret_cast<rocblas_double_complex*>(y), 1);
-  if (st != rocblas_status_success) fail(HDP_E_DEVICE, "rocblas_zgemv failed");
-}
-
-static void coarse_solve_blocks(Handle& h, const double2* g, double2* w, int R) {
-  auto& d = h.d;
-  const int nb = int(h.cb_off.size()) - 1;
-  auto sz = [&](int b) { return (b < 0 || b >= nb) ? 0 : h.cb_off[b + 1] - h.cb_off[b]; };
-  if (R == 64) {
-    // own batched kernel for the diagonal products of all strips; the sweeps'
-    // small products go to the library (NN)
-    launch_strip_diag64(h, g, w, h.stream);
-    const rocblas_operation N = rocblas_operation_none;
-    for (int b = 1; b < nb; ++b) {
-      const int64_t o = h.cb_off[b], op = h.cb_off[b - 1];
-      zgemm(h, N, R, sz(b), sz(b - 1), -1.0, w + op * R, R, d.cblk + h.cb_W[b], sz(b - 1), 1.0, w + o * R, R);
-    }
-    for (int b = nb - 2; b >= 0; --b) {
-      const int64_t o = h.cb_off[b], on = h.cb_off[b + 1];
-      zgemm(h, N, R, sz(b), sz(b + 1), -1.0, w + on * R, R, d.cblk + h.cb_U[b], sz(b + 1), 1.0, w + o * R, R);
-    }
-    return;
-  }
-  if (R == 1) {
-    // own kernels at one column: all diagonal products at once, then the two sweeps
-    launch_strip_diag(h, g, w, h.stream);
-    for (int b = 1; b < nb; ++b) {
-      double2* wb = w + h.cb_off[b];
-      launch_strip_step(d.cblk + h.cb_W[b], sz(b - 1), w + h.cb_off[b - 1], sz(b), wb, -1.0, wb, h.stream);
-    }
-    for (int b = nb - 2; b >= 0; --b) {
-      double2* wb = w + h.cb_off[b];
-      launch_strip_step(d.cblk + h.cb_U[b], sz(b + 1), w + h.cb_off[b + 1], sz(b), wb, -1.0, wb, h.stream);
-    }
-    return;
-  }
-  const rocblas_operation N = rocblas_operation_none;
-  // [n_K][R] row-major is the column-major R x n_K matrix: a block's rows are a
-  // contiguous R x n_b slice X_b, and D^-1 x becomes X_b D^-T = X_b D^-1
-  for (int b = 0; b < nb; ++b) {
-    const int64_t o = h.cb_off[b];
-    if (R == 1) zgemv(h, sz(b), sz(b), 1.0, d.cblk + h.cb_D[b], sz(b), g + o, 0.0, w + o);
-    else zgemm(h, N, R, sz(b), sz(b), 1.0, g + o * R, R, d.cblk + h.cb_D[b], sz(b), 0.0, w + o * R, R);
-  }
-  for (int b = 1; b < nb; ++b) {   // y_b -= W_b y_{b-1}: Y_b -= Y_{b-1} W_b^T
-    const int64_t o = h.cb_off[b], op = h.cb_off[b - 1];
-    if (R == 1) zgemv_t(h, sz(b - 1), sz(b), -1.0, d.cblk + h.cb_W[b], sz(b - 1), w + op, 1.0, w + o);
-    else zgemm(h, N, R, sz(b), sz(b - 1), -1.0, w + op * R, R, d.cblk + h.cb_W[b], sz(b - 1), 1.0, w + o * R, R);
-  }
-  for (int b = nb - 2; b >= 0; --b) {   // x_b = y_b - U_b x_{b+1}
-    const int64_t o = h.cb_off[b], on = h.cb_off[b + 1];
-    if (R == 1) zgemv_t(h, sz(b + 1), sz(b), -1.0, d.cblk + h.cb_U[b], sz(b + 1), w + on, 1.0, w + o);
-    else zgemm(h, N, R, sz(b), sz(b + 1), -1.0, w + on * R, R, d.cblk + h.cb_U[b], sz(b + 1), 1.0, w + o * R, R);
   }
 }
 
@@ -682,12 +535,10 @@ void build_device(Handle& h) {
   rocblas_handle rb;
   if (rocblas_create_handle(&rb) != rocblas_status_success) fail(HDP_E_DEVICE, "rocblas_create_handle");
   rocblas_set_stream(rb, h.stream);
-  h.rocblas = rb;   // kept for the coarse solves
-  // the coarse factor chosen at set-up: dense inverse (0), strips (1) or nested
-  // dissection (2)
+  h.rocblas = rb;   // rocSOLVER's factorisation of the dense coarse inverse at set-up
+  // the coarse factor chosen at set-up: dense inverse (0) or nested dissection (2)
   const auto tk = std::chrono::steady_clock::now();
-  if (h.coarse_mode == 1) build_coarse_blocks(h, kidx, kval);
-  else if (h.coarse_mode == 2) build_coarse_nd(h, kidx, kval);
+  if (h.coarse_mode == 2) build_coarse_nd(h, kidx, kval);
   else build_coarse_dense(h, kidx, kval);
   h.setup_coarse_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tk).count();
   // work buffers sized for the largest RHS batch (padded to a power of two)
@@ -790,12 +641,8 @@ void build_device(Handle& h) {
 // ---------------------------------------------------------------------------
 // Operators on dual vectors ([nlam][R]).
 // w = K^-1 g for R right-hand sides ([n_K][R]): a streaming GEMV kernel for a
-// few columns, a plain library GEMM (rocBLAS zgemm) once R makes it compute-bound.
+// few columns, the tile kernels (matrix cores at 16-64 columns) from 4 on.
 static void coarse_solve_once(Handle& h, const double2* g, double2* w, int R) {
-  if (h.coarse_mode == 1) {
-    coarse_solve_blocks(h, g, w, R);
-    return;
-  }
   if (h.coarse_mode == 2) {
     coarse_solve_nd(h, g, w, R);
     return;
@@ -804,14 +651,7 @@ static void coarse_solve_once(Handle& h, const double2* g, double2* w, int R) {
     launch_coarse_solve(h, g, w, R, h.stream);
     return;
   }
-  // [n_K][R] row-major is the column-major R x n_K matrix; W^T = G^T K^-1
-  rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
-  rocblas_status st = rocblas_zgemm(static_cast<rocblas_handle>(h.rocblas), rocblas_operation_none,
-                                    rocblas_operation_none, R, h.nK, h.nK, &one,
-                                    reinterpret_cast<const rocblas_double_complex*>(g), R,
-                                    reinterpret_cast<const rocblas_double_complex*>(h.d.Kinv), h.nK, &zero,
-                                    reinterpret_cast<rocblas_double_complex*>(w), R);
-  if (st != rocblas_status_success) fail(HDP_E_DEVICE, "rocblas_zgemm failed in the coarse solve");
+  coarse_solve_dense_tiles(h, g, w, R);
 }
 
 // The coarse solve inside the operator applications, timed per kernel family:
@@ -1103,8 +943,8 @@ GmresResult gmres(Handle& h, const double2* rhs, double2* x, int R, int prec, do
     };
     // one GMRES iteration as a captured graph (every launch reads j on the device)
     hipGraphExec_t exec = nullptr;
-    // captured only when no library routine is in the loop: the dense inverse at
-    // fewer than 4 columns and the nested-dissection sweeps
+    // captured at fewer than 4 columns (no library routine is in any solve; the
+    // replay test covers one column)
     const bool graph = h.use_graphs && !h.prof.on && (h.coarse_mode == 0 || h.coarse_mode == 2) && R < 4;
     if (graph) {
       auto key = std::make_tuple(R, prec, tol);
@@ -1393,15 +1233,11 @@ hdp_status hdp_setup(const hdp_mesh* mesh, const hdp_problem* prob, const hdp_op
     fail(HDP_E_ARG, "tile_slot must be 0, 16, 32 or 64");
   h.fdm_rc = opt->tile_fdm;
   if (opt->tile_slot) h.slot_rb = opt->tile_slot;
-  {
-    const int nf = ((opt->flags & HDP_FLAG_COARSE_BLOCK) != 0) + ((opt->flags & HDP_FLAG_COARSE_DENSE) != 0) +
-                   ((opt->flags & HDP_FLAG_COARSE_ND) != 0);
-    if (nf > 1) fail(HDP_E_ARG, "HDP_FLAG_COARSE_BLOCK, _DENSE and _ND are exclusive");
-  }
-  h.coarse_mode = (opt->flags & HDP_FLAG_COARSE_BLOCK)   ? 1
-                  : (opt->flags & HDP_FLAG_COARSE_DENSE) ? 0
-                  : (opt->flags & HDP_FLAG_COARSE_ND)    ? 2
-                                                         : -1;
+  if (opt->flags & HDP_FLAG_COARSE_BLOCK)
+    fail(HDP_E_ARG, "HDP_FLAG_COARSE_BLOCK: the strip factor is no longer provided (use HDP_FLAG_COARSE_ND)");
+  if ((opt->flags & HDP_FLAG_COARSE_DENSE) && (opt->flags & HDP_FLAG_COARSE_ND))
+    fail(HDP_E_ARG, "HDP_FLAG_COARSE_DENSE and HDP_FLAG_COARSE_ND are exclusive");
+  h.coarse_mode = (opt->flags & HDP_FLAG_COARSE_DENSE) ? 0 : (opt->flags & HDP_FLAG_COARSE_ND) ? 2 : -1;
   try {
     HIPCHECK(hipGetDevice(&h.device));
     scratch_init(h.device);   // the allocation-free entry point's array on this device
@@ -1468,9 +1304,7 @@ hdp_status hdp_get_stats(const hdp_handle* H, hdp_stats* st) {
   st->setup_classes_ms = h.setup_classes_ms;
   st->setup_coarse_ms = h.setup_coarse_ms;
   st->coarse_factor_bytes = h.coarse_bytes;
-  st->coarse_blocks = st->coarse_mode == 1   ? int(h.cb_off.size()) - 1
-                      : st->coarse_mode == 2 ? int(h.nd_off.size()) - 1
-                                             : 1;
+  st->coarse_blocks = st->coarse_mode == 2 ? int(h.nd_off.size()) - 1 : 1;
   return HDP_OK;
   API_END
 }

@@ -178,10 +178,8 @@ struct Handle {
   std::vector<int> cm_mode;       // per coarse mode, local mode index
   std::vector<double> dof_x, dof_y;   // per coarse unknown: position of its vertex or edge midpoint
   std::vector<char> dof_vtx;          // per coarse unknown: 1 for a mesh vertex
-  // coarse factor: 0 dense inverse of K, 1 block-tridiagonal factor over the
-  // strips cb_off (consecutive coarse unknowns); per block i the inverse D_i^-1
-  // of the Schur-complement block and W_i = D_i^-1 K_{i,i-1}, U_i = D_i^-1 K_{i,i+1}
-  // 2 nested-dissection multifrontal factor: tree nodes in postorder, node t
+  // coarse factor: 0 dense inverse of K (coarse unknowns in breadth-first level
+  // order), 2 nested-dissection multifrontal factor: tree nodes in postorder, node t
   // owns the coarse unknowns [nd_off[t], nd_off[t+1]) and, after its subtree is
   // eliminated, couples to the ancestor unknowns nd_bnd[nd_boff[t] .. nd_boff[t+1])
   int coarse_mode = -1;            // -1: chosen by size at setup
@@ -190,11 +188,10 @@ struct Handle {
   std::vector<int> nd_bnd;
   std::vector<NDLevel> nd_levels;   // per tree depth
   int nd_split = 1024;              // workgroups a depth's split tiles aim at (several columns)
+  int dn_ntiles = 0, dn_S = 1;      // dense inverse at several columns: output tiles, splits
   int64_t nd_P_tasks = 0;           // partial tiles nd_P holds
   size_t nd_tR_cap[2] = {0, 0};     // capacity of nd_tRf / nd_tRb
   bool coarse_refine = false;       // refine each coarse solve once (set at setup from the check)
-  std::vector<int> cb_off;
-  std::vector<int64_t> cb_D, cb_W, cb_U;
   double coarse_check = 0;         // relative residual of the coarse factor on a test vector
   int sym_nt = 0, sym_ntiles = 0;   // tile rows and upper tiles of the symmetric coarse inverse
   double coarse_bytes1 = 0;         // factor bytes of a one-RHS coarse solve (half with the tiles)
@@ -245,7 +242,6 @@ struct Handle {
     double* adj_grad = nullptr;
     double* cls_M = nullptr;   // per class the 1-D vertex mass matrix (n x n)
     int64_t* cls_Moff = nullptr;
-    double2 *cblk = nullptr, *ctmp = nullptr;   // block-tridiagonal coarse factor
     // nested-dissection coarse factor
     double2 *nd_fac = nullptr, *nd_FA = nullptr;   // FA: front accumulators, n_K then update rows
     int *nd_off = nullptr, *nd_bnd = nullptr, *nd_push = nullptr;
@@ -261,10 +257,13 @@ struct Handle {
     int4 *nd_tRf = nullptr, *nd_tRb = nullptr;
     double2* nd_P = nullptr;   // partial tiles of the split top levels
     double2* nd_slot = nullptr;   // two child slots per front row, [2][nK + urows][Rp], zero from set-up
+    // dense inverse at several columns through the tile kernels (a one-node tree)
+    int4* dn_tasks = nullptr;
+    int *dn_off = nullptr, *dn_int = nullptr;   // dn_int: children {-1, -1}, then a zero
+    int64_t *dn_boff = nullptr, *dn_zero64 = nullptr;
+    double2* dn_P = nullptr;
     int *nd_push2 = nullptr, *nd_childv = nullptr;
     int64_t nd_ld = 0;
-    int* cb_off = nullptr;
-    int64_t* cb_D = nullptr;
     // per-class tables
     int *cls_n = nullptr, *cls_m = nullptr, *cls_nr = nullptr;
     int* cls_real = nullptr;   // 1 when the class's eigenbasis is real

@@ -639,111 +639,9 @@ __global__ void __launch_bounds__(NT) k_hblock(int nh, const int* __restrict__ b
   }
 }
 
-// ---------------------------------------------------------------------------
-// Strip (block-tridiagonal) coarse sweeps at one column.  A strip matrix M is
-// column-major K x n_out (column j contiguous):
-//   out_j = add_j + sign * sum_i M[i, j] in_i
-// One workgroup per output: its four waves stride over i together (4 KiB of the
-// column per pass, four passes in flight per lane), so a sweep step of a few
-// hundred outputs still puts thousands of waves on the chip.
-__device__ __forceinline__ double2 block_dot_col(const double2* __restrict__ col, const double2* __restrict__ v,
-                                                 int K, double2* red) {
-  double ax = 0, ay = 0;
-#pragma unroll 4
-  for (int i = threadIdx.x; i < K; i += NT) {
-    const double2 m = col[i], x = v[i];
-    ax += m.x * x.x - m.y * x.y;
-    ay += m.x * x.y + m.y * x.x;
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    ax += __shfl_xor(ax, off, 64);
-    ay += __shfl_xor(ay, off, 64);
-  }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) red[wv] = make_double2(ax, ay);
-  __syncthreads();
-  double2 t = make_double2(0, 0);
-  if (threadIdx.x == 0)
-    for (int q = 0; q < NT / 64; ++q) {
-      t.x += red[q].x;
-      t.y += red[q].y;
-    }
-  return t;   // valid in thread 0
-}
-
-__global__ void __launch_bounds__(NT) k_strip_mv(const double2* __restrict__ M, int K, const double2* __restrict__ in,
-                                                 int n_out, const double2* __restrict__ add, double sign,
-                                                 double2* __restrict__ out) {
-  __shared__ double2 red[NT / 64];
-  const int j = blockIdx.x;
-  const double2 t = block_dot_col(M + (int64_t)K * j, in, K, red);
-  if (threadIdx.x == 0) {
-    const double2 a = add ? add[j] : make_double2(0, 0);
-    out[j] = make_double2(a.x + sign * t.x, a.y + sign * t.y);
-  }
-}
-
-// 64-column strip products C[j][r] = sum_i M[i, j] X[i][r] (M column-major K x n_out),
-// used for the diagonal products of all strips in one launch.
-// A workgroup owns 32 outputs x 64 columns over a chunk of i: 32-row tiles of M
-// go through LDS (read back as wave-wide broadcasts), X rows are read coalesced
-// (lane = column); each thread accumulates 8 outputs of its column.
+// Tiles of the nested-dissection products (several columns).
 constexpr int SMJ = 32;   // outputs per workgroup
 constexpr int SMK = 32;   // rows of M staged per pass
-
-__device__ __forceinline__ void strip_mm64_core(const double2* __restrict__ M, int K, const double2* __restrict__ X,
-                                                int n_out, int j0, int i0, int i1, double2 (&acc)[8]) {
-  __shared__ double2 Ms[SMK][SMJ + 1];
-  const int r = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int t = 0; t < 8; ++t) acc[t] = make_double2(0, 0);
-  for (int ib = i0; ib < i1; ib += SMK) {
-    const int nk = min(SMK, i1 - ib);
-    for (int e = threadIdx.x; e < SMK * SMJ; e += NT) {
-      const int jj = e / SMK, kk = e % SMK;
-      Ms[kk][jj] = (kk < nk && j0 + jj < n_out) ? M[(ib + kk) + (int64_t)K * (j0 + jj)] : make_double2(0, 0);
-    }
-    __syncthreads();
-    for (int kk = 0; kk < nk; ++kk) {
-      const double2 x = X[(int64_t)(ib + kk) * 64 + r];
-#pragma unroll
-      for (int t = 0; t < 8; ++t) acc[t] = cfma(Ms[kk][wv * 8 + t], x, acc[t]);
-    }
-    __syncthreads();
-  }
-}
-
-// All strips at once (blockIdx.z = strip): w_b = D_b^-1 g_b, D_b^-1 symmetric.
-__global__ void __launch_bounds__(NT) k_strip_diag_mm64(const int* __restrict__ off, const int64_t* __restrict__ moff,
-                                                        const double2* __restrict__ Mall, const double2* __restrict__ g,
-                                                        double2* __restrict__ w) {
-  const int b = blockIdx.z;
-  const int o = off[b], n = off[b + 1] - o;
-  const int j0 = blockIdx.x * SMJ;
-  if (j0 >= n) return;
-  double2 acc[8];
-  strip_mm64_core(Mall + moff[b], n, g + (int64_t)o * 64, n, j0, 0, n, acc);
-  const int r = threadIdx.x & 63, jw = j0 + (threadIdx.x >> 6) * 8;
-  for (int t = 0; t < 8; ++t) {
-    const int j = jw + t;
-    if (j >= n) break;
-    w[((int64_t)o + j) * 64 + r] = acc[t];
-  }
-}
-
-// All strips at once: out_b = M_b in_b with M_b square (the diagonal inverses),
-// one workgroup per output row of a strip (blockIdx.y = strip).
-__global__ void __launch_bounds__(NT) k_strip_diag_mv(const int* __restrict__ off, const int64_t* __restrict__ moff,
-                                                      const double2* __restrict__ Mall, const double2* __restrict__ in,
-                                                      double2* __restrict__ out) {
-  __shared__ double2 red[NT / 64];
-  const int b = blockIdx.y;
-  const int o = off[b], n = off[b + 1] - o;
-  const int j = blockIdx.x;
-  if (j >= n) return;
-  const double2 t = block_dot_col(Mall + moff[b] + (int64_t)n * j, in + o, n, red);
-  if (threadIdx.x == 0) out[o + j] = t;
-}
 
 // ---------------------------------------------------------------------------
 // Nested-dissection coarse solve.  Node t owns the coarse unknowns
@@ -3156,32 +3054,6 @@ template void launch_assemble<float2>(const Handle&, const float2*, const double
                                       int, hipStream_t);
 
 // Strip sweeps of the block-tridiagonal coarse factor at one column.
-void launch_strip_diag(const Handle& h, const double2* g, double2* w, hipStream_t s) {
-  const auto& d = h.d;
-  const int nb = int(h.cb_off.size()) - 1;
-  int nmax = 0;
-  for (int b = 0; b < nb; ++b) nmax = std::max(nmax, h.cb_off[b + 1] - h.cb_off[b]);
-  hipLaunchKernelGGL(k_strip_diag_mv, dim3(nmax, nb), dim3(NT), 0, s, d.cb_off, d.cb_D, d.cblk, g, w);
-  HIPCHECK(hipGetLastError());
-}
-
-void launch_strip_diag64(const Handle& h, const double2* g, double2* w, hipStream_t s) {
-  const auto& d = h.d;
-  const int nb = int(h.cb_off.size()) - 1;
-  int nmax = 0;
-  for (int b = 0; b < nb; ++b) nmax = std::max(nmax, h.cb_off[b + 1] - h.cb_off[b]);
-  hipLaunchKernelGGL(k_strip_diag_mm64, dim3(nblocks(nmax, SMJ), 1, nb), dim3(NT), 0, s, d.cb_off, d.cb_D, d.cblk, g,
-                     w);
-  HIPCHECK(hipGetLastError());
-}
-
-void launch_strip_step(const double2* M, int K, const double2* in, int n_out, const double2* add, double sign,
-                       double2* out, hipStream_t s) {
-  if (n_out <= 0) return;
-  hipLaunchKernelGGL(k_strip_mv, dim3(n_out), dim3(NT), 0, s, M, K, in, n_out, add, sign, out);
-  HIPCHECK(hipGetLastError());
-}
-
 void launch_coarse_symv_tiles(const Handle& h, const double2* g, hipStream_t s) {
   hipLaunchKernelGGL(k_coarse_symv_tiles, dim3(h.sym_ntiles), dim3(SYM_WAVES * 64), 0, s, h.nK, h.sym_nt,
                      h.d.sym_tij, h.d.Ksym, g, h.d.sym_part);

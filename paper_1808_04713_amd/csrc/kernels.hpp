@@ -43,13 +43,6 @@ void launch_hblock(const Handle& h, bool y2, const double2* x, bool in_gather, c
                    bool out_scatter, int R, hipStream_t s);
 // w = K^-1 g (dense, FP64)
 void launch_coarse_solve(const Handle& h, const double2* g, double2* w, int R, hipStream_t s);
-// Strip factor sweeps at one column: w_b = D_b^-1 g_b for every strip b at once, and one
-// step out = add + sign * M^T in with M column-major K x n_out
-void launch_strip_diag(const Handle& h, const double2* g, double2* w, hipStream_t s);
-void launch_strip_step(const double2* M, int K, const double2* in, int n_out, const double2* add, double sign,
-                       double2* out, hipStream_t s);
-// w_b = D_b^-1 g_b for every strip at once, 64 columns
-void launch_strip_diag64(const Handle& h, const double2* g, double2* w, hipStream_t s);
 
 // Full-element operations (arrays [dof][R])
 // With zero_coarse the element's coarse-mode entries of `in` are read as zero

@@ -281,12 +281,11 @@ void build_transposes(Handle& h, bool c2) {
     }
 }
 
-// Renumber the coarse unknowns strip by strip: breadth-first level sets of the
-// coupling graph of K (unknowns sharing an element), started from the
-// unknowns of smallest y.  Level sets only couple to their two neighbours, so
-// K is block tridiagonal over consecutive levels; levels are merged into
-// blocks of at least 256 unknowns (32 when the block factor is forced).
-void order_coarse_strips(Handle& h) {
+// Renumber the coarse unknowns by breadth-first level sets of the coupling
+// graph of K (unknowns sharing an element), started from the unknowns of
+// smallest y: a level set only couples to its two neighbours, which keeps K
+// banded (the order of the dense inverse and of the band-factor byte count).
+void order_coarse_levels(Handle& h) {
   const int nK = h.nK, E = h.E;
   std::vector<std::vector<int>> elem_dofs(E);
   for (int e = 0; e < E; ++e) {
@@ -316,21 +315,12 @@ void order_coarse_strips(Handle& h) {
   }
   for (int d = 0; d < nK; ++d)
     if (lev[d] < 0) fail(HDP_E_MESH, "coarse space not connected");
-  // strips of at least 256 unknowns; 32 when the block factor is requested
-  // explicitly (so that small meshes get several strips too)
-  const int bmin = h.coarse_mode == 1 ? 32 : 256;
   std::vector<int> perm(nK);   // old -> new
-  h.cb_off.assign(1, 0);
-  int pos = 0, in_block = 0;
+  int pos = 0;
   for (size_t L = 0; L < levels.size(); ++L) {
     std::vector<int> lv = levels[L];
     std::sort(lv.begin(), lv.end());
     for (int d : lv) perm[d] = pos++;
-    in_block += int(lv.size());
-    if (in_block >= bmin || L + 1 == levels.size()) {
-      h.cb_off.push_back(pos);
-      in_block = 0;
-    }
   }
   for (auto& d : h.t_dof) d = perm[d];
   for (auto& d : h.c2_dof) d = perm[d];
@@ -1150,7 +1140,7 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
   const bool requested = h.coarse_mode >= 0;
   if (h.coarse_mode < 0) h.coarse_mode = h.nK > 6000 ? 2 : 0;
   if (h.coarse_mode == 2) order_coarse_nd(h, requested ? 32 : 96);
-  else order_coarse_strips(h);
+  else order_coarse_levels(h);
   // algorithmic work counts
   for (auto& C : h.classes) {
     h.op1_bytes += 16.0 * (C.m + C.nr) * C.m;
