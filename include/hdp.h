@@ -133,6 +133,18 @@ typedef struct {
                                  iterations on a 10x10 mesh with an eps_r = 4 block at k = 25). */
 } hdp_problem;
 
+/* Device memory of a handle: hipMalloc / hipFree unless the caller passes its own
+ * pair (a framework's caching allocator, a memory pool).  alloc(bytes, ctx) returns
+ * memory of the current device, aligned to at least 256 bytes, or NULL (the call
+ * that needed it then fails with HDP_E_NOMEM); free(p, ctx) takes back a block alloc
+ * returned.  hdp_destroy, and a failing hdp_setup, free every block the handle took
+ * after its stream has finished.  Both pointers set, or both NULL. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* p, void* ctx);
+  void* ctx;
+} hdp_allocator;
+
 typedef struct {
   int32_t precision;          /* HDP_FP64, or HDP_MIXED (FP32 local operators, FP64 outer GMRES) */
   double tol;                 /* preconditioned relative residual target, e.g. 1e-8 */
@@ -145,6 +157,7 @@ typedef struct {
                                  with HDP_FLAG_AUTOTUNE, else a shared-memory heuristic) */
   int32_t tile_slot;          /* right-hand sides per workgroup of the matrix-core slot operators
                                  at 16 or more columns (16, 32 or 64; 0: autotuned or 32) */
+  hdp_allocator allocator;    /* device memory of the handle (zero: hipMalloc / hipFree) */
 } hdp_options;
 
 /* hdp_options.flags: replay each GMRES iteration as a captured HIP graph

@@ -39,10 +39,18 @@ class _Problem(ctypes.Structure):
                 ("l_per_edge", ctypes.c_int32), ("l_free_space", ctypes.c_int32)]
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class _Allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
 class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("max_rhs", ctypes.c_int32), ("stream", ctypes.c_void_p), ("flags", ctypes.c_int32),
-                ("tile_fdm", ctypes.c_int32), ("tile_slot", ctypes.c_int32)]
+                ("tile_fdm", ctypes.c_int32), ("tile_slot", ctypes.c_int32), ("allocator", _Allocator)]
 
 
 class _Rhs(ctypes.Structure):
@@ -198,7 +206,7 @@ class Solver:
     """
 
     def __init__(self, w, precision="fp64", tol=1e-8, max_iter=300, max_rhs=1, l_safety=0, device=0,
-                 graphs=False, coarse="auto", autotune=False, tile_fdm=0, tile_slot=0):
+                 graphs=False, coarse="auto", autotune=False, tile_fdm=0, tile_slot=0, torch_memory=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("hdp needs a ROCm GPU (torch.cuda.is_available() is False)")
@@ -211,8 +219,26 @@ class Solver:
             stream = torch.cuda.current_stream(self.device).cuda_stream
             flags = ((1 if graphs else 0) | {"auto": 0, "dense": 4, "nd": 8}[coarse]
                      | (16 if autotune else 0))
+            alloc = _Allocator()
+            if torch_memory:
+                # the handle's device memory from torch's caching allocator (on the
+                # caller's stream, which the solver orders after)
+                dev = self.device
+
+                def _alloc(nbytes, ctx):
+                    try:
+                        return torch.cuda.caching_allocator_alloc(int(nbytes), device=dev,
+                                                                  stream=torch.cuda.current_stream(dev))
+                    except Exception:
+                        return None
+
+                def _free(p, ctx):
+                    torch.cuda.caching_allocator_delete(p)
+
+                self._allocator_fns = (_ALLOC_FN(_alloc), _FREE_FN(_free))   # alive until close()
+                alloc = _Allocator(self._allocator_fns[0], self._allocator_fns[1], None)
             opt = _Options(self.precision, float(tol), int(max_iter), int(max_rhs), ctypes.c_void_p(stream), flags,
-                           int(tile_fdm), int(tile_slot))
+                           int(tile_fdm), int(tile_slot), alloc)
             h = ctypes.c_void_p()
             _check(L.hdp_setup(ctypes.byref(mesh), ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(h)))
         self.h = h
@@ -226,6 +252,7 @@ class Solver:
         if getattr(self, "h", None):
             load_library().hdp_destroy(self.h)
             self.h = None
+        self._allocator_fns = None
 
     def __del__(self):
         try:

@@ -31,9 +31,17 @@ template <class T>
 T* dalloc(Handle& h, size_t count) {
   void* p = nullptr;
   if (count == 0) count = 1;
-  if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+  const size_t bytes = count * sizeof(T);
+  if (h.allocator.alloc) {
+    p = h.allocator.alloc(bytes, h.allocator.ctx);
+    if (!p) fail(HDP_E_NOMEM, "the caller's allocator returned no memory for " + std::to_string(bytes) + " bytes");
+    if (reinterpret_cast<uintptr_t>(p) % 256 != 0) {
+      h.allocator.free(p, h.allocator.ctx);
+      fail(HDP_E_NOMEM, "the caller's allocator returned memory aligned to less than 256 bytes");
+    }
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();
-    fail(HDP_E_NOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    fail(HDP_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
   }
   h.allocations.push_back(p);
   return static_cast<T*>(p);
@@ -99,6 +107,14 @@ void prof_flush(Handle& h) {
     h.prof.pool.push_back(p.b);
   }
   h.prof.pend.clear();
+}
+
+void release_allocations(Handle& h) {
+  for (void* p : h.allocations) {
+    if (h.allocator.free) h.allocator.free(p, h.allocator.ctx);
+    else (void)hipFree(p);
+  }
+  h.allocations.clear();
 }
 
 void check_hip(hipError_t e, const char* what) {
@@ -1233,6 +1249,9 @@ hdp_status hdp_setup(const hdp_mesh* mesh, const hdp_problem* prob, const hdp_op
     fail(HDP_E_ARG, "tile_slot must be 0, 16, 32 or 64");
   h.fdm_rc = opt->tile_fdm;
   if (opt->tile_slot) h.slot_rb = opt->tile_slot;
+  if ((opt->allocator.alloc == nullptr) != (opt->allocator.free == nullptr))
+    fail(HDP_E_ARG, "hdp_allocator: set both alloc and free, or neither");
+  h.allocator = opt->allocator;
   if (opt->flags & HDP_FLAG_COARSE_BLOCK)
     fail(HDP_E_ARG, "HDP_FLAG_COARSE_BLOCK: the strip factor is no longer provided (use HDP_FLAG_COARSE_ND)");
   if ((opt->flags & HDP_FLAG_COARSE_DENSE) && (opt->flags & HDP_FLAG_COARSE_ND))
@@ -1255,7 +1274,7 @@ hdp_status hdp_setup(const hdp_mesh* mesh, const hdp_problem* prob, const hdp_op
     if (opt->flags & HDP_FLAG_AUTOTUNE) autotune(h, opt->tile_fdm == 0, opt->tile_slot == 0);
   } catch (...) {
     if (h.stream) (void)hipStreamSynchronize(h.stream);
-    for (void* p : h.allocations) (void)hipFree(p);
+    release_allocations(h);
     if (h.d.status_host) (void)hipHostFree(h.d.status_host);
     if (h.order_ev) (void)hipEventDestroy(h.order_ev);
     if (h.rocblas) rocblas_destroy_handle(static_cast<rocblas_handle>(h.rocblas));
@@ -1826,7 +1845,7 @@ void hdp_destroy(hdp_handle* H) {
   for (auto& kv : H->h.graphs) (void)hipGraphExecDestroy(kv.second);
   if (H->h.order_ev) (void)hipEventDestroy(H->h.order_ev);
   if (H->h.stream) (void)hipStreamDestroy(H->h.stream);
-  for (void* p : H->h.allocations) (void)hipFree(p);
+  release_allocations(H->h);
   delete H;
 }
 

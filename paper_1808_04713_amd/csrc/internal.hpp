@@ -318,6 +318,7 @@ struct Handle {
     double2* ycoef = nullptr;
   } d;
   std::vector<void*> allocations;
+  hdp_allocator allocator{};   // the caller's device-memory pair, or zero for hipMalloc / hipFree
   Prof prof;
   // far-field geometry of the last request (device arrays, grown on demand)
   struct Far {
@@ -405,6 +406,8 @@ struct NDHost {
   double flops_per_col = 0;   // 8 (nI^2 + 2 nB nI) summed over the nodes
 };
 void nd_factor(const Handle& h, const std::vector<int64_t>& kidx, const std::vector<double2>& kval, NDHost& f);
+// every device block of the handle back through its allocator (or hipFree)
+void release_allocations(Handle& h);
 // the row tasks alone (levels, t1f/t1b, tRf/tRb, part_tasks) for a split target;
 // ND_SPLITS are the targets the set-up autotuner tries
 void nd_tasks(const Handle& h, NDHost& f, int target);

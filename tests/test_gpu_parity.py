@@ -283,6 +283,32 @@ def test_coarse_solvers_against_the_oracle(name, coarse, oracles):
     s.close()
 
 
+def test_handle_memory_from_the_callers_allocator(oracles):
+    """hdp_options.allocator: with torch's caching allocator the handle's device
+    memory comes from torch's pool (torch.cuda.memory_allocated grows by at least
+    the coarse inverse and returns to its value after close), and the solve is the
+    same as with hipMalloc."""
+    name = "scatterer_6x6_p6"
+    w = CASES[name]
+    kind, vals = hdp().rhs_values(w)
+    s0 = hdp().Solver(w, tol=1e-12, max_iter=400, max_rhs=4)
+    f0, st0 = s0.solve(kind, vals)
+    s0.close()
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    s = hdp().Solver(w, tol=1e-12, max_iter=400, max_rhs=4, torch_memory=True)
+    grown = torch.cuda.memory_allocated() - before
+    assert grown >= 16 * s.n_coarse ** 2
+    f, st = s.solve(kind, vals)
+    got = f.cpu().numpy()
+    del f
+    assert st["iterations"] == st0["iterations"]
+    assert rel(got, f0.cpu().numpy()) < 1e-14
+    s.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == before
+
+
 def test_autotuned_nested_dissection_split(oracles):
     """The set-up autotuner times the nested-dissection sweeps at every split
     target and keeps the fastest; the interface operator with the chosen task
