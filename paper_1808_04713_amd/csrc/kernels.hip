@@ -226,6 +226,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // copied out with R fastest.  The LDS buffer holds max(K, nrow) x R entries
 // (at most the largest such count over the classes, times R).
 constexpr int SLOT_MF_LDS = 65536;
+constexpr int SLOT_GB = 4;   // gathered operand entries per thread and pass
 
 template <int MODE>
 __global__ void __launch_bounds__(NT) k_slot_mfma(const SlotBlock* __restrict__ blk,
@@ -243,30 +244,48 @@ __global__ void __launch_bounds__(NT) k_slot_mfma(const SlotBlock* __restrict__ 
   const int nrow = MODE == 0 ? m + nr : m;
   const double2* Mat = MODE == 0 ? op1 + B.op1 : (MODE == 3 ? phi + B.phi : se + B.se);
   // operand rows kk x R
-  for (int idx = threadIdx.x; idx < K * RB; idx += NT) {
-    const int kk = idx / RB, r = idx - kk * RB;
-    double ax = 0, ay = 0;
-    if (MODE == 3) {
+  if (MODE == 3) {
+    for (int idx = threadIdx.x; idx < K * RB; idx += NT) {
+      const int kk = idx / RB, r = idx - kk * RB;
+      double ax = 0, ay = 0;
       const int co = B.cmo + kk;
       for (int t = t_ptr[co]; t < t_ptr[co + 1]; ++t) {
         const double2 a = v[(int64_t)t_dof[t] * R + r0 + r];
         ax += t_coef[t] * a.x;
         ay += t_coef[t] * a.y;
       }
-    } else {
-      const SlotIn g = sin[so + kk];
-      if (g.s0 >= 0) {
-        const double2 z = v[(int64_t)g.s0 * R + r0 + r];
-        ax += g.a0 * z.x;
-        ay += g.a0 * z.y;
+      buf[idx] = make_double2(ax, ay);
+    }
+  } else {
+    // SLOT_GB entries per thread and pass: the slot records, then the gathered
+    // rows, are all requested before any is used
+    for (int i0 = threadIdx.x; i0 < K * RB; i0 += NT * SLOT_GB) {
+      SlotIn g[SLOT_GB];
+#pragma unroll
+      for (int u = 0; u < SLOT_GB; ++u) {
+        const int idx = min(i0 + u * NT, K * RB - 1);
+        g[u] = sin[so + idx / RB];
       }
-      if (MODE == 2 && g.s1 >= 0) {
-        const double2 z = v[(int64_t)g.s1 * R + r0 + r];
-        ax += g.a1 * z.x;
-        ay += g.a1 * z.y;
+      double2 z0[SLOT_GB], z1[SLOT_GB];
+#pragma unroll
+      for (int u = 0; u < SLOT_GB; ++u) {
+        const int idx = i0 + u * NT, r = idx % RB;
+        z0[u] = z1[u] = make_double2(0, 0);
+        if (idx < K * RB && g[u].s0 >= 0) z0[u] = v[(int64_t)g[u].s0 * R + r0 + r];
+        if (MODE == 2 && idx < K * RB && g[u].s1 >= 0) z1[u] = v[(int64_t)g[u].s1 * R + r0 + r];
+      }
+#pragma unroll
+      for (int u = 0; u < SLOT_GB; ++u) {
+        const int idx = i0 + u * NT;
+        if (idx >= K * RB) break;
+        double ax = g[u].a0 * z0[u].x, ay = g[u].a0 * z0[u].y;
+        if (MODE == 2) {
+          ax += g[u].a1 * z1[u].x;
+          ay += g[u].a1 * z1[u].y;
+        }
+        buf[idx] = make_double2(ax, ay);
       }
     }
-    buf[idx] = make_double2(ax, ay);
   }
   __syncthreads();
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -279,21 +298,41 @@ __global__ void __launch_bounds__(NT) k_slot_mfma(const SlotBlock* __restrict__ 
     cr[q] = (d4){0, 0, 0, 0};
     ci[q] = (d4){0, 0, 0, 0};
   }
-  for (int k0 = 0; k0 < K; k0 += 4) {
-    const int kk = k0 + kq;
-    const bool kv = kk < K;
+  // two steps of 4 summation rows per pass: the operator entries of both steps
+  // (global, cached) are requested before their matrix operations (one step per
+  // pass for MODE 3, whose gather of coarse values needs the occupancy more)
+  constexpr int NS = MODE == 3 ? 1 : 2;
+  for (int k0 = 0; k0 < K; k0 += 4 * NS) {
+    double2 bq[NS][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int tile = wv + 4 * q;
-      if (tile >= ntile) break;   // uniform over the wave
-      const int it = tile / nrt, rt = tile - it * nrt;
-      const int i = 16 * it + jl;
-      const double2 b = (kv && i < nrow) ? Mat[i + (int64_t)nrow * kk] : make_double2(0, 0);
-      const double2 a = kv ? buf[kk * RB + 16 * rt + jl] : make_double2(0, 0);
-      cr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr[q], 0, 0, 0);
-      ci[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ci[q], 0, 0, 0);
-      cr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cr[q], 0, 0, 0);
-      ci[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, ci[q], 0, 0, 0);
+    for (int st = 0; st < NS; ++st) {
+      const int kk = k0 + 4 * st + kq;
+      const bool kv = kk < K;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int tile = min(wv + 4 * q, ntile - 1);
+        const int it = tile / nrt;
+        const int i = 16 * it + jl;
+        bq[st][q] = (kv && i < nrow) ? Mat[i + (int64_t)nrow * kk] : make_double2(0, 0);
+      }
+    }
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+      const int kk = k0 + 4 * st + kq;
+      const bool kv = kk < K;
+      if (k0 + 4 * st >= K) break;   // uniform: a step wholly past K
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int tile = wv + 4 * q;
+        if (tile >= ntile) break;   // uniform over the wave
+        const int rt = tile - (tile / nrt) * nrt;
+        const double2 b = bq[st][q];
+        const double2 a = kv ? buf[kk * RB + 16 * rt + jl] : make_double2(0, 0);
+        cr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr[q], 0, 0, 0);
+        ci[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ci[q], 0, 0, 0);
+        cr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cr[q], 0, 0, 0);
+        ci[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, ci[q], 0, 0, 0);
+      }
     }
   }
   __syncthreads();   // every wave is done with the operand
@@ -347,10 +386,9 @@ __global__ void __launch_bounds__(NT) k_slot_mfma32(const SlotBlock* __restrict_
   const int K = MODE == 3 ? nr : m;
   const int nrow = MODE == 0 ? m + nr : m;
   const float2* Mat = MODE == 0 ? op1 + B.op1 : (MODE == 3 ? phi + B.phi : se + B.se);
-  for (int idx = threadIdx.x; idx < K * RB; idx += NT) {
-    const int kk = idx / RB, r = idx - kk * RB;
-    float ax = 0, ay = 0;
-    if (MODE == 3) {
+  if (MODE == 3) {
+    for (int idx = threadIdx.x; idx < K * RB; idx += NT) {
+      const int kk = idx / RB, r = idx - kk * RB;
       const int co = B.cmo + kk;
       double sx = 0, sy = 0;
       for (int t = t_ptr[co]; t < t_ptr[co + 1]; ++t) {
@@ -358,22 +396,38 @@ __global__ void __launch_bounds__(NT) k_slot_mfma32(const SlotBlock* __restrict_
         sx += t_coef[t] * a.x;
         sy += t_coef[t] * a.y;
       }
-      ax = float(sx);
-      ay = float(sy);
-    } else {
-      const SlotIn g = sin[so + kk];
-      if (g.s0 >= 0) {
-        const VT z = v[(int64_t)g.s0 * R + r0 + r];
-        ax += float(g.a0) * z.x;
-        ay += float(g.a0) * z.y;
+      buf32[idx] = make_float2(float(sx), float(sy));
+    }
+  } else {
+    // as k_slot_mfma: the slot records, then the gathered rows, all requested
+    // before any is used
+    for (int i0 = threadIdx.x; i0 < K * RB; i0 += NT * SLOT_GB) {
+      SlotIn g[SLOT_GB];
+#pragma unroll
+      for (int u = 0; u < SLOT_GB; ++u) {
+        const int idx = min(i0 + u * NT, K * RB - 1);
+        g[u] = sin[so + idx / RB];
       }
-      if (MODE == 2 && g.s1 >= 0) {
-        const VT z = v[(int64_t)g.s1 * R + r0 + r];
-        ax += float(g.a1) * z.x;
-        ay += float(g.a1) * z.y;
+      VT z0[SLOT_GB], z1[SLOT_GB];
+#pragma unroll
+      for (int u = 0; u < SLOT_GB; ++u) {
+        const int idx = i0 + u * NT, r = idx % RB;
+        z0[u].x = z0[u].y = z1[u].x = z1[u].y = 0;
+        if (idx < K * RB && g[u].s0 >= 0) z0[u] = v[(int64_t)g[u].s0 * R + r0 + r];
+        if (MODE == 2 && idx < K * RB && g[u].s1 >= 0) z1[u] = v[(int64_t)g[u].s1 * R + r0 + r];
+      }
+#pragma unroll
+      for (int u = 0; u < SLOT_GB; ++u) {
+        const int idx = i0 + u * NT;
+        if (idx >= K * RB) break;
+        float ax = float(g[u].a0) * z0[u].x, ay = float(g[u].a0) * z0[u].y;
+        if (MODE == 2) {
+          ax += float(g[u].a1) * z1[u].x;
+          ay += float(g[u].a1) * z1[u].y;
+        }
+        buf32[idx] = make_float2(ax, ay);
       }
     }
-    buf32[idx] = make_float2(ax, ay);
   }
   __syncthreads();
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -385,21 +439,37 @@ __global__ void __launch_bounds__(NT) k_slot_mfma32(const SlotBlock* __restrict_
     cr[q] = (f4){0, 0, 0, 0};
     ci[q] = (f4){0, 0, 0, 0};
   }
-  for (int k0 = 0; k0 < K; k0 += 4) {
-    const int kk = k0 + kq;
-    const bool kv = kk < K;
+  constexpr int NS = MODE == 3 ? 1 : 2;   // steps per pass, operator loads first (as k_slot_mfma)
+  for (int k0 = 0; k0 < K; k0 += 4 * NS) {
+    float2 bq[NS][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int tile = wv + 4 * q;
-      if (tile >= ntile) break;   // uniform over the wave
-      const int it = tile / nrt, rt = tile - it * nrt;
-      const int i = 16 * it + jl;
-      const float2 b = (kv && i < nrow) ? Mat[i + (int64_t)nrow * kk] : make_float2(0, 0);
-      const float2 a = kv ? buf32[kk * RB + 16 * rt + jl] : make_float2(0, 0);
-      cr[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, cr[q], 0, 0, 0);
-      ci[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, ci[q], 0, 0, 0);
-      cr[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, cr[q], 0, 0, 0);
-      ci[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, ci[q], 0, 0, 0);
+    for (int st = 0; st < NS; ++st) {
+      const int kk = k0 + 4 * st + kq;
+      const bool kv = kk < K;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int tile = min(wv + 4 * q, ntile - 1);
+        const int i = 16 * (tile / nrt) + jl;
+        bq[st][q] = (kv && i < nrow) ? Mat[i + (int64_t)nrow * kk] : make_float2(0, 0);
+      }
+    }
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+      const int kk = k0 + 4 * st + kq;
+      const bool kv = kk < K;
+      if (k0 + 4 * st >= K) break;   // uniform: a step wholly past K
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int tile = wv + 4 * q;
+        if (tile >= ntile) break;   // uniform over the wave
+        const int rt = tile - (tile / nrt) * nrt;
+        const float2 b = bq[st][q];
+        const float2 a = kv ? buf32[kk * RB + 16 * rt + jl] : make_float2(0, 0);
+        cr[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, cr[q], 0, 0, 0);
+        ci[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, ci[q], 0, 0, 0);
+        cr[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, cr[q], 0, 0, 0);
+        ci[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, ci[q], 0, 0, 0);
+      }
     }
   }
   __syncthreads();   // every wave is done with the operand
