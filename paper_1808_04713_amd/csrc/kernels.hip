@@ -1407,10 +1407,11 @@ __global__ void __launch_bounds__(NT) k_fdm(const int* __restrict__ elem_cls, co
 // MODE 0: out = A~^-1 in on every element.
 // MODE 1: the coarse pass of the element solve of eq. block_matrix_inversion:
 //   y = in with the coarse-mode rows zeroed and C_1^T nu subtracted at the dual
-//   slots; only the coarse-mode values x_R of A~^-1 y are formed (two full
-//   contractions, then the lines i < 2 and j < 2 of the last two on the vector
-//   ALUs) and written to Xr, and GL = K_e x_R (the element's share of -Phi^T y)
-//   to GL, both [coarse mode][R].
+//   slots; only the coarse-mode values x_R of A~^-1 y are kept (the algorithmic
+//   work is two contractions plus the lines i < 2 and j < 2 of the other two; the
+//   kernel runs all four on the matrix cores and reads x_R at the coarse modes,
+//   which measured faster than the lines on the vector ALUs) and written to Xr,
+//   and GL = K_e x_R (the element's share of -Phi^T y) to GL, both [coarse mode][R].
 // MODE 2: the full solve with the Woodbury correction folded in: mu =
 //   K_e (x_R - T_e w), and out = A~^-1 (y - E_R mu) (y's coarse rows are zero,
 //   so they become -mu), which equals A~^-1 y - G mu.
