@@ -1575,17 +1575,21 @@ __host__ __device__ inline size_t fdm_mf_entries(int nmax, int npmax, int nrmax,
 }
 
 // Loads of one item's coefficients kept in registers: entry i = threadIdx.x +
-// u NT of the item's n^2 x RC stage (the batch covers n^2 RC <= FDM_FB NT; larger
-// stages load the rest when they are staged).
-constexpr int FDM_FB = 8;
+// u NT of the item's n^2 x RC stage (the batch covers n^2 RC <= fdm_fb(RC) NT;
+// larger stages load the rest when they are staged).  At 16 columns a block
+// holds the compute unit's shared memory alone (one wave per SIMD), so the
+// batch takes 12 entries and covers a 13x13 element; narrower items run two
+// blocks per compute unit and keep 8 (the register file of two waves per SIMD).
+constexpr int FDM_FB = 8;   // batch of the staging loops
+__host__ __device__ constexpr int fdm_fb(int rc) { return rc >= 16 ? 12 : FDM_FB; }
 
 template <int RC>
-__device__ __forceinline__ void fdm_prefetch(const FdmArgs& g, int e, int r0, double2 (&v)[FDM_FB]) {
+__device__ __forceinline__ void fdm_prefetch(const FdmArgs& g, int e, int r0, double2 (&v)[fdm_fb(RC)]) {
   const FdmRec fr = g.rec[e];
   const int ny = fr.n * fr.n * RC, R = g.R, rc = min(RC, R - r0);
   const double2* __restrict__ in = g.in + fr.base * R + r0;
 #pragma unroll
-  for (int u = 0; u < FDM_FB; ++u) {
+  for (int u = 0; u < fdm_fb(RC); ++u) {
     const int i = threadIdx.x + u * NT;
     const int t = i / RC, r = i - t * RC;
     v[u] = (i < ny && r < rc) ? in[(int64_t)t * R + r] : make_double2(0, 0);
@@ -1598,7 +1602,7 @@ __device__ __forceinline__ void fdm_prefetch(const FdmArgs& g, int e, int r0, do
 // had the same class).
 template <int RC, int MODE, int NPMAX>
 __device__ __forceinline__ void fdm_item(const FdmArgs& g, int nmax, int nrmax, double2* sm, int e, int r0,
-                                         bool load_e, double2 (&v)[FDM_FB], int next_e, int next_r0) {
+                                         bool load_e, double2 (&v)[fdm_fb(RC)], int next_e, int next_r0) {
   const int R = g.R;
   const int rc = min(RC, R - r0);
   const FdmRec fr = g.rec[e];   // one record per element: offsets and sizes of its class
@@ -1631,13 +1635,13 @@ __device__ __forceinline__ void fdm_item(const FdmArgs& g, int nmax, int nrmax, 
   // the prefetched coefficients, then (only for stages larger than the
   // prefetch) the rest, loads batched; the stage tails past n^2 are zero
 #pragma unroll
-  for (int u = 0; u < FDM_FB; ++u) {
+  for (int u = 0; u < fdm_fb(RC); ++u) {
     const int i = threadIdx.x + u * NT;
     if (i < ny) A[i] = v[u];
   }
   {
     const double2* __restrict__ in = g.in + base * R + r0;
-    for (int i0 = threadIdx.x + FDM_FB * NT; i0 < ny; i0 += NT * FDM_FB) {
+    for (int i0 = threadIdx.x + fdm_fb(RC) * NT; i0 < ny; i0 += NT * FDM_FB) {
       double2 w[FDM_FB];
 #pragma unroll
       for (int u = 0; u < FDM_FB; ++u) {
@@ -1765,7 +1769,7 @@ template <int RC, int MODE, int NPMAX>
 __global__ void __launch_bounds__(NT) k_fdm_mf(FdmArgs g, int nmax, int nrmax, int nitems, int nchunk) {
   extern __shared__ double2 sm[];
   int cur = -1;
-  double2 v[FDM_FB];
+  double2 v[fdm_fb(RC)];
   int it = blockIdx.x;
   int e = -1, r0 = 0;
   if (it < nitems) {
