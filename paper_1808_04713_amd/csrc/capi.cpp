@@ -929,9 +929,10 @@ GmresResult gmres(Handle& h, const double2* rhs, double2* x, int R, int prec, do
   for (int q = 0; q < 2 * STATUS_SLOTS; ++q) d.status_host[q] = 0;   // no kernel of this stream writes it yet
   // the fused preconditioner adds into w; later iterations find it cleared by the update
   HIPCHECK(hipMemsetAsync(d.w, 0, size_t(vs) * sizeof(double2), s));
-  // up to GMRES_AHEAD iterations are queued beyond the one whose status the
-  // host reads; the device writes the status of iteration j to slot j mod
+  // up to `ahead` iterations are queued beyond the one whose status the host
+  // reads; the device writes the status of iteration j to slot j mod
   // STATUS_SLOTS (more slots than iterations in flight)
+  const int ahead = vs >= GMRES_LONG ? 0 : GMRES_AHEAD;
   hipEvent_t ev[STATUS_SLOTS];
   for (int q = 0; q < STATUS_SLOTS; ++q) HIPCHECK(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming));
   int launched = 0;
@@ -988,10 +989,10 @@ GmresResult gmres(Handle& h, const double2* rhs, double2* x, int R, int prec, do
       auto t1 = clk::now();
       h.t_launch += std::chrono::duration<double, std::milli>(t1 - t0).count();
       launched = it + 1;
-      if (it >= GMRES_AHEAD) {
-        HIPCHECK(hipEventSynchronize(ev[(it - GMRES_AHEAD) % STATUS_SLOTS]));
+      if (it >= ahead) {
+        HIPCHECK(hipEventSynchronize(ev[(it - ahead) % STATUS_SLOTS]));
         h.t_wait += std::chrono::duration<double, std::milli>(clk::now() - t1).count();
-        if (d.status_host[2 * ((it - GMRES_AHEAD) % STATUS_SLOTS)]) break;
+        if (d.status_host[2 * ((it - ahead) % STATUS_SLOTS)]) break;
       }
     }
     HIPCHECK(hipStreamSynchronize(s));

@@ -97,8 +97,12 @@ struct ND1Bwd {
 // reads (one keeps the GPU busy on the point source; two measured no faster and
 // cost one more iteration past convergence), and status slots in mapped host
 // memory (iteration j writes slot j mod STATUS_SLOTS; more slots than
-// iterations in flight).
+// iterations in flight).  Where one iteration streams long vectors (n_lambda R
+// at least GMRES_LONG entries, iterations of a millisecond at 64 columns) the
+// host's wait between iterations is small beside the queued iteration that
+// would run past convergence, so none is queued.
 constexpr int GMRES_AHEAD = 1;
+constexpr int64_t GMRES_LONG = int64_t(1) << 20;
 constexpr int STATUS_SLOTS = 4;
 
 // Per-block record of the slot kernels (blocks follow the class-grouped element
