@@ -196,6 +196,7 @@ struct Handle {
   int64_t nd_P_tasks = 0;           // partial tiles nd_P holds
   size_t nd_tR_cap[2] = {0, 0};     // capacity of nd_tRf / nd_tRb
   bool coarse_refine = false;       // refine each coarse solve once (set at setup from the check)
+  int cmA_b_R = 0;                  // columns of d.cmA_b valid for the current loads (0: none)
   double coarse_check = 0;         // relative residual of the coarse factor on a test vector
   int sym_nt = 0, sym_ntiles = 0;   // tile rows and upper tiles of the symmetric coarse inverse
   double coarse_bytes1 = 0;         // factor bytes of a one-RHS coarse solve (half with the tiles)
@@ -293,6 +294,7 @@ struct Handle {
     // work
     double2 *slotA = nullptr, *slotB = nullptr, *cmA = nullptr, *gK = nullptr, *wK = nullptr;
     double2* cmX = nullptr;   // [ncm][R]: coarse-mode values x_R of the element solve's first pass
+    double2* cmA_b = nullptr; // [ncm][R]: K_e x_R of the loads alone (the interface right-hand side's pass)
     float2 *slotA_f = nullptr, *slotB_f = nullptr, *cmA_f = nullptr;
     double2 *full0 = nullptr, *full1 = nullptr;   // [dof][R]
     double2 *V_kry = nullptr;                      // (max_iter+1) x nlam x R

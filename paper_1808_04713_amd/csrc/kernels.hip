@@ -1448,6 +1448,9 @@ struct FdmArgs {
   const int* t_dof;
   const double* t_coef;
   const double2* w;
+  // mode 2: K_e x_R given ([ncm][R]; Xr then holds -T_e w), the correction
+  // formed as K_e x_R - K_e T_e w
+  const double2* kx;
 };
 
 // D = M S over one mode index (see above), for classes of n <= NP modes (NP 16
@@ -1624,11 +1627,15 @@ __device__ __forceinline__ void fdm_item(const FdmArgs& g, int nmax, int nrmax, 
   // pass 2: x_R - T_e w of the thread's coarse-mode entries (formed by
   // k_coarse_minus_tw), loaded before the staging
   double2 gx[2] = {make_double2(0, 0), make_double2(0, 0)};
+  double2 gk[2] = {make_double2(0, 0), make_double2(0, 0)};   // K_e x_R when given
   if (MODE == 2) {
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int idx = threadIdx.x + u * NT, a = idx / RC, r = idx - a * RC;
-      if (a < nr && r < rc) gx[u] = g.Xr[(int64_t)(cmo + a) * R + r0 + r];
+      if (a < nr && r < rc) {
+        gx[u] = g.Xr[(int64_t)(cmo + a) * R + r0 + r];
+        if (g.kx) gk[u] = g.kx[(int64_t)(cmo + a) * R + r0 + r];
+      }
     }
   }
   const int ny = n2 * RC;
@@ -1713,10 +1720,19 @@ __device__ __forceinline__ void fdm_item(const FdmArgs& g, int nmax, int nrmax, 
     for (int idx = threadIdx.x; idx < nr * RC; idx += NT) {
       const int a = idx / RC, r = idx - a * RC;
       double2 y = make_double2(0, 0);
-      if (MODE == 2) {   // -mu = -K_e (x_R - T_e w)
+      if (MODE == 2) {   // -mu = -K_e (x_R - T_e w), or K_e T_e w - K_e x_R from kx
         for (int b = 0; b < nr; ++b) y = cfma(ks[a + nr * b], xs[b * RC + r], y);
         y.x = -y.x;
         y.y = -y.y;
+        if (g.kx) {
+          const int u = (idx - (int)threadIdx.x) / NT;
+          double2 k = make_double2(0, 0);
+          if (u == 0) k = gk[0];
+          else if (u == 1) k = gk[1];
+          else if (r < rc) k = g.kx[(int64_t)(cmo + a) * R + r0 + r];
+          y.x -= k.x;
+          y.y -= k.y;
+        }
       }
       A[rm[a] * RC + r] = y;
     }
@@ -1796,15 +1812,17 @@ __global__ void __launch_bounds__(NT) k_fdm_mf(FdmArgs g, int nmax, int nrmax, i
 }
 
 // Xr[i][r] -= sum_t T(i, t) w[t][r] for every coarse mode i (its expansion over
-// the coarse unknowns): the x_R - T_e w of the corrected element solve.
+// the coarse unknowns): the x_R - T_e w of the corrected element solve (-T_e w
+// with from_zero).
 __global__ void __launch_bounds__(NT) k_coarse_minus_tw(int ncm, int R, const int* __restrict__ t_ptr,
                                                         const int* __restrict__ t_dof,
                                                         const double* __restrict__ t_coef,
-                                                        const double2* __restrict__ w, double2* __restrict__ Xr) {
+                                                        const double2* __restrict__ w, double2* __restrict__ Xr,
+                                                        int from_zero) {
   const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (idx >= (int64_t)ncm * R) return;
   const int i = int(idx / R), r = int(idx - (int64_t)i * R);
-  double2 x = Xr[idx];
+  double2 x = from_zero ? make_double2(0, 0) : Xr[idx];
   for (int t = t_ptr[i]; t < t_ptr[i + 1]; ++t) {
     const double2 ww = w[(int64_t)t_dof[t] * R + r];
     x.x -= t_coef[t] * ww.x;
@@ -3236,7 +3254,7 @@ int fdm_mf_rc(const Handle& h, int R) {
 }
 
 void launch_fdm_mf(const Handle& h, int mode, const double2* in, double2* out, int R, hipStream_t s,
-                   const double2* nu, const double2* w, int rc) {
+                   const double2* nu, const double2* w, int rc, const double2* kx) {
   const int np = fdm_npmax(h), nrmax = fdm_nrmax(h), nmax = fdm_nmax(h);
   if (!fdm_mf_ok(h, mode != 0)) fail(HDP_E_UNSUPPORTED, "matrix-core element solve: class too large");
   if (rc <= 0) rc = fdm_mf_rc(h, R);
@@ -3247,12 +3265,13 @@ void launch_fdm_mf(const Handle& h, int mode, const double2* in, double2* out, i
   const auto& d = h.d;
   if (mode == 2) {   // x_R - T_e w in place, before the corrected solve
     hipLaunchKernelGGL(k_coarse_minus_tw, dim3(nblocks(int64_t(h.ncm) * R)), dim3(NT), 0, s, h.ncm, R, d.t_ptr,
-                       d.t_dof, d.t_coef, w, d.cmX);
+                       d.t_dof, d.t_coef, w, d.cmX, kx ? 1 : 0);
     HIPCHECK(hipGetLastError());
   }
   FdmArgs a{d.fdm_rec, d.order, d.elem_cls, d.dof_off, d.cls_n, d.cls_E, d.cls_D, d.Ex, d.Ey, d.Dinv, d.cls_real, in, out, R,
             d.cls_nr, d.cls_R, d.r_modes, mode != 0 ? 1 : 0, d.slot_off, d.slot_pos, d.slot_row, d.slot_coef,
-            mode != 0 ? nu : nullptr, d.cm_off, d.cls_Kc, d.Kc, d.cmX, d.cmA, d.t_ptr, d.t_dof, d.t_coef, w};
+            mode != 0 ? nu : nullptr, d.cm_off, d.cls_Kc, d.Kc, d.cmX, d.cmA, d.t_ptr, d.t_dof, d.t_coef, w,
+            mode == 2 ? kx : nullptr};
   const int nchunk = (R + rc - 1) / rc, nitems = h.E * nchunk;
   // blocks resident at once: shared memory and 3 waves per SIMD allow this many per compute unit
   const int per_cu = std::max(1, std::min(3, int((160 * 1024) / shm1)));

@@ -55,12 +55,13 @@ void launch_zero_R(const Handle& h, double2* X, int R, hipStream_t s);
 // coarse: the two passes also fit shared memory): mode 0 out = A~^-1 in;
 // mode 1 the coarse pass (x_R into cmX, K_e x_R into cmA; in read with the
 // coarse rows zeroed and C_1^T nu subtracted when nu is given); mode 2 the full
-// solve with the Woodbury correction from cmX and the coarse solution w.  rc:
+// solve with the Woodbury correction from cmX and the coarse solution w (with
+// kx: from K_e x_R given in kx, [ncm][R], instead of the first pass's x_R).  rc:
 // right-hand sides per block (0: the handle's choice).
 bool fdm_mf_ok(const Handle& h, bool coarse);
 int fdm_mf_rc(const Handle& h, int R);
 void launch_fdm_mf(const Handle& h, int mode, const double2* in, double2* out, int R, hipStream_t s,
-                   const double2* nu, const double2* w, int rc = 0);
+                   const double2* nu, const double2* w, int rc = 0, const double2* kx = nullptr);
 void launch_extract_kc(const Handle& h, const double2* X, double2* GL, int R, hipStream_t s);
 void launch_correct(const Handle& h, double2* X, const double2* w, int R, hipStream_t s);
 void launch_gll(const Handle& h, const double2* X, double2* field, int R, int64_t rhs_stride,
