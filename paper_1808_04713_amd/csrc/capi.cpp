@@ -371,6 +371,14 @@ void build_device(Handle& h) {
   d.t_ptr = upload(h, h.t_ptr);
   d.t_dof = upload(h, h.t_dof);
   d.t_coef = upload(h, h.t_coef);
+  {
+    std::vector<int> ip(size_t(h.ncm) + 1), id(h.ncm);
+    for (int i = 0; i <= h.ncm; ++i) ip[i] = i;
+    for (int i = 0; i < h.ncm; ++i) id[i] = i;
+    d.id_ptr = upload(h, ip);
+    d.id_dof = upload(h, id);
+    d.id_coef = upload(h, std::vector<double>(h.ncm, -1.0));
+  }
   d.cdof_ptr = upload(h, h.cdof_ptr);
   d.cdof_list = upload(h, h.cdof_list);
   d.cdof_coef = upload(h, h.cdof_coef);
@@ -889,18 +897,45 @@ void element_solve(Handle& h, double2* X, const double2* Bfull, const double2* n
 }
 
 // Interface right-hand side g = C_1 x_I with x_I from the element loads in full0.
+// Interface right-hand side g = C_1 x_1 + C_2 x_2 of x = A^-1 b^ with the element
+// loads in full0 (eq. block_matrix_inversion).  On the matrix cores only the
+// dual-slot values of x are formed: the first pass of the element solve keeps
+// the slot values x_S and coarse-mode values x_R of A~^-1 b (coarse rows of b
+// zeroed), and the Woodbury correction restricted to the slots is
+// x_1 = x_S - Phi (x_R - T_e w) (Phi = G_S K_e, G = A~^-1 E_R), which the slot
+// coarse correction applies; the full corrected solve is left to the recovery.
 void interface_rhs(Handle& h, double2* g, int R) {
   auto& d = h.d;
-  element_solve(h, d.full1, d.full0, nullptr, R, d.full0);
-  if (fdm_mf_ok(h, true)) {
+  hipStream_t s = h.stream;
+  const double c = 16.0 * R, nsl = h.nslots, ncm = h.ncm, nK = h.nK, dof = double(h.dof);
+  if (!fdm_mf_ok(h, true)) {
+    element_solve(h, d.full1, d.full0, nullptr, R, d.full0);
+    Timed t(h, KF_ROWGATHER, nsl * c + h.nlam * c, 0);
+    launch_rowgather<double2>(h, d.full1, true, false, d.wK, g, R, s);   // C_1 x_1 + C_2 x_2
+    return;
+  }
+  {
+    Timed t(h, KF_FDM, dof * c + 2 * ncm * c + nsl * c, h.flops_fdm_coarse * R);
+    launch_fdm_mf(h, 1, d.full0, nullptr, R, s, nullptr, nullptr, 0, nullptr, d.slotA);   // x_S, x_R, K_e x_R
+  }
+  {
     // K_e x_R of the loads, for the recovery of the same loads
-    Timed t(h, KF_ELEMENT_MISC, 2.0 * h.ncm * 16.0 * R, 0);
-    HIPCHECK(hipMemcpyAsync(d.cmA_b, d.cmA, size_t(h.ncm) * R * sizeof(double2), hipMemcpyDeviceToDevice,
-                            h.stream));
+    Timed t(h, KF_ELEMENT_MISC, 2 * ncm * c, 0);
+    HIPCHECK(hipMemcpyAsync(d.cmA_b, d.cmA, size_t(h.ncm) * R * sizeof(double2), hipMemcpyDeviceToDevice, s));
     h.cmA_b_R = R;
   }
-  Timed t(h, KF_ROWGATHER, h.nslots * 16.0 * R + h.nlam * 16.0 * R, 0);
-  launch_rowgather<double2>(h, d.full1, true, false, d.wK, g, R, h.stream);   // C_1 x_1 + C_2 x_2
+  {
+    Timed t(h, KF_ASSEMBLE, 2 * ncm * c + nK * c, 0);
+    launch_assemble<double2>(h, d.cmA, d.full0, nullptr, -1.0, d.gK, R, s);
+  }
+  coarse_solve_timed(h, d.gK, d.wK, R);
+  {
+    Timed t(h, KF_SLOT_COARSE, nsl * c * 2 + 2 * ncm * c + h.phi_bytes, h.flops_coarse * R);
+    launch_coarse_minus_tw(h, d.wK, R, s);                      // cmX = x_R - T_e w
+    launch_slot_coarse_cm(h, d.slotA, d.cmX, d.slotB, R, s);    // x_1 = x_S - Phi cmX
+  }
+  Timed t(h, KF_ROWGATHER, nsl * c + h.nlam * c, 0);
+  launch_rowgather<double2>(h, d.slotB, false, false, d.wK, g, R, s);   // C_1 x_1 + C_2 x_2
 }
 
 // Recovery phi = A^-1 (b^ - C^T nu) of the loads in full0 after interface_rhs

@@ -237,6 +237,11 @@ struct Handle {
     double *row_coef = nullptr, *row_xinv = nullptr, *slot_coef = nullptr;
     int *t_ptr = nullptr, *t_dof = nullptr, *cdof_ptr = nullptr, *cdof_list = nullptr, *cm_mode = nullptr;
     double *t_coef = nullptr, *cdof_coef = nullptr;
+    // the identity expansion with coefficient -1 (coarse mode i -> entry i of a
+    // [ncm][R] array): the slot coarse correction then applies -Phi to
+    // per-element coarse values instead of Phi T_e w
+    int *id_ptr = nullptr, *id_dof = nullptr;
+    double* id_coef = nullptr;
     int *c2_ptr = nullptr, *c2_dof = nullptr, *c2t_ptr = nullptr, *c2t_row = nullptr;
     double *c2_coef = nullptr, *c2t_coef = nullptr;
     int *hb_off = nullptr, *hb_rows = nullptr, *hb_blk = nullptr;

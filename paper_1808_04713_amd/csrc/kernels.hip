@@ -1451,6 +1451,8 @@ struct FdmArgs {
   // mode 2: K_e x_R given ([ncm][R]; Xr then holds -T_e w), the correction
   // formed as K_e x_R - K_e T_e w
   const double2* kx;
+  // mode 1: the dual-slot values of A~^-1 y as well ([nslots][R])
+  double2* xslot;
 };
 
 // D = M S over one mode index (see above), for classes of n <= NP modes (NP 16
@@ -1767,6 +1769,13 @@ __device__ __forceinline__ void fdm_item(const FdmArgs& g, int nmax, int nrmax, 
       double2 acc = make_double2(0, 0);
       for (int b = 0; b < nr; ++b) acc = cfma(ks[a + nr * b], xs[b * RC + r], acc);
       g.GL[(int64_t)(cmo + a) * R + r0 + r] = acc;
+    }
+    if (g.xslot) {   // the element's dual slots (distinct modes, none of them coarse)
+      const int s0 = fr.s0, ns = fr.s1 - s0;
+      for (int idx = threadIdx.x; idx < ns * rc; idx += NT) {
+        const int q = idx / rc, r = idx - q * rc, sl = s0 + q;
+        g.xslot[(int64_t)sl * R + r0 + r] = A[(int)(g.slot_pos[sl] - base) * RC + r];
+      }
     }
     return;
   }
@@ -3068,14 +3077,28 @@ template void launch_slot_coarse_sym<double2>(const Handle&, const double2*, dou
 template void launch_slot_coarse_sym<float2>(const Handle&, const float2*, float2*, hipStream_t);
 
 template <class T2>
+static void slot_coarse_impl(const Handle& h, const T2* X, const double2* w, T2* Z, int R, hipStream_t s,
+                             const int* t_ptr, const int* t_dof, const double* t_coef);
+
+template <class T2>
 void launch_slot_coarse(const Handle& h, const T2* X, const double2* w, T2* Z, int R, hipStream_t s) {
+  slot_coarse_impl(h, X, w, Z, R, s, h.d.t_ptr, h.d.t_dof, h.d.t_coef);
+}
+
+void launch_slot_coarse_cm(const Handle& h, const double2* X, const double2* cm, double2* Z, int R, hipStream_t s) {
+  slot_coarse_impl(h, X, cm, Z, R, s, h.d.id_ptr, h.d.id_dof, h.d.id_coef);
+}
+
+template <class T2>
+static void slot_coarse_impl(const Handle& h, const T2* X, const double2* w, T2* Z, int R, hipStream_t s,
+                             const int* t_ptr, const int* t_dof, const double* t_coef) {
   dim3 grid(h.E, (R + RC - 1) / RC);
   const auto& d = h.d;
   if constexpr (std::is_same<T2, double2>::value) {
     if (const size_t lds = slot_mfma_lds(h, R, 3)) {
       const int rb = slot_rb(h, R);
       hipLaunchKernelGGL(k_slot_mfma<3>, dim3(h.E, R / rb), dim3(NT), lds, s, d.slot_blk, nullptr, d.op1, d.se,
-                         d.phi, d.t_ptr, d.t_dof, d.t_coef, w, X, Z, nullptr, R, rb);
+                         d.phi, t_ptr, t_dof, t_coef, w, X, Z, nullptr, R, rb);
       HIPCHECK(hipGetLastError());
       return;
     }
@@ -3084,15 +3107,14 @@ void launch_slot_coarse(const Handle& h, const T2* X, const double2* w, T2* Z, i
     if (const size_t lds = slot_mfma_lds(h, R, 3)) {
       const int rb = slot_rb(h, R);
       hipLaunchKernelGGL((k_slot_mfma32<3, double2>), dim3(h.E, R / rb), dim3(NT), lds / 2, s, d.slot_blk, nullptr,
-                         d.op1_f, d.se_f, d.phi_f, d.t_ptr, d.t_dof, d.t_coef, w, X, Z, nullptr, R, rb);
+                         d.op1_f, d.se_f, d.phi_f, t_ptr, t_dof, t_coef, w, X, Z, nullptr, R, rb);
       HIPCHECK(hipGetLastError());
       return;
     }
   }
   const T2* phi;
   if constexpr (std::is_same<T2, double2>::value) phi = d.phi; else phi = d.phi_f;
-  hipLaunchKernelGGL((k_slot_coarse<T2>), grid, dim3(NT), 0, s, d.slot_blk, phi, d.t_ptr, d.t_dof, d.t_coef, X, w, Z,
-                     R);
+  hipLaunchKernelGGL((k_slot_coarse<T2>), grid, dim3(NT), 0, s, d.slot_blk, phi, t_ptr, t_dof, t_coef, X, w, Z, R);
   HIPCHECK(hipGetLastError());
 }
 
@@ -3253,8 +3275,15 @@ int fdm_mf_rc(const Handle& h, int R) {
   return rc;
 }
 
+void launch_coarse_minus_tw(const Handle& h, const double2* w, int R, hipStream_t s) {
+  const auto& d = h.d;
+  hipLaunchKernelGGL(k_coarse_minus_tw, dim3(nblocks(int64_t(h.ncm) * R)), dim3(NT), 0, s, h.ncm, R, d.t_ptr, d.t_dof,
+                     d.t_coef, w, d.cmX, 0);
+  HIPCHECK(hipGetLastError());
+}
+
 void launch_fdm_mf(const Handle& h, int mode, const double2* in, double2* out, int R, hipStream_t s,
-                   const double2* nu, const double2* w, int rc, const double2* kx) {
+                   const double2* nu, const double2* w, int rc, const double2* kx, double2* xslot) {
   const int np = fdm_npmax(h), nrmax = fdm_nrmax(h), nmax = fdm_nmax(h);
   if (!fdm_mf_ok(h, mode != 0)) fail(HDP_E_UNSUPPORTED, "matrix-core element solve: class too large");
   if (rc <= 0) rc = fdm_mf_rc(h, R);
@@ -3271,7 +3300,7 @@ void launch_fdm_mf(const Handle& h, int mode, const double2* in, double2* out, i
   FdmArgs a{d.fdm_rec, d.order, d.elem_cls, d.dof_off, d.cls_n, d.cls_E, d.cls_D, d.Ex, d.Ey, d.Dinv, d.cls_real, in, out, R,
             d.cls_nr, d.cls_R, d.r_modes, mode != 0 ? 1 : 0, d.slot_off, d.slot_pos, d.slot_row, d.slot_coef,
             mode != 0 ? nu : nullptr, d.cm_off, d.cls_Kc, d.Kc, d.cmX, d.cmA, d.t_ptr, d.t_dof, d.t_coef, w,
-            mode == 2 ? kx : nullptr};
+            mode == 2 ? kx : nullptr, mode == 1 ? xslot : nullptr};
   const int nchunk = (R + rc - 1) / rc, nitems = h.E * nchunk;
   // blocks resident at once: shared memory and 3 waves per SIMD allow this many per compute unit
   const int per_cu = std::max(1, std::min(3, int((160 * 1024) / shm1)));

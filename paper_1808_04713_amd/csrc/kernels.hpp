@@ -28,6 +28,10 @@ void launch_slot_apply(const Handle& h, int mode, const T2* v, T2* X, T2* GL, in
 // Z = X + Phi_c (T_e w)
 template <class T2>
 void launch_slot_coarse(const Handle& h, const T2* X, const double2* w, T2* Z, int R, hipStream_t s);
+// Z = X - Phi_c cm with cm per-element coarse-mode values ([ncm][R], FP64)
+void launch_slot_coarse_cm(const Handle& h, const double2* X, const double2* cm, double2* Z, int R, hipStream_t s);
+// cmX -= T_e w at every coarse mode
+void launch_coarse_minus_tw(const Handle& h, const double2* w, int R, hipStream_t s);
 // u[row] = scale_row * (sum coef * src[pos(slot)] + (C_2 w)[row])  (pos = slot if full == false;
 // the C_2 term only on meshes with hanging edges and w != nullptr)
 template <class T2>
@@ -57,11 +61,13 @@ void launch_zero_R(const Handle& h, double2* X, int R, hipStream_t s);
 // coarse rows zeroed and C_1^T nu subtracted when nu is given); mode 2 the full
 // solve with the Woodbury correction from cmX and the coarse solution w (with
 // kx: from K_e x_R given in kx, [ncm][R], instead of the first pass's x_R).  rc:
-// right-hand sides per block (0: the handle's choice).
+// right-hand sides per block (0: the handle's choice).  xslot (mode 1): the
+// dual-slot values of the first pass's A~^-1 y as well ([nslots][R]).
 bool fdm_mf_ok(const Handle& h, bool coarse);
 int fdm_mf_rc(const Handle& h, int R);
 void launch_fdm_mf(const Handle& h, int mode, const double2* in, double2* out, int R, hipStream_t s,
-                   const double2* nu, const double2* w, int rc = 0, const double2* kx = nullptr);
+                   const double2* nu, const double2* w, int rc = 0, const double2* kx = nullptr,
+                   double2* xslot = nullptr);
 void launch_extract_kc(const Handle& h, const double2* X, double2* GL, int R, hipStream_t s);
 void launch_correct(const Handle& h, double2* X, const double2* w, int R, hipStream_t s);
 void launch_gll(const Handle& h, const double2* X, double2* field, int R, int64_t rhs_stride,
