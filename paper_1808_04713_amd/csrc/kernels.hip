@@ -228,6 +228,54 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int SLOT_MF_LDS = 65536;
 constexpr int SLOT_GB = 4;   // gathered operand entries per thread and pass
 
+// The coarse values (T_e w)[kk][r] of an element's coarse modes kk < K (their
+// expansions over the coarse unknowns, from t_ptr[cmo + kk]) for the RB columns
+// from r0, into out (K x RB, r fastest).  SLOT_GB entries per thread and pass:
+// the first term of every expansion (pointer, then index and coefficient, then
+// the row of w) is requested for all of them before any is used; further terms
+// (modes on hanging edges) follow in expansion order.
+template <class OT>
+__device__ __forceinline__ void gather_coarse(const int* __restrict__ t_ptr, const int* __restrict__ t_dof,
+                                              const double* __restrict__ t_coef, const double2* __restrict__ v,
+                                              int cmo, int K, int RB, int R, int r0, OT* out) {
+  for (int i0 = threadIdx.x; i0 < K * RB; i0 += NT * SLOT_GB) {
+    int p0[SLOT_GB], p1[SLOT_GB];
+#pragma unroll
+    for (int u = 0; u < SLOT_GB; ++u) {
+      const int co = cmo + min(i0 + u * NT, K * RB - 1) / RB;
+      p0[u] = t_ptr[co];
+      p1[u] = t_ptr[co + 1];
+    }
+    int d[SLOT_GB];
+    double c[SLOT_GB];
+#pragma unroll
+    for (int u = 0; u < SLOT_GB; ++u) {
+      const bool has = p1[u] > p0[u];
+      d[u] = has ? t_dof[p0[u]] : -1;
+      c[u] = has ? t_coef[p0[u]] : 0.0;
+    }
+    double2 z[SLOT_GB];
+#pragma unroll
+    for (int u = 0; u < SLOT_GB; ++u) {
+      const int idx = i0 + u * NT, r = idx % RB;
+      z[u] = make_double2(0, 0);
+      if (idx < K * RB && d[u] >= 0) z[u] = v[(int64_t)d[u] * R + r0 + r];
+    }
+#pragma unroll
+    for (int u = 0; u < SLOT_GB; ++u) {
+      const int idx = i0 + u * NT, r = idx % RB;
+      if (idx >= K * RB) break;
+      double sx = c[u] * z[u].x, sy = c[u] * z[u].y;
+      for (int t = p0[u] + 1; t < p1[u]; ++t) {
+        const double2 a = v[(int64_t)t_dof[t] * R + r0 + r];
+        sx += t_coef[t] * a.x;
+        sy += t_coef[t] * a.y;
+      }
+      out[idx] = mk<OT>(sx, sy);
+    }
+  }
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(NT) k_slot_mfma(const SlotBlock* __restrict__ blk,
                                                   const SlotIn* __restrict__ sin, const double2* __restrict__ op1,
@@ -245,17 +293,7 @@ __global__ void __launch_bounds__(NT) k_slot_mfma(const SlotBlock* __restrict__ 
   const double2* Mat = MODE == 0 ? op1 + B.op1 : (MODE == 3 ? phi + B.phi : se + B.se);
   // operand rows kk x R
   if (MODE == 3) {
-    for (int idx = threadIdx.x; idx < K * RB; idx += NT) {
-      const int kk = idx / RB, r = idx - kk * RB;
-      double ax = 0, ay = 0;
-      const int co = B.cmo + kk;
-      for (int t = t_ptr[co]; t < t_ptr[co + 1]; ++t) {
-        const double2 a = v[(int64_t)t_dof[t] * R + r0 + r];
-        ax += t_coef[t] * a.x;
-        ay += t_coef[t] * a.y;
-      }
-      buf[idx] = make_double2(ax, ay);
-    }
+    gather_coarse<double2>(t_ptr, t_dof, t_coef, v, B.cmo, K, RB, R, r0, buf);
   } else {
     // SLOT_GB entries per thread and pass: the slot records, then the gathered
     // rows, are all requested before any is used
@@ -387,17 +425,7 @@ __global__ void __launch_bounds__(NT) k_slot_mfma32(const SlotBlock* __restrict_
   const int nrow = MODE == 0 ? m + nr : m;
   const float2* Mat = MODE == 0 ? op1 + B.op1 : (MODE == 3 ? phi + B.phi : se + B.se);
   if (MODE == 3) {
-    for (int idx = threadIdx.x; idx < K * RB; idx += NT) {
-      const int kk = idx / RB, r = idx - kk * RB;
-      const int co = B.cmo + kk;
-      double sx = 0, sy = 0;
-      for (int t = t_ptr[co]; t < t_ptr[co + 1]; ++t) {
-        const VT a = v[(int64_t)t_dof[t] * R + r0 + r];
-        sx += t_coef[t] * a.x;
-        sy += t_coef[t] * a.y;
-      }
-      buf32[idx] = make_float2(float(sx), float(sy));
-    }
+    if constexpr (std::is_same<VT, double2>::value) gather_coarse<float2>(t_ptr, t_dof, t_coef, v, B.cmo, K, RB, R, r0, buf32);
   } else {
     // as k_slot_mfma: the slot records, then the gathered rows, all requested
     // before any is used
