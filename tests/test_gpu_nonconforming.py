@@ -108,6 +108,34 @@ def test_mixed_precision_solve(name, literal):
     s.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["h4_p4to6_l2_lens", "disk_6x6_p3to6"])
+def test_sixteen_angles_in_one_solve(name, precision, literal):
+    """16 incidence angles in one solve on a quadtree mesh: the matrix-core slot
+    operators and element solves at 16 columns, the right-hand side formed on the
+    dual slots alone and the recovery from the loads' kept K_e x_R, with expansion
+    lists of several terms on the hanging edges.  Every column equals its
+    single-angle solve (FP64: 1e-10; mixed: 1e-8), and the workload's own angle
+    equals the literal method (the same bars)."""
+    disc, D = literal[name]
+    w = CASES[name]
+    a0 = w["rhs"]["angles"][0]
+    angles = a0 + np.arange(16) * (2 * np.pi / 16)
+    bar = 1e-10 if precision == "fp64" else 1e-8
+    s = hdp().Solver(w, precision=precision, tol=1e-12, max_iter=400, max_rhs=16)
+    fb, st = s.solve("plane_wave_scattered", angles)
+    fb = fb.cpu().numpy()
+    assert st["converged"]
+    for i in (0, 5, 11):
+        f1, st1 = s.solve("plane_wave_scattered", [angles[i]])
+        assert st1["converged"]
+        assert rel(fb[i], f1.cpu().numpy()[0]) < bar, (i, rel(fb[i], f1.cpu().numpy()[0]))
+    phis = D.solve(tol=1e-12, max_iter=400)
+    ref = np.concatenate(pb.gll_field(disc.mesh, disc.degrees, phis))
+    assert rel(fb[0], ref) < bar
+    s.close()
+
+
 def test_refined_disk_full_size():
     """The 712-leaf refined disk (p 8..24, k = 200, l = 14): too large for the
     oracle, so checked by properties that hold at any size: both paths reach
