@@ -276,8 +276,10 @@ __device__ __forceinline__ void gather_coarse(const int* __restrict__ t_ptr, con
   }
 }
 
+// (at most 128 registers: four blocks per compute unit where the shared memory
+// allows them; unbounded the compiler took 146 and three)
 template <int MODE>
-__global__ void __launch_bounds__(NT) k_slot_mfma(const SlotBlock* __restrict__ blk,
+__global__ void __launch_bounds__(NT, 4) k_slot_mfma(const SlotBlock* __restrict__ blk,
                                                   const SlotIn* __restrict__ sin, const double2* __restrict__ op1,
                                                   const double2* __restrict__ se, const double2* __restrict__ phi,
                                                   const int* __restrict__ t_ptr, const int* __restrict__ t_dof,
