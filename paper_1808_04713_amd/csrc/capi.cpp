@@ -896,7 +896,6 @@ void element_solve(Handle& h, double2* X, const double2* Bfull, const double2* n
   }
 }
 
-// Interface right-hand side g = C_1 x_I with x_I from the element loads in full0.
 // Interface right-hand side g = C_1 x_1 + C_2 x_2 of x = A^-1 b^ with the element
 // loads in full0 (eq. block_matrix_inversion).  On the matrix cores only the
 // dual-slot values of x are formed: the first pass of the element solve keeps
