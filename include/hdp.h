@@ -213,6 +213,13 @@ typedef struct {
    * element classes, coarse maps), its element-class operators (eigenbases, unit solves,
    * Schur blocks; built on up to 16 host threads), and the coarse factor */
   double setup_host_ms, setup_classes_ms, setup_coarse_ms;
+  /* nested-dissection factor at several columns: the unknowns of the tree's top
+   * depths solved as one dense block (rows of K^-1 at those unknowns, built at
+   * set-up), 0 when the sweeps run every depth; and the set-up check of the sweeps
+   * with the block, ||K x - b|| / ||b|| over two columns (the block is not used
+   * when it exceeds max(1e-10, 10 coarse_residual)) */
+  int32_t coarse_top_unknowns;
+  double coarse_top_check;
 } hdp_stats;
 
 typedef struct hdp_handle hdp_handle;

@@ -71,7 +71,8 @@ class Stats(ctypes.Structure):
                 ("coarse_mode", ctypes.c_int32), ("coarse_blocks", ctypes.c_int32),
                 ("coarse_factor_bytes", ctypes.c_double), ("coarse_band_bytes", ctypes.c_double),
                 ("setup_host_ms", ctypes.c_double), ("setup_classes_ms", ctypes.c_double),
-                ("setup_coarse_ms", ctypes.c_double)]
+                ("setup_coarse_ms", ctypes.c_double), ("coarse_top_unknowns", ctypes.c_int32),
+                ("coarse_top_check", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

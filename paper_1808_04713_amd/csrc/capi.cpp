@@ -274,6 +274,47 @@ static void build_coarse_nd(Handle& h, const std::vector<int64_t>& kidx, const s
   h.coarse_mode = 2;
   h.coarse_bytes = 16.0 * double(f.fac.size());
   h.coarse_flops = f.flops_per_col;
+  // several columns: the depths above D as one dense block of at most ND_TOP_MAX
+  // unknowns (D >= 2, at least one depth below it).  Once every node deeper than
+  // D - 1 is eliminated, a top unknown's right-hand side is g plus what those
+  // nodes pushed into the fronts of depth D - 1: the child slots of its own row
+  // there and of those fronts' update rows for it.  The block itself is filled
+  // at the end of set-up (build_nd_top).
+  const int nn = int(h.nd_off.size()) - 1, maxd = int(h.nd_levels.size()) - 1;
+  if (Rp > 1 && maxd >= 2) {
+    std::vector<int64_t> above(maxd + 2, 0);   // unknowns at depths < d
+    for (int t = 0; t < nn; ++t) above[h.nd_depth[t] + 1] += h.nd_off[t + 1] - h.nd_off[t];
+    for (int q = 1; q <= maxd + 1; ++q) above[q] += above[q - 1];
+    int D = 0;
+    for (int q = 2; q <= maxd; ++q)
+      if (above[q] <= ND_TOP_MAX) D = q;
+    if (D >= 2) {
+      std::vector<int> tops;
+      for (int t = 0; t < nn; ++t)
+        if (h.nd_depth[t] < D)
+          for (int x = h.nd_off[t]; x < h.nd_off[t + 1]; ++x) tops.push_back(x);
+      std::sort(tops.begin(), tops.end());
+      std::vector<std::vector<int>> rows(tops.size());
+      auto pos = [&](int x) { return int(std::lower_bound(tops.begin(), tops.end(), x) - tops.begin()); };
+      for (int t = 0; t < nn; ++t) {
+        if (h.nd_depth[t] != D - 1) continue;
+        for (int x = h.nd_off[t]; x < h.nd_off[t + 1]; ++x) rows[pos(x)].push_back(x);
+        for (int64_t b = h.nd_boff[t]; b < h.nd_boff[t + 1]; ++b)
+          rows[pos(h.nd_bnd[b])].push_back(int(h.nK + f.uoff[t] + (b - h.nd_boff[t])));
+      }
+      std::vector<int64_t> gptr(tops.size() + 1, 0);
+      std::vector<int> grow;
+      for (size_t i = 0; i < tops.size(); ++i) {
+        grow.insert(grow.end(), rows[i].begin(), rows[i].end());
+        gptr[i + 1] = int64_t(grow.size());
+      }
+      d.nd_top_idx = upload(h, tops);
+      d.nd_top_gptr = upload(h, gptr);
+      d.nd_top_grow = upload(h, grow.empty() ? std::vector<int>{0} : grow);
+      h.nd_top_host = tops;
+      h.nd_top_depth = D;
+    }
+  }
 }
 
 // Re-cut the several-column tasks for another split target (the factor and the
@@ -316,14 +357,108 @@ static void coarse_solve_nd(Handle& h, const double2* g, double2* w, int R) {
   }
   v.push2 = d.nd_push2; v.child = d.nd_childv; v.slot = d.nd_slot; v.ld = d.nd_ld;
   v.srows = int64_t(h.nK) + d.nd_urows; v.nK = h.nK;
-  for (int L = nd - 1; L >= 0; --L) {   // leaves first
+  // with the dense top block the depths above nd_top_depth are one product
+  const int top = h.nd_top_n > 0 ? h.nd_top_depth : 0;
+  for (int L = nd - 1; L >= top; --L) {   // leaves first
     const NDLevel& lv = h.nd_levels[L];
     launch_nd_tiles(false, d.nd_tRf + lv.fR, lv.nfR, lv.Sf, v, g, w, R, d.nd_P, h.stream);
   }
-  for (int L = 0; L < nd; ++L) {   // root first
+  if (top > 0) {
+    launch_nd_top_gather(h.nd_top_n, d.nd_top_idx, d.nd_top_gptr, d.nd_top_grow, g, d.nd_slot, d.nd_ld,
+                         v.srows * d.nd_ld, d.nd_top_r, R, h.stream);
+    NDView tv;
+    tv.off = d.nd_top_off; tv.boff = d.nd_top_boff; tv.bnd = d.nd_top_int + 2; tv.uoff = d.nd_top_zero64;
+    tv.push = d.nd_top_int + 2; tv.mD = d.nd_top_zero64; tv.mL = d.nd_top_zero64; tv.mLt = d.nd_top_zero64;
+    tv.fac = d.nd_top_inv; tv.push2 = d.nd_top_int + 2; tv.child = d.nd_top_int; tv.slot = nullptr;
+    tv.ld = d.nd_ld; tv.srows = 0; tv.nK = h.nd_top_n;
+    launch_nd_tiles(true, d.nd_top_tasks, h.nd_top_ntiles, h.nd_top_S, tv, d.nd_top_r, d.nd_top_x, R, d.nd_top_P,
+                    h.stream);
+    launch_nd_top_scatter(h.nd_top_n, d.nd_top_idx, d.nd_top_x, w, R, h.stream);
+  }
+  for (int L = top; L < nd; ++L) {   // root first
     const NDLevel& lv = h.nd_levels[L];
     launch_nd_tiles(true, d.nd_tRb + lv.bR, lv.nbR, lv.Sb, v, g, w, R, d.nd_P, h.stream);
   }
+}
+
+void coarse_solve(Handle& h, const double2* g, double2* w, int R);
+
+// The dense top block of the nested-dissection sweeps at several columns: the
+// rows of K^-1 at the top unknowns (the inverse of their Schur complement once
+// the deeper nodes are eliminated), from the factor's own solves of the unit
+// vectors at those unknowns; then a check of the sweeps that use it against the
+// assembled K, which switches the block off if it fails.
+static void build_nd_top(Handle& h, const std::vector<int64_t>& kidx, const std::vector<double2>& kval) {
+  auto& d = h.d;
+  const int n = int(h.nd_top_host.size());
+  const int Rp = pow2ceil(h.max_rhs);
+  const int64_t nK = h.nK;
+  if (n == 0 || Rp < 2) return;
+  d.nd_top_inv = dalloc<double2>(h, size_t(n) * n);
+  d.nd_top_r = dalloc<double2>(h, size_t(n) * Rp);
+  d.nd_top_x = dalloc<double2>(h, size_t(n) * Rp);
+  int64_t* uidx = dalloc<int64_t>(h, Rp);
+  double2* uval = dalloc<double2>(h, Rp);
+  std::vector<int64_t> hidx(Rp);
+  const std::vector<double2> ones(Rp, make_double2(1.0, 0.0));
+  HIPCHECK(hipMemcpyAsync(uval, ones.data(), Rp * sizeof(double2), hipMemcpyHostToDevice, h.stream));
+  for (int k0 = 0; k0 < n; k0 += Rp) {
+    const int cols = std::min(Rp, n - k0);
+    for (int c = 0; c < cols; ++c) hidx[c] = int64_t(h.nd_top_host[k0 + c]) * Rp + c;
+    HIPCHECK(hipMemcpyAsync(uidx, hidx.data(), cols * sizeof(int64_t), hipMemcpyHostToDevice, h.stream));
+    launch_fill_zero(d.gK, nK * Rp, h.stream);
+    launch_dense_scatter(uidx, uval, cols, d.gK, h.stream);
+    coarse_solve(h, d.gK, d.wK, Rp);
+    launch_nd_top_collect(n, d.nd_top_idx, d.wK, Rp, k0, cols, d.nd_top_inv, h.stream);
+    HIPCHECK(hipStreamSynchronize(h.stream));   // hidx is rewritten by the next batch
+  }
+  // 32-row output tiles, each tile's sum split so that about 1024 workgroups run
+  const int ntiles = (n + 31) / 32;
+  const int S = std::max(1, std::min((1024 + ntiles - 1) / ntiles, ntiles));
+  const int chunk = (n + S - 1) / S;
+  std::vector<int4> tasks;
+  for (int j = 0; j < n; j += 32)
+    for (int c = 0; c < S; ++c) tasks.push_back(make_int4(0, j, std::min(n, c * chunk), std::min(n, (c + 1) * chunk)));
+  d.nd_top_tasks = upload(h, tasks);
+  d.nd_top_off = upload(h, std::vector<int>{0, n});
+  d.nd_top_boff = upload(h, std::vector<int64_t>{0, 0});
+  d.nd_top_zero64 = upload(h, std::vector<int64_t>{0});
+  d.nd_top_int = upload(h, std::vector<int>{-1, -1, 0});
+  if (S > 1) d.nd_top_P = dalloc<double2>(h, size_t(ntiles) * S * 32 * 64);
+  h.nd_top_ntiles = ntiles;
+  h.nd_top_S = S;
+  h.nd_top_n = n;
+  // check: two pseudo-random columns through the sweeps with the block
+  std::vector<double2> b(size_t(nK) * Rp, make_double2(0, 0)), x(size_t(nK) * Rp);
+  uint64_t state = 0x2545F4914F6CDD1Dull;
+  auto next = [&]() {
+    state = state * 6364136223846793005ull + 1442695040888963407ull;
+    return double(state >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  };
+  const int nc = std::min(Rp, 2);
+  for (int64_t i = 0; i < nK; ++i)
+    for (int c = 0; c < nc; ++c) b[i * Rp + c] = make_double2(next(), next());
+  HIPCHECK(hipMemcpyAsync(d.gK, b.data(), b.size() * sizeof(double2), hipMemcpyHostToDevice, h.stream));
+  coarse_solve(h, d.gK, d.wK, Rp);
+  HIPCHECK(hipMemcpyAsync(x.data(), d.wK, x.size() * sizeof(double2), hipMemcpyDeviceToHost, h.stream));
+  HIPCHECK(hipStreamSynchronize(h.stream));
+  double worst = 0;
+  for (int c = 0; c < nc; ++c) {
+    std::vector<cd> r(nK);
+    for (int64_t i = 0; i < nK; ++i) r[i] = -cd(b[i * Rp + c].x, b[i * Rp + c].y);
+    for (size_t t = 0; t < kidx.size(); ++t) {
+      const int64_t i = kidx[t] % nK, j = kidx[t] / nK;
+      r[i] += cd(kval[t].x, kval[t].y) * cd(x[j * Rp + c].x, x[j * Rp + c].y);
+    }
+    double rn = 0, bn = 0;
+    for (int64_t i = 0; i < nK; ++i) {
+      rn += std::norm(r[i]);
+      bn += b[i * Rp + c].x * b[i * Rp + c].x + b[i * Rp + c].y * b[i * Rp + c].y;
+    }
+    worst = std::max(worst, std::sqrt(rn / bn));
+  }
+  h.nd_top_check = worst;
+  if (!(worst <= std::max(1e-10, 10 * h.coarse_check))) h.nd_top_n = 0;
 }
 
 void coarse_solve(Handle& h, const double2* g, double2* w, int R);
@@ -660,6 +795,7 @@ void build_device(Handle& h) {
     d.fv = dalloc<double2>(h, nl * Rp);
     d.pv = dalloc<double2>(h, nl * Rp);
   }
+  if (h.coarse_mode == 2 && h.nd_top_depth > 0) build_nd_top(h, kidx, kval);
   HIPCHECK(hipStreamSynchronize(h.stream));
 }
 
@@ -1400,6 +1536,8 @@ hdp_status hdp_get_stats(const hdp_handle* H, hdp_stats* st) {
   st->setup_coarse_ms = h.setup_coarse_ms;
   st->coarse_factor_bytes = h.coarse_bytes;
   st->coarse_blocks = st->coarse_mode == 2 ? int(h.nd_off.size()) - 1 : 1;
+  st->coarse_top_unknowns = h.nd_top_n;
+  st->coarse_top_check = h.nd_top_check;
   return HDP_OK;
   API_END
 }

@@ -197,6 +197,11 @@ struct Handle {
   size_t nd_tR_cap[2] = {0, 0};     // capacity of nd_tRf / nd_tRb
   bool coarse_refine = false;       // refine each coarse solve once (set at setup from the check)
   int cmA_b_R = 0;                  // columns of d.cmA_b valid for the current loads (0: none)
+  // nested dissection at several columns: the depths above nd_top_depth solved as
+  // one dense block (the top unknowns' rows of K^-1), nd_top_n unknowns (0: off)
+  int nd_top_depth = 0, nd_top_n = 0, nd_top_ntiles = 0, nd_top_S = 1;
+  std::vector<int> nd_top_host;     // the top unknowns (nested-dissection indices)
+  double nd_top_check = 0;          // set-up check of the block: ||K x - b|| / ||b||
   double coarse_check = 0;         // relative residual of the coarse factor on a test vector
   int sym_nt = 0, sym_ntiles = 0;   // tile rows and upper tiles of the symmetric coarse inverse
   double coarse_bytes1 = 0;         // factor bytes of a one-RHS coarse solve (half with the tiles)
@@ -273,6 +278,12 @@ struct Handle {
     int64_t *dn_boff = nullptr, *dn_zero64 = nullptr;
     double2* dn_P = nullptr;
     int *nd_push2 = nullptr, *nd_childv = nullptr;
+    // the dense top block (several columns): its unknowns, their gather lists of
+    // front rows, the block (row-major), work arrays [n][R_max] and tile tasks
+    int *nd_top_idx = nullptr, *nd_top_grow = nullptr, *nd_top_off = nullptr, *nd_top_int = nullptr;
+    int64_t *nd_top_gptr = nullptr, *nd_top_boff = nullptr, *nd_top_zero64 = nullptr;
+    double2 *nd_top_inv = nullptr, *nd_top_r = nullptr, *nd_top_x = nullptr, *nd_top_P = nullptr;
+    int4* nd_top_tasks = nullptr;
     int64_t nd_ld = 0;
     // per-class tables
     int *cls_n = nullptr, *cls_m = nullptr, *cls_nr = nullptr;
@@ -423,6 +434,8 @@ void release_allocations(Handle& h);
 // ND_SPLITS are the targets the set-up autotuner tries
 void nd_tasks(const Handle& h, NDHost& f, int target);
 constexpr int ND_SPLITS[] = {256, 512, 1024, 2048};
+// most unknowns of the dense top block of the nested-dissection sweeps
+constexpr int64_t ND_TOP_MAX = 3072;
 void build_device(Handle& h);
 // Element loads of the elements with a non-zero load: elems lists them and
 // vals holds their blocks back to back, each [n_e^2][R].

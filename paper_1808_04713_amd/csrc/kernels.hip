@@ -1105,6 +1105,48 @@ __global__ void k_nd_reduce(const int4* __restrict__ task, int ntiles, int S, co
   }
 }
 
+// The top depths of the tree as one dense block (several columns): the
+// right-hand side of the top unknowns once every deeper node is eliminated,
+// r[i] = g[x_i] plus both child slots of each front row listed for x_i
+// (its own row in a front of the deepest top depth, and the update rows of
+// those fronts that couple to it); x_i = idx[i]; [n][R] and [nK][R] arrays.
+__global__ void k_nd_top_gather(int n, const int* __restrict__ idx, const int64_t* __restrict__ gptr,
+                                const int* __restrict__ grow, const double2* __restrict__ g,
+                                const double2* __restrict__ slot, int64_t ld, int64_t sst, double2* __restrict__ r,
+                                int R) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * R) return;
+  const int i = int(e / R), c = int(e - (int64_t)i * R);
+  double2 v = g[(int64_t)idx[i] * R + c];
+  for (int64_t q = gptr[i]; q < gptr[i + 1]; ++q) {
+    const double2* p = slot + (int64_t)grow[q] * ld + c;
+    const double2 a = p[0], b = p[sst];
+    v.x += a.x + b.x;
+    v.y += a.y + b.y;
+  }
+  r[e] = v;
+}
+
+// w[x_i] = x[i] for the top unknowns ([n][R] into [nK][R]).
+__global__ void k_nd_top_scatter(int n, const int* __restrict__ idx, const double2* __restrict__ x,
+                                 double2* __restrict__ w, int R) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * R) return;
+  const int i = int(e / R), c = int(e - (int64_t)i * R);
+  w[(int64_t)idx[i] * R + c] = x[e];
+}
+
+// Set-up of the dense top block: columns k0 .. k0 + cols - 1 of (K^-1) restricted
+// to the top unknowns, from the coarse solutions w ([nK][R]) of the unit vectors
+// at x_k0 .., into the row-major n x n block M.
+__global__ void k_nd_top_collect(int n, const int* __restrict__ idx, const double2* __restrict__ w, int R, int k0,
+                                 int cols, double2* __restrict__ M) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * cols) return;
+  const int i = int(e / cols), c = int(e - (int64_t)i * cols);
+  M[(int64_t)i * n + k0 + c] = w[(int64_t)idx[i] * R + c];
+}
+
 // r = g - K x with K in CSR by row: one wave per row; at one column the lanes
 // take the row's entries, otherwise the lanes are the columns.
 __global__ void __launch_bounds__(NT) k_csr_residual(int n, const int64_t* __restrict__ ptr,
@@ -3621,6 +3663,27 @@ void launch_nd_tiles(bool bwd, const int4* task, int ntiles, int S, const NDView
 void launch_csr_residual(int n, const int64_t* ptr, const int* col, const double2* val, const double2* x,
                          const double2* g, double2* r, int R, hipStream_t s) {
   hipLaunchKernelGGL(k_csr_residual, dim3(nblocks(n, NT / 64)), dim3(NT), 0, s, n, ptr, col, val, x, g, r, R);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_nd_top_gather(int n, const int* idx, const int64_t* gptr, const int* grow, const double2* g,
+                          const double2* slot, int64_t ld, int64_t sst, double2* r, int R, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_nd_top_gather, dim3(nblocks(int64_t(n) * R)), dim3(NT), 0, s, n, idx, gptr, grow, g, slot, ld,
+                     sst, r, R);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_nd_top_scatter(int n, const int* idx, const double2* x, double2* w, int R, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_nd_top_scatter, dim3(nblocks(int64_t(n) * R)), dim3(NT), 0, s, n, idx, x, w, R);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_nd_top_collect(int n, const int* idx, const double2* w, int R, int k0, int cols, double2* M,
+                           hipStream_t s) {
+  if (n == 0 || cols == 0) return;
+  hipLaunchKernelGGL(k_nd_top_collect, dim3(nblocks(int64_t(n) * cols)), dim3(NT), 0, s, n, idx, w, R, k0, cols, M);
   HIPCHECK(hipGetLastError());
 }
 

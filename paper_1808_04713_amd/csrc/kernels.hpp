@@ -117,6 +117,14 @@ void launch_nd_bwd1(const ND1Bwd* task, int ntask, const NDView& v, const double
 // tiles go to P (ntiles * S * 32 * 64 values) and a second kernel adds them
 void launch_nd_tiles(bool bwd, const int4* task, int ntiles, int S, const NDView& v, const double2* g, double2* X,
                      int R, double2* P, hipStream_t s);
+// the top depths as one dense block (several columns): gather the top unknowns'
+// right-hand side (g plus the listed front rows' two child slots), scatter the
+// block's solution back, and at set-up collect columns of K^-1 restricted to them
+void launch_nd_top_gather(int n, const int* idx, const int64_t* gptr, const int* grow, const double2* g,
+                          const double2* slot, int64_t ld, int64_t sst, double2* r, int R, hipStream_t s);
+void launch_nd_top_scatter(int n, const int* idx, const double2* x, double2* w, int R, hipStream_t s);
+void launch_nd_top_collect(int n, const int* idx, const double2* w, int R, int k0, int cols, double2* M,
+                           hipStream_t s);
 // r = g - K x, K in CSR by row (ptr[n + 1], col, val), [n][R] vectors
 void launch_csr_residual(int n, const int64_t* ptr, const int* col, const double2* val, const double2* x,
                          const double2* g, double2* r, int R, hipStream_t s);

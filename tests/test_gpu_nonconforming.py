@@ -157,12 +157,15 @@ def test_refined_disk_full_size():
 @pytest.mark.parametrize("name", ["h4_p2to5_l3", "disk_6x6_p3to6"])
 def test_coarse_factors_on_hanging_meshes(name, coarse, literal):
     """Dense-inverse and nested-dissection coarse factors on quadtree meshes:
-    the literal method's F and field."""
+    the literal method's F and field (two columns: the nested-dissection sweeps
+    with their dense top block)."""
     disc, D = literal[name]
     w = CASES[name]
     s = hdp().Solver(w, tol=1e-12, max_iter=400, max_rhs=2, coarse=coarse)
     mode, nblk = (0, 1) if coarse == "dense" else (2, 3)
     assert s.info["coarse_mode"] == mode and s.info["coarse_blocks"] >= nblk and s.info["coarse_residual"] < 1e-11
+    if coarse == "nd":
+        assert 0 < s.info["coarse_top_unknowns"] < s.n_coarse and s.info["coarse_top_check"] < 1e-11
     rng = np.random.default_rng(9)
     v = rng.standard_normal((s.n_lambda, 2)) + 1j * rng.standard_normal((s.n_lambda, 2))
     Fv = s.apply_interface(torch.from_numpy(v).cuda(), "fp64").cpu().numpy()

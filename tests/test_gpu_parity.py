@@ -261,14 +261,16 @@ def test_coarse_solvers_against_the_oracle(name, coarse, oracles):
     """Both coarse factors give the oracle's interface operator at 1, 5, 16 and 64
     columns and its field: the dense inverse (streamed symmetric tiles at one
     column, tile products of the inverse from 4 columns on, on the matrix cores
-    at 16..64) and the nested-dissection factor (one-column rows, tile products);
-    5 columns exercise the masked lanes of the vector path."""
+    at 16..64) and the nested-dissection factor (one-column rows, tile products,
+    the top depths as one dense block at several columns); 5 columns exercise the
+    masked lanes of the vector path."""
     disc, l, E = oracles[name]
     w = CASES[name]
     s = hdp().Solver(w, tol=1e-12, max_iter=400, max_rhs=64, coarse=coarse)
     st = s.info
     assert st["coarse_mode"] == (0 if coarse == "dense" else 2) and st["coarse_residual"] < 1e-12
     assert coarse == "dense" or st["coarse_blocks"] >= 3
+    assert coarse == "dense" or (0 < st["coarse_top_unknowns"] < st["n_coarse"] and st["coarse_top_check"] < 1e-12)
     rng = np.random.default_rng(5)
     for R in (1, 5, 16, 64):
         v = rng.standard_normal((E.nlam, R)) + 1j * rng.standard_normal((E.nlam, R))
