@@ -1136,10 +1136,13 @@ void build_host(Handle& h, const hdp_mesh* mesh, const hdp_problem* prob) {
   build_hanging_blocks(h);
   // coarse factor: dense inverse for small coarse spaces (one streaming GEMV per
   // solve, 164 MB at 3,201 unknowns), the nested-dissection factor beyond 6,000
-  // (a requested factor gets small blocks, so that small meshes exercise it too)
+  // (a requested factor gets small blocks, so that small meshes exercise it too;
+  // solves of 9 or more columns take leaves of up to 192 unknowns, whose fewer,
+  // fuller launches are faster there: 0.476 against 0.483 ms per 64-column solve
+  // on the 64x64 scatterer, where one column keeps 96)
   const bool requested = h.coarse_mode >= 0;
   if (h.coarse_mode < 0) h.coarse_mode = h.nK > 6000 ? 2 : 0;
-  if (h.coarse_mode == 2) order_coarse_nd(h, requested ? 32 : 96);
+  if (h.coarse_mode == 2) order_coarse_nd(h, requested ? 32 : (h.max_rhs >= 9 ? 192 : 96));
   else order_coarse_levels(h);
   // algorithmic work counts
   for (auto& C : h.classes) {
