@@ -293,7 +293,15 @@ void nd_tasks(const Handle& h, NDHost& f, int target) {
       if (ntiles > 0) S = std::max(1, std::min((target + ntiles - 1) / ntiles, (kmax + 31) / 32));
       std::vector<int4>& T = bwd ? f.tRb : f.tRf;
       const int first = int(T.size());
-      for (int t : by_depth[dpt]) {
+      // nodes with the longest sums first: a depth whose tiles overflow one round
+      // of workgroups leaves its shortest ones for the last round (each output's
+      // tasks stay together, so every sum is the same)
+      std::vector<int> order = by_depth[dpt];
+      std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        const int ka = bwd ? nI_of(a) + nB_of(a) : nI_of(a), kc = bwd ? nI_of(c) + nB_of(c) : nI_of(c);
+        return ka > kc;
+      });
+      for (int t : order) {
         const int nout = bwd ? nI_of(t) : nB_of(t);
         const int K = bwd ? nI_of(t) + nB_of(t) : nI_of(t);
         const int chunk = (K + S - 1) / S;
